@@ -1,0 +1,266 @@
+"""Thin Python binding of the race-checker C ABI (include/rc.h).
+
+Argument marshalling only: every step of the check runs in the HIP library
+``librc.so``.  torch supplies device memory (workspace, record and summary
+buffers) and the stream.  There is no CPU fallback: without the built library
+every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librc.so")
+
+RC_OK, RC_E_INVAL, RC_E_PARSE, RC_E_LIMIT, RC_E_STATE, RC_E_OVERFLOW, RC_E_HIP = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", 1: "OOB", 2: "DIV_ZERO", 3: "ASSERT", 4: "ASSUME", 5: "BARRIER_DIVERGENCE"}
+NONE = 0xFFFFFFFF
+
+RECORD_DTYPE = np.dtype([
+    ("instance", "<u4"), ("gid", "<u4"), ("interval", "<u4"),
+    ("array", "<u2"), ("label", "<u2"), ("cell", "<u4"),
+    ("rw_a", "<u4"), ("rw_b", "<u4"), ("ww_a", "<u4"), ("ww_b", "<u4"), ("pad", "<u4"),
+])
+SUMMARY_DTYPE = np.dtype([
+    ("n_accesses", "<u8"), ("n_race_cells", "<u4"), ("n_benign_cells", "<u4"),
+    ("n_intervals", "<u4"), ("status", "<i4"), ("fault_gid", "<u4"),
+    ("fault_pc", "<u4"), ("fault_tid", "<u4"), ("flags", "<u4"),
+])
+RECORD_BYTES = 40
+SUMMARY_BYTES = 40
+
+EXPORTS = [
+    "rc_last_error", "rc_ctx_create", "rc_ctx_destroy", "rc_ctx_set_stream", "rc_prog_load",
+    "rc_prog_free", "rc_prog_get_info", "rc_prog_array", "rc_prog_scalar", "rc_set_ndrange",
+    "rc_bind_seeded", "rc_bind_device", "rc_bind_scalar_seeded", "rc_bind_scalar",
+    "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final",
+]
+
+
+class RcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rc status {status}: {msg}")
+        self.status = status
+
+
+class _ProgInfo(ctypes.Structure):
+    _fields_ = [("n_global_arrays", ctypes.c_uint32), ("n_local_arrays", ctypes.c_uint32),
+                ("n_scalars", ctypes.c_uint32), ("n_vars", ctypes.c_uint32), ("n_stmts", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1308_3203_amd/build.py "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, u32, u64, i32, i64, sz = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                                  ctypes.c_int64, ctypes.c_size_t)
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "rc_last_error": ([], ctypes.c_char_p),
+        "rc_ctx_create": ([ctypes.c_int, vp, pp], ctypes.c_int),
+        "rc_ctx_destroy": ([vp], ctypes.c_int),
+        "rc_ctx_set_stream": ([vp, vp], ctypes.c_int),
+        "rc_prog_load": ([vp, ctypes.c_char_p, sz, pp], ctypes.c_int),
+        "rc_prog_free": ([vp], ctypes.c_int),
+        "rc_prog_get_info": ([vp, ctypes.POINTER(_ProgInfo)], ctypes.c_int),
+        "rc_prog_array": ([vp, u32, ctypes.c_char_p, sz, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_int)],
+                          ctypes.c_int),
+        "rc_prog_scalar": ([vp, u32, ctypes.c_char_p, sz], ctypes.c_int),
+        "rc_set_ndrange": ([vp, u32, u32], ctypes.c_int),
+        "rc_bind_seeded": ([vp, u32, i64, i64], ctypes.c_int),
+        "rc_bind_device": ([vp, u32, vp], ctypes.c_int),
+        "rc_bind_scalar_seeded": ([vp, u32, i64, i64], ctypes.c_int),
+        "rc_bind_scalar": ([vp, u32, i32], ctypes.c_int),
+        "rc_workspace_size": ([vp, u32, ctypes.POINTER(sz)], ctypes.c_int),
+        "rc_check": ([vp, u64, u32, vp, sz, vp, u64, vp, vp], ctypes.c_int),
+        "rc_sync": ([vp], ctypes.c_int),
+        "rc_read_final": ([vp, u64, u32, vp, vp, sz], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _call(fn, *args):
+    st = fn(*args)
+    if st != RC_OK:
+        raise RcError(st, _lib.rc_last_error().decode())
+    return st
+
+
+class Context:
+    """A library context on one device, bound to a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load_library()
+        self.device = device
+        self._torch_stream = stream if stream is not None else torch.cuda.current_stream(device)
+        out = ctypes.c_void_p()
+        _call(lib.rc_ctx_create, device, ctypes.c_void_p(self._torch_stream.cuda_stream), ctypes.byref(out))
+        self._h = out
+
+    def sync(self):
+        _call(_lib.rc_sync, self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Program:
+    """A compiled kernel program with its launch shape and input bindings."""
+
+    def __init__(self, ctx: Context, src: str):
+        lib = load_library()
+        self.ctx = ctx
+        self.src = src
+        raw = src.encode()
+        out = ctypes.c_void_p()
+        _call(lib.rc_prog_load, ctx._h, raw, len(raw), ctypes.byref(out))
+        self._h = out
+        info = _ProgInfo()
+        _call(lib.rc_prog_get_info, self._h, ctypes.byref(info))
+        self.info = info
+        self.arrays = []
+        name = ctypes.create_string_buffer(64)
+        cells = ctypes.c_uint64()
+        glob = ctypes.c_int()
+        for i in range(info.n_global_arrays + info.n_local_arrays):
+            _call(lib.rc_prog_array, self._h, i, name, 64, ctypes.byref(cells), ctypes.byref(glob))
+            self.arrays.append((name.value.decode(), int(cells.value), bool(glob.value)))
+        self.scalars = []
+        for j in range(info.n_scalars):
+            _call(lib.rc_prog_scalar, self._h, j, name, 64)
+            self.scalars.append(name.value.decode())
+        self._keep = {}
+        self.G = self.W = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rc_prog_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def array_id(self, name: str) -> int:
+        for i, (n, _, _) in enumerate(self.arrays):
+            if n == name:
+                return i
+        raise KeyError(name)
+
+    def set_ndrange(self, groups: int, group_size: int):
+        _call(_lib.rc_set_ndrange, self._h, groups, group_size)
+        self.G, self.W = groups, group_size
+
+    def bind(self, arrays: dict | None = None, scalars: dict | None = None):
+        """arrays: name -> ("seeded", lo, hi) or an int32 cuda tensor;
+        scalars: name -> ("seeded", lo, hi) or an int."""
+        for name, b in (arrays or {}).items():
+            aid = self.array_id(name)
+            if isinstance(b, tuple):
+                _call(_lib.rc_bind_seeded, self._h, aid, int(b[1]), int(b[2]))
+            else:
+                t = b.contiguous()
+                self._keep[name] = t
+                _call(_lib.rc_bind_device, self._h, aid, ctypes.c_void_p(t.data_ptr()))
+        for name, b in (scalars or {}).items():
+            sid = self.scalars.index(name)
+            if isinstance(b, tuple):
+                _call(_lib.rc_bind_scalar_seeded, self._h, sid, int(b[1]), int(b[2]))
+            else:
+                _call(_lib.rc_bind_scalar, self._h, sid, ((int(b) + 2 ** 31) % 2 ** 32) - 2 ** 31)
+
+    def workspace_size(self, n_seeds: int) -> int:
+        out = ctypes.c_size_t()
+        _call(_lib.rc_workspace_size, self._h, n_seeds, ctypes.byref(out))
+        return int(out.value)
+
+    def check_async(self, seed0: int, n_seeds: int, ws, records, n_records, summaries):
+        """Enqueue a check into caller-owned torch buffers (uint8 workspace,
+        uint8 records of 40*cap bytes, one int64 counter, uint8 summaries)."""
+        cap = records.numel() // RECORD_BYTES
+        _call(_lib.rc_check, self._h, ctypes.c_uint64(seed0 & (2 ** 64 - 1)), n_seeds,
+              ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+              ctypes.c_void_p(records.data_ptr() if cap else 0), cap,
+              ctypes.c_void_p(n_records.data_ptr()), ctypes.c_void_p(summaries.data_ptr()))
+
+    def read_final(self, seed: int, name: str, ws):
+        import torch
+        aid = self.array_id(name)
+        out = torch.empty(self.arrays[aid][1], dtype=torch.int32, device=ws.device)
+        _call(_lib.rc_read_final, self._h, ctypes.c_uint64(seed & (2 ** 64 - 1)), aid,
+              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel())
+        return out
+
+
+class Buffers:
+    """Device buffers for checks of up to n_seeds instances."""
+
+    def __init__(self, prog: Program, n_seeds: int, cap: int, ws_limit: int = 8 << 30, device=None):
+        import torch
+        dev = device or torch.device("cuda", prog.ctx.device)
+        need = prog.workspace_size(n_seeds)
+        if need > ws_limit:
+            need = max(prog.workspace_size(1), ws_limit)
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.records = torch.empty(max(cap, 1) * RECORD_BYTES, dtype=torch.uint8, device=dev)
+        self.cap = cap
+        self.n_records = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.summaries = torch.empty(max(n_seeds, 1) * SUMMARY_BYTES, dtype=torch.uint8, device=dev)
+        self.n_seeds = n_seeds
+
+
+def records_to_numpy(records_u8, n: int) -> np.ndarray:
+    raw = records_u8[: n * RECORD_BYTES].cpu().numpy()
+    return raw.view(RECORD_DTYPE).copy()
+
+
+def summaries_to_numpy(summ_u8, n: int) -> np.ndarray:
+    raw = summ_u8[: n * SUMMARY_BYTES].cpu().numpy()
+    return raw.view(SUMMARY_DTYPE).copy()
+
+
+def check(src: str, G: int, W: int, arrays: dict | None = None, scalars: dict | None = None,
+          seed0: int = 0, n_seeds: int = 1, cap: int | None = None, ctx: Context | None = None,
+          ws_limit: int = 8 << 30):
+    """Compile, bind and check n_seeds instances; returns numpy (records, summaries)."""
+    ctx = ctx or Context()
+    prog = Program(ctx, src)
+    prog.set_ndrange(G, W)
+    prog.bind(arrays, scalars)
+    if cap is None:
+        cap = 1 << 20
+    buf = Buffers(prog, n_seeds, cap, ws_limit)
+    prog.check_async(seed0, n_seeds, buf.ws, buf.records, buf.n_records, buf.summaries)
+    ctx.sync()
+    n = int(buf.n_records.item())
+    recs = records_to_numpy(buf.records, min(n, cap))
+    summ = summaries_to_numpy(buf.summaries, n_seeds)
+    prog.close()
+    return recs, summ

@@ -1,0 +1,873 @@
+// kernels.hip -- HIP kernels of the race checker for gfx950.
+//
+//  * rc_interp_kernel: the lockstep interpreter.  One workgroup runs one
+//    work-group of one instance; lane l is work-item l.  Statements run one
+//    at a time for the whole work-group (paper Section 4 thread-local rules
+//    under the lockstep schedule); a barrier closes an interval (Section 4
+//    global rules).  Private variables live in LDS, laid out register-major
+//    so a wave reads 64 consecutive dwords.  Every access to an array that
+//    the program writes somewhere is appended to the access log.
+//  * rs_* / scan_*: stable LSD radix sort (8-bit digits) and exclusive scan.
+//  * seg_check_kernel: after the log is sorted by (instance, cell, gid,
+//    interval), each run of one cell is checked for eligible pairs (the
+//    Section 4 race rule made concrete; Section 1: equal-value writes are
+//    benign) with two passes of min-reductions per scope.
+//  * rec_gather_kernel / finalize: canonical record order and summaries.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rc_internal.h"
+#include "kernels.h"
+
+namespace rc {
+
+typedef unsigned long long u64;
+
+// ---------------------------------------------------------------------------
+// seeded inputs: SplitMix64 (Steele, Lea, Flood 2014) in counter form
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + counter * 0x9E3779B97F4A7C15ull;
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int32_t seeded_cell(uint64_t seed, uint32_t stream, uint32_t idx,
+                                                int64_t lo, int64_t hi) {
+  uint64_t hi32 = sm64(seed, ((uint64_t)stream << 32) | ((uint64_t)idx + 1)) >> 32;
+  // stream < 2^17 and idx < 2^24: the counter never carries out of the low word
+  uint64_t scaled = (hi32 * (uint64_t)(hi - lo)) >> 32;
+  return (int32_t)(uint32_t)((uint64_t)lo + scaled);
+}
+
+// ---------------------------------------------------------------------------
+// int32 operators (two's complement, wrapping; division faults on zero)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t alu_bin(uint32_t op, int32_t x, int32_t y, bool& dz) {
+  const uint32_t ux = (uint32_t)x, uy = (uint32_t)y;
+  switch (op) {
+    case B_ADD: return (int32_t)(ux + uy);
+    case B_SUB: return (int32_t)(ux - uy);
+    case B_MUL: return (int32_t)(ux * uy);
+    case B_DIV:
+      if (y == 0) { dz = true; return 0; }
+      if (y == -1) return (int32_t)(0u - ux);
+      return x / y;
+    case B_REM:
+      if (y == 0) { dz = true; return 0; }
+      if (y == -1) return 0;
+      return x % y;
+    case B_MOD: {
+      if (y == 0) { dz = true; return 0; }
+      if (y == -1 || y == 1) return 0;
+      int32_t r = x % y;
+      if (r < 0) r = (int32_t)((uint32_t)r + (y < 0 ? 0u - uy : uy));
+      return r;
+    }
+    case B_AND: return x & y;
+    case B_OR: return x | y;
+    case B_XOR: return x ^ y;
+    case B_SHL: return (int32_t)(ux << (uy & 31u));
+    case B_SHR: return x >> (int32_t)(uy & 31u);
+    case B_LT: return x < y;
+    case B_LE: return x <= y;
+    case B_GT: return x > y;
+    case B_GE: return x >= y;
+    case B_EQ: return x == y;
+    case B_NE: return x != y;
+    case B_LAND: return (x != 0) & (y != 0);
+    case B_LOR: return (x != 0) | (y != 0);
+    case B_MIN: return x < y ? x : y;
+    default: return x > y ? x : y;   // B_MAX
+  }
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// fault key: dynamic statement | lid | pc | priority | code  (smaller = earlier)
+// priority orders one item's faults inside a statement: DIV, OOB, the rest.
+__device__ __forceinline__ u64 fault_key(uint32_t step, uint32_t lid, uint32_t pc, uint32_t code) {
+  uint32_t prio = code == F_DIV ? 0u : (code == F_OOB ? 1u : 2u);
+  return ((u64)step << 32) | ((u64)lid << 17) | ((u64)pc << 5) | ((u64)prio << 3) | code;
+}
+
+extern __shared__ __attribute__((aligned(16))) unsigned char rc_smem[];
+
+__global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
+  const uint32_t tl = threadIdx.x;
+  const uint32_t WP = P.nwaves * 64u;
+  const uint32_t wave = tl >> 6, lane = tl & 63u;
+  const uint32_t slot = blockIdx.x / P.G;
+  const uint32_t gid = blockIdx.x - slot * P.G;
+  const uint64_t seed = P.seed0 + (uint64_t)(P.inst_offset + slot);
+  const bool real = tl < P.W;
+
+  // dynamic LDS: local array cells (u64), registers, control block
+  u64* locc = reinterpret_cast<u64*>(rc_smem);
+  int32_t* regs = reinterpret_cast<int32_t*>(locc + P.lds_local_cells);
+  Ctl* ctl = reinterpret_cast<Ctl*>(regs + (size_t)P.nregs * WP);
+
+  for (uint32_t i = tl; i < P.lds_local_cells; i += WP) locc[i] = 0ull;
+  for (uint32_t i = tl; i < P.nregs * WP; i += WP) regs[i] = 0;
+  if (tl == 0) ctl->fault = ~0ull;
+  if (tl < P.n_scalars) {
+    const ScalarDesc& S = P.scalars[tl];
+    ctl->scal[tl] = S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
+  }
+  // overlay epochs: versions written by earlier runs on this overlay are older
+  const size_t ovl_index = (size_t)slot * P.G + gid;
+  u64* ovl = P.overlay + ovl_index * (size_t)P.overlay_cells;
+  if (tl == 0) {
+    uint32_t e = P.epochs[ovl_index];
+    if (e == 0u || e + P.max_store_seq + 2u >= (1u << 22)) e = 0u;   // fresh or wrapping
+    ctl->epoch_base = e;
+  }
+  __syncthreads();
+  uint32_t epoch_base = uni(ctl->epoch_base);
+  if (epoch_base == 0u) {
+    for (size_t i = tl; i < P.overlay_cells; i += WP) ovl[i] = 0ull;
+    __threadfence_block();
+    __syncthreads();
+    epoch_base = 1u;
+  }
+  if (tl == 0) P.epoch_used[ovl_index] = epoch_base;
+
+  const u64 key_slot = (u64)slot << (P.bc + P.bg + P.bk);
+  uint32_t pc = 0, depth = 0, eany = 0, last_spc = ~0u;
+  uint32_t step = 0, store_seq = 0, interval = 0, parity = 0;
+  uint32_t mbits = real ? 1u : 0u, ebits = 0u;
+  uint32_t n_acc = 0;
+  u64 my_fault = ~0ull;      // earliest fault of this work-item (fault_key order)
+  bool faulted = false;
+
+  auto fetch = [&](bool imm, uint32_t w) -> int32_t {
+    if (imm) return (int32_t)w;
+    if (w < MAX_REGS) return regs[w * WP + tl];
+    switch (w) {
+      case SEL_LID: return (int32_t)tl;
+      case SEL_TID: return (int32_t)(gid * P.W + tl);
+      case SEL_GID: return (int32_t)gid;
+      case SEL_WGSIZE: return (int32_t)P.W;
+      case SEL_NGROUPS: return (int32_t)P.G;
+      case SEL_NTHREADS: return (int32_t)(P.G * P.W);
+      default: return ctl->scal[w - SEL_SCALAR0];
+    }
+  };
+  // Group-wide OR of two per-lane predicates (bits 0, 1) and of "some
+  // work-item has a pending fault" (bit 2).  Every wave publishes its word
+  // before the barrier and reads all words after it, so all waves decide on
+  // the same snapshot.  The words are double-buffered: a wave can only reuse
+  // a buffer after the next reduction's barrier, which every reader passes
+  // after reading.
+  auto group_red = [&](bool p0, bool p1, bool sync_always) -> uint32_t {
+    const u64 b0 = __ballot(p0), b1 = __ballot(p1), bf = __ballot(my_fault != ~0ull);
+    const uint32_t mine = (b0 != 0ull ? 1u : 0u) | (b1 != 0ull ? 2u : 0u) | (bf != 0ull ? 4u : 0u);
+    if (P.nwaves == 1) {
+      if (sync_always) __syncthreads();
+      return uni(mine);
+    }
+    if (lane == 0) ctl->red[parity][wave] = mine;
+    __syncthreads();
+    uint32_t acc = 0;
+    for (uint32_t w = 0; w < P.nwaves; ++w) acc |= ctl->red[parity][w];
+    parity ^= 1u;
+    return uni(acc);
+  };
+  auto raise = [&](uint32_t spc, uint32_t code) {
+    const u64 k = fault_key(step, tl, spc, code);
+    if (k < my_fault) my_fault = k;
+  };
+
+  for (;;) {
+    pc = uni(pc);
+    const uint32_t* ip = P.code + (size_t)pc * 4u;
+    const uint32_t h = uni(ip[0]), wa = uni(ip[1]), wb = uni(ip[2]), wc = uni(ip[3]);
+    const uint32_t op = h & 63u, sub = (h >> 8) & 63u, dst = (h >> 14) & 63u, spc = h >> 20;
+    const bool fa = (h >> 6) & 1u, fb = (h >> 7) & 1u;
+    if (spc != last_spc) { ++step; last_spc = spc; }
+    const bool active = (mbits >> depth) & 1u;
+
+    if (op == OP_BIN) {
+      int32_t x = fetch(fa, wa), y = fetch(fb, wb);
+      bool dz = false;
+      int32_t r = alu_bin(sub, x, y, dz);
+      if (active) {
+        regs[dst * WP + tl] = r;
+        if (dz) raise(spc, F_DIV);
+      }
+      ++pc;
+    } else if (op == OP_UN) {
+      int32_t x = fetch(fa, wa);
+      int32_t r = sub == U_MOV ? x : sub == U_NEG ? (int32_t)(0u - (uint32_t)x) : sub == U_BNOT ? ~x : (int32_t)(x == 0);
+      if (active) regs[dst * WP + tl] = r;
+      ++pc;
+    } else if (op == OP_LOAD || op == OP_STORE) {
+      const ArrayDesc& A = P.arrays[wc];
+      const int32_t idx = fetch(fa, wa);
+      const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;
+      if (active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);
+      // the barrier completes every earlier statement's accesses and
+      // publishes pending faults; a faulting statement has no effect
+      if (group_red(false, false, true) & 4u) { faulted = true; break; }
+      const uint32_t cell = (uint32_t)idx;
+      if (op == OP_LOAD) {
+        if (active) {
+          int32_t v;
+          if (A.kind == AK_LOCAL) {
+            v = (int32_t)(uint32_t)locc[A.offset + cell];
+          } else {
+            bool have = false;
+            v = 0;
+            if (A.kind == AK_GLOBAL_RW) {
+              u64 w = __hip_atomic_load(&ovl[A.offset + cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if ((uint32_t)(w >> 42) >= epoch_base) { v = (int32_t)(uint32_t)w; have = true; }
+            }
+            if (!have)
+              v = A.bind == BIND_SEEDED ? seeded_cell(seed, wc, cell, A.lo, A.hi) : A.dptr[cell];
+          }
+          regs[dst * WP + tl] = v;
+          ++n_acc;
+        }
+      } else {
+        ++store_seq;
+        if (active) {
+          // within one statement the highest work-item's value stays
+          const uint32_t ep = A.kind == AK_LOCAL ? store_seq : epoch_base + store_seq;
+          const u64 word = ((u64)((ep << 10) | tl) << 32) | (uint32_t)val;
+          if (A.kind == AK_LOCAL) atomicMax(&locc[A.offset + cell], word);
+          else atomicMax(&ovl[A.offset + cell], word);
+          ++n_acc;
+        }
+      }
+      if (P.do_log && A.logged) {
+        const bool rec = active;
+        const u64 m = __ballot(rec);
+        if (m != 0ull) {
+          const uint32_t first = (uint32_t)__ffsll((long long)m) - 1u;
+          const uint32_t cnt = (uint32_t)__popcll(m);
+          u64 base = 0ull;
+          if (lane == first) base = atomicAdd(P.log_count, (u64)cnt);
+          const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, first);
+          const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), first);
+          base = ((u64)bhi << 32) | blo;
+          if (rec) {
+            const u64 pos = base + (u64)__popcll(m & ((1ull << lane) - 1ull));
+            const u64 key = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
+            const u64 pay = ((u64)(uint32_t)val << 32) | ((op == OP_STORE) ? 1024u : 0u) | tl;
+            if (pos < P.log_cap) {
+              P.log_keys[pos] = key;
+              P.log_vals[pos] = pay;
+            } else {
+              atomicOr(P.status_word, 1u);
+            }
+          }
+        }
+      }
+      ++pc;
+    } else if (op == OP_IF) {
+      const int32_t c = fetch(fa, wa);
+      const bool t = active && c != 0, e = active && c == 0;
+      const uint32_t d1 = depth + 1u;
+      mbits = (mbits & ~(1u << d1)) | ((uint32_t)t << d1);
+      ebits = (ebits & ~(1u << d1)) | ((uint32_t)e << d1);
+      const uint32_t any = group_red(t, e, false);
+      if (any & 4u) { faulted = true; break; }
+      depth = d1;
+      eany = (eany & ~(1u << d1)) | (((any >> 1) & 1u) << d1);
+      pc = (any & 1u) ? pc + 1u : wb;
+    } else if (op == OP_ELSE) {
+      mbits = (mbits & ~(1u << depth)) | (((ebits >> depth) & 1u) << depth);
+      pc = ((eany >> depth) & 1u) ? pc + 1u : wc;
+    } else if (op == OP_ENDIF) {
+      --depth;
+      ++pc;
+    } else if (op == OP_FOR) {
+      const int32_t lo = (int32_t)wa, hi = (int32_t)wb;
+      if (active) regs[dst * WP + tl] = lo;
+      if ((int64_t)hi - (int64_t)lo <= 0) {
+        pc = wc;
+      } else {
+        if (lane == 0) ctl->loopctr[wave][sub] = 0u;
+        ++pc;
+      }
+    } else if (op == OP_ENDFOR) {
+      const int32_t lo = (int32_t)wa, hi = (int32_t)wb;
+      const uint32_t iters = (uint32_t)((int64_t)hi - (int64_t)lo);
+      const uint32_t ctr = uni(ctl->loopctr[wave][sub]) + 1u;
+      if (lane == 0) ctl->loopctr[wave][sub] = ctr;
+      if (active) regs[dst * WP + tl] = (int32_t)((uint32_t)lo + ctr);
+      pc = ctr < iters ? wc : pc + 1u;
+    } else if (op == OP_BARRIER) {
+      // every work-item of the group must arrive (bit 0: some are missing)
+      const uint32_t r = group_red(real && !active, active, true);
+      if (r & 4u) { faulted = true; break; }
+      if (r & 1u) {
+        if (real && !active) raise(spc, F_BARDIV);
+        faulted = true;
+        break;
+      }
+      ++interval;
+      ++pc;
+    } else if (op == OP_ASSERT || op == OP_ASSUME) {
+      const int32_t c = fetch(fa, wa);
+      if (active && c == 0) raise(spc, op == OP_ASSERT ? F_ASSERT : F_ASSUME);
+      ++pc;
+    } else {  // OP_END
+      if (group_red(false, false, true) & 4u) faulted = true;
+      break;
+    }
+  }
+
+  // every wave leaves the loop at the same point; the earliest fault wins
+  if (faulted) {
+    if (my_fault != ~0ull) atomicMin(&ctl->fault, my_fault);
+    __syncthreads();
+  }
+  // the last interval (complete, or cut by a fault) is closed
+  if (tl == 0) {
+    atomicAdd(&P.inst_intervals[slot], interval + 1u);
+    P.epochs[ovl_index] = epoch_base + store_seq + 1u;
+    if (faulted) {
+      const u64 f = ctl->fault;
+      const uint32_t lid = (uint32_t)(f >> 17) & 1023u, fpc = (uint32_t)(f >> 5) & 4095u, code = (uint32_t)f & 7u;
+      // instance status: the lowest faulting work-group
+      atomicMin(&P.inst_fault[slot], ((u64)gid << 38) | ((u64)fpc << 26) | ((u64)lid << 16) | code);
+    }
+  }
+  // accesses of the group
+  u64 acc = n_acc;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  if (lane == 0 && acc) atomicAdd(&P.inst_acc[slot], acc);
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of u32 arrays (three-level, 1024 elements per block)
+// ---------------------------------------------------------------------------
+constexpr uint32_t SCAN_BLOCK = 1024;
+
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // 256 threads: inclusive scan via waves + LDS
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  uint32_t before = 0;
+  for (uint32_t i = 0; i < w; ++i) before += sh[i];
+  *total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* in, uint64_t m, uint32_t* sums) {
+  __shared__ uint32_t sh[4];
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * 4u;
+  uint32_t s = 0;
+  for (int k = 0; k < 4; ++k) if (base + k < m) s += in[base + k];
+  uint32_t total;
+  block_excl_scan_256(s, sh, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void scan_block_kernel(uint32_t* data, uint64_t m, const uint32_t* offs) {
+  __shared__ uint32_t sh[4];
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * 4u;
+  uint32_t v[4];
+  uint32_t s = 0;
+  for (int k = 0; k < 4; ++k) { v[k] = base + k < m ? data[base + k] : 0u; s += v[k]; }
+  uint32_t total;
+  uint32_t ex = block_excl_scan_256(s, sh, &total);
+  if (offs) ex += offs[blockIdx.x];
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < m) data[base + k] = ex;
+    ex += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits; n lives on the device
+// ---------------------------------------------------------------------------
+constexpr uint32_t RS_THREADS = 256, RS_ROUNDS = 16, RS_TILE = RS_THREADS * RS_ROUNDS;
+
+__global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, const u64* n_ptr, uint32_t shift,
+                                                      uint32_t* hist, uint32_t nblocks) {
+  __shared__ uint32_t h[256];
+  const uint32_t t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const u64 n = *n_ptr;
+  const u64 base = (u64)blockIdx.x * RS_TILE;
+  if (base < n) {
+    for (uint32_t i = t; i < RS_TILE; i += RS_THREADS) {
+      const u64 p = base + i;
+      if (p < n) atomicAdd(&h[(uint32_t)(keys[p] >> shift) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  hist[(size_t)t * nblocks + blockIdx.x] = h[t];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
+                                                         const u64* n_ptr, uint32_t shift,
+                                                         const uint32_t* offs, uint32_t nblocks) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[4][256];
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  const u64 n = *n_ptr;
+  const u64 tile0 = (u64)blockIdx.x * RS_TILE;
+  if (tile0 >= n) return;
+  base[t] = offs[(size_t)t * nblocks + blockIdx.x];
+  const u64 below = (1ull << lane) - 1ull;
+  for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+    const u64 p = tile0 + (u64)r * RS_THREADS + t;
+    const bool valid = p < n;
+    u64 k = 0;
+    V v = 0;
+    uint32_t d = 0;
+    if (valid) { k = kin[p]; v = vin[p]; d = (uint32_t)(k >> shift) & 255u; }
+    u64 eq = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      const u64 bb = __ballot((d >> b) & 1u);
+      eq &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(eq & below);
+    const uint32_t cnt = (uint32_t)__popcll(eq);
+    for (uint32_t ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
+    __syncthreads();
+    if (valid && rank == 0) wcnt[w][d] = cnt;
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base[d];
+      for (uint32_t ww = 0; ww < w; ++ww) off += wcnt[ww][d];
+      kout[off + rank] = k;
+      vout[off + rank] = v;
+    }
+    __syncthreads();
+    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// segment check
+// ---------------------------------------------------------------------------
+struct Pair {
+  uint32_t a, b;
+};
+__device__ __forceinline__ void pair_take(Pair& best, uint32_t x, uint32_t y) {
+  const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+  if (lo < best.a || (lo == best.a && hi < best.b)) { best.a = lo; best.b = hi; }
+}
+
+__device__ __forceinline__ uint32_t pay_lid(u64 p) { return (uint32_t)p & 1023u; }
+__device__ __forceinline__ bool pay_w(u64 p) { return ((uint32_t)p >> 10) & 1u; }
+__device__ __forceinline__ int32_t pay_val(u64 p) { return (int32_t)(uint32_t)(p >> 32); }
+
+// INTRA scope over records [s, e) of one work-group (ids compared by lid).
+__device__ bool intra_check(const u64* vals, u64 s, u64 e, uint32_t* label, Pair* rw, Pair* ww) {
+  const uint32_t NONE = 0xFFFFFFFFu;
+  uint32_t r1 = NONE;
+  u64 wmin = ~0ull;  // (lid, value ^ sign) of the smallest writer
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = vals[i];
+    const uint32_t l = pay_lid(p);
+    if (pay_w(p)) {
+      const u64 kx = ((u64)l << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
+      if (kx < wmin) wmin = kx;
+    } else if (l < r1) {
+      r1 = l;
+    }
+  }
+  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
+  uint32_t r2 = NONE, w2 = NONE, q = NONE;
+  bool multi1 = false;
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = vals[i];
+    const uint32_t l = pay_lid(p);
+    if (pay_w(p)) {
+      const int32_t v = pay_val(p);
+      if (l == w1) { if (v != x1) multi1 = true; }
+      else {
+        if (l < w2) w2 = l;
+        if (v != x1 && l < q) q = l;
+      }
+    } else if (l != r1 && l < r2) {
+      r2 = l;
+    }
+  }
+  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
+  const uint32_t rs[2] = {r1, r2}, ws[2] = {w1, w2};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (rs[i] != NONE && ws[j] != NONE && rs[i] != ws[j]) pair_take(brw, rs[i], ws[j]);
+  bool wwd = false;
+  if (multi1 && w2 != NONE) { bww = {w1, w2}; wwd = true; }
+  else if (q != NONE) { bww = {w1, q}; wwd = true; }
+  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
+  if (lab == 0u) {
+    if (w2 == NONE) return false;   // no eligible pair
+    lab = 4u;
+    bww = {w1, w2};
+  }
+  *label = lab;
+  *rw = brw;
+  *ww = bww;
+  return true;
+}
+
+// INTER scope over records [s, e) of one cell, all groups (global tids).
+__device__ bool inter_check(const u64* keys, const u64* vals, u64 s, u64 e, uint32_t bk, uint32_t gmask,
+                            uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
+  const uint32_t NONE = 0xFFFFFFFFu;
+  uint32_t r1 = NONE;
+  u64 wmin = ~0ull;
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = vals[i];
+    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
+    const uint32_t t = g * W + pay_lid(p);
+    if (pay_w(p)) {
+      const u64 kx = ((u64)t << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
+      if (kx < wmin) wmin = kx;
+    } else if (t < r1) {
+      r1 = t;
+    }
+  }
+  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
+  const uint32_t gr1 = r1 == NONE ? NONE : r1 / W;
+  const uint32_t g1 = w1 == NONE ? NONE : w1 / W;
+  uint32_t r1p = NONE, w1p = NONE, q = NONE, A = NONE;
+  bool multi1 = false;
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = vals[i];
+    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
+    const uint32_t t = g * W + pay_lid(p);
+    if (pay_w(p)) {
+      const int32_t v = pay_val(p);
+      if (t == w1) { if (v != x1) multi1 = true; }
+      if (g != g1) {
+        if (t < w1p) w1p = t;
+        if (v != x1 && t < q) q = t;
+      } else if (t != w1 && v != x1 && t < A) {
+        A = t;
+      }
+    } else if (g != gr1 && t < r1p) {
+      r1p = t;
+    }
+  }
+  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
+  const uint32_t rs[2] = {r1, r1p}, ws[2] = {w1, w1p};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (rs[i] != NONE && ws[j] != NONE && rs[i] / W != ws[j] / W) pair_take(brw, rs[i], ws[j]);
+  bool wwd = false;
+  if (multi1 && w1p != NONE) { bww = {w1, w1p}; wwd = true; }
+  else if (q != NONE) { bww = {w1, q}; wwd = true; }
+  else if (A != NONE && w1p != NONE) { bww = {A < w1p ? A : w1p, A < w1p ? w1p : A}; wwd = true; }
+  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
+  if (lab == 0u) {
+    if (w1p == NONE) return false;
+    lab = 4u;
+    bww = {w1, w1p};
+  }
+  *label = lab;
+  *rw = brw;
+  *ww = bww;
+  return true;
+}
+
+struct PendingRec {
+  uint32_t gid, interval, aid, cell, cellkey, label, lidbase;
+  Pair rw, ww;
+};
+
+__device__ __forceinline__ void write_record(const SegParams& S, u64 pos, uint32_t slot, const PendingRec& p,
+                                             bool inter) {
+  if (pos >= S.rec_cap) { atomicOr(S.status_word, 2u); return; }
+  const uint32_t NONE = 0xFFFFFFFFu;
+  rc_record_dev r;
+  r.instance = S.inst_offset + slot;
+  r.gid = inter ? NONE : p.gid;
+  r.interval = inter ? 0u : p.interval;
+  r.array_label = p.aid | (p.label << 16);
+  r.cell = p.cell;
+  r.rw_a = p.rw.a == NONE ? NONE : p.rw.a + p.lidbase;
+  r.rw_b = p.rw.b == NONE ? NONE : p.rw.b + p.lidbase;
+  r.ww_a = p.ww.a == NONE ? NONE : p.ww.a + p.lidbase;
+  r.ww_b = p.ww.b == NONE ? NONE : p.ww.b + p.lidbase;
+  r.pad = 0;
+  S.staging[pos] = r;
+  const u64 scope = inter ? (u64)S.G * S.NI : (u64)p.gid * S.NI + p.interval;
+  S.rec_keys[pos] = ((u64)slot << (S.bs + S.bc)) | (scope << S.bc) | p.cellkey;
+  S.rec_idx[pos] = (uint32_t)pos;
+}
+
+// One thread per sorted log entry.  The first entry of a run of equal keys
+// checks its INTRA(gid, interval) scope; the first entry of a cell's run
+// also checks the INTER scope (global arrays, several groups).
+__global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
+  const u64 n = *S.n_ptr;
+  const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  bool has_intra = false, has_inter = false;
+  uint32_t slot = 0;
+  PendingRec pa, pb;
+  if (i < n) {
+    const u64 k = S.keys[i];
+    const uint32_t low = S.bg + S.bk;
+    const bool sub_head = i == 0 || S.keys[i - 1] != k;
+    if (sub_head) {
+      const bool seg_head = i == 0 || (S.keys[i - 1] >> low) != (k >> low);
+      const uint32_t cmask = S.bc >= 32 ? 0xFFFFFFFFu : ((1u << S.bc) - 1u);
+      const uint32_t gmask = (1u << S.bg) - 1u, imask = (1u << S.bk) - 1u;
+      const uint32_t cellkey = (uint32_t)(k >> low) & cmask;
+      slot = (uint32_t)(k >> (low + S.bc));
+      const uint32_t gid = (uint32_t)(k >> S.bk) & gmask;
+      const uint32_t interval = (uint32_t)k & imask;
+      uint32_t aid = 0;
+      for (uint32_t a = 0; a < S.n_arrays; ++a) {
+        const uint32_t cb = S.cellbase[a];
+        if (cb != 0xFFFFFFFFu && cellkey >= cb && cellkey - cb < S.size[a]) aid = a;
+      }
+      const uint32_t cell = cellkey - S.cellbase[aid];
+      u64 e = i + 1;
+      while (e < n && S.keys[e] == k) ++e;
+      if (e - i >= 2) {
+        has_intra = intra_check(S.vals, i, e, &pa.label, &pa.rw, &pa.ww);
+        pa.gid = gid; pa.interval = interval; pa.aid = aid; pa.cell = cell; pa.cellkey = cellkey;
+        pa.lidbase = gid * S.W;
+      }
+      if (seg_head && S.G > 1 && aid < S.n_global) {
+        u64 f = e;
+        while (f < n && (S.keys[f] >> low) == (k >> low)) ++f;
+        if (f - i >= 2) {
+          has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, S.W, &pb.label, &pb.rw, &pb.ww);
+          pb.gid = gid; pb.interval = 0; pb.aid = aid; pb.cell = cell; pb.cellkey = cellkey;
+          pb.lidbase = 0;
+        }
+      }
+    }
+  }
+  const u64 m1 = __ballot(has_intra), m2 = __ballot(has_inter);
+  const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
+  if (c1 + c2 == 0) return;
+  u64 base = 0;
+  if (lane == 0) base = atomicAdd(S.rec_count, (u64)(c1 + c2));
+  const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
+  const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
+  base = ((u64)bhi << 32) | blo;
+  const u64 below = (1ull << lane) - 1ull;
+  if (has_intra) write_record(S, base + (u64)__popcll(m1 & below), slot, pa, false);
+  if (has_inter) write_record(S, base + c1 + (u64)__popcll(m2 & below), slot, pb, true);
+}
+
+// ---------------------------------------------------------------------------
+// ordered output and summaries
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
+  const u64 n = *Gp.n_ptr;
+  const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  bool valid = p < n;
+  uint32_t slot = 0;
+  bool race = false, benign = false;
+  if (valid) {
+    const rc_record_dev r = Gp.staging[Gp.idx[p]];
+    const u64 out = *Gp.out_base + p;
+    slot = r.instance - Gp.inst_offset;
+    const uint32_t label = r.array_label >> 16;
+    race = (label & 3u) != 0u;
+    benign = label == 4u;
+    if (out < Gp.cap) Gp.out[out] = r;
+    else atomicOr(&Gp.inst_flags[slot], 1u);
+  }
+  // aggregate per-instance counts over the wave when it holds one instance
+  const uint32_t s0 = __builtin_amdgcn_readfirstlane(slot);
+  const u64 same = __ballot(!valid || slot == s0);
+  if (same == ~0ull) {
+    const uint32_t nr = (uint32_t)__popcll(__ballot(race)), nb = (uint32_t)__popcll(__ballot(benign));
+    if (lane == 0) {
+      if (nr) atomicAdd(&Gp.inst_race[s0], nr);
+      if (nb) atomicAdd(&Gp.inst_benign[s0], nb);
+    }
+  } else if (valid) {
+    if (race) atomicAdd(&Gp.inst_race[slot], 1u);
+    if (benign) atomicAdd(&Gp.inst_benign[slot], 1u);
+  }
+}
+
+__global__ void advance_base_kernel(u64* out_base, const u64* n_ptr) { *out_base += *n_ptr; }
+
+// entries past a buffer's capacity were dropped (and flagged): later kernels
+// see at most `cap`
+__global__ void clamp_count_kernel(u64* n_ptr, u64 cap, uint32_t* status, uint32_t bit) {
+  if (*n_ptr > cap) {
+    *n_ptr = cap;
+    *status |= bit;
+  }
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinalParams F) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= F.n_slots) return;
+  rc_summary_dev o;
+  o.n_accesses = F.inst_acc[s];
+  o.n_race_cells = F.inst_race[s];
+  o.n_benign_cells = F.inst_benign[s];
+  o.n_intervals = F.inst_intervals[s];
+  const u64 f = F.inst_fault[s];
+  if (f == ~0ull) {
+    o.status = 0;
+    o.fault_gid = o.fault_pc = o.fault_tid = 0xFFFFFFFFu;
+  } else {
+    const uint32_t g = (uint32_t)(f >> 38), fpc = (uint32_t)(f >> 26) & 4095u, lid = (uint32_t)(f >> 16) & 1023u;
+    o.status = (int32_t)(f & 7u);
+    o.fault_gid = g;
+    o.fault_pc = fpc;
+    o.fault_tid = g * F.W + lid;
+  }
+  o.flags = F.inst_flags[s];
+  F.out[F.inst_offset + s] = o;
+}
+
+__global__ __launch_bounds__(256) void fill_u64_kernel(u64* p, u64 n, u64 v) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* p, u64 n, uint32_t v) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// final memory of one global array: highest writing work-group wins
+__global__ __launch_bounds__(256) void final_merge_kernel(FinalMemParams M) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M.size) return;
+  int32_t v = M.bind == BIND_SEEDED ? seeded_cell(M.seed, M.array_id, c, M.lo, M.hi) : M.dptr[c];
+  if (M.rw) {
+    for (uint32_t g = 0; g < M.G; ++g) {
+      const u64 w = M.overlay[(size_t)g * M.overlay_cells + M.offset + c];
+      if ((uint32_t)(w >> 42) >= M.epoch_used[g]) v = (int32_t)(uint32_t)w;
+    }
+  }
+  M.out[c] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t blocks_for(u64 n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
+
+hipError_t launch_interp(const InterpParams& P, size_t lds_bytes, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rc_interp_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(rc_interp_kernel, dim3(P.n_slots * P.G), dim3(P.nwaves * 64), lds_bytes, st, P);
+  return hipGetLastError();
+}
+
+// exclusive scan in place; tmp needs scan_tmp_words(m) words
+size_t scan_tmp_words(u64 m) {
+  size_t words = 0;
+  while (m > SCAN_BLOCK) {
+    m = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    words += m;
+  }
+  return words + 1;
+}
+
+static void scan_excl(uint32_t* data, u64 m, uint32_t* tmp, hipStream_t st) {
+  if (m <= SCAN_BLOCK) {
+    hipLaunchKernelGGL(scan_block_kernel, dim3(1), dim3(256), 0, st, data, m, (const uint32_t*)nullptr);
+    return;
+  }
+  const uint32_t nb = blocks_for(m, SCAN_BLOCK);
+  uint32_t* sums = tmp;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, st, (const uint32_t*)data, m, sums);
+  scan_excl(sums, nb, tmp + nb, st);
+  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, st, data, m, (const uint32_t*)sums);
+}
+
+size_t sort_hist_words(u64 cap) {
+  const u64 nb = (cap + RS_TILE - 1) / RS_TILE;
+  const u64 m = 256ull * (nb ? nb : 1);
+  return m + scan_tmp_words(m);
+}
+
+template <typename V>
+static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
+                                  uint32_t* hist, hipStream_t st, int* result_in_second) {
+  const uint32_t nb = blocks_for(cap ? cap : 1, RS_TILE);
+  const u64 m = 256ull * nb;
+  uint32_t* tmp = hist + m;
+  u64 *ka = k0, *kb = k1;
+  V *va = v0, *vb = v1;
+  int passes = 0;
+  for (uint32_t shift = 0; shift < nbits; shift += 8) {
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, n_ptr, shift, hist, nb);
+    scan_excl(hist, m, tmp, st);
+    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
+                       vb, n_ptr, shift, (const uint32_t*)hist, nb);
+    u64* tk = ka; ka = kb; kb = tk;
+    V* tv = va; va = vb; vb = tv;
+    ++passes;
+  }
+  *result_in_second = passes & 1;
+  return hipGetLastError();
+}
+
+hipError_t sort_pairs_u64(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
+                          uint32_t* hist, hipStream_t st, int* in_second) {
+  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, hist, st, in_second);
+}
+hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
+                          uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {
+  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, hist, st, in_second);
+}
+
+hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
+  hipLaunchKernelGGL(seg_check_kernel, dim3(blocks_for(cap ? cap : 1, 256)), dim3(256), 0, st, S);
+  return hipGetLastError();
+}
+hipError_t launch_gather(const GatherParams& G, u64 cap, hipStream_t st) {
+  hipLaunchKernelGGL(rec_gather_kernel, dim3(blocks_for(cap ? cap : 1, 256)), dim3(256), 0, st, G);
+  hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, st, G.out_base, G.n_ptr);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const FinalParams& F, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(F.n_slots, 256)), dim3(256), 0, st, F);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint32_t nb = blocks_for(n, 256);
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(nb), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, u64 n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint32_t nb = blocks_for(n, 256);
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(nb), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_clamp(u64* n_ptr, u64 cap, uint32_t* status, uint32_t bit, hipStream_t st) {
+  hipLaunchKernelGGL(clamp_count_kernel, dim3(1), dim3(1), 0, st, n_ptr, cap, status, bit);
+  return hipGetLastError();
+}
+hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st) {
+  hipLaunchKernelGGL(final_merge_kernel, dim3(blocks_for(M.size, 256)), dim3(256), 0, st, M);
+  return hipGetLastError();
+}
+
+}  // namespace rc

@@ -1,0 +1,123 @@
+// rc_internal.h -- bytecode format, compiled-program description and the
+// parameter blocks shared by the host front end and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace rc {
+
+// ---------------------------------------------------------------------------
+// Bytecode: every instruction is four 32-bit words {hdr, a, b, c}, so the
+// interpreter fetches one with a single 16-byte scalar load.
+//   hdr = op:6 | fa:1 | fb:1 | sub:6 | dst:6 | pc:12      (low bits first)
+//   fa / fb: operand a / b is an immediate (else a source selector)
+// ---------------------------------------------------------------------------
+enum Op : uint32_t {
+  OP_BIN = 1,     // R[dst] = a <sub> b
+  OP_UN = 2,      // R[dst] = <sub> a
+  OP_LOAD = 3,    // R[dst] = array c [a]
+  OP_STORE = 4,   // array c [a] = b
+  OP_IF = 5,      // cond a; b = index of the matching OP_ELSE
+  OP_ELSE = 6,    // c = index of the matching OP_ENDIF
+  OP_ENDIF = 7,
+  OP_FOR = 8,     // var dst, slot sub, lo a, hi b, c = index after OP_ENDFOR
+  OP_ENDFOR = 9,  // var dst, slot sub, lo a, hi b, c = index of the first body instruction
+  OP_BARRIER = 10,
+  OP_ASSERT = 11, // cond a
+  OP_ASSUME = 12, // cond a
+  OP_END = 13,
+};
+
+enum BinOp : uint32_t {
+  B_ADD, B_SUB, B_MUL, B_DIV, B_REM, B_MOD, B_AND, B_OR, B_XOR, B_SHL, B_SHR,
+  B_LT, B_LE, B_GT, B_GE, B_EQ, B_NE, B_LAND, B_LOR, B_MIN, B_MAX, B_COUNT
+};
+enum UnOp : uint32_t { U_MOV, U_NEG, U_BNOT, U_LNOT };
+
+// source selectors (operands that are not immediates)
+enum : uint32_t {
+  MAX_REGS = 64,
+  SEL_LID = 64, SEL_TID = 65, SEL_GID = 66, SEL_WGSIZE = 67, SEL_NGROUPS = 68,
+  SEL_NTHREADS = 69, SEL_SCALAR0 = 96,
+};
+
+inline uint32_t make_hdr(uint32_t op, bool fa, bool fb, uint32_t sub, uint32_t dst, uint32_t pc) {
+  return (op & 63u) | (uint32_t(fa) << 6) | (uint32_t(fb) << 7) | ((sub & 63u) << 8) |
+         ((dst & 63u) << 14) | ((pc & 4095u) << 20);
+}
+
+// fault codes (rc_summary.status)
+enum : uint32_t { F_OK = 0, F_OOB = 1, F_DIV = 2, F_ASSERT = 3, F_ASSUME = 4, F_BARDIV = 5 };
+
+// limits
+enum : uint32_t {
+  MAX_GLOBAL_ARRAYS = 8, MAX_LOCAL_ARRAYS = 8, MAX_ARRAYS = 16, MAX_SCALARS = 16,
+  MAX_VARS = 32, MAX_STMTS = 4096, MAX_NEST = 16, MAX_WG = 1024, MAX_WAVES = 16,
+};
+
+// array kinds as the interpreter sees them
+enum : uint32_t {
+  AK_LOCAL = 0,        // work-group local array in LDS (u64 cells: version | value)
+  AK_GLOBAL_RW = 1,    // written global array: per-group overlay in the workspace
+  AK_GLOBAL_RO = 2,    // never-written global array: read its input directly
+};
+enum : uint32_t { BIND_NONE = 0, BIND_SEEDED = 1, BIND_DEVICE = 2 };
+
+struct ArrayDesc {        // 48 bytes
+  uint32_t kind;          // AK_*
+  uint32_t size;          // cells
+  uint32_t logged;        // accesses go to the access log (array is written somewhere)
+  uint32_t bind;          // BIND_* (global arrays)
+  int64_t lo, hi;         // seeded range
+  const int32_t* dptr;    // device binding
+  uint32_t offset;        // LDS cell offset (local) or overlay cell offset (global rw)
+  uint32_t cellbase;      // first cell key of this array in the log key space
+};
+
+struct ScalarDesc {
+  uint32_t bind;          // BIND_SEEDED or fixed value
+  int32_t value;
+  int64_t lo, hi;
+};
+
+// Parameters of one interpreter launch (passed by value).
+struct InterpParams {
+  const uint32_t* code;                      // 4 words per instruction
+  uint32_t n_arrays, n_global, n_scalars, nregs;
+  uint32_t G, W, nwaves, lds_local_cells;   // u64 cells of local arrays in LDS
+  uint32_t n_slots;                          // instances in this pass (grid = n_slots * G)
+  uint32_t overlay_cells;                    // u64 cells per (slot, group) overlay
+  uint32_t max_store_seq;                    // static bound of store statements per group run
+  uint32_t inst_offset;                      // first instance index of this pass
+  uint64_t seed0;
+  // log key layout: [instance : bi][cellkey : bc][gid : bg][interval : bk]
+  uint32_t bc, bg, bk, pad0;
+  const ArrayDesc* arrays;                   // device copy of the descriptor table
+  const ScalarDesc* scalars;
+  // workspace pointers
+  uint32_t* epochs;         // [n_slots * G] next free epoch per overlay
+  uint32_t* epoch_used;     // [n_slots * G] epoch base used by the last run
+  unsigned long long* overlay;        // [n_slots * G * overlay_cells]
+  unsigned long long* log_keys;       // access log
+  unsigned long long* log_vals;
+  unsigned long long* log_count;      // u64 counter
+  uint64_t log_cap;
+  unsigned long long* inst_acc;       // [n_slots] accesses
+  unsigned int* inst_intervals;       // [n_slots]
+  unsigned long long* inst_fault;     // [n_slots] min (gid, pc, lid, code) key
+  unsigned int* status_word;          // bit 0: internal log overflow
+  int do_log;                          // 0: run only (final memory)
+};
+
+// LDS control block of the interpreter (after the local cells and registers)
+struct Ctl {
+  unsigned long long fault;             // min fault key of the group (~0 = none)
+  uint32_t red[2][MAX_WAVES];           // per-wave reduction words, double-buffered
+  int32_t scal[MAX_SCALARS];
+  uint32_t loopctr[MAX_WAVES][MAX_NEST];
+  uint32_t epoch_base;
+  uint32_t pad;
+};
+
+constexpr uint32_t LDS_LIMIT = 160u * 1024u;
+
+}  // namespace rc

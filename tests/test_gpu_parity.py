@@ -1,0 +1,232 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle,
+record for record and summary for summary, on the same seeded instances."""
+import random
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_3203_amd import binding as B
+from paper_1308_3203_amd import workloads as WL
+from tests import gpu_util as U
+from tests import interleave as IL
+
+pytestmark = pytest.mark.gpu
+
+
+def both(src, G, W, arrays=None, scalars=None, seed0=0, n=1, **kw):
+    dev_arrays = U.host_arrays_to_device(arrays)
+    g = U.gpu_run(src, G, W, dev_arrays, scalars, seed0, n, **kw)
+    o = U.oracle_run(src, G, W, arrays, scalars, seed0, n)
+    return g, o
+
+
+# ---------------------------------------------------------------------------
+# the paper's examples
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("one_based", [False, True])
+@pytest.mark.parametrize("n", [4, 64, 65, 200])
+def test_fig1(n, one_based):
+    w = WL.fig1(n, one_based)
+    g, o = both(w.src, w.G, w.W, w.arrays, n=3)
+    U.assert_same(g, o, w.name)
+
+
+@pytest.mark.parametrize("n", [2, 64, 100])
+def test_fig3(n):
+    w = WL.fig3(n)
+    g, o = both(w.src, w.G, w.W, w.arrays, seed0=5, n=8)
+    U.assert_same(g, o, w.name)
+
+
+# ---------------------------------------------------------------------------
+# c1: one random kernel, 1000 seeds
+# ---------------------------------------------------------------------------
+def test_c1_all_seeds():
+    w = WL.c1_kernel(1)
+    g, o = both(w.src, w.G, w.W, w.arrays, seed0=0, n=1000)
+    U.assert_same(g, o, "c1")
+
+
+@pytest.mark.parametrize("pseed", [2, 3, 4, 5])
+def test_c1_other_programs(pseed):
+    w = WL.c1_kernel(pseed)
+    g, o = both(w.src, w.G, w.W, w.arrays, seed0=100, n=50)
+    U.assert_same(g, o, w.name)
+
+
+# ---------------------------------------------------------------------------
+# random small kernels across launch shapes (single and multi-wave groups,
+# ragged last waves, several groups)
+# ---------------------------------------------------------------------------
+SHAPES = [(1, 1), (1, 7), (1, 64), (1, 65), (2, 33), (3, 130), (1, 256), (2, 300), (1, 1000), (4, 1024)]
+
+
+@pytest.mark.parametrize("G,W", SHAPES)
+@pytest.mark.parametrize("pseed", range(3))
+def test_random_shapes(G, W, pseed):
+    r = random.Random(pseed * 101 + W)
+    prog, arrays, vars_ = IL.random_program(r, r.randint(4, 12), r.choice([4, 16, 64]), r.randint(0, 3))
+    src = IL.render(prog, arrays, vars_)
+    g, o = both(src, G, W, {a: ("seeded", 0, 4) for a in arrays}, seed0=pseed, n=4)
+    U.assert_same(g, o, f"random G={G} W={W}\n{src}")
+
+
+# ---------------------------------------------------------------------------
+# control flow, faults, int32 semantics
+# ---------------------------------------------------------------------------
+FAULTS = [
+    "kernel k(global int A[8]) { int v; A[tid % 8] := 1; v := 5 / (tid - 3); A[tid % 8] := v; }",
+    "kernel k(global int A[8]) { int v; A[0] := tid; v := 1 mod (tid - 70); }",
+    "kernel k(global int A[8]) { assert(tid < 5); }",
+    "kernel k(global int A[8]) { A[0] := 1; assume(tid != 100); }",
+    "kernel k(global int A[8]) { if (tid < 2) { barrier; } }",
+    "kernel k(global int A[8]) { if (lid < 70) { barrier; } }",
+    "kernel k(global int A[8]) { A[tid + 6] := 1; }",
+    "kernel k(global int A[8]) { int v; v := A[(tid * 7) mod 9]; }",
+    """kernel k(global int A[8]) { int i, v;
+       for i in 0..3 { v := 1 / (i - 1 + 100 * tid); v := 1 / (tid - 67); } }""",
+    """kernel k(global int A[64]) { int v; A[lid % 64] := tid; v := 1 / (gid - 1); v := 2 / (gid - 2); }""",
+    """kernel k(global int A[8]) { int v; A[9] := 5 / (tid - 3); }""",
+]
+
+
+@pytest.mark.parametrize("src", FAULTS)
+@pytest.mark.parametrize("G,W", [(1, 8), (1, 100), (4, 130)])
+def test_faults(src, G, W):
+    g, o = both(src, G, W, {"A": ("seeded", 0, 16)}, n=2)
+    U.assert_same(g, o, src)
+
+
+CONTROL = [
+    """kernel k(global int A[256], global int B[256]) { int i, j, v, w;
+       for i in 0..5 { for j in 2..4 { v := A[(tid + i * j) mod 256]; if (v < 8) { B[tid mod 256] := v + i; } else { w := v * j; } } barrier; }
+       if ((tid & 3) == 1) { B[(tid * 3) mod 256] := w; } else { if (tid > 100) { v := B[5]; } } }""",
+    """kernel k(global int A[64]) { int i, v; for i in 0..0 { A[0] := 1; } for i in 5..2 { A[1] := 2; } v := i; A[tid mod 64] := v; }""",
+    """kernel k(global int A[64], int s, int t) { int v; v := s * tid + t; A[(v mod 64)] := v; barrier; v := A[(tid + 1) mod 64]; }""",
+    """kernel k(global int A[32]) { local int L[32]; int v; L[lid mod 32] := tid; barrier; v := L[(lid + 1) mod 32]; A[lid mod 32] := v; L[0] := v; }""",
+    """kernel k(global int A[16]) { int v; if (tid == 0) { v := A[3]; } if (tid == 1) { A[3] := 5; } if (tid == 2) { A[3] := 6; } if (tid == 3) { A[3] := 5; } }""",
+]
+
+
+@pytest.mark.parametrize("src", CONTROL)
+@pytest.mark.parametrize("G,W", [(1, 4), (1, 64), (2, 100), (3, 257)])
+def test_control_flow(src, G, W):
+    scal = {"s": ("seeded", -1000, 1000), "t": 7} if "int s" in src else None
+    g, o = both(src, G, W, {"A": ("seeded", 0, 16)} | ({"B": ("seeded", 0, 16)} if "B[" in src else {}),
+                scal, seed0=9, n=3)
+    U.assert_same(g, o, src)
+
+
+def test_int32_corners_final_memory():
+    src = """kernel ar(global int out[24], int m) {
+      out[0] := 0 - 7 / 2; out[1] := (0 - 7) / 2; out[2] := (0 - 7) % 2; out[3] := (0 - 7) mod 2;
+      out[4] := 7 mod (0 - 2); out[5] := m / (0 - 1); out[6] := m % (0 - 1); out[7] := 1 << 33;
+      out[8] := (0 - 8) >> 1; out[9] := (0 - 1) >> 40; out[10] := m - 1; out[11] := 2147483647 + 1;
+      out[12] := 65536 * 65536; out[13] := 0 - m; out[14] := m mod 3; out[15] := (0 - 7) mod (0 - 2);
+      out[16] := (3 < 4) + (4 <= 4) * 2 + (5 == 5) * 4 + !0 * 8 + (0 && 1) * 16 + (0 || 2) * 32;
+      out[17] := ~5; out[18] := min(0 - 3, 2) * 10 + max(0 - 3, 2); out[19] := (12 ^ 10) + (12 | 3) * 100;
+      out[20] := 4294967295; out[21] := (0 - 9) >> 2; out[22] := m >> 31; out[23] := 7 % (0 - 3); }"""
+    import torch
+    prog = B.Program(U.ctx(), src)
+    prog.set_ndrange(1, 1)
+    prog.bind({"out": torch.zeros(24, dtype=torch.int32, device="cuda")}, {"m": -(2 ** 31)})
+    ws = torch.empty(prog.workspace_size(1), dtype=torch.uint8, device="cuda")
+    fin = prog.read_final(0, "out", ws)
+    U.ctx().sync()
+    orc = O.check(src, 1, 1, arrays={"out": np.zeros(24, np.int32)}, scalars={"m": -(2 ** 31)}, final="out")
+    assert np.array_equal(fin.cpu().numpy(), orc.final)
+
+
+# ---------------------------------------------------------------------------
+# c2 templates
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("w", WL.c2_templates(), ids=lambda w: w.name)
+def test_c2_templates(w):
+    g, o = both(w.src, w.G, w.W, w.arrays, seed0=0, n=4)
+    U.assert_same(g, o, w.name)
+
+
+@pytest.mark.parametrize("tmpl", ["tree_reduce", "prefix_sum", "transpose"])
+def test_c2_final_memory(tmpl):
+    import torch
+    w = getattr(WL, tmpl)(False)
+    prog = B.Program(U.ctx(), w.src)
+    prog.set_ndrange(w.G, w.W)
+    x = np.random.default_rng(1).integers(-(2 ** 31), 2 ** 31, 65536, dtype=np.int64).astype(np.int32)
+    out0 = np.random.default_rng(2).integers(-(2 ** 31), 2 ** 31, 65536, dtype=np.int64).astype(np.int32)
+    prog.bind({"inp": torch.from_numpy(x).cuda(), "out": torch.from_numpy(out0).cuda()})
+    ws = torch.empty(prog.workspace_size(1), dtype=torch.uint8, device="cuda")
+    fin = prog.read_final(0, "out", ws).cpu().numpy()
+    U.ctx().sync()
+    orc = O.check(w.src, w.G, w.W, arrays={"inp": x, "out": out0}, final="out")
+    assert np.array_equal(fin, orc.final)
+
+
+# ---------------------------------------------------------------------------
+# c3 random kernels and c4 large intervals
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pseed", range(0, 24))
+def test_c3_kernels(pseed):
+    w = WL.c3_kernel(pseed)
+    g, o = both(w.src, w.G, w.W, w.arrays, seed0=0, n=2)
+    U.assert_same(g, o, w.name)
+
+
+@pytest.mark.parametrize("groups,wg,iters", [(4, 64, 8), (8, 256, 16), (3, 1000, 4)])
+def test_c4_scaled(groups, wg, iters):
+    w = WL.c4_kernel(groups, wg, iters, log2_cells=14)
+    g, o = both(w.src, w.G, w.W, w.arrays, w.scalars, seed0=3, n=3)
+    U.assert_same(g, o, f"c4 {groups}x{wg}x{iters}")
+
+
+def test_c4_full_size_one_seed():
+    w = WL.c4_kernel()
+    g, o = both(w.src, w.G, w.W, w.arrays, w.scalars, seed0=0, n=1, cap=1 << 21)
+    U.assert_same(g, o, "c4 full")
+
+
+# ---------------------------------------------------------------------------
+# library mechanics
+# ---------------------------------------------------------------------------
+def test_determinism_and_passes():
+    w = WL.c1_kernel(7)
+    a = U.gpu_run(w.src, w.G, w.W, w.arrays, None, 0, 300)
+    b = U.gpu_run(w.src, w.G, w.W, w.arrays, None, 0, 300)
+    assert a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+    # a workspace that fits only a few instances per pass gives the same bytes
+    prog = B.Program(U.ctx(), w.src)
+    prog.set_ndrange(w.G, w.W)
+    small = prog.workspace_size(7)
+    c = U.gpu_run(w.src, w.G, w.W, w.arrays, None, 0, 300, ws_limit=small)
+    assert a[0].tobytes() == c[0].tobytes() and a[1].tobytes() == c[1].tobytes()
+
+
+def test_record_overflow():
+    w = WL.fig1(64, True)
+    with pytest.raises(B.RcError) as ei:
+        U.gpu_run(w.src, w.G, w.W, w.arrays, None, 0, 4, cap=100)
+    assert ei.value.status == B.RC_E_OVERFLOW
+
+
+def test_api_errors():
+    ctx = U.ctx()
+    with pytest.raises(B.RcError) as ei:
+        B.Program(ctx, "kernel k(global int A[4]) { v := 1; }")
+    assert ei.value.status == B.RC_E_PARSE
+    p = B.Program(ctx, "kernel k(global int A[4]) { A[0] := 1; }")
+    with pytest.raises(B.RcError) as ei:
+        p.set_ndrange(1, 2000)
+    assert ei.value.status == B.RC_E_LIMIT
+    with pytest.raises(B.RcError) as ei:
+        p.workspace_size(1)
+    assert ei.value.status == B.RC_E_STATE
+    p.set_ndrange(1, 4)
+    import torch
+    ws = torch.empty(p.workspace_size(1), dtype=torch.uint8, device="cuda")
+    rec = torch.empty(400, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    summ = torch.empty(40, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.RcError) as ei:
+        p.check_async(0, 1, ws, rec, cnt, summ)     # A is unbound
+    assert ei.value.status == B.RC_E_STATE

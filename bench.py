@@ -1,0 +1,163 @@
+"""Benchmark of the race-check hot path on one MI355X.
+
+A step is one pass of the whole path (interpretation, access logging, interval
+checks, ordered race report) over one batch of synthetic instances, with inputs
+seeded on the device.  Prints one JSON line.
+
+    python bench.py [--config c2] [--steps K] [--warmup W] [--seeds N]
+
+Configs: c1 (one random 20-statement kernel, 1 x 64, 1000 seeds),
+c2 (six template kernels, 16 x 256, 10^4 seeds each; the default),
+c4 (large intervals, 64 x 1024 x 64 iterations, 16 seeds).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per race-checked access: the simulated cell (4 B), the
+# 12-byte access record written once (interpretation) and read once (check)
+ALGO_BYTES = {"interpret": 16.0, "interval_check": 12.0}
+KERNEL_OF_PHASE = {"interpret": "rc_interp_kernel", "log_sort": "rs_scatter_kernel/rs_hist_kernel",
+                   "interval_check": "seg_check_kernel", "record_sort": "rs_scatter_kernel/rs_hist_kernel",
+                   "output": "rec_gather_kernel", "setup": "fill kernels"}
+
+
+def workload(name: str, seeds: int | None):
+    from paper_1308_3203_amd import workloads as WL
+    if name == "c1":
+        return [(WL.c1_kernel(1), seeds or 1000)], "c1: one random 20-statement kernel, G=1 x W=64"
+    if name == "c2":
+        return ([(w, seeds or 10000) for w in WL.c2_templates()],
+                "c2: tree reduction, Hillis-Steele prefix sum, 32x32 tiled transpose (clean + injected), G=16 x W=256")
+    if name == "c4":
+        return [(WL.c4_kernel(), seeds or 16)], "c4: large intervals, G=64 x W=1024 x 64 iterations, 2^20 cells"
+    raise SystemExit(f"unknown config {name}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--seeds", type=int, default=None, help="seeds per program (default: the config's)")
+    ap.add_argument("--ws-gb", type=float, default=48.0, help="workspace budget over all programs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1308_3203_amd import binding as B
+
+    progs, desc = workload(args.config, args.seeds)
+    ctx = B.Context(0)
+    runs = []
+    per_ws = int(args.ws_gb * (1 << 30) / len(progs))
+    for w, n in progs:
+        p = B.Program(ctx, w.src)
+        p.set_ndrange(w.G, w.W)
+        p.bind(w.arrays, w.scalars)
+        buf = B.Buffers(p, n, cap=1 << 24, ws_limit=per_ws)
+        runs.append((w, n, p, buf))
+
+    def step(seed0):
+        for w, n, p, buf in runs:
+            p.check_async(seed0, n, buf.ws, buf.records, buf.n_records, buf.summaries)
+
+    # warmup (also the first-use clearing of each workspace); instances checked
+    # per step are deterministic, so the access count is taken here
+    for i in range(max(1, args.warmup)):
+        step(0)
+        ctx.sync()
+    accesses = 0
+    records = 0
+    race_instances = 0
+    for w, n, p, buf in runs:
+        s = B.summaries_to_numpy(buf.summaries, n)
+        accesses += int(s["n_accesses"].sum())
+        records += int(buf.n_records.item())
+        race_instances += int((s["n_race_cells"] > 0).sum())
+
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(0)
+        ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    elapsed = t1 - t0
+    value = accesses * args.steps / elapsed
+
+    # roofline of the dominant phase
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, launches = prof[dom]
+    per_launch_ms = ms / max(1, launches)
+    units_per_launch = accesses * args.steps / max(1, launches)
+    algo = ALGO_BYTES.get(dom, 0.0) * units_per_launch
+    achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": KERNEL_OF_PHASE[dom], "phase": dom,
+                "avg_launch_ms": round(per_launch_ms, 4),
+                "phases_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+                "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline([(w, n) for w, n, _, _ in runs], args.cpu_seconds)
+
+    line = {
+        "metric": "race-checked accesses/s", "value": round(value, 1), "unit": "accesses/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": desc, "programs": len(runs), "seeds_per_program": runs[0][1],
+                   "instances_per_step": sum(n for _, n, _, _ in runs),
+                   "accesses_per_step": accesses, "race_records_per_step": records,
+                   "racy_instances_per_step": race_instances},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(programs, budget_s: float):
+    """The oracle as it stands, single-threaded, on a bounded sample of the
+    same instances (round-robin over the programs, seeds from 0)."""
+    from oracle import oracle as O
+    compiled = [(w, O.Program(w.src)) for w, _ in programs]
+    t_total = 0.0
+    acc = 0
+    n_inst = 0
+    seed = 0
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < budget_s:
+        for w, p in compiled:
+            t = time.perf_counter()
+            r = p.run(w.G, w.W, arrays=w.arrays, scalars=w.scalars, seed=seed, instance=seed)
+            t_total += time.perf_counter() - t
+            acc += int(r.summary["n_accesses"])
+            n_inst += 1
+            if time.perf_counter() - t_start >= budget_s:
+                break
+        seed += 1
+    return {"value": round(acc / t_total, 1), "unit": "accesses/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_inst} instances (seeds from 0, round-robin over {len(compiled)} programs), "
+                      f"{acc} accesses in {t_total:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

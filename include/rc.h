@@ -111,6 +111,20 @@ rc_status rc_ctx_destroy(rc_ctx* ctx);
 /* Replace the borrowed stream (same rules as rc_ctx_create). */
 rc_status rc_ctx_set_stream(rc_ctx* ctx, void* hip_stream);
 
+/* Per-phase device time of the work enqueued while profiling is on, measured
+ * with HIP events on the context's stream.  Phases: 0 interpretation, 1 log
+ * sort, 2 interval check, 3 record sort, 4 ordered output and summaries,
+ * 5 per-pass setup. */
+#define RC_N_PHASES 6
+typedef struct {
+  double ms[8];          /* summed elapsed time per phase                   */
+  uint32_t launches[8];  /* number of timed spans per phase                 */
+} rc_profile;
+/* Start (enable = 1) or stop (0) timing; starting clears earlier timings. */
+rc_status rc_ctx_profile(rc_ctx* ctx, int enable);
+/* Wait for the stream and return the timings gathered so far (then clear). */
+rc_status rc_ctx_profile_read(rc_ctx* ctx, rc_profile* out);
+
 /* ---- program ------------------------------------------------------------ */
 
 /* Parse, validate and compile program text (Section 3 language; the surface

@@ -36,14 +36,20 @@ EXPORTS = [
     "rc_last_error", "rc_ctx_create", "rc_ctx_destroy", "rc_ctx_set_stream", "rc_prog_load",
     "rc_prog_free", "rc_prog_get_info", "rc_prog_array", "rc_prog_scalar", "rc_set_ndrange",
     "rc_bind_seeded", "rc_bind_device", "rc_bind_scalar_seeded", "rc_bind_scalar",
-    "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final",
+    "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
+    "rc_ctx_profile_read",
 ]
+PHASES = ["interpret", "log_sort", "interval_check", "record_sort", "output", "setup"]
 
 
 class RcError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"rc status {status}: {msg}")
         self.status = status
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint32 * 8)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -86,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "rc_check": ([vp, u64, u32, vp, sz, vp, u64, vp, vp], ctypes.c_int),
         "rc_sync": ([vp], ctypes.c_int),
         "rc_read_final": ([vp, u64, u32, vp, vp, sz], ctypes.c_int),
+        "rc_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
+        "rc_ctx_profile_read": ([vp, ctypes.POINTER(_Profile)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -116,6 +124,15 @@ class Context:
 
     def sync(self):
         _call(_lib.rc_sync, self._h)
+
+    def profile(self, enable: bool = True):
+        _call(_lib.rc_ctx_profile, self._h, 1 if enable else 0)
+
+    def profile_read(self) -> dict:
+        """Per-phase {name: (total ms, spans)} since profiling started."""
+        out = _Profile()
+        _call(_lib.rc_ctx_profile_read, self._h, ctypes.byref(out))
+        return {PHASES[i]: (float(out.ms[i]), int(out.launches[i])) for i in range(len(PHASES))}
 
     def close(self):
         if getattr(self, "_h", None):

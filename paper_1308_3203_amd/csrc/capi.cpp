@@ -60,6 +60,10 @@ struct Pending {
 struct rc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool profiling = false;
+  std::vector<hipEvent_t> events;            // pool, reused after each read
+  size_t events_used = 0;
+  std::vector<std::pair<int, size_t>> spans; // (phase, index of the start event)
   std::map<void*, std::string> ws_sig;   // workspace -> layout of its persistent part
   std::vector<Pending> pending;
   rc_status deferred = RC_OK;
@@ -83,15 +87,42 @@ struct rc_prog {
 
 namespace {
 
+// record a HIP event on the ctx stream when profiling; returns its pool index
+rc_status prof_mark(rc_ctx* ctx, size_t* idx) {
+  if (!ctx->profiling) return RC_OK;
+  if (ctx->events_used == ctx->events.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    ctx->events.push_back(e);
+  }
+  *idx = ctx->events_used++;
+  HIP_TRY(hipEventRecord(ctx->events[*idx], ctx->stream));
+  return RC_OK;
+}
+
+struct PhaseTimer {
+  rc_ctx* ctx;
+  int phase;
+  size_t start = 0;
+  PhaseTimer(rc_ctx* c, int ph) : ctx(c), phase(ph) {
+    if (ctx->profiling) prof_mark(ctx, &start);
+  }
+  ~PhaseTimer() {
+    if (!ctx->profiling) return;
+    size_t end = 0;
+    if (prof_mark(ctx, &end) == RC_OK && end == start + 1) ctx->spans.push_back({phase, start});
+  }
+};
+
 struct Layout {
   uint32_t n_slots = 0;
-  u64 log_cap = 0, rec_cap = 0;
+  u64 log_cap = 0, rec_cap = 0, wg_log_cap = 0;
   uint32_t bi = 0, bc = 0, bg = 0, bk = 0, bs = 0, nbits_log = 0, nbits_rec = 0;
   uint32_t NI = 0;
   // persistent
   size_t epochs = 0, epoch_used = 0, overlay = 0, persistent_end = 0;
   // per pass
-  size_t counters = 0, inst_acc = 0, inst_fault = 0, inst_int = 0, inst_race = 0, inst_benign = 0, inst_flags = 0;
+  size_t counters = 0, wg_count = 0, inst_acc = 0, inst_fault = 0, inst_int = 0, inst_race = 0, inst_benign = 0, inst_flags = 0;
   size_t lk0 = 0, lv0 = 0, lk1 = 0, lv1 = 0, hist = 0, stage = 0, rk0 = 0, ri0 = 0, rk1 = 0, ri1 = 0;
   size_t total = 0;
   std::string signature;
@@ -106,7 +137,8 @@ bool make_layout(const rc_prog* p, uint32_t n_slots, Layout* L, std::string* why
   const u64 items = (u64)n_slots * p->G * p->W;
   const double logcap = (double)items * (double)c.dyn_logged_mem;
   if (logcap > 4.0e9) { *why = "access-log bound exceeds 4e9 entries for this pass"; return false; }
-  L->log_cap = std::max<u64>(1, (u64)logcap);
+  L->wg_log_cap = std::max<u64>(1, (u64)p->W * c.dyn_logged_mem);
+  L->log_cap = L->wg_log_cap * n_slots * p->G;
   L->rec_cap = L->log_cap;
   L->NI = (uint32_t)std::min<u64>(c.max_intervals, 0xFFFFFFFFull);
   L->bi = bits_for(n_slots);
@@ -128,6 +160,7 @@ bool make_layout(const rc_prog* p, uint32_t n_slots, Layout* L, std::string* why
   L->overlay = take(ovl * (u64)p->overlay_cells * 8);
   L->persistent_end = o;
   L->counters = take(CNT_WORDS * 8);
+  L->wg_count = take((size_t)n_slots * p->G * 4);
   L->inst_acc = take((size_t)n_slots * 8);
   L->inst_fault = take((size_t)n_slots * 8);
   L->inst_int = take((size_t)n_slots * 4);
@@ -138,7 +171,8 @@ bool make_layout(const rc_prog* p, uint32_t n_slots, Layout* L, std::string* why
   L->lv0 = take(L->log_cap * 8);
   L->lk1 = take(L->log_cap * 8);
   L->lv1 = take(L->log_cap * 8);
-  L->hist = take(std::max(sort_hist_words(L->log_cap), sort_hist_words(L->rec_cap)) * 4);
+  L->hist = take(std::max(sort_log_hist_words((u64)n_slots * p->G, L->wg_log_cap, L->log_cap),
+                          sort_hist_words(L->rec_cap)) * 4);
   L->stage = take(L->rec_cap * sizeof(rc_record));
   L->rk0 = take(L->rec_cap * 8);
   L->ri0 = take(L->rec_cap * 4);
@@ -212,8 +246,8 @@ InterpParams interp_params(const rc_prog* p, const Layout& L, char* ws, uint64_t
   u64* cnt = (u64*)(ws + L.counters);
   P.log_keys = (u64*)(ws + L.lk0);
   P.log_vals = (u64*)(ws + L.lv0);
-  P.log_count = cnt + CNT_LOG;
-  P.log_cap = L.log_cap;
+  P.wg_count = (uint32_t*)(ws + L.wg_count);
+  P.wg_log_cap = L.wg_log_cap;
   P.inst_acc = (u64*)(ws + L.inst_acc);
   P.inst_intervals = (uint32_t*)(ws + L.inst_int);
   P.inst_fault = (u64*)(ws + L.inst_fault);
@@ -262,7 +296,31 @@ rc_status rc_ctx_create(int device, void* hip_stream, rc_ctx** out) {
 
 rc_status rc_ctx_destroy(rc_ctx* ctx) {
   if (!ctx) return fail(RC_E_INVAL, "ctx is NULL");
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   delete ctx;
+  return RC_OK;
+}
+
+rc_status rc_ctx_profile(rc_ctx* ctx, int enable) {
+  if (!ctx) return fail(RC_E_INVAL, "ctx is NULL");
+  ctx->profiling = enable != 0;
+  ctx->spans.clear();
+  ctx->events_used = 0;
+  return RC_OK;
+}
+
+rc_status rc_ctx_profile_read(rc_ctx* ctx, rc_profile* out) {
+  if (!ctx || !out) return fail(RC_E_INVAL, "NULL argument");
+  memset(out, 0, sizeof *out);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (const auto& sp : ctx->spans) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->events[sp.second], ctx->events[sp.second + 1]));
+    out->ms[sp.first] += ms;
+    out->launches[sp.first] += 1;
+  }
+  ctx->spans.clear();
+  ctx->events_used = 0;
   return RC_OK;
 }
 
@@ -487,16 +545,24 @@ rc_status rc_check(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, siz
   const size_t lds = lds_bytes(p);
   for (uint32_t off = 0; off < n_seeds; off += L.n_slots) {
     const uint32_t n = std::min(L.n_slots, n_seeds - off);
-    s = reset_pass(p, L, ws, st);
-    if (s) return s;
+    {
+      PhaseTimer t(ctx, 5);
+      s = reset_pass(p, L, ws, st);
+      if (s) return s;
+    }
     InterpParams P = interp_params(p, L, ws, seed0, off, n, 1);
-    HIP_TRY(launch_interp(P, lds, st));
-    HIP_TRY(launch_clamp(cnt + CNT_LOG, L.log_cap, (uint32_t*)(cnt + CNT_STATUS), 1u, st));
+    {
+      PhaseTimer t(ctx, 0);
+      HIP_TRY(launch_interp(P, lds, st));
+    }
     // sort the access log by (instance, cell, gid, interval)
     int second = 0;
     u64 *lk0 = (u64*)(ws + L.lk0), *lv0 = (u64*)(ws + L.lv0), *lk1 = (u64*)(ws + L.lk1), *lv1 = (u64*)(ws + L.lv1);
-    HIP_TRY(sort_pairs_u64(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.log_cap, L.nbits_log, (uint32_t*)(ws + L.hist), st,
-                           &second));
+    {
+      PhaseTimer t(ctx, 1);
+      HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.log_cap, L.nbits_log, (const uint32_t*)(ws + L.wg_count),
+                       (u64)n * p->G, L.wg_log_cap, (uint32_t*)(ws + L.hist), st, &second));
+    }
     SegParams S;
     memset(&S, 0, sizeof S);
     S.keys = second ? lk1 : lk0;
@@ -520,12 +586,20 @@ rc_status rc_check(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, siz
     S.rec_keys = (u64*)(ws + L.rk0);
     S.rec_idx = (uint32_t*)(ws + L.ri0);
     S.status_word = (uint32_t*)(cnt + CNT_STATUS);
-    HIP_TRY(launch_seg_check(S, L.log_cap, st));
+    {
+      PhaseTimer t(ctx, 2);
+      HIP_TRY(launch_seg_check(S, L.log_cap, st));
+    }
     HIP_TRY(launch_clamp(cnt + CNT_REC, L.rec_cap, (uint32_t*)(cnt + CNT_STATUS), 2u, st));
     // canonical order of the records
     int rsecond = 0;
-    HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1), (uint32_t*)(ws + L.ri1),
-                           cnt + CNT_REC, L.rec_cap, L.nbits_rec, (uint32_t*)(ws + L.hist), st, &rsecond));
+    {
+      PhaseTimer t(ctx, 3);
+      HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1),
+                             (uint32_t*)(ws + L.ri1), cnt + CNT_REC, L.rec_cap, L.nbits_rec,
+                             (uint32_t*)(ws + L.hist), st, &rsecond));
+    }
+    PhaseTimer out_timer(ctx, 4);
     GatherParams Gp;
     memset(&Gp, 0, sizeof Gp);
     Gp.staging = (const rc_record_dev*)(ws + L.stage);

@@ -72,9 +72,14 @@ struct FinalMemParams {
 hipError_t launch_interp(const InterpParams& P, size_t lds_bytes, hipStream_t st);
 size_t scan_tmp_words(unsigned long long m);
 size_t sort_hist_words(unsigned long long cap);
-hipError_t sort_pairs_u64(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1,
-                          unsigned long long* v1, const unsigned long long* n_ptr, unsigned long long cap,
-                          uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second);
+size_t sort_log_hist_words(unsigned long long n_seg, unsigned long long R, unsigned long long cap);
+// Sort the access log: regions of seg_R entries (seg_count[r] used in region
+// r) become one dense array sorted by the low nbits of the key; *n_ptr (zero
+// on entry) receives the number of entries.
+hipError_t sort_log(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
+                    const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
+                    const uint32_t* seg_count, unsigned long long n_seg, unsigned long long seg_R, uint32_t* hist,
+                    hipStream_t st, int* in_second);
 hipError_t sort_pairs_u32(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1,
                           const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
                           uint32_t* hist, hipStream_t st, int* in_second);

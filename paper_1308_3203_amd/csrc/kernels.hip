@@ -15,6 +15,9 @@
 //  * rec_gather_kernel / finalize: canonical record order and summaries.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
 
 #include "rc_internal.h"
 #include "kernels.h"
@@ -87,6 +90,20 @@ __device__ __forceinline__ int32_t alu_bin(uint32_t op, int32_t x, int32_t y, bo
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Reads through the constant address space: with a uniform index these are
+// scalar loads (the code and descriptor tables are never written by kernels).
+struct Insn {
+  uint32_t h, a, b, c;
+};
+template <typename T>
+__device__ __forceinline__ T const_load(const void* base, uint32_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) T*)base)[i];
+#else
+  return ((const T*)base)[i];   // the host pass only parses device code
+#endif
+}
+
 // fault key: dynamic statement | lid | pc | priority | code  (smaller = earlier)
 // priority orders one item's faults inside a statement: DIV, OOB, the rest.
 __device__ __forceinline__ u64 fault_key(uint32_t step, uint32_t lid, uint32_t pc, uint32_t code) {
@@ -114,7 +131,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   for (uint32_t i = tl; i < P.nregs * WP; i += WP) regs[i] = 0;
   if (tl == 0) ctl->fault = ~0ull;
   if (tl < P.n_scalars) {
-    const ScalarDesc& S = P.scalars[tl];
+    const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
     ctl->scal[tl] = S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
   }
   // overlay epochs: versions written by earlier runs on this overlay are older
@@ -136,6 +153,8 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   if (tl == 0) P.epoch_used[ovl_index] = epoch_base;
 
   const u64 key_slot = (u64)slot << (P.bc + P.bg + P.bk);
+  const u64 log_base = (u64)ovl_index * P.wg_log_cap;
+  u64 log_used = 0;
   uint32_t pc = 0, depth = 0, eany = 0, last_spc = ~0u;
   uint32_t step = 0, store_seq = 0, interval = 0, parity = 0;
   uint32_t mbits = real ? 1u : 0u, ebits = 0u;
@@ -176,6 +195,33 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
     parity ^= 1u;
     return uni(acc);
   };
+  // The same snapshot reduction for a memory statement: bit 0 of each wave's
+  // word is its pending-fault flag, bits 8.. its count of log entries; every
+  // wave gets the group total and the count of the waves before it.
+  auto mem_red = [&](bool rec, u64* brec, uint32_t* prefix, uint32_t* total) -> bool {
+    const u64 br = __ballot(rec), bf = __ballot(my_fault != ~0ull);
+    *brec = br;
+    const uint32_t cnt = (uint32_t)__popcll(br);
+    if (P.nwaves == 1) {
+      __syncthreads();
+      *prefix = 0u;
+      *total = uni(cnt);
+      return bf != 0ull;
+    }
+    if (lane == 0) ctl->red[parity][wave] = (bf != 0ull ? 1u : 0u) | (cnt << 8);
+    __syncthreads();
+    uint32_t f = 0, tot = 0, pre = 0;
+    for (uint32_t w = 0; w < P.nwaves; ++w) {
+      const uint32_t x = ctl->red[parity][w];
+      f |= x & 1u;
+      tot += x >> 8;
+      if (w < wave) pre += x >> 8;
+    }
+    parity ^= 1u;
+    *prefix = uni(pre);
+    *total = uni(tot);
+    return uni(f) != 0u;
+  };
   auto raise = [&](uint32_t spc, uint32_t code) {
     const u64 k = fault_key(step, tl, spc, code);
     if (k < my_fault) my_fault = k;
@@ -183,8 +229,8 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
 
   for (;;) {
     pc = uni(pc);
-    const uint32_t* ip = P.code + (size_t)pc * 4u;
-    const uint32_t h = uni(ip[0]), wa = uni(ip[1]), wb = uni(ip[2]), wc = uni(ip[3]);
+    const Insn in = const_load<Insn>(P.code, pc);
+    const uint32_t h = in.h, wa = in.a, wb = in.b, wc = in.c;
     const uint32_t op = h & 63u, sub = (h >> 8) & 63u, dst = (h >> 14) & 63u, spc = h >> 20;
     const bool fa = (h >> 6) & 1u, fb = (h >> 7) & 1u;
     if (spc != last_spc) { ++step; last_spc = spc; }
@@ -205,13 +251,17 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
       if (active) regs[dst * WP + tl] = r;
       ++pc;
     } else if (op == OP_LOAD || op == OP_STORE) {
-      const ArrayDesc& A = P.arrays[wc];
+      const ArrayDesc A = const_load<ArrayDesc>(P.arrays, wc);
       const int32_t idx = fetch(fa, wa);
       const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;
       if (active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);
-      // the barrier completes every earlier statement's accesses and
-      // publishes pending faults; a faulting statement has no effect
-      if (group_red(false, false, true) & 4u) { faulted = true; break; }
+      const bool rec = active && P.do_log && A.logged;
+      // the barrier completes every earlier statement's accesses, publishes
+      // pending faults (a faulting statement has no effect) and each wave's
+      // number of log entries for this statement
+      u64 brec;
+      uint32_t prefix, total;
+      if (mem_red(rec, &brec, &prefix, &total)) { faulted = true; break; }
       const uint32_t cell = (uint32_t)idx;
       if (op == OP_LOAD) {
         if (active) {
@@ -242,29 +292,19 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
           ++n_acc;
         }
       }
-      if (P.do_log && A.logged) {
-        const bool rec = active;
-        const u64 m = __ballot(rec);
-        if (m != 0ull) {
-          const uint32_t first = (uint32_t)__ffsll((long long)m) - 1u;
-          const uint32_t cnt = (uint32_t)__popcll(m);
-          u64 base = 0ull;
-          if (lane == first) base = atomicAdd(P.log_count, (u64)cnt);
-          const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, first);
-          const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), first);
-          base = ((u64)bhi << 32) | blo;
-          if (rec) {
-            const u64 pos = base + (u64)__popcll(m & ((1ull << lane) - 1ull));
+      if (total != 0u) {
+        if (rec) {
+          const u64 pos = log_used + prefix + (u64)__popcll(brec & ((1ull << lane) - 1ull));
+          if (pos < P.wg_log_cap) {
             const u64 key = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
             const u64 pay = ((u64)(uint32_t)val << 32) | ((op == OP_STORE) ? 1024u : 0u) | tl;
-            if (pos < P.log_cap) {
-              P.log_keys[pos] = key;
-              P.log_vals[pos] = pay;
-            } else {
-              atomicOr(P.status_word, 1u);
-            }
+            P.log_keys[log_base + pos] = key;
+            P.log_vals[log_base + pos] = pay;
+          } else {
+            atomicOr(P.status_word, 1u);
           }
         }
+        log_used += total;
       }
       ++pc;
     } else if (op == OP_IF) {
@@ -328,6 +368,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   }
   // the last interval (complete, or cut by a fault) is closed
   if (tl == 0) {
+    P.wg_count[ovl_index] = (uint32_t)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
     atomicAdd(&P.inst_intervals[slot], interval + 1u);
     P.epochs[ovl_index] = epoch_base + store_seq + 1u;
     if (faulted) {
@@ -395,43 +436,66 @@ __global__ __launch_bounds__(256) void scan_block_kernel(uint32_t* data, uint64_
 // ---------------------------------------------------------------------------
 constexpr uint32_t RS_THREADS = 256, RS_ROUNDS = 16, RS_TILE = RS_THREADS * RS_ROUNDS;
 
-__global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, const u64* n_ptr, uint32_t shift,
+// Input of one radix pass: dense (n on the device), or segmented (region r of
+// seg_R entries holds seg_count[r] entries; blocks walk the regions tile by
+// tile, so the pass also compacts the regions into a dense output).
+struct RsIn {
+  const u64* n_ptr;
+  const uint32_t* seg_count;
+  u64 seg_R;
+  uint32_t tiles_per_seg, pad;
+};
+
+__device__ __forceinline__ void rs_tile(const RsIn& in, uint32_t b, u64* start, uint32_t* count) {
+  if (in.seg_R == 0) {
+    const u64 n = *in.n_ptr;
+    const u64 t0 = (u64)b * RS_TILE;
+    *start = t0;
+    *count = t0 >= n ? 0u : (uint32_t)(n - t0 < RS_TILE ? n - t0 : RS_TILE);
+  } else {
+    const uint32_t r = b / in.tiles_per_seg, t = b - r * in.tiles_per_seg;
+    const u64 used = in.seg_count[r];
+    const u64 t0 = (u64)t * RS_TILE;
+    *start = (u64)r * in.seg_R + t0;
+    *count = t0 >= used ? 0u : (uint32_t)(used - t0 < RS_TILE ? used - t0 : RS_TILE);
+  }
+}
+
+__global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, uint32_t shift,
                                                       uint32_t* hist, uint32_t nblocks) {
   __shared__ uint32_t h[256];
   const uint32_t t = threadIdx.x;
   h[t] = 0;
   __syncthreads();
-  const u64 n = *n_ptr;
-  const u64 base = (u64)blockIdx.x * RS_TILE;
-  if (base < n) {
-    for (uint32_t i = t; i < RS_TILE; i += RS_THREADS) {
-      const u64 p = base + i;
-      if (p < n) atomicAdd(&h[(uint32_t)(keys[p] >> shift) & 255u], 1u);
-    }
-  }
+  u64 start;
+  uint32_t count;
+  rs_tile(in, blockIdx.x, &start, &count);
+  for (uint32_t i = t; i < count; i += RS_THREADS) atomicAdd(&h[(uint32_t)(keys[start + i] >> shift) & 255u], 1u);
   __syncthreads();
   hist[(size_t)t * nblocks + blockIdx.x] = h[t];
 }
 
 template <typename V>
 __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
-                                                         const u64* n_ptr, uint32_t shift,
+                                                         RsIn in, uint32_t shift,
                                                          const uint32_t* offs, uint32_t nblocks) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[4][256];
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
-  const u64 n = *n_ptr;
-  const u64 tile0 = (u64)blockIdx.x * RS_TILE;
-  if (tile0 >= n) return;
+  u64 start;
+  uint32_t count;
+  rs_tile(in, blockIdx.x, &start, &count);
+  if (count == 0) return;
   base[t] = offs[(size_t)t * nblocks + blockIdx.x];
   const u64 below = (1ull << lane) - 1ull;
-  for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
-    const u64 p = tile0 + (u64)r * RS_THREADS + t;
-    const bool valid = p < n;
+  const uint32_t rounds = (count + RS_THREADS - 1) / RS_THREADS;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const uint32_t i = r * RS_THREADS + t;
+    const bool valid = i < count;
     u64 k = 0;
     V v = 0;
     uint32_t d = 0;
-    if (valid) { k = kin[p]; v = vin[p]; d = (uint32_t)(k >> shift) & 255u; }
+    if (valid) { k = kin[start + i]; v = vin[start + i]; d = (uint32_t)(k >> shift) & 255u; }
     u64 eq = __ballot(valid);
     for (int b = 0; b < 8; ++b) {
       const u64 bb = __ballot((d >> b) & 1u);
@@ -453,6 +517,13 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
     base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void sum_u32_kernel(const uint32_t* v, u64 n, u64* out) {
+  u64 s = 0;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) s += v[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if ((threadIdx.x & 63u) == 0 && s) atomicAdd(out, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -803,20 +874,45 @@ size_t sort_hist_words(u64 cap) {
   return m + scan_tmp_words(m);
 }
 
+// number of tiles the first (segmented) pass launches for n_seg regions of R entries
+static u64 seg_blocks(u64 n_seg, u64 R) { return n_seg * ((R + RS_TILE - 1) / RS_TILE); }
+
+size_t sort_log_hist_words(u64 n_seg, u64 R, u64 cap) {
+  const u64 nb = std::max<u64>(seg_blocks(n_seg, R), (cap + RS_TILE - 1) / RS_TILE);
+  const u64 m = 256ull * (nb ? nb : 1);
+  return m + scan_tmp_words(m);
+}
+
+
 template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
-                                  uint32_t* hist, hipStream_t st, int* result_in_second) {
-  const uint32_t nb = blocks_for(cap ? cap : 1, RS_TILE);
-  const u64 m = 256ull * nb;
-  uint32_t* tmp = hist + m;
+                                  const uint32_t* seg_count, u64 n_seg, u64 seg_R, uint32_t* hist,
+                                  hipStream_t st, int* result_in_second) {
   u64 *ka = k0, *kb = k1;
   V *va = v0, *vb = v1;
   int passes = 0;
-  for (uint32_t shift = 0; shift < nbits; shift += 8) {
-    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, n_ptr, shift, hist, nb);
+  // a segmented input always takes one pass, which also makes it dense
+  const uint32_t want = seg_R ? (nbits > 8 ? nbits : 8) : nbits;
+  for (uint32_t shift = 0; shift < want; shift += 8) {
+    RsIn in;
+    memset(&in, 0, sizeof in);
+    in.n_ptr = n_ptr;
+    u64 nbl;
+    if (passes == 0 && seg_R) {
+      in.seg_count = seg_count;
+      in.seg_R = seg_R;
+      in.tiles_per_seg = (uint32_t)((seg_R + RS_TILE - 1) / RS_TILE);
+      nbl = seg_blocks(n_seg, seg_R);
+    } else {
+      nbl = blocks_for(cap ? cap : 1, RS_TILE);
+    }
+    const uint32_t nb = (uint32_t)(nbl ? nbl : 1);
+    const u64 m = 256ull * nb;
+    uint32_t* tmp = hist + m;
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, in, shift, hist, nb);
     scan_excl(hist, m, tmp, st);
     hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
-                       vb, n_ptr, shift, (const uint32_t*)hist, nb);
+                       vb, in, shift, (const uint32_t*)hist, nb);
     u64* tk = ka; ka = kb; kb = tk;
     V* tv = va; va = vb; vb = tv;
     ++passes;
@@ -825,13 +921,16 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
   return hipGetLastError();
 }
 
-hipError_t sort_pairs_u64(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
-                          uint32_t* hist, hipStream_t st, int* in_second) {
-  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, hist, st, in_second);
+hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
+                    const uint32_t* seg_count, u64 n_seg, u64 seg_R, uint32_t* hist, hipStream_t st,
+                    int* in_second) {
+  hipLaunchKernelGGL(sum_u32_kernel, dim3(n_seg > 65536 ? 1024 : (uint32_t)blocks_for(n_seg, 256)), dim3(256), 0,
+                     st, seg_count, n_seg, (u64*)n_ptr);
+  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, n_seg, seg_R, hist, st, in_second);
 }
 hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {
-  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, hist, st, in_second);
+  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, nullptr, 0, 0, hist, st, in_second);
 }
 
 hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {

@@ -97,10 +97,10 @@ struct InterpParams {
   uint32_t* epochs;         // [n_slots * G] next free epoch per overlay
   uint32_t* epoch_used;     // [n_slots * G] epoch base used by the last run
   unsigned long long* overlay;        // [n_slots * G * overlay_cells]
-  unsigned long long* log_keys;       // access log
+  unsigned long long* log_keys;       // access log: one region of wg_log_cap entries per work-group
   unsigned long long* log_vals;
-  unsigned long long* log_count;      // u64 counter
-  uint64_t log_cap;
+  uint32_t* wg_count;                 // [n_slots * G] entries written in each region
+  uint64_t wg_log_cap;
   unsigned long long* inst_acc;       // [n_slots] accesses
   unsigned int* inst_intervals;       // [n_slots]
   unsigned long long* inst_fault;     // [n_slots] min (gid, pc, lid, code) key

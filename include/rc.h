@@ -156,6 +156,16 @@ rc_status rc_bind_device(rc_prog* prog, uint32_t array_id, const int32_t* d_cell
 rc_status rc_bind_scalar_seeded(rc_prog* prog, uint32_t scalar_id, int64_t lo, int64_t hi);
 rc_status rc_bind_scalar(rc_prog* prog, uint32_t scalar_id, int32_t value);
 
+/* Implementation tuning (never changes results).  lds_log_entries: size of
+ * the per-work-group interval log kept in LDS (rounded down to a power of
+ * two and clamped to what LDS holds; 0 = the library's choice).  Intervals
+ * larger than it are checked by the global pass instead. */
+typedef struct {
+  uint32_t lds_log_entries;
+  uint32_t reserved[7];
+} rc_tuning;
+rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
+
 /* ---- checking ----------------------------------------------------------- */
 
 /* Workspace bytes needed to check `n_seeds` instances in one pass.  Smaller

@@ -37,7 +37,7 @@ EXPORTS = [
     "rc_prog_free", "rc_prog_get_info", "rc_prog_array", "rc_prog_scalar", "rc_set_ndrange",
     "rc_bind_seeded", "rc_bind_device", "rc_bind_scalar_seeded", "rc_bind_scalar",
     "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
-    "rc_ctx_profile_read",
+    "rc_ctx_profile_read", "rc_prog_set_tuning",
 ]
 PHASES = ["interpret", "log_sort", "interval_check", "record_sort", "output", "setup"]
 
@@ -50,6 +50,10 @@ class RcError(RuntimeError):
 
 class _Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint32 * 8)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("lds_log_entries", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -94,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "rc_read_final": ([vp, u64, u32, vp, vp, sz], ctypes.c_int),
         "rc_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "rc_ctx_profile_read": ([vp, ctypes.POINTER(_Profile)], ctypes.c_int),
+        "rc_prog_set_tuning": ([vp, ctypes.POINTER(_Tuning)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -213,6 +218,11 @@ class Program:
             else:
                 _call(_lib.rc_bind_scalar, self._h, sid, ((int(b) + 2 ** 31) % 2 ** 32) - 2 ** 31)
 
+    def set_tuning(self, lds_log_entries: int = 0):
+        t = _Tuning()
+        t.lds_log_entries = lds_log_entries
+        _call(_lib.rc_prog_set_tuning, self._h, ctypes.byref(t))
+
     def workspace_size(self, n_seeds: int) -> int:
         out = ctypes.c_size_t()
         _call(_lib.rc_workspace_size, self._h, n_seeds, ctypes.byref(out))
@@ -265,11 +275,13 @@ def summaries_to_numpy(summ_u8, n: int) -> np.ndarray:
 
 def check(src: str, G: int, W: int, arrays: dict | None = None, scalars: dict | None = None,
           seed0: int = 0, n_seeds: int = 1, cap: int | None = None, ctx: Context | None = None,
-          ws_limit: int = 8 << 30):
+          ws_limit: int = 8 << 30, lds_log_entries: int = 0):
     """Compile, bind and check n_seeds instances; returns numpy (records, summaries)."""
     ctx = ctx or Context()
     prog = Program(ctx, src)
     prog.set_ndrange(G, W)
+    if lds_log_entries:
+        prog.set_tuning(lds_log_entries)
     prog.bind(arrays, scalars)
     if cap is None:
         cap = 1 << 20

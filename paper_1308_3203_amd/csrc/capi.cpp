@@ -79,9 +79,11 @@ struct rc_prog {
   std::vector<ScalarDesc> scalars;
   std::vector<uint32_t> cellbase, sizes;
   uint32_t n_logged_cells = 0, overlay_cells = 0, lds_local_cells = 0;
+  uint32_t lds_log_pref = 0;         // preferred LDS log entries when a spill is possible (0: default)
+  uint32_t lds_log_cap = 0;          // chosen for the current shape
   // device: code, then tables
   void* d_mem = nullptr;
-  size_t off_arrays = 0, off_scalars = 0, off_cellbase = 0, off_size = 0, d_bytes = 0;
+  size_t off_arrays = 0, off_scalars = 0, off_cellbase = 0, off_size = 0, off_recout = 0, d_bytes = 0;
   std::vector<unsigned char> h_tables;   // staging for the async table upload
 };
 
@@ -185,6 +187,49 @@ bool make_layout(const rc_prog* p, uint32_t n_slots, Layout* L, std::string* why
   return true;
 }
 
+rc_record_out record_out(const Layout& L, char* ws) {
+  rc_record_out R;
+  memset(&R, 0, sizeof R);
+  u64* cnt = (u64*)(ws + L.counters);
+  R.staging = ws + L.stage;
+  R.rec_keys = (u64*)(ws + L.rk0);
+  R.rec_idx = (uint32_t*)(ws + L.ri0);
+  R.rec_count = cnt + CNT_REC;
+  R.rec_cap = L.rec_cap;
+  R.status_word = (uint32_t*)(cnt + CNT_STATUS);
+  return R;
+}
+
+// LDS bytes of everything except the interval log
+size_t lds_fixed_bytes(const rc_prog* p) {
+  const uint32_t WP = ((p->W + 63) / 64) * 64;
+  return (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4 + sizeof(Ctl);
+}
+
+// Entries of the interval log kept in LDS (a power of two; 0 = none): large
+// enough for the program's static bound when that fits, else as large as LDS
+// allows up to `pref` entries.
+uint32_t lds_log_entries(const rc_prog* p) {
+  const bool lds_globals = p->G == 1;
+  const u64 per_item = p->c.dyn_logged_local + (lds_globals ? p->c.dyn_logged_mem - p->c.dyn_logged_local : 0);
+  if (per_item == 0) return 0;
+  const size_t fixed = lds_fixed_bytes(p);
+  if (fixed + 32 > LDS_LIMIT) return 0;
+  uint32_t fit = 2;
+  while ((size_t)fit * 2 * 16 + fixed <= LDS_LIMIT && fit * 2 <= 65536u) fit *= 2;
+  const double bound = (double)p->W * (lds_globals ? p->c.interval_logged_all : p->c.interval_logged_local);
+  if (p->lds_log_pref) {   // explicit tuning
+    uint32_t t = 2;
+    while (t * 2 <= p->lds_log_pref && t * 2 <= fit) t *= 2;
+    return t;
+  }
+  const uint32_t pref = 4096u;
+  uint32_t want = 2;
+  while (want < bound && want < 65536u) want *= 2;
+  if ((double)want >= bound && want <= fit) return want;   // never spills
+  return std::min(fit, std::max<uint32_t>(pref, 2));
+}
+
 rc_status check_ready(const rc_prog* p) {
   if (!p->shaped) return fail(RC_E_STATE, "rc_set_ndrange has not been called");
   for (uint32_t a = 0; a < p->c.n_global; ++a)
@@ -196,9 +241,16 @@ rc_status check_ready(const rc_prog* p) {
   return RC_OK;
 }
 
-rc_status upload_tables(rc_prog* p, hipStream_t st) {
+rc_status upload_tables(rc_prog* p, hipStream_t st, const rc_record_out* R) {
   unsigned char* h = p->h_tables.data();
+  for (size_t a = 0; a < p->arrays.size(); ++a) {
+    ArrayDesc& d = p->arrays[a];
+    if (!p->c.arrays[a].written) d.logged = LOG_NONE;
+    else if (p->lds_log_cap && (!p->c.arrays[a].global || p->G == 1)) d.logged = LOG_LDS;
+    else d.logged = LOG_GLOBAL;
+  }
   memcpy(h + p->off_arrays - p->off_arrays, p->arrays.data(), p->arrays.size() * sizeof(ArrayDesc));
+  if (R) memcpy(h + (p->off_recout - p->off_arrays), R, sizeof *R);
   memcpy(h + (p->off_scalars - p->off_arrays), p->scalars.data(), p->scalars.size() * sizeof(ScalarDesc));
   memcpy(h + (p->off_cellbase - p->off_arrays), p->cellbase.data(), p->cellbase.size() * 4);
   memcpy(h + (p->off_size - p->off_arrays), p->sizes.data(), p->sizes.size() * 4);
@@ -253,13 +305,14 @@ InterpParams interp_params(const rc_prog* p, const Layout& L, char* ws, uint64_t
   P.inst_fault = (u64*)(ws + L.inst_fault);
   P.status_word = (uint32_t*)(cnt + CNT_STATUS);
   P.do_log = do_log;
+  P.lds_log_cap = p->lds_log_cap;
+  P.bs = L.bs;
+  P.NI = L.NI;
+  P.rec = (rc_record_out*)((char*)p->d_mem + p->off_recout);
   return P;
 }
 
-size_t lds_bytes(const rc_prog* p) {
-  const uint32_t WP = ((p->W + 63) / 64) * 64;
-  return (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4 + sizeof(Ctl);
-}
+size_t lds_bytes(const rc_prog* p) { return lds_fixed_bytes(p) + (size_t)p->lds_log_cap * 16; }
 
 rc_status reset_pass(const rc_prog* p, const Layout& L, char* ws, hipStream_t st) {
   HIP_TRY(launch_fill_u64((u64*)(ws + L.counters), 2, 0ull, st));   // log and record counters
@@ -387,6 +440,8 @@ rc_status rc_prog_load(rc_ctx* ctx, const char* src, size_t len, rc_prog** out) 
   o += align_up(na * 4 + 1, 64);
   p->off_size = o;
   o += align_up(na * 4 + 1, 64);
+  p->off_recout = o;
+  o += align_up(sizeof(rc_record_out), 64);
   p->d_bytes = o;
   p->h_tables.assign(o - p->off_arrays, 0);
   hipError_t e = hipMalloc(&p->d_mem, o);
@@ -452,6 +507,7 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->G = num_groups;
   p->W = W;
   p->shaped = true;
+  p->lds_log_cap = lds_log_entries(p);
   return RC_OK;
 }
 
@@ -500,6 +556,13 @@ rc_status rc_bind_scalar(rc_prog* p, uint32_t id, int32_t value) {
   return RC_OK;
 }
 
+rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
+  if (!p || !t) return fail(RC_E_INVAL, "NULL argument");
+  p->lds_log_pref = t->lds_log_entries;
+  if (p->shaped) p->lds_log_cap = lds_log_entries(p);
+  return RC_OK;
+}
+
 rc_status rc_workspace_size(const rc_prog* p, uint32_t n_seeds, size_t* bytes) {
   if (!p || !bytes) return fail(RC_E_INVAL, "NULL argument");
   if (!p->shaped) return fail(RC_E_STATE, "rc_set_ndrange has not been called");
@@ -538,7 +601,8 @@ rc_status rc_check(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, siz
   char* ws = (char*)d_ws;
   s = prepare_workspace(p, ws, L);
   if (s) return s;
-  s = upload_tables(p, st);
+  const rc_record_out R = record_out(L, ws);
+  s = upload_tables(p, st, &R);
   if (s) return s;
   u64* cnt = (u64*)(ws + L.counters);
   HIP_TRY(launch_fill_u64(cnt + CNT_STATUS, 1, 0ull, st));
@@ -580,12 +644,7 @@ rc_status rc_check(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, siz
     S.inst_offset = off;
     S.cellbase = (const uint32_t*)((char*)p->d_mem + p->off_cellbase);
     S.size = (const uint32_t*)((char*)p->d_mem + p->off_size);
-    S.rec_count = cnt + CNT_REC;
-    S.rec_cap = L.rec_cap;
-    S.staging = (rc_record_dev*)(ws + L.stage);
-    S.rec_keys = (u64*)(ws + L.rk0);
-    S.rec_idx = (uint32_t*)(ws + L.ri0);
-    S.status_word = (uint32_t*)(cnt + CNT_STATUS);
+    S.out = record_out(L, ws);
     {
       PhaseTimer t(ctx, 2);
       HIP_TRY(launch_seg_check(S, L.log_cap, st));
@@ -681,7 +740,7 @@ rc_status rc_read_final(rc_prog* p, uint64_t seed, uint32_t array_id, int32_t* d
   char* ws = (char*)d_ws;
   s = prepare_workspace(p, ws, L);
   if (s) return s;
-  s = upload_tables(p, st);
+  s = upload_tables(p, st, nullptr);
   if (s) return s;
   s = reset_pass(p, L, ws, st);
   if (s) return s;

@@ -6,6 +6,7 @@
 #include "frontend.h"
 
 #include <cctype>
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -581,7 +582,7 @@ class Lowering {
 // static bounds per work-item (every branch taken)
 // ---------------------------------------------------------------------------
 struct Bounds {
-  double instr = 0, mem = 0, logged = 0, stores = 0, barriers = 0;
+  double instr = 0, mem = 0, logged = 0, logged_local = 0, stores = 0, barriers = 0;
 };
 
 uint64_t expr_ops(const Node& e) {
@@ -599,7 +600,10 @@ void bound_block(const std::vector<Statement>& body, const Compiled& c, double m
         double ops = (double)expr_ops(*s.e1) + (s.e2 ? (double)expr_ops(*s.e2) : 0.0) + 1;
         b->instr += mult * ops;
         b->mem += mult;
-        if (c.arrays[s.arr].written) b->logged += mult;
+        if (c.arrays[s.arr].written) {
+          b->logged += mult;
+          if (!c.arrays[s.arr].global) b->logged_local += mult;
+        }
         if (s.kind == Statement::STORE) b->stores += mult;
         break;
       }
@@ -621,6 +625,66 @@ void bound_block(const std::vector<Statement>& body, const Compiled& c, double m
   }
 }
 
+bool has_barrier(const std::vector<Statement>& body) {
+  for (const Statement& s : body) {
+    if (s.kind == Statement::BARRIER) return true;
+    if ((s.kind == Statement::IF || s.kind == Statement::FOR) &&
+        (has_barrier(s.then_body) || has_barrier(s.else_body)))
+      return true;
+  }
+  return false;
+}
+
+// Largest number of accesses (per work-item, along any path) between two
+// consecutive barriers, counting accesses to arrays selected by `pick`.
+struct IntervalBound {
+  double open = 0;     // accesses since the last barrier at this point
+  double worst = 0;    // largest closed interval so far
+};
+
+template <typename Pick>
+IntervalBound interval_block(const std::vector<Statement>& body, IntervalBound in, Pick pick) {
+  IntervalBound st = in;
+  for (const Statement& s : body) {
+    switch (s.kind) {
+      case Statement::LOAD:
+      case Statement::STORE:
+        if (pick(s.arr)) st.open += 1;
+        break;
+      case Statement::BARRIER:
+        st.worst = std::max(st.worst, st.open);
+        st.open = 0;
+        break;
+      case Statement::IF: {
+        IntervalBound a = interval_block(s.then_body, st, pick);
+        IntervalBound b = interval_block(s.else_body, st, pick);
+        st.open = std::max(a.open, b.open);
+        st.worst = std::max(a.worst, b.worst);
+        break;
+      }
+      case Statement::FOR: {
+        const int64_t iters = s.hi > s.lo ? s.hi - s.lo : 0;
+        if (iters == 0) break;
+        IntervalBound one = interval_block(s.then_body, {0, 0}, pick);
+        if (one.worst == 0 && one.open > 0 && !has_barrier(s.then_body)) {
+          st.open += one.open * (double)iters;   // no barrier inside: the counts add up
+          break;
+        }
+        if (!has_barrier(s.then_body)) break;
+        // a barrier inside: after two iterations the counts repeat
+        IntervalBound a = interval_block(s.then_body, st, pick);
+        IntervalBound b = iters >= 2 ? interval_block(s.then_body, a, pick) : a;
+        st.open = b.open;
+        st.worst = std::max(a.worst, b.worst);
+        break;
+      }
+      default:
+        break;
+    }
+  }
+  return st;
+}
+
 }  // namespace
 
 bool compile_program(const char* src, size_t len, Compiled* out, std::string* err, bool* is_limit) {
@@ -639,8 +703,16 @@ bool compile_program(const char* src, size_t len, Compiled* out, std::string* er
     out->dyn_instr = (uint64_t)(b.instr + 1);
     out->dyn_mem = (uint64_t)(b.mem < cap ? b.mem : cap);
     out->dyn_logged_mem = (uint64_t)(b.logged < cap ? b.logged : cap);
+    out->dyn_logged_local = (uint64_t)(b.logged_local < cap ? b.logged_local : cap);
     out->dyn_stores = (uint64_t)b.stores;
     out->max_intervals = (uint64_t)(b.barriers + 1);
+    {
+      const Compiled& cc = *out;
+      IntervalBound lo = interval_block(body, {0, 0}, [&](int a) { return cc.arrays[a].written && !cc.arrays[a].global; });
+      IntervalBound al = interval_block(body, {0, 0}, [&](int a) { return cc.arrays[a].written; });
+      out->interval_logged_local = std::max(lo.worst, lo.open);
+      out->interval_logged_all = std::max(al.worst, al.open);
+    }
     Lowering low(out);
     low.run(body);
     return true;

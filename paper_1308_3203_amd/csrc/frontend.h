@@ -24,9 +24,13 @@ struct Compiled {
   // static bounds for one work-item (both branches of every if counted)
   uint64_t dyn_instr = 0;              // instructions executed
   uint64_t dyn_logged_mem = 0;         // loads/stores on written arrays
+  uint64_t dyn_logged_local = 0;       // ... of which on written local arrays
   uint64_t dyn_mem = 0;                // all loads/stores
   uint64_t dyn_stores = 0;             // store statements
   uint64_t max_intervals = 1;          // 1 + barriers executed
+  // largest interval (accesses per work-item between two barriers) on
+  // written local arrays / on all written arrays
+  double interval_logged_local = 0, interval_logged_all = 0;
 };
 
 // Returns true on success; on failure `err` holds "line:col: message" and

@@ -27,12 +27,7 @@ struct SegParams {
   uint32_t G, W, NI, n_arrays, n_global, inst_offset;
   const uint32_t* cellbase;         // per array, 0xFFFFFFFF when not logged
   const uint32_t* size;
-  unsigned long long* rec_count;
-  unsigned long long rec_cap;
-  rc_record_dev* staging;
-  unsigned long long* rec_keys;
-  uint32_t* rec_idx;
-  uint32_t* status_word;
+  rc_record_out out;
 };
 
 struct GatherParams {

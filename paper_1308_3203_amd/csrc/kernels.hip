@@ -111,6 +111,177 @@ __device__ __forceinline__ u64 fault_key(uint32_t step, uint32_t lid, uint32_t p
   return ((u64)step << 32) | ((u64)lid << 17) | ((u64)pc << 5) | ((u64)prio << 3) | code;
 }
 
+// ---------------------------------------------------------------------------
+// interval checks (shared by the interpreter's LDS path and the global pass)
+// ---------------------------------------------------------------------------
+struct Pair {
+  uint32_t a, b;
+};
+__device__ __forceinline__ void pair_take(Pair& best, uint32_t x, uint32_t y) {
+  const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+  if (lo < best.a || (lo == best.a && hi < best.b)) { best.a = lo; best.b = hi; }
+}
+
+__device__ __forceinline__ uint32_t pay_lid(u64 p) { return (uint32_t)p & 1023u; }
+__device__ __forceinline__ bool pay_w(u64 p) { return ((uint32_t)p >> 10) & 1u; }
+__device__ __forceinline__ int32_t pay_val(u64 p) { return (int32_t)(uint32_t)(p >> 32); }
+
+// INTRA scope over entries [s, e) of one work-group (ids compared by lid);
+// get(i) returns entry i's payload: value << 32 | is_write << 10 | lid.
+template <typename Get>
+__device__ bool intra_check(Get get, u64 s, u64 e, uint32_t* label, Pair* rw, Pair* ww) {
+  const uint32_t NONE = 0xFFFFFFFFu;
+  uint32_t r1 = NONE;
+  u64 wmin = ~0ull;  // (lid, value ^ sign) of the smallest writer
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = get(i);
+    const uint32_t l = pay_lid(p);
+    if (pay_w(p)) {
+      const u64 kx = ((u64)l << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
+      if (kx < wmin) wmin = kx;
+    } else if (l < r1) {
+      r1 = l;
+    }
+  }
+  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
+  uint32_t r2 = NONE, w2 = NONE, q = NONE;
+  bool multi1 = false;
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = get(i);
+    const uint32_t l = pay_lid(p);
+    if (pay_w(p)) {
+      const int32_t v = pay_val(p);
+      if (l == w1) { if (v != x1) multi1 = true; }
+      else {
+        if (l < w2) w2 = l;
+        if (v != x1 && l < q) q = l;
+      }
+    } else if (l != r1 && l < r2) {
+      r2 = l;
+    }
+  }
+  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
+  const uint32_t rs[2] = {r1, r2}, ws[2] = {w1, w2};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (rs[i] != NONE && ws[j] != NONE && rs[i] != ws[j]) pair_take(brw, rs[i], ws[j]);
+  bool wwd = false;
+  if (multi1 && w2 != NONE) { bww = {w1, w2}; wwd = true; }
+  else if (q != NONE) { bww = {w1, q}; wwd = true; }
+  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
+  if (lab == 0u) {
+    if (w2 == NONE) return false;   // no eligible pair
+    lab = 4u;
+    bww = {w1, w2};
+  }
+  *label = lab;
+  *rw = brw;
+  *ww = bww;
+  return true;
+}
+
+// INTER scope over records [s, e) of one cell, all groups (global tids).
+__device__ bool inter_check(const u64* keys, const u64* vals, u64 s, u64 e, uint32_t bk, uint32_t gmask,
+                            uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
+  const uint32_t NONE = 0xFFFFFFFFu;
+  uint32_t r1 = NONE;
+  u64 wmin = ~0ull;
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = vals[i];
+    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
+    const uint32_t t = g * W + pay_lid(p);
+    if (pay_w(p)) {
+      const u64 kx = ((u64)t << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
+      if (kx < wmin) wmin = kx;
+    } else if (t < r1) {
+      r1 = t;
+    }
+  }
+  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
+  const uint32_t gr1 = r1 == NONE ? NONE : r1 / W;
+  const uint32_t g1 = w1 == NONE ? NONE : w1 / W;
+  uint32_t r1p = NONE, w1p = NONE, q = NONE, A = NONE;
+  bool multi1 = false;
+  for (u64 i = s; i < e; ++i) {
+    const u64 p = vals[i];
+    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
+    const uint32_t t = g * W + pay_lid(p);
+    if (pay_w(p)) {
+      const int32_t v = pay_val(p);
+      if (t == w1) { if (v != x1) multi1 = true; }
+      if (g != g1) {
+        if (t < w1p) w1p = t;
+        if (v != x1 && t < q) q = t;
+      } else if (t != w1 && v != x1 && t < A) {
+        A = t;
+      }
+    } else if (g != gr1 && t < r1p) {
+      r1p = t;
+    }
+  }
+  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
+  const uint32_t rs[2] = {r1, r1p}, ws[2] = {w1, w1p};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (rs[i] != NONE && ws[j] != NONE && rs[i] / W != ws[j] / W) pair_take(brw, rs[i], ws[j]);
+  bool wwd = false;
+  if (multi1 && w1p != NONE) { bww = {w1, w1p}; wwd = true; }
+  else if (q != NONE) { bww = {w1, q}; wwd = true; }
+  else if (A != NONE && w1p != NONE) { bww = {A < w1p ? A : w1p, A < w1p ? w1p : A}; wwd = true; }
+  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
+  if (lab == 0u) {
+    if (w1p == NONE) return false;
+    lab = 4u;
+    bww = {w1, w1p};
+  }
+  *label = lab;
+  *rw = brw;
+  *ww = bww;
+  return true;
+}
+
+struct PendingRec {
+  uint32_t gid, interval, aid, cell, cellkey, label, lidbase;
+  Pair rw, ww;
+};
+
+// canonical sort key fields of a record
+struct RecKey {
+  uint32_t bs, bc, G, NI, inst_offset;
+};
+
+__device__ __forceinline__ void store_record(const rc_record_out& R, const RecKey& K, u64 pos, uint32_t slot,
+                                             const PendingRec& p, bool inter) {
+  if (pos >= R.rec_cap) { atomicOr(R.status_word, 2u); return; }
+  const uint32_t NONE = 0xFFFFFFFFu;
+  rc_record_dev r;
+  r.instance = K.inst_offset + slot;
+  r.gid = inter ? NONE : p.gid;
+  r.interval = inter ? 0u : p.interval;
+  r.array_label = p.aid | (p.label << 16);
+  r.cell = p.cell;
+  r.rw_a = p.rw.a == NONE ? NONE : p.rw.a + p.lidbase;
+  r.rw_b = p.rw.b == NONE ? NONE : p.rw.b + p.lidbase;
+  r.ww_a = p.ww.a == NONE ? NONE : p.ww.a + p.lidbase;
+  r.ww_b = p.ww.b == NONE ? NONE : p.ww.b + p.lidbase;
+  r.pad = 0;
+  reinterpret_cast<rc_record_dev*>(R.staging)[pos] = r;
+  const u64 scope = inter ? (u64)K.G * K.NI : (u64)p.gid * K.NI + p.interval;
+  R.rec_keys[pos] = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
+  R.rec_idx[pos] = (uint32_t)pos;
+}
+
+// wave-wide allocation of record slots: one atomic per wave
+__device__ __forceinline__ u64 wave_reserve(unsigned long long* counter, uint32_t n, uint32_t lane) {
+  u64 base = 0;
+  if (lane == 0 && n) base = atomicAdd(counter, (u64)n);
+  const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
+  const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
+  return ((u64)bhi << 32) | blo;
+}
+
 extern __shared__ __attribute__((aligned(16))) unsigned char rc_smem[];
 
 __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
@@ -122,9 +293,13 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   const uint64_t seed = P.seed0 + (uint64_t)(P.inst_offset + slot);
   const bool real = tl < P.W;
 
-  // dynamic LDS: local array cells (u64), registers, control block
+  // dynamic LDS: local array cells (u64), the interval log (T keys, T
+  // payload words, T values), registers, control block
   u64* locc = reinterpret_cast<u64*>(rc_smem);
-  int32_t* regs = reinterpret_cast<int32_t*>(locc + P.lds_local_cells);
+  u64* lkey = locc + P.lds_local_cells;
+  uint32_t* lmeta = reinterpret_cast<uint32_t*>(lkey + P.lds_log_cap);
+  int32_t* lval = reinterpret_cast<int32_t*>(lmeta + P.lds_log_cap);
+  int32_t* regs = lval + P.lds_log_cap;
   Ctl* ctl = reinterpret_cast<Ctl*>(regs + (size_t)P.nregs * WP);
 
   for (uint32_t i = tl; i < P.lds_local_cells; i += WP) locc[i] = 0ull;
@@ -155,6 +330,8 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   const u64 key_slot = (u64)slot << (P.bc + P.bg + P.bk);
   const u64 log_base = (u64)ovl_index * P.wg_log_cap;
   u64 log_used = 0;
+  uint32_t lds_used = 0;       // entries of the current interval in the LDS log
+  bool lds_spilled = false;    // the current interval moved to the global log
   uint32_t pc = 0, depth = 0, eany = 0, last_spc = ~0u;
   uint32_t step = 0, store_seq = 0, interval = 0, parity = 0;
   uint32_t mbits = real ? 1u : 0u, ebits = 0u;
@@ -227,6 +404,70 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
     if (k < my_fault) my_fault = k;
   };
 
+  // Close the current interval on the LDS path: sort its log by cell in LDS
+  // (bitonic), then the first entry of every cell's run checks the run
+  // (INTRA scope) and records go to the staging area.  Callers have passed a
+  // barrier since the interval's last access.
+  auto close_interval = [&]() {
+    const uint32_t n = lds_used;
+    const bool spilled = lds_spilled;
+    lds_used = 0;
+    lds_spilled = false;
+    if (spilled || n < 2u) return;
+    uint32_t P2 = 2;
+    while (P2 < n) P2 <<= 1;
+    for (uint32_t i = n + tl; i < P2; i += WP) lkey[i] = ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P2; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = tl; i < P2; i += WP) {
+          const uint32_t ixj = i ^ j;
+          if (ixj > i) {
+            const u64 a = lkey[i], b = lkey[ixj];
+            if ((a > b) == ((i & k) == 0u)) { lkey[i] = b; lkey[ixj] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
+    const RecKey K = {P.bs, P.bc, P.G, P.NI, P.inst_offset};
+    for (uint32_t b0 = 0; b0 < n; b0 += WP) {
+      const uint32_t i = b0 + tl;
+      bool has = false;
+      PendingRec pr;
+      if (i < n) {
+        const u64 ck = lkey[i] >> 16;
+        if (i == 0 || (lkey[i - 1] >> 16) != ck) {
+          uint32_t e = i + 1;
+          while (e < n && (lkey[e] >> 16) == ck) ++e;
+          if (e - i >= 2u) {
+            has = intra_check([&](u64 q) {
+                                const uint32_t ix = (uint32_t)lkey[q] & 0xFFFFu;
+                                return ((u64)(uint32_t)lval[ix] << 32) | lmeta[ix];
+                              }, i, e, &pr.label, &pr.rw, &pr.ww);
+            if (has) {
+              uint32_t aid = 0;
+              for (uint32_t a = 0; a < P.n_arrays; ++a) {
+                const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
+                if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
+              }
+              const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
+              pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = (uint32_t)ck - D.cellbase;
+              pr.cellkey = (uint32_t)ck; pr.lidbase = gid * P.W;
+            }
+          }
+        }
+      }
+      const u64 m = __ballot(has);
+      if (m != 0ull) {
+        const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
+        if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, pr, false);
+      }
+    }
+    __syncthreads();
+  };
+
   for (;;) {
     pc = uni(pc);
     const Insn in = const_load<Insn>(P.code, pc);
@@ -255,7 +496,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
       const int32_t idx = fetch(fa, wa);
       const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;
       if (active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);
-      const bool rec = active && P.do_log && A.logged;
+      const bool rec = active && P.do_log && A.logged != LOG_NONE;
       // the barrier completes every earlier statement's accesses, publishes
       // pending faults (a faulting statement has no effect) and each wave's
       // number of log entries for this statement
@@ -293,18 +534,47 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
         }
       }
       if (total != 0u) {
-        if (rec) {
-          const u64 pos = log_used + prefix + (u64)__popcll(brec & ((1ull << lane) - 1ull));
-          if (pos < P.wg_log_cap) {
-            const u64 key = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
-            const u64 pay = ((u64)(uint32_t)val << 32) | ((op == OP_STORE) ? 1024u : 0u) | tl;
-            P.log_keys[log_base + pos] = key;
-            P.log_vals[log_base + pos] = pay;
-          } else {
-            atomicOr(P.status_word, 1u);
+        bool to_lds = A.logged == LOG_LDS && !lds_spilled;
+        if (to_lds && lds_used + total > P.lds_log_cap) {
+          // the interval outgrows LDS: move its log to the global log, where
+          // the global pass checks it
+          for (uint32_t i = tl; i < lds_used; i += WP) {
+            const u64 pos = log_used + i;
+            const u64 ck = lkey[i] >> 16;
+            if (pos < P.wg_log_cap) {
+              P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
+              P.log_vals[log_base + pos] = ((u64)(uint32_t)lval[i] << 32) | lmeta[i];
+            } else {
+              atomicOr(P.status_word, 1u);
+            }
           }
+          log_used += lds_used;
+          lds_used = 0;
+          lds_spilled = true;
+          to_lds = false;
         }
-        log_used += total;
+        const uint32_t below = prefix + (uint32_t)__popcll(brec & ((1ull << lane) - 1ull));
+        const uint32_t meta = ((op == OP_STORE) ? 1024u : 0u) | tl;
+        if (to_lds) {
+          if (rec) {
+            const uint32_t j = lds_used + below;
+            lkey[j] = ((u64)(A.cellbase + cell) << 16) | j;
+            lmeta[j] = meta;
+            lval[j] = val;
+          }
+          lds_used += total;
+        } else {
+          if (rec) {
+            const u64 pos = log_used + below;
+            if (pos < P.wg_log_cap) {
+              P.log_keys[log_base + pos] = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
+              P.log_vals[log_base + pos] = ((u64)(uint32_t)val << 32) | meta;
+            } else {
+              atomicOr(P.status_word, 1u);
+            }
+          }
+          log_used += total;
+        }
       }
       ++pc;
     } else if (op == OP_IF) {
@@ -349,6 +619,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
         faulted = true;
         break;
       }
+      if (P.do_log) close_interval();
       ++interval;
       ++pc;
     } else if (op == OP_ASSERT || op == OP_ASSUME) {
@@ -361,11 +632,13 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
     }
   }
 
-  // every wave leaves the loop at the same point; the earliest fault wins
+  // every wave leaves the loop at the same point; the earliest fault wins.
+  // The last interval (complete, or cut short by the fault) is checked.
   if (faulted) {
     if (my_fault != ~0ull) atomicMin(&ctl->fault, my_fault);
     __syncthreads();
   }
+  if (P.do_log) close_interval();
   // the last interval (complete, or cut by a fault) is closed
   if (tl == 0) {
     P.wg_count[ovl_index] = (uint32_t)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
@@ -529,158 +802,6 @@ __global__ __launch_bounds__(256) void sum_u32_kernel(const uint32_t* v, u64 n, 
 // ---------------------------------------------------------------------------
 // segment check
 // ---------------------------------------------------------------------------
-struct Pair {
-  uint32_t a, b;
-};
-__device__ __forceinline__ void pair_take(Pair& best, uint32_t x, uint32_t y) {
-  const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
-  if (lo < best.a || (lo == best.a && hi < best.b)) { best.a = lo; best.b = hi; }
-}
-
-__device__ __forceinline__ uint32_t pay_lid(u64 p) { return (uint32_t)p & 1023u; }
-__device__ __forceinline__ bool pay_w(u64 p) { return ((uint32_t)p >> 10) & 1u; }
-__device__ __forceinline__ int32_t pay_val(u64 p) { return (int32_t)(uint32_t)(p >> 32); }
-
-// INTRA scope over records [s, e) of one work-group (ids compared by lid).
-__device__ bool intra_check(const u64* vals, u64 s, u64 e, uint32_t* label, Pair* rw, Pair* ww) {
-  const uint32_t NONE = 0xFFFFFFFFu;
-  uint32_t r1 = NONE;
-  u64 wmin = ~0ull;  // (lid, value ^ sign) of the smallest writer
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = vals[i];
-    const uint32_t l = pay_lid(p);
-    if (pay_w(p)) {
-      const u64 kx = ((u64)l << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
-      if (kx < wmin) wmin = kx;
-    } else if (l < r1) {
-      r1 = l;
-    }
-  }
-  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
-  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
-  uint32_t r2 = NONE, w2 = NONE, q = NONE;
-  bool multi1 = false;
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = vals[i];
-    const uint32_t l = pay_lid(p);
-    if (pay_w(p)) {
-      const int32_t v = pay_val(p);
-      if (l == w1) { if (v != x1) multi1 = true; }
-      else {
-        if (l < w2) w2 = l;
-        if (v != x1 && l < q) q = l;
-      }
-    } else if (l != r1 && l < r2) {
-      r2 = l;
-    }
-  }
-  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
-  const uint32_t rs[2] = {r1, r2}, ws[2] = {w1, w2};
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      if (rs[i] != NONE && ws[j] != NONE && rs[i] != ws[j]) pair_take(brw, rs[i], ws[j]);
-  bool wwd = false;
-  if (multi1 && w2 != NONE) { bww = {w1, w2}; wwd = true; }
-  else if (q != NONE) { bww = {w1, q}; wwd = true; }
-  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
-  if (lab == 0u) {
-    if (w2 == NONE) return false;   // no eligible pair
-    lab = 4u;
-    bww = {w1, w2};
-  }
-  *label = lab;
-  *rw = brw;
-  *ww = bww;
-  return true;
-}
-
-// INTER scope over records [s, e) of one cell, all groups (global tids).
-__device__ bool inter_check(const u64* keys, const u64* vals, u64 s, u64 e, uint32_t bk, uint32_t gmask,
-                            uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
-  const uint32_t NONE = 0xFFFFFFFFu;
-  uint32_t r1 = NONE;
-  u64 wmin = ~0ull;
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = vals[i];
-    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
-    const uint32_t t = g * W + pay_lid(p);
-    if (pay_w(p)) {
-      const u64 kx = ((u64)t << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
-      if (kx < wmin) wmin = kx;
-    } else if (t < r1) {
-      r1 = t;
-    }
-  }
-  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
-  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
-  const uint32_t gr1 = r1 == NONE ? NONE : r1 / W;
-  const uint32_t g1 = w1 == NONE ? NONE : w1 / W;
-  uint32_t r1p = NONE, w1p = NONE, q = NONE, A = NONE;
-  bool multi1 = false;
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = vals[i];
-    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
-    const uint32_t t = g * W + pay_lid(p);
-    if (pay_w(p)) {
-      const int32_t v = pay_val(p);
-      if (t == w1) { if (v != x1) multi1 = true; }
-      if (g != g1) {
-        if (t < w1p) w1p = t;
-        if (v != x1 && t < q) q = t;
-      } else if (t != w1 && v != x1 && t < A) {
-        A = t;
-      }
-    } else if (g != gr1 && t < r1p) {
-      r1p = t;
-    }
-  }
-  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
-  const uint32_t rs[2] = {r1, r1p}, ws[2] = {w1, w1p};
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      if (rs[i] != NONE && ws[j] != NONE && rs[i] / W != ws[j] / W) pair_take(brw, rs[i], ws[j]);
-  bool wwd = false;
-  if (multi1 && w1p != NONE) { bww = {w1, w1p}; wwd = true; }
-  else if (q != NONE) { bww = {w1, q}; wwd = true; }
-  else if (A != NONE && w1p != NONE) { bww = {A < w1p ? A : w1p, A < w1p ? w1p : A}; wwd = true; }
-  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
-  if (lab == 0u) {
-    if (w1p == NONE) return false;
-    lab = 4u;
-    bww = {w1, w1p};
-  }
-  *label = lab;
-  *rw = brw;
-  *ww = bww;
-  return true;
-}
-
-struct PendingRec {
-  uint32_t gid, interval, aid, cell, cellkey, label, lidbase;
-  Pair rw, ww;
-};
-
-__device__ __forceinline__ void write_record(const SegParams& S, u64 pos, uint32_t slot, const PendingRec& p,
-                                             bool inter) {
-  if (pos >= S.rec_cap) { atomicOr(S.status_word, 2u); return; }
-  const uint32_t NONE = 0xFFFFFFFFu;
-  rc_record_dev r;
-  r.instance = S.inst_offset + slot;
-  r.gid = inter ? NONE : p.gid;
-  r.interval = inter ? 0u : p.interval;
-  r.array_label = p.aid | (p.label << 16);
-  r.cell = p.cell;
-  r.rw_a = p.rw.a == NONE ? NONE : p.rw.a + p.lidbase;
-  r.rw_b = p.rw.b == NONE ? NONE : p.rw.b + p.lidbase;
-  r.ww_a = p.ww.a == NONE ? NONE : p.ww.a + p.lidbase;
-  r.ww_b = p.ww.b == NONE ? NONE : p.ww.b + p.lidbase;
-  r.pad = 0;
-  S.staging[pos] = r;
-  const u64 scope = inter ? (u64)S.G * S.NI : (u64)p.gid * S.NI + p.interval;
-  S.rec_keys[pos] = ((u64)slot << (S.bs + S.bc)) | (scope << S.bc) | p.cellkey;
-  S.rec_idx[pos] = (uint32_t)pos;
-}
-
 // One thread per sorted log entry.  The first entry of a run of equal keys
 // checks its INTRA(gid, interval) scope; the first entry of a cell's run
 // also checks the INTER scope (global arrays, several groups).
@@ -712,7 +833,8 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
       u64 e = i + 1;
       while (e < n && S.keys[e] == k) ++e;
       if (e - i >= 2) {
-        has_intra = intra_check(S.vals, i, e, &pa.label, &pa.rw, &pa.ww);
+        const u64* vals = S.vals;
+        has_intra = intra_check([vals](u64 j) { return vals[j]; }, i, e, &pa.label, &pa.rw, &pa.ww);
         pa.gid = gid; pa.interval = interval; pa.aid = aid; pa.cell = cell; pa.cellkey = cellkey;
         pa.lidbase = gid * S.W;
       }
@@ -730,14 +852,11 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
   const u64 m1 = __ballot(has_intra), m2 = __ballot(has_inter);
   const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
   if (c1 + c2 == 0) return;
-  u64 base = 0;
-  if (lane == 0) base = atomicAdd(S.rec_count, (u64)(c1 + c2));
-  const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
-  const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
-  base = ((u64)bhi << 32) | blo;
+  const u64 base = wave_reserve(S.out.rec_count, c1 + c2, lane);
   const u64 below = (1ull << lane) - 1ull;
-  if (has_intra) write_record(S, base + (u64)__popcll(m1 & below), slot, pa, false);
-  if (has_inter) write_record(S, base + c1 + (u64)__popcll(m2 & below), slot, pb, true);
+  const RecKey K = {S.bs, S.bc, S.G, S.NI, S.inst_offset};
+  if (has_intra) store_record(S.out, K, base + (u64)__popcll(m1 & below), slot, pa, false);
+  if (has_inter) store_record(S.out, K, base + c1 + (u64)__popcll(m2 & below), slot, pb, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -61,11 +61,17 @@ enum : uint32_t {
   AK_GLOBAL_RO = 2,    // never-written global array: read its input directly
 };
 enum : uint32_t { BIND_NONE = 0, BIND_SEEDED = 1, BIND_DEVICE = 2 };
+// Where an array's accesses are logged.  Arrays never written cannot pair.
+// Local arrays, and global arrays when there is one work-group, pair only
+// inside a work-group interval: their log stays in LDS and is checked at the
+// barrier.  Global arrays with several work-groups also pair across groups
+// (INTER scope): their accesses go to the global log.
+enum : uint32_t { LOG_NONE = 0, LOG_GLOBAL = 1, LOG_LDS = 2 };
 
 struct ArrayDesc {        // 48 bytes
   uint32_t kind;          // AK_*
   uint32_t size;          // cells
-  uint32_t logged;        // accesses go to the access log (array is written somewhere)
+  uint32_t logged;        // LOG_NONE, LOG_GLOBAL or LOG_LDS (see below)
   uint32_t bind;          // BIND_* (global arrays)
   int64_t lo, hi;         // seeded range
   const int32_t* dptr;    // device binding
@@ -106,6 +112,20 @@ struct InterpParams {
   unsigned long long* inst_fault;     // [n_slots] min (gid, pc, lid, code) key
   unsigned int* status_word;          // bit 0: internal log overflow
   int do_log;                          // 0: run only (final memory)
+  // interval checks inside the interpreter (LDS path)
+  uint32_t lds_log_cap;                // T entries (power of two), 0: no LDS path
+  uint32_t bs, NI;                     // record key: scope bits, intervals per group
+  struct rc_record_out* rec;           // where records go (device struct)
+};
+
+// Record output shared by the interval checks (interpreter and global pass).
+struct rc_record_out {
+  void* staging;                       // rc_record[rec_cap]
+  unsigned long long* rec_keys;        // canonical sort key per staged record
+  uint32_t* rec_idx;
+  unsigned long long* rec_count;
+  unsigned long long rec_cap;
+  uint32_t* status_word;               // bit 1: staging capacity exceeded
 };
 
 // LDS control block of the interpreter (after the local cells and registers)

@@ -230,3 +230,18 @@ def test_api_errors():
     with pytest.raises(B.RcError) as ei:
         p.check_async(0, 1, ws, rec, cnt, summ)     # A is unbound
     assert ei.value.status == B.RC_E_STATE
+
+
+# ---------------------------------------------------------------------------
+# the LDS interval log: results do not depend on its size (small logs spill
+# intervals to the global pass)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("entries", [2, 64, 1024])
+@pytest.mark.parametrize("case", ["c1", "fig3", "tree", "transpose_race", "c3_1", "c3_5"])
+def test_lds_log_size_invariance(case, entries):
+    w = {"c1": lambda: WL.c1_kernel(1), "fig3": lambda: WL.fig3(64), "tree": lambda: WL.tree_reduce(True),
+         "transpose_race": lambda: WL.transpose(True), "c3_1": lambda: WL.c3_kernel(1),
+         "c3_5": lambda: WL.c3_kernel(5)}[case]()
+    g = U.gpu_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 3, lds_log_entries=entries)
+    o = U.oracle_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 3)
+    U.assert_same(g, o, f"{case} lds_log_entries={entries}")

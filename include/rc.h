@@ -193,6 +193,19 @@ rc_status rc_check(rc_prog* prog, uint64_t seed0, uint32_t n_seeds,
                    rc_record* d_records, uint64_t cap, uint64_t* d_n_records,
                    rc_summary* d_summaries);
 
+/*
+ * Check a list of instances of possibly different programs (all loaded on
+ * `ctx`, shaped and bound): instance i runs programs[i] with seed seeds[i].
+ * Records and summaries follow the list order (record.instance = i); other
+ * arguments and rules as rc_check.  The instances run in chunks that fit the
+ * workspace; inside a chunk, persistent workgroups take (instance, group)
+ * work items from a queue ordered longest first.
+ */
+rc_status rc_batch_check(rc_ctx* ctx, rc_prog* const* programs, const uint64_t* seeds, uint32_t n,
+                         void* d_ws, size_t ws_bytes,
+                         rc_record* d_records, uint64_t cap, uint64_t* d_n_records,
+                         rc_summary* d_summaries);
+
 /* Wait for the ctx stream; returns RC_E_OVERFLOW or RC_E_HIP for deferred
  * failures of earlier rc_check calls on this ctx, then clears them. */
 rc_status rc_sync(rc_ctx* ctx);

@@ -37,7 +37,7 @@ EXPORTS = [
     "rc_prog_free", "rc_prog_get_info", "rc_prog_array", "rc_prog_scalar", "rc_set_ndrange",
     "rc_bind_seeded", "rc_bind_device", "rc_bind_scalar_seeded", "rc_bind_scalar",
     "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
-    "rc_ctx_profile_read", "rc_prog_set_tuning",
+    "rc_ctx_profile_read", "rc_prog_set_tuning", "rc_batch_check",
 ]
 PHASES = ["interpret", "log_sort", "interval_check", "record_sort", "output", "setup"]
 
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         "rc_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "rc_ctx_profile_read": ([vp, ctypes.POINTER(_Profile)], ctypes.c_int),
         "rc_prog_set_tuning": ([vp, ctypes.POINTER(_Tuning)], ctypes.c_int),
+        "rc_batch_check": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64), u32, vp, sz,
+                            vp, u64, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -129,6 +131,16 @@ class Context:
 
     def sync(self):
         _call(_lib.rc_sync, self._h)
+
+    def batch_check_async(self, programs, seeds, ws, records, n_records, summaries):
+        """Enqueue a check of instances (programs[i], seeds[i]) into caller-owned buffers."""
+        n = len(programs)
+        parr = (ctypes.c_void_p * max(n, 1))(*[p._h.value for p in programs])
+        sarr = (ctypes.c_uint64 * max(n, 1))(*[int(x) & (2 ** 64 - 1) for x in seeds])
+        cap = records.numel() // RECORD_BYTES
+        _call(_lib.rc_batch_check, self._h, parr, sarr, n, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+              ctypes.c_void_p(records.data_ptr() if cap else 0), cap,
+              ctypes.c_void_p(n_records.data_ptr()), ctypes.c_void_p(summaries.data_ptr()))
 
     def profile(self, enable: bool = True):
         _call(_lib.rc_ctx_profile, self._h, 1 if enable else 0)

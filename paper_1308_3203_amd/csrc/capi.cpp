@@ -64,10 +64,17 @@ struct rc_ctx {
   std::vector<hipEvent_t> events;            // pool, reused after each read
   size_t events_used = 0;
   std::vector<std::pair<int, size_t>> spans; // (phase, index of the start event)
-  std::map<void*, std::string> ws_sig;   // workspace -> layout of its persistent part
+  struct WsState {
+    u64 gen = 0;               // generation this context last wrote to the header
+    uint32_t next_epoch = 1;   // first overlay version base not used yet
+  };
+  std::map<void*, WsState> ws_state;
   std::vector<Pending> pending;
-  rc_status deferred = RC_OK;
-  std::string deferred_msg;
+  hipEvent_t upload_done = nullptr;        // last host-to-device table upload
+  std::vector<unsigned char> h_call;       // host staging of the call tables
+  hipStream_t capture_stream = nullptr;    // private stream used only to capture graphs
+  std::vector<hipGraphExec_t> graphs_to_free;   // executable graphs of calls in flight
+  bool use_graphs = true;
 };
 
 struct rc_prog {
@@ -79,18 +86,18 @@ struct rc_prog {
   std::vector<ScalarDesc> scalars;
   std::vector<uint32_t> cellbase, sizes;
   uint32_t n_logged_cells = 0, overlay_cells = 0, lds_local_cells = 0;
-  uint32_t lds_log_pref = 0;         // preferred LDS log entries when a spill is possible (0: default)
+  uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
   uint32_t lds_log_cap = 0;          // chosen for the current shape
   // device: code, then tables
   void* d_mem = nullptr;
-  size_t off_arrays = 0, off_scalars = 0, off_cellbase = 0, off_size = 0, off_recout = 0, d_bytes = 0;
-  std::vector<unsigned char> h_tables;   // staging for the async table upload
+  size_t off_arrays = 0, off_scalars = 0, off_cellbase = 0, off_size = 0, d_bytes = 0;
+  std::vector<unsigned char> h_tables;   // staging for the table upload
 };
 
 namespace {
 
 // record a HIP event on the ctx stream when profiling; returns its pool index
-rc_status prof_mark(rc_ctx* ctx, size_t* idx) {
+rc_status prof_mark(rc_ctx* ctx, hipStream_t st, size_t* idx) {
   if (!ctx->profiling) return RC_OK;
   if (ctx->events_used == ctx->events.size()) {
     hipEvent_t e;
@@ -98,117 +105,39 @@ rc_status prof_mark(rc_ctx* ctx, size_t* idx) {
     ctx->events.push_back(e);
   }
   *idx = ctx->events_used++;
-  HIP_TRY(hipEventRecord(ctx->events[*idx], ctx->stream));
+  HIP_TRY(hipEventRecord(ctx->events[*idx], st));
   return RC_OK;
 }
 
 struct PhaseTimer {
   rc_ctx* ctx;
+  hipStream_t st;
   int phase;
   size_t start = 0;
-  PhaseTimer(rc_ctx* c, int ph) : ctx(c), phase(ph) {
-    if (ctx->profiling) prof_mark(ctx, &start);
+  bool on;
+  PhaseTimer(rc_ctx* c, hipStream_t s, int ph, bool enabled) : ctx(c), st(s), phase(ph), on(enabled && c->profiling) {
+    if (on) prof_mark(ctx, st, &start);
   }
   ~PhaseTimer() {
-    if (!ctx->profiling) return;
+    if (!on) return;
     size_t end = 0;
-    if (prof_mark(ctx, &end) == RC_OK && end == start + 1) ctx->spans.push_back({phase, start});
+    if (prof_mark(ctx, st, &end) == RC_OK && end == start + 1) ctx->spans.push_back({phase, start});
   }
 };
 
-struct Layout {
-  uint32_t n_slots = 0;
-  u64 log_cap = 0, rec_cap = 0, wg_log_cap = 0;
-  uint32_t bi = 0, bc = 0, bg = 0, bk = 0, bs = 0, nbits_log = 0, nbits_rec = 0;
-  uint32_t NI = 0;
-  // persistent
-  size_t epochs = 0, epoch_used = 0, overlay = 0, persistent_end = 0;
-  // per pass
-  size_t counters = 0, wg_count = 0, inst_acc = 0, inst_fault = 0, inst_int = 0, inst_race = 0, inst_benign = 0, inst_flags = 0;
-  size_t lk0 = 0, lv0 = 0, lk1 = 0, lv1 = 0, hist = 0, stage = 0, rk0 = 0, ri0 = 0, rk1 = 0, ri1 = 0;
-  size_t total = 0;
-  std::string signature;
-};
-
-// counters block: [0] log_count, [1] rec_count, [2] status word (u32 in a u64 slot)
-enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_WORDS = 4 };
-
-bool make_layout(const rc_prog* p, uint32_t n_slots, Layout* L, std::string* why) {
-  const Compiled& c = p->c;
-  L->n_slots = n_slots;
-  const u64 items = (u64)n_slots * p->G * p->W;
-  const double logcap = (double)items * (double)c.dyn_logged_mem;
-  if (logcap > 4.0e9) { *why = "access-log bound exceeds 4e9 entries for this pass"; return false; }
-  L->wg_log_cap = std::max<u64>(1, (u64)p->W * c.dyn_logged_mem);
-  L->log_cap = L->wg_log_cap * n_slots * p->G;
-  L->rec_cap = L->log_cap;
-  L->NI = (uint32_t)std::min<u64>(c.max_intervals, 0xFFFFFFFFull);
-  L->bi = bits_for(n_slots);
-  L->bc = bits_for(std::max<u64>(1, p->n_logged_cells));
-  L->bg = bits_for(p->G);
-  L->bk = bits_for(c.max_intervals);
-  L->nbits_log = L->bi + L->bc + L->bg + L->bk;
-  L->bs = bits_for((u64)p->G * c.max_intervals + 1);
-  L->nbits_rec = L->bi + L->bs + L->bc;
-  if (L->nbits_log > 64 || L->nbits_rec > 64 || L->bc > 32 || L->bg > 26 || L->bk > 32) {
-    *why = "sort key wider than 64 bits";
-    return false;
-  }
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
-  const u64 ovl = (u64)n_slots * p->G;
-  L->epochs = take(ovl * 4);
-  L->epoch_used = take(ovl * 4);
-  L->overlay = take(ovl * (u64)p->overlay_cells * 8);
-  L->persistent_end = o;
-  L->counters = take(CNT_WORDS * 8);
-  L->wg_count = take((size_t)n_slots * p->G * 4);
-  L->inst_acc = take((size_t)n_slots * 8);
-  L->inst_fault = take((size_t)n_slots * 8);
-  L->inst_int = take((size_t)n_slots * 4);
-  L->inst_race = take((size_t)n_slots * 4);
-  L->inst_benign = take((size_t)n_slots * 4);
-  L->inst_flags = take((size_t)n_slots * 4);
-  L->lk0 = take(L->log_cap * 8);
-  L->lv0 = take(L->log_cap * 8);
-  L->lk1 = take(L->log_cap * 8);
-  L->lv1 = take(L->log_cap * 8);
-  L->hist = take(std::max(sort_log_hist_words((u64)n_slots * p->G, L->wg_log_cap, L->log_cap),
-                          sort_hist_words(L->rec_cap)) * 4);
-  L->stage = take(L->rec_cap * sizeof(rc_record));
-  L->rk0 = take(L->rec_cap * 8);
-  L->ri0 = take(L->rec_cap * 4);
-  L->rk1 = take(L->rec_cap * 8);
-  L->ri1 = take(L->rec_cap * 4);
-  L->total = o;
-  char sig[160];
-  snprintf(sig, sizeof sig, "%p/%u/%u/%u/%zu", (const void*)p, n_slots, p->G, p->overlay_cells, L->persistent_end);
-  L->signature = sig;
-  return true;
-}
-
-rc_record_out record_out(const Layout& L, char* ws) {
-  rc_record_out R;
-  memset(&R, 0, sizeof R);
-  u64* cnt = (u64*)(ws + L.counters);
-  R.staging = ws + L.stage;
-  R.rec_keys = (u64*)(ws + L.rk0);
-  R.rec_idx = (uint32_t*)(ws + L.ri0);
-  R.rec_count = cnt + CNT_REC;
-  R.rec_cap = L.rec_cap;
-  R.status_word = (uint32_t*)(cnt + CNT_STATUS);
-  return R;
-}
-
-// LDS bytes of everything except the interval log
+// ---------------------------------------------------------------------------
+// per-program quantities
+// ---------------------------------------------------------------------------
 size_t lds_fixed_bytes(const rc_prog* p) {
   const uint32_t WP = ((p->W + 63) / 64) * 64;
-  return (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4 + sizeof(Ctl);
+  return ((sizeof(Ctl) + 15) & ~(size_t)15) + (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4;
 }
 
+size_t lds_bytes(const rc_prog* p) { return lds_fixed_bytes(p) + (size_t)p->lds_log_cap * 16; }
+
 // Entries of the interval log kept in LDS (a power of two; 0 = none): large
-// enough for the program's static bound when that fits, else as large as LDS
-// allows up to `pref` entries.
+// enough for the program's static per-interval bound when that fits, else as
+// large as LDS allows up to 4096 entries (or the tuned size).
 uint32_t lds_log_entries(const rc_prog* p) {
   const bool lds_globals = p->G == 1;
   const u64 per_item = p->c.dyn_logged_local + (lds_globals ? p->c.dyn_logged_mem - p->c.dyn_logged_local : 0);
@@ -217,17 +146,37 @@ uint32_t lds_log_entries(const rc_prog* p) {
   if (fixed + 32 > LDS_LIMIT) return 0;
   uint32_t fit = 2;
   while ((size_t)fit * 2 * 16 + fixed <= LDS_LIMIT && fit * 2 <= 65536u) fit *= 2;
-  const double bound = (double)p->W * (lds_globals ? p->c.interval_logged_all : p->c.interval_logged_local);
-  if (p->lds_log_pref) {   // explicit tuning
+  if (p->lds_log_pref) {
     uint32_t t = 2;
     while (t * 2 <= p->lds_log_pref && t * 2 <= fit) t *= 2;
     return t;
   }
-  const uint32_t pref = 4096u;
+  const double bound = (double)p->W * (lds_globals ? p->c.interval_logged_all : p->c.interval_logged_local);
   uint32_t want = 2;
   while (want < bound && want < 65536u) want *= 2;
   if ((double)want >= bound && want <= fit) return want;   // never spills
-  return std::min(fit, std::max<uint32_t>(pref, 2));
+  return std::min(fit, 4096u);
+}
+
+bool lds_logged(const rc_prog* p, uint32_t a) {
+  return p->lds_log_cap && p->c.arrays[a].written && (!p->c.arrays[a].global || p->G == 1);
+}
+
+// log entries one work-group may write to the global log
+u64 wg_log_entries(const rc_prog* p) {
+  const Compiled& c = p->c;
+  const u64 lds = p->lds_log_cap ? c.dyn_logged_local + (p->G == 1 ? c.dyn_logged_mem - c.dyn_logged_local : 0) : 0;
+  const u64 glob = c.dyn_logged_mem - lds;
+  const double ib = p->G == 1 ? c.interval_logged_all : c.interval_logged_local;
+  const bool spill = p->lds_log_cap && (double)p->W * ib > (double)p->lds_log_cap;
+  return std::max<u64>(1, (u64)p->W * (glob + (spill ? lds : 0)));
+}
+
+uint32_t width_class(uint32_t W) {
+  const uint32_t nw = (W + 63) / 64;
+  uint32_t c = 0;
+  while ((1u << c) < nw) ++c;
+  return c;   // 0..4
 }
 
 rc_status check_ready(const rc_prog* p) {
@@ -241,94 +190,444 @@ rc_status check_ready(const rc_prog* p) {
   return RC_OK;
 }
 
-rc_status upload_tables(rc_prog* p, hipStream_t st, const rc_record_out* R) {
-  unsigned char* h = p->h_tables.data();
-  for (size_t a = 0; a < p->arrays.size(); ++a) {
-    ArrayDesc& d = p->arrays[a];
-    if (!p->c.arrays[a].written) d.logged = LOG_NONE;
-    else if (p->lds_log_cap && (!p->c.arrays[a].global || p->G == 1)) d.logged = LOG_LDS;
-    else d.logged = LOG_GLOBAL;
-  }
-  memcpy(h + p->off_arrays - p->off_arrays, p->arrays.data(), p->arrays.size() * sizeof(ArrayDesc));
-  if (R) memcpy(h + (p->off_recout - p->off_arrays), R, sizeof *R);
-  memcpy(h + (p->off_scalars - p->off_arrays), p->scalars.data(), p->scalars.size() * sizeof(ScalarDesc));
-  memcpy(h + (p->off_cellbase - p->off_arrays), p->cellbase.data(), p->cellbase.size() * 4);
-  memcpy(h + (p->off_size - p->off_arrays), p->sizes.data(), p->sizes.size() * 4);
-  HIP_TRY(hipMemcpyAsync((char*)p->d_mem + p->off_arrays, h, p->h_tables.size(), hipMemcpyHostToDevice, st));
-  return RC_OK;
+// ---------------------------------------------------------------------------
+// a call: instances -> chunks under one workspace layout
+// ---------------------------------------------------------------------------
+struct Need {          // resources of one instance
+  u64 log, recs, ovl;
+  uint32_t wg;
+};
+
+Need need_of(const rc_prog* p) {
+  Need n;
+  n.wg = p->G;
+  n.log = (u64)p->G * wg_log_entries(p);
+  n.recs = std::max<u64>(1, (u64)p->G * p->W * p->c.dyn_logged_mem);
+  n.ovl = (u64)p->G * p->overlay_cells;
+  return n;
 }
 
-rc_status prepare_workspace(rc_prog* p, void* ws, const Layout& L) {
-  rc_ctx* ctx = p->ctx;
-  auto it = ctx->ws_sig.find(ws);
-  if (it == ctx->ws_sig.end() || it->second != L.signature) {
-    // fresh (or re-laid-out) workspace: clear epochs, epoch records and overlays
-    HIP_TRY(launch_fill_u64((u64*)ws, L.persistent_end / 8, 0ull, ctx->stream));
-    ctx->ws_sig[ws] = L.signature;
-  }
-  return RC_OK;
+struct Layout {
+  // limits of one chunk
+  u64 max_log = 0, max_rec = 0, max_ovl = 0;
+  uint32_t max_slots = 0, max_wg = 0, max_items_class[N_WCLASS] = {0, 0, 0, 0, 0};
+  // key layout
+  uint32_t bi = 0, bc = 0, bg = 0, bk = 0, bs = 0, nbits_log = 0, nbits_rec = 0;
+  // offsets in the workspace
+  size_t header = 0, overlay = 0, tables = 0, progs = 0, slots = 0, chunks = 0, items = 0, recout = 0;
+  size_t counters = 0, queue = 0, chunk_index = 0, wg_count = 0, wg_base = 0, tiles = 0;
+  size_t inst_acc = 0, inst_fault = 0, inst_int = 0, inst_race = 0, inst_benign = 0, inst_flags = 0;
+  size_t lk0 = 0, lv0 = 0, lk1 = 0, lv1 = 0, hist = 0, stage = 0, rk0 = 0, ri0 = 0, rk1 = 0, ri1 = 0;
+  size_t total = 0;
+};
+
+// counters block: [0] log entries, [1] records, [2] status word
+enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_WORDS = 8 };
+
+void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n_items) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+  L->header = take(64);                        // workspace header (validity of the pool)
+  L->overlay = take(L->max_ovl * 8);           // the versioned overlay pool
+  L->tables = o;
+  L->progs = take(n_progs * sizeof(ProgDesc));
+  L->slots = take(n_inst * sizeof(SlotDesc));
+  L->chunks = take(n_chunks * sizeof(ChunkDesc));
+  L->items = take(n_items * 8);
+  L->recout = take(sizeof(rc_record_out));
+  L->counters = take(CNT_WORDS * 8);
+  L->queue = take(N_WCLASS * 4);
+  L->chunk_index = take(4);
+  L->wg_count = take((size_t)L->max_wg * 4);
+  L->wg_base = take((size_t)L->max_wg * 8);
+  L->tiles = take(((size_t)L->max_wg + 1) * 4);
+  L->inst_acc = take((size_t)L->max_slots * 8);
+  L->inst_fault = take((size_t)L->max_slots * 8);
+  L->inst_int = take((size_t)L->max_slots * 4);
+  L->inst_race = take((size_t)L->max_slots * 4);
+  L->inst_benign = take((size_t)L->max_slots * 4);
+  L->inst_flags = take((size_t)L->max_slots * 4);
+  L->lk0 = take(L->max_log * 8);
+  L->lv0 = take(L->max_log * 8);
+  L->lk1 = take(L->max_log * 8);
+  L->lv1 = take(L->max_log * 8);
+  L->hist = take(std::max(sort_log_hist_words(L->max_wg, L->max_log), sort_hist_words(L->max_rec)) * 4);
+  L->stage = take(L->max_rec * sizeof(rc_record));
+  L->rk0 = take(L->max_rec * 8);
+  L->ri0 = take(L->max_rec * 4);
+  L->rk1 = take(L->max_rec * 8);
+  L->ri1 = take(L->max_rec * 4);
+  L->total = o;
 }
 
-InterpParams interp_params(const rc_prog* p, const Layout& L, char* ws, uint64_t seed0, uint32_t inst_offset,
-                           uint32_t n, int do_log) {
-  InterpParams P;
-  memset(&P, 0, sizeof P);
-  P.code = (const uint32_t*)p->d_mem;
-  P.n_arrays = (uint32_t)p->c.arrays.size();
-  P.n_global = p->c.n_global;
-  P.n_scalars = (uint32_t)p->c.scalars.size();
-  P.nregs = p->c.nregs;
-  P.G = p->G;
-  P.W = p->W;
-  P.nwaves = (p->W + 63) / 64;
-  P.lds_local_cells = p->lds_local_cells;
-  P.n_slots = n;
-  P.overlay_cells = p->overlay_cells;
-  P.max_store_seq = (uint32_t)std::min<u64>(p->c.dyn_stores, (1u << 22));
-  P.inst_offset = inst_offset;
-  P.seed0 = seed0;
-  P.bc = L.bc;
-  P.bg = L.bg;
-  P.bk = L.bk;
-  P.arrays = (const ArrayDesc*)((char*)p->d_mem + p->off_arrays);
-  P.scalars = (const ScalarDesc*)((char*)p->d_mem + p->off_scalars);
-  P.epochs = (uint32_t*)(ws + L.epochs);
-  P.epoch_used = (uint32_t*)(ws + L.epoch_used);
-  P.overlay = (u64*)(ws + L.overlay);
+struct Call {
+  std::vector<rc_prog*> progs;          // distinct programs
+  std::vector<uint32_t> inst_prog;      // instance -> program index
+  std::vector<uint64_t> inst_seed;
+  std::vector<SlotDesc> slots;
+  std::vector<ChunkDesc> chunks;
+  std::vector<uint32_t> items;          // pairs (instance, gid)
+  Layout L;
+  uint32_t classes_used = 0;            // bit c: width class c occurs
+  size_t class_lds[N_WCLASS] = {0, 0, 0, 0, 0};
+  uint32_t epoch_stride = 1;
+};
+
+// Split the instances into chunks whose resources stay under the limits.
+void partition(Call& C, const Layout& lim) {
+  C.chunks.clear();
+  C.slots.assign(C.inst_prog.size(), SlotDesc());
+  std::vector<std::vector<uint32_t>> class_items(N_WCLASS);
+  u64 log = 0, ovl = 0;
+  uint32_t wg = 0, n = 0;
+  ChunkDesc cur;
+  memset(&cur, 0, sizeof cur);
+  auto flush = [&](uint32_t next_slot0) {
+    cur.n_slots = n;
+    cur.n_wg = wg;
+    uint32_t at = (uint32_t)(C.items.size() / 2);
+    for (uint32_t c = 0; c < N_WCLASS; ++c) {
+      cur.item0[c] = at;
+      // longest first: cost = width x static instructions
+      std::vector<uint32_t>& v = class_items[c];
+      std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) {
+        const rc_prog* pa = C.progs[C.inst_prog[a >> 0]];
+        const rc_prog* pb = C.progs[C.inst_prog[b >> 0]];
+        return (double)pa->W * (double)pa->c.dyn_instr > (double)pb->W * (double)pb->c.dyn_instr;
+      });
+      for (uint32_t inst : v) {
+        const rc_prog* p = C.progs[C.inst_prog[inst]];
+        for (uint32_t g = 0; g < p->G; ++g) { C.items.push_back(inst); C.items.push_back(g); }
+      }
+      at = (uint32_t)(C.items.size() / 2);
+      v.clear();
+    }
+    cur.item0[N_WCLASS] = at;
+    cur.n_items = at - cur.item0[0];
+    C.chunks.push_back(cur);
+    memset(&cur, 0, sizeof cur);
+    cur.slot0 = next_slot0;
+    log = ovl = 0;
+    wg = n = 0;
+  };
+  const uint32_t N = (uint32_t)C.inst_prog.size();
+  for (uint32_t i = 0; i < N; ++i) {
+    const rc_prog* p = C.progs[C.inst_prog[i]];
+    const Need nd = need_of(p);
+    if (n > 0 && (n + 1 > lim.max_slots || wg + nd.wg > lim.max_wg || log + nd.log > lim.max_log ||
+                  ovl + nd.ovl > lim.max_ovl))
+      flush(i);
+    SlotDesc& s = C.slots[i];
+    s.seed = C.inst_seed[i];
+    s.log_base = log;
+    s.ovl_base = ovl;
+    s.prog = C.inst_prog[i];
+    s.wg_base = wg;
+    class_items[width_class(p->W)].push_back(i);
+    log += nd.log;
+    ovl += nd.ovl;
+    wg += nd.wg;
+    ++n;
+  }
+  if (n > 0) flush(N);
+}
+
+// Choose chunk limits so that the layout fits `ws_bytes`, then partition.
+bool plan(Call& C, size_t ws_bytes, std::string* why) {
+  const uint32_t N = (uint32_t)C.inst_prog.size();
+  u64 T_log = 0, T_rec = 0, T_ovl = 0, T_wg = 0, M_log = 0, M_rec = 0, M_ovl = 0, M_wg = 0;
+  uint32_t bc = 0, bg = 0, bk = 0, bs = 0;
+  u64 max_stores = 0, items_total = 0;
+  for (uint32_t i = 0; i < N; ++i) {
+    const Need nd = need_of(C.progs[C.inst_prog[i]]);
+    T_log += nd.log; T_rec += nd.recs; T_ovl += nd.ovl; T_wg += nd.wg;
+    M_log = std::max(M_log, nd.log); M_rec = std::max(M_rec, nd.recs);
+    M_ovl = std::max(M_ovl, nd.ovl); M_wg = std::max<u64>(M_wg, nd.wg);
+    items_total += nd.wg;
+  }
+  C.classes_used = 0;
+  for (rc_prog* p : C.progs) {
+    bc = std::max(bc, bits_for(std::max<u64>(1, p->n_logged_cells)));
+    bg = std::max(bg, bits_for(p->G));
+    bk = std::max(bk, bits_for(p->c.max_intervals));
+    bs = std::max(bs, bits_for((u64)p->G * p->c.max_intervals + 1));
+    max_stores = std::max<u64>(max_stores, p->c.dyn_stores);
+    const uint32_t c = width_class(p->W);
+    C.classes_used |= 1u << c;
+    C.class_lds[c] = std::max(C.class_lds[c], lds_bytes(p));
+  }
+  C.epoch_stride = (uint32_t)std::min<u64>(max_stores + 1, 1u << 22);
+  if (bc > 32 || bg > 26 || bk > 32) { *why = "sort key fields too wide"; return false; }
+  // try 1, 2, 4, ... chunks
+  for (u64 k = 1;; k *= 2) {
+    Layout L;
+    const u64 per = (N + k - 1) / k;
+    L.max_slots = (uint32_t)std::min<u64>(N, per + 1);
+    L.max_wg = (uint32_t)std::min<u64>(T_wg, (T_wg + k - 1) / k + M_wg);
+    L.max_log = std::min<u64>(T_log, (T_log + k - 1) / k + M_log);
+    L.max_rec = std::min<u64>(T_rec, (T_rec + k - 1) / k + M_rec);
+    L.max_ovl = std::min<u64>(T_ovl, (T_ovl + k - 1) / k + M_ovl);
+    L.max_rec = std::max<u64>(L.max_rec, L.max_log);
+    L.bi = bits_for(L.max_slots);
+    L.bc = bc; L.bg = bg; L.bk = bk; L.bs = bs;
+    L.nbits_log = L.bi + bc + bg + bk;
+    L.nbits_rec = L.bi + bs + bc;
+    if (L.nbits_log > 64 || L.nbits_rec > 64) { *why = "sort key wider than 64 bits"; return false; }
+    Layout lim = L;
+    partition(C, lim);
+    lay_out(&L, C.progs.size(), N, C.chunks.size(), C.items.size() / 2);
+    if (L.total <= ws_bytes) {
+      // class grid sizes: the most items one class has in any chunk
+      for (const ChunkDesc& ch : C.chunks)
+        for (uint32_t c = 0; c < N_WCLASS; ++c)
+          L.max_items_class[c] = std::max(L.max_items_class[c], ch.item0[c + 1] - ch.item0[c]);
+      C.L = L;
+      return true;
+    }
+    if (k >= 2 * (u64)N + 2) {
+      char b[200];
+      snprintf(b, sizeof b, "workspace of %zu bytes is too small: one instance needs %zu", ws_bytes, L.total);
+      *why = b;
+      return false;
+    }
+    C.items.clear();
+  }
+}
+
+// the per-chunk kernel sequence
+rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u64* d_n_records,
+                        rc_record* d_records, u64 cap, rc_summary* d_summaries, int do_log, bool timed) {
+  const Layout& L = C.L;
   u64* cnt = (u64*)(ws + L.counters);
-  P.log_keys = (u64*)(ws + L.lk0);
-  P.log_vals = (u64*)(ws + L.lv0);
-  P.wg_count = (uint32_t*)(ws + L.wg_count);
-  P.wg_log_cap = L.wg_log_cap;
-  P.inst_acc = (u64*)(ws + L.inst_acc);
-  P.inst_intervals = (uint32_t*)(ws + L.inst_int);
-  P.inst_fault = (u64*)(ws + L.inst_fault);
-  P.status_word = (uint32_t*)(cnt + CNT_STATUS);
-  P.do_log = do_log;
-  P.lds_log_cap = p->lds_log_cap;
-  P.bs = L.bs;
-  P.NI = L.NI;
-  P.rec = (rc_record_out*)((char*)p->d_mem + p->off_recout);
-  return P;
+  const ProgDesc* progs = (const ProgDesc*)(ws + L.progs);
+  const SlotDesc* slots = (const SlotDesc*)(ws + L.slots);
+  const ChunkDesc* chunks = (const ChunkDesc*)(ws + L.chunks);
+  const uint32_t* chunk_index = (const uint32_t*)(ws + L.chunk_index);
+  {
+    PhaseTimer t(ctx, st, 5, timed);
+    SetupParams S;
+    memset(&S, 0, sizeof S);
+    S.chunks = chunks; S.chunk_index = chunk_index; S.counters = cnt; S.queue = (uint32_t*)(ws + L.queue);
+    S.inst_acc = (u64*)(ws + L.inst_acc); S.inst_fault = (u64*)(ws + L.inst_fault);
+    S.inst_intervals = (uint32_t*)(ws + L.inst_int); S.inst_race = (uint32_t*)(ws + L.inst_race);
+    S.inst_benign = (uint32_t*)(ws + L.inst_benign); S.inst_flags = (uint32_t*)(ws + L.inst_flags);
+    S.overlay = (u64*)(ws + L.overlay); S.overlay_cells = L.max_ovl; S.max_slots = L.max_slots;
+    HIP_TRY(launch_setup(S, st));
+    HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.wg_count), L.max_wg, 0u, st));
+  }
+  {
+    PhaseTimer t(ctx, st, 0, timed);
+    PassParams P;
+    memset(&P, 0, sizeof P);
+    P.progs = progs; P.slots = slots; P.chunks = chunks; P.chunk_index = chunk_index;
+    P.items = (const uint32_t*)(ws + L.items); P.queue = (uint32_t*)(ws + L.queue);
+    P.bc = L.bc; P.bg = L.bg; P.bk = L.bk; P.bs = L.bs; P.do_log = (uint32_t)do_log;
+    P.overlay = (u64*)(ws + L.overlay); P.log_keys = (u64*)(ws + L.lk0); P.log_vals = (u64*)(ws + L.lv0);
+    P.wg_count = (uint32_t*)(ws + L.wg_count); P.wg_base = (u64*)(ws + L.wg_base);
+    P.inst_acc = (u64*)(ws + L.inst_acc); P.inst_intervals = (uint32_t*)(ws + L.inst_int);
+    P.inst_fault = (u64*)(ws + L.inst_fault); P.status_word = (uint32_t*)(cnt + CNT_STATUS);
+    P.rec = (rc_record_out*)(ws + L.recout);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    for (uint32_t c = 0; c < N_WCLASS; ++c) {
+      if (!(C.classes_used & (1u << c))) continue;
+      P.wclass = c;
+      const uint32_t threads = 64u << c;
+      const size_t lds = C.class_lds[c];
+      const uint32_t resident = (uint32_t)cus * (uint32_t)interp_occupancy(threads, lds);
+      const uint32_t blocks = std::max<uint32_t>(1, std::min(L.max_items_class[c], resident));
+      HIP_TRY(launch_interp(P, blocks, threads, lds, st));
+    }
+  }
+  if (!do_log) return RC_OK;
+  int second = 0;
+  u64 *lk0 = (u64*)(ws + L.lk0), *lv0 = (u64*)(ws + L.lv0), *lk1 = (u64*)(ws + L.lk1), *lv1 = (u64*)(ws + L.lv1);
+  {
+    PhaseTimer t(ctx, st, 1, timed);
+    HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.max_log, L.nbits_log, (const uint32_t*)(ws + L.wg_count),
+                     (const u64*)(ws + L.wg_base), (uint32_t*)(ws + L.tiles), L.max_wg, (uint32_t*)(ws + L.hist), st,
+                     &second));
+  }
+  {
+    PhaseTimer t(ctx, st, 2, timed);
+    SegParams S;
+    memset(&S, 0, sizeof S);
+    S.keys = second ? lk1 : lk0;
+    S.vals = second ? lv1 : lv0;
+    S.n_ptr = cnt + CNT_LOG;
+    S.bc = L.bc; S.bg = L.bg; S.bk = L.bk; S.bs = L.bs;
+    S.progs = progs; S.slots = slots; S.chunks = chunks; S.chunk_index = chunk_index;
+    memset(&S.out, 0, sizeof S.out);
+    S.out.staging = ws + L.stage; S.out.rec_keys = (u64*)(ws + L.rk0); S.out.rec_idx = (uint32_t*)(ws + L.ri0);
+    S.out.rec_count = cnt + CNT_REC; S.out.rec_cap = L.max_rec; S.out.status_word = (uint32_t*)(cnt + CNT_STATUS);
+    HIP_TRY(launch_seg_check(S, L.max_log, st));
+  }
+  HIP_TRY(launch_clamp(cnt + CNT_REC, L.max_rec, (uint32_t*)(cnt + CNT_STATUS), 2u, st));
+  int rsecond = 0;
+  {
+    PhaseTimer t(ctx, st, 3, timed);
+    HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1), (uint32_t*)(ws + L.ri1),
+                           cnt + CNT_REC, L.max_rec, L.nbits_rec, (uint32_t*)(ws + L.hist), st, &rsecond));
+  }
+  {
+    PhaseTimer t(ctx, st, 4, timed);
+    GatherParams Gp;
+    memset(&Gp, 0, sizeof Gp);
+    Gp.staging = (const rc_record_dev*)(ws + L.stage);
+    Gp.idx = (const uint32_t*)(ws + (rsecond ? L.ri1 : L.ri0));
+    Gp.n_ptr = cnt + CNT_REC;
+    Gp.out_base = (u64*)d_n_records;
+    Gp.out = (rc_record_dev*)d_records;
+    Gp.cap = cap;
+    Gp.chunks = chunks; Gp.chunk_index = chunk_index;
+    Gp.inst_flags = (uint32_t*)(ws + L.inst_flags);
+    Gp.inst_race = (uint32_t*)(ws + L.inst_race);
+    Gp.inst_benign = (uint32_t*)(ws + L.inst_benign);
+    HIP_TRY(launch_gather(Gp, L.max_rec, st));
+    FinalParams F;
+    memset(&F, 0, sizeof F);
+    F.progs = progs; F.slots = slots; F.chunks = chunks; F.chunk_index = chunk_index;
+    F.inst_acc = (const u64*)(ws + L.inst_acc);
+    F.inst_race = (const uint32_t*)(ws + L.inst_race);
+    F.inst_benign = (const uint32_t*)(ws + L.inst_benign);
+    F.inst_intervals = (const uint32_t*)(ws + L.inst_int);
+    F.inst_flags = (const uint32_t*)(ws + L.inst_flags);
+    F.inst_fault = (const u64*)(ws + L.inst_fault);
+    F.out = (rc_summary_dev*)d_summaries;
+    F.max_slots = L.max_slots;
+    HIP_TRY(launch_finalize(F, st));
+    HIP_TRY(launch_advance((u64*)d_n_records, cnt + CNT_REC, (uint32_t*)(ws + L.chunk_index), st));
+  }
+  return RC_OK;
 }
 
-size_t lds_bytes(const rc_prog* p) { return lds_fixed_bytes(p) + (size_t)p->lds_log_cap * 16; }
+// Build the call's tables, upload them, and enqueue every chunk.
+rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d_records, u64 cap,
+                   u64* d_n_records, rc_summary* d_summaries, int do_log, uint32_t* epoch_out) {
+  hipStream_t st = ctx->stream;
+  std::string why;
+  if (!plan(C, ws_bytes, &why)) return fail(RC_E_INVAL, "%s", why.c_str());
+  const Layout& L = C.L;
+  // overlay versions: one base per chunk, above everything earlier on this workspace
+  // The device checks the workspace header and clears the pool unless it
+  // holds only cells this context versioned (a cleared pool is valid for any
+  // version base, so the host keeps its own sequence).
+  rc_ctx::WsState& wst = ctx->ws_state[(void*)ws];
+  HIP_TRY(launch_ws_validate((u64*)(ws + L.header), 0x52433147524146ull, (u64)(uintptr_t)ctx, wst.gen,
+                             (u64*)(ws + L.overlay), L.max_ovl, (uint32_t*)(ws + L.header + 32), st));
+  wst.gen += 1;
+  for (ChunkDesc& ch : C.chunks) {
+    if (wst.next_epoch + C.epoch_stride >= (1u << 22)) {
+      ch.clear_overlay = 1;
+      wst.next_epoch = 1;
+    }
+    ch.epoch = wst.next_epoch;
+    wst.next_epoch += C.epoch_stride;
+  }
+  if (epoch_out) *epoch_out = C.chunks.empty() ? 1u : C.chunks.back().epoch;
+  // per-program descriptor tables (bindings and log placement may change between calls)
+  if (ctx->upload_done) HIP_TRY(hipEventSynchronize(ctx->upload_done));
+  std::vector<ProgDesc> pd(C.progs.size());
+  for (size_t i = 0; i < C.progs.size(); ++i) {
+    rc_prog* p = C.progs[i];
+    for (size_t a = 0; a < p->arrays.size(); ++a) {
+      ArrayDesc& d = p->arrays[a];
+      d.logged = !p->c.arrays[a].written ? LOG_NONE : (lds_logged(p, (uint32_t)a) ? LOG_LDS : LOG_GLOBAL);
+    }
+    unsigned char* h = p->h_tables.data();
+    memcpy(h, p->arrays.data(), p->arrays.size() * sizeof(ArrayDesc));
+    memcpy(h + (p->off_scalars - p->off_arrays), p->scalars.data(), p->scalars.size() * sizeof(ScalarDesc));
+    memcpy(h + (p->off_cellbase - p->off_arrays), p->cellbase.data(), p->cellbase.size() * 4);
+    memcpy(h + (p->off_size - p->off_arrays), p->sizes.data(), p->sizes.size() * 4);
+    HIP_TRY(hipMemcpyAsync((char*)p->d_mem + p->off_arrays, h, p->h_tables.size(), hipMemcpyHostToDevice, st));
+    ProgDesc& D = pd[i];
+    memset(&D, 0, sizeof D);
+    D.code = (const uint32_t*)p->d_mem;
+    D.arrays = (const ArrayDesc*)((char*)p->d_mem + p->off_arrays);
+    D.scalars = (const ScalarDesc*)((char*)p->d_mem + p->off_scalars);
+    D.cellbase = (const uint32_t*)((char*)p->d_mem + p->off_cellbase);
+    D.size = (const uint32_t*)((char*)p->d_mem + p->off_size);
+    D.n_arrays = (uint32_t)p->c.arrays.size();
+    D.n_global = p->c.n_global;
+    D.n_scalars = (uint32_t)p->c.scalars.size();
+    D.nregs = p->c.nregs;
+    D.G = p->G;
+    D.W = p->W;
+    D.nwaves = (p->W + 63) / 64;
+    D.lds_local_cells = p->lds_local_cells;
+    D.lds_log_cap = p->lds_log_cap;
+    D.overlay_cells = p->overlay_cells;
+    D.NI = (uint32_t)p->c.max_intervals;
+    D.wg_log_cap = wg_log_entries(p);
+  }
+  rc_record_out R;
+  memset(&R, 0, sizeof R);
+  u64* cnt = (u64*)(ws + L.counters);
+  R.staging = ws + L.stage;
+  R.rec_keys = (u64*)(ws + L.rk0);
+  R.rec_idx = (uint32_t*)(ws + L.ri0);
+  R.rec_count = cnt + CNT_REC;
+  R.rec_cap = L.max_rec;
+  R.status_word = (uint32_t*)(cnt + CNT_STATUS);
+  // one upload of all call tables (they sit contiguously after the overlay pool)
+  const size_t tbytes = L.counters - L.tables;
+  ctx->h_call.assign(tbytes, 0);
+  unsigned char* h = ctx->h_call.data();
+  memcpy(h + (L.progs - L.tables), pd.data(), pd.size() * sizeof(ProgDesc));
+  memcpy(h + (L.slots - L.tables), C.slots.data(), C.slots.size() * sizeof(SlotDesc));
+  memcpy(h + (L.chunks - L.tables), C.chunks.data(), C.chunks.size() * sizeof(ChunkDesc));
+  memcpy(h + (L.items - L.tables), C.items.data(), C.items.size() * 4);
+  memcpy(h + (L.recout - L.tables), &R, sizeof R);
+  HIP_TRY(hipMemcpyAsync(ws + L.tables, h, tbytes, hipMemcpyHostToDevice, st));
+  if (!ctx->upload_done) HIP_TRY(hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ctx->upload_done, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.chunk_index), 1, 0u, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)(cnt + CNT_STATUS), 1, 0u, st));
+  if (d_n_records) HIP_TRY(launch_fill_u64((u64*)d_n_records, 1, 0ull, st));
+  const size_t n_chunks = C.chunks.size();
+  // With several chunks and no profiling, capture one chunk's kernels as a
+  // graph and replay it; every chunk reads its parameters from device tables.
+  if (n_chunks > 1 && ctx->use_graphs && !ctx->profiling) {
+    if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    rc_status s = enqueue_chunk(ctx, C, ws, ctx->capture_stream, d_n_records, d_records, cap, d_summaries, do_log,
+                                false);
+    hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (s != RC_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+    if (e != hipSuccess) return fail(RC_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(RC_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    for (size_t c = 0; c < n_chunks; ++c) {
+      e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess) { (void)hipGraphExecDestroy(exec); return fail(RC_E_HIP, "graph launch: %s", hipGetErrorString(e)); }
+    }
+    ctx->graphs_to_free.push_back(exec);
+    return RC_OK;
+  }
+  for (size_t c = 0; c < n_chunks; ++c) {
+    rc_status s = enqueue_chunk(ctx, C, ws, st, d_n_records, d_records, cap, d_summaries, do_log, true);
+    if (s) return s;
+  }
+  return RC_OK;
+}
 
-rc_status reset_pass(const rc_prog* p, const Layout& L, char* ws, hipStream_t st) {
-  HIP_TRY(launch_fill_u64((u64*)(ws + L.counters), 2, 0ull, st));   // log and record counters
-  HIP_TRY(launch_fill_u64((u64*)(ws + L.inst_acc), L.n_slots, 0ull, st));
-  HIP_TRY(launch_fill_u64((u64*)(ws + L.inst_fault), L.n_slots, ~0ull, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.inst_int), L.n_slots, 0u, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.inst_race), L.n_slots, 0u, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.inst_benign), L.n_slots, 0u, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.inst_flags), L.n_slots, 0u, st));
-  (void)p;
+rc_status add_program(Call& C, rc_prog* p, std::map<rc_prog*, uint32_t>& index, uint32_t* out) {
+  auto it = index.find(p);
+  if (it != index.end()) { *out = it->second; return RC_OK; }
+  rc_status s = check_ready(p);
+  if (s) return s;
+  const uint32_t k = (uint32_t)C.progs.size();
+  C.progs.push_back(p);
+  index[p] = k;
+  *out = k;
   return RC_OK;
 }
 
 }  // namespace
 
-// ===========================================================================
 extern "C" {
 
 const char* rc_last_error(void) { return g_err.c_str(); }
@@ -349,7 +648,11 @@ rc_status rc_ctx_create(int device, void* hip_stream, rc_ctx** out) {
 
 rc_status rc_ctx_destroy(rc_ctx* ctx) {
   if (!ctx) return fail(RC_E_INVAL, "ctx is NULL");
+  (void)hipStreamSynchronize(ctx->stream);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  for (hipGraphExec_t g : ctx->graphs_to_free) (void)hipGraphExecDestroy(g);
+  if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
   return RC_OK;
 }
@@ -440,8 +743,6 @@ rc_status rc_prog_load(rc_ctx* ctx, const char* src, size_t len, rc_prog** out) 
   o += align_up(na * 4 + 1, 64);
   p->off_size = o;
   o += align_up(na * 4 + 1, 64);
-  p->off_recout = o;
-  o += align_up(sizeof(rc_record_out), 64);
   p->d_bytes = o;
   p->h_tables.assign(o - p->off_arrays, 0);
   hipError_t e = hipMalloc(&p->d_mem, o);
@@ -500,7 +801,7 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   if ((u64)num_groups * group_size >= (1ull << 26)) return fail(RC_E_LIMIT, "num_groups * group_size must be < 2^26");
   const uint32_t W = group_size;
   const uint32_t WP = ((W + 63) / 64) * 64;
-  const size_t lds = (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4 + sizeof(Ctl);
+  const size_t lds = ((sizeof(Ctl) + 15) & ~(size_t)15) + (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4;
   if (lds > LDS_LIMIT)
     return fail(RC_E_LIMIT, "local arrays and registers need %zu bytes of LDS (limit %u)", lds, LDS_LIMIT);
   if (p->c.max_intervals >= (1ull << 32)) return fail(RC_E_LIMIT, "too many barrier intervals");
@@ -566,10 +867,14 @@ rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
 rc_status rc_workspace_size(const rc_prog* p, uint32_t n_seeds, size_t* bytes) {
   if (!p || !bytes) return fail(RC_E_INVAL, "NULL argument");
   if (!p->shaped) return fail(RC_E_STATE, "rc_set_ndrange has not been called");
-  Layout L;
+  Call C;
+  C.progs.push_back(const_cast<rc_prog*>(p));
+  const uint32_t n = std::max<uint32_t>(1, n_seeds);
+  C.inst_prog.assign(n, 0);
+  C.inst_seed.assign(n, 0);
   std::string why;
-  if (!make_layout(p, std::max<uint32_t>(1, n_seeds), &L, &why)) return fail(RC_E_LIMIT, "%s", why.c_str());
-  *bytes = L.total;
+  if (!plan(C, ~(size_t)0, &why)) return fail(RC_E_LIMIT, "%s", why.c_str());
+  *bytes = C.L.total;
   return RC_OK;
 }
 
@@ -580,113 +885,46 @@ rc_status rc_check(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, siz
   rc_status s = check_ready(p);
   if (s) return s;
   rc_ctx* ctx = p->ctx;
-  hipStream_t st = ctx->stream;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(launch_fill_u64((u64*)d_n_records, 1, 0ull, st));
-  if (n_seeds == 0) return RC_OK;
-  // largest pass that fits the workspace
-  Layout L;
-  std::string why;
-  uint32_t lo = 1, hi = n_seeds;
-  if (!make_layout(p, 1, &L, &why)) return fail(RC_E_LIMIT, "%s", why.c_str());
-  if (L.total > ws_bytes)
-    return fail(RC_E_INVAL, "workspace of %zu bytes is smaller than the %zu needed for one seed", ws_bytes, L.total);
-  while (lo < hi) {
-    uint32_t mid = lo + (hi - lo + 1) / 2;
-    Layout M;
-    if (make_layout(p, mid, &M, &why) && M.total <= ws_bytes) lo = mid;
-    else hi = mid - 1;
+  if (n_seeds == 0) {
+    HIP_TRY(launch_fill_u64((u64*)d_n_records, 1, 0ull, ctx->stream));
+    return RC_OK;
   }
-  make_layout(p, lo, &L, &why);
-  char* ws = (char*)d_ws;
-  s = prepare_workspace(p, ws, L);
+  Call C;
+  C.progs.push_back(p);
+  C.inst_prog.assign(n_seeds, 0);
+  C.inst_seed.resize(n_seeds);
+  for (uint32_t j = 0; j < n_seeds; ++j) C.inst_seed[j] = seed0 + j;
+  s = run_call(ctx, C, (char*)d_ws, ws_bytes, d_records, cap, (u64*)d_n_records, d_summaries, 1, nullptr);
   if (s) return s;
-  const rc_record_out R = record_out(L, ws);
-  s = upload_tables(p, st, &R);
-  if (s) return s;
-  u64* cnt = (u64*)(ws + L.counters);
-  HIP_TRY(launch_fill_u64(cnt + CNT_STATUS, 1, 0ull, st));
-  const size_t lds = lds_bytes(p);
-  for (uint32_t off = 0; off < n_seeds; off += L.n_slots) {
-    const uint32_t n = std::min(L.n_slots, n_seeds - off);
-    {
-      PhaseTimer t(ctx, 5);
-      s = reset_pass(p, L, ws, st);
-      if (s) return s;
-    }
-    InterpParams P = interp_params(p, L, ws, seed0, off, n, 1);
-    {
-      PhaseTimer t(ctx, 0);
-      HIP_TRY(launch_interp(P, lds, st));
-    }
-    // sort the access log by (instance, cell, gid, interval)
-    int second = 0;
-    u64 *lk0 = (u64*)(ws + L.lk0), *lv0 = (u64*)(ws + L.lv0), *lk1 = (u64*)(ws + L.lk1), *lv1 = (u64*)(ws + L.lv1);
-    {
-      PhaseTimer t(ctx, 1);
-      HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.log_cap, L.nbits_log, (const uint32_t*)(ws + L.wg_count),
-                       (u64)n * p->G, L.wg_log_cap, (uint32_t*)(ws + L.hist), st, &second));
-    }
-    SegParams S;
-    memset(&S, 0, sizeof S);
-    S.keys = second ? lk1 : lk0;
-    S.vals = second ? lv1 : lv0;
-    S.n_ptr = cnt + CNT_LOG;
-    S.bc = L.bc;
-    S.bg = L.bg;
-    S.bk = L.bk;
-    S.bs = L.bs;
-    S.G = p->G;
-    S.W = p->W;
-    S.NI = L.NI;
-    S.n_arrays = (uint32_t)p->c.arrays.size();
-    S.n_global = p->c.n_global;
-    S.inst_offset = off;
-    S.cellbase = (const uint32_t*)((char*)p->d_mem + p->off_cellbase);
-    S.size = (const uint32_t*)((char*)p->d_mem + p->off_size);
-    S.out = record_out(L, ws);
-    {
-      PhaseTimer t(ctx, 2);
-      HIP_TRY(launch_seg_check(S, L.log_cap, st));
-    }
-    HIP_TRY(launch_clamp(cnt + CNT_REC, L.rec_cap, (uint32_t*)(cnt + CNT_STATUS), 2u, st));
-    // canonical order of the records
-    int rsecond = 0;
-    {
-      PhaseTimer t(ctx, 3);
-      HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1),
-                             (uint32_t*)(ws + L.ri1), cnt + CNT_REC, L.rec_cap, L.nbits_rec,
-                             (uint32_t*)(ws + L.hist), st, &rsecond));
-    }
-    PhaseTimer out_timer(ctx, 4);
-    GatherParams Gp;
-    memset(&Gp, 0, sizeof Gp);
-    Gp.staging = (const rc_record_dev*)(ws + L.stage);
-    Gp.idx = (const uint32_t*)(ws + (rsecond ? L.ri1 : L.ri0));
-    Gp.n_ptr = cnt + CNT_REC;
-    Gp.out_base = (u64*)d_n_records;
-    Gp.out = (rc_record_dev*)d_records;
-    Gp.cap = cap;
-    Gp.inst_offset = off;
-    Gp.inst_flags = (uint32_t*)(ws + L.inst_flags);
-    Gp.inst_race = (uint32_t*)(ws + L.inst_race);
-    Gp.inst_benign = (uint32_t*)(ws + L.inst_benign);
-    HIP_TRY(launch_gather(Gp, L.rec_cap, st));
-    FinalParams F;
-    memset(&F, 0, sizeof F);
-    F.n_slots = n;
-    F.inst_offset = off;
-    F.W = p->W;
-    F.inst_acc = (const u64*)(ws + L.inst_acc);
-    F.inst_race = (const uint32_t*)(ws + L.inst_race);
-    F.inst_benign = (const uint32_t*)(ws + L.inst_benign);
-    F.inst_intervals = (const uint32_t*)(ws + L.inst_int);
-    F.inst_flags = (const uint32_t*)(ws + L.inst_flags);
-    F.inst_fault = (const u64*)(ws + L.inst_fault);
-    F.out = (rc_summary_dev*)d_summaries;
-    HIP_TRY(launch_finalize(F, st));
+  ctx->pending.push_back(Pending{(u64*)d_n_records, cap, (uint32_t*)((char*)d_ws + C.L.counters + CNT_STATUS * 8)});
+  return RC_OK;
+}
+
+rc_status rc_batch_check(rc_ctx* ctx, rc_prog* const* progs, const uint64_t* seeds, uint32_t n, void* d_ws,
+                         size_t ws_bytes, rc_record* d_records, uint64_t cap, uint64_t* d_n_records,
+                         rc_summary* d_summaries) {
+  if (!ctx || !d_ws || !d_n_records || !d_summaries || (n && (!progs || !seeds)))
+    return fail(RC_E_INVAL, "NULL argument");
+  if (cap > 0 && !d_records) return fail(RC_E_INVAL, "d_records is NULL with cap > 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (n == 0) {
+    HIP_TRY(launch_fill_u64((u64*)d_n_records, 1, 0ull, ctx->stream));
+    return RC_OK;
   }
-  ctx->pending.push_back(Pending{(u64*)d_n_records, cap, (uint32_t*)(cnt + CNT_STATUS)});
+  Call C;
+  std::map<rc_prog*, uint32_t> index;
+  C.inst_prog.resize(n);
+  C.inst_seed.assign(seeds, seeds + n);
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!progs[i]) return fail(RC_E_INVAL, "programs[%u] is NULL", i);
+    if (progs[i]->ctx != ctx) return fail(RC_E_INVAL, "programs[%u] belongs to another context", i);
+    rc_status s = add_program(C, progs[i], index, &C.inst_prog[i]);
+    if (s) return s;
+  }
+  rc_status s = run_call(ctx, C, (char*)d_ws, ws_bytes, d_records, cap, (u64*)d_n_records, d_summaries, 1, nullptr);
+  if (s) return s;
+  ctx->pending.push_back(Pending{(u64*)d_n_records, cap, (uint32_t*)((char*)d_ws + C.L.counters + CNT_STATUS * 8)});
   return RC_OK;
 }
 
@@ -694,6 +932,8 @@ rc_status rc_sync(rc_ctx* ctx) {
   if (!ctx) return fail(RC_E_INVAL, "ctx is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
   hipError_t e = hipStreamSynchronize(ctx->stream);
+  for (hipGraphExec_t g : ctx->graphs_to_free) (void)hipGraphExecDestroy(g);
+  ctx->graphs_to_free.clear();
   if (e != hipSuccess) {
     ctx->pending.clear();
     return fail(RC_E_HIP, "stream synchronize: %s", hipGetErrorString(e));
@@ -731,21 +971,14 @@ rc_status rc_read_final(rc_prog* p, uint64_t seed, uint32_t array_id, int32_t* d
   rc_status s = check_ready(p);
   if (s) return s;
   rc_ctx* ctx = p->ctx;
-  hipStream_t st = ctx->stream;
   HIP_TRY(hipSetDevice(ctx->device));
-  Layout L;
-  std::string why;
-  if (!make_layout(p, 1, &L, &why)) return fail(RC_E_LIMIT, "%s", why.c_str());
-  if (L.total > ws_bytes) return fail(RC_E_INVAL, "workspace too small (%zu < %zu)", ws_bytes, L.total);
-  char* ws = (char*)d_ws;
-  s = prepare_workspace(p, ws, L);
+  Call C;
+  C.progs.push_back(p);
+  C.inst_prog.assign(1, 0);
+  C.inst_seed.assign(1, seed);
+  uint32_t epoch = 1;
+  s = run_call(ctx, C, (char*)d_ws, ws_bytes, nullptr, 0, nullptr, nullptr, 0, &epoch);
   if (s) return s;
-  s = upload_tables(p, st, nullptr);
-  if (s) return s;
-  s = reset_pass(p, L, ws, st);
-  if (s) return s;
-  InterpParams P = interp_params(p, L, ws, seed, 0, 1, 0);
-  HIP_TRY(launch_interp(P, lds_bytes(p), st));
   const ArrayDesc& A = p->arrays[array_id];
   FinalMemParams M;
   memset(&M, 0, sizeof M);
@@ -756,14 +989,14 @@ rc_status rc_read_final(rc_prog* p, uint64_t seed, uint32_t array_id, int32_t* d
   M.array_id = array_id;
   M.bind = A.bind;
   M.rw = A.kind == AK_GLOBAL_RW ? 1u : 0u;
+  M.epoch = epoch;
   M.lo = A.lo;
   M.hi = A.hi;
   M.seed = seed;
   M.dptr = A.dptr;
-  M.overlay = (const u64*)(ws + L.overlay);
-  M.epoch_used = (const uint32_t*)(ws + L.epoch_used);
+  M.overlay = (const u64*)((char*)d_ws + C.L.overlay);
   M.out = d_out;
-  HIP_TRY(launch_final_merge(M, st));
+  HIP_TRY(launch_final_merge(M, ctx->stream));
   return RC_OK;
 }
 

@@ -24,9 +24,10 @@ struct SegParams {
   const unsigned long long* vals;   // payloads in the same order
   const unsigned long long* n_ptr;  // number of log entries
   uint32_t bc, bg, bk, bs;          // key field widths; bs = scope bits of record keys
-  uint32_t G, W, NI, n_arrays, n_global, inst_offset;
-  const uint32_t* cellbase;         // per array, 0xFFFFFFFF when not logged
-  const uint32_t* size;
+  const ProgDesc* progs;
+  const SlotDesc* slots;
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_index;
   rc_record_out out;
 };
 
@@ -34,17 +35,21 @@ struct GatherParams {
   const rc_record_dev* staging;
   const uint32_t* idx;              // sorted order of staged records
   const unsigned long long* n_ptr;  // staged records
-  unsigned long long* out_base;     // records written by earlier passes (caller's counter)
+  unsigned long long* out_base;     // records written by earlier chunks (caller's counter)
   rc_record_dev* out;
   unsigned long long cap;
-  uint32_t inst_offset;
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_index;
   uint32_t* inst_flags;
   uint32_t* inst_race;
   uint32_t* inst_benign;
 };
 
 struct FinalParams {
-  uint32_t n_slots, inst_offset, W, pad;
+  const ProgDesc* progs;
+  const SlotDesc* slots;
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_index;
   const unsigned long long* inst_acc;
   const uint32_t* inst_race;
   const uint32_t* inst_benign;
@@ -52,35 +57,60 @@ struct FinalParams {
   const uint32_t* inst_flags;
   const unsigned long long* inst_fault;
   rc_summary_dev* out;
+  uint32_t max_slots, pad;
+};
+
+struct SetupParams {
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_index;
+  unsigned long long* counters;     // 8 words
+  uint32_t* queue;                  // [N_WCLASS]
+  unsigned long long* inst_acc;
+  unsigned long long* inst_fault;
+  uint32_t* inst_intervals;
+  uint32_t* inst_race;
+  uint32_t* inst_benign;
+  uint32_t* inst_flags;
+  unsigned long long* overlay;
+  unsigned long long overlay_cells;
+  uint32_t max_slots, pad;
 };
 
 struct FinalMemParams {
-  uint32_t size, G, overlay_cells, offset, array_id, bind, rw, pad;
+  uint32_t size, G, overlay_cells, offset, array_id, bind, rw, epoch;
   int64_t lo, hi;
   uint64_t seed;
   const int32_t* dptr;
-  const unsigned long long* overlay;   // overlays of slot 0, groups 0..G-1
-  const uint32_t* epoch_used;          // [G]
+  const unsigned long long* overlay;   // overlays of the instance, groups 0..G-1
   int32_t* out;
 };
 
-hipError_t launch_interp(const InterpParams& P, size_t lds_bytes, hipStream_t st);
+hipError_t launch_interp(const PassParams& P, uint32_t blocks, uint32_t threads, size_t lds_bytes, hipStream_t st);
+int interp_occupancy(uint32_t threads, size_t lds_bytes);
+hipError_t launch_setup(const SetupParams& P, hipStream_t st);
+hipError_t launch_ws_validate(unsigned long long* header, unsigned long long magic, unsigned long long ctx_id,
+                              unsigned long long gen, unsigned long long* pool, unsigned long long pool_cells,
+                              uint32_t* dirty, hipStream_t st);
+hipError_t launch_advance(unsigned long long* out_base, const unsigned long long* rec_n, uint32_t* chunk_index,
+                          hipStream_t st);
 size_t scan_tmp_words(unsigned long long m);
 size_t sort_hist_words(unsigned long long cap);
-size_t sort_log_hist_words(unsigned long long n_seg, unsigned long long R, unsigned long long cap);
-// Sort the access log: regions of seg_R entries (seg_count[r] used in region
-// r) become one dense array sorted by the low nbits of the key; *n_ptr (zero
-// on entry) receives the number of entries.
+size_t sort_log_hist_words(unsigned long long n_regions, unsigned long long cap);
+// Sort the access log: region r (seg_count[r] entries from seg_base[r])
+// becomes part of one dense array sorted by the low nbits of the key; *n_ptr
+// (zero on entry) receives the number of entries; tiles holds n_regions + 1
+// words of scratch.
 hipError_t sort_log(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
                     const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
-                    const uint32_t* seg_count, unsigned long long n_seg, unsigned long long seg_R, uint32_t* hist,
-                    hipStream_t st, int* in_second);
+                    const uint32_t* seg_count, const unsigned long long* seg_base, uint32_t* tiles,
+                    unsigned long long n_regions, uint32_t* hist, hipStream_t st, int* in_second);
 hipError_t sort_pairs_u32(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1,
                           const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
                           uint32_t* hist, hipStream_t st, int* in_second);
 hipError_t launch_seg_check(const SegParams& S, unsigned long long cap, hipStream_t st);
 hipError_t launch_gather(const GatherParams& G, unsigned long long cap, hipStream_t st);
 hipError_t launch_finalize(const FinalParams& F, hipStream_t st);
+hipError_t launch_region_tiles(const uint32_t* counts, uint32_t* tiles, unsigned long long n_regions, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStream_t st);
 hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st);

@@ -249,15 +249,15 @@ struct PendingRec {
 
 // canonical sort key fields of a record
 struct RecKey {
-  uint32_t bs, bc, G, NI, inst_offset;
+  uint32_t bs, bc, G, NI;
 };
 
 __device__ __forceinline__ void store_record(const rc_record_out& R, const RecKey& K, u64 pos, uint32_t slot,
-                                             const PendingRec& p, bool inter) {
+                                             uint32_t instance, const PendingRec& p, bool inter) {
   if (pos >= R.rec_cap) { atomicOr(R.status_word, 2u); return; }
   const uint32_t NONE = 0xFFFFFFFFu;
   rc_record_dev r;
-  r.instance = K.inst_offset + slot;
+  r.instance = instance;
   r.gid = inter ? NONE : p.gid;
   r.interval = inter ? 0u : p.interval;
   r.array_label = p.aid | (p.label << 16);
@@ -284,51 +284,54 @@ __device__ __forceinline__ u64 wave_reserve(unsigned long long* counter, uint32_
 
 extern __shared__ __attribute__((aligned(16))) unsigned char rc_smem[];
 
-__global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
+// Everything one work item (an instance's work-group) needs; uniform.
+struct ItemView {
+  const uint32_t* code;
+  const ArrayDesc* arrays;
+  const ScalarDesc* scalars;
+  uint32_t n_arrays, n_global, n_scalars, nregs, G, W, nwaves, lds_local_cells;
+  uint32_t lds_log_cap, overlay_cells, NI, bc, bg, bk, bs, do_log;
+  u64 wg_log_cap;
+  u64* log_keys;
+  u64* log_vals;
+  uint32_t* status_word;
+  const rc_record_out* rec;
+  u64* inst_acc;
+  uint32_t* inst_intervals;
+  u64* inst_fault;
+  uint32_t* wg_count;
+  u64* wg_base;
+};
+
+// Run one work-group of one instance, lockstep, on the calling workgroup.
+// `slot` indexes the chunk's per-instance counters, `instance` the call's.
+__device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t slot, uint32_t instance,
+                                         uint32_t gid, uint64_t seed, u64 log_base, u64* ovl,
+                                         uint32_t epoch_base, uint32_t wg_index) {
   const uint32_t tl = threadIdx.x;
   const uint32_t WP = P.nwaves * 64u;
   const uint32_t wave = tl >> 6, lane = tl & 63u;
-  const uint32_t slot = blockIdx.x / P.G;
-  const uint32_t gid = blockIdx.x - slot * P.G;
-  const uint64_t seed = P.seed0 + (uint64_t)(P.inst_offset + slot);
   const bool real = tl < P.W;
+  const uint32_t tr = tl < WP ? tl : WP - 1u;   // waves past the group read a real lane's registers
 
-  // dynamic LDS: local array cells (u64), the interval log (T keys, T
-  // payload words, T values), registers, control block
-  u64* locc = reinterpret_cast<u64*>(rc_smem);
+  // dynamic LDS after the control block: local array cells (u64), the
+  // interval log (T keys, T payload words, T values), registers
+  u64* locc = reinterpret_cast<u64*>(reinterpret_cast<unsigned char*>(ctl) + ((sizeof(Ctl) + 15) & ~(size_t)15));
   u64* lkey = locc + P.lds_local_cells;
   uint32_t* lmeta = reinterpret_cast<uint32_t*>(lkey + P.lds_log_cap);
   int32_t* lval = reinterpret_cast<int32_t*>(lmeta + P.lds_log_cap);
   int32_t* regs = lval + P.lds_log_cap;
-  Ctl* ctl = reinterpret_cast<Ctl*>(regs + (size_t)P.nregs * WP);
 
-  for (uint32_t i = tl; i < P.lds_local_cells; i += WP) locc[i] = 0ull;
-  for (uint32_t i = tl; i < P.nregs * WP; i += WP) regs[i] = 0;
+  for (uint32_t i = tl; i < P.lds_local_cells; i += blockDim.x) locc[i] = 0ull;
+  for (uint32_t i = tl; i < P.nregs * WP; i += blockDim.x) regs[i] = 0;
   if (tl == 0) ctl->fault = ~0ull;
   if (tl < P.n_scalars) {
     const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
     ctl->scal[tl] = S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
   }
-  // overlay epochs: versions written by earlier runs on this overlay are older
-  const size_t ovl_index = (size_t)slot * P.G + gid;
-  u64* ovl = P.overlay + ovl_index * (size_t)P.overlay_cells;
-  if (tl == 0) {
-    uint32_t e = P.epochs[ovl_index];
-    if (e == 0u || e + P.max_store_seq + 2u >= (1u << 22)) e = 0u;   // fresh or wrapping
-    ctl->epoch_base = e;
-  }
   __syncthreads();
-  uint32_t epoch_base = uni(ctl->epoch_base);
-  if (epoch_base == 0u) {
-    for (size_t i = tl; i < P.overlay_cells; i += WP) ovl[i] = 0ull;
-    __threadfence_block();
-    __syncthreads();
-    epoch_base = 1u;
-  }
-  if (tl == 0) P.epoch_used[ovl_index] = epoch_base;
 
   const u64 key_slot = (u64)slot << (P.bc + P.bg + P.bk);
-  const u64 log_base = (u64)ovl_index * P.wg_log_cap;
   u64 log_used = 0;
   uint32_t lds_used = 0;       // entries of the current interval in the LDS log
   bool lds_spilled = false;    // the current interval moved to the global log
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
 
   auto fetch = [&](bool imm, uint32_t w) -> int32_t {
     if (imm) return (int32_t)w;
-    if (w < MAX_REGS) return regs[w * WP + tl];
+    if (w < MAX_REGS) return regs[w * WP + tr];
     switch (w) {
       case SEL_LID: return (int32_t)tl;
       case SEL_TID: return (int32_t)(gid * P.W + tl);
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
       }
     }
     const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
-    const RecKey K = {P.bs, P.bc, P.G, P.NI, P.inst_offset};
+    const RecKey K = {P.bs, P.bc, P.G, P.NI};
     for (uint32_t b0 = 0; b0 < n; b0 += WP) {
       const uint32_t i = b0 + tl;
       bool has = false;
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
       const u64 m = __ballot(has);
       if (m != 0ull) {
         const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
-        if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, pr, false);
+        if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, instance, pr, false);
       }
     }
     __syncthreads();
@@ -641,9 +644,9 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   if (P.do_log) close_interval();
   // the last interval (complete, or cut by a fault) is closed
   if (tl == 0) {
-    P.wg_count[ovl_index] = (uint32_t)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
+    P.wg_count[wg_index] = (uint32_t)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
+    P.wg_base[wg_index] = log_base;
     atomicAdd(&P.inst_intervals[slot], interval + 1u);
-    P.epochs[ovl_index] = epoch_base + store_seq + 1u;
     if (faulted) {
       const u64 f = ctl->fault;
       const uint32_t lid = (uint32_t)(f >> 17) & 1023u, fpc = (uint32_t)(f >> 5) & 4095u, code = (uint32_t)f & 7u;
@@ -655,6 +658,41 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(InterpParams P) {
   u64 acc = n_acc;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
   if (lane == 0 && acc) atomicAdd(&P.inst_acc[slot], acc);
+  __syncthreads();
+}
+
+// Persistent interpreter: the workgroups of one width class take work items
+// (an instance's work-group) from the chunk's queue until it is empty.  The
+// queue is ordered longest-first, so stealing in order balances the tail.
+__global__ __launch_bounds__(1024) void rc_interp_kernel(PassParams PP) {
+  Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
+  const uint32_t ci = const_load<uint32_t>(PP.chunk_index, 0);
+  const ChunkDesc C = const_load<ChunkDesc>(PP.chunks, ci);
+  const uint32_t i0 = C.item0[PP.wclass], i1 = C.item0[PP.wclass + 1];
+  if (i0 == i1) return;
+  for (;;) {
+    if (threadIdx.x == 0) ctl->item = i0 + atomicAdd(&PP.queue[PP.wclass], 1u);
+    __syncthreads();
+    const uint32_t item = uni(ctl->item);
+    __syncthreads();
+    if (item >= i1) break;
+    const uint32_t instance = const_load<uint32_t>(PP.items, 2u * item);
+    const uint32_t gid = const_load<uint32_t>(PP.items, 2u * item + 1u);
+    const SlotDesc S = const_load<SlotDesc>(PP.slots, instance);
+    const ProgDesc D = const_load<ProgDesc>(PP.progs, S.prog);
+    ItemView P;
+    P.code = D.code; P.arrays = D.arrays; P.scalars = D.scalars;
+    P.n_arrays = D.n_arrays; P.n_global = D.n_global; P.n_scalars = D.n_scalars; P.nregs = D.nregs;
+    P.G = D.G; P.W = D.W; P.nwaves = D.nwaves; P.lds_local_cells = D.lds_local_cells;
+    P.lds_log_cap = D.lds_log_cap; P.overlay_cells = D.overlay_cells; P.NI = D.NI;
+    P.bc = PP.bc; P.bg = PP.bg; P.bk = PP.bk; P.bs = PP.bs; P.do_log = PP.do_log;
+    P.wg_log_cap = D.wg_log_cap;
+    P.log_keys = PP.log_keys; P.log_vals = PP.log_vals; P.status_word = PP.status_word; P.rec = PP.rec;
+    P.inst_acc = PP.inst_acc; P.inst_intervals = PP.inst_intervals; P.inst_fault = PP.inst_fault;
+    P.wg_count = PP.wg_count; P.wg_base = PP.wg_base;
+    run_item(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,
+             PP.overlay + S.ovl_base + (u64)gid * D.overlay_cells, C.epoch, S.wg_base + gid);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -709,29 +747,45 @@ __global__ __launch_bounds__(256) void scan_block_kernel(uint32_t* data, uint64_
 // ---------------------------------------------------------------------------
 constexpr uint32_t RS_THREADS = 256, RS_ROUNDS = 16, RS_TILE = RS_THREADS * RS_ROUNDS;
 
-// Input of one radix pass: dense (n on the device), or segmented (region r of
-// seg_R entries holds seg_count[r] entries; blocks walk the regions tile by
-// tile, so the pass also compacts the regions into a dense output).
+// Input of one radix pass: dense (n on the device), or segmented: region r
+// starts at entry seg_base[r] and holds seg_count[r] entries; tiles[r] is the
+// exclusive prefix of the regions' tile counts (n_regions + 1 words), so each
+// block finds its region by binary search and the pass also compacts the
+// regions into a dense output.
 struct RsIn {
   const u64* n_ptr;
   const uint32_t* seg_count;
-  u64 seg_R;
-  uint32_t tiles_per_seg, pad;
+  const u64* seg_base;
+  const uint32_t* tiles;
+  uint32_t n_regions, pad;
 };
 
 __device__ __forceinline__ void rs_tile(const RsIn& in, uint32_t b, u64* start, uint32_t* count) {
-  if (in.seg_R == 0) {
+  if (in.seg_count == nullptr) {
     const u64 n = *in.n_ptr;
     const u64 t0 = (u64)b * RS_TILE;
     *start = t0;
     *count = t0 >= n ? 0u : (uint32_t)(n - t0 < RS_TILE ? n - t0 : RS_TILE);
-  } else {
-    const uint32_t r = b / in.tiles_per_seg, t = b - r * in.tiles_per_seg;
-    const u64 used = in.seg_count[r];
-    const u64 t0 = (u64)t * RS_TILE;
-    *start = (u64)r * in.seg_R + t0;
-    *count = t0 >= used ? 0u : (uint32_t)(used - t0 < RS_TILE ? used - t0 : RS_TILE);
+    return;
   }
+  *start = 0;
+  *count = 0;
+  if (b >= in.tiles[in.n_regions]) return;
+  uint32_t lo = 0, hi = in.n_regions;   // tiles[lo] <= b < tiles[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (in.tiles[mid] <= b) lo = mid; else hi = mid;
+  }
+  const u64 t0 = (u64)(b - in.tiles[lo]) * RS_TILE;
+  const u64 used = in.seg_count[lo];
+  *start = in.seg_base[lo] + t0;
+  *count = t0 >= used ? 0u : (uint32_t)(used - t0 < RS_TILE ? used - t0 : RS_TILE);
+}
+
+__global__ __launch_bounds__(256) void region_tiles_kernel(const uint32_t* counts, uint32_t* tiles, u64 n) {
+  const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) tiles[r] = (counts[r] + RS_TILE - 1) / RS_TILE;
+  else if (r == n) tiles[r] = 0;
 }
 
 __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, uint32_t shift,
@@ -810,7 +864,8 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
   const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   bool has_intra = false, has_inter = false;
-  uint32_t slot = 0;
+  uint32_t slot = 0, instance = 0;
+  RecKey K = {S.bs, S.bc, 1u, 1u};
   PendingRec pa, pb;
   if (i < n) {
     const u64 k = S.keys[i];
@@ -824,25 +879,30 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
       slot = (uint32_t)(k >> (low + S.bc));
       const uint32_t gid = (uint32_t)(k >> S.bk) & gmask;
       const uint32_t interval = (uint32_t)k & imask;
+      const ChunkDesc C = S.chunks[*S.chunk_index];
+      instance = C.slot0 + slot;
+      const ProgDesc D = S.progs[S.slots[instance].prog];
+      K.G = D.G;
+      K.NI = D.NI;
       uint32_t aid = 0;
-      for (uint32_t a = 0; a < S.n_arrays; ++a) {
-        const uint32_t cb = S.cellbase[a];
-        if (cb != 0xFFFFFFFFu && cellkey >= cb && cellkey - cb < S.size[a]) aid = a;
+      for (uint32_t a = 0; a < D.n_arrays; ++a) {
+        const uint32_t cb = D.cellbase[a];
+        if (cb != 0xFFFFFFFFu && cellkey >= cb && cellkey - cb < D.size[a]) aid = a;
       }
-      const uint32_t cell = cellkey - S.cellbase[aid];
+      const uint32_t cell = cellkey - D.cellbase[aid];
       u64 e = i + 1;
       while (e < n && S.keys[e] == k) ++e;
       if (e - i >= 2) {
         const u64* vals = S.vals;
         has_intra = intra_check([vals](u64 j) { return vals[j]; }, i, e, &pa.label, &pa.rw, &pa.ww);
         pa.gid = gid; pa.interval = interval; pa.aid = aid; pa.cell = cell; pa.cellkey = cellkey;
-        pa.lidbase = gid * S.W;
+        pa.lidbase = gid * D.W;
       }
-      if (seg_head && S.G > 1 && aid < S.n_global) {
+      if (seg_head && D.G > 1 && aid < D.n_global) {
         u64 f = e;
         while (f < n && (S.keys[f] >> low) == (k >> low)) ++f;
         if (f - i >= 2) {
-          has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, S.W, &pb.label, &pb.rw, &pb.ww);
+          has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, D.W, &pb.label, &pb.rw, &pb.ww);
           pb.gid = gid; pb.interval = 0; pb.aid = aid; pb.cell = cell; pb.cellkey = cellkey;
           pb.lidbase = 0;
         }
@@ -854,9 +914,8 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
   if (c1 + c2 == 0) return;
   const u64 base = wave_reserve(S.out.rec_count, c1 + c2, lane);
   const u64 below = (1ull << lane) - 1ull;
-  const RecKey K = {S.bs, S.bc, S.G, S.NI, S.inst_offset};
-  if (has_intra) store_record(S.out, K, base + (u64)__popcll(m1 & below), slot, pa, false);
-  if (has_inter) store_record(S.out, K, base + c1 + (u64)__popcll(m2 & below), slot, pb, true);
+  if (has_intra) store_record(S.out, K, base + (u64)__popcll(m1 & below), slot, instance, pa, false);
+  if (has_inter) store_record(S.out, K, base + c1 + (u64)__popcll(m2 & below), slot, instance, pb, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,7 +931,7 @@ __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
   if (valid) {
     const rc_record_dev r = Gp.staging[Gp.idx[p]];
     const u64 out = *Gp.out_base + p;
-    slot = r.instance - Gp.inst_offset;
+    slot = r.instance - Gp.chunks[*Gp.chunk_index].slot0;
     const uint32_t label = r.array_label >> 16;
     race = (label & 3u) != 0u;
     benign = label == 4u;
@@ -894,7 +953,6 @@ __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
   }
 }
 
-__global__ void advance_base_kernel(u64* out_base, const u64* n_ptr) { *out_base += *n_ptr; }
 
 // entries past a buffer's capacity were dropped (and flagged): later kernels
 // see at most `cap`
@@ -906,8 +964,10 @@ __global__ void clamp_count_kernel(u64* n_ptr, u64 cap, uint32_t* status, uint32
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinalParams F) {
+  const ChunkDesc C = F.chunks[*F.chunk_index];
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= F.n_slots) return;
+  if (s >= C.n_slots) return;
+  const uint32_t W = F.progs[F.slots[C.slot0 + s].prog].W;
   rc_summary_dev o;
   o.n_accesses = F.inst_acc[s];
   o.n_race_cells = F.inst_race[s];
@@ -922,10 +982,55 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams F) {
     o.status = (int32_t)(f & 7u);
     o.fault_gid = g;
     o.fault_pc = fpc;
-    o.fault_tid = g * F.W + lid;
+    o.fault_tid = g * W + lid;
   }
   o.flags = F.inst_flags[s];
-  F.out[F.inst_offset + s] = o;
+  F.out[C.slot0 + s] = o;
+}
+
+// Start of a chunk: clear its counters (and the overlay pool when the
+// overlay versions wrap).  One block per 256 instances; block 0 also clears
+// the scalar counters.
+__global__ __launch_bounds__(256) void chunk_setup_kernel(SetupParams P) {
+  const ChunkDesc C = P.chunks[*P.chunk_index];
+  const uint32_t t = threadIdx.x;
+  if (blockIdx.x == 0 && t < 8) P.counters[t] = 0ull;       // log, records, queue words
+  if (blockIdx.x == 0 && t < N_WCLASS) P.queue[t] = 0u;
+  for (uint32_t s = blockIdx.x * blockDim.x + t; s < P.max_slots; s += gridDim.x * blockDim.x) {
+    P.inst_acc[s] = 0ull;
+    P.inst_fault[s] = ~0ull;
+    P.inst_intervals[s] = 0u;
+    P.inst_race[s] = 0u;
+    P.inst_benign[s] = 0u;
+    P.inst_flags[s] = 0u;
+  }
+  if (C.clear_overlay)
+    for (u64 c = (u64)blockIdx.x * blockDim.x + t; c < P.overlay_cells; c += (u64)gridDim.x * blockDim.x)
+      P.overlay[c] = 0ull;
+}
+
+// Start of a call: the workspace header (magic, context, generation, pool
+// size) tells whether the overlay pool still holds only versioned cells from
+// this context's earlier calls; if not (a new or reused buffer), the pool is
+// cleared before anything reads it.
+__global__ void ws_validate_kernel(u64* header, u64 magic, u64 ctx_id, u64 gen, u64 pool_cells, uint32_t* dirty) {
+  const bool ok = header[0] == magic && header[1] == ctx_id && header[2] == gen && header[3] >= pool_cells;
+  *dirty = ok ? 0u : 1u;
+  header[0] = magic;
+  header[1] = ctx_id;
+  header[2] = gen + 1ull;
+  header[3] = pool_cells;   // bytes past this pool will hold other data
+}
+
+__global__ __launch_bounds__(256) void pool_clear_kernel(u64* pool, u64 cells, const uint32_t* dirty) {
+  if (*dirty == 0u) return;
+  for (u64 c = (u64)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (u64)gridDim.x * blockDim.x) pool[c] = 0ull;
+}
+
+// End of a chunk: advance the output base and the chunk index.
+__global__ void chunk_advance_kernel(u64* out_base, const u64* rec_n, uint32_t* chunk_index) {
+  *out_base += *rec_n;
+  *chunk_index += 1u;
 }
 
 __global__ __launch_bounds__(256) void fill_u64_kernel(u64* p, u64 n, u64 v) {
@@ -943,7 +1048,7 @@ __global__ __launch_bounds__(256) void final_merge_kernel(FinalMemParams M) {
   if (M.rw) {
     for (uint32_t g = 0; g < M.G; ++g) {
       const u64 w = M.overlay[(size_t)g * M.overlay_cells + M.offset + c];
-      if ((uint32_t)(w >> 42) >= M.epoch_used[g]) v = (int32_t)(uint32_t)w;
+      if ((uint32_t)(w >> 42) >= M.epoch) v = (int32_t)(uint32_t)w;
     }
   }
   M.out[c] = v;
@@ -954,14 +1059,53 @@ __global__ __launch_bounds__(256) void final_merge_kernel(FinalMemParams M) {
 // ---------------------------------------------------------------------------
 static inline uint32_t blocks_for(u64 n, uint32_t per) { return (uint32_t)((n + per - 1) / per); }
 
-hipError_t launch_interp(const InterpParams& P, size_t lds_bytes, hipStream_t st) {
+static void set_lds_attr() {
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rc_interp_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL(rc_interp_kernel, dim3(P.n_slots * P.G), dim3(P.nwaves * 64), lds_bytes, st, P);
+}
+
+hipError_t launch_interp(const PassParams& P, uint32_t blocks, uint32_t threads, size_t lds_bytes, hipStream_t st) {
+  set_lds_attr();
+  hipLaunchKernelGGL(rc_interp_kernel, dim3(blocks), dim3(threads), lds_bytes, st, P);
+  return hipGetLastError();
+}
+
+int interp_occupancy(uint32_t threads, size_t lds_bytes) {
+  set_lds_attr();
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rc_interp_kernel, (int)threads, lds_bytes) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_setup(const SetupParams& P, hipStream_t st) {
+  uint32_t nb = blocks_for(std::max<u64>(P.max_slots, 1), 256);
+  if (nb < 1024) nb = 1024;
+  hipLaunchKernelGGL(chunk_setup_kernel, dim3(nb), dim3(256), 0, st, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_ws_validate(u64* header, u64 magic, u64 ctx_id, u64 gen, u64* pool, u64 pool_cells,
+                              uint32_t* dirty, hipStream_t st) {
+  hipLaunchKernelGGL(ws_validate_kernel, dim3(1), dim3(1), 0, st, header, magic, ctx_id, gen, pool_cells, dirty);
+  uint32_t nb = blocks_for(std::max<u64>(pool_cells, 1), 256);
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(pool_clear_kernel, dim3(nb), dim3(256), 0, st, pool, pool_cells, (const uint32_t*)dirty);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(u64* out_base, const u64* rec_n, uint32_t* chunk_index, hipStream_t st) {
+  hipLaunchKernelGGL(chunk_advance_kernel, dim3(1), dim3(1), 0, st, out_base, rec_n, chunk_index);
+  return hipGetLastError();
+}
+
+hipError_t launch_region_tiles(const uint32_t* counts, uint32_t* tiles, u64 n_regions, hipStream_t st) {
+  hipLaunchKernelGGL(region_tiles_kernel, dim3(blocks_for(n_regions + 1, 256)), dim3(256), 0, st, counts, tiles,
+                     n_regions);
   return hipGetLastError();
 }
 
@@ -993,35 +1137,35 @@ size_t sort_hist_words(u64 cap) {
   return m + scan_tmp_words(m);
 }
 
-// number of tiles the first (segmented) pass launches for n_seg regions of R entries
-static u64 seg_blocks(u64 n_seg, u64 R) { return n_seg * ((R + RS_TILE - 1) / RS_TILE); }
+// upper bound of the tiles the first (segmented) pass walks
+static u64 seg_blocks(u64 n_regions, u64 cap) { return (cap + RS_TILE - 1) / RS_TILE + n_regions; }
 
-size_t sort_log_hist_words(u64 n_seg, u64 R, u64 cap) {
-  const u64 nb = std::max<u64>(seg_blocks(n_seg, R), (cap + RS_TILE - 1) / RS_TILE);
+size_t sort_log_hist_words(u64 n_regions, u64 cap) {
+  const u64 nb = std::max<u64>(seg_blocks(n_regions, cap), (cap + RS_TILE - 1) / RS_TILE);
   const u64 m = 256ull * (nb ? nb : 1);
-  return m + scan_tmp_words(m);
+  return m + scan_tmp_words(std::max<u64>(m, n_regions + 1));
 }
-
 
 template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
-                                  const uint32_t* seg_count, u64 n_seg, u64 seg_R, uint32_t* hist,
-                                  hipStream_t st, int* result_in_second) {
+                                  const uint32_t* seg_count, const u64* seg_base, const uint32_t* tiles,
+                                  u64 n_regions, uint32_t* hist, hipStream_t st, int* result_in_second) {
   u64 *ka = k0, *kb = k1;
   V *va = v0, *vb = v1;
   int passes = 0;
   // a segmented input always takes one pass, which also makes it dense
-  const uint32_t want = seg_R ? (nbits > 8 ? nbits : 8) : nbits;
+  const uint32_t want = seg_count ? (nbits > 8 ? nbits : 8) : nbits;
   for (uint32_t shift = 0; shift < want; shift += 8) {
     RsIn in;
     memset(&in, 0, sizeof in);
     in.n_ptr = n_ptr;
     u64 nbl;
-    if (passes == 0 && seg_R) {
+    if (passes == 0 && seg_count) {
       in.seg_count = seg_count;
-      in.seg_R = seg_R;
-      in.tiles_per_seg = (uint32_t)((seg_R + RS_TILE - 1) / RS_TILE);
-      nbl = seg_blocks(n_seg, seg_R);
+      in.seg_base = seg_base;
+      in.tiles = tiles;
+      in.n_regions = (uint32_t)n_regions;
+      nbl = seg_blocks(n_regions, cap);
     } else {
       nbl = blocks_for(cap ? cap : 1, RS_TILE);
     }
@@ -1041,15 +1185,21 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
 }
 
 hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
-                    const uint32_t* seg_count, u64 n_seg, u64 seg_R, uint32_t* hist, hipStream_t st,
-                    int* in_second) {
-  hipLaunchKernelGGL(sum_u32_kernel, dim3(n_seg > 65536 ? 1024 : (uint32_t)blocks_for(n_seg, 256)), dim3(256), 0,
-                     st, seg_count, n_seg, (u64*)n_ptr);
-  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, n_seg, seg_R, hist, st, in_second);
+                    const uint32_t* seg_count, const u64* seg_base, uint32_t* tiles, u64 n_regions,
+                    uint32_t* hist, hipStream_t st, int* in_second) {
+  // the number of entries, and the regions' tile prefix
+  hipLaunchKernelGGL(sum_u32_kernel, dim3(n_regions > 65536 ? 1024 : (uint32_t)blocks_for(n_regions, 256)),
+                     dim3(256), 0, st, seg_count, n_regions, (u64*)n_ptr);
+  hipLaunchKernelGGL(region_tiles_kernel, dim3(blocks_for(n_regions + 1, 256)), dim3(256), 0, st, seg_count,
+                     tiles, n_regions);
+  scan_excl(tiles, n_regions + 1, hist, st);
+  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, seg_base, tiles, n_regions, hist, st,
+                              in_second);
 }
 hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {
-  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, nullptr, 0, 0, hist, st, in_second);
+  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, nullptr, nullptr, nullptr, 0, hist, st,
+                                   in_second);
 }
 
 hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
@@ -1058,11 +1208,10 @@ hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
 }
 hipError_t launch_gather(const GatherParams& G, u64 cap, hipStream_t st) {
   hipLaunchKernelGGL(rec_gather_kernel, dim3(blocks_for(cap ? cap : 1, 256)), dim3(256), 0, st, G);
-  hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, st, G.out_base, G.n_ptr);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const FinalParams& F, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(F.n_slots, 256)), dim3(256), 0, st, F);
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(std::max<u64>(F.max_slots, 1), 256)), dim3(256), 0, st, F);
   return hipGetLastError();
 }
 hipError_t launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st) {

@@ -85,37 +85,61 @@ struct ScalarDesc {
   int64_t lo, hi;
 };
 
-// Parameters of one interpreter launch (passed by value).
-struct InterpParams {
-  const uint32_t* code;                      // 4 words per instruction
-  uint32_t n_arrays, n_global, n_scalars, nregs;
-  uint32_t G, W, nwaves, lds_local_cells;   // u64 cells of local arrays in LDS
-  uint32_t n_slots;                          // instances in this pass (grid = n_slots * G)
-  uint32_t overlay_cells;                    // u64 cells per (slot, group) overlay
-  uint32_t max_store_seq;                    // static bound of store statements per group run
-  uint32_t inst_offset;                      // first instance index of this pass
-  uint64_t seed0;
-  // log key layout: [instance : bi][cellkey : bc][gid : bg][interval : bk]
-  uint32_t bc, bg, bk, pad0;
-  const ArrayDesc* arrays;                   // device copy of the descriptor table
+// ---------------------------------------------------------------------------
+// A check call is a list of instances (program, seed).  It runs in chunks;
+// every chunk uses the same workspace layout, and all per-chunk parameters
+// live in device tables, so the kernel sequence of one chunk is the same for
+// every chunk (and is captured once as a HIP graph).
+// ---------------------------------------------------------------------------
+struct ProgDesc {                 // one program of the call
+  const uint32_t* code;           // 4 words per instruction
+  const ArrayDesc* arrays;
   const ScalarDesc* scalars;
-  // workspace pointers
-  uint32_t* epochs;         // [n_slots * G] next free epoch per overlay
-  uint32_t* epoch_used;     // [n_slots * G] epoch base used by the last run
-  unsigned long long* overlay;        // [n_slots * G * overlay_cells]
-  unsigned long long* log_keys;       // access log: one region of wg_log_cap entries per work-group
+  const uint32_t* cellbase;       // per array: first log cell key (0xFFFFFFFF: not logged)
+  const uint32_t* size;           // per array: cells
+  uint32_t n_arrays, n_global, n_scalars, nregs;
+  uint32_t G, W, nwaves, lds_local_cells;
+  uint32_t lds_log_cap, overlay_cells, NI, pad;
+  uint64_t wg_log_cap;            // log entries reserved per work-group
+};
+
+struct SlotDesc {                 // one instance of the call
+  uint64_t seed;
+  uint64_t log_base;              // first log entry of its group 0 (in the chunk's log)
+  uint64_t ovl_base;              // first overlay cell of its group 0 (in the chunk's pool)
+  uint32_t prog;                  // index into the call's program table
+  uint32_t wg_base;               // index of its group 0 among the chunk's work-groups
+};
+
+constexpr uint32_t N_WCLASS = 5;  // work-group widths up to 64, 128, 256, 512, 1024
+
+struct ChunkDesc {
+  uint32_t slot0, n_slots;        // instances [slot0, slot0 + n_slots) of the call
+  uint32_t n_wg, n_items;
+  uint32_t item0[N_WCLASS + 1];   // items of width class c: [item0[c], item0[c+1])
+  uint32_t epoch;                 // overlay version base of this chunk
+  uint32_t clear_overlay;         // versions wrapped: clear the pool first
+};
+
+// Parameters of the interpreter launches of a call (constant for the call).
+struct PassParams {
+  const ProgDesc* progs;
+  const SlotDesc* slots;
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_index;    // device: the chunk being processed
+  const uint32_t* items;          // (instance, gid) pairs, per chunk and class, longest first
+  uint32_t* queue;                // [N_WCLASS] work-stealing counters
+  uint32_t wclass, bc, bg, bk, bs, do_log;
+  unsigned long long* overlay;    // overlay pool of the chunk
+  unsigned long long* log_keys;   // access log (one region per work-group)
   unsigned long long* log_vals;
-  uint32_t* wg_count;                 // [n_slots * G] entries written in each region
-  uint64_t wg_log_cap;
-  unsigned long long* inst_acc;       // [n_slots] accesses
-  unsigned int* inst_intervals;       // [n_slots]
-  unsigned long long* inst_fault;     // [n_slots] min (gid, pc, lid, code) key
-  unsigned int* status_word;          // bit 0: internal log overflow
-  int do_log;                          // 0: run only (final memory)
-  // interval checks inside the interpreter (LDS path)
-  uint32_t lds_log_cap;                // T entries (power of two), 0: no LDS path
-  uint32_t bs, NI;                     // record key: scope bits, intervals per group
-  struct rc_record_out* rec;           // where records go (device struct)
+  uint32_t* wg_count;             // [work-group] log entries written
+  unsigned long long* wg_base;    // [work-group] first entry of its region
+  unsigned long long* inst_acc;   // [chunk slot] accesses
+  uint32_t* inst_intervals;       // [chunk slot]
+  unsigned long long* inst_fault; // [chunk slot] min (gid, pc, lid, code) key
+  uint32_t* status_word;          // bit 0: internal log overflow
+  struct rc_record_out* rec;      // record staging
 };
 
 // Record output shared by the interval checks (interpreter and global pass).
@@ -134,7 +158,7 @@ struct Ctl {
   uint32_t red[2][MAX_WAVES];           // per-wave reduction words, double-buffered
   int32_t scal[MAX_SCALARS];
   uint32_t loopctr[MAX_WAVES][MAX_NEST];
-  uint32_t epoch_base;
+  uint32_t item;                        // work item taken by the group
   uint32_t pad;
 };
 

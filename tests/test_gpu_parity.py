@@ -245,3 +245,99 @@ def test_lds_log_size_invariance(case, entries):
     g = U.gpu_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 3, lds_log_entries=entries)
     o = U.oracle_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 3)
     U.assert_same(g, o, f"{case} lds_log_entries={entries}")
+
+
+# ---------------------------------------------------------------------------
+# batches of different programs in one call; chunked calls replay a graph
+# ---------------------------------------------------------------------------
+def _batch(programs_and_seeds, ws_bytes=None, profile=False):
+    import torch
+    ctx = U.ctx()
+    progs = {}
+    plist, seeds = [], []
+    for w, seed in programs_and_seeds:
+        if w.name not in progs:
+            p = B.Program(ctx, w.src)
+            p.set_ndrange(w.G, w.W)
+            p.bind(w.arrays, w.scalars)
+            progs[w.name] = p
+        plist.append(progs[w.name])
+        seeds.append(seed)
+    n = len(plist)
+    need = max(p.workspace_size(1) for p in progs.values()) * 2 if ws_bytes is None else ws_bytes
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    cap = 1 << 20
+    rec = torch.empty(cap * B.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    summ = torch.empty(n * B.SUMMARY_BYTES, dtype=torch.uint8, device="cuda")
+    if profile:
+        ctx.profile(True)
+    ctx.batch_check_async(plist, seeds, ws, rec, cnt, summ)
+    ctx.sync()
+    if profile:
+        ctx.profile_read()
+        ctx.profile(False)
+    k = int(cnt.item())
+    return B.records_to_numpy(rec, k), B.summaries_to_numpy(summ, n)
+
+
+def _oracle_batch(programs_and_seeds):
+    recs, summs = [], []
+    cache = {}
+    for i, (w, seed) in enumerate(programs_and_seeds):
+        if w.name not in cache:
+            cache[w.name] = O.Program(w.src)
+        r = cache[w.name].run(w.G, w.W, arrays=w.arrays, scalars=w.scalars, seed=seed, instance=i)
+        recs.append(r.records)
+        summs.append(r.summary)
+    return np.concatenate(recs), np.array(summs, dtype=O.SUMMARY_DTYPE)
+
+
+def test_batch_of_different_programs():
+    ws = [WL.c3_kernel(s) for s in range(6)] + [WL.fig3(40), WL.c1_kernel(3), WL.tree_reduce(True)]
+    items = [(ws[(i * 7) % len(ws)], 1000 + i) for i in range(27)]
+    g = _batch(items)
+    o = _oracle_batch(items)
+    U.assert_same(g, o, "batch")
+
+
+def test_chunked_batch_graph_replay_matches_eager():
+    items = [(WL.c3_kernel(s % 4), s) for s in range(40)]
+    import torch  # noqa: F401
+    progs_ws = None
+    # a small workspace forces many chunks: the graph is replayed once per chunk
+    small = max(B.Program(U.ctx(), w.src).workspace_size(1) if False else 0 for w, _ in items[:1])
+    g1 = _batch(items, ws_bytes=None)
+    ctx = U.ctx()
+    p = B.Program(ctx, items[0][0].src)
+    p.set_ndrange(items[0][0].G, items[0][0].W)
+    one = p.workspace_size(3)
+    g2 = _batch(items, ws_bytes=one * 3)            # graphs (several chunks)
+    g3 = _batch(items, ws_bytes=one * 3, profile=True)  # eager launches
+    o = _oracle_batch(items)
+    U.assert_same(g1, o, "one chunk")
+    U.assert_same(g2, o, "graph replay")
+    U.assert_same(g3, o, "eager chunks")
+    del progs_ws, small
+
+
+def test_workspace_overwritten_between_calls():
+    """A workspace whose bytes changed since the last call (new buffer at a
+    reused address, or scribbled on) is detected and its overlay pool cleared."""
+    import torch
+    w = WL.tree_reduce(True)
+    ctx = U.ctx()
+    p = B.Program(ctx, w.src)
+    p.set_ndrange(w.G, w.W)
+    p.bind(w.arrays, w.scalars)
+    buf = B.Buffers(p, 3, cap=1 << 16)
+    o = U.oracle_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 3)
+    for trial in range(3):
+        if trial:
+            buf.ws.random_(0, 255)   # every byte, header included
+        p.check_async(0, 3, buf.ws, buf.records, buf.n_records, buf.summaries)
+        ctx.sync()
+        n = int(buf.n_records.item())
+        g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 3))
+        U.assert_same(g, o, f"trial {trial}")
+    del torch

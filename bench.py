@@ -8,6 +8,7 @@ seeded on the device.  Prints one JSON line.
 
 Configs: c1 (one random 20-statement kernel, 1 x 64, 1000 seeds),
 c2 (six template kernels, 16 x 256, 10^4 seeds each; the default),
+c3 (random kernels of widths 32..1024 in one batched call; --programs x --seeds),
 c4 (large intervals, 64 x 1024 x 64 iterations, 16 seeds).
 """
 from __future__ import annotations
@@ -37,6 +38,8 @@ def workload(name: str, seeds: int | None):
     if name == "c2":
         return ([(w, seeds or 10000) for w in WL.c2_templates()],
                 "c2: tree reduction, Hillis-Steele prefix sum, 32x32 tiled transpose (clean + injected), G=16 x W=256")
+    if name == "c3":
+        return None, "c3: random kernels, W in {32..1024}, 10-200 statements, 1-8 barriers, one batched call"
     if name == "c4":
         return [(WL.c4_kernel(), seeds or 16)], "c4: large intervals, G=64 x W=1024 x 64 iterations, 2^20 cells"
     raise SystemExit(f"unknown config {name}")
@@ -51,6 +54,8 @@ def main():
     ap.add_argument("--seeds", type=int, default=None, help="seeds per program (default: the config's)")
     ap.add_argument("--ws-gb", type=float, default=48.0, help="workspace budget over all programs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0: skip)")
+    ap.add_argument("--programs", type=int, default=10000, help="c3: number of random programs")
+    ap.add_argument("--tune-cache", default=None, help="c3: autotuner cache file (default: a temp file)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -62,6 +67,8 @@ def main():
 
     progs, desc = workload(args.config, args.seeds)
     ctx = B.Context(0)
+    if args.config == "c3":
+        return bench_c3(args, ctx, desc)
     runs = []
     per_ws = int(args.ws_gb * (1 << 30) / len(progs))
     for w, n in progs:
@@ -129,6 +136,90 @@ def main():
                    "instances_per_step": sum(n for _, n, _, _ in runs),
                    "accesses_per_step": accesses, "race_records_per_step": records,
                    "racy_instances_per_step": race_instances},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_c3(args, ctx, desc):
+    """The batched sweep: every (program, seed) instance of the random-kernel
+    generator in one rc_batch_check call per step."""
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_1308_3203_amd import binding as B
+    from paper_1308_3203_amd import workloads as WL
+    seeds = args.seeds or 100
+    t0 = time.perf_counter()
+    works = [WL.c3_kernel(s) for s in range(args.programs)]
+    progs = []
+    for w in works:
+        p = B.Program(ctx, w.src)
+        p.set_ndrange(w.G, w.W)
+        p.bind(w.arrays, w.scalars)
+        progs.append(p)
+    cache = args.tune_cache or os.path.join(tempfile.gettempdir(), f"rc_tune_{os.getpid()}.json")
+    small = torch.empty(max(p.workspace_size(2) for p in progs[:64]) * 2, dtype=torch.uint8, device="cuda")
+    tuned = {}
+    for p in progs:
+        need = p.workspace_size(2)
+        if need > small.numel():
+            small = torch.empty(need, dtype=torch.uint8, device="cuda")
+        key = json.dumps(p.autotune(1 << 40, 2, small, cache), sort_keys=True)
+        tuned[key] = tuned.get(key, 0) + 1
+    del small
+    setup_s = time.perf_counter() - t0
+    handles = np.repeat(B.handles_of(progs), seeds)
+    seed_arr = np.tile(np.arange(seeds, dtype=np.uint64), len(progs))
+    n = int(handles.size)
+    ws = torch.empty(int(args.ws_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
+    cap = 1 << 24
+    rec = torch.empty(cap * B.RECORD_BYTES, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    summ = torch.empty(n * B.SUMMARY_BYTES, dtype=torch.uint8, device="cuda")
+
+    def step():
+        ctx.batch_check_async(handles, seed_arr, ws, rec, cnt, summ)
+        ctx.sync()
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    s = B.summaries_to_numpy(summ, n)
+    accesses = int(s["n_accesses"].sum())
+    records = int(cnt.item())
+    racy = int((s["n_race_cells"] > 0).sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # phase split from one more (profiled, eager) step
+    ctx.profile(True)
+    step()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    value = accesses * args.steps / elapsed
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, launches = prof[dom]
+    per_launch_ms = ms / max(1, launches)
+    algo = ALGO_BYTES.get(dom, 0.0) * accesses / max(1, launches)
+    achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": KERNEL_OF_PHASE[dom],
+                "phase": dom, "avg_launch_ms": round(per_launch_ms, 4),
+                "phases_ms": {k: round(v[0], 3) for k, v in prof.items()},
+                "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}
+    cpu = cpu_baseline([(w, seeds) for w in works[: max(1, min(len(works), 50))]], args.cpu_seconds) \
+        if args.cpu_seconds > 0 else None
+    line = {
+        "metric": "race-checked accesses/s", "value": round(value, 1), "unit": "accesses/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": desc, "programs": len(progs), "seeds_per_program": seeds, "instances_per_step": n,
+                   "accesses_per_step": accesses, "race_records_per_step": records,
+                   "racy_instances_per_step": racy, "setup_s": round(setup_s, 2), "tunings": tuned},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

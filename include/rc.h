@@ -159,12 +159,29 @@ rc_status rc_bind_scalar(rc_prog* prog, uint32_t scalar_id, int32_t value);
 /* Implementation tuning (never changes results).  lds_log_entries: size of
  * the per-work-group interval log kept in LDS (rounded down to a power of
  * two and clamped to what LDS holds; 0 = the library's choice).  Intervals
- * larger than it are checked by the global pass instead. */
+ * larger than it are checked by the global pass instead.  radix_bits: digit
+ * width of the global access-log sort, 1..8 (0 = 8); a batch uses the value
+ * of its first instance's program. */
 typedef struct {
   uint32_t lds_log_entries;
-  uint32_t reserved[7];
+  uint32_t radix_bits;
+  uint32_t reserved[6];
 } rc_tuning;
 rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
+
+/*
+ * Autotuner.  Times candidate tunings (LDS interval-log sizes x radix digit
+ * widths) on a calibration slice (seeds seed0 .. seed0 + n_seeds - 1, checked
+ * with d_ws), verifies that every candidate reports identical records and
+ * summaries (RC_E_HIP if not), applies the fastest to `prog` and returns it in
+ * *chosen.  With cache_path non-NULL the choice is stored in that JSON file
+ * under the program's shape bucket (device, work-group width class, groups,
+ * interval size, logged cells); a later call for the same bucket applies the
+ * cached choice without timing.  Allocates its own scratch buffers (an
+ * offline tool, not for use inside a capture).
+ */
+rc_status rc_autotune(rc_prog* prog, uint64_t seed0, uint32_t n_seeds, void* d_ws, size_t ws_bytes,
+                      const char* cache_path, rc_tuning* chosen);
 
 /* ---- checking ----------------------------------------------------------- */
 

@@ -37,7 +37,7 @@ EXPORTS = [
     "rc_prog_free", "rc_prog_get_info", "rc_prog_array", "rc_prog_scalar", "rc_set_ndrange",
     "rc_bind_seeded", "rc_bind_device", "rc_bind_scalar_seeded", "rc_bind_scalar",
     "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
-    "rc_ctx_profile_read", "rc_prog_set_tuning", "rc_batch_check",
+    "rc_ctx_profile_read", "rc_prog_set_tuning", "rc_batch_check", "rc_autotune",
 ]
 PHASES = ["interpret", "log_sort", "interval_check", "record_sort", "output", "setup"]
 
@@ -53,7 +53,8 @@ class _Profile(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("lds_log_entries", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 7)]
+    _fields_ = [("lds_log_entries", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "rc_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "rc_ctx_profile_read": ([vp, ctypes.POINTER(_Profile)], ctypes.c_int),
         "rc_prog_set_tuning": ([vp, ctypes.POINTER(_Tuning)], ctypes.c_int),
+        "rc_autotune": ([vp, u64, u32, vp, sz, ctypes.c_char_p, ctypes.POINTER(_Tuning)], ctypes.c_int),
         "rc_batch_check": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64), u32, vp, sz,
                             vp, u64, vp, vp], ctypes.c_int),
     }
@@ -133,13 +135,19 @@ class Context:
         _call(_lib.rc_sync, self._h)
 
     def batch_check_async(self, programs, seeds, ws, records, n_records, summaries):
-        """Enqueue a check of instances (programs[i], seeds[i]) into caller-owned buffers."""
-        n = len(programs)
-        parr = (ctypes.c_void_p * max(n, 1))(*[p._h.value for p in programs])
-        sarr = (ctypes.c_uint64 * max(n, 1))(*[int(x) & (2 ** 64 - 1) for x in seeds])
+        """Enqueue a check of instances (programs[i], seeds[i]) into caller-owned
+        buffers.  `programs` is a list of Program or a numpy uint64 array of
+        handles (see handles()); `seeds` any integer sequence."""
+        if isinstance(programs, np.ndarray):
+            handles = np.ascontiguousarray(programs, dtype=np.uint64)
+        else:
+            handles = handles_of(programs)
+        sarr = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+        n = int(handles.size)
         cap = records.numel() // RECORD_BYTES
-        _call(_lib.rc_batch_check, self._h, parr, sarr, n, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-              ctypes.c_void_p(records.data_ptr() if cap else 0), cap,
+        _call(_lib.rc_batch_check, self._h, handles.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p)),
+              sarr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n, ctypes.c_void_p(ws.data_ptr()),
+              ws.numel(), ctypes.c_void_p(records.data_ptr() if cap else 0), cap,
               ctypes.c_void_p(n_records.data_ptr()), ctypes.c_void_p(summaries.data_ptr()))
 
     def profile(self, enable: bool = True):
@@ -161,6 +169,11 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def handles_of(programs) -> np.ndarray:
+    """Library handles of Program objects, for batch_check_async."""
+    return np.array([p._h.value for p in programs], dtype=np.uint64)
 
 
 class Program:
@@ -230,10 +243,18 @@ class Program:
             else:
                 _call(_lib.rc_bind_scalar, self._h, sid, ((int(b) + 2 ** 31) % 2 ** 32) - 2 ** 31)
 
-    def set_tuning(self, lds_log_entries: int = 0):
+    def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0):
         t = _Tuning()
         t.lds_log_entries = lds_log_entries
+        t.radix_bits = radix_bits
         _call(_lib.rc_prog_set_tuning, self._h, ctypes.byref(t))
+
+    def autotune(self, seed0: int, n_seeds: int, ws, cache_path: str | None = None) -> dict:
+        """Pick (and apply) the fastest tuning on a calibration slice."""
+        t = _Tuning()
+        _call(_lib.rc_autotune, self._h, ctypes.c_uint64(seed0), n_seeds, ctypes.c_void_p(ws.data_ptr()),
+              ws.numel(), cache_path.encode() if cache_path else None, ctypes.byref(t))
+        return {"lds_log_entries": int(t.lds_log_entries), "radix_bits": int(t.radix_bits)}
 
     def workspace_size(self, n_seeds: int) -> int:
         out = ctypes.c_size_t()

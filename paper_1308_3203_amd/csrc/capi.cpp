@@ -6,7 +6,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -87,6 +89,7 @@ struct rc_prog {
   std::vector<uint32_t> cellbase, sizes;
   uint32_t n_logged_cells = 0, overlay_cells = 0, lds_local_cells = 0;
   uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
+  uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t lds_log_cap = 0;          // chosen for the current shape
   // device: code, then tables
   void* d_mem = nullptr;
@@ -271,6 +274,7 @@ struct Call {
   uint32_t classes_used = 0;            // bit c: width class c occurs
   size_t class_lds[N_WCLASS] = {0, 0, 0, 0, 0};
   uint32_t epoch_stride = 1;
+  uint32_t radix_bits = 8;              // digit width of the access-log sort
 };
 
 // Split the instances into chunks whose resources stay under the limits.
@@ -357,6 +361,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     C.class_lds[c] = std::max(C.class_lds[c], lds_bytes(p));
   }
   C.epoch_stride = (uint32_t)std::min<u64>(max_stores + 1, 1u << 22);
+  C.radix_bits = C.progs.empty() ? 8u : C.progs[0]->radix_bits;
   if (bc > 32 || bg > 26 || bk > 32) { *why = "sort key fields too wide"; return false; }
   // try 1, 2, 4, ... chunks
   for (u64 k = 1;; k *= 2) {
@@ -445,8 +450,8 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
   {
     PhaseTimer t(ctx, st, 1, timed);
     HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.max_log, L.nbits_log, (const uint32_t*)(ws + L.wg_count),
-                     (const u64*)(ws + L.wg_base), (uint32_t*)(ws + L.tiles), L.max_wg, (uint32_t*)(ws + L.hist), st,
-                     &second));
+                     (const u64*)(ws + L.wg_base), (uint32_t*)(ws + L.tiles), L.max_wg, (uint32_t*)(ws + L.hist),
+                     C.radix_bits, st, &second));
   }
   {
     PhaseTimer t(ctx, st, 2, timed);
@@ -859,8 +864,168 @@ rc_status rc_bind_scalar(rc_prog* p, uint32_t id, int32_t value) {
 
 rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   if (!p || !t) return fail(RC_E_INVAL, "NULL argument");
+  if (t->radix_bits > 8) return fail(RC_E_INVAL, "radix_bits must be in 1..8 (0: default)");
   p->lds_log_pref = t->lds_log_entries;
+  p->radix_bits = t->radix_bits ? t->radix_bits : 8;
   if (p->shaped) p->lds_log_cap = lds_log_entries(p);
+  return RC_OK;
+}
+
+static std::string bucket_key(const rc_prog* p, int device) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  const double ib = (double)p->W * (p->G == 1 ? p->c.interval_logged_all : p->c.interval_logged_local);
+  char b[160];
+  snprintf(b, sizeof b, "%s|wclass%u|groups%u|interval%u|cells%u|v1", arch.c_str(), width_class(p->W),
+           bits_for(p->G), bits_for((u64)(ib + 1)), bits_for(std::max<uint32_t>(1, p->n_logged_cells)));
+  return b;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, rc_tuning* t) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  const std::string q = "\"" + key + "\"";
+  while (std::getline(f, line)) {
+    const size_t at = line.find(q);
+    if (at == std::string::npos) continue;
+    unsigned T = 0, d = 0;
+    const size_t a = line.find("\"lds_log_entries\":"), b = line.find("\"radix_bits\":");
+    if (a == std::string::npos || b == std::string::npos) return false;
+    if (sscanf(line.c_str() + a + 18, "%u", &T) != 1 || sscanf(line.c_str() + b + 13, "%u", &d) != 1) return false;
+    memset(t, 0, sizeof *t);
+    t->lds_log_entries = T;
+    t->radix_bits = d;
+    return true;
+  }
+  return false;
+}
+
+static void cache_store(const char* path, const std::string& key, const rc_tuning& t, double ms) {
+  std::vector<std::string> entries;
+  {
+    std::ifstream f(path);
+    std::string line;
+    const std::string q = "\"" + key + "\"";
+    while (f && std::getline(f, line)) {
+      if (line.find("\": {") == std::string::npos || line.find(q) != std::string::npos) continue;
+      while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+      entries.push_back(line);
+    }
+  }
+  char b[320];
+  snprintf(b, sizeof b, "  \"%s\": {\"lds_log_entries\": %u, \"radix_bits\": %u, \"ms\": %.4f}", key.c_str(),
+           t.lds_log_entries, t.radix_bits, ms);
+  entries.push_back(b);
+  std::ofstream f(path, std::ios::trunc);
+  f << "{\n";
+  for (size_t i = 0; i < entries.size(); ++i) f << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, size_t ws_bytes,
+                      const char* cache_path, rc_tuning* chosen) {
+  if (!p || !d_ws || !chosen || n_seeds == 0) return fail(RC_E_INVAL, "bad argument");
+  rc_status s = check_ready(p);
+  if (s) return s;
+  rc_ctx* ctx = p->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const std::string key = bucket_key(p, ctx->device);
+  rc_tuning t;
+  if (cache_path && cache_lookup(cache_path, key, &t)) {
+    s = rc_prog_set_tuning(p, &t);
+    if (s) return s;
+    *chosen = t;
+    return RC_OK;
+  }
+  // candidates: LDS log sizes (deduplicated after clamping) x digit widths
+  std::vector<rc_tuning> cands;
+  std::vector<uint32_t> seen_caps;
+  const uint32_t T_opts[] = {0, 256, 1024, 4096, 8192, 16384};
+  const uint32_t d_opts[] = {8, 6, 4};
+  const uint32_t saved_pref = p->lds_log_pref, saved_bits = p->radix_bits;
+  for (uint32_t T : T_opts) {
+    p->lds_log_pref = T;
+    const uint32_t cap = lds_log_entries(p);
+    if (std::find(seen_caps.begin(), seen_caps.end(), cap) != seen_caps.end()) continue;
+    seen_caps.push_back(cap);
+    for (uint32_t d : d_opts) {
+      rc_tuning c;
+      memset(&c, 0, sizeof c);
+      c.lds_log_entries = T;
+      c.radix_bits = d;
+      cands.push_back(c);
+    }
+  }
+  p->lds_log_pref = saved_pref;
+  p->radix_bits = saved_bits;
+  const u64 cap = 1ull << 20;
+  rc_record* d_rec = nullptr;
+  rc_summary* d_sum = nullptr;
+  u64* d_n = nullptr;
+  HIP_TRY(hipMalloc(&d_rec, cap * sizeof(rc_record)));
+  HIP_TRY(hipMalloc(&d_sum, (size_t)n_seeds * sizeof(rc_summary)));
+  HIP_TRY(hipMalloc(&d_n, 8));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::vector<unsigned char> ref_rec, ref_sum, cur_rec, cur_sum;
+  u64 ref_n = 0;
+  double best = 1e30;
+  rc_tuning best_t = cands.empty() ? rc_tuning() : cands[0];
+  rc_status result = RC_OK;
+  for (size_t i = 0; i < cands.size() && result == RC_OK; ++i) {
+    rc_prog_set_tuning(p, &cands[i]);
+    double ms_best = 1e30;
+    for (int rep = 0; rep < 3 && result == RC_OK; ++rep) {
+      (void)hipEventRecord(e0, ctx->stream);
+      result = rc_check(p, seed0, n_seeds, d_ws, ws_bytes, d_rec, cap, (uint64_t*)d_n, d_sum);
+      (void)hipEventRecord(e1, ctx->stream);
+      if (result == RC_OK) result = rc_sync(ctx);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ms_best = std::min(ms_best, (double)ms);   // the first run warms up
+    }
+    if (result != RC_OK) break;
+    u64 n = 0;
+    (void)hipMemcpy(&n, d_n, 8, hipMemcpyDeviceToHost);
+    const u64 k = std::min(n, cap);
+    cur_rec.resize(k * sizeof(rc_record));
+    cur_sum.resize((size_t)n_seeds * sizeof(rc_summary));
+    (void)hipMemcpy(cur_rec.data(), d_rec, cur_rec.size(), hipMemcpyDeviceToHost);
+    (void)hipMemcpy(cur_sum.data(), d_sum, cur_sum.size(), hipMemcpyDeviceToHost);
+    if (i == 0) {
+      ref_rec = cur_rec;
+      ref_sum = cur_sum;
+      ref_n = n;
+    } else if (n != ref_n || cur_rec != ref_rec || cur_sum != ref_sum) {
+      result = fail(RC_E_HIP, "tuning candidate %zu changed the report: results must not depend on tuning", i);
+      break;
+    }
+    if (ms_best < best) {
+      best = ms_best;
+      best_t = cands[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_rec);
+  (void)hipFree(d_sum);
+  (void)hipFree(d_n);
+  if (result != RC_OK) {
+    rc_tuning back;
+    memset(&back, 0, sizeof back);
+    back.lds_log_entries = saved_pref;
+    back.radix_bits = saved_bits;
+    rc_prog_set_tuning(p, &back);
+    return result;
+  }
+  rc_prog_set_tuning(p, &best_t);
+  if (cache_path) cache_store(cache_path, key, best_t, best);
+  *chosen = best_t;
   return RC_OK;
 }
 

@@ -103,7 +103,7 @@ size_t sort_log_hist_words(unsigned long long n_regions, unsigned long long cap)
 hipError_t sort_log(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
                     const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
                     const uint32_t* seg_count, const unsigned long long* seg_base, uint32_t* tiles,
-                    unsigned long long n_regions, uint32_t* hist, hipStream_t st, int* in_second);
+                    unsigned long long n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second);
 hipError_t sort_pairs_u32(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1,
                           const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
                           uint32_t* hist, hipStream_t st, int* in_second);

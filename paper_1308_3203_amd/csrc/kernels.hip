@@ -757,7 +757,7 @@ struct RsIn {
   const uint32_t* seg_count;
   const u64* seg_base;
   const uint32_t* tiles;
-  uint32_t n_regions, pad;
+  uint32_t n_regions, dbits;   // dbits: digit width of this pass (1..8)
 };
 
 __device__ __forceinline__ void rs_tile(const RsIn& in, uint32_t b, u64* start, uint32_t* count) {
@@ -792,14 +792,15 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, 
                                                       uint32_t* hist, uint32_t nblocks) {
   __shared__ uint32_t h[256];
   const uint32_t t = threadIdx.x;
+  const uint32_t dmask = (1u << in.dbits) - 1u;
   h[t] = 0;
   __syncthreads();
   u64 start;
   uint32_t count;
   rs_tile(in, blockIdx.x, &start, &count);
-  for (uint32_t i = t; i < count; i += RS_THREADS) atomicAdd(&h[(uint32_t)(keys[start + i] >> shift) & 255u], 1u);
+  for (uint32_t i = t; i < count; i += RS_THREADS) atomicAdd(&h[(uint32_t)(keys[start + i] >> shift) & dmask], 1u);
   __syncthreads();
-  hist[(size_t)t * nblocks + blockIdx.x] = h[t];
+  if (t <= dmask) hist[(size_t)t * nblocks + blockIdx.x] = h[t];
 }
 
 template <typename V>
@@ -813,7 +814,8 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
   uint32_t count;
   rs_tile(in, blockIdx.x, &start, &count);
   if (count == 0) return;
-  base[t] = offs[(size_t)t * nblocks + blockIdx.x];
+  const uint32_t dmask = (1u << in.dbits) - 1u;
+  base[t] = t <= dmask ? offs[(size_t)t * nblocks + blockIdx.x] : 0u;
   const u64 below = (1ull << lane) - 1ull;
   const uint32_t rounds = (count + RS_THREADS - 1) / RS_THREADS;
   for (uint32_t r = 0; r < rounds; ++r) {
@@ -822,9 +824,9 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
     u64 k = 0;
     V v = 0;
     uint32_t d = 0;
-    if (valid) { k = kin[start + i]; v = vin[start + i]; d = (uint32_t)(k >> shift) & 255u; }
+    if (valid) { k = kin[start + i]; v = vin[start + i]; d = (uint32_t)(k >> shift) & dmask; }
     u64 eq = __ballot(valid);
-    for (int b = 0; b < 8; ++b) {
+    for (uint32_t b = 0; b < in.dbits; ++b) {
       const u64 bb = __ballot((d >> b) & 1u);
       eq &= ((d >> b) & 1u) ? bb : ~bb;
     }
@@ -1149,16 +1151,20 @@ size_t sort_log_hist_words(u64 n_regions, u64 cap) {
 template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
                                   const uint32_t* seg_count, const u64* seg_base, const uint32_t* tiles,
-                                  u64 n_regions, uint32_t* hist, hipStream_t st, int* result_in_second) {
+                                  u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st,
+                                  int* result_in_second) {
   u64 *ka = k0, *kb = k1;
   V *va = v0, *vb = v1;
   int passes = 0;
-  // a segmented input always takes one pass, which also makes it dense
-  const uint32_t want = seg_count ? (nbits > 8 ? nbits : 8) : nbits;
-  for (uint32_t shift = 0; shift < want; shift += 8) {
+  if (dbits < 1 || dbits > 8) dbits = 8;
+  // passes of dbits each; a segmented input always takes one pass, which
+  // also makes it dense
+  const uint32_t want = seg_count ? (nbits > 1 ? nbits : 1) : nbits;
+  for (uint32_t shift = 0; shift < want; shift += dbits) {
     RsIn in;
     memset(&in, 0, sizeof in);
     in.n_ptr = n_ptr;
+    in.dbits = dbits;
     u64 nbl;
     if (passes == 0 && seg_count) {
       in.seg_count = seg_count;
@@ -1170,7 +1176,7 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
       nbl = blocks_for(cap ? cap : 1, RS_TILE);
     }
     const uint32_t nb = (uint32_t)(nbl ? nbl : 1);
-    const u64 m = 256ull * nb;
+    const u64 m = (1ull << dbits) * nb;
     uint32_t* tmp = hist + m;
     hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, in, shift, hist, nb);
     scan_excl(hist, m, tmp, st);
@@ -1186,19 +1192,19 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
 
 hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
                     const uint32_t* seg_count, const u64* seg_base, uint32_t* tiles, u64 n_regions,
-                    uint32_t* hist, hipStream_t st, int* in_second) {
+                    uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second) {
   // the number of entries, and the regions' tile prefix
   hipLaunchKernelGGL(sum_u32_kernel, dim3(n_regions > 65536 ? 1024 : (uint32_t)blocks_for(n_regions, 256)),
                      dim3(256), 0, st, seg_count, n_regions, (u64*)n_ptr);
   hipLaunchKernelGGL(region_tiles_kernel, dim3(blocks_for(n_regions + 1, 256)), dim3(256), 0, st, seg_count,
                      tiles, n_regions);
   scan_excl(tiles, n_regions + 1, hist, st);
-  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, seg_base, tiles, n_regions, hist, st,
-                              in_second);
+  return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, seg_base, tiles, n_regions, hist, dbits,
+                              st, in_second);
 }
 hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {
-  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, nullptr, nullptr, nullptr, 0, hist, st,
+  return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, nullptr, nullptr, nullptr, 0, hist, 8, st,
                                    in_second);
 }
 

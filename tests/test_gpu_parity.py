@@ -341,3 +341,31 @@ def test_workspace_overwritten_between_calls():
         g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 3))
         U.assert_same(g, o, f"trial {trial}")
     del torch
+
+
+# ---------------------------------------------------------------------------
+# autotuner: every candidate must give the same report; the cache is reused
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["c3_2", "tree_race", "c4_small"])
+def test_autotune_invariance_and_cache(case, tmp_path):
+    import json
+    import torch
+    w = {"c3_2": lambda: WL.c3_kernel(2), "tree_race": lambda: WL.tree_reduce(True),
+         "c4_small": lambda: WL.c4_kernel(4, 256, 8, 14)}[case]()
+    ctx = U.ctx()
+    p = B.Program(ctx, w.src)
+    p.set_ndrange(w.G, w.W)
+    p.bind(w.arrays, w.scalars)
+    ws = torch.empty(p.workspace_size(4), dtype=torch.uint8, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    chosen = p.autotune(0, 4, ws, cache)
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and list(entries.values())[0]["radix_bits"] == chosen["radix_bits"]
+    again = p.autotune(0, 4, ws, cache)          # from the cache
+    assert again == chosen
+    buf = B.Buffers(p, 4, cap=1 << 20)
+    p.check_async(0, 4, buf.ws, buf.records, buf.n_records, buf.summaries)
+    ctx.sync()
+    n = int(buf.n_records.item())
+    g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 4))
+    U.assert_same(g, U.oracle_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 4), f"{case} tuned {chosen}")

@@ -419,11 +419,11 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
     if (spilled || n < 2u) return;
     uint32_t P2 = 2;
     while (P2 < n) P2 <<= 1;
-    for (uint32_t i = n + tl; i < P2; i += WP) lkey[i] = ~0ull;
+    for (uint32_t i = n + tl; i < P2; i += blockDim.x) lkey[i] = ~0ull;
     __syncthreads();
     for (uint32_t k = 2; k <= P2; k <<= 1) {
       for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tl; i < P2; i += WP) {
+        for (uint32_t i = tl; i < P2; i += blockDim.x) {
           const uint32_t ixj = i ^ j;
           if (ixj > i) {
             const u64 a = lkey[i], b = lkey[ixj];
@@ -435,7 +435,7 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
     }
     const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
     const RecKey K = {P.bs, P.bc, P.G, P.NI};
-    for (uint32_t b0 = 0; b0 < n; b0 += WP) {
+    for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
       const uint32_t i = b0 + tl;
       bool has = false;
       PendingRec pr;
@@ -541,7 +541,7 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
         if (to_lds && lds_used + total > P.lds_log_cap) {
           // the interval outgrows LDS: move its log to the global log, where
           // the global pass checks it
-          for (uint32_t i = tl; i < lds_used; i += WP) {
+          for (uint32_t i = tl; i < lds_used; i += blockDim.x) {
             const u64 pos = log_used + i;
             const u64 ck = lkey[i] >> 16;
             if (pos < P.wg_log_cap) {

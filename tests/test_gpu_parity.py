@@ -59,7 +59,9 @@ def test_c1_other_programs(pseed):
 # random small kernels across launch shapes (single and multi-wave groups,
 # ragged last waves, several groups)
 # ---------------------------------------------------------------------------
-SHAPES = [(1, 1), (1, 7), (1, 64), (1, 65), (2, 33), (3, 130), (1, 256), (2, 300), (1, 1000), (4, 1024)]
+SHAPES = [(1, 1), (1, 7), (1, 64), (1, 65), (2, 33), (3, 130), (1, 256), (2, 300), (1, 1000), (4, 1024),
+          # one group, widths whose last waves leave part of the workgroup idle
+          (1, 130), (1, 200), (1, 352), (1, 600), (1, 900)]
 
 
 @pytest.mark.parametrize("G,W", SHAPES)
@@ -166,10 +168,10 @@ def test_c2_final_memory(tmpl):
 # ---------------------------------------------------------------------------
 # c3 random kernels and c4 large intervals
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("pseed", range(0, 24))
+@pytest.mark.parametrize("pseed", list(range(0, 24)) + [100, 101, 137, 250])
 def test_c3_kernels(pseed):
     w = WL.c3_kernel(pseed)
-    g, o = both(w.src, w.G, w.W, w.arrays, seed0=0, n=2)
+    g, o = both(w.src, w.G, w.W, w.arrays, seed0=1 << 40, n=2)
     U.assert_same(g, o, w.name)
 
 

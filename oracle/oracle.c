@@ -1070,3 +1070,288 @@ void orc_result_free(orc_result* r) {
   free(r->records); free(r->final_mem);
   memset(r, 0, sizeof *r);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Triage features of one instance                                           */
+/* ------------------------------------------------------------------------ */
+/*
+ * The 128 features are not part of the paper's method: they are the inputs
+ * of the learned triage score, defined by the library's documentation of
+ * rc_features.  This is that definition written out directly over the
+ * oracle's own syntax tree, statement by statement in program order.
+ */
+typedef struct { int ok, modded; int64_t a, b; } Lin;   /* index = a*tid + b [mod N] */
+
+static Lin lin_bad(void) { Lin r = {0, 0, 0, 0}; return r; }
+
+static Lin lin_check(Lin r) {
+  const int64_t big = (int64_t)1 << 31;
+  if (r.a > big || r.a < -big || r.b > big || r.b < -big) return lin_bad();
+  return r;
+}
+
+static Lin lin_of(const Expr* e) {
+  Lin r = lin_bad();
+  if (e->kind == E_CONST) { r.ok = 1; r.b = e->val; return r; }
+  if (e->kind == E_TID) { r.ok = 1; r.a = 1; return r; }
+  if (e->kind == E_NEG) {
+    Lin x = lin_of(e->a);
+    if (!x.ok || x.modded) return lin_bad();
+    x.a = -x.a; x.b = -x.b;
+    return lin_check(x);
+  }
+  if (e->kind != E_BIN) return r;
+  Lin x = lin_of(e->a), y = lin_of(e->b);
+  if (!x.ok || !y.ok || x.modded || y.modded) return r;
+  if (e->op == B_ADD) { r.ok = 1; r.a = x.a + y.a; r.b = x.b + y.b; return lin_check(r); }
+  if (e->op == B_SUB) { r.ok = 1; r.a = x.a - y.a; r.b = x.b - y.b; return lin_check(r); }
+  if (e->op == B_MUL) {
+    /* affine only when one factor is a constant */
+    if (x.a == 0) { r.ok = 1; r.a = x.b * y.a; r.b = x.b * y.b; return lin_check(r); }
+    if (y.a == 0) { r.ok = 1; r.a = x.a * y.b; r.b = x.b * y.b; return lin_check(r); }
+    return r;
+  }
+  if (e->op == B_MOD || e->op == B_REM) {
+    if (y.a != 0 || y.b <= 0) return r;
+    x.modded = 1;
+    return x;
+  }
+  return r;
+}
+
+typedef struct {
+  int is_store, arr;
+  Lin idx;
+  int64_t interval;
+  int under_if, under_loop, under_barrier_loop;
+} FMem;
+
+typedef struct {
+  const orc_prog* P;
+  int64_t kind_count[8];
+  int64_t n_stmts, loads_g, loads_l, stores_g, stores_l;
+  int64_t interval, mem_since_barrier, max_mem_interval, loop_barriers, trips;
+  int64_t tid_values, other_values, ifs_open, max_ifs, loops_open, max_loops;
+  int64_t mem_under_if, mem_under_loop, barrier_loops_open;
+  FMem* mem; int64_t n_mem, cap_mem;
+} FState;
+
+static int body_has_barrier(Stmt** b, int n) {
+  for (int i = 0; i < n; i++) {
+    if (b[i]->kind == S_BARRIER) return 1;
+    if (b[i]->kind == S_IF || b[i]->kind == S_FOR)
+      if (body_has_barrier(b[i]->body, b[i]->nbody) || body_has_barrier(b[i]->els, b[i]->nels)) return 1;
+  }
+  return 0;
+}
+
+static void fwalk(FState* F, Stmt** b, int n) {
+  for (int i = 0; i < n; i++) {
+    const Stmt* s = b[i];
+    F->n_stmts++;
+    F->kind_count[s->kind]++;
+    if (s->kind == S_LOAD || s->kind == S_STORE) {
+      int global = s->arr < F->P->n_global;
+      int st = s->kind == S_STORE;
+      if (st && global) F->stores_g++;
+      if (st && !global) F->stores_l++;
+      if (!st && global) F->loads_g++;
+      if (!st && !global) F->loads_l++;
+      if (F->n_mem == F->cap_mem) {
+        F->cap_mem = F->cap_mem ? 2 * F->cap_mem : 64;
+        F->mem = (FMem*)realloc(F->mem, (size_t)F->cap_mem * sizeof(FMem));
+      }
+      FMem* m = &F->mem[F->n_mem++];
+      m->is_store = st;
+      m->arr = s->arr;
+      m->idx = lin_of(s->e1);
+      m->interval = F->interval;
+      m->under_if = F->ifs_open > 0;
+      m->under_loop = F->loops_open > 0;
+      m->under_barrier_loop = F->barrier_loops_open > 0;
+      if (m->under_if) F->mem_under_if++;
+      if (m->under_loop) F->mem_under_loop++;
+      F->mem_since_barrier++;
+      if (st) {
+        Lin v = lin_of(s->e2);
+        if (!v.ok) F->other_values++;
+        else if (v.a != 0) F->tid_values++;
+      }
+    } else if (s->kind == S_BARRIER) {
+      if (F->loops_open > 0) F->loop_barriers++;
+      if (F->mem_since_barrier > F->max_mem_interval) F->max_mem_interval = F->mem_since_barrier;
+      F->mem_since_barrier = 0;
+      F->interval++;
+    } else if (s->kind == S_IF) {
+      F->ifs_open++;
+      if (F->ifs_open > F->max_ifs) F->max_ifs = F->ifs_open;
+      fwalk(F, s->body, s->nbody);
+      fwalk(F, s->els, s->nels);
+      F->ifs_open--;
+    } else if (s->kind == S_FOR) {
+      int with_barrier = body_has_barrier(s->body, s->nbody);
+      if (s->hi > s->lo) F->trips += s->hi - s->lo;
+      F->loops_open++;
+      if (F->loops_open > F->max_loops) F->max_loops = F->loops_open;
+      if (with_barrier) F->barrier_loops_open++;
+      fwalk(F, s->body, s->nbody);
+      if (with_barrier) F->barrier_loops_open--;
+      F->loops_open--;
+    }
+  }
+}
+
+static float fdiv(int64_t a, int64_t b) { return (float)a / (float)b; }
+
+static int64_t pos_mod(int64_t x, int64_t m) {
+  int64_t r = x % m;
+  return r < 0 ? r + m : r;
+}
+
+static int64_t ceil_log2(int64_t s) {
+  int64_t k = 0;
+  while (((int64_t)1 << k) < s) k++;
+  return k;
+}
+
+int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arrays, int n_arrays,
+                 uint64_t seed, float* f, char* err, int errlen) {
+  FState F;
+  memset(&F, 0, sizeof F);
+  F.P = P;
+  for (int k = 0; k < 128; k++) f[k] = 0.0f;
+  if (n_arrays < P->n_global) {
+    snprintf(err, (size_t)errlen, "every global array needs a binding");
+    return -1;
+  }
+  fwalk(&F, P->body, P->nbody);
+  if (F.mem_since_barrier > F.max_mem_interval) F.max_mem_interval = F.mem_since_barrier;
+  int64_t n = F.n_stmts > 0 ? F.n_stmts : 1;
+  /* statement mix */
+  for (int k = 0; k < 8; k++) f[k] = fdiv(F.kind_count[k], n);
+  f[8] = fdiv(F.loads_g, n);
+  f[9] = fdiv(F.loads_l, n);
+  f[10] = fdiv(F.stores_g, n);
+  f[11] = fdiv(F.stores_l, n);
+  f[12] = fdiv(F.n_stmts, 256);
+  f[13] = fdiv(P->n_global, 8);
+  f[14] = fdiv(P->n_local, 8);
+  f[15] = fdiv(P->n_scalars, 16);
+  /* candidate conflicting pairs: same array, a store among them, same static
+     interval (statements under a loop that holds a barrier counted apart) */
+  int64_t self_const = 0, self_const_if = 0, self_other = 0, shifted = 0, aligned = 0;
+  int64_t strides = 0, opaque = 0, looped = 0;
+  for (int64_t i = 0; i < F.n_mem; i++) {
+    for (int64_t j = i; j < F.n_mem; j++) {
+      const FMem* x = &F.mem[i];
+      const FMem* y = &F.mem[j];
+      if (x->arr != y->arr) continue;
+      if (!x->is_store && !y->is_store) continue;
+      if (x->under_barrier_loop || y->under_barrier_loop) { looped++; continue; }
+      if (x->interval != y->interval) continue;
+      if (i == j) {
+        if (!x->idx.ok) self_other++;
+        else if (x->idx.a == 0) { self_const++; if (x->under_if) self_const_if++; }
+        continue;
+      }
+      if (!x->idx.ok || !y->idx.ok) { opaque++; continue; }
+      if (x->idx.a != y->idx.a) { strides++; continue; }
+      int64_t S = P->arr_size[x->arr];
+      if (pos_mod(x->idx.b, S) == pos_mod(y->idx.b, S)) aligned++;
+      else shifted++;
+    }
+  }
+  f[16] = fdiv(self_const, 8);
+  f[17] = fdiv(self_const_if, 8);
+  f[18] = fdiv(self_other, 8);
+  f[19] = fdiv(shifted, 8);
+  f[20] = fdiv(aligned, 8);
+  f[21] = fdiv(strides, 8);
+  f[22] = fdiv(opaque, 8);
+  f[23] = fdiv(looped, 8);
+  f[24] = fdiv(F.tid_values, 16);
+  f[25] = fdiv(F.other_values, 16);
+  f[26] = fdiv(F.max_ifs, 16);
+  f[27] = fdiv(F.max_loops, 4);
+  f[28] = fdiv(F.mem_under_if, 16);
+  f[29] = fdiv(F.mem_under_loop, 16);
+  {
+    int64_t distinct = 0;
+    for (int64_t i = 0; i < F.n_mem; i++) {
+      if (!F.mem[i].is_store) continue;
+      int seen = 0;
+      for (int64_t j = 0; j < i; j++)
+        if (F.mem[j].is_store && F.mem[j].interval == F.mem[i].interval) seen = 1;
+      if (!seen) distinct++;
+    }
+    f[30] = fdiv(distinct, 8);
+  }
+  /* the first 16 memory statements */
+  for (int64_t k = 0; k < 16 && k < F.n_mem; k++) {
+    const FMem* m = &F.mem[k];
+    float* s = f + 32 + 4 * k;
+    s[0] = m->is_store ? 1.0f : -1.0f;
+    if (m->idx.ok) {
+      int64_t mag = m->idx.a < 0 ? -m->idx.a : m->idx.a;
+      s[1] = (float)m->idx.a / (float)(1 + mag);
+      s[2] = fdiv(pos_mod(m->idx.b, P->arr_size[m->arr]), P->arr_size[m->arr]);
+    } else {
+      s[1] = -2.0f;
+      s[2] = -2.0f;
+    }
+    s[3] = fdiv(m->interval + 1, 8);
+  }
+  /* barrier and loop structure */
+  f[96] = fdiv(F.kind_count[S_BARRIER], 8);
+  f[97] = fdiv(F.loop_barriers, 8);
+  f[98] = fdiv(F.max_mem_interval, 64);
+  f[99] = fdiv(F.trips, 64);
+  f[100] = fdiv(F.n_mem, 64);
+  f[101] = fdiv(F.kind_count[S_STORE], 64);
+  {
+    int64_t distinct = 0;
+    for (int64_t i = 0; i < F.n_mem; i++) {
+      if (!F.mem[i].is_store) continue;
+      int seen = 0;
+      for (int64_t j = 0; j < i; j++)
+        if (F.mem[j].is_store && F.mem[j].arr == F.mem[i].arr) seen = 1;
+      if (!seen) distinct++;
+    }
+    f[102] = fdiv(distinct, 8);
+  }
+  /* launch shape and array sizes */
+  f[104] = fdiv(W, 1024);
+  f[105] = fdiv(G, 1024);
+  if (P->n_global > 0) f[106] = fdiv(ceil_log2(P->arr_size[0]), 32);
+  if (P->n_global > 1) f[107] = fdiv(ceil_log2(P->arr_size[1]), 32);
+  {
+    int64_t local_cells = 0;
+    for (int a = P->n_global; a < P->n_global + P->n_local; a++) local_cells += P->arr_size[a];
+    f[108] = fdiv(local_cells, 65536);
+  }
+  f[109] = fdiv((int64_t)G * (int64_t)W, 1048576);
+  /* seed statistics: 8-bin histograms of the first 256 initial cells of
+     global arrays 0 and 1 */
+  for (int a = 0; a < 2 && a < P->n_global; a++) {
+    const orc_bind* b = &arrays[a];
+    int64_t cells = P->arr_size[a] < 256 ? P->arr_size[a] : 256;
+    int64_t hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t c = 0; c < cells; c++) {
+      int bin;
+      if (b->kind == 0) {
+        int32_t v = orc_seeded_value(seed, (uint64_t)a, (uint64_t)c, b->lo, b->hi);
+        /* the draw's offset in [lo, hi), taken mod 2^32 because a range of
+           2^32 values wraps in int32, then its eighth of the range */
+        uint64_t u = (uint32_t)((uint32_t)v - (uint32_t)(uint64_t)b->lo);
+        bin = (int)(u * 8u / (uint64_t)(b->hi - b->lo));
+      } else {
+        int64_t v = b->data[c];
+        bin = (int)((v + 2147483648LL) / 536870912LL);   /* eighths of the int32 range */
+      }
+      hist[bin]++;
+    }
+    for (int k = 0; k < 8; k++) f[112 + 8 * a + k] = fdiv(hist[k], 256);
+  }
+  free(F.mem);
+  return 0;
+}

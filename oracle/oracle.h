@@ -75,6 +75,14 @@ int orc_run(const orc_prog* p, uint32_t G, uint32_t W,
             orc_result* out, char* err, int errlen);
 void orc_result_free(orc_result*);
 
+/*
+ * The 128 triage features of one instance (inputs of the learned score that
+ * orders a sweep; not part of the paper's method), as the library documents
+ * them for rc_features.  Returns 0, or -1 with a message in err.
+ */
+int orc_features(const orc_prog* p, uint32_t G, uint32_t W, const orc_bind* arrays, int n_arrays,
+                 uint64_t seed, float* out128, char* err, int errlen);
+
 /* The seeded input generator, exposed for tests of its published definition. */
 int32_t orc_seeded_value(uint64_t seed, uint64_t stream, uint64_t idx,
                          int64_t lo, int64_t hi);

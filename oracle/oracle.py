@@ -98,6 +98,10 @@ def _load():
         lib.orc_seeded_value.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int64, ctypes.c_int64]
         lib.orc_seeded_value.restype = ctypes.c_int32
+        lib.orc_features.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_Bind),
+                                     ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
+                                     ctypes.c_char_p, ctypes.c_int]
+        lib.orc_features.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -143,13 +147,7 @@ class Program:
             _lib.orc_prog_free(p)
             self._p = None
 
-    def run(self, G: int, W: int, arrays: dict | None = None, scalars: dict | None = None,
-            seed: int = 0, instance: int = 0, literal: bool = False,
-            final: str | None = None) -> OracleResult:
-        lib = _load()
-        arrays = arrays or {}
-        scalars = scalars or {}
-        keep = []
+    def _array_binds(self, arrays, keep):
         abind = (_Bind * max(1, len(self.arrays)))()
         for i, (name, size) in enumerate(self.arrays):
             b = arrays.get(name, ("seeded", 0, 16))
@@ -162,6 +160,29 @@ class Program:
                 keep.append(data)
                 abind[i].kind = 1
                 abind[i].data = data.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        return abind
+
+    def features(self, G: int, W: int, arrays: dict | None = None, seed: int = 0) -> np.ndarray:
+        """The 128 float32 triage features of one instance."""
+        lib = _load()
+        keep = []
+        abind = self._array_binds(arrays or {}, keep)
+        out = np.zeros(128, dtype=np.float32)
+        err = ctypes.create_string_buffer(256)
+        rc = lib.orc_features(self._p, G, W, abind, len(self.arrays), ctypes.c_uint64(seed & (2**64 - 1)),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), err, 256)
+        if rc != 0:
+            raise OracleError(err.value.decode())
+        return out
+
+    def run(self, G: int, W: int, arrays: dict | None = None, scalars: dict | None = None,
+            seed: int = 0, instance: int = 0, literal: bool = False,
+            final: str | None = None) -> OracleResult:
+        lib = _load()
+        arrays = arrays or {}
+        scalars = scalars or {}
+        keep = []
+        abind = self._array_binds(arrays, keep)
         sbind = (_Bind * max(1, len(self.scalars)))()
         for j, name in enumerate(self.scalars):
             b = scalars.get(name, ("seeded", 0, 16))

@@ -75,7 +75,16 @@ def main():
         p = B.Program(ctx, w.src)
         p.set_ndrange(w.G, w.W)
         p.bind(w.arrays, w.scalars)
-        buf = B.Buffers(p, n, cap=1 << 24, ws_limit=per_ws)
+        # record capacity from a probe over the first seeds (every record of
+        # the timed steps is written out)
+        n_probe = min(n, 16)
+        probe = B.Buffers(p, n_probe, cap=1 << 22, ws_limit=per_ws)
+        p.check_async(0, n_probe, probe.ws, probe.records, probe.n_records, probe.summaries)
+        ctx.sync()
+        per_inst = int(probe.n_records.item()) / n_probe
+        del probe
+        cap = int(per_inst * n * 1.25) + (1 << 16)
+        buf = B.Buffers(p, n, cap=cap, ws_limit=per_ws)
         runs.append((w, n, p, buf))
 
     def step(seed0):

@@ -233,6 +233,104 @@ rc_status rc_sync(rc_ctx* ctx);
 rc_status rc_read_final(rc_prog* prog, uint64_t seed, uint32_t array_id, int32_t* d_out,
                         void* d_ws, size_t ws_bytes);
 
+/* ---- triage network ------------------------------------------------------
+ * A learned score that orders (program, seed) instances by how likely the
+ * exact check is to find a race in them, so a sweep can check the likely ones
+ * first.  It is not part of the paper's method and never changes a report:
+ * every instance that is checked is checked exactly.
+ *
+ * Network (fp32): logit = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 for a
+ * feature row x of RC_MLP_IN floats.  Parameters are one flat device vector
+ * of RC_MLP_PARAMS floats: W1 [256][128] row-major, b1 [256], W2 [256][256],
+ * b2 [256], w3 [256], b3 [1].  Loss: mean over rows of the binary
+ * cross-entropy on logits, softplus(z) - y z, labels y in {0, 1}.
+ * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * counted from 1).  Feature rows are row-major [n][RC_MLP_IN] floats.
+ * All buffers are caller-owned device memory; work is asynchronous on the
+ * ctx stream; n must be >= 1; the workspace must hold
+ * rc_mlp_workspace_size(n) bytes (RC_E_INVAL otherwise).
+ */
+/*
+ * Triage features: RC_FEATURES floats per instance (programs[i], seeds[i]),
+ * written row-major to d_feat [n][RC_FEATURES].  Every value is a ratio of
+ * integers computed in fp32 (exactly reproducible).  "Memory statements" are
+ * the loads and stores in program order (statements in both branches of an
+ * if, loop bodies once); a statement's static interval is the number of
+ * barrier statements before it in that order.  An index expression is affine
+ * when it is built from integer literals, size(A), tid, unary -, + and -, and
+ * * with a constant factor, optionally under one outer mod or % by a positive
+ * constant; it then reads (a*tid + b) [mod N] (intermediate |a|,|b| <= 2^31,
+ * else not affine).  b is reduced into [0, size(A)).
+ *   [0..8)    statement counts / #statements: assign, load, store, barrier,
+ *             assume, assert, if, for
+ *   [8..12)   loads of global, loads of local, stores to global, stores to
+ *             local arrays / #statements
+ *   [12..16)  #statements/256, #global arrays/8, #local arrays/8, #scalars/16
+ *   [16..24)  /8 each, over pairs {p, q} of memory statements on one array,
+ *             at least one a store, in one static interval, p = q allowed
+ *             for a store ("self"):  self with a == 0; of those, under an if;
+ *             self not affine; p != q affine with equal a and different b;
+ *             equal a and equal b; different a; p != q with one not affine;
+ *             pairs with p or q under a loop holding a barrier (any interval)
+ *   [24..32)  stores whose value is affine with a != 0 (/16); stores whose
+ *             value is not affine (/16); deepest if nesting (/16); deepest
+ *             loop nesting (/4); memory statements under an if (/16), under a
+ *             loop (/16); distinct static intervals holding a store (/8); 0
+ *   [32..96)  memory statements k = 0..15, 4 each (zeros when absent):
+ *             store ? 1 : -1;  affine ? a/(1+|a|) : -2;  affine ? b/size : -2;
+ *             (interval+1)/8
+ *   [96..104) barriers/8, barriers under loops/8, most memory statements in
+ *             one static interval/64, sum of loop trip counts/64, memory
+ *             statements/64, stores/64, distinct arrays stored to/8, 0
+ *   [104..112) W/1024, G/1024, ceil(log2 size) of global arrays 0 and 1 /32
+ *             (0 if absent), local cells/65536, G*W/2^20, 0, 0
+ *   [112..128) for global arrays 0 and 1 (zeros if absent): counts of the
+ *             first min(size, 256) initial cells in 8 bins / 256; seeded
+ *             bindings bin floor(8 u / (hi - lo)) with u = (v - lo) mod 2^32
+ *             the draw's offset in the range, bound buffers bin
+ *             floor((v + 2^31) / 2^29)
+ * Programs must be shaped and bound; the workspace holds
+ * rc_features_workspace_size(n, number of distinct programs) bytes.
+ * Asynchronous on the ctx stream.
+ */
+#define RC_FEATURES 128
+rc_status rc_features_workspace_size(uint32_t n, uint32_t n_programs, size_t* bytes);
+rc_status rc_features(rc_ctx* ctx, rc_prog* const* programs, const uint64_t* seeds, uint32_t n, float* d_feat,
+                      void* d_ws, size_t ws_bytes);
+
+/*
+ * Visiting order of a triage sweep: d_order[k] = index of the k-th largest
+ * score (ties by ascending index; NaN ranks last).  d_order holds n uint32;
+ * the workspace holds rc_rank_workspace_size(n) bytes.  Asynchronous.
+ */
+rc_status rc_rank_workspace_size(uint32_t n, size_t* bytes);
+rc_status rc_rank(rc_ctx* ctx, const float* d_scores, uint32_t n, uint32_t* d_order, void* d_ws, size_t ws_bytes);
+
+#define RC_MLP_IN 128
+#define RC_MLP_HIDDEN 256
+#define RC_MLP_PARAMS 99073
+
+rc_status rc_mlp_workspace_size(uint32_t n, size_t* bytes);
+
+/* d_logits[i] = network(d_feat[i]) for i < n. */
+rc_status rc_mlp_forward(rc_ctx* ctx, const float* d_params, const float* d_feat, uint32_t n, float* d_logits,
+                         void* d_ws, size_t ws_bytes);
+
+/* d_grad (RC_MLP_PARAMS floats, same layout as the parameters) = gradient of
+ * the mean loss over the minibatch; *d_loss = that loss.  The minibatch is
+ * rows d_rows[0..n) of d_feat / d_labels (each < the caller's row count), or
+ * rows 0..n-1 when d_rows is NULL. */
+rc_status rc_mlp_grad(rc_ctx* ctx, const float* d_params, const float* d_feat, const float* d_labels,
+                      const uint32_t* d_rows, uint32_t n, float* d_grad, float* d_loss, void* d_ws, size_t ws_bytes);
+
+/* One Adam step on the mean loss of the minibatch (rows as rc_mlp_grad):
+ * updates d_params and the moment vectors d_adam_m, d_adam_v (RC_MLP_PARAMS
+ * floats each, zero before step 1) in place; *d_loss = the loss before the
+ * update.  step >= 1. */
+rc_status rc_mlp_train_step(rc_ctx* ctx, float* d_params, float* d_adam_m, float* d_adam_v, uint32_t step,
+                            const float* d_feat, const float* d_labels, const uint32_t* d_rows, uint32_t n, float lr,
+                            float* d_loss, void* d_ws, size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

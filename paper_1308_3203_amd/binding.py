@@ -38,7 +38,11 @@ EXPORTS = [
     "rc_bind_seeded", "rc_bind_device", "rc_bind_scalar_seeded", "rc_bind_scalar",
     "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
     "rc_ctx_profile_read", "rc_prog_set_tuning", "rc_batch_check", "rc_autotune",
+    "rc_features_workspace_size", "rc_features", "rc_mlp_workspace_size", "rc_mlp_forward", "rc_mlp_grad",
+    "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank",
 ]
+N_FEATURES = 128
+MLP_PARAMS = 99073
 PHASES = ["interpret", "log_sort", "interval_check", "record_sort", "output", "setup"]
 
 
@@ -103,6 +107,15 @@ def load_library(path: str = LIB_PATH):
         "rc_autotune": ([vp, u64, u32, vp, sz, ctypes.c_char_p, ctypes.POINTER(_Tuning)], ctypes.c_int),
         "rc_batch_check": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64), u32, vp, sz,
                             vp, u64, vp, vp], ctypes.c_int),
+        "rc_features_workspace_size": ([u32, u32, ctypes.POINTER(sz)], ctypes.c_int),
+        "rc_features": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64), u32, vp, vp, sz],
+                        ctypes.c_int),
+        "rc_mlp_workspace_size": ([u32, ctypes.POINTER(sz)], ctypes.c_int),
+        "rc_rank_workspace_size": ([u32, ctypes.POINTER(sz)], ctypes.c_int),
+        "rc_rank": ([vp, vp, u32, vp, vp, sz], ctypes.c_int),
+        "rc_mlp_forward": ([vp, vp, vp, u32, vp, vp, sz], ctypes.c_int),
+        "rc_mlp_grad": ([vp, vp, vp, vp, vp, u32, vp, vp, vp, sz], ctypes.c_int),
+        "rc_mlp_train_step": ([vp, vp, vp, vp, u32, vp, vp, vp, u32, ctypes.c_float, vp, vp, sz], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -153,6 +166,83 @@ class Context:
     def profile(self, enable: bool = True):
         _call(_lib.rc_ctx_profile, self._h, 1 if enable else 0)
 
+    # ---- triage -------------------------------------------------------------
+    @staticmethod
+    def features_workspace_size(n: int, n_programs: int) -> int:
+        out = ctypes.c_size_t()
+        _call(load_library().rc_features_workspace_size, n, n_programs, ctypes.byref(out))
+        return out.value
+
+    def features_async(self, programs, seeds, feat, ws):
+        """Triage features of instances (programs[i], seeds[i]) into the float32
+        device tensor feat [n, 128]."""
+        handles = (np.ascontiguousarray(programs, dtype=np.uint64) if isinstance(programs, np.ndarray)
+                   else handles_of(programs))
+        sarr = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+        n = int(handles.size)
+        _check_f32(feat, n * N_FEATURES, "feat")
+        _call(_lib.rc_features, self._h, handles.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p)),
+              sarr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n, ctypes.c_void_p(feat.data_ptr()),
+              ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size())
+
+    @staticmethod
+    def rank_workspace_size(n: int) -> int:
+        out = ctypes.c_size_t()
+        _call(load_library().rc_rank_workspace_size, n, ctypes.byref(out))
+        return out.value
+
+    def rank_async(self, scores, order, ws):
+        """order (int32/uint32 device tensor of n) = indices by descending score."""
+        import torch
+        n = scores.numel()
+        _check_f32(scores, n, "scores")
+        if order.numel() != n or order.dtype not in (torch.int32,) or not order.is_cuda:
+            raise ValueError("order: expected an int32 device tensor of n elements")
+        _call(_lib.rc_rank, self._h, _p(scores), n, _p(order), _p(ws), ws.numel() * ws.element_size())
+
+    @staticmethod
+    def mlp_workspace_size(n: int) -> int:
+        out = ctypes.c_size_t()
+        _call(load_library().rc_mlp_workspace_size, n, ctypes.byref(out))
+        return out.value
+
+    def mlp_forward_async(self, params, feat, logits, ws):
+        n = logits.numel()
+        _check_f32(params, MLP_PARAMS, "params")
+        _check_f32(feat, n * N_FEATURES, "feat")
+        _call(_lib.rc_mlp_forward, self._h, _p(params), _p(feat), n, _p(logits), _p(ws),
+              ws.numel() * ws.element_size())
+
+    @staticmethod
+    def _batch(feat, labels, rows):
+        """(n, rows pointer) of a minibatch: all rows, or the int32 row list."""
+        import torch
+        total = labels.numel()
+        _check_f32(labels, total, "labels")
+        _check_f32(feat, total * N_FEATURES, "feat")
+        if rows is None:
+            return total, ctypes.c_void_p(0)
+        if rows.dtype != torch.int32 or not rows.is_cuda or not rows.is_contiguous():
+            raise ValueError("rows: expected a contiguous int32 device tensor")
+        return rows.numel(), _p(rows)
+
+    def mlp_grad_async(self, params, feat, labels, grad, loss, ws, rows=None):
+        n, rp = self._batch(feat, labels, rows)
+        for t, k, name in ((params, MLP_PARAMS, "params"), (grad, MLP_PARAMS, "grad"), (loss, 1, "loss")):
+            _check_f32(t, k, name)
+        _call(_lib.rc_mlp_grad, self._h, _p(params), _p(feat), _p(labels), rp, n, _p(grad), _p(loss), _p(ws),
+              ws.numel() * ws.element_size())
+
+    def mlp_train_step_async(self, params, m, v, step: int, feat, labels, lr: float, loss, ws, rows=None):
+        """One Adam step on rows `rows` (int32 device tensor, row indices into
+        feat / labels; None: every row)."""
+        n, rp = self._batch(feat, labels, rows)
+        for t, k, name in ((params, MLP_PARAMS, "params"), (m, MLP_PARAMS, "m"), (v, MLP_PARAMS, "v"),
+                           (loss, 1, "loss")):
+            _check_f32(t, k, name)
+        _call(_lib.rc_mlp_train_step, self._h, _p(params), _p(m), _p(v), step, _p(feat), _p(labels), rp, n,
+              ctypes.c_float(lr), _p(loss), _p(ws), ws.numel() * ws.element_size())
+
     def profile_read(self) -> dict:
         """Per-phase {name: (total ms, spans)} since profiling started."""
         out = _Profile()
@@ -169,6 +259,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_f32(t, numel: int, name: str):
+    import torch
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != numel or not t.is_cuda:
+        raise ValueError(f"{name}: expected a contiguous float32 device tensor of {numel} elements")
 
 
 def handles_of(programs) -> np.ndarray:

@@ -14,12 +14,12 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librc.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["frontend.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["frontend.cpp", "capi.cpp", "kernels.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    # packed fp32 instructions stay off: the library does no float math, and
-    # this keeps hipcc from ever emitting them
+    # packed fp32 instructions stay off: hipcc must not emit them for the
+    # triage network's float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

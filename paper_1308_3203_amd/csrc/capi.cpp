@@ -15,6 +15,7 @@
 #include "../../include/rc.h"
 #include "frontend.h"
 #include "kernels.h"
+#include "mlp.h"
 #include "rc_internal.h"
 
 using namespace rc;
@@ -221,11 +222,13 @@ struct Layout {
   size_t counters = 0, queue = 0, chunk_index = 0, wg_count = 0, wg_base = 0, tiles = 0;
   size_t inst_acc = 0, inst_fault = 0, inst_int = 0, inst_race = 0, inst_benign = 0, inst_flags = 0;
   size_t lk0 = 0, lv0 = 0, lk1 = 0, lv1 = 0, hist = 0, stage = 0, rk0 = 0, ri0 = 0, rk1 = 0, ri1 = 0;
+  size_t longq = 0;
+  u64 long_cap = 0;
   size_t total = 0;
 };
 
-// counters block: [0] log entries, [1] records, [2] status word
-enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_WORDS = 8 };
+// counters block: [0] log entries, [1] records, [2] status word, [3] long runs
+enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_WORDS = 8 };
 
 void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n_items) {
   size_t o = 0;
@@ -254,6 +257,8 @@ void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n
   L->lv0 = take(L->max_log * 8);
   L->lk1 = take(L->max_log * 8);
   L->lv1 = take(L->max_log * 8);
+  L->long_cap = 2 * L->max_log / (SEG_SHORT_RUN + 1) + 2;
+  L->longq = take(L->long_cap * 16);
   L->hist = take(std::max(sort_log_hist_words(L->max_wg, L->max_log), sort_hist_words(L->max_rec)) * 4);
   L->stage = take(L->max_rec * sizeof(rc_record));
   L->rk0 = take(L->max_rec * 8);
@@ -465,6 +470,9 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     memset(&S.out, 0, sizeof S.out);
     S.out.staging = ws + L.stage; S.out.rec_keys = (u64*)(ws + L.rk0); S.out.rec_idx = (uint32_t*)(ws + L.ri0);
     S.out.rec_count = cnt + CNT_REC; S.out.rec_cap = L.max_rec; S.out.status_word = (uint32_t*)(cnt + CNT_STATUS);
+    S.longq = (u64*)(ws + L.longq);
+    S.long_count = cnt + CNT_LONG;
+    S.long_cap = L.long_cap;
     HIP_TRY(launch_seg_check(S, L.max_log, st));
   }
   HIP_TRY(launch_clamp(cnt + CNT_REC, L.max_rec, (uint32_t*)(cnt + CNT_STATUS), 2u, st));
@@ -1162,6 +1170,183 @@ rc_status rc_read_final(rc_prog* p, uint64_t seed, uint32_t array_id, int32_t* d
   M.overlay = (const u64*)((char*)d_ws + C.L.overlay);
   M.out = d_out;
   HIP_TRY(launch_final_merge(M, ctx->stream));
+  return RC_OK;
+}
+
+
+// ---- triage features -----------------------------------------------------
+static size_t feat_items_bytes(uint32_t n) { return ((size_t)n * sizeof(FeatItem) + 255) & ~(size_t)255; }
+
+rc_status rc_features_workspace_size(uint32_t n, uint32_t n_programs, size_t* bytes) {
+  if (!bytes) return fail(RC_E_INVAL, "NULL argument");
+  *bytes = feat_items_bytes(n) + (size_t)n_programs * sizeof(FeatProg);
+  return RC_OK;
+}
+
+static int64_t ceil_log2_u(uint64_t s) {
+  int64_t k = 0;
+  while (((uint64_t)1 << k) < s) ++k;
+  return k;
+}
+
+static void fill_feat_prog(const rc_prog* p, FeatProg* F) {
+  memset(F, 0, sizeof *F);
+  const Compiled& c = p->c;
+  for (int k = 0; k < 104; ++k) F->stat[k] = c.feat[k];
+  F->stat[104] = (float)p->W / 1024.f;
+  F->stat[105] = (float)p->G / 1024.f;
+  if (c.n_global > 0) F->stat[106] = (float)ceil_log2_u(c.arrays[0].size) / 32.f;
+  if (c.n_global > 1) F->stat[107] = (float)ceil_log2_u(c.arrays[1].size) / 32.f;
+  int64_t local_cells = 0;
+  for (const CompiledArray& a : c.arrays)
+    if (!a.global) local_cells += a.size;
+  F->stat[108] = (float)local_cells / 65536.f;
+  F->stat[109] = (float)((int64_t)p->G * (int64_t)p->W) / 1048576.f;
+  for (uint32_t j = 0; j < 2 && j < c.n_global; ++j) {
+    const ArrayDesc& A = p->arrays[j];
+    FeatArray& fa = F->arr[j];
+    fa.present = 1;
+    fa.bind = A.bind;
+    fa.size = A.size;
+    fa.lo = A.lo;
+    fa.hi = A.hi;
+    fa.dptr = A.dptr;
+  }
+}
+
+rc_status rc_features(rc_ctx* ctx, rc_prog* const* progs, const uint64_t* seeds, uint32_t n, float* d_feat,
+                      void* d_ws, size_t ws_bytes) {
+  if (!ctx || (n && (!progs || !seeds || !d_feat || !d_ws))) return fail(RC_E_INVAL, "NULL argument");
+  if (n == 0) return RC_OK;
+  if (n > (1u << 26)) return fail(RC_E_LIMIT, "n = %u instances exceeds 2^26", n);
+  std::map<const rc_prog*, uint32_t> index;
+  std::vector<const rc_prog*> uniq;
+  std::vector<FeatItem> items(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const rc_prog* p = progs[i];
+    if (!p) return fail(RC_E_INVAL, "programs[%u] is NULL", i);
+    if (p->ctx != ctx) return fail(RC_E_INVAL, "programs[%u] belongs to another context", i);
+    auto it = index.find(p);
+    if (it == index.end()) {
+      rc_status s = check_ready(p);
+      if (s) return s;
+      it = index.emplace(p, (uint32_t)uniq.size()).first;
+      uniq.push_back(p);
+    }
+    items[i].seed = seeds[i];
+    items[i].prog = it->second;
+    items[i].pad = 0;
+  }
+  const size_t off_progs = feat_items_bytes(n);
+  const size_t need = off_progs + uniq.size() * sizeof(FeatProg);
+  if (ws_bytes < need)
+    return fail(RC_E_INVAL, "workspace of %zu bytes is below the %zu needed for %u instances of %zu programs",
+                ws_bytes, need, n, uniq.size());
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  if (ctx->upload_done) HIP_TRY(hipEventSynchronize(ctx->upload_done));
+  ctx->h_call.assign(need, 0);
+  unsigned char* h = ctx->h_call.data();
+  memcpy(h, items.data(), items.size() * sizeof(FeatItem));
+  for (size_t k = 0; k < uniq.size(); ++k) fill_feat_prog(uniq[k], (FeatProg*)(h + off_progs) + k);
+  HIP_TRY(hipMemcpyAsync(d_ws, h, need, hipMemcpyHostToDevice, st));
+  if (!ctx->upload_done) HIP_TRY(hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ctx->upload_done, st));
+  HIP_TRY(launch_features((const FeatItem*)d_ws, (const FeatProg*)((char*)d_ws + off_progs), n, d_feat, st));
+  return RC_OK;
+}
+
+// ---- ranking -----------------------------------------------------------------
+struct RankLayout {
+  size_t k0, v0, k1, v1, hist, n_ptr, total;
+};
+static RankLayout rank_layout(uint32_t n) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  RankLayout L;
+  size_t o = 0;
+  L.k0 = o; o = up(o + (size_t)n * 8);
+  L.v0 = o; o = up(o + (size_t)n * 4);
+  L.k1 = o; o = up(o + (size_t)n * 8);
+  L.v1 = o; o = up(o + (size_t)n * 4);
+  L.hist = o; o = up(o + sort_hist_words(n ? n : 1) * 4);
+  L.n_ptr = o; o = up(o + 8);
+  L.total = o;
+  return L;
+}
+
+rc_status rc_rank_workspace_size(uint32_t n, size_t* bytes) {
+  if (!bytes) return fail(RC_E_INVAL, "NULL argument");
+  *bytes = rank_layout(n).total;
+  return RC_OK;
+}
+
+rc_status rc_rank(rc_ctx* ctx, const float* d_scores, uint32_t n, uint32_t* d_order, void* d_ws, size_t ws_bytes) {
+  if (!ctx || (n && (!d_scores || !d_order || !d_ws))) return fail(RC_E_INVAL, "NULL argument");
+  if (n == 0) return RC_OK;
+  const RankLayout L = rank_layout(n);
+  if (ws_bytes < L.total) return fail(RC_E_INVAL, "workspace of %zu bytes is below the %zu needed", ws_bytes, L.total);
+  HIP_TRY(hipSetDevice(ctx->device));
+  char* ws = (char*)d_ws;
+  hipStream_t st = ctx->stream;
+  uint32_t idx_bits = 0;
+  while (idx_bits < 32 && ((u64)1 << idx_bits) < (u64)n) ++idx_bits;
+  HIP_TRY(launch_rank_keys(d_scores, n, idx_bits, (u64*)(ws + L.k0), (uint32_t*)(ws + L.v0), (u64*)(ws + L.n_ptr),
+                           st));
+  int in_second = 0;
+  HIP_TRY(sort_pairs_u32((u64*)(ws + L.k0), (uint32_t*)(ws + L.v0), (u64*)(ws + L.k1), (uint32_t*)(ws + L.v1),
+                         (const u64*)(ws + L.n_ptr), n, 32 + idx_bits, (uint32_t*)(ws + L.hist), st, &in_second));
+  HIP_TRY(hipMemcpyAsync(d_order, ws + (in_second ? L.v1 : L.v0), (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+  return RC_OK;
+}
+
+// ---- triage network ------------------------------------------------------
+rc_status rc_mlp_workspace_size(uint32_t n, size_t* bytes) {
+  if (!bytes) return fail(RC_E_INVAL, "NULL argument");
+  *bytes = mlp_ws_bytes(n);
+  return RC_OK;
+}
+
+static rc_status mlp_args(rc_ctx* ctx, uint32_t n, const void* ws, size_t ws_bytes) {
+  if (!ctx || !ws) return fail(RC_E_INVAL, "NULL argument");
+  if (n == 0) return fail(RC_E_INVAL, "n must be at least 1");
+  if (n > (1u << 26)) return fail(RC_E_LIMIT, "n = %u rows exceeds 2^26", n);
+  if (ws_bytes < mlp_ws_bytes(n))
+    return fail(RC_E_INVAL, "workspace of %zu bytes is below the %zu needed for %u rows", ws_bytes, mlp_ws_bytes(n),
+                n);
+  return RC_OK;
+}
+
+rc_status rc_mlp_forward(rc_ctx* ctx, const float* d_params, const float* d_feat, uint32_t n, float* d_logits,
+                         void* d_ws, size_t ws_bytes) {
+  rc_status s = mlp_args(ctx, n, d_ws, ws_bytes);
+  if (s) return s;
+  if (!d_params || !d_feat || !d_logits) return fail(RC_E_INVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(mlp_forward(d_params, d_feat, n, d_logits, d_ws, ctx->stream));
+  return RC_OK;
+}
+
+rc_status rc_mlp_grad(rc_ctx* ctx, const float* d_params, const float* d_feat, const float* d_labels,
+                      const uint32_t* d_rows, uint32_t n, float* d_grad, float* d_loss, void* d_ws, size_t ws_bytes) {
+  rc_status s = mlp_args(ctx, n, d_ws, ws_bytes);
+  if (s) return s;
+  if (!d_params || !d_feat || !d_labels || !d_grad || !d_loss) return fail(RC_E_INVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(mlp_grad(d_params, d_feat, d_labels, d_rows, n, d_grad, d_loss, d_ws, ctx->stream));
+  return RC_OK;
+}
+
+rc_status rc_mlp_train_step(rc_ctx* ctx, float* d_params, float* d_adam_m, float* d_adam_v, uint32_t step,
+                            const float* d_feat, const float* d_labels, const uint32_t* d_rows, uint32_t n, float lr,
+                            float* d_loss, void* d_ws, size_t ws_bytes) {
+  rc_status s = mlp_args(ctx, n, d_ws, ws_bytes);
+  if (s) return s;
+  if (!d_params || !d_adam_m || !d_adam_v || !d_feat || !d_labels || !d_loss) return fail(RC_E_INVAL, "NULL argument");
+  if (step == 0) return fail(RC_E_INVAL, "Adam steps count from 1");
+  if (!(lr > 0.f) || !(lr < 1e30f)) return fail(RC_E_INVAL, "learning rate must be positive and finite");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(mlp_train_step(d_params, d_adam_m, d_adam_v, step, d_feat, d_labels, d_rows, n, lr, d_loss, d_ws,
+                         ctx->stream));
   return RC_OK;
 }
 

@@ -685,6 +685,220 @@ IntervalBound interval_block(const std::vector<Statement>& body, IntervalBound i
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// static triage features (layout documented with rc_features in rc.h)
+// ---------------------------------------------------------------------------
+struct Affine {          // index = (a * tid + b) [mod N]
+  bool ok = false, has_mod = false;
+  int64_t a = 0, b = 0, N = 0;
+};
+
+Affine affine_of(const Node& e) {
+  Affine r;
+  const int64_t lim = (int64_t)1 << 31;
+  auto in_range = [&](Affine x) {
+    if (x.a > lim || x.a < -lim || x.b > lim || x.b < -lim) x.ok = false;
+    return x;
+  };
+  switch (e.kind) {
+    case Node::NUM: r.ok = true; r.b = e.value; return r;
+    case Node::SPECIAL: if ((uint32_t)e.value == SEL_TID) { r.ok = true; r.a = 1; } return r;
+    case Node::UNARY: {
+      if (e.op != U_NEG) return r;
+      Affine x = affine_of(*e.l);
+      if (!x.ok || x.has_mod) return r;
+      x.a = -x.a; x.b = -x.b;
+      return in_range(x);
+    }
+    case Node::BINARY: {
+      Affine x = affine_of(*e.l), y = affine_of(*e.r);
+      if (!x.ok || !y.ok || x.has_mod || y.has_mod) return r;
+      switch (e.op) {
+        case B_ADD: r.ok = true; r.a = x.a + y.a; r.b = x.b + y.b; return in_range(r);
+        case B_SUB: r.ok = true; r.a = x.a - y.a; r.b = x.b - y.b; return in_range(r);
+        case B_MUL:
+          if (x.a != 0 && y.a != 0) return r;
+          r.ok = true;
+          if (x.a == 0) { r.a = x.b * y.a; r.b = x.b * y.b; }
+          else { r.a = x.a * y.b; r.b = x.b * y.b; }
+          return in_range(r);
+        case B_MOD:
+        case B_REM:
+          if (y.a != 0 || y.b <= 0) return r;
+          x.has_mod = true; x.N = y.b;
+          return x;
+        default: return r;
+      }
+    }
+    default: return r;
+  }
+}
+
+struct MemStmt {
+  bool store;
+  int arr;
+  Affine idx;
+  int64_t ivl;
+  bool in_if, in_loop, in_barrier_loop;
+};
+
+struct FeatWalk {
+  const Compiled* c;
+  int64_t counts[8] = {};        // assign, load, store, barrier, assume, assert, if, for
+  int64_t ld_g = 0, ld_l = 0, st_g = 0, st_l = 0, n = 0;
+  int64_t ivl = 0, mem_in_ivl = 0, max_mem_in_ivl = 0, barriers_in_loops = 0, trip_sum = 0;
+  int64_t val_tid = 0, val_other = 0, if_depth = 0, max_if_depth = 0, loop_depth = 0, max_loop_depth = 0;
+  int64_t mem_in_if = 0, mem_in_loop = 0, barrier_loop_depth = 0;
+  std::vector<MemStmt> mem;
+
+  void walk(const std::vector<Statement>& body) {
+    for (const Statement& s : body) {
+      ++n;
+      counts[(int)s.kind] += 1;
+      switch (s.kind) {
+        case Statement::LOAD:
+        case Statement::STORE: {
+          const bool st = s.kind == Statement::STORE;
+          const bool g = c->arrays[s.arr].global;
+          if (st) (g ? st_g : st_l) += 1; else (g ? ld_g : ld_l) += 1;
+          MemStmt m;
+          m.store = st;
+          m.arr = s.arr;
+          m.idx = affine_of(*s.e1);
+          m.ivl = ivl;
+          m.in_if = if_depth > 0;
+          m.in_loop = loop_depth > 0;
+          m.in_barrier_loop = barrier_loop_depth > 0;
+          mem.push_back(m);
+          if (m.in_if) ++mem_in_if;
+          if (m.in_loop) ++mem_in_loop;
+          ++mem_in_ivl;
+          if (st) {
+            Affine v = affine_of(*s.e2);
+            if (!v.ok) ++val_other;
+            else if (v.a != 0) ++val_tid;
+          }
+          break;
+        }
+        case Statement::BARRIER:
+          if (loop_depth > 0) ++barriers_in_loops;
+          max_mem_in_ivl = std::max(max_mem_in_ivl, mem_in_ivl);
+          mem_in_ivl = 0;
+          ++ivl;
+          break;
+        case Statement::IF:
+          ++if_depth;
+          max_if_depth = std::max(max_if_depth, if_depth);
+          walk(s.then_body);
+          walk(s.else_body);
+          --if_depth;
+          break;
+        case Statement::FOR: {
+          trip_sum += s.hi > s.lo ? s.hi - s.lo : 0;
+          const bool bl = has_barrier(s.then_body);
+          ++loop_depth;
+          max_loop_depth = std::max(max_loop_depth, loop_depth);
+          if (bl) ++barrier_loop_depth;
+          walk(s.then_body);
+          if (bl) --barrier_loop_depth;
+          --loop_depth;
+          break;
+        }
+        default:
+          break;
+      }
+    }
+  }
+};
+
+float ratio(int64_t num, int64_t den) { return (float)num / (float)den; }
+
+int64_t emod(int64_t x, int64_t m) { return ((x % m) + m) % m; }
+
+void static_features(const std::vector<Statement>& body, const Compiled& c, float* f) {
+  FeatWalk w;
+  w.c = &c;
+  w.walk(body);
+  w.max_mem_in_ivl = std::max(w.max_mem_in_ivl, w.mem_in_ivl);
+  const int64_t n = std::max<int64_t>(w.n, 1);
+  for (int k = 0; k < 8; ++k) f[k] = ratio(w.counts[k], n);
+  f[8] = ratio(w.ld_g, n);
+  f[9] = ratio(w.ld_l, n);
+  f[10] = ratio(w.st_g, n);
+  f[11] = ratio(w.st_l, n);
+  f[12] = ratio(w.n, 256);
+  f[13] = ratio(c.n_global, 8);
+  f[14] = ratio(c.n_local, 8);
+  f[15] = ratio((int64_t)c.scalars.size(), 16);
+  // pairs of memory statements that may touch one cell from two work-items
+  int64_t pc[8] = {};
+  const size_t M = w.mem.size();
+  for (size_t p = 0; p < M; ++p) {
+    for (size_t q = p; q < M; ++q) {
+      const MemStmt& x = w.mem[p];
+      const MemStmt& y = w.mem[q];
+      if (x.arr != y.arr || !(x.store || y.store)) continue;
+      if (p == q && !x.store) continue;
+      if (x.in_barrier_loop || y.in_barrier_loop) { ++pc[7]; continue; }
+      if (x.ivl != y.ivl) continue;
+      if (p == q) {
+        if (!x.idx.ok) ++pc[2];
+        else if (x.idx.a == 0) { ++pc[0]; if (x.in_if) ++pc[1]; }
+        continue;
+      }
+      if (!x.idx.ok || !y.idx.ok) { ++pc[6]; continue; }
+      if (x.idx.a != y.idx.a) { ++pc[5]; continue; }
+      const int64_t S = c.arrays[x.arr].size;
+      if (emod(x.idx.b, S) != emod(y.idx.b, S)) ++pc[3]; else ++pc[4];
+    }
+  }
+  for (int k = 0; k < 8; ++k) f[16 + k] = ratio(pc[k], 8);
+  f[24] = ratio(w.val_tid, 16);
+  f[25] = ratio(w.val_other, 16);
+  f[26] = ratio(w.max_if_depth, 16);
+  f[27] = ratio(w.max_loop_depth, 4);
+  f[28] = ratio(w.mem_in_if, 16);
+  f[29] = ratio(w.mem_in_loop, 16);
+  {
+    std::vector<int64_t> ivls;
+    std::vector<int> stored;
+    for (const MemStmt& m : w.mem) {
+      if (!m.store) continue;
+      if (std::find(ivls.begin(), ivls.end(), m.ivl) == ivls.end()) ivls.push_back(m.ivl);
+    }
+    f[30] = ratio((int64_t)ivls.size(), 8);
+  }
+  f[31] = 0.f;
+  for (size_t k = 0; k < 16; ++k) {
+    float* s = f + 32 + 4 * k;
+    if (k >= M) { s[0] = s[1] = s[2] = s[3] = 0.f; continue; }
+    const MemStmt& m = w.mem[k];
+    s[0] = m.store ? 1.f : -1.f;
+    if (m.idx.ok) {
+      const int64_t S = c.arrays[m.arr].size;
+      s[1] = (float)m.idx.a / (float)(1 + (m.idx.a < 0 ? -m.idx.a : m.idx.a));
+      s[2] = ratio(emod(m.idx.b, S), S);
+    } else {
+      s[1] = -2.f;
+      s[2] = -2.f;
+    }
+    s[3] = ratio(m.ivl + 1, 8);
+  }
+  f[96] = ratio(w.counts[Statement::BARRIER], 8);
+  f[97] = ratio(w.barriers_in_loops, 8);
+  f[98] = ratio(w.max_mem_in_ivl, 64);
+  f[99] = ratio(w.trip_sum, 64);
+  f[100] = ratio((int64_t)M, 64);
+  f[101] = ratio(w.counts[Statement::STORE], 64);
+  {
+    std::vector<int> arrs;
+    for (const MemStmt& m : w.mem)
+      if (m.store && std::find(arrs.begin(), arrs.end(), m.arr) == arrs.end()) arrs.push_back(m.arr);
+    f[102] = ratio((int64_t)arrs.size(), 8);
+  }
+  f[103] = 0.f;
+}
+
 }  // namespace
 
 bool compile_program(const char* src, size_t len, Compiled* out, std::string* err, bool* is_limit) {
@@ -713,6 +927,7 @@ bool compile_program(const char* src, size_t len, Compiled* out, std::string* er
       out->interval_logged_local = std::max(lo.worst, lo.open);
       out->interval_logged_all = std::max(al.worst, al.open);
     }
+    static_features(body, *out, out->feat);
     Lowering low(out);
     low.run(body);
     return true;

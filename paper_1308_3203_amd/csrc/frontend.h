@@ -31,6 +31,9 @@ struct Compiled {
   // largest interval (accesses per work-item between two barriers) on
   // written local arrays / on all written arrays
   double interval_logged_local = 0, interval_logged_all = 0;
+  // triage features 0..103: statement mix, affine index analysis, barrier
+  // structure (independent of the launch shape and the bindings)
+  float feat[104] = {};
 };
 
 // Returns true on success; on failure `err` holds "line:col: message" and

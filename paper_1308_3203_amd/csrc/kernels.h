@@ -29,7 +29,13 @@ struct SegParams {
   const ChunkDesc* chunks;
   const uint32_t* chunk_index;
   rc_record_out out;
+  unsigned long long* longq;        // queued long runs: (start, end | inter << 63)
+  unsigned long long* long_count;   // zero at chunk start
+  unsigned long long long_cap;      // queue capacity in runs
 };
+// runs longer than this go to the queue; the queue needs at most
+// 2 * entries / (SEG_SHORT_RUN + 1) + 2 slots
+constexpr unsigned long long SEG_SHORT_RUN = 64;
 
 struct GatherParams {
   const rc_record_dev* staging;
@@ -114,6 +120,9 @@ hipError_t launch_region_tiles(const uint32_t* counts, uint32_t* tiles, unsigned
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStream_t st);
 hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st);
+hipError_t launch_rank_keys(const float* scores, uint32_t n, uint32_t idx_bits, unsigned long long* keys,
+                            uint32_t* vals, unsigned long long* n_ptr, hipStream_t st);
+hipError_t launch_features(const FeatItem* items, const FeatProg* progs, uint32_t n, float* out, hipStream_t st);
 hipError_t launch_clamp(unsigned long long* n_ptr, unsigned long long cap, uint32_t* status, uint32_t bit,
                         hipStream_t st);
 

@@ -126,54 +126,122 @@ __device__ __forceinline__ uint32_t pay_lid(u64 p) { return (uint32_t)p & 1023u;
 __device__ __forceinline__ bool pay_w(u64 p) { return ((uint32_t)p >> 10) & 1u; }
 __device__ __forceinline__ int32_t pay_val(u64 p) { return (int32_t)(uint32_t)(p >> 32); }
 
+// Both scopes are decided by two passes over a cell's accesses: the first
+// finds the smallest reader and the smallest writer (with its smallest
+// value), the second finds the partners those need.  Every quantity is a
+// minimum or an OR, so a pass can be split over lanes and merged.
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+
+struct Pass1 {            // r1: smallest reader; wmin: (writer id, value ^ sign) minimum
+  uint32_t r1;
+  u64 wmin;
+};
+__device__ __forceinline__ Pass1 pass1_init() { return Pass1{NONE32, ~0ull}; }
+__device__ __forceinline__ void pass1_add(Pass1& a, uint32_t id, bool w, int32_t v) {
+  if (w) {
+    const u64 kx = ((u64)id << 32) | ((uint32_t)v ^ 0x80000000u);
+    if (kx < a.wmin) a.wmin = kx;
+  } else if (id < a.r1) {
+    a.r1 = id;
+  }
+}
+
+// INTRA (ids are lids of one group): partners of r1 / w1
+struct Intra2 {
+  uint32_t r2, w2, q, multi1;
+};
+__device__ __forceinline__ Intra2 intra2_init() { return Intra2{NONE32, NONE32, NONE32, 0u}; }
+__device__ __forceinline__ void intra2_add(Intra2& a, uint32_t l, bool w, int32_t v, uint32_t r1, uint32_t w1,
+                                           int32_t x1) {
+  if (w) {
+    if (l == w1) { if (v != x1) a.multi1 = 1u; }
+    else {
+      if (l < a.w2) a.w2 = l;
+      if (v != x1 && l < a.q) a.q = l;
+    }
+  } else if (l != r1 && l < a.r2) {
+    a.r2 = l;
+  }
+}
+__device__ bool intra_finish(const Pass1& p1, const Intra2& p2, uint32_t* label, Pair* rw, Pair* ww) {
+  const uint32_t r1 = p1.r1, w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
+  Pair brw = {NONE32, NONE32}, bww = {NONE32, NONE32};
+  const uint32_t rs[2] = {r1, p2.r2}, ws[2] = {w1, p2.w2};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (rs[i] != NONE32 && ws[j] != NONE32 && rs[i] != ws[j]) pair_take(brw, rs[i], ws[j]);
+  bool wwd = false;
+  if (p2.multi1 && p2.w2 != NONE32) { bww = {w1, p2.w2}; wwd = true; }
+  else if (p2.q != NONE32) { bww = {w1, p2.q}; wwd = true; }
+  uint32_t lab = (brw.a != NONE32 ? 1u : 0u) | (wwd ? 2u : 0u);
+  if (lab == 0u) {
+    if (p2.w2 == NONE32) return false;   // no eligible pair
+    lab = 4u;
+    bww = {w1, p2.w2};
+  }
+  *label = lab;
+  *rw = brw;
+  *ww = bww;
+  return true;
+}
+
 // INTRA scope over entries [s, e) of one work-group (ids compared by lid);
 // get(i) returns entry i's payload: value << 32 | is_write << 10 | lid.
 template <typename Get>
 __device__ bool intra_check(Get get, u64 s, u64 e, uint32_t* label, Pair* rw, Pair* ww) {
-  const uint32_t NONE = 0xFFFFFFFFu;
-  uint32_t r1 = NONE;
-  u64 wmin = ~0ull;  // (lid, value ^ sign) of the smallest writer
+  Pass1 p1 = pass1_init();
   for (u64 i = s; i < e; ++i) {
     const u64 p = get(i);
-    const uint32_t l = pay_lid(p);
-    if (pay_w(p)) {
-      const u64 kx = ((u64)l << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
-      if (kx < wmin) wmin = kx;
-    } else if (l < r1) {
-      r1 = l;
-    }
+    pass1_add(p1, pay_lid(p), pay_w(p), pay_val(p));
   }
-  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
-  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
-  uint32_t r2 = NONE, w2 = NONE, q = NONE;
-  bool multi1 = false;
+  const uint32_t w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)p1.wmin ^ 0x80000000u);
+  Intra2 p2 = intra2_init();
   for (u64 i = s; i < e; ++i) {
     const u64 p = get(i);
-    const uint32_t l = pay_lid(p);
-    if (pay_w(p)) {
-      const int32_t v = pay_val(p);
-      if (l == w1) { if (v != x1) multi1 = true; }
-      else {
-        if (l < w2) w2 = l;
-        if (v != x1 && l < q) q = l;
-      }
-    } else if (l != r1 && l < r2) {
-      r2 = l;
-    }
+    intra2_add(p2, pay_lid(p), pay_w(p), pay_val(p), p1.r1, w1, x1);
   }
-  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
-  const uint32_t rs[2] = {r1, r2}, ws[2] = {w1, w2};
+  return intra_finish(p1, p2, label, rw, ww);
+}
+
+// INTER (ids are global tids; pairs must come from different groups)
+struct Inter2 {
+  uint32_t r1p, w1p, q, A, multi1;
+};
+__device__ __forceinline__ Inter2 inter2_init() { return Inter2{NONE32, NONE32, NONE32, NONE32, 0u}; }
+__device__ __forceinline__ void inter2_add(Inter2& a, uint32_t t, uint32_t g, bool w, int32_t v, uint32_t gr1,
+                                           uint32_t w1, uint32_t g1, int32_t x1) {
+  if (w) {
+    if (t == w1) { if (v != x1) a.multi1 = 1u; }
+    if (g != g1) {
+      if (t < a.w1p) a.w1p = t;
+      if (v != x1 && t < a.q) a.q = t;
+    } else if (t != w1 && v != x1 && t < a.A) {
+      a.A = t;
+    }
+  } else if (g != gr1 && t < a.r1p) {
+    a.r1p = t;
+  }
+}
+__device__ bool inter_finish(const Pass1& p1, const Inter2& p2, uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
+  const uint32_t r1 = p1.r1, w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
+  Pair brw = {NONE32, NONE32}, bww = {NONE32, NONE32};
+  const uint32_t rs[2] = {r1, p2.r1p}, ws[2] = {w1, p2.w1p};
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
-      if (rs[i] != NONE && ws[j] != NONE && rs[i] != ws[j]) pair_take(brw, rs[i], ws[j]);
+      if (rs[i] != NONE32 && ws[j] != NONE32 && rs[i] / W != ws[j] / W) pair_take(brw, rs[i], ws[j]);
   bool wwd = false;
-  if (multi1 && w2 != NONE) { bww = {w1, w2}; wwd = true; }
-  else if (q != NONE) { bww = {w1, q}; wwd = true; }
-  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
+  if (p2.multi1 && p2.w1p != NONE32) { bww = {w1, p2.w1p}; wwd = true; }
+  else if (p2.q != NONE32) { bww = {w1, p2.q}; wwd = true; }
+  else if (p2.A != NONE32 && p2.w1p != NONE32) {
+    bww = {p2.A < p2.w1p ? p2.A : p2.w1p, p2.A < p2.w1p ? p2.w1p : p2.A};
+    wwd = true;
+  }
+  uint32_t lab = (brw.a != NONE32 ? 1u : 0u) | (wwd ? 2u : 0u);
   if (lab == 0u) {
-    if (w2 == NONE) return false;   // no eligible pair
+    if (p2.w1p == NONE32) return false;
     lab = 4u;
-    bww = {w1, w2};
+    bww = {w1, p2.w1p};
   }
   *label = lab;
   *rw = brw;
@@ -184,62 +252,23 @@ __device__ bool intra_check(Get get, u64 s, u64 e, uint32_t* label, Pair* rw, Pa
 // INTER scope over records [s, e) of one cell, all groups (global tids).
 __device__ bool inter_check(const u64* keys, const u64* vals, u64 s, u64 e, uint32_t bk, uint32_t gmask,
                             uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
-  const uint32_t NONE = 0xFFFFFFFFu;
-  uint32_t r1 = NONE;
-  u64 wmin = ~0ull;
+  Pass1 p1 = pass1_init();
   for (u64 i = s; i < e; ++i) {
     const u64 p = vals[i];
     const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
-    const uint32_t t = g * W + pay_lid(p);
-    if (pay_w(p)) {
-      const u64 kx = ((u64)t << 32) | ((uint32_t)pay_val(p) ^ 0x80000000u);
-      if (kx < wmin) wmin = kx;
-    } else if (t < r1) {
-      r1 = t;
-    }
+    pass1_add(p1, g * W + pay_lid(p), pay_w(p), pay_val(p));
   }
-  const uint32_t w1 = wmin == ~0ull ? NONE : (uint32_t)(wmin >> 32);
-  const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
-  const uint32_t gr1 = r1 == NONE ? NONE : r1 / W;
-  const uint32_t g1 = w1 == NONE ? NONE : w1 / W;
-  uint32_t r1p = NONE, w1p = NONE, q = NONE, A = NONE;
-  bool multi1 = false;
+  const uint32_t w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)p1.wmin ^ 0x80000000u);
+  const uint32_t gr1 = p1.r1 == NONE32 ? NONE32 : p1.r1 / W;
+  const uint32_t g1 = w1 == NONE32 ? NONE32 : w1 / W;
+  Inter2 p2 = inter2_init();
   for (u64 i = s; i < e; ++i) {
     const u64 p = vals[i];
     const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
-    const uint32_t t = g * W + pay_lid(p);
-    if (pay_w(p)) {
-      const int32_t v = pay_val(p);
-      if (t == w1) { if (v != x1) multi1 = true; }
-      if (g != g1) {
-        if (t < w1p) w1p = t;
-        if (v != x1 && t < q) q = t;
-      } else if (t != w1 && v != x1 && t < A) {
-        A = t;
-      }
-    } else if (g != gr1 && t < r1p) {
-      r1p = t;
-    }
+    inter2_add(p2, g * W + pay_lid(p), g, pay_w(p), pay_val(p), gr1, w1, g1, x1);
   }
-  Pair brw = {NONE, NONE}, bww = {NONE, NONE};
-  const uint32_t rs[2] = {r1, r1p}, ws[2] = {w1, w1p};
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      if (rs[i] != NONE && ws[j] != NONE && rs[i] / W != ws[j] / W) pair_take(brw, rs[i], ws[j]);
-  bool wwd = false;
-  if (multi1 && w1p != NONE) { bww = {w1, w1p}; wwd = true; }
-  else if (q != NONE) { bww = {w1, q}; wwd = true; }
-  else if (A != NONE && w1p != NONE) { bww = {A < w1p ? A : w1p, A < w1p ? w1p : A}; wwd = true; }
-  uint32_t lab = (brw.a != NONE ? 1u : 0u) | (wwd ? 2u : 0u);
-  if (lab == 0u) {
-    if (w1p == NONE) return false;
-    lab = 4u;
-    bww = {w1, w1p};
-  }
-  *label = lab;
-  *rw = brw;
-  *ww = bww;
-  return true;
+  return inter_finish(p1, p2, W, label, rw, ww);
 }
 
 struct PendingRec {
@@ -861,63 +890,201 @@ __global__ __launch_bounds__(256) void sum_u32_kernel(const uint32_t* v, u64 n, 
 // One thread per sorted log entry.  The first entry of a run of equal keys
 // checks its INTRA(gid, interval) scope; the first entry of a cell's run
 // also checks the INTER scope (global arrays, several groups).
+// A run of the sorted log is the entries sharing a key prefix: the full key
+// for an INTRA run (instance, cell, group, interval), the key above the group
+// and interval fields for an INTER run (instance, cell).  A run of at most
+// SEG_SHORT entries is checked by the thread at its head; a longer one is
+// queued and checked by a whole workgroup (seg_long_kernel), so a hot cell
+// never serialises a wave.
+constexpr u64 SEG_SHORT = SEG_SHORT_RUN;
+
+// first index after i whose key differs from keys[i] above `shift` bits
+// (galloping then bisection: O(log run length) reads)
+__device__ __forceinline__ u64 run_end(const u64* keys, u64 i, u64 n, uint32_t shift) {
+  const u64 kk = keys[i] >> shift;
+  u64 lo = i, hi = n, step = 1;
+  while (true) {
+    const u64 probe = i + step;
+    if (probe >= n) { hi = n; break; }
+    if ((keys[probe] >> shift) != kk) { hi = probe; break; }
+    lo = probe;
+    step <<= 1;
+  }
+  while (hi - lo > 1) {
+    const u64 mid = lo + (hi - lo) / 2;
+    if ((keys[mid] >> shift) == kk) lo = mid; else hi = mid;
+  }
+  return hi;
+}
+
+struct SegHead {          // what a run's first key says about it
+  uint32_t slot, instance, gid, interval, aid, cell, cellkey, G, W, NI, n_global;
+};
+__device__ __forceinline__ SegHead seg_head(const SegParams& S, u64 k) {
+  SegHead h;
+  const uint32_t low = S.bg + S.bk;
+  const uint32_t cmask = S.bc >= 32 ? 0xFFFFFFFFu : ((1u << S.bc) - 1u);
+  h.cellkey = (uint32_t)(k >> low) & cmask;
+  h.slot = (uint32_t)(k >> (low + S.bc));
+  h.gid = (uint32_t)(k >> S.bk) & ((1u << S.bg) - 1u);
+  h.interval = (uint32_t)k & ((1u << S.bk) - 1u);
+  const ChunkDesc C = S.chunks[*S.chunk_index];
+  h.instance = C.slot0 + h.slot;
+  const ProgDesc& D = S.progs[S.slots[h.instance].prog];
+  h.G = D.G;
+  h.W = D.W;
+  h.NI = D.NI;
+  h.n_global = D.n_global;
+  uint32_t aid = 0;
+  for (uint32_t a = 0; a < D.n_arrays; ++a) {
+    const uint32_t cb = D.cellbase[a];
+    if (cb != 0xFFFFFFFFu && h.cellkey >= cb && h.cellkey - cb < D.size[a]) aid = a;
+  }
+  h.aid = aid;
+  h.cell = h.cellkey - D.cellbase[aid];
+  return h;
+}
+
+__device__ __forceinline__ void push_long(const SegParams& S, u64 s, u64 e, bool inter) {
+  const u64 q = atomicAdd(S.long_count, 1ull);
+  if (q < S.long_cap) {
+    S.longq[2 * q] = s;
+    S.longq[2 * q + 1] = e | ((u64)(inter ? 1u : 0u) << 63);
+  }
+}
+
 __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
   const u64 n = *S.n_ptr;
-  const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
-  bool has_intra = false, has_inter = false;
-  uint32_t slot = 0, instance = 0;
-  RecKey K = {S.bs, S.bc, 1u, 1u};
-  PendingRec pa, pb;
-  if (i < n) {
-    const u64 k = S.keys[i];
-    const uint32_t low = S.bg + S.bk;
-    const bool sub_head = i == 0 || S.keys[i - 1] != k;
-    if (sub_head) {
-      const bool seg_head = i == 0 || (S.keys[i - 1] >> low) != (k >> low);
-      const uint32_t cmask = S.bc >= 32 ? 0xFFFFFFFFu : ((1u << S.bc) - 1u);
-      const uint32_t gmask = (1u << S.bg) - 1u, imask = (1u << S.bk) - 1u;
-      const uint32_t cellkey = (uint32_t)(k >> low) & cmask;
-      slot = (uint32_t)(k >> (low + S.bc));
-      const uint32_t gid = (uint32_t)(k >> S.bk) & gmask;
-      const uint32_t interval = (uint32_t)k & imask;
-      const ChunkDesc C = S.chunks[*S.chunk_index];
-      instance = C.slot0 + slot;
-      const ProgDesc D = S.progs[S.slots[instance].prog];
-      K.G = D.G;
-      K.NI = D.NI;
-      uint32_t aid = 0;
-      for (uint32_t a = 0; a < D.n_arrays; ++a) {
-        const uint32_t cb = D.cellbase[a];
-        if (cb != 0xFFFFFFFFu && cellkey >= cb && cellkey - cb < D.size[a]) aid = a;
-      }
-      const uint32_t cell = cellkey - D.cellbase[aid];
-      u64 e = i + 1;
-      while (e < n && S.keys[e] == k) ++e;
-      if (e - i >= 2) {
-        const u64* vals = S.vals;
-        has_intra = intra_check([vals](u64 j) { return vals[j]; }, i, e, &pa.label, &pa.rw, &pa.ww);
-        pa.gid = gid; pa.interval = interval; pa.aid = aid; pa.cell = cell; pa.cellkey = cellkey;
-        pa.lidbase = gid * D.W;
-      }
-      if (seg_head && D.G > 1 && aid < D.n_global) {
-        u64 f = e;
-        while (f < n && (S.keys[f] >> low) == (k >> low)) ++f;
-        if (f - i >= 2) {
-          has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, D.W, &pb.label, &pb.rw, &pb.ww);
-          pb.gid = gid; pb.interval = 0; pb.aid = aid; pb.cell = cell; pb.cellkey = cellkey;
-          pb.lidbase = 0;
+  const uint32_t low = S.bg + S.bk;
+  const uint32_t gmask = (1u << S.bg) - 1u;
+  // block-uniform rounds, so the whole wave reaches the ballots below
+  for (u64 base = (u64)blockIdx.x * blockDim.x; base < n; base += (u64)gridDim.x * blockDim.x) {
+    const u64 i = base + threadIdx.x;
+    bool has_intra = false, has_inter = false;
+    SegHead H;
+    PendingRec pa, pb;
+    if (i < n) {
+      const u64 k = S.keys[i];
+      const bool sub_head = i == 0 || S.keys[i - 1] != k;
+      if (sub_head) {
+        const bool head = i == 0 || (S.keys[i - 1] >> low) != (k >> low);
+        H = seg_head(S, k);
+        const u64 e = run_end(S.keys, i, n, 0);
+        if (e - i >= 2) {
+          if (e - i <= SEG_SHORT) {
+            const u64* vals = S.vals;
+            has_intra = intra_check([vals](u64 j) { return vals[j]; }, i, e, &pa.label, &pa.rw, &pa.ww);
+            pa.gid = H.gid; pa.interval = H.interval; pa.aid = H.aid; pa.cell = H.cell; pa.cellkey = H.cellkey;
+            pa.lidbase = H.gid * H.W;
+          } else {
+            push_long(S, i, e, false);
+          }
+        }
+        if (head && H.G > 1 && H.aid < H.n_global) {
+          const u64 f = run_end(S.keys, i, n, low);
+          if (f - i >= 2) {
+            if (f - i <= SEG_SHORT) {
+              has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, H.W, &pb.label, &pb.rw, &pb.ww);
+              pb.gid = H.gid; pb.interval = 0; pb.aid = H.aid; pb.cell = H.cell; pb.cellkey = H.cellkey;
+              pb.lidbase = 0;
+            } else {
+              push_long(S, i, f, true);
+            }
+          }
         }
       }
     }
+    const u64 m1 = __ballot(has_intra), m2 = __ballot(has_inter);
+    const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
+    if (c1 + c2 == 0) continue;
+    const u64 rbase = wave_reserve(S.out.rec_count, c1 + c2, lane);
+    const u64 below = (1ull << lane) - 1ull;
+    RecKey K = {S.bs, S.bc, has_intra || has_inter ? H.G : 1u, has_intra || has_inter ? H.NI : 1u};
+    if (has_intra) store_record(S.out, K, rbase + (u64)__popcll(m1 & below), H.slot, H.instance, pa, false);
+    if (has_inter) store_record(S.out, K, rbase + c1 + (u64)__popcll(m2 & below), H.slot, H.instance, pb, true);
   }
-  const u64 m1 = __ballot(has_intra), m2 = __ballot(has_inter);
-  const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
-  if (c1 + c2 == 0) return;
-  const u64 base = wave_reserve(S.out.rec_count, c1 + c2, lane);
-  const u64 below = (1ull << lane) - 1ull;
-  if (has_intra) store_record(S.out, K, base + (u64)__popcll(m1 & below), slot, instance, pa, false);
-  if (has_inter) store_record(S.out, K, base + c1 + (u64)__popcll(m2 & below), slot, instance, pb, true);
+}
+
+// minimum over the workgroup (256 lanes, 4 waves); sh holds 4 words
+__device__ __forceinline__ u64 block_min_u64(u64 v, u64* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, off), hi = __shfl_xor((uint32_t)(v >> 32), off);
+    const u64 o = ((u64)hi << 32) | lo;
+    v = o < v ? o : v;
+  }
+  if ((threadIdx.x & 63u) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  u64 r = sh[0];
+  for (uint32_t w = 1; w < (blockDim.x >> 6); ++w) r = sh[w] < r ? sh[w] : r;
+  __syncthreads();
+  return r;
+}
+
+// Long runs queued by seg_check_kernel: one workgroup per run, both passes
+// split over its lanes and merged with block minima.
+__global__ __launch_bounds__(256) void seg_long_kernel(SegParams S) {
+  __shared__ u64 sh[4];
+  const u64 total = *S.long_count;
+  const u64 nq = total < S.long_cap ? total : S.long_cap;
+  const uint32_t gmask = (1u << S.bg) - 1u;
+  for (u64 q = blockIdx.x; q < nq; q += gridDim.x) {
+    const u64 s = S.longq[2 * q], ew = S.longq[2 * q + 1];
+    const bool inter = (ew >> 63) != 0;
+    const u64 e = ew & ~(1ull << 63);
+    const SegHead H = seg_head(S, S.keys[s]);
+    Pass1 p1 = pass1_init();
+    for (u64 i = s + threadIdx.x; i < e; i += blockDim.x) {
+      const u64 p = S.vals[i];
+      uint32_t id = pay_lid(p);
+      if (inter) id += ((uint32_t)(S.keys[i] >> S.bk) & gmask) * H.W;
+      pass1_add(p1, id, pay_w(p), pay_val(p));
+    }
+    p1.r1 = (uint32_t)block_min_u64(p1.r1, sh);
+    p1.wmin = block_min_u64(p1.wmin, sh);
+    const uint32_t w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
+    const int32_t x1 = (int32_t)((uint32_t)p1.wmin ^ 0x80000000u);
+    PendingRec pr;
+    bool has = false;
+    if (!inter) {
+      Intra2 p2 = intra2_init();
+      for (u64 i = s + threadIdx.x; i < e; i += blockDim.x) {
+        const u64 p = S.vals[i];
+        intra2_add(p2, pay_lid(p), pay_w(p), pay_val(p), p1.r1, w1, x1);
+      }
+      p2.r2 = (uint32_t)block_min_u64(p2.r2, sh);
+      p2.w2 = (uint32_t)block_min_u64(p2.w2, sh);
+      p2.q = (uint32_t)block_min_u64(p2.q, sh);
+      p2.multi1 = block_min_u64(p2.multi1 ? 0u : 1u, sh) == 0u ? 1u : 0u;
+      if (threadIdx.x == 0) {
+        has = intra_finish(p1, p2, &pr.label, &pr.rw, &pr.ww);
+        pr.gid = H.gid; pr.interval = H.interval; pr.lidbase = H.gid * H.W;
+      }
+    } else {
+      const uint32_t gr1 = p1.r1 == NONE32 ? NONE32 : p1.r1 / H.W;
+      const uint32_t g1 = w1 == NONE32 ? NONE32 : w1 / H.W;
+      Inter2 p2 = inter2_init();
+      for (u64 i = s + threadIdx.x; i < e; i += blockDim.x) {
+        const u64 p = S.vals[i];
+        const uint32_t g = (uint32_t)(S.keys[i] >> S.bk) & gmask;
+        inter2_add(p2, g * H.W + pay_lid(p), g, pay_w(p), pay_val(p), gr1, w1, g1, x1);
+      }
+      p2.r1p = (uint32_t)block_min_u64(p2.r1p, sh);
+      p2.w1p = (uint32_t)block_min_u64(p2.w1p, sh);
+      p2.q = (uint32_t)block_min_u64(p2.q, sh);
+      p2.A = (uint32_t)block_min_u64(p2.A, sh);
+      p2.multi1 = block_min_u64(p2.multi1 ? 0u : 1u, sh) == 0u ? 1u : 0u;
+      if (threadIdx.x == 0) {
+        has = inter_finish(p1, p2, H.W, &pr.label, &pr.rw, &pr.ww);
+        pr.gid = H.gid; pr.interval = 0; pr.lidbase = 0;
+      }
+    }
+    if (threadIdx.x == 0 && has) {
+      pr.aid = H.aid; pr.cell = H.cell; pr.cellkey = H.cellkey;
+      const RecKey K = {S.bs, S.bc, H.G, H.NI};
+      store_record(S.out, K, atomicAdd(S.out.rec_count, 1ull), H.slot, H.instance, pr, inter);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1209,7 +1376,12 @@ hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u6
 }
 
 hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
-  hipLaunchKernelGGL(seg_check_kernel, dim3(blocks_for(cap ? cap : 1, 256)), dim3(256), 0, st, S);
+  // the entry count is on the device: a fixed grid walks it in rounds
+  uint32_t blocks = blocks_for(cap ? cap : 1, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(seg_check_kernel, dim3(blocks), dim3(256), 0, st, S);
+  uint32_t lblocks = (uint32_t)std::min<u64>(S.long_cap ? S.long_cap : 1, 2048);
+  hipLaunchKernelGGL(seg_long_kernel, dim3(lblocks), dim3(256), 0, st, S);
   return hipGetLastError();
 }
 hipError_t launch_gather(const GatherParams& G, u64 cap, hipStream_t st) {
@@ -1240,6 +1412,78 @@ hipError_t launch_clamp(u64* n_ptr, u64 cap, uint32_t* status, uint32_t bit, hip
 }
 hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st) {
   hipLaunchKernelGGL(final_merge_kernel, dim3(blocks_for(M.size, 256)), dim3(256), 0, st, M);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// triage features: one wave per instance copies the program's static part and
+// bins the first 256 initial cells of global arrays 0 and 1 into eighths of
+// their value range (seeded: [lo, hi); bound buffers: the int32 range)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void features_kernel(const FeatItem* items, const FeatProg* progs, uint32_t n,
+                                                       float* out) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t i = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const FeatItem it = items[i];
+  const FeatProg* P = progs + it.prog;
+  float* row = out + i * N_FEAT;
+  for (uint32_t k = lane; k < (uint32_t)N_FEAT_STATIC; k += 64u) row[k] = P->stat[k];
+  for (uint32_t j = 0; j < 2; ++j) {
+    const FeatArray A = P->arr[j];
+    uint32_t count = 0;   // lane b < 8 counts bin b
+    if (A.present) {
+      const uint32_t cells = A.size < 256u ? A.size : 256u;
+      for (uint32_t c0 = 0; c0 < cells; c0 += 64u) {
+        const uint32_t c = c0 + lane;
+        int bin = -1;
+        if (c < cells) {
+          if (A.bind == BIND_SEEDED) {
+            // offset of the draw in [lo, hi) mod 2^32 (a 2^32-wide range wraps in int32)
+            const uint32_t u = (uint32_t)seeded_cell(it.seed, j, c, A.lo, A.hi) - (uint32_t)(uint64_t)A.lo;
+            bin = (int)((uint64_t)u * 8ull / (uint64_t)(A.hi - A.lo));
+          } else {
+            bin = (int)(((uint32_t)A.dptr[c] ^ 0x80000000u) >> 29);
+          }
+        }
+        for (int b = 0; b < 8; ++b) {
+          const uint64_t m = __ballot(bin == b);
+          if (lane == (uint32_t)b) count += (uint32_t)__popcll(m);
+        }
+      }
+    }
+    if (lane < 8u) row[N_FEAT_STATIC + 8u * j + lane] = (float)count / 256.f;
+  }
+}
+
+hipError_t launch_features(const FeatItem* items, const FeatProg* progs, uint32_t n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(features_kernel, dim3((n + 3u) / 4u), dim3(256), 0, st, items, progs, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ranking keys: score descending, then index ascending, as one u64
+// ---------------------------------------------------------------------------
+// key = (descending score) << idx_bits | index, so a sort by the low
+// 32 + idx_bits bits orders by score, then index
+__global__ __launch_bounds__(256) void rank_keys_kernel(const float* scores, uint32_t n, uint32_t idx_bits, u64* keys,
+                                                        uint32_t* vals, u64* n_ptr) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *n_ptr = n;
+  if (i >= n) return;
+  const float f = scores[i];
+  uint32_t b = __float_as_uint(f);
+  // monotone map of float order onto u32 order; NaN ranks below every number
+  uint32_t asc = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  if (f != f) asc = 0u;
+  keys[i] = ((u64)(~asc) << idx_bits) | i;
+  vals[i] = i;
+}
+
+hipError_t launch_rank_keys(const float* scores, uint32_t n, uint32_t idx_bits, u64* keys, uint32_t* vals,
+                            u64* n_ptr, hipStream_t st) {
+  hipLaunchKernelGGL(rank_keys_kernel, dim3(blocks_for(n ? n : 1, 256)), dim3(256), 0, st, scores, n, idx_bits, keys,
+                     vals, n_ptr);
   return hipGetLastError();
 }
 

@@ -164,4 +164,22 @@ struct Ctl {
 
 constexpr uint32_t LDS_LIMIT = 160u * 1024u;
 
+// triage features: per program the shape- and seed-independent part plus the
+// two arrays whose initial cells are summarised; per instance a program index
+// and a seed
+constexpr int N_FEAT = 128, N_FEAT_STATIC = 112;
+struct FeatArray {       // 32 bytes
+  uint32_t present, bind, size, pad;
+  int64_t lo, hi;
+  const int32_t* dptr;
+};
+struct FeatProg {        // 512 bytes
+  float stat[N_FEAT_STATIC];
+  FeatArray arr[2];
+};
+struct FeatItem {        // 16 bytes
+  uint64_t seed;
+  uint32_t prog, pad;
+};
+
 }  // namespace rc

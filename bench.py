@@ -42,6 +42,8 @@ def workload(name: str, seeds: int | None):
         return None, "c3: random kernels, W in {32..1024}, 10-200 statements, 1-8 barriers, one batched call"
     if name == "c4":
         return [(WL.c4_kernel(), seeds or 16)], "c4: large intervals, G=64 x W=1024 x 64 iterations, 2^20 cells"
+    if name == "c5":
+        return None, "c5"
     raise SystemExit(f"unknown config {name}")
 
 
@@ -56,6 +58,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0: skip)")
     ap.add_argument("--programs", type=int, default=10000, help="c3: number of random programs")
     ap.add_argument("--tune-cache", default=None, help="c3: autotuner cache file (default: a temp file)")
+    ap.add_argument("--eval-programs", type=int, default=1000, help="c5: held-out programs")
+    ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
+    ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -69,6 +74,8 @@ def main():
     ctx = B.Context(0)
     if args.config == "c3":
         return bench_c3(args, ctx, desc)
+    if args.config == "c5":
+        return bench_c5(args, ctx)
     runs = []
     per_ws = int(args.ws_gb * (1 << 30) / len(progs))
     for w, n in progs:
@@ -230,6 +237,48 @@ def bench_c3(args, ctx, desc):
                    "accesses_per_step": accesses, "race_records_per_step": records,
                    "racy_instances_per_step": racy, "setup_s": round(setup_s, 2), "tunings": tuned},
         "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_c5(args, ctx):
+    """Learned triage: label the training instances with the exact checker,
+    train the network on the GPU, then sweep the held-out instances in plain
+    and in learned order and compare what each finds within a quarter of the
+    plain sweep's GPU time.  One step is the whole experiment."""
+    import torch
+    from paper_1308_3203_amd import triage as T
+    from paper_1308_3203_amd import workloads as WL
+    n_train, n_eval = args.programs, args.eval_programs
+    seeds = args.seeds or 100
+    t0 = time.perf_counter()
+    r = T.run(ctx, [WL.c3_kernel(s) for s in range(n_train)], seeds,
+              [WL.c3_kernel(10000 + s) for s in range(n_eval)], seeds,
+              epochs=args.epochs, batch=4096, lr=1e-3, chunk=args.chunk, label_chunk=20000,
+              ws_bytes=int(args.ws_gb * (1 << 30)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rep = r.report
+    line = {
+        "metric": "RACE records found per GPU-second within 25% of the plain sweep's GPU time, learned order",
+        "value": round(rep.races_per_gpu_s_learned, 1), "unit": "RACE records/GPU-s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(wall * 1e3, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 network, int32 checker", "data": "synthetic",
+        "config": {"workload": "c5: learned triage over the c3 generator; train programs 0..%d x %d seeds, "
+                               "held-out programs 10000..%d x %d seeds" % (n_train - 1, seeds, 10000 + n_eval - 1,
+                                                                          seeds),
+                   "train_instances": r.n_train, "eval_instances": r.n_eval,
+                   "train_racy_frac": round(r.train_racy_frac, 4), "epochs": args.epochs,
+                   "losses": [round(x, 5) for x in r.losses]},
+        "triage": {"recall_racy_instances": round(rep.recall_instances, 4),
+                   "recall_race_records": round(rep.recall_records, 4),
+                   "plain_recall_racy_instances": round(rep.plain_recall_instances, 4),
+                   "races_per_gpu_s_plain": round(rep.races_per_gpu_s_plain, 1),
+                   "plain_sweep_gpu_ms": round(rep.plain_ms, 2), "budget_frac": rep.budget_frac,
+                   "inference_gpu_ms": round(rep.inference_ms, 3), "label_sweep_gpu_ms": round(r.label_ms, 1),
+                   "train_gpu_ms": round(r.train_ms, 1), "racy_instances": rep.n_racy,
+                   "race_records": rep.n_race_records},
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -260,12 +260,14 @@ rc_status rc_read_final(rc_prog* prog, uint64_t seed, uint32_t array_id, int32_t
  * when it is built from integer literals, size(A), tid, unary -, + and -, and
  * * with a constant factor, optionally under one outer mod or % by a positive
  * constant; it then reads (a*tid + b) [mod N] (intermediate |a|,|b| <= 2^31,
- * else not affine).  b is reduced into [0, size(A)).
- *   [0..8)    statement counts / #statements: assign, load, store, barrier,
- *             assume, assert, if, for
+ * else not affine).  b is reduced into [0, size(A)).  A count c "/k" below
+ * stands for the bounded c / (c + k).
+ *   [0..8)    exact ratios statement count / #statements: assign, load,
+ *             store, barrier, assume, assert, if, for
  *   [8..12)   loads of global, loads of local, stores to global, stores to
- *             local arrays / #statements
- *   [12..16)  #statements/256, #global arrays/8, #local arrays/8, #scalars/16
+ *             local arrays / #statements (exact ratios, as [0..8))
+ *   [12..16)  #statements/256, then exact ratios #global arrays / 8,
+ *             #local arrays / 8, #scalars / 16
  *   [16..24)  /8 each, over pairs {p, q} of memory statements on one array,
  *             at least one a store, in one static interval, p = q allowed
  *             for a store ("self"):  self with a == 0; of those, under an if;
@@ -277,15 +279,16 @@ rc_status rc_read_final(rc_prog* prog, uint64_t seed, uint32_t array_id, int32_t
  *             loop nesting (/4); memory statements under an if (/16), under a
  *             loop (/16); distinct static intervals holding a store (/8); 0
  *   [32..96)  memory statements k = 0..15, 4 each (zeros when absent):
- *             store ? 1 : -1;  affine ? a/(1+|a|) : -2;  affine ? b/size : -2;
- *             (interval+1)/8
+ *             store ? 1 : -1;  affine ? a / (1+|a|) : -2;  affine ? b / size
+ *             : -2;  (interval+1) / 8 (all three exact ratios)
  *   [96..104) barriers/8, barriers under loops/8, most memory statements in
  *             one static interval/64, sum of loop trip counts/64, memory
  *             statements/64, stores/64, distinct arrays stored to/8, 0
- *   [104..112) W/1024, G/1024, ceil(log2 size) of global arrays 0 and 1 /32
- *             (0 if absent), local cells/65536, G*W/2^20, 0, 0
+ *   [104..112) exact ratios: W / 1024, G / 1024, ceil(log2 size) of global
+ *             arrays 0 and 1 / 32 (0 if absent), local cells / 65536,
+ *             G*W / 2^20, 0, 0
  *   [112..128) for global arrays 0 and 1 (zeros if absent): counts of the
- *             first min(size, 256) initial cells in 8 bins / 256; seeded
+ *             first min(size, 256) initial cells in 8 bins, exact / 256; seeded
  *             bindings bin floor(8 u / (hi - lo)) with u = (v - lo) mod 2^32
  *             the draw's offset in the range, bound buffers bin
  *             floor((v + 2^31) / 2^29)

@@ -1203,6 +1203,9 @@ static void fwalk(FState* F, Stmt** b, int n) {
 
 static float fdiv(int64_t a, int64_t b) { return (float)a / (float)b; }
 
+/* a count c on scale k, kept bounded: c / (c + k) */
+static float fsq(int64_t c, int64_t k) { return (float)c / (float)(c + k); }
+
 static int64_t pos_mod(int64_t x, int64_t m) {
   int64_t r = x % m;
   return r < 0 ? r + m : r;
@@ -1233,7 +1236,7 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
   f[9] = fdiv(F.loads_l, n);
   f[10] = fdiv(F.stores_g, n);
   f[11] = fdiv(F.stores_l, n);
-  f[12] = fdiv(F.n_stmts, 256);
+  f[12] = fsq(F.n_stmts, 256);
   f[13] = fdiv(P->n_global, 8);
   f[14] = fdiv(P->n_local, 8);
   f[15] = fdiv(P->n_scalars, 16);
@@ -1261,20 +1264,20 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
       else shifted++;
     }
   }
-  f[16] = fdiv(self_const, 8);
-  f[17] = fdiv(self_const_if, 8);
-  f[18] = fdiv(self_other, 8);
-  f[19] = fdiv(shifted, 8);
-  f[20] = fdiv(aligned, 8);
-  f[21] = fdiv(strides, 8);
-  f[22] = fdiv(opaque, 8);
-  f[23] = fdiv(looped, 8);
-  f[24] = fdiv(F.tid_values, 16);
-  f[25] = fdiv(F.other_values, 16);
-  f[26] = fdiv(F.max_ifs, 16);
-  f[27] = fdiv(F.max_loops, 4);
-  f[28] = fdiv(F.mem_under_if, 16);
-  f[29] = fdiv(F.mem_under_loop, 16);
+  f[16] = fsq(self_const, 8);
+  f[17] = fsq(self_const_if, 8);
+  f[18] = fsq(self_other, 8);
+  f[19] = fsq(shifted, 8);
+  f[20] = fsq(aligned, 8);
+  f[21] = fsq(strides, 8);
+  f[22] = fsq(opaque, 8);
+  f[23] = fsq(looped, 8);
+  f[24] = fsq(F.tid_values, 16);
+  f[25] = fsq(F.other_values, 16);
+  f[26] = fsq(F.max_ifs, 16);
+  f[27] = fsq(F.max_loops, 4);
+  f[28] = fsq(F.mem_under_if, 16);
+  f[29] = fsq(F.mem_under_loop, 16);
   {
     int64_t distinct = 0;
     for (int64_t i = 0; i < F.n_mem; i++) {
@@ -1284,7 +1287,7 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
         if (F.mem[j].is_store && F.mem[j].interval == F.mem[i].interval) seen = 1;
       if (!seen) distinct++;
     }
-    f[30] = fdiv(distinct, 8);
+    f[30] = fsq(distinct, 8);
   }
   /* the first 16 memory statements */
   for (int64_t k = 0; k < 16 && k < F.n_mem; k++) {
@@ -1302,12 +1305,12 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
     s[3] = fdiv(m->interval + 1, 8);
   }
   /* barrier and loop structure */
-  f[96] = fdiv(F.kind_count[S_BARRIER], 8);
-  f[97] = fdiv(F.loop_barriers, 8);
-  f[98] = fdiv(F.max_mem_interval, 64);
-  f[99] = fdiv(F.trips, 64);
-  f[100] = fdiv(F.n_mem, 64);
-  f[101] = fdiv(F.kind_count[S_STORE], 64);
+  f[96] = fsq(F.kind_count[S_BARRIER], 8);
+  f[97] = fsq(F.loop_barriers, 8);
+  f[98] = fsq(F.max_mem_interval, 64);
+  f[99] = fsq(F.trips, 64);
+  f[100] = fsq(F.n_mem, 64);
+  f[101] = fsq(F.kind_count[S_STORE], 64);
   {
     int64_t distinct = 0;
     for (int64_t i = 0; i < F.n_mem; i++) {
@@ -1317,7 +1320,7 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
         if (F.mem[j].is_store && F.mem[j].arr == F.mem[i].arr) seen = 1;
       if (!seen) distinct++;
     }
-    f[102] = fdiv(distinct, 8);
+    f[102] = fsq(distinct, 8);
   }
   /* launch shape and array sizes */
   f[104] = fdiv(W, 1024);

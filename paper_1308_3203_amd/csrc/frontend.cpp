@@ -812,6 +812,8 @@ struct FeatWalk {
 };
 
 float ratio(int64_t num, int64_t den) { return (float)num / (float)den; }
+// a count c on scale k, bounded: c / (c + k)
+float squash(int64_t c, int64_t k) { return (float)c / (float)(c + k); }
 
 int64_t emod(int64_t x, int64_t m) { return ((x % m) + m) % m; }
 
@@ -826,7 +828,7 @@ void static_features(const std::vector<Statement>& body, const Compiled& c, floa
   f[9] = ratio(w.ld_l, n);
   f[10] = ratio(w.st_g, n);
   f[11] = ratio(w.st_l, n);
-  f[12] = ratio(w.n, 256);
+  f[12] = squash(w.n, 256);
   f[13] = ratio(c.n_global, 8);
   f[14] = ratio(c.n_local, 8);
   f[15] = ratio((int64_t)c.scalars.size(), 16);
@@ -852,21 +854,20 @@ void static_features(const std::vector<Statement>& body, const Compiled& c, floa
       if (emod(x.idx.b, S) != emod(y.idx.b, S)) ++pc[3]; else ++pc[4];
     }
   }
-  for (int k = 0; k < 8; ++k) f[16 + k] = ratio(pc[k], 8);
-  f[24] = ratio(w.val_tid, 16);
-  f[25] = ratio(w.val_other, 16);
-  f[26] = ratio(w.max_if_depth, 16);
-  f[27] = ratio(w.max_loop_depth, 4);
-  f[28] = ratio(w.mem_in_if, 16);
-  f[29] = ratio(w.mem_in_loop, 16);
+  for (int k = 0; k < 8; ++k) f[16 + k] = squash(pc[k], 8);
+  f[24] = squash(w.val_tid, 16);
+  f[25] = squash(w.val_other, 16);
+  f[26] = squash(w.max_if_depth, 16);
+  f[27] = squash(w.max_loop_depth, 4);
+  f[28] = squash(w.mem_in_if, 16);
+  f[29] = squash(w.mem_in_loop, 16);
   {
     std::vector<int64_t> ivls;
-    std::vector<int> stored;
     for (const MemStmt& m : w.mem) {
       if (!m.store) continue;
       if (std::find(ivls.begin(), ivls.end(), m.ivl) == ivls.end()) ivls.push_back(m.ivl);
     }
-    f[30] = ratio((int64_t)ivls.size(), 8);
+    f[30] = squash((int64_t)ivls.size(), 8);
   }
   f[31] = 0.f;
   for (size_t k = 0; k < 16; ++k) {
@@ -884,17 +885,17 @@ void static_features(const std::vector<Statement>& body, const Compiled& c, floa
     }
     s[3] = ratio(m.ivl + 1, 8);
   }
-  f[96] = ratio(w.counts[Statement::BARRIER], 8);
-  f[97] = ratio(w.barriers_in_loops, 8);
-  f[98] = ratio(w.max_mem_in_ivl, 64);
-  f[99] = ratio(w.trip_sum, 64);
-  f[100] = ratio((int64_t)M, 64);
-  f[101] = ratio(w.counts[Statement::STORE], 64);
+  f[96] = squash(w.counts[Statement::BARRIER], 8);
+  f[97] = squash(w.barriers_in_loops, 8);
+  f[98] = squash(w.max_mem_in_ivl, 64);
+  f[99] = squash(w.trip_sum, 64);
+  f[100] = squash((int64_t)M, 64);
+  f[101] = squash(w.counts[Statement::STORE], 64);
   {
     std::vector<int> arrs;
     for (const MemStmt& m : w.mem)
       if (m.store && std::find(arrs.begin(), arrs.end(), m.arr) == arrs.end()) arrs.push_back(m.arr);
-    f[102] = ratio((int64_t)arrs.size(), 8);
+    f[102] = squash((int64_t)arrs.size(), 8);
   }
   f[103] = 0.f;
 }

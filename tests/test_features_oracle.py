@@ -6,12 +6,17 @@ from oracle import oracle as O
 
 
 def _expect(entries, shape_part):
+    """entries: index -> number, or (num, den) for the fp32 quotient."""
     f = np.zeros(128, dtype=np.float32)
-    for k, v in entries.items():
-        f[k] = np.float32(v)
-    for k, v in shape_part.items():
-        f[k] = np.float32(v)
+    for d in (entries, shape_part):
+        for k, v in d.items():
+            f[k] = np.float32(v[0]) / np.float32(v[1]) if isinstance(v, tuple) else np.float32(v)
     return f
+
+
+def sq(c, k):
+    """A bounded count: c / (c + k)."""
+    return (c, c + k)
 
 
 def _hist(values, lo, hi, cells):
@@ -41,19 +46,19 @@ def test_features_two_intervals_with_shifted_and_constant_cells():
     G, W, seed = 3, 40, 11
     f = p.features(G, W, {"A": ("seeded", 0, 16), "B": Bdata}, seed=seed)
     # statements in order: load, store, barrier, store, if, store  (6)
-    e = {1: 1 / 6, 2: 3 / 6, 3: 1 / 6, 6: 1 / 6,
-         8: 1 / 6, 10: 3 / 6, 12: 6 / 256, 13: 2 / 8,
+    e = {1: (1, 6), 2: (3, 6), 3: (1, 6), 6: (1, 6),
+         8: (1, 6), 10: (3, 6), 12: sq(6, 256), 13: (2, 8),
          # self pairs with a constant cell: B[0], B[2] (the second under an if);
          # shifted pairs: A[tid] / A[tid+1 mod 64], B[0] / B[2]
-         16: 2 / 8, 17: 1 / 8, 19: 2 / 8,
-         24: 1 / 16, 25: 1 / 16, 26: 1 / 16, 28: 1 / 16, 30: 2 / 8,
+         16: sq(2, 8), 17: sq(1, 8), 19: sq(2, 8),
+         24: sq(1, 16), 25: sq(1, 16), 26: sq(1, 16), 28: sq(1, 16), 30: sq(2, 8),
          # memory statements: (kind, a/(1+|a|), b/size, (interval+1)/8)
-         32: -1, 33: 0.5, 34: 0, 35: 1 / 8,
-         36: 1, 37: 0.5, 38: 1 / 64, 39: 1 / 8,
-         40: 1, 41: 0, 42: 0, 43: 2 / 8,
-         44: 1, 45: 0, 46: 2 / 8, 47: 2 / 8,
-         96: 1 / 8, 98: 2 / 64, 100: 4 / 64, 101: 3 / 64, 102: 2 / 8}
-    shape = {104: W / 1024, 105: G / 1024, 106: 6 / 32, 107: 3 / 32, 109: G * W / 2**20}
+         32: -1, 33: 0.5, 34: 0, 35: (1, 8),
+         36: 1, 37: 0.5, 38: (1, 64), 39: (1, 8),
+         40: 1, 41: 0, 42: 0, 43: (2, 8),
+         44: 1, 45: 0, 46: (2, 8), 47: (2, 8),
+         96: sq(1, 8), 98: sq(2, 64), 100: sq(4, 64), 101: sq(3, 64), 102: sq(2, 8)}
+    shape = {104: (W, 1024), 105: (G, 1024), 106: (6, 32), 107: (3, 32), 109: (G * W, 2**20)}
     want = _expect(e, shape)
     avals = [O.seeded_value(seed, 0, c, 0, 16) for c in range(64)]
     want[112:120] = _hist(avals, 0, 16, 64).astype(np.float32)
@@ -79,14 +84,15 @@ def test_features_loop_with_barrier():
     p = O.Program(SRC2)
     f = p.features(1, 16, {"A": ("seeded", -5, 300)}, seed=2)
     # statements: for, store, barrier, load, load (5)
-    e = {1: 2 / 5, 2: 1 / 5, 3: 1 / 5, 7: 1 / 5, 8: 2 / 5, 10: 1 / 5, 12: 5 / 256, 13: 1 / 8,
+    e = {1: (2, 5), 2: (1, 5), 3: (1, 5), 7: (1, 5), 8: (2, 5), 10: (1, 5), 12: sq(5, 256), 13: (1, 8),
          # every pair with the store inside the barrier loop is counted apart
-         23: 3 / 8, 25: 1 / 16, 27: 1 / 4, 29: 2 / 16, 30: 1 / 8,
-         32: 1, 33: 0.5, 34: 0, 35: 1 / 8,
-         36: -1, 37: 0.5, 38: 1 / 16, 39: 2 / 8,
-         40: -1, 41: 2 / 3, 42: 0, 43: 2 / 8,
-         96: 1 / 8, 97: 1 / 8, 98: 2 / 64, 99: 4 / 64, 100: 3 / 64, 101: 1 / 64, 102: 1 / 8}
-    shape = {104: 16 / 1024, 105: 1 / 1024, 106: 4 / 32, 109: 16 / 2**20}
+         23: sq(3, 8), 25: sq(1, 16), 27: sq(1, 4), 29: sq(2, 16), 30: sq(1, 8),
+         32: 1, 33: 0.5, 34: 0, 35: (1, 8),
+         36: -1, 37: 0.5, 38: (1, 16), 39: (2, 8),
+         40: -1, 41: (2, 3), 42: 0, 43: (2, 8),
+         96: sq(1, 8), 97: sq(1, 8), 98: sq(2, 64), 99: sq(4, 64), 100: sq(3, 64), 101: sq(1, 64),
+         102: sq(1, 8)}
+    shape = {104: (16, 1024), 105: (1, 1024), 106: (4, 32), 109: (16, 2**20)}
     want = _expect(e, shape)
     avals = [O.seeded_value(2, 0, c, -5, 300) for c in range(16)]
     want[112:120] = _hist(avals, -5, 300, 16).astype(np.float32)
@@ -113,20 +119,20 @@ def test_features_not_affine_and_local_arrays():
     f = p.features(2, 8, {"A": ("seeded", 0, 16)}, seed=0)
     # statements: store, store, store, load, assume, assert, store (7)
     n = 7
-    e = {1: 1 / n, 2: 4 / n, 4: 1 / n, 5: 1 / n,
-         9: 1 / n, 10: 2 / n, 11: 2 / n, 12: 7 / 256, 13: 1 / 8, 14: 1 / 8, 15: 1 / 16,
+    e = {1: (1, n), 2: (4, n), 4: (1, n), 5: (1, n),
+         9: (1, n), 10: (2, n), 11: (2, n), 12: sq(7, 256), 13: (1, 8), 14: (1, 8), 15: (1, 16),
          # self pairs not affine: A[lid], L[v], A[(tid*3) % v]; L pairs with one
          # side not affine: (L[v], L[-3tid-5]), (L[v], L[load]),
          # (L[-3tid-5], L[load]); A pairs: (A[lid], A[% v])
-         18: 3 / 8, 22: 4 / 8,
-         24: 0, 25: 2 / 16, 30: 1 / 8,
-         32: 1, 33: -2, 34: -2, 35: 1 / 8,
-         36: 1, 37: -2, 38: -2, 39: 1 / 8,
-         40: 1, 41: -0.75, 42: 27 / 32, 43: 1 / 8,
-         44: -1, 45: -2, 46: -2, 47: 1 / 8,
-         48: 1, 49: -2, 50: -2, 51: 1 / 8,
-         98: 5 / 64, 100: 5 / 64, 101: 4 / 64, 102: 2 / 8}
-    shape = {104: 8 / 1024, 105: 2 / 1024, 106: 4 / 32, 108: 32 / 65536, 109: 16 / 2**20}
+         18: sq(3, 8), 22: sq(4, 8),
+         24: 0, 25: sq(2, 16), 30: sq(1, 8),
+         32: 1, 33: -2, 34: -2, 35: (1, 8),
+         36: 1, 37: -2, 38: -2, 39: (1, 8),
+         40: 1, 41: -0.75, 42: (27, 32), 43: (1, 8),
+         44: -1, 45: -2, 46: -2, 47: (1, 8),
+         48: 1, 49: -2, 50: -2, 51: (1, 8),
+         98: sq(5, 64), 100: sq(5, 64), 101: sq(4, 64), 102: sq(2, 8)}
+    shape = {104: (8, 1024), 105: (2, 1024), 106: (4, 32), 108: (32, 65536), 109: (16, 2**20)}
     want = _expect(e, shape)
     avals = [O.seeded_value(0, 0, c, 0, 16) for c in range(16)]
     want[112:120] = _hist(avals, 0, 16, 16).astype(np.float32)

@@ -9,7 +9,9 @@ seeded on the device.  Prints one JSON line.
 Configs: c1 (one random 20-statement kernel, 1 x 64, 1000 seeds),
 c2 (six template kernels, 16 x 256, 10^4 seeds each; the default),
 c3 (random kernels of widths 32..1024 in one batched call; --programs x --seeds),
-c4 (large intervals, 64 x 1024 x 64 iterations, 16 seeds).
+c4 (large intervals, 64 x 1024 x 64 iterations, 16 seeds),
+c5 (learned triage over the c3 generator: train, then sweep held-out
+instances in learned and in plain order).
 """
 from __future__ import annotations
 
@@ -23,12 +25,57 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # algorithmic bytes per race-checked access: the simulated cell (4 B), the
 # 12-byte access record written once (interpretation) and read once (check)
 ALGO_BYTES = {"interpret": 16.0, "interval_check": 12.0}
 KERNEL_OF_PHASE = {"interpret": "rc_interp_kernel", "log_sort": "rs_scatter_kernel/rs_hist_kernel",
-                   "interval_check": "seg_check_kernel", "record_sort": "rs_scatter_kernel/rs_hist_kernel",
+                   "interval_check": "seg_check_kernel+seg_long_kernel",
+                   "record_sort": "rs_scatter_kernel/rs_hist_kernel",
                    "output": "rec_gather_kernel", "setup": "fill kernels"}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources: counter-derived traffic is valid only for
+    the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "rc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1308_3203_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload_name: str):
+    """HBM bytes per launch of `kernel` on `workload_name` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel
+    calibration), or None when absent or taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = table.get(f"{kernel}|{workload_name}")
+    if not e or e.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def copy_probe(gib: float, reps: int = 3):
+    """A plain device-to-device copy of known size, to calibrate the HBM
+    byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps,
+                      "gbs": round(2 * n * 4 / dt / 1e9, 1)}), flush=True)
 
 
 def workload(name: str, seeds: int | None):
@@ -61,6 +108,7 @@ def main():
     ap.add_argument("--eval-programs", type=int, default=1000, help="c5: held-out programs")
     ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
     ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
+    ap.add_argument("--copy-probe", type=float, default=0.0, help="only run a plain copy of this many GiB")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -70,6 +118,8 @@ def main():
     import torch
     from paper_1308_3203_amd import binding as B
 
+    if args.copy_probe > 0:
+        return copy_probe(args.copy_probe)
     progs, desc = workload(args.config, args.seeds)
     ctx = B.Context(0)
     if args.config == "c3":
@@ -133,7 +183,8 @@ def main():
     algo = ALGO_BYTES.get(dom, 0.0) * units_per_launch
     achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(KERNEL_OF_PHASE[dom], args.config),
                 "kernel": KERNEL_OF_PHASE[dom], "phase": dom,
                 "avg_launch_ms": round(per_launch_ms, 4),
                 "phases_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
@@ -222,7 +273,8 @@ def bench_c3(args, ctx, desc):
     algo = ALGO_BYTES.get(dom, 0.0) * accesses / max(1, launches)
     achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": KERNEL_OF_PHASE[dom],
+                "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(KERNEL_OF_PHASE[dom], "c3"), "kernel": KERNEL_OF_PHASE[dom],
                 "phase": dom, "avg_launch_ms": round(per_launch_ms, 4),
                 "phases_ms": {k: round(v[0], 3) for k, v in prof.items()},
                 "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}

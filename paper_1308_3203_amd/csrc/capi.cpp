@@ -454,7 +454,12 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
   u64 *lk0 = (u64*)(ws + L.lk0), *lv0 = (u64*)(ws + L.lv0), *lk1 = (u64*)(ws + L.lk1), *lv1 = (u64*)(ws + L.lv1);
   {
     PhaseTimer t(ctx, st, 1, timed);
-    HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.max_log, L.nbits_log, (const uint32_t*)(ws + L.wg_count),
+    // Each work-group's log region holds one (instance, group) in execution
+    // (so interval) order; a stable sort above the group and interval fields
+    // therefore leaves every run of equal full keys, and every (instance,
+    // cell) run, contiguous, which is all the check needs.
+    HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.max_log, L.nbits_log, L.bg + L.bk,
+                     (const uint32_t*)(ws + L.wg_count),
                      (const u64*)(ws + L.wg_base), (uint32_t*)(ws + L.tiles), L.max_wg, (uint32_t*)(ws + L.hist),
                      C.radix_bits, st, &second));
   }

@@ -103,11 +103,12 @@ size_t scan_tmp_words(unsigned long long m);
 size_t sort_hist_words(unsigned long long cap);
 size_t sort_log_hist_words(unsigned long long n_regions, unsigned long long cap);
 // Sort the access log: region r (seg_count[r] entries from seg_base[r])
-// becomes part of one dense array sorted by the low nbits of the key; *n_ptr
-// (zero on entry) receives the number of entries; tiles holds n_regions + 1
-// words of scratch.
+// becomes part of one dense array, stably sorted by key bits
+// [start_bit, nbits); *n_ptr (zero on entry) receives the number of entries;
+// tiles holds n_regions + 1 words of scratch.  Bits below start_bit keep the
+// regions' order (region by region, each in its own order).
 hipError_t sort_log(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
-                    const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
+                    const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits, uint32_t start_bit,
                     const uint32_t* seg_count, const unsigned long long* seg_base, uint32_t* tiles,
                     unsigned long long n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second);
 hipError_t sort_pairs_u32(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1,

@@ -1319,15 +1319,15 @@ template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
                                   const uint32_t* seg_count, const u64* seg_base, const uint32_t* tiles,
                                   u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st,
-                                  int* result_in_second) {
+                                  int* result_in_second, uint32_t start_bit = 0) {
   u64 *ka = k0, *kb = k1;
   V *va = v0, *vb = v1;
   int passes = 0;
   if (dbits < 1 || dbits > 8) dbits = 8;
-  // passes of dbits each; a segmented input always takes one pass, which
-  // also makes it dense
-  const uint32_t want = seg_count ? (nbits > 1 ? nbits : 1) : nbits;
-  for (uint32_t shift = 0; shift < want; shift += dbits) {
+  // passes of dbits each over bits [start_bit, nbits); a segmented input
+  // always takes at least one pass, which also makes it dense
+  const uint32_t want = seg_count ? std::max(nbits, start_bit + 1) : nbits;
+  for (uint32_t shift = start_bit; shift < want; shift += dbits) {
     RsIn in;
     memset(&in, 0, sizeof in);
     in.n_ptr = n_ptr;
@@ -1358,8 +1358,8 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
 }
 
 hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
-                    const uint32_t* seg_count, const u64* seg_base, uint32_t* tiles, u64 n_regions,
-                    uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second) {
+                    uint32_t start_bit, const uint32_t* seg_count, const u64* seg_base, uint32_t* tiles,
+                    u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second) {
   // the number of entries, and the regions' tile prefix
   hipLaunchKernelGGL(sum_u32_kernel, dim3(n_regions > 65536 ? 1024 : (uint32_t)blocks_for(n_regions, 256)),
                      dim3(256), 0, st, seg_count, n_regions, (u64*)n_ptr);
@@ -1367,7 +1367,7 @@ hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 ca
                      tiles, n_regions);
   scan_excl(tiles, n_regions + 1, hist, st);
   return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, seg_base, tiles, n_regions, hist, dbits,
-                              st, in_second);
+                              st, in_second, start_bit);
 }
 hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {

@@ -355,14 +355,17 @@ def test_rank_orders_by_score_then_index(n):
 # ---------------------------------------------------------------------------
 def test_learned_order_finds_races_sooner_than_plain_order():
     from paper_1308_3203_amd import triage as T
-    train = [WL.c3_kernel(s) for s in range(400)]
-    held = [WL.c3_kernel(10000 + s) for s in range(100)]
-    r = T.run(ctx(), train, 10, held, 10, epochs=40, batch=512, lr=2e-3, chunk=100, label_chunk=4000,
-              ws_bytes=4 << 30)
+    train = [WL.c3_kernel(s) for s in range(3000)]
+    held = [WL.c3_kernel(10000 + s) for s in range(300)]
+    r = T.run(ctx(), train, 4, held, 5, epochs=10, batch=1024, lr=2e-3, chunk=50, label_chunk=4000,
+              ws_bytes=8 << 30)
     rep = r.report
     print("triage:", rep, "losses", r.losses[0], r.losses[-1], "train racy", r.train_racy_frac, flush=True)
     assert rep.n_racy > 0
-    # the learned order reaches most racy instances within a quarter of the
-    # plain sweep's GPU time, and clearly more than the plain order does
-    assert rep.recall_instances >= 0.8
+    # within a quarter of the plain sweep's GPU time the learned order reaches
+    # most racy instances and nearly every RACE record, far more than the
+    # plain order does
+    assert rep.recall_instances >= 0.75
+    assert rep.recall_records >= 0.95
     assert rep.recall_instances >= rep.plain_recall_instances + 0.3
+    assert rep.races_per_gpu_s_learned >= 10 * rep.races_per_gpu_s_plain

@@ -132,9 +132,29 @@ struct PhaseTimer {
 // ---------------------------------------------------------------------------
 // per-program quantities
 // ---------------------------------------------------------------------------
-size_t lds_fixed_bytes(const rc_prog* p) {
+// The LDS check uses a per-cell table when the LDS-logged cells are few:
+// written local arrays when G > 1 (their log cell keys follow the written
+// global arrays'), every written array when G == 1 (keys from 0).
+size_t lds_base_bytes(const rc_prog* p) {
   const uint32_t WP = ((p->W + 63) / 64) * 64;
-  return ((sizeof(Ctl) + 15) & ~(size_t)15) + (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4;
+  return ((sizeof(Ctl) + 15) & ~(size_t)15) + (size_t)p->lds_local_cells * 8 + (size_t)p->c.nregs * WP * 4 + 8;
+}
+
+// (Only when the table and a minimal log fit in LDS beside the rest.)
+void lds_table(const rc_prog* p, uint32_t* base, uint32_t* cells) {
+  uint32_t gcells = 0;
+  for (const CompiledArray& a : p->c.arrays)
+    if (a.global && a.written) gcells += a.size;
+  *base = p->G == 1 ? 0u : gcells;
+  const uint32_t n = p->n_logged_cells - *base;
+  const bool fits = lds_base_bytes(p) + (size_t)n * sizeof(TabCell) + 64 * 16 <= LDS_LIMIT;
+  *cells = (n > 0 && n <= TAB_MAX_CELLS && fits) ? n : 0u;
+}
+
+size_t lds_fixed_bytes(const rc_prog* p) {
+  uint32_t tb, tc;
+  lds_table(p, &tb, &tc);
+  return lds_base_bytes(p) + (size_t)tc * sizeof(TabCell);
 }
 
 size_t lds_bytes(const rc_prog* p) { return lds_fixed_bytes(p) + (size_t)p->lds_log_cap * 16; }
@@ -574,6 +594,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     D.nwaves = (p->W + 63) / 64;
     D.lds_local_cells = p->lds_local_cells;
     D.lds_log_cap = p->lds_log_cap;
+    lds_table(p, &D.tab_base, &D.tab_cells);
+    if (!p->lds_log_cap) D.tab_cells = 0;
     D.overlay_cells = p->overlay_cells;
     D.NI = (uint32_t)p->c.max_intervals;
     D.wg_log_cap = wg_log_entries(p);

@@ -320,6 +320,7 @@ struct ItemView {
   const ScalarDesc* scalars;
   uint32_t n_arrays, n_global, n_scalars, nregs, G, W, nwaves, lds_local_cells;
   uint32_t lds_log_cap, overlay_cells, NI, bc, bg, bk, bs, do_log;
+  uint32_t tab_base, tab_cells;
   u64 wg_log_cap;
   u64* log_keys;
   u64* log_vals;
@@ -350,9 +351,14 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
   uint32_t* lmeta = reinterpret_cast<uint32_t*>(lkey + P.lds_log_cap);
   int32_t* lval = reinterpret_cast<int32_t*>(lmeta + P.lds_log_cap);
   int32_t* regs = lval + P.lds_log_cap;
+  // the per-cell check table (8-byte aligned after the registers)
+  TabCell* tab = reinterpret_cast<TabCell*>(
+      (reinterpret_cast<uintptr_t>(regs + P.nregs * WP) + 7u) & ~(uintptr_t)7u);
+  const TabCell empty_cell = {~0ull, NONE32, NONE32, NONE32, NONE32, 0u, NONE32};
 
   for (uint32_t i = tl; i < P.lds_local_cells; i += blockDim.x) locc[i] = 0ull;
   for (uint32_t i = tl; i < P.nregs * WP; i += blockDim.x) regs[i] = 0;
+  for (uint32_t i = tl; i < P.tab_cells; i += blockDim.x) tab[i] = empty_cell;
   if (tl == 0) ctl->fault = ~0ull;
   if (tl < P.n_scalars) {
     const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
@@ -446,6 +452,73 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
     lds_used = 0;
     lds_spilled = false;
     if (spilled || n < 2u) return;
+    const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
+    const RecKey K = {P.bs, P.bc, P.G, P.NI};
+    if (P.tab_cells) {
+      // Per-cell table: the same two passes as intra_check, merged with LDS
+      // atomics; the cell's first log entry (the owner) finishes the check
+      // and clears the cell for the next interval.
+      for (uint32_t i = tl; i < n; i += blockDim.x) {
+        TabCell& c = tab[(uint32_t)(lkey[i] >> 16) - P.tab_base];
+        const uint32_t meta = lmeta[i];
+        const uint32_t l = meta & 1023u;
+        if (meta & 1024u) atomicMin(&c.wmin, ((u64)l << 32) | ((uint32_t)lval[i] ^ 0x80000000u));
+        else atomicMin(&c.r1, l);
+        atomicMin(&c.owner, i);
+      }
+      __syncthreads();
+      for (uint32_t i = tl; i < n; i += blockDim.x) {
+        TabCell& c = tab[(uint32_t)(lkey[i] >> 16) - P.tab_base];
+        const uint32_t meta = lmeta[i];
+        const uint32_t l = meta & 1023u;
+        const u64 wmin = c.wmin;
+        const uint32_t w1 = wmin == ~0ull ? NONE32 : (uint32_t)(wmin >> 32);
+        const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
+        if (meta & 1024u) {
+          const int32_t v = lval[i];
+          if (l == w1) { if (v != x1) atomicOr(&c.multi1, 1u); }
+          else {
+            atomicMin(&c.w2, l);
+            if (v != x1) atomicMin(&c.q, l);
+          }
+        } else if (l != c.r1) {
+          atomicMin(&c.r2, l);
+        }
+      }
+      __syncthreads();
+      for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
+        const uint32_t i = b0 + tl;
+        bool has = false;
+        PendingRec pr;
+        if (i < n) {
+          const uint32_t ck = (uint32_t)(lkey[i] >> 16);
+          TabCell& c = tab[ck - P.tab_base];
+          if (c.owner == i) {
+            const Pass1 p1 = {c.r1, c.wmin};
+            const Intra2 p2 = {c.r2, c.w2, c.q, c.multi1};
+            c = empty_cell;
+            has = intra_finish(p1, p2, &pr.label, &pr.rw, &pr.ww);
+            if (has) {
+              uint32_t aid = 0;
+              for (uint32_t a = 0; a < P.n_arrays; ++a) {
+                const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
+                if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
+              }
+              const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
+              pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
+              pr.cellkey = ck; pr.lidbase = gid * P.W;
+            }
+          }
+        }
+        const u64 m = __ballot(has);
+        if (m != 0ull) {
+          const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
+          if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, instance, pr, false);
+        }
+      }
+      __syncthreads();
+      return;
+    }
     uint32_t P2 = 2;
     while (P2 < n) P2 <<= 1;
     for (uint32_t i = n + tl; i < P2; i += blockDim.x) lkey[i] = ~0ull;
@@ -462,8 +535,6 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
         __syncthreads();
       }
     }
-    const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
-    const RecKey K = {P.bs, P.bc, P.G, P.NI};
     for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
       const uint32_t i = b0 + tl;
       bool has = false;
@@ -714,6 +785,7 @@ __global__ __launch_bounds__(1024) void rc_interp_kernel(PassParams PP) {
     P.n_arrays = D.n_arrays; P.n_global = D.n_global; P.n_scalars = D.n_scalars; P.nregs = D.nregs;
     P.G = D.G; P.W = D.W; P.nwaves = D.nwaves; P.lds_local_cells = D.lds_local_cells;
     P.lds_log_cap = D.lds_log_cap; P.overlay_cells = D.overlay_cells; P.NI = D.NI;
+    P.tab_base = D.tab_base; P.tab_cells = D.tab_cells;
     P.bc = PP.bc; P.bg = PP.bg; P.bk = PP.bk; P.bs = PP.bs; P.do_log = PP.do_log;
     P.wg_log_cap = D.wg_log_cap;
     P.log_keys = PP.log_keys; P.log_vals = PP.log_vals; P.status_word = PP.status_word; P.rec = PP.rec;
@@ -817,63 +889,99 @@ __global__ __launch_bounds__(256) void region_tiles_kernel(const uint32_t* count
   else if (r == n) tiles[r] = 0;
 }
 
+// Lanes of a wave holding the same digit (dbits ballots); rank = position
+// among them, count = how many.
+__device__ __forceinline__ void digit_peers(uint32_t d, bool valid, uint32_t dbits, uint32_t lane,
+                                            uint32_t* rank, uint32_t* count) {
+  u64 eq = __ballot(valid);
+  for (uint32_t b = 0; b < dbits; ++b) {
+    const u64 bb = __ballot((d >> b) & 1u);
+    eq &= ((d >> b) & 1u) ? bb : ~bb;
+  }
+  *rank = (uint32_t)__popcll(eq & ((1ull << lane) - 1ull));
+  *count = (uint32_t)__popcll(eq);
+}
+
+// Digit counts of one tile; one LDS atomic per distinct digit per wave
+// (sorted inputs make high digits nearly constant within a tile).
 __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, uint32_t shift,
                                                       uint32_t* hist, uint32_t nblocks) {
   __shared__ uint32_t h[256];
-  const uint32_t t = threadIdx.x;
+  const uint32_t t = threadIdx.x, lane = t & 63u;
   const uint32_t dmask = (1u << in.dbits) - 1u;
   h[t] = 0;
   __syncthreads();
   u64 start;
   uint32_t count;
   rs_tile(in, blockIdx.x, &start, &count);
-  for (uint32_t i = t; i < count; i += RS_THREADS) atomicAdd(&h[(uint32_t)(keys[start + i] >> shift) & dmask], 1u);
+  for (uint32_t i0 = 0; i0 < count; i0 += RS_THREADS) {
+    const uint32_t i = i0 + t;
+    const bool valid = i < count;
+    const uint32_t d = valid ? (uint32_t)(keys[start + i] >> shift) & dmask : 0u;
+    uint32_t rank, cnt;
+    digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
+    if (valid && rank == 0) atomicAdd(&h[d], cnt);
+  }
   __syncthreads();
   if (t <= dmask) hist[(size_t)t * nblocks + blockIdx.x] = h[t];
 }
 
+// Stable scatter of one tile: wave w owns the tile's w-th quarter (RS_ROUNDS
+// rounds of 64 consecutive entries, kept in registers).  Each wave counts its
+// digits, one pass turns the counts into per-wave running offsets, and each
+// wave then writes its entries in order.  Two block barriers per tile.
 template <typename V>
 __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
                                                          RsIn in, uint32_t shift,
                                                          const uint32_t* offs, uint32_t nblocks) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t woff[4][256];
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
   u64 start;
   uint32_t count;
   rs_tile(in, blockIdx.x, &start, &count);
   if (count == 0) return;
   const uint32_t dmask = (1u << in.dbits) - 1u;
-  base[t] = t <= dmask ? offs[(size_t)t * nblocks + blockIdx.x] : 0u;
-  const u64 below = (1ull << lane) - 1ull;
-  const uint32_t rounds = (count + RS_THREADS - 1) / RS_THREADS;
-  for (uint32_t r = 0; r < rounds; ++r) {
-    const uint32_t i = r * RS_THREADS + t;
+  for (uint32_t ww = 0; ww < 4; ++ww) woff[ww][t] = 0u;
+  __syncthreads();
+  const uint32_t wbeg = w * (RS_TILE / 4);
+  u64 kr[RS_ROUNDS];
+  V vr[RS_ROUNDS];
+#pragma unroll
+  for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+    const uint32_t i = wbeg + r * 64u + lane;
     const bool valid = i < count;
-    u64 k = 0;
-    V v = 0;
-    uint32_t d = 0;
-    if (valid) { k = kin[start + i]; v = vin[start + i]; d = (uint32_t)(k >> shift) & dmask; }
-    u64 eq = __ballot(valid);
-    for (uint32_t b = 0; b < in.dbits; ++b) {
-      const u64 bb = __ballot((d >> b) & 1u);
-      eq &= ((d >> b) & 1u) ? bb : ~bb;
+    kr[r] = valid ? kin[start + i] : 0ull;
+    vr[r] = valid ? vin[start + i] : (V)0;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & dmask;
+    uint32_t rank, cnt;
+    digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
+    if (valid && rank == 0) woff[w][d] += cnt;      // one lane per digit: no conflict in the wave
+  }
+  __syncthreads();
+  if (t <= dmask) {
+    uint32_t o = offs[(size_t)t * nblocks + blockIdx.x];
+    for (uint32_t ww = 0; ww < 4; ++ww) {
+      const uint32_t c = woff[ww][t];
+      woff[ww][t] = o;
+      o += c;
     }
-    const uint32_t rank = (uint32_t)__popcll(eq & below);
-    const uint32_t cnt = (uint32_t)__popcll(eq);
-    for (uint32_t ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
-    __syncthreads();
-    if (valid && rank == 0) wcnt[w][d] = cnt;
-    __syncthreads();
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+    const uint32_t i = wbeg + r * 64u + lane;
+    const bool valid = i < count;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & dmask;
+    uint32_t rank, cnt;
+    digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
     if (valid) {
-      uint32_t off = base[d];
-      for (uint32_t ww = 0; ww < w; ++ww) off += wcnt[ww][d];
-      kout[off + rank] = k;
-      vout[off + rank] = v;
+      const uint32_t base = woff[w][d];
+      kout[base + rank] = kr[r];
+      vout[base + rank] = vr[r];
+      // the new offset depends on the value just read, so the wave's read
+      // of this round is complete before any lane advances the counter
+      if (rank == 0) woff[w][d] = base + cnt;
     }
-    __syncthreads();
-    base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
-    __syncthreads();
   }
 }
 

@@ -101,7 +101,17 @@ struct ProgDesc {                 // one program of the call
   uint32_t G, W, nwaves, lds_local_cells;
   uint32_t lds_log_cap, overlay_cells, NI, pad;
   uint64_t wg_log_cap;            // log entries reserved per work-group
+  // LDS interval check by a per-cell table instead of a sort: table entry of
+  // log cell key ck is ck - tab_base; tab_cells = 0 selects the sort
+  uint32_t tab_base, tab_cells, pad2[2];
 };
+
+// one cell's running check state in the LDS table (32 bytes)
+struct TabCell {
+  unsigned long long wmin;   // (writer lid, value ^ sign) minimum
+  uint32_t r1, r2, w2, q, multi1, owner;
+};
+constexpr uint32_t TAB_MAX_CELLS = 4096;
 
 struct SlotDesc {                 // one instance of the call
   uint64_t seed;

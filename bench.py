@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
     ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
     ap.add_argument("--copy-probe", type=float, default=0.0, help="only run a plain copy of this many GiB")
+    ap.add_argument("--no-jit", action="store_true", help="c1/c2/c4: interpret instead of per-program kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,6 +133,8 @@ def main():
         p = B.Program(ctx, w.src)
         p.set_ndrange(w.G, w.W)
         p.bind(w.arrays, w.scalars)
+        if not args.no_jit:
+            p.jit(True)            # compiled here, outside the timed region
         # record capacity from a probe over the first seeds (every record of
         # the timed steps is written out)
         n_probe = min(n, 16)
@@ -203,7 +206,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": desc, "programs": len(runs), "seeds_per_program": runs[0][1],
+        "config": {"workload": desc, "execution": "interpreter" if args.no_jit else "per-program kernels",
+                   "programs": len(runs), "seeds_per_program": runs[0][1],
                    "instances_per_step": sum(n for _, n, _, _ in runs),
                    "accesses_per_step": accesses, "race_records_per_step": records,
                    "racy_instances_per_step": race_instances},

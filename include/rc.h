@@ -183,6 +183,18 @@ rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
 rc_status rc_autotune(rc_prog* prog, uint64_t seed0, uint32_t n_seeds, void* d_ws, size_t ws_bytes,
                       const char* cache_path, rc_tuning* chosen);
 
+/*
+ * Per-program kernel.  enable != 0: translate the program's bytecode into a
+ * kernel of its own (private variables in registers, no instruction
+ * dispatch) and compile it for gfx950 with the runtime compiler (about a
+ * second, synchronous); rc_check calls of this program then run it.  Results
+ * are identical to the interpreter's.  Needs the NDRange; re-compiled when
+ * the work-group size moves to another width class.  rc_batch_check calls
+ * that mix programs always interpret.  enable == 0: back to the interpreter.
+ * RC_E_HIP with the compiler's log if compilation fails.
+ */
+rc_status rc_prog_jit(rc_prog* prog, int enable);
+
 /* ---- checking ----------------------------------------------------------- */
 
 /* Workspace bytes needed to check `n_seeds` instances in one pass.  Smaller

@@ -39,7 +39,7 @@ EXPORTS = [
     "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
     "rc_ctx_profile_read", "rc_prog_set_tuning", "rc_batch_check", "rc_autotune",
     "rc_features_workspace_size", "rc_features", "rc_mlp_workspace_size", "rc_mlp_forward", "rc_mlp_grad",
-    "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank",
+    "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank", "rc_prog_jit",
 ]
 N_FEATURES = 128
 MLP_PARAMS = 99073
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "rc_mlp_workspace_size": ([u32, ctypes.POINTER(sz)], ctypes.c_int),
         "rc_rank_workspace_size": ([u32, ctypes.POINTER(sz)], ctypes.c_int),
         "rc_rank": ([vp, vp, u32, vp, vp, sz], ctypes.c_int),
+        "rc_prog_jit": ([vp, ctypes.c_int], ctypes.c_int),
         "rc_mlp_forward": ([vp, vp, vp, u32, vp, vp, sz], ctypes.c_int),
         "rc_mlp_grad": ([vp, vp, vp, vp, vp, u32, vp, vp, vp, sz], ctypes.c_int),
         "rc_mlp_train_step": ([vp, vp, vp, vp, u32, vp, vp, vp, u32, ctypes.c_float, vp, vp, sz], ctypes.c_int),
@@ -343,6 +344,11 @@ class Program:
             else:
                 _call(_lib.rc_bind_scalar, self._h, sid, ((int(b) + 2 ** 31) % 2 ** 32) - 2 ** 31)
 
+    def jit(self, enable: bool = True):
+        """Compile this program's own kernel (needs the NDRange); single-program
+        checks then run it instead of the interpreter."""
+        _call(_lib.rc_prog_jit, self._h, 1 if enable else 0)
+
     def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0):
         t = _Tuning()
         t.lds_log_entries = lds_log_entries
@@ -408,11 +414,13 @@ def summaries_to_numpy(summ_u8, n: int) -> np.ndarray:
 
 def check(src: str, G: int, W: int, arrays: dict | None = None, scalars: dict | None = None,
           seed0: int = 0, n_seeds: int = 1, cap: int | None = None, ctx: Context | None = None,
-          ws_limit: int = 8 << 30, lds_log_entries: int = 0):
+          ws_limit: int = 8 << 30, lds_log_entries: int = 0, jit: bool = False):
     """Compile, bind and check n_seeds instances; returns numpy (records, summaries)."""
     ctx = ctx or Context()
     prog = Program(ctx, src)
     prog.set_ndrange(G, W)
+    if jit:
+        prog.jit(True)
     if lds_log_entries:
         prog.set_tuning(lds_log_entries)
     prog.bind(arrays, scalars)

@@ -14,6 +14,7 @@
 
 #include "../../include/rc.h"
 #include "frontend.h"
+#include "jit.h"
 #include "kernels.h"
 #include "mlp.h"
 #include "rc_internal.h"
@@ -92,6 +93,12 @@ struct rc_prog {
   uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t lds_log_cap = 0;          // chosen for the current shape
+  // per-program kernel (rc_prog_jit): module of the generated kernel, the
+  // width class it was compiled for, and whether single-program calls use it
+  hipModule_t jit_mod = nullptr;
+  hipFunction_t jit_fn = nullptr;
+  uint32_t jit_class = ~0u;
+  bool jit_on = false;
   // device: code, then tables
   void* d_mem = nullptr;
   size_t off_arrays = 0, off_scalars = 0, off_cellbase = 0, off_size = 0, d_bytes = 0;
@@ -459,11 +466,24 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     P.rec = (rc_record_out*)(ws + L.recout);
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    // a call of one program with a compiled kernel runs that kernel; any
+    // other call runs the interpreter
+    rc_prog* jp = C.progs.size() == 1 && C.progs[0]->jit_on && C.progs[0]->jit_fn ? C.progs[0] : nullptr;
     for (uint32_t c = 0; c < N_WCLASS; ++c) {
       if (!(C.classes_used & (1u << c))) continue;
       P.wclass = c;
       const uint32_t threads = 64u << c;
       const size_t lds = C.class_lds[c];
+      if (jp && jp->jit_class == c) {
+        int occ = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, jp->jit_fn, (int)threads, lds) != hipSuccess ||
+            occ < 1)
+          occ = 1;
+        const uint32_t blocks = std::max<uint32_t>(1, std::min(L.max_items_class[c], (uint32_t)(cus * occ)));
+        void* args[] = {&P};
+        HIP_TRY(hipModuleLaunchKernel(jp->jit_fn, blocks, 1, 1, threads, 1, 1, (unsigned)lds, st, args, nullptr));
+        continue;
+      }
       const uint32_t resident = (uint32_t)cus * (uint32_t)interp_occupancy(threads, lds);
       const uint32_t blocks = std::max<uint32_t>(1, std::min(L.max_items_class[c], resident));
       HIP_TRY(launch_interp(P, blocks, threads, lds, st));
@@ -802,6 +822,7 @@ rc_status rc_prog_load(rc_ctx* ctx, const char* src, size_t len, rc_prog** out) 
 
 rc_status rc_prog_free(rc_prog* p) {
   if (!p) return fail(RC_E_INVAL, "prog is NULL");
+  if (p->jit_mod) (void)hipModuleUnload(p->jit_mod);
   if (p->d_mem) (void)hipFree(p->d_mem);
   delete p;
   return RC_OK;
@@ -834,6 +855,48 @@ rc_status rc_prog_scalar(const rc_prog* p, uint32_t id, char* name, size_t name_
   return RC_OK;
 }
 
+// Generate, compile and load the program's kernel for its current width
+// class (synchronous; the runtime compiler takes about a second).
+static rc_status jit_build(rc_prog* p) {
+  const uint32_t cls = width_class(p->W);
+  const std::string src = jit_source(p->c.code, p->c.nregs, 64u << cls);
+  std::vector<char> obj;
+  std::string log;
+  if (!jit_compile(src, &obj, &log)) {
+    p->jit_on = false;
+    return fail(RC_E_HIP, "runtime compilation of the program kernel failed: %.900s", log.c_str());
+  }
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  hipModule_t mod = nullptr;
+  HIP_TRY(hipModuleLoadData(&mod, obj.data()));
+  hipFunction_t fn = nullptr;
+  hipError_t e = hipModuleGetFunction(&fn, mod, "rc_jit_kernel");
+  if (e != hipSuccess) {
+    (void)hipModuleUnload(mod);
+    return fail(RC_E_HIP, "hipModuleGetFunction: %s", hipGetErrorString(e));
+  }
+  if (p->jit_mod) (void)hipModuleUnload(p->jit_mod);
+  p->jit_mod = mod;
+  p->jit_fn = fn;
+  p->jit_class = cls;
+  p->jit_on = true;
+  return RC_OK;
+}
+
+rc_status rc_prog_jit(rc_prog* p, int enable) {
+  if (!p) return fail(RC_E_INVAL, "prog is NULL");
+  if (!enable) {
+    p->jit_on = false;
+    return RC_OK;
+  }
+  if (!p->shaped) return fail(RC_E_STATE, "set the NDRange before compiling the program kernel");
+  if (p->jit_fn && p->jit_class == width_class(p->W)) {
+    p->jit_on = true;
+    return RC_OK;
+  }
+  return jit_build(p);
+}
+
 rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   if (!p) return fail(RC_E_INVAL, "prog is NULL");
   if (group_size < 1 || group_size > MAX_WG) return fail(RC_E_LIMIT, "group size must be in [1, 1024]");
@@ -849,6 +912,8 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->W = W;
   p->shaped = true;
   p->lds_log_cap = lds_log_entries(p);
+  // a per-program kernel is compiled for one width class
+  if (p->jit_on && p->jit_class != width_class(W)) return jit_build(p);
   return RC_OK;
 }
 

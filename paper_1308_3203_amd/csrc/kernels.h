@@ -7,9 +7,6 @@
 
 namespace rc {
 
-struct rc_record_dev {      // same bytes as rc_record
-  uint32_t instance, gid, interval, array_label, cell, rw_a, rw_b, ww_a, ww_b, pad;
-};
 struct rc_summary_dev {     // same bytes as rc_summary
   unsigned long long n_accesses;
   uint32_t n_race_cells, n_benign_cells, n_intervals;

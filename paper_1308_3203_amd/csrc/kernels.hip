@@ -19,556 +19,28 @@
 
 #include <algorithm>
 
-#include "rc_internal.h"
+#include "item_rt.h"
 #include "kernels.h"
 
 namespace rc {
 
-typedef unsigned long long u64;
-
-// ---------------------------------------------------------------------------
-// seeded inputs: SplitMix64 (Steele, Lea, Flood 2014) in counter form
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t counter) {
-  uint64_t z = seed + counter * 0x9E3779B97F4A7C15ull;
-  z ^= z >> 30;
-  z *= 0xBF58476D1CE4E5B9ull;
-  z ^= z >> 27;
-  z *= 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ int32_t seeded_cell(uint64_t seed, uint32_t stream, uint32_t idx,
-                                                int64_t lo, int64_t hi) {
-  uint64_t hi32 = sm64(seed, ((uint64_t)stream << 32) | ((uint64_t)idx + 1)) >> 32;
-  // stream < 2^17 and idx < 2^24: the counter never carries out of the low word
-  uint64_t scaled = (hi32 * (uint64_t)(hi - lo)) >> 32;
-  return (int32_t)(uint32_t)((uint64_t)lo + scaled);
-}
-
-// ---------------------------------------------------------------------------
-// int32 operators (two's complement, wrapping; division faults on zero)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int32_t alu_bin(uint32_t op, int32_t x, int32_t y, bool& dz) {
-  const uint32_t ux = (uint32_t)x, uy = (uint32_t)y;
-  switch (op) {
-    case B_ADD: return (int32_t)(ux + uy);
-    case B_SUB: return (int32_t)(ux - uy);
-    case B_MUL: return (int32_t)(ux * uy);
-    case B_DIV:
-      if (y == 0) { dz = true; return 0; }
-      if (y == -1) return (int32_t)(0u - ux);
-      return x / y;
-    case B_REM:
-      if (y == 0) { dz = true; return 0; }
-      if (y == -1) return 0;
-      return x % y;
-    case B_MOD: {
-      if (y == 0) { dz = true; return 0; }
-      if (y == -1 || y == 1) return 0;
-      int32_t r = x % y;
-      if (r < 0) r = (int32_t)((uint32_t)r + (y < 0 ? 0u - uy : uy));
-      return r;
-    }
-    case B_AND: return x & y;
-    case B_OR: return x | y;
-    case B_XOR: return x ^ y;
-    case B_SHL: return (int32_t)(ux << (uy & 31u));
-    case B_SHR: return x >> (int32_t)(uy & 31u);
-    case B_LT: return x < y;
-    case B_LE: return x <= y;
-    case B_GT: return x > y;
-    case B_GE: return x >= y;
-    case B_EQ: return x == y;
-    case B_NE: return x != y;
-    case B_LAND: return (x != 0) & (y != 0);
-    case B_LOR: return (x != 0) | (y != 0);
-    case B_MIN: return x < y ? x : y;
-    default: return x > y ? x : y;   // B_MAX
-  }
-}
-
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Reads through the constant address space: with a uniform index these are
-// scalar loads (the code and descriptor tables are never written by kernels).
-struct Insn {
-  uint32_t h, a, b, c;
-};
-template <typename T>
-__device__ __forceinline__ T const_load(const void* base, uint32_t i) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return ((const __attribute__((address_space(4))) T*)base)[i];
-#else
-  return ((const T*)base)[i];   // the host pass only parses device code
-#endif
-}
-
-// fault key: dynamic statement | lid | pc | priority | code  (smaller = earlier)
-// priority orders one item's faults inside a statement: DIV, OOB, the rest.
-__device__ __forceinline__ u64 fault_key(uint32_t step, uint32_t lid, uint32_t pc, uint32_t code) {
-  uint32_t prio = code == F_DIV ? 0u : (code == F_OOB ? 1u : 2u);
-  return ((u64)step << 32) | ((u64)lid << 17) | ((u64)pc << 5) | ((u64)prio << 3) | code;
-}
-
-// ---------------------------------------------------------------------------
-// interval checks (shared by the interpreter's LDS path and the global pass)
-// ---------------------------------------------------------------------------
-struct Pair {
-  uint32_t a, b;
-};
-__device__ __forceinline__ void pair_take(Pair& best, uint32_t x, uint32_t y) {
-  const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
-  if (lo < best.a || (lo == best.a && hi < best.b)) { best.a = lo; best.b = hi; }
-}
-
-__device__ __forceinline__ uint32_t pay_lid(u64 p) { return (uint32_t)p & 1023u; }
-__device__ __forceinline__ bool pay_w(u64 p) { return ((uint32_t)p >> 10) & 1u; }
-__device__ __forceinline__ int32_t pay_val(u64 p) { return (int32_t)(uint32_t)(p >> 32); }
-
-// Both scopes are decided by two passes over a cell's accesses: the first
-// finds the smallest reader and the smallest writer (with its smallest
-// value), the second finds the partners those need.  Every quantity is a
-// minimum or an OR, so a pass can be split over lanes and merged.
-constexpr uint32_t NONE32 = 0xFFFFFFFFu;
-
-struct Pass1 {            // r1: smallest reader; wmin: (writer id, value ^ sign) minimum
-  uint32_t r1;
-  u64 wmin;
-};
-__device__ __forceinline__ Pass1 pass1_init() { return Pass1{NONE32, ~0ull}; }
-__device__ __forceinline__ void pass1_add(Pass1& a, uint32_t id, bool w, int32_t v) {
-  if (w) {
-    const u64 kx = ((u64)id << 32) | ((uint32_t)v ^ 0x80000000u);
-    if (kx < a.wmin) a.wmin = kx;
-  } else if (id < a.r1) {
-    a.r1 = id;
-  }
-}
-
-// INTRA (ids are lids of one group): partners of r1 / w1
-struct Intra2 {
-  uint32_t r2, w2, q, multi1;
-};
-__device__ __forceinline__ Intra2 intra2_init() { return Intra2{NONE32, NONE32, NONE32, 0u}; }
-__device__ __forceinline__ void intra2_add(Intra2& a, uint32_t l, bool w, int32_t v, uint32_t r1, uint32_t w1,
-                                           int32_t x1) {
-  if (w) {
-    if (l == w1) { if (v != x1) a.multi1 = 1u; }
-    else {
-      if (l < a.w2) a.w2 = l;
-      if (v != x1 && l < a.q) a.q = l;
-    }
-  } else if (l != r1 && l < a.r2) {
-    a.r2 = l;
-  }
-}
-__device__ bool intra_finish(const Pass1& p1, const Intra2& p2, uint32_t* label, Pair* rw, Pair* ww) {
-  const uint32_t r1 = p1.r1, w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
-  Pair brw = {NONE32, NONE32}, bww = {NONE32, NONE32};
-  const uint32_t rs[2] = {r1, p2.r2}, ws[2] = {w1, p2.w2};
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      if (rs[i] != NONE32 && ws[j] != NONE32 && rs[i] != ws[j]) pair_take(brw, rs[i], ws[j]);
-  bool wwd = false;
-  if (p2.multi1 && p2.w2 != NONE32) { bww = {w1, p2.w2}; wwd = true; }
-  else if (p2.q != NONE32) { bww = {w1, p2.q}; wwd = true; }
-  uint32_t lab = (brw.a != NONE32 ? 1u : 0u) | (wwd ? 2u : 0u);
-  if (lab == 0u) {
-    if (p2.w2 == NONE32) return false;   // no eligible pair
-    lab = 4u;
-    bww = {w1, p2.w2};
-  }
-  *label = lab;
-  *rw = brw;
-  *ww = bww;
-  return true;
-}
-
-// INTRA scope over entries [s, e) of one work-group (ids compared by lid);
-// get(i) returns entry i's payload: value << 32 | is_write << 10 | lid.
-template <typename Get>
-__device__ bool intra_check(Get get, u64 s, u64 e, uint32_t* label, Pair* rw, Pair* ww) {
-  Pass1 p1 = pass1_init();
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = get(i);
-    pass1_add(p1, pay_lid(p), pay_w(p), pay_val(p));
-  }
-  const uint32_t w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
-  const int32_t x1 = (int32_t)((uint32_t)p1.wmin ^ 0x80000000u);
-  Intra2 p2 = intra2_init();
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = get(i);
-    intra2_add(p2, pay_lid(p), pay_w(p), pay_val(p), p1.r1, w1, x1);
-  }
-  return intra_finish(p1, p2, label, rw, ww);
-}
-
-// INTER (ids are global tids; pairs must come from different groups)
-struct Inter2 {
-  uint32_t r1p, w1p, q, A, multi1;
-};
-__device__ __forceinline__ Inter2 inter2_init() { return Inter2{NONE32, NONE32, NONE32, NONE32, 0u}; }
-__device__ __forceinline__ void inter2_add(Inter2& a, uint32_t t, uint32_t g, bool w, int32_t v, uint32_t gr1,
-                                           uint32_t w1, uint32_t g1, int32_t x1) {
-  if (w) {
-    if (t == w1) { if (v != x1) a.multi1 = 1u; }
-    if (g != g1) {
-      if (t < a.w1p) a.w1p = t;
-      if (v != x1 && t < a.q) a.q = t;
-    } else if (t != w1 && v != x1 && t < a.A) {
-      a.A = t;
-    }
-  } else if (g != gr1 && t < a.r1p) {
-    a.r1p = t;
-  }
-}
-__device__ bool inter_finish(const Pass1& p1, const Inter2& p2, uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
-  const uint32_t r1 = p1.r1, w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
-  Pair brw = {NONE32, NONE32}, bww = {NONE32, NONE32};
-  const uint32_t rs[2] = {r1, p2.r1p}, ws[2] = {w1, p2.w1p};
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      if (rs[i] != NONE32 && ws[j] != NONE32 && rs[i] / W != ws[j] / W) pair_take(brw, rs[i], ws[j]);
-  bool wwd = false;
-  if (p2.multi1 && p2.w1p != NONE32) { bww = {w1, p2.w1p}; wwd = true; }
-  else if (p2.q != NONE32) { bww = {w1, p2.q}; wwd = true; }
-  else if (p2.A != NONE32 && p2.w1p != NONE32) {
-    bww = {p2.A < p2.w1p ? p2.A : p2.w1p, p2.A < p2.w1p ? p2.w1p : p2.A};
-    wwd = true;
-  }
-  uint32_t lab = (brw.a != NONE32 ? 1u : 0u) | (wwd ? 2u : 0u);
-  if (lab == 0u) {
-    if (p2.w1p == NONE32) return false;
-    lab = 4u;
-    bww = {w1, p2.w1p};
-  }
-  *label = lab;
-  *rw = brw;
-  *ww = bww;
-  return true;
-}
-
-// INTER scope over records [s, e) of one cell, all groups (global tids).
-__device__ bool inter_check(const u64* keys, const u64* vals, u64 s, u64 e, uint32_t bk, uint32_t gmask,
-                            uint32_t W, uint32_t* label, Pair* rw, Pair* ww) {
-  Pass1 p1 = pass1_init();
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = vals[i];
-    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
-    pass1_add(p1, g * W + pay_lid(p), pay_w(p), pay_val(p));
-  }
-  const uint32_t w1 = p1.wmin == ~0ull ? NONE32 : (uint32_t)(p1.wmin >> 32);
-  const int32_t x1 = (int32_t)((uint32_t)p1.wmin ^ 0x80000000u);
-  const uint32_t gr1 = p1.r1 == NONE32 ? NONE32 : p1.r1 / W;
-  const uint32_t g1 = w1 == NONE32 ? NONE32 : w1 / W;
-  Inter2 p2 = inter2_init();
-  for (u64 i = s; i < e; ++i) {
-    const u64 p = vals[i];
-    const uint32_t g = (uint32_t)(keys[i] >> bk) & gmask;
-    inter2_add(p2, g * W + pay_lid(p), g, pay_w(p), pay_val(p), gr1, w1, g1, x1);
-  }
-  return inter_finish(p1, p2, W, label, rw, ww);
-}
-
-struct PendingRec {
-  uint32_t gid, interval, aid, cell, cellkey, label, lidbase;
-  Pair rw, ww;
-};
-
-// canonical sort key fields of a record
-struct RecKey {
-  uint32_t bs, bc, G, NI;
-};
-
-__device__ __forceinline__ void store_record(const rc_record_out& R, const RecKey& K, u64 pos, uint32_t slot,
-                                             uint32_t instance, const PendingRec& p, bool inter) {
-  if (pos >= R.rec_cap) { atomicOr(R.status_word, 2u); return; }
-  const uint32_t NONE = 0xFFFFFFFFu;
-  rc_record_dev r;
-  r.instance = instance;
-  r.gid = inter ? NONE : p.gid;
-  r.interval = inter ? 0u : p.interval;
-  r.array_label = p.aid | (p.label << 16);
-  r.cell = p.cell;
-  r.rw_a = p.rw.a == NONE ? NONE : p.rw.a + p.lidbase;
-  r.rw_b = p.rw.b == NONE ? NONE : p.rw.b + p.lidbase;
-  r.ww_a = p.ww.a == NONE ? NONE : p.ww.a + p.lidbase;
-  r.ww_b = p.ww.b == NONE ? NONE : p.ww.b + p.lidbase;
-  r.pad = 0;
-  reinterpret_cast<rc_record_dev*>(R.staging)[pos] = r;
-  const u64 scope = inter ? (u64)K.G * K.NI : (u64)p.gid * K.NI + p.interval;
-  R.rec_keys[pos] = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
-  R.rec_idx[pos] = (uint32_t)pos;
-}
-
-// wave-wide allocation of record slots: one atomic per wave
-__device__ __forceinline__ u64 wave_reserve(unsigned long long* counter, uint32_t n, uint32_t lane) {
-  u64 base = 0;
-  if (lane == 0 && n) base = atomicAdd(counter, (u64)n);
-  const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
-  const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
-  return ((u64)bhi << 32) | blo;
-}
-
-extern __shared__ __attribute__((aligned(16))) unsigned char rc_smem[];
-
-// Everything one work item (an instance's work-group) needs; uniform.
-struct ItemView {
-  const uint32_t* code;
-  const ArrayDesc* arrays;
-  const ScalarDesc* scalars;
-  uint32_t n_arrays, n_global, n_scalars, nregs, G, W, nwaves, lds_local_cells;
-  uint32_t lds_log_cap, overlay_cells, NI, bc, bg, bk, bs, do_log;
-  uint32_t tab_base, tab_cells;
-  u64 wg_log_cap;
-  u64* log_keys;
-  u64* log_vals;
-  uint32_t* status_word;
-  const rc_record_out* rec;
-  u64* inst_acc;
-  uint32_t* inst_intervals;
-  u64* inst_fault;
-  uint32_t* wg_count;
-  u64* wg_base;
-};
-
-// Run one work-group of one instance, lockstep, on the calling workgroup.
-// `slot` indexes the chunk's per-instance counters, `instance` the call's.
-__device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t slot, uint32_t instance,
-                                         uint32_t gid, uint64_t seed, u64 log_base, u64* ovl,
-                                         uint32_t epoch_base, uint32_t wg_index) {
-  const uint32_t tl = threadIdx.x;
-  const uint32_t WP = P.nwaves * 64u;
-  const uint32_t wave = tl >> 6, lane = tl & 63u;
-  const bool real = tl < P.W;
-  const uint32_t tr = tl < WP ? tl : WP - 1u;   // waves past the group read a real lane's registers
-
-  // dynamic LDS after the control block: local array cells (u64), the
-  // interval log (T keys, T payload words, T values), registers
-  u64* locc = reinterpret_cast<u64*>(reinterpret_cast<unsigned char*>(ctl) + ((sizeof(Ctl) + 15) & ~(size_t)15));
-  u64* lkey = locc + P.lds_local_cells;
-  uint32_t* lmeta = reinterpret_cast<uint32_t*>(lkey + P.lds_log_cap);
-  int32_t* lval = reinterpret_cast<int32_t*>(lmeta + P.lds_log_cap);
-  int32_t* regs = lval + P.lds_log_cap;
-  // the per-cell check table (8-byte aligned after the registers)
-  TabCell* tab = reinterpret_cast<TabCell*>(
-      (reinterpret_cast<uintptr_t>(regs + P.nregs * WP) + 7u) & ~(uintptr_t)7u);
-  const TabCell empty_cell = {~0ull, NONE32, NONE32, NONE32, NONE32, 0u, NONE32};
-
-  for (uint32_t i = tl; i < P.lds_local_cells; i += blockDim.x) locc[i] = 0ull;
-  for (uint32_t i = tl; i < P.nregs * WP; i += blockDim.x) regs[i] = 0;
-  for (uint32_t i = tl; i < P.tab_cells; i += blockDim.x) tab[i] = empty_cell;
-  if (tl == 0) ctl->fault = ~0ull;
-  if (tl < P.n_scalars) {
-    const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
-    ctl->scal[tl] = S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
-  }
-  __syncthreads();
-
-  const u64 key_slot = (u64)slot << (P.bc + P.bg + P.bk);
-  u64 log_used = 0;
-  uint32_t lds_used = 0;       // entries of the current interval in the LDS log
-  bool lds_spilled = false;    // the current interval moved to the global log
-  uint32_t pc = 0, depth = 0, eany = 0, last_spc = ~0u;
-  uint32_t step = 0, store_seq = 0, interval = 0, parity = 0;
-  uint32_t mbits = real ? 1u : 0u, ebits = 0u;
-  uint32_t n_acc = 0;
-  u64 my_fault = ~0ull;      // earliest fault of this work-item (fault_key order)
-  bool faulted = false;
+// The bytecode interpreter: one item's program, instruction by instruction,
+// on the Item runtime.  Private variables live in LDS (register-major, so a
+// wave reads 64 consecutive dwords); control flow keeps a mask bit per
+// nesting depth.
+__device__ __forceinline__ void interp_item(Item& it) {
+  const ItemView& P = it.P;
+  int32_t* regs = it.regs;
+  const uint32_t WP = it.WP, tl = it.tl, tr = it.tr, lane = it.lane, wave = it.wave;
+  Ctl* ctl = it.ctl;
+  uint32_t pc = 0, depth = 0, eany = 0;
+  uint32_t mbits = it.real ? 1u : 0u, ebits = 0u;
+  (void)lane;
 
   auto fetch = [&](bool imm, uint32_t w) -> int32_t {
     if (imm) return (int32_t)w;
     if (w < MAX_REGS) return regs[w * WP + tr];
-    switch (w) {
-      case SEL_LID: return (int32_t)tl;
-      case SEL_TID: return (int32_t)(gid * P.W + tl);
-      case SEL_GID: return (int32_t)gid;
-      case SEL_WGSIZE: return (int32_t)P.W;
-      case SEL_NGROUPS: return (int32_t)P.G;
-      case SEL_NTHREADS: return (int32_t)(P.G * P.W);
-      default: return ctl->scal[w - SEL_SCALAR0];
-    }
-  };
-  // Group-wide OR of two per-lane predicates (bits 0, 1) and of "some
-  // work-item has a pending fault" (bit 2).  Every wave publishes its word
-  // before the barrier and reads all words after it, so all waves decide on
-  // the same snapshot.  The words are double-buffered: a wave can only reuse
-  // a buffer after the next reduction's barrier, which every reader passes
-  // after reading.
-  auto group_red = [&](bool p0, bool p1, bool sync_always) -> uint32_t {
-    const u64 b0 = __ballot(p0), b1 = __ballot(p1), bf = __ballot(my_fault != ~0ull);
-    const uint32_t mine = (b0 != 0ull ? 1u : 0u) | (b1 != 0ull ? 2u : 0u) | (bf != 0ull ? 4u : 0u);
-    if (P.nwaves == 1) {
-      if (sync_always) __syncthreads();
-      return uni(mine);
-    }
-    if (lane == 0) ctl->red[parity][wave] = mine;
-    __syncthreads();
-    uint32_t acc = 0;
-    for (uint32_t w = 0; w < P.nwaves; ++w) acc |= ctl->red[parity][w];
-    parity ^= 1u;
-    return uni(acc);
-  };
-  // The same snapshot reduction for a memory statement: bit 0 of each wave's
-  // word is its pending-fault flag, bits 8.. its count of log entries; every
-  // wave gets the group total and the count of the waves before it.
-  auto mem_red = [&](bool rec, u64* brec, uint32_t* prefix, uint32_t* total) -> bool {
-    const u64 br = __ballot(rec), bf = __ballot(my_fault != ~0ull);
-    *brec = br;
-    const uint32_t cnt = (uint32_t)__popcll(br);
-    if (P.nwaves == 1) {
-      __syncthreads();
-      *prefix = 0u;
-      *total = uni(cnt);
-      return bf != 0ull;
-    }
-    if (lane == 0) ctl->red[parity][wave] = (bf != 0ull ? 1u : 0u) | (cnt << 8);
-    __syncthreads();
-    uint32_t f = 0, tot = 0, pre = 0;
-    for (uint32_t w = 0; w < P.nwaves; ++w) {
-      const uint32_t x = ctl->red[parity][w];
-      f |= x & 1u;
-      tot += x >> 8;
-      if (w < wave) pre += x >> 8;
-    }
-    parity ^= 1u;
-    *prefix = uni(pre);
-    *total = uni(tot);
-    return uni(f) != 0u;
-  };
-  auto raise = [&](uint32_t spc, uint32_t code) {
-    const u64 k = fault_key(step, tl, spc, code);
-    if (k < my_fault) my_fault = k;
-  };
-
-  // Close the current interval on the LDS path: sort its log by cell in LDS
-  // (bitonic), then the first entry of every cell's run checks the run
-  // (INTRA scope) and records go to the staging area.  Callers have passed a
-  // barrier since the interval's last access.
-  auto close_interval = [&]() {
-    const uint32_t n = lds_used;
-    const bool spilled = lds_spilled;
-    lds_used = 0;
-    lds_spilled = false;
-    if (spilled || n < 2u) return;
-    const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
-    const RecKey K = {P.bs, P.bc, P.G, P.NI};
-    if (P.tab_cells) {
-      // Per-cell table: the same two passes as intra_check, merged with LDS
-      // atomics; the cell's first log entry (the owner) finishes the check
-      // and clears the cell for the next interval.
-      for (uint32_t i = tl; i < n; i += blockDim.x) {
-        TabCell& c = tab[(uint32_t)(lkey[i] >> 16) - P.tab_base];
-        const uint32_t meta = lmeta[i];
-        const uint32_t l = meta & 1023u;
-        if (meta & 1024u) atomicMin(&c.wmin, ((u64)l << 32) | ((uint32_t)lval[i] ^ 0x80000000u));
-        else atomicMin(&c.r1, l);
-        atomicMin(&c.owner, i);
-      }
-      __syncthreads();
-      for (uint32_t i = tl; i < n; i += blockDim.x) {
-        TabCell& c = tab[(uint32_t)(lkey[i] >> 16) - P.tab_base];
-        const uint32_t meta = lmeta[i];
-        const uint32_t l = meta & 1023u;
-        const u64 wmin = c.wmin;
-        const uint32_t w1 = wmin == ~0ull ? NONE32 : (uint32_t)(wmin >> 32);
-        const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
-        if (meta & 1024u) {
-          const int32_t v = lval[i];
-          if (l == w1) { if (v != x1) atomicOr(&c.multi1, 1u); }
-          else {
-            atomicMin(&c.w2, l);
-            if (v != x1) atomicMin(&c.q, l);
-          }
-        } else if (l != c.r1) {
-          atomicMin(&c.r2, l);
-        }
-      }
-      __syncthreads();
-      for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
-        const uint32_t i = b0 + tl;
-        bool has = false;
-        PendingRec pr;
-        if (i < n) {
-          const uint32_t ck = (uint32_t)(lkey[i] >> 16);
-          TabCell& c = tab[ck - P.tab_base];
-          if (c.owner == i) {
-            const Pass1 p1 = {c.r1, c.wmin};
-            const Intra2 p2 = {c.r2, c.w2, c.q, c.multi1};
-            c = empty_cell;
-            has = intra_finish(p1, p2, &pr.label, &pr.rw, &pr.ww);
-            if (has) {
-              uint32_t aid = 0;
-              for (uint32_t a = 0; a < P.n_arrays; ++a) {
-                const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
-                if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
-              }
-              const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
-              pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
-              pr.cellkey = ck; pr.lidbase = gid * P.W;
-            }
-          }
-        }
-        const u64 m = __ballot(has);
-        if (m != 0ull) {
-          const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
-          if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, instance, pr, false);
-        }
-      }
-      __syncthreads();
-      return;
-    }
-    uint32_t P2 = 2;
-    while (P2 < n) P2 <<= 1;
-    for (uint32_t i = n + tl; i < P2; i += blockDim.x) lkey[i] = ~0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= P2; k <<= 1) {
-      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tl; i < P2; i += blockDim.x) {
-          const uint32_t ixj = i ^ j;
-          if (ixj > i) {
-            const u64 a = lkey[i], b = lkey[ixj];
-            if ((a > b) == ((i & k) == 0u)) { lkey[i] = b; lkey[ixj] = a; }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
-      const uint32_t i = b0 + tl;
-      bool has = false;
-      PendingRec pr;
-      if (i < n) {
-        const u64 ck = lkey[i] >> 16;
-        if (i == 0 || (lkey[i - 1] >> 16) != ck) {
-          uint32_t e = i + 1;
-          while (e < n && (lkey[e] >> 16) == ck) ++e;
-          if (e - i >= 2u) {
-            has = intra_check([&](u64 q) {
-                                const uint32_t ix = (uint32_t)lkey[q] & 0xFFFFu;
-                                return ((u64)(uint32_t)lval[ix] << 32) | lmeta[ix];
-                              }, i, e, &pr.label, &pr.rw, &pr.ww);
-            if (has) {
-              uint32_t aid = 0;
-              for (uint32_t a = 0; a < P.n_arrays; ++a) {
-                const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
-                if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
-              }
-              const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
-              pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = (uint32_t)ck - D.cellbase;
-              pr.cellkey = (uint32_t)ck; pr.lidbase = gid * P.W;
-            }
-          }
-        }
-      }
-      const u64 m = __ballot(has);
-      if (m != 0ull) {
-        const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
-        if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, instance, pr, false);
-      }
-    }
-    __syncthreads();
+    return it.special(w);
   };
 
   for (;;) {
@@ -577,7 +49,7 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
     const uint32_t h = in.h, wa = in.a, wb = in.b, wc = in.c;
     const uint32_t op = h & 63u, sub = (h >> 8) & 63u, dst = (h >> 14) & 63u, spc = h >> 20;
     const bool fa = (h >> 6) & 1u, fb = (h >> 7) & 1u;
-    if (spc != last_spc) { ++step; last_spc = spc; }
+    it.stmt(spc);
     const bool active = (mbits >> depth) & 1u;
 
     if (op == OP_BIN) {
@@ -586,7 +58,7 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
       int32_t r = alu_bin(sub, x, y, dz);
       if (active) {
         regs[dst * WP + tl] = r;
-        if (dz) raise(spc, F_DIV);
+        if (dz) it.raise(spc, F_DIV);
       }
       ++pc;
     } else if (op == OP_UN) {
@@ -595,90 +67,11 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
       if (active) regs[dst * WP + tl] = r;
       ++pc;
     } else if (op == OP_LOAD || op == OP_STORE) {
-      const ArrayDesc A = const_load<ArrayDesc>(P.arrays, wc);
       const int32_t idx = fetch(fa, wa);
       const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;
-      if (active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);
-      const bool rec = active && P.do_log && A.logged != LOG_NONE;
-      // the barrier completes every earlier statement's accesses, publishes
-      // pending faults (a faulting statement has no effect) and each wave's
-      // number of log entries for this statement
-      u64 brec;
-      uint32_t prefix, total;
-      if (mem_red(rec, &brec, &prefix, &total)) { faulted = true; break; }
-      const uint32_t cell = (uint32_t)idx;
-      if (op == OP_LOAD) {
-        if (active) {
-          int32_t v;
-          if (A.kind == AK_LOCAL) {
-            v = (int32_t)(uint32_t)locc[A.offset + cell];
-          } else {
-            bool have = false;
-            v = 0;
-            if (A.kind == AK_GLOBAL_RW) {
-              u64 w = __hip_atomic_load(&ovl[A.offset + cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              if ((uint32_t)(w >> 42) >= epoch_base) { v = (int32_t)(uint32_t)w; have = true; }
-            }
-            if (!have)
-              v = A.bind == BIND_SEEDED ? seeded_cell(seed, wc, cell, A.lo, A.hi) : A.dptr[cell];
-          }
-          regs[dst * WP + tl] = v;
-          ++n_acc;
-        }
-      } else {
-        ++store_seq;
-        if (active) {
-          // within one statement the highest work-item's value stays
-          const uint32_t ep = A.kind == AK_LOCAL ? store_seq : epoch_base + store_seq;
-          const u64 word = ((u64)((ep << 10) | tl) << 32) | (uint32_t)val;
-          if (A.kind == AK_LOCAL) atomicMax(&locc[A.offset + cell], word);
-          else atomicMax(&ovl[A.offset + cell], word);
-          ++n_acc;
-        }
-      }
-      if (total != 0u) {
-        bool to_lds = A.logged == LOG_LDS && !lds_spilled;
-        if (to_lds && lds_used + total > P.lds_log_cap) {
-          // the interval outgrows LDS: move its log to the global log, where
-          // the global pass checks it
-          for (uint32_t i = tl; i < lds_used; i += blockDim.x) {
-            const u64 pos = log_used + i;
-            const u64 ck = lkey[i] >> 16;
-            if (pos < P.wg_log_cap) {
-              P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
-              P.log_vals[log_base + pos] = ((u64)(uint32_t)lval[i] << 32) | lmeta[i];
-            } else {
-              atomicOr(P.status_word, 1u);
-            }
-          }
-          log_used += lds_used;
-          lds_used = 0;
-          lds_spilled = true;
-          to_lds = false;
-        }
-        const uint32_t below = prefix + (uint32_t)__popcll(brec & ((1ull << lane) - 1ull));
-        const uint32_t meta = ((op == OP_STORE) ? 1024u : 0u) | tl;
-        if (to_lds) {
-          if (rec) {
-            const uint32_t j = lds_used + below;
-            lkey[j] = ((u64)(A.cellbase + cell) << 16) | j;
-            lmeta[j] = meta;
-            lval[j] = val;
-          }
-          lds_used += total;
-        } else {
-          if (rec) {
-            const u64 pos = log_used + below;
-            if (pos < P.wg_log_cap) {
-              P.log_keys[log_base + pos] = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
-              P.log_vals[log_base + pos] = ((u64)(uint32_t)val << 32) | meta;
-            } else {
-              atomicOr(P.status_word, 1u);
-            }
-          }
-          log_used += total;
-        }
-      }
+      int32_t v = 0;
+      if (it.mem(op, wc, idx, val, active, spc, v)) { it.faulted = true; break; }
+      if (op == OP_LOAD && active) regs[dst * WP + tl] = v;
       ++pc;
     } else if (op == OP_IF) {
       const int32_t c = fetch(fa, wa);
@@ -686,8 +79,8 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
       const uint32_t d1 = depth + 1u;
       mbits = (mbits & ~(1u << d1)) | ((uint32_t)t << d1);
       ebits = (ebits & ~(1u << d1)) | ((uint32_t)e << d1);
-      const uint32_t any = group_red(t, e, false);
-      if (any & 4u) { faulted = true; break; }
+      const uint32_t any = it.group_red(t, e, false);
+      if (any & 4u) { it.faulted = true; break; }
       depth = d1;
       eany = (eany & ~(1u << d1)) | (((any >> 1) & 1u) << d1);
       pc = (any & 1u) ? pc + 1u : wb;
@@ -703,97 +96,32 @@ __device__ __forceinline__ void run_item(const ItemView& P, Ctl* ctl, uint32_t s
       if ((int64_t)hi - (int64_t)lo <= 0) {
         pc = wc;
       } else {
-        if (lane == 0) ctl->loopctr[wave][sub] = 0u;
+        if (it.lane == 0) ctl->loopctr[wave][sub] = 0u;
         ++pc;
       }
     } else if (op == OP_ENDFOR) {
       const int32_t lo = (int32_t)wa, hi = (int32_t)wb;
       const uint32_t iters = (uint32_t)((int64_t)hi - (int64_t)lo);
       const uint32_t ctr = uni(ctl->loopctr[wave][sub]) + 1u;
-      if (lane == 0) ctl->loopctr[wave][sub] = ctr;
+      if (it.lane == 0) ctl->loopctr[wave][sub] = ctr;
       if (active) regs[dst * WP + tl] = (int32_t)((uint32_t)lo + ctr);
       pc = ctr < iters ? wc : pc + 1u;
     } else if (op == OP_BARRIER) {
-      // every work-item of the group must arrive (bit 0: some are missing)
-      const uint32_t r = group_red(real && !active, active, true);
-      if (r & 4u) { faulted = true; break; }
-      if (r & 1u) {
-        if (real && !active) raise(spc, F_BARDIV);
-        faulted = true;
-        break;
-      }
-      if (P.do_log) close_interval();
-      ++interval;
+      if (it.barrier(active, spc)) { it.faulted = true; break; }
       ++pc;
     } else if (op == OP_ASSERT || op == OP_ASSUME) {
       const int32_t c = fetch(fa, wa);
-      if (active && c == 0) raise(spc, op == OP_ASSERT ? F_ASSERT : F_ASSUME);
+      if (active && c == 0) it.raise(spc, op == OP_ASSERT ? F_ASSERT : F_ASSUME);
       ++pc;
     } else {  // OP_END
-      if (group_red(false, false, true) & 4u) faulted = true;
+      if (it.end()) it.faulted = true;
       break;
     }
   }
-
-  // every wave leaves the loop at the same point; the earliest fault wins.
-  // The last interval (complete, or cut short by the fault) is checked.
-  if (faulted) {
-    if (my_fault != ~0ull) atomicMin(&ctl->fault, my_fault);
-    __syncthreads();
-  }
-  if (P.do_log) close_interval();
-  // the last interval (complete, or cut by a fault) is closed
-  if (tl == 0) {
-    P.wg_count[wg_index] = (uint32_t)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
-    P.wg_base[wg_index] = log_base;
-    atomicAdd(&P.inst_intervals[slot], interval + 1u);
-    if (faulted) {
-      const u64 f = ctl->fault;
-      const uint32_t lid = (uint32_t)(f >> 17) & 1023u, fpc = (uint32_t)(f >> 5) & 4095u, code = (uint32_t)f & 7u;
-      // instance status: the lowest faulting work-group
-      atomicMin(&P.inst_fault[slot], ((u64)gid << 38) | ((u64)fpc << 26) | ((u64)lid << 16) | code);
-    }
-  }
-  // accesses of the group
-  u64 acc = n_acc;
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
-  if (lane == 0 && acc) atomicAdd(&P.inst_acc[slot], acc);
-  __syncthreads();
 }
 
-// Persistent interpreter: the workgroups of one width class take work items
-// (an instance's work-group) from the chunk's queue until it is empty.  The
-// queue is ordered longest-first, so stealing in order balances the tail.
 __global__ __launch_bounds__(1024) void rc_interp_kernel(PassParams PP) {
-  Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
-  const uint32_t ci = const_load<uint32_t>(PP.chunk_index, 0);
-  const ChunkDesc C = const_load<ChunkDesc>(PP.chunks, ci);
-  const uint32_t i0 = C.item0[PP.wclass], i1 = C.item0[PP.wclass + 1];
-  if (i0 == i1) return;
-  for (;;) {
-    if (threadIdx.x == 0) ctl->item = i0 + atomicAdd(&PP.queue[PP.wclass], 1u);
-    __syncthreads();
-    const uint32_t item = uni(ctl->item);
-    __syncthreads();
-    if (item >= i1) break;
-    const uint32_t instance = const_load<uint32_t>(PP.items, 2u * item);
-    const uint32_t gid = const_load<uint32_t>(PP.items, 2u * item + 1u);
-    const SlotDesc S = const_load<SlotDesc>(PP.slots, instance);
-    const ProgDesc D = const_load<ProgDesc>(PP.progs, S.prog);
-    ItemView P;
-    P.code = D.code; P.arrays = D.arrays; P.scalars = D.scalars;
-    P.n_arrays = D.n_arrays; P.n_global = D.n_global; P.n_scalars = D.n_scalars; P.nregs = D.nregs;
-    P.G = D.G; P.W = D.W; P.nwaves = D.nwaves; P.lds_local_cells = D.lds_local_cells;
-    P.lds_log_cap = D.lds_log_cap; P.overlay_cells = D.overlay_cells; P.NI = D.NI;
-    P.tab_base = D.tab_base; P.tab_cells = D.tab_cells;
-    P.bc = PP.bc; P.bg = PP.bg; P.bk = PP.bk; P.bs = PP.bs; P.do_log = PP.do_log;
-    P.wg_log_cap = D.wg_log_cap;
-    P.log_keys = PP.log_keys; P.log_vals = PP.log_vals; P.status_word = PP.status_word; P.rec = PP.rec;
-    P.inst_acc = PP.inst_acc; P.inst_intervals = PP.inst_intervals; P.inst_fault = PP.inst_fault;
-    P.wg_count = PP.wg_count; P.wg_base = PP.wg_base;
-    run_item(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,
-             PP.overlay + S.ovl_base + (u64)gid * D.overlay_cells, C.epoch, S.wg_base + gid);
-  }
+  run_items(PP, [](Item& it) { interp_item(it); });
 }
 
 // ---------------------------------------------------------------------------

@@ -152,6 +152,10 @@ struct PassParams {
   struct rc_record_out* rec;      // record staging
 };
 
+struct rc_record_dev {      // same bytes as rc_record
+  uint32_t instance, gid, interval, array_label, cell, rw_a, rw_b, ww_a, ww_b, pad;
+};
+
 // Record output shared by the interval checks (interpreter and global pass).
 struct rc_record_out {
   void* staging;                       // rc_record[rec_cap]

@@ -18,9 +18,9 @@ def ctx():
 
 
 def gpu_run(src, G, W, arrays=None, scalars=None, seed0=0, n=1, cap=1 << 20, ws_limit=4 << 30,
-            lds_log_entries=0):
+            lds_log_entries=0, jit=False):
     return B.check(src, G, W, arrays=arrays, scalars=scalars, seed0=seed0, n_seeds=n, cap=cap,
-                   ctx=ctx(), ws_limit=ws_limit, lds_log_entries=lds_log_entries)
+                   ctx=ctx(), ws_limit=ws_limit, lds_log_entries=lds_log_entries, jit=jit)
 
 
 def oracle_run(src, G, W, arrays=None, scalars=None, seed0=0, n=1):

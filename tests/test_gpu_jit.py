@@ -1,0 +1,89 @@
+"""GPU parity of the per-program kernels (rc_prog_jit): the same oracle
+comparisons as the interpreter's, with each program translated to its own
+kernel.  Every program is compiled once per work-group width class."""
+import random
+
+import numpy as np
+import pytest
+
+from paper_1308_3203_amd import binding as B
+from paper_1308_3203_amd import workloads as WL
+from tests import gpu_util as U
+from tests import interleave as IL
+from tests.test_gpu_parity import CONTROL, FAULTS
+
+pytestmark = pytest.mark.gpu
+
+
+def both(src, G, W, arrays=None, scalars=None, seed0=0, n=1, **kw):
+    dev_arrays = U.host_arrays_to_device(arrays)
+    g = U.gpu_run(src, G, W, dev_arrays, scalars, seed0, n, jit=True, **kw)
+    o = U.oracle_run(src, G, W, arrays, scalars, seed0, n)
+    return g, o
+
+
+@pytest.mark.parametrize("n,one_based", [(64, True), (65, True), (200, False)])
+def test_fig1(n, one_based):
+    w = WL.fig1(n, one_based)
+    U.assert_same(*both(w.src, w.G, w.W, w.arrays, n=3), w.name)
+
+
+def test_fig3():
+    w = WL.fig3(100)
+    U.assert_same(*both(w.src, w.G, w.W, w.arrays, seed0=5, n=8), w.name)
+
+
+def test_c1_all_seeds():
+    w = WL.c1_kernel(1)
+    U.assert_same(*both(w.src, w.G, w.W, w.arrays, seed0=0, n=1000), "c1")
+
+
+@pytest.mark.parametrize("G,W", [(1, 7), (1, 65), (3, 130), (2, 300), (1, 900), (4, 1024)])
+def test_random_shapes(G, W):
+    r = random.Random(7 * W + G)
+    prog, arrays, vars_ = IL.random_program(r, r.randint(6, 12), r.choice([4, 16, 64]), r.randint(1, 3))
+    src = IL.render(prog, arrays, vars_)
+    U.assert_same(*both(src, G, W, {a: ("seeded", 0, 4) for a in arrays}, seed0=3, n=4), f"G={G} W={W}\n{src}")
+
+
+@pytest.mark.parametrize("src", FAULTS)
+def test_faults(src):
+    for G, W in [(1, 8), (4, 130)]:
+        U.assert_same(*both(src, G, W, {"A": ("seeded", 0, 16)}, n=2), f"{src} G={G} W={W}")
+
+
+@pytest.mark.parametrize("src", CONTROL)
+def test_control_flow(src):
+    scal = {"s": ("seeded", -1000, 1000), "t": 7} if "int s" in src else None
+    arrays = {"A": ("seeded", 0, 16)} | ({"B": ("seeded", 0, 16)} if "B[" in src else {})
+    for G, W in [(1, 64), (3, 257)]:
+        U.assert_same(*both(src, G, W, arrays, scal, seed0=9, n=3), f"{src} G={G} W={W}")
+
+
+@pytest.mark.parametrize("w", WL.c2_templates(), ids=lambda w: w.name)
+def test_c2_templates(w):
+    U.assert_same(*both(w.src, w.G, w.W, w.arrays, w.scalars, seed0=11, n=3), w.name)
+
+
+def test_c4_scaled():
+    w = WL.c4_kernel(groups=4, wgsize=256, iters=8, log2_cells=12)
+    U.assert_same(*both(w.src, w.G, w.W, w.arrays, w.scalars, seed0=2, n=2), w.name)
+
+
+def test_jit_and_interpreter_agree_across_width_change():
+    """A program re-shaped into another width class is recompiled; results
+    match the interpreter's byte for byte."""
+    w = WL.c1_kernel(3)
+    p = B.Program(U.ctx(), w.src)
+    p.bind(w.arrays, w.scalars)
+    for W in (64, 200):
+        p.set_ndrange(1, W)
+        outs = []
+        for jit in (False, True):
+            p.jit(jit)
+            buf = B.Buffers(p, 16, 1 << 16)
+            p.check_async(0, 16, buf.ws, buf.records, buf.n_records, buf.summaries)
+            U.ctx().sync()
+            n = int(buf.n_records.item())
+            outs.append((B.records_to_numpy(buf.records, n).tobytes(), B.summaries_to_numpy(buf.summaries, 16).tobytes()))
+        assert outs[0] == outs[1], W

@@ -251,6 +251,11 @@ struct Layout {
   size_t lk0 = 0, lv0 = 0, lk1 = 0, lv1 = 0, hist = 0, stage = 0, rk0 = 0, ri0 = 0, rk1 = 0, ri1 = 0;
   size_t longq = 0;
   u64 long_cap = 0;
+  // per-(slot, cell) owner words of the global log (cc_stride cells per
+  // slot), when the table is small beside the log it filters
+  size_t cc = 0;
+  uint32_t cc_stride = 0;
+  bool filter = false;
   size_t total = 0;
 };
 
@@ -286,6 +291,7 @@ void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n
   L->lv1 = take(L->max_log * 8);
   L->long_cap = 2 * L->max_log / (SEG_SHORT_RUN + 1) + 2;
   L->longq = take(L->long_cap * 16);
+  L->cc = take(L->filter ? (size_t)L->max_slots * L->cc_stride * 4 : 0);
   L->hist = take(std::max(sort_log_hist_words(L->max_wg, L->max_log), sort_hist_words(L->max_rec)) * 4);
   L->stage = take(L->max_rec * sizeof(rc_record));
   L->rk0 = take(L->max_rec * 8);
@@ -372,7 +378,7 @@ void partition(Call& C, const Layout& lim) {
 bool plan(Call& C, size_t ws_bytes, std::string* why) {
   const uint32_t N = (uint32_t)C.inst_prog.size();
   u64 T_log = 0, T_rec = 0, T_ovl = 0, T_wg = 0, M_log = 0, M_rec = 0, M_ovl = 0, M_wg = 0;
-  uint32_t bc = 0, bg = 0, bk = 0, bs = 0;
+  uint32_t bc = 0, bg = 0, bk = 0, bs = 0, max_cells = 0;
   u64 max_stores = 0, items_total = 0;
   for (uint32_t i = 0; i < N; ++i) {
     const Need nd = need_of(C.progs[C.inst_prog[i]]);
@@ -384,6 +390,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
   C.classes_used = 0;
   for (rc_prog* p : C.progs) {
     bc = std::max(bc, bits_for(std::max<u64>(1, p->n_logged_cells)));
+    max_cells = std::max(max_cells, p->n_logged_cells);
     bg = std::max(bg, bits_for(p->G));
     bk = std::max(bk, bits_for(p->c.max_intervals));
     bs = std::max(bs, bits_for((u64)p->G * p->c.max_intervals + 1));
@@ -409,6 +416,9 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     L.bc = bc; L.bg = bg; L.bk = bk; L.bs = bs;
     L.nbits_log = L.bi + bc + bg + bk;
     L.nbits_rec = L.bi + bs + bc;
+    L.cc_stride = std::max<uint32_t>(1, max_cells);
+    // a count word costs less than one entry's log and sort traffic
+    L.filter = L.max_log >= 4096 && (u64)L.max_slots * L.cc_stride <= 4 * L.max_log && bg <= 21;
     if (L.nbits_log > 64 || L.nbits_rec > 64) { *why = "sort key wider than 64 bits"; return false; }
     Layout lim = L;
     partition(C, lim);
@@ -464,6 +474,9 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     P.inst_acc = (u64*)(ws + L.inst_acc); P.inst_intervals = (uint32_t*)(ws + L.inst_int);
     P.inst_fault = (u64*)(ws + L.inst_fault); P.status_word = (uint32_t*)(cnt + CNT_STATUS);
     P.rec = (rc_record_out*)(ws + L.recout);
+    // owner words need no clearing: each is written before it is read
+    P.cell_owner = (L.filter && do_log) ? (uint32_t*)(ws + L.cc) : nullptr;
+    P.cell_owner_stride = L.cc_stride;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     // a call of one program with a compiled kernel runs that kernel; any
@@ -501,7 +514,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     HIP_TRY(sort_log(lk0, lv0, lk1, lv1, cnt + CNT_LOG, L.max_log, L.nbits_log, L.bg + L.bk,
                      (const uint32_t*)(ws + L.wg_count),
                      (const u64*)(ws + L.wg_base), (uint32_t*)(ws + L.tiles), L.max_wg, (uint32_t*)(ws + L.hist),
-                     C.radix_bits, st, &second));
+                     C.radix_bits, st, &second, L.filter ? (const uint32_t*)(ws + L.cc) : nullptr, L.cc_stride, L.bc, L.bk));
   }
   {
     PhaseTimer t(ctx, st, 2, timed);

@@ -320,6 +320,8 @@ struct ItemView {
   u64* inst_fault;
   uint32_t* wg_count;
   u64* wg_base;
+  uint32_t* cell_owner;    // see PassParams
+  uint32_t co_stride;
 };
 
 __device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE32, NONE32, NONE32, NONE32, 0u, NONE32}; }
@@ -649,6 +651,7 @@ struct Item {
           if (pos < P.wg_log_cap) {
             P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
             P.log_vals[log_base + pos] = ((u64)(uint32_t)lval[i] << 32) | lmeta[i];
+            if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (lmeta[i] & 1023u);
           } else {
             atomicOr(P.status_word, 1u);
           }
@@ -674,6 +677,7 @@ struct Item {
           if (pos < P.wg_log_cap) {
             P.log_keys[log_base + pos] = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
             P.log_vals[log_base + pos] = ((u64)(uint32_t)val << 32) | meta;
+            if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + A.cellbase + cell] = (gid << 10) | tl;
           } else {
             atomicOr(P.status_word, 1u);
           }
@@ -762,6 +766,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.log_keys = PP.log_keys; P.log_vals = PP.log_vals; P.status_word = PP.status_word; P.rec = PP.rec;
     P.inst_acc = PP.inst_acc; P.inst_intervals = PP.inst_intervals; P.inst_fault = PP.inst_fault;
     P.wg_count = PP.wg_count; P.wg_base = PP.wg_base;
+    P.cell_owner = PP.cell_owner; P.co_stride = PP.cell_owner_stride;
     Item it;
     it.init(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,
             PP.overlay + S.ovl_base + (u64)gid * D.overlay_cells, C.epoch, S.wg_base + gid);

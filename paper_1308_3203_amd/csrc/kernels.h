@@ -103,11 +103,17 @@ size_t sort_log_hist_words(unsigned long long n_regions, unsigned long long cap)
 // becomes part of one dense array, stably sorted by key bits
 // [start_bit, nbits); *n_ptr (zero on entry) receives the number of entries;
 // tiles holds n_regions + 1 words of scratch.  Bits below start_bit keep the
-// regions' order (region by region, each in its own order).
+// regions' order (region by region, each in its own order).  With `keep`
+// (owner words per (slot, cell key), keep_stride cells per slot, the cell key
+// of keep_bc bits at start_bit, group and interval fields below it, the
+// interval keep_bk bits wide), entries of cells touched by one work-item only
+// are dropped first and *n_ptr becomes the number kept.
 hipError_t sort_log(unsigned long long* k0, unsigned long long* v0, unsigned long long* k1, unsigned long long* v1,
                     const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits, uint32_t start_bit,
                     const uint32_t* seg_count, const unsigned long long* seg_base, uint32_t* tiles,
-                    unsigned long long n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second);
+                    unsigned long long n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second,
+                    const uint32_t* keep = nullptr, uint32_t keep_stride = 0, uint32_t keep_bc = 0,
+                    uint32_t keep_bk = 0);
 hipError_t sort_pairs_u32(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1,
                           const unsigned long long* n_ptr, unsigned long long cap, uint32_t nbits,
                           uint32_t* hist, hipStream_t st, int* in_second);

@@ -187,7 +187,22 @@ struct RsIn {
   const u64* seg_base;
   const uint32_t* tiles;
   uint32_t n_regions, dbits;   // dbits: digit width of this pass (1..8)
+  // filter pass: the 1-bit digit is 0 for entries of cells whose owner word
+  // says OWNER_SHARED (kept) and 1 otherwise; the cell key is key >> keep_low
+  // (keep_bc bits), the slot the bits above it
+  const uint32_t* keep;
+  uint32_t keep_stride, keep_low, keep_bc, keep_bk;
 };
+
+__device__ __forceinline__ uint32_t rs_digit(const RsIn& in, u64 k, uint32_t shift, uint32_t dmask) {
+  if (in.keep) {
+    const u64 cmask = in.keep_bc >= 32 ? 0xFFFFFFFFull : ((1ull << in.keep_bc) - 1ull);
+    const u64 cell = (k >> in.keep_low) & cmask;
+    const u64 slot = k >> (in.keep_low + in.keep_bc);
+    return in.keep[slot * in.keep_stride + cell] == OWNER_SHARED ? 0u : 1u;
+  }
+  return (uint32_t)(k >> shift) & dmask;
+}
 
 __device__ __forceinline__ void rs_tile(const RsIn& in, uint32_t b, u64* start, uint32_t* count) {
   if (in.seg_count == nullptr) {
@@ -245,7 +260,7 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, 
   for (uint32_t i0 = 0; i0 < count; i0 += RS_THREADS) {
     const uint32_t i = i0 + t;
     const bool valid = i < count;
-    const uint32_t d = valid ? (uint32_t)(keys[start + i] >> shift) & dmask : 0u;
+    const uint32_t d = valid ? rs_digit(in, keys[start + i], shift, dmask) : 0u;
     uint32_t rank, cnt;
     digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
     if (valid && rank == 0) atomicAdd(&h[d], cnt);
@@ -280,7 +295,7 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
     const bool valid = i < count;
     kr[r] = valid ? kin[start + i] : 0ull;
     vr[r] = valid ? vin[start + i] : (V)0;
-    const uint32_t d = (uint32_t)(kr[r] >> shift) & dmask;
+    const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
     uint32_t rank, cnt;
     digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
     if (valid && rank == 0) woff[w][d] += cnt;      // one lane per digit: no conflict in the wave
@@ -299,7 +314,7 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
   for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
     const uint32_t i = wbeg + r * 64u + lane;
     const bool valid = i < count;
-    const uint32_t d = (uint32_t)(kr[r] >> shift) & dmask;
+    const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
     uint32_t rank, cnt;
     digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
     if (valid) {
@@ -751,15 +766,65 @@ size_t sort_log_hist_words(u64 n_regions, u64 cap) {
   return m + scan_tmp_words(std::max<u64>(m, n_regions + 1));
 }
 
+// Second owner pass over the log regions: the interpreter stored, for every
+// logged access, its work-item id into the cell's owner word (one of the
+// stores survives).  An entry whose id differs from the stored one marks the
+// cell shared; a cell touched by a single work-item keeps its id.
+__global__ __launch_bounds__(256) void mark_shared_kernel(const u64* keys, const u64* vals, RsIn in,
+                                                          uint32_t* owner) {
+  u64 start;
+  uint32_t count;
+  rs_tile(in, blockIdx.x, &start, &count);
+  const u64 cmask = in.keep_bc >= 32 ? 0xFFFFFFFFull : ((1ull << in.keep_bc) - 1ull);
+  const uint32_t gmask = in.keep_low > in.keep_bk ? ((1u << (in.keep_low - in.keep_bk)) - 1u) : 0u;
+  for (uint32_t i = threadIdx.x; i < count; i += RS_THREADS) {
+    const u64 k = keys[start + i];
+    const u64 cell = (k >> in.keep_low) & cmask;
+    const u64 slot = k >> (in.keep_low + in.keep_bc);
+    const uint32_t id = ((((uint32_t)(k >> in.keep_bk)) & gmask) << 10) | ((uint32_t)vals[start + i] & 1023u);
+    uint32_t* w = (uint32_t*)&in.keep[slot * in.keep_stride + cell];
+    if (*w != id) *w = OWNER_SHARED;
+  }
+  (void)owner;
+}
+
+// after a filter pass: the exclusive digit-major scan holds the number of
+// kept (digit 0) entries at the first digit-1 slot
+__global__ void kept_count_kernel(const uint32_t* hist, uint32_t nblocks, u64* n_ptr) { *n_ptr = hist[nblocks]; }
+
 template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
                                   const uint32_t* seg_count, const u64* seg_base, const uint32_t* tiles,
                                   u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st,
-                                  int* result_in_second, uint32_t start_bit = 0) {
+                                  int* result_in_second, uint32_t start_bit = 0, const RsIn* filter = nullptr) {
   u64 *ka = k0, *kb = k1;
   V *va = v0, *vb = v1;
   int passes = 0;
   if (dbits < 1 || dbits > 8) dbits = 8;
+  if (filter && seg_count) {
+    // stable partition of the regions: entries of cells touched at least
+    // twice first, in region order; the rest is dropped
+    RsIn in = *filter;
+    in.n_ptr = n_ptr;
+    in.dbits = 1;
+    in.seg_count = seg_count;
+    in.seg_base = seg_base;
+    in.tiles = tiles;
+    in.n_regions = (uint32_t)n_regions;
+    const uint32_t nb = (uint32_t)std::max<u64>(1, seg_blocks(n_regions, cap));
+    uint32_t* tmp = hist + 2ull * nb;
+    hipLaunchKernelGGL(mark_shared_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const u64*)va, in,
+                       (uint32_t*)in.keep);
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, in, 0u, hist, nb);
+    scan_excl(hist, 2ull * nb, tmp, st);
+    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
+                       vb, in, 0u, (const uint32_t*)hist, nb);
+    hipLaunchKernelGGL(kept_count_kernel, dim3(1), dim3(1), 0, st, (const uint32_t*)hist, nb, (u64*)n_ptr);
+    u64* tk = ka; ka = kb; kb = tk;
+    V* tv = va; va = vb; vb = tv;
+    ++passes;
+    seg_count = nullptr;     // the rest is dense
+  }
   // passes of dbits each over bits [start_bit, nbits); a segmented input
   // always takes at least one pass, which also makes it dense
   const uint32_t want = seg_count ? std::max(nbits, start_bit + 1) : nbits;
@@ -795,15 +860,23 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
 
 hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
                     uint32_t start_bit, const uint32_t* seg_count, const u64* seg_base, uint32_t* tiles,
-                    u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second) {
+                    u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st, int* in_second,
+                    const uint32_t* keep, uint32_t keep_stride, uint32_t keep_bc, uint32_t keep_bk) {
   // the number of entries, and the regions' tile prefix
   hipLaunchKernelGGL(sum_u32_kernel, dim3(n_regions > 65536 ? 1024 : (uint32_t)blocks_for(n_regions, 256)),
                      dim3(256), 0, st, seg_count, n_regions, (u64*)n_ptr);
   hipLaunchKernelGGL(region_tiles_kernel, dim3(blocks_for(n_regions + 1, 256)), dim3(256), 0, st, seg_count,
                      tiles, n_regions);
   scan_excl(tiles, n_regions + 1, hist, st);
+  RsIn f;
+  memset(&f, 0, sizeof f);
+  f.keep = keep;
+  f.keep_stride = keep_stride;
+  f.keep_low = start_bit;
+  f.keep_bc = keep_bc;
+  f.keep_bk = keep_bk;
   return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, seg_base, tiles, n_regions, hist, dbits,
-                              st, in_second, start_bit);
+                              st, in_second, start_bit, keep ? &f : nullptr);
 }
 hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {

@@ -150,7 +150,14 @@ struct PassParams {
   unsigned long long* inst_fault; // [chunk slot] min (gid, pc, lid, code) key
   uint32_t* status_word;          // bit 0: internal log overflow
   struct rc_record_out* rec;      // record staging
+  // owner word per (chunk slot, log cell key) of the global log, or null:
+  // every logged access stores its work-item id (gid << 10 | lid) there;
+  // the log sort later keeps only cells touched by two work-items (no other
+  // cell can hold an eligible pair in any scope)
+  uint32_t* cell_owner;
+  uint32_t cell_owner_stride, pad_co;
 };
+constexpr uint32_t OWNER_SHARED = 0xFFFFFFFFu;
 
 struct rc_record_dev {      // same bytes as rc_record
   uint32_t instance, gid, interval, array_label, cell, rw_a, rw_b, ww_a, ww_b, pad;

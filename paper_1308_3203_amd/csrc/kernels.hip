@@ -379,7 +379,7 @@ __device__ __forceinline__ SegHead seg_head(const SegParams& S, u64 k) {
   h.slot = (uint32_t)(k >> (low + S.bc));
   h.gid = (uint32_t)(k >> S.bk) & ((1u << S.bg) - 1u);
   h.interval = (uint32_t)k & ((1u << S.bk) - 1u);
-  const ChunkDesc C = S.chunks[*S.chunk_index];
+  const ChunkDesc C = const_load<ChunkDesc>(S.chunks, const_load<uint32_t>(S.chunk_index, 0));
   h.instance = C.slot0 + h.slot;
   const ProgDesc& D = S.progs[S.slots[h.instance].prog];
   h.G = D.G;
@@ -418,10 +418,13 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
     if (i < n) {
       const u64 k = S.keys[i];
       const bool sub_head = i == 0 || S.keys[i - 1] != k;
-      if (sub_head) {
-        const bool head = i == 0 || (S.keys[i - 1] >> low) != (k >> low);
+      const bool head = sub_head && (i == 0 || (S.keys[i - 1] >> low) != (k >> low));
+      // run ends first (keys only): a head whose runs hold a single entry has
+      // nothing to check and skips the descriptor loads
+      const u64 e = sub_head ? run_end(S.keys, i, n, 0) : i;
+      const u64 f = head ? run_end(S.keys, i, n, low) : i;
+      if (sub_head && (e - i >= 2 || f - i >= 2)) {
         H = seg_head(S, k);
-        const u64 e = run_end(S.keys, i, n, 0);
         if (e - i >= 2) {
           if (e - i <= SEG_SHORT) {
             const u64* vals = S.vals;
@@ -433,7 +436,6 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
           }
         }
         if (head && H.G > 1 && H.aid < H.n_global) {
-          const u64 f = run_end(S.keys, i, n, low);
           if (f - i >= 2) {
             if (f - i <= SEG_SHORT) {
               has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, H.W, &pb.label, &pb.rw, &pb.ww);

@@ -270,6 +270,26 @@ struct RecKey {
   uint32_t bs, bc, G, NI;
 };
 
+// the record of a finished check and its canonical sort key
+__device__ __forceinline__ rc_record_dev make_record(const RecKey& K, uint32_t slot, uint32_t instance,
+                                                     const PendingRec& p, bool inter, u64* key) {
+  const uint32_t NONE = 0xFFFFFFFFu;
+  rc_record_dev r;
+  r.instance = instance;
+  r.gid = inter ? NONE : p.gid;
+  r.interval = inter ? 0u : p.interval;
+  r.array_label = p.aid | (p.label << 16);
+  r.cell = p.cell;
+  r.rw_a = p.rw.a == NONE ? NONE : p.rw.a + p.lidbase;
+  r.rw_b = p.rw.b == NONE ? NONE : p.rw.b + p.lidbase;
+  r.ww_a = p.ww.a == NONE ? NONE : p.ww.a + p.lidbase;
+  r.ww_b = p.ww.b == NONE ? NONE : p.ww.b + p.lidbase;
+  r.pad = 0;
+  const u64 scope = inter ? (u64)K.G * K.NI : (u64)p.gid * K.NI + p.interval;
+  *key = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
+  return r;
+}
+
 __device__ __forceinline__ void store_record(const rc_record_out& R, const RecKey& K, u64 pos, uint32_t slot,
                                              uint32_t instance, const PendingRec& p, bool inter) {
   if (pos >= R.rec_cap) { atomicOr(R.status_word, 2u); return; }

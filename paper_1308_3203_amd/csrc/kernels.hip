@@ -404,59 +404,251 @@ __device__ __forceinline__ void push_long(const SegParams& S, u64 s, u64 e, bool
   }
 }
 
+// Segmented inclusive minimum over the lanes of a wave: `heads` has a bit
+// per lane that starts a run; each lane ends with the minimum of its run up
+// to itself, so a run's last lane holds the run's minimum.
+__device__ __forceinline__ uint32_t seg_min_u32(uint32_t v, u64 heads, uint32_t lane) {
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off);
+    // lanes (lane - off, lane] hold no run head: the source is in this run
+    if (lane >= off && ((heads >> (lane + 1u - off)) & ((1ull << off) - 1ull)) == 0ull) v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ u64 seg_min_u64(u64 v, u64 heads, uint32_t lane) {
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t lo = __shfl_up((uint32_t)v, off), hi = __shfl_up((uint32_t)(v >> 32), off);
+    const u64 o = ((u64)hi << 32) | lo;
+    if (lane >= off && ((heads >> (lane + 1u - off)) & ((1ull << off) - 1ull)) == 0ull) v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ u64 shfl_u64(u64 v, uint32_t src) {
+  const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
+// Both passes of the runs that lie inside the wave's window, for one scope:
+// `heads` marks run starts (bit 64 of the window = the entry after it, when
+// a run reaches the window's end it is not complete here and is skipped by
+// the caller), id = lid (INTRA) or gid << 10 | lid (INTER; ids of one group
+// share id >> 10).  Every lane returns its run's reductions; `inter` selects
+// the rules.
+struct RunSums {
+  Pass1 p1;
+  uint32_t a, b, q, A, multi1;   // INTRA: r2, w2, q; INTER: r1', w1', q, A
+};
+__device__ __forceinline__ RunSums window_runs(bool valid, uint32_t id, bool w, int32_t v, u64 heads,
+                                               uint32_t last, uint32_t lane, bool inter) {
+  RunSums r;
+  // pass 1
+  uint32_t r1 = valid && !w ? id : NONE32;
+  u64 wm = valid && w ? (((u64)id << 32) | ((uint32_t)v ^ 0x80000000u)) : ~0ull;
+  r1 = __shfl(seg_min_u32(r1, heads, lane), last);
+  wm = shfl_u64(seg_min_u64(wm, heads, lane), last);
+  r.p1.r1 = r1;
+  r.p1.wmin = wm;
+  const uint32_t w1 = wm == ~0ull ? NONE32 : (uint32_t)(wm >> 32);
+  const int32_t x1 = (int32_t)((uint32_t)wm ^ 0x80000000u);
+  // pass 2
+  uint32_t a = NONE32, b = NONE32, q = NONE32, A = NONE32;
+  bool m1 = false;
+  if (valid) {
+    if (!inter) {
+      if (w) {
+        if (id == w1) { if (v != x1) m1 = true; }
+        else {
+          b = id;
+          if (v != x1) q = id;
+        }
+      } else if (id != r1) {
+        a = id;
+      }
+    } else {
+      const uint32_t g = id >> 10, g1 = w1 == NONE32 ? NONE32 : w1 >> 10, gr1 = r1 == NONE32 ? NONE32 : r1 >> 10;
+      if (w) {
+        if (id == w1 && v != x1) m1 = true;
+        if (g != g1) {
+          b = id;
+          if (v != x1) q = id;
+        } else if (id != w1 && v != x1) {
+          A = id;
+        }
+      } else if (g != gr1) {
+        a = id;
+      }
+    }
+  }
+  r.a = __shfl(seg_min_u32(a, heads, lane), last);
+  r.b = __shfl(seg_min_u32(b, heads, lane), last);
+  r.q = __shfl(seg_min_u32(q, heads, lane), last);
+  r.A = inter ? __shfl(seg_min_u32(A, heads, lane), last) : NONE32;
+  // OR over the run: the run's lanes are [first, last]
+  const u64 mm = __ballot(m1);
+  // the run's first lane: the last head at or below this lane (lane 0 when
+  // the run began in an earlier window)
+  const u64 below_heads = heads & (lane == 63u ? ~0ull : ((2ull << lane) - 1ull));
+  const uint32_t first = below_heads ? 63u - (uint32_t)__clzll(below_heads) : 0u;
+  const u64 run_mask = (last >= 63u ? ~0ull : ((2ull << last) - 1ull)) & ~((1ull << first) - 1ull);
+  r.multi1 = (mm & run_mask) != 0ull ? 1u : 0u;
+  return r;
+}
+
+// Convert INTER ids (gid << 10 | lid) of a finished check to global tids.
+__device__ __forceinline__ uint32_t id_to_tid(uint32_t id, uint32_t W) {
+  return id == NONE32 ? NONE32 : (id >> 10) * W + (id & 1023u);
+}
+
+// One wave per window of 64 sorted entries.  Runs that start and end inside
+// the window are checked by lane reductions; a run that starts inside and
+// reaches past the window is checked by its first lane as before (serially
+// when short, else queued for seg_long_kernel).  Runs that start before the
+// window belong to an earlier window.
+// Records of one wave, staged in LDS and handed to the global staging area
+// in batches, so the shared record counter sees one atomic per batch.
+constexpr uint32_t WREC = 128;
+struct WaveRecs {
+  uint32_t words[WREC][10];   // rc_record_dev
+  u64 keys[WREC];
+};
+
+__device__ __forceinline__ void flush_wave_recs(const rc_record_out& R, WaveRecs& B, uint32_t count,
+                                                uint32_t lane) {
+  if (count == 0) return;
+  const u64 base = wave_reserve(R.rec_count, count, lane);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(R.staging);
+  bool over = false;
+  for (uint32_t j = lane; j < count * 10u; j += 64u) {
+    const u64 pos = base + j / 10u;
+    if (pos < R.rec_cap) dst[pos * 10u + j % 10u] = B.words[j / 10u][j % 10u];
+    else over = true;
+  }
+  for (uint32_t j = lane; j < count; j += 64u) {
+    const u64 pos = base + j;
+    if (pos < R.rec_cap) {
+      R.rec_keys[pos] = B.keys[j];
+      R.rec_idx[pos] = (uint32_t)pos;
+    }
+  }
+  if (__ballot(over) != 0ull && lane == 0) atomicOr(R.status_word, 2u);
+}
+
 __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
+  __shared__ WaveRecs wrecs[4];
   const u64 n = *S.n_ptr;
   const uint32_t lane = threadIdx.x & 63u;
+  WaveRecs& B = wrecs[threadIdx.x >> 6];
+  uint32_t staged = 0;        // records in this wave's buffer (uniform)
   const uint32_t low = S.bg + S.bk;
   const uint32_t gmask = (1u << S.bg) - 1u;
-  // block-uniform rounds, so the whole wave reaches the ballots below
-  for (u64 base = (u64)blockIdx.x * blockDim.x; base < n; base += (u64)gridDim.x * blockDim.x) {
-    const u64 i = base + threadIdx.x;
+  const u64 waves = (u64)gridDim.x * (blockDim.x >> 6);
+  for (u64 win = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); win * 64u < n; win += waves) {
+    const u64 i = win * 64u + lane;
+    const bool valid = i < n;
+    const u64 k = valid ? S.keys[i] : ~0ull;
+    const u64 p = valid ? S.vals[i] : 0ull;
+    const u64 kprev = (i == 0 || lane != 0) ? ~0ull : S.keys[i - 1];
+    const u64 kleft = shfl_u64(k, (lane + 63u) & 63u);   // every lane takes part
+    const u64 kp = lane == 0 ? kprev : kleft;
+    const bool first_entry = i == 0;
+    const bool sub_head = valid && (first_entry || kp != k);
+    const bool head = valid && (first_entry || (kp >> low) != (k >> low));
+    // the entry after the window decides whether the last runs are complete
+    const u64 knext = lane == 63u ? (i + 1 < n ? S.keys[i + 1] : ~0ull) : 0ull;
+    const u64 kafter = __shfl(knext, 63u);
+    const u64 hsub = __ballot(sub_head), hcell = __ballot(head);
+    const u64 vmask = __ballot(valid);
+    // run bounds of this lane: [its run's first lane, its run's last lane]
+    const u64 above = lane == 63u ? 0ull : ~((2ull << lane) - 1ull);    // lanes after this one
+    const uint32_t nsub = (uint32_t)__ffsll((long long)(hsub & above));    // 1 + next run start, or 0
+    const uint32_t ncell = (uint32_t)__ffsll((long long)(hcell & above));
+    const uint32_t nvalid = 64u - (uint32_t)__clzll(vmask);   // valid lanes
+    uint32_t last_sub = nsub ? nsub - 2u : nvalid - 1u;
+    uint32_t last_cell = ncell ? ncell - 2u : nvalid - 1u;
+    // does the lane's run continue past the window?
+    const u64 klast = __shfl(k, 63u);
+    const bool open_sub = nsub == 0u && nvalid == 64u && i + (63u - lane) + 1u < n && kafter == klast;
+    const bool open_cell = ncell == 0u && nvalid == 64u && i + (63u - lane) + 1u < n &&
+                           (kafter >> low) == (klast >> low);
+    const bool w = pay_w(p);
+    const int32_t v = pay_val(p);
+    const uint32_t lid = pay_lid(p);
+    const uint32_t g = (uint32_t)(k >> S.bk) & gmask;
+    const RunSums ri = window_runs(valid, lid, w, v, hsub, last_sub, lane, false);
+    const RunSums rx = window_runs(valid, (g << 10) | lid, w, v, hcell, last_cell, lane, true);
     bool has_intra = false, has_inter = false;
     SegHead H;
     PendingRec pa, pb;
-    if (i < n) {
-      const u64 k = S.keys[i];
-      const bool sub_head = i == 0 || S.keys[i - 1] != k;
-      const bool head = sub_head && (i == 0 || (S.keys[i - 1] >> low) != (k >> low));
-      // run ends first (keys only): a head whose runs hold a single entry has
-      // nothing to check and skips the descriptor loads
-      const u64 e = sub_head ? run_end(S.keys, i, n, 0) : i;
-      const u64 f = head ? run_end(S.keys, i, n, low) : i;
-      if (sub_head && (e - i >= 2 || f - i >= 2)) {
-        H = seg_head(S, k);
-        if (e - i >= 2) {
+    const uint32_t len_sub = last_sub + 1u - lane, len_cell = last_cell + 1u - lane;
+    const bool want_intra = sub_head && (open_sub || len_sub >= 2u);
+    const bool want_inter = head && (open_cell || len_cell >= 2u);
+    if (want_intra || want_inter) {
+      H = seg_head(S, k);
+      if (want_intra) {
+        if (!open_sub) {
+          const Intra2 p2 = {ri.a, ri.b, ri.q, ri.multi1};
+          has_intra = intra_finish(ri.p1, p2, &pa.label, &pa.rw, &pa.ww);
+        } else {
+          const u64 e = run_end(S.keys, i, n, 0);
           if (e - i <= SEG_SHORT) {
             const u64* vals = S.vals;
             has_intra = intra_check([vals](u64 j) { return vals[j]; }, i, e, &pa.label, &pa.rw, &pa.ww);
-            pa.gid = H.gid; pa.interval = H.interval; pa.aid = H.aid; pa.cell = H.cell; pa.cellkey = H.cellkey;
-            pa.lidbase = H.gid * H.W;
           } else {
             push_long(S, i, e, false);
           }
         }
-        if (head && H.G > 1 && H.aid < H.n_global) {
-          if (f - i >= 2) {
-            if (f - i <= SEG_SHORT) {
-              has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, H.W, &pb.label, &pb.rw, &pb.ww);
-              pb.gid = H.gid; pb.interval = 0; pb.aid = H.aid; pb.cell = H.cell; pb.cellkey = H.cellkey;
-              pb.lidbase = 0;
-            } else {
-              push_long(S, i, f, true);
-            }
+        pa.gid = H.gid; pa.interval = H.interval; pa.aid = H.aid; pa.cell = H.cell; pa.cellkey = H.cellkey;
+        pa.lidbase = H.gid * H.W;
+      }
+      if (want_inter && H.G > 1 && H.aid < H.n_global) {
+        if (!open_cell) {
+          Pass1 p1 = rx.p1;
+          p1.r1 = id_to_tid(p1.r1, H.W);
+          const uint32_t w1 = p1.wmin == ~0ull ? NONE32 : id_to_tid((uint32_t)(p1.wmin >> 32), H.W);
+          if (w1 != NONE32) p1.wmin = ((u64)w1 << 32) | (uint32_t)p1.wmin;
+          const Inter2 p2 = {id_to_tid(rx.a, H.W), id_to_tid(rx.b, H.W), id_to_tid(rx.q, H.W),
+                             id_to_tid(rx.A, H.W), rx.multi1};
+          has_inter = inter_finish(p1, p2, H.W, &pb.label, &pb.rw, &pb.ww);
+        } else {
+          const u64 f = run_end(S.keys, i, n, low);
+          if (f - i <= SEG_SHORT) {
+            has_inter = inter_check(S.keys, S.vals, i, f, S.bk, gmask, H.W, &pb.label, &pb.rw, &pb.ww);
+          } else {
+            push_long(S, i, f, true);
           }
         }
+        pb.gid = H.gid; pb.interval = 0; pb.aid = H.aid; pb.cell = H.cell; pb.cellkey = H.cellkey;
+        pb.lidbase = 0;
       }
     }
     const u64 m1 = __ballot(has_intra), m2 = __ballot(has_inter);
     const uint32_t c1 = (uint32_t)__popcll(m1), c2 = (uint32_t)__popcll(m2);
     if (c1 + c2 == 0) continue;
-    const u64 rbase = wave_reserve(S.out.rec_count, c1 + c2, lane);
+    if (staged + c1 + c2 > WREC) {     // at most 128 per window: make room first
+      flush_wave_recs(S.out, B, staged, lane);
+      staged = 0;
+    }
     const u64 below = (1ull << lane) - 1ull;
     RecKey K = {S.bs, S.bc, has_intra || has_inter ? H.G : 1u, has_intra || has_inter ? H.NI : 1u};
-    if (has_intra) store_record(S.out, K, rbase + (u64)__popcll(m1 & below), H.slot, H.instance, pa, false);
-    if (has_inter) store_record(S.out, K, rbase + c1 + (u64)__popcll(m2 & below), H.slot, H.instance, pb, true);
+    if (has_intra) {
+      const uint32_t j = staged + (uint32_t)__popcll(m1 & below);
+      const rc_record_dev r = make_record(K, H.slot, H.instance, pa, false, &B.keys[j]);
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(&r);
+      for (int q = 0; q < 10; ++q) B.words[j][q] = w[q];
+    }
+    if (has_inter) {
+      const uint32_t j = staged + c1 + (uint32_t)__popcll(m2 & below);
+      const rc_record_dev r = make_record(K, H.slot, H.instance, pb, true, &B.keys[j]);
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(&r);
+      for (int q = 0; q < 10; ++q) B.words[j][q] = w[q];
+    }
+    staged += c1 + c2;
+    if (staged >= WREC / 2) {
+      flush_wave_recs(S.out, B, staged, lane);
+      staged = 0;
+    }
   }
+  flush_wave_recs(S.out, B, staged, lane);
 }
 
 // minimum over the workgroup (256 lanes, 4 waves); sh holds 4 words
@@ -888,7 +1080,7 @@ hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u6
 
 hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
   // the entry count is on the device: a fixed grid walks it in rounds
-  uint32_t blocks = blocks_for(cap ? cap : 1, 256);
+  uint32_t blocks = blocks_for(cap ? cap : 1, 256);   // 4 windows of 64 entries per block
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(seg_check_kernel, dim3(blocks), dim3(256), 0, st, S);
   uint32_t lblocks = (uint32_t)std::min<u64>(S.long_cap ? S.long_cap : 1, 2048);

@@ -276,12 +276,15 @@ class TriageRun:
 
 def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_seeds: int, epochs: int = 5,
         batch: int = 4096, lr: float = 1e-3, chunk: int = 2000, label_chunk: int = 20000, init_seed: int = 7,
-        ws_bytes: int = 16 << 30, budget_frac: float = 0.25) -> TriageRun:
+        ws_bytes: int = 16 << 30, budget_frac: float = 0.25, progress=None) -> TriageRun:
     torch = _torch()
+    say = progress or (lambda msg: None)
     train = Instances.grid(load_programs(ctx, train_workloads), train_seeds)
     held = Instances.grid(load_programs(ctx, eval_workloads), eval_seeds)
+    say(f"loaded {len(train_workloads)} + {len(eval_workloads)} programs")
     # labels from the exact checker
     lab = sweep(ctx, train, chunk=label_chunk, ws_bytes=ws_bytes)
+    say(f"labelled {len(train)} instances ({int(lab.racy.sum())} racy)")
     labels = torch.from_numpy(lab.racy.astype(np.float32)).cuda()
     net = TriageNet(ctx, seed=init_seed)
 
@@ -289,9 +292,11 @@ def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_
         f = features(ctx, train)
         return net.train(f, labels, epochs=epochs, batch=batch, lr=lr)
     losses, train_ms = timed(fit)
+    say(f"trained: losses {losses}")
     # warm the held-out programs' tables, then the plain sweep
     sweep(ctx, Instances(held.programs, held.prog[:64], held.seed[:64]), chunk=chunk, ws_bytes=ws_bytes)
     plain = sweep(ctx, held, chunk=chunk, ws_bytes=ws_bytes)
+    say("plain sweep done")
 
     def infer():
         return rank(ctx, net.scores(features(ctx, held)))

@@ -189,10 +189,13 @@ def main():
     units_per_launch = accesses * args.steps / max(1, launches)
     algo = ALGO_BYTES.get(dom, 0.0) * units_per_launch
     achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    kernel = KERNEL_OF_PHASE[dom]
+    if dom == "interpret" and not args.no_jit:
+        kernel = "rc_jit_kernel"       # the program's own kernel runs the interpret phase
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(KERNEL_OF_PHASE[dom], args.config),
-                "kernel": KERNEL_OF_PHASE[dom], "phase": dom,
+                "traffic": measured_traffic(kernel, args.config),
+                "kernel": kernel, "phase": dom,
                 "avg_launch_ms": round(per_launch_ms, 4),
                 "phases_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
                 "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}

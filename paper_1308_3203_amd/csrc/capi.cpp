@@ -872,7 +872,9 @@ rc_status rc_prog_scalar(const rc_prog* p, uint32_t id, char* name, size_t name_
 // class (synchronous; the runtime compiler takes about a second).
 static rc_status jit_build(rc_prog* p) {
   const uint32_t cls = width_class(p->W);
-  const std::string src = jit_source(p->c.code, p->c.nregs, 64u << cls);
+  std::vector<uint32_t> kinds;
+  for (const ArrayDesc& a : p->arrays) kinds.push_back(a.kind);
+  const std::string src = jit_source(p->c.code, p->c.nregs, 64u << cls, kinds);
   std::vector<char> obj;
   std::string log;
   if (!jit_compile(src, &obj, &log)) {

@@ -619,9 +619,14 @@ struct Item {
   // One load or store statement (op OP_LOAD / OP_STORE on array wc) for the
   // whole group; a load's value goes to `out` on active lanes.  Returns true
   // when the group stops on a fault (the statement then has no effect).
+  // KIND >= 0: the array's kind (AK_*) known when the caller is compiled,
+  // so only its path is generated; -1: read from the descriptor.
+  template <int KIND = -1>
   __device__ __forceinline__ bool mem(uint32_t op, uint32_t wc, int32_t idx, int32_t val, bool active,
                                       uint32_t spc, int32_t& out) {
-    const ArrayDesc A = const_load<ArrayDesc>(P.arrays, wc);
+    ArrayDesc A = const_load<ArrayDesc>(P.arrays, wc);
+    if (KIND >= 0) A.kind = (uint32_t)KIND;
+    if (KIND == (int)AK_GLOBAL_RO) A.logged = LOG_NONE;   // never written, never logged
     if (active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);
     const bool rec = active && P.do_log && A.logged != LOG_NONE;
     // the barrier completes every earlier statement's accesses, publishes

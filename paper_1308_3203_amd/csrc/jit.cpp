@@ -32,7 +32,8 @@ std::string operand(bool imm, uint32_t w) {
 
 }  // namespace
 
-std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32_t threads) {
+std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32_t threads,
+                       const std::vector<uint32_t>& array_kind) {
   const uint32_t n = (uint32_t)(code.size() / 4);
   std::set<uint32_t> targets;
   std::set<uint32_t> slots;
@@ -88,9 +89,10 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
       case OP_LOAD:
       case OP_STORE: {
         const std::string val = op == OP_STORE ? operand(fb, wb) : std::string("0");
+        const int kind = wc < array_kind.size() ? (int)array_kind[wc] : -1;
         snprintf(buf, sizeof buf,
-                 "  { int32_t v = 0; if (it.mem(%uu, %uu, %s, %s, %s, %uu, v)) { it.faulted = true; goto Ldone; }",
-                 op, wc, operand(fa, wa).c_str(), val.c_str(), act, spc);
+                 "  { int32_t v = 0; if (it.mem<%d>(%uu, %uu, %s, %s, %s, %uu, v)) { it.faulted = true; goto Ldone; }",
+                 kind, op, wc, operand(fa, wa).c_str(), val.c_str(), act, spc);
         s += buf;
         if (op == OP_LOAD) {
           snprintf(buf, sizeof buf, " if (%s) R%u = v;", act, dst);

@@ -40,9 +40,11 @@ def kernel_source_hash() -> str:
     the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h", "rc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1308_3203_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1308_3203_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -196,6 +198,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": measured_traffic(kernel, args.config),
                 "kernel": kernel, "phase": dom,
+                "algo_bytes_per_launch": round(algo),
                 "avg_launch_ms": round(per_launch_ms, 4),
                 "phases_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
                 "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}

@@ -146,6 +146,26 @@ rc_status rc_prog_scalar(const rc_prog* prog, uint32_t scalar_id, char* name, si
  * program's static bounds exceed the library's limits for this shape. */
 rc_status rc_set_ndrange(rc_prog* prog, uint32_t num_groups, uint32_t group_size);
 
+/* *owned = 1 when, under the current launch shape, no two work-items can
+ * touch a common cell of array `array_id`, so that the array can carry no
+ * record (every record pairs two work-items, Section 4) and its accesses are
+ * not logged; 0 when that is not proven.  The proof: every index of the
+ * array is S * tid + o for one stride S != 0 and offsets o in a range
+ * shorter than |S|, with indices followed through + - * << by constants over
+ * gid, lid, tid, the shape constants and loop counters, in int32 without
+ * wrapping.  Results never depend on it.  RC_E_STATE before rc_set_ndrange. */
+rc_status rc_prog_owned(const rc_prog* prog, uint32_t array_id, int* owned);
+
+/* The same proof on program text, host only (no context, no device), under
+ * num_groups groups of group_size work-items: *n_arrays receives the
+ * program's array count (global arrays first, then local arrays, in
+ * declaration order) and owned[a] (0 or 1) is written for the first
+ * min(capacity, *n_arrays) arrays; owned may be NULL when capacity is 0.
+ * RC_E_PARSE / RC_E_LIMIT as rc_prog_load, RC_E_INVAL for a shape outside
+ * rc_set_ndrange's range. */
+rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint32_t group_size,
+                          uint8_t* owned, uint32_t capacity, uint32_t* n_arrays);
+
 /* Inputs (Section 3 K(Args): arguments passed by the host).  A global array is
  * bound either to seeded values U[lo, hi) (1 <= hi - lo <= 2^32; instance j's
  * seed is seed0 + j) or to caller-owned device memory of size(array) int32

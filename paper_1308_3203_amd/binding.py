@@ -39,7 +39,8 @@ EXPORTS = [
     "rc_workspace_size", "rc_check", "rc_sync", "rc_read_final", "rc_ctx_profile",
     "rc_ctx_profile_read", "rc_prog_set_tuning", "rc_batch_check", "rc_autotune",
     "rc_features_workspace_size", "rc_features", "rc_mlp_workspace_size", "rc_mlp_forward", "rc_mlp_grad",
-    "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank", "rc_prog_jit",
+    "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank", "rc_prog_jit", "rc_prog_owned",
+    "rc_owned_arrays",
 ]
 N_FEATURES = 128
 MLP_PARAMS = 99073
@@ -93,6 +94,9 @@ def load_library(path: str = LIB_PATH):
                           ctypes.c_int),
         "rc_prog_scalar": ([vp, u32, ctypes.c_char_p, sz], ctypes.c_int),
         "rc_set_ndrange": ([vp, u32, u32], ctypes.c_int),
+        "rc_prog_owned": ([vp, u32, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "rc_owned_arrays": ([ctypes.c_char_p, sz, u32, u32, ctypes.POINTER(ctypes.c_uint8), u32,
+                             ctypes.POINTER(u32)], ctypes.c_int),
         "rc_bind_seeded": ([vp, u32, i64, i64], ctypes.c_int),
         "rc_bind_device": ([vp, u32, vp], ctypes.c_int),
         "rc_bind_scalar_seeded": ([vp, u32, i64, i64], ctypes.c_int),
@@ -131,6 +135,18 @@ def _call(fn, *args):
     if st != RC_OK:
         raise RcError(st, _lib.rc_last_error().decode())
     return st
+
+
+def owned_arrays(src: str, groups: int, group_size: int) -> list:
+    """Per array (global arrays first, then local ones): True when no two
+    work-items of the shape can touch a common cell of it (host only)."""
+    lib = load_library()
+    b = src.encode()
+    n = ctypes.c_uint32(0)
+    _call(lib.rc_owned_arrays, b, len(b), groups, group_size, None, 0, ctypes.byref(n))
+    out = (ctypes.c_uint8 * max(1, n.value))()
+    _call(lib.rc_owned_arrays, b, len(b), groups, group_size, out, n.value, ctypes.byref(n))
+    return [bool(out[i]) for i in range(n.value)]
 
 
 class Context:
@@ -325,6 +341,13 @@ class Program:
     def set_ndrange(self, groups: int, group_size: int):
         _call(_lib.rc_set_ndrange, self._h, groups, group_size)
         self.G, self.W = groups, group_size
+
+    def owned(self, name: str) -> bool:
+        """True when no two work-items can touch a common cell of the array
+        under the current shape (its accesses are then not logged)."""
+        v = ctypes.c_int(0)
+        _call(_lib.rc_prog_owned, self._h, self.array_id(name), ctypes.byref(v))
+        return bool(v.value)
 
     def bind(self, arrays: dict | None = None, scalars: dict | None = None):
         """arrays: name -> ("seeded", lo, hi) or an int32 cuda tensor;

@@ -17,6 +17,7 @@
 #include "jit.h"
 #include "kernels.h"
 #include "mlp.h"
+#include "ownership.h"
 #include "rc_internal.h"
 
 using namespace rc;
@@ -93,6 +94,10 @@ struct rc_prog {
   uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t lds_log_cap = 0;          // chosen for the current shape
+  // arrays no two work-items share under the current shape (never logged),
+  // and the per-item access bounds on the arrays that are logged
+  std::vector<uint8_t> owned;
+  uint64_t logged_mem = 0, logged_local = 0;
   // per-program kernel (rc_prog_jit): module of the generated kernel, the
   // width class it was compiled for, and whether single-program calls use it
   hipModule_t jit_mod = nullptr;
@@ -164,19 +169,34 @@ size_t lds_fixed_bytes(const rc_prog* p) {
   return lds_base_bytes(p) + (size_t)tc * sizeof(TabCell);
 }
 
-size_t lds_bytes(const rc_prog* p) { return lds_fixed_bytes(p) + (size_t)p->lds_log_cap * 16; }
+// Bytes of one LDS log entry: with the per-cell table an entry packs into
+// one word (cell - table base, store flag, local id, value); the sort path
+// keeps a sort key, a payload word and the value.
+size_t lds_entry_bytes(const rc_prog* p) {
+  uint32_t tb, tc;
+  lds_table(p, &tb, &tc);
+  return tc ? 8u : 16u;
+}
+
+// LDS of one work-group; a per-program kernel keeps the private variables in
+// registers, so they take no LDS there.
+size_t lds_bytes(const rc_prog* p, bool jit) {
+  const uint32_t WP = ((p->W + 63) / 64) * 64;
+  const size_t regs = jit ? (size_t)p->c.nregs * WP * 4 : 0;
+  return lds_fixed_bytes(p) - regs + (size_t)p->lds_log_cap * lds_entry_bytes(p);
+}
 
 // Entries of the interval log kept in LDS (a power of two; 0 = none): large
 // enough for the program's static per-interval bound when that fits, else as
 // large as LDS allows up to 4096 entries (or the tuned size).
 uint32_t lds_log_entries(const rc_prog* p) {
   const bool lds_globals = p->G == 1;
-  const u64 per_item = p->c.dyn_logged_local + (lds_globals ? p->c.dyn_logged_mem - p->c.dyn_logged_local : 0);
+  const u64 per_item = p->logged_local + (lds_globals ? p->logged_mem - p->logged_local : 0);
   if (per_item == 0) return 0;
-  const size_t fixed = lds_fixed_bytes(p);
-  if (fixed + 32 > LDS_LIMIT) return 0;
+  const size_t fixed = lds_fixed_bytes(p), eb = lds_entry_bytes(p);
+  if (fixed + 2 * eb > LDS_LIMIT) return 0;
   uint32_t fit = 2;
-  while ((size_t)fit * 2 * 16 + fixed <= LDS_LIMIT && fit * 2 <= 65536u) fit *= 2;
+  while ((size_t)fit * 2 * eb + fixed <= LDS_LIMIT && fit * 2 <= 65536u) fit *= 2;
   if (p->lds_log_pref) {
     uint32_t t = 2;
     while (t * 2 <= p->lds_log_pref && t * 2 <= fit) t *= 2;
@@ -190,14 +210,14 @@ uint32_t lds_log_entries(const rc_prog* p) {
 }
 
 bool lds_logged(const rc_prog* p, uint32_t a) {
-  return p->lds_log_cap && p->c.arrays[a].written && (!p->c.arrays[a].global || p->G == 1);
+  return p->lds_log_cap && p->c.arrays[a].written && !p->owned[a] && (!p->c.arrays[a].global || p->G == 1);
 }
 
 // log entries one work-group may write to the global log
 u64 wg_log_entries(const rc_prog* p) {
   const Compiled& c = p->c;
-  const u64 lds = p->lds_log_cap ? c.dyn_logged_local + (p->G == 1 ? c.dyn_logged_mem - c.dyn_logged_local : 0) : 0;
-  const u64 glob = c.dyn_logged_mem - lds;
+  const u64 lds = p->lds_log_cap ? p->logged_local + (p->G == 1 ? p->logged_mem - p->logged_local : 0) : 0;
+  const u64 glob = p->logged_mem - lds;
   const double ib = p->G == 1 ? c.interval_logged_all : c.interval_logged_local;
   const bool spill = p->lds_log_cap && (double)p->W * ib > (double)p->lds_log_cap;
   return std::max<u64>(1, (u64)p->W * (glob + (spill ? lds : 0)));
@@ -233,7 +253,7 @@ Need need_of(const rc_prog* p) {
   Need n;
   n.wg = p->G;
   n.log = (u64)p->G * wg_log_entries(p);
-  n.recs = std::max<u64>(1, (u64)p->G * p->W * p->c.dyn_logged_mem);
+  n.recs = std::max<u64>(1, (u64)p->G * p->W * p->logged_mem);
   n.ovl = (u64)p->G * p->overlay_cells;
   return n;
 }
@@ -313,6 +333,7 @@ struct Call {
   size_t class_lds[N_WCLASS] = {0, 0, 0, 0, 0};
   uint32_t epoch_stride = 1;
   uint32_t radix_bits = 8;              // digit width of the access-log sort
+  bool jit = false;                     // one program, run by its own kernel
 };
 
 // Split the instances into chunks whose resources stay under the limits.
@@ -388,6 +409,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     items_total += nd.wg;
   }
   C.classes_used = 0;
+  C.jit = C.progs.size() == 1 && C.progs[0]->jit_on && C.progs[0]->jit_fn;
   for (rc_prog* p : C.progs) {
     bc = std::max(bc, bits_for(std::max<u64>(1, p->n_logged_cells)));
     max_cells = std::max(max_cells, p->n_logged_cells);
@@ -397,7 +419,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     max_stores = std::max<u64>(max_stores, p->c.dyn_stores);
     const uint32_t c = width_class(p->W);
     C.classes_used |= 1u << c;
-    C.class_lds[c] = std::max(C.class_lds[c], lds_bytes(p));
+    C.class_lds[c] = std::max(C.class_lds[c], lds_bytes(p, C.jit));
   }
   C.epoch_stride = (uint32_t)std::min<u64>(max_stores + 1, 1u << 22);
   C.radix_bits = C.progs.empty() ? 8u : C.progs[0]->radix_bits;
@@ -481,7 +503,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     // a call of one program with a compiled kernel runs that kernel; any
     // other call runs the interpreter
-    rc_prog* jp = C.progs.size() == 1 && C.progs[0]->jit_on && C.progs[0]->jit_fn ? C.progs[0] : nullptr;
+    rc_prog* jp = C.jit ? C.progs[0] : nullptr;
     for (uint32_t c = 0; c < N_WCLASS; ++c) {
       if (!(C.classes_used & (1u << c))) continue;
       P.wclass = c;
@@ -603,7 +625,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     rc_prog* p = C.progs[i];
     for (size_t a = 0; a < p->arrays.size(); ++a) {
       ArrayDesc& d = p->arrays[a];
-      d.logged = !p->c.arrays[a].written ? LOG_NONE : (lds_logged(p, (uint32_t)a) ? LOG_LDS : LOG_GLOBAL);
+      d.logged = !p->c.arrays[a].written || p->owned[a] ? LOG_NONE
+                 : (lds_logged(p, (uint32_t)a) ? LOG_LDS : LOG_GLOBAL);
     }
     unsigned char* h = p->h_tables.data();
     memcpy(h, p->arrays.data(), p->arrays.size() * sizeof(ArrayDesc));
@@ -621,7 +644,7 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     D.n_arrays = (uint32_t)p->c.arrays.size();
     D.n_global = p->c.n_global;
     D.n_scalars = (uint32_t)p->c.scalars.size();
-    D.nregs = p->c.nregs;
+    D.nregs = C.jit ? 0u : p->c.nregs;   // no LDS registers in a per-program kernel
     D.G = p->G;
     D.W = p->W;
     D.nwaves = (p->W + 63) / 64;
@@ -803,6 +826,7 @@ rc_status rc_prog_load(rc_ctx* ctx, const char* src, size_t len, rc_prog** out) 
   }
   p->n_logged_cells = cb;
   p->overlay_cells = ov;
+  p->owned.assign(na, 0);
   p->lds_local_cells = lds;
   p->scalars.assign(c.scalars.size(), ScalarDesc());
   for (auto& s : p->scalars) memset(&s, 0, sizeof s);
@@ -868,6 +892,29 @@ rc_status rc_prog_scalar(const rc_prog* p, uint32_t id, char* name, size_t name_
   return RC_OK;
 }
 
+rc_status rc_prog_owned(const rc_prog* p, uint32_t id, int* owned) {
+  if (!p || !owned) return fail(RC_E_INVAL, "NULL argument");
+  if (!p->shaped) return fail(RC_E_STATE, "rc_set_ndrange has not been called");
+  if (id >= p->c.arrays.size()) return fail(RC_E_INVAL, "array id %u out of range", id);
+  *owned = p->owned[id] ? 1 : 0;
+  return RC_OK;
+}
+
+rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint32_t group_size, uint8_t* owned,
+                          uint32_t capacity, uint32_t* n_arrays) {
+  if (!src || !n_arrays || (capacity && !owned)) return fail(RC_E_INVAL, "NULL argument");
+  if (group_size < 1 || group_size > MAX_WG || num_groups < 1 || (u64)num_groups * group_size >= (1ull << 26))
+    return fail(RC_E_INVAL, "launch shape out of range");
+  Compiled c;
+  std::string err;
+  bool is_limit = false;
+  if (!compile_program(src, len, &c, &err, &is_limit)) return fail(is_limit ? RC_E_LIMIT : RC_E_PARSE, "%s", err.c_str());
+  const std::vector<uint8_t> o = owned_arrays(c, num_groups, group_size);
+  *n_arrays = (uint32_t)o.size();
+  for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a];
+  return RC_OK;
+}
+
 // Generate, compile and load the program's kernel for its current width
 // class (synchronous; the runtime compiler takes about a second).
 static rc_status jit_build(rc_prog* p) {
@@ -926,6 +973,14 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->G = num_groups;
   p->W = W;
   p->shaped = true;
+  p->owned = owned_arrays(p->c, p->G, p->W);
+  p->logged_mem = p->c.dyn_logged_mem;
+  p->logged_local = p->c.dyn_logged_local;
+  for (size_t a = 0; a < p->owned.size(); ++a) {
+    if (!p->owned[a] || !p->c.arrays[a].written) continue;
+    p->logged_mem -= std::min(p->logged_mem, p->c.dyn_mem_array[a]);
+    if (!p->c.arrays[a].global) p->logged_local -= std::min(p->logged_local, p->c.dyn_mem_array[a]);
+  }
   p->lds_log_cap = lds_log_entries(p);
   // a per-program kernel is compiled for one width class
   if (p->jit_on && p->jit_class != width_class(W)) return jit_build(p);

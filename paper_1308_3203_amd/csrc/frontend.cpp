@@ -583,6 +583,7 @@ class Lowering {
 // ---------------------------------------------------------------------------
 struct Bounds {
   double instr = 0, mem = 0, logged = 0, logged_local = 0, stores = 0, barriers = 0;
+  std::vector<double> arr;   // loads/stores per array
 };
 
 uint64_t expr_ops(const Node& e) {
@@ -600,6 +601,8 @@ void bound_block(const std::vector<Statement>& body, const Compiled& c, double m
         double ops = (double)expr_ops(*s.e1) + (s.e2 ? (double)expr_ops(*s.e2) : 0.0) + 1;
         b->instr += mult * ops;
         b->mem += mult;
+        if (b->arr.size() <= (size_t)s.arr) b->arr.resize((size_t)s.arr + 1, 0.0);
+        b->arr[(size_t)s.arr] += mult;
         if (c.arrays[s.arr].written) {
           b->logged += mult;
           if (!c.arrays[s.arr].global) b->logged_local += mult;
@@ -920,6 +923,9 @@ bool compile_program(const char* src, size_t len, Compiled* out, std::string* er
     out->dyn_logged_mem = (uint64_t)(b.logged < cap ? b.logged : cap);
     out->dyn_logged_local = (uint64_t)(b.logged_local < cap ? b.logged_local : cap);
     out->dyn_stores = (uint64_t)b.stores;
+    out->dyn_mem_array.assign(out->arrays.size(), 0);
+    for (size_t a = 0; a < b.arr.size() && a < out->arrays.size(); ++a)
+      out->dyn_mem_array[a] = (uint64_t)(b.arr[a] < cap ? b.arr[a] : cap);
     out->max_intervals = (uint64_t)(b.barriers + 1);
     {
       const Compiled& cc = *out;

@@ -27,6 +27,7 @@ struct Compiled {
   uint64_t dyn_logged_local = 0;       // ... of which on written local arrays
   uint64_t dyn_mem = 0;                // all loads/stores
   uint64_t dyn_stores = 0;             // store statements
+  std::vector<uint64_t> dyn_mem_array; // loads/stores per array
   uint64_t max_intervals = 1;          // 1 + barriers executed
   // largest interval (accesses per work-item between two barriers) on
   // written local arrays / on all written arrays

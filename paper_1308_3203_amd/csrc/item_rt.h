@@ -290,9 +290,21 @@ __device__ __forceinline__ rc_record_dev make_record(const RecKey& K, uint32_t s
   return r;
 }
 
+// Pointers read from descriptors in memory are generic to the compiler; these
+// casts let it emit global (not flat) memory instructions, which do not hold
+// up waits on LDS.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RC_GLOBAL(T, ptr) ((__attribute__((address_space(1))) T*)(ptr))
+#else
+#define RC_GLOBAL(T, ptr) ((T*)(ptr))   // the host pass only parses device code
+#endif
+
 __device__ __forceinline__ void store_record(const rc_record_out& R, const RecKey& K, u64 pos, uint32_t slot,
                                              uint32_t instance, const PendingRec& p, bool inter) {
-  if (pos >= R.rec_cap) { atomicOr(R.status_word, 2u); return; }
+  if (pos >= R.rec_cap) {
+    __hip_atomic_fetch_or(RC_GLOBAL(uint32_t, R.status_word), 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   const uint32_t NONE = 0xFFFFFFFFu;
   rc_record_dev r;
   r.instance = instance;
@@ -305,16 +317,18 @@ __device__ __forceinline__ void store_record(const rc_record_out& R, const RecKe
   r.ww_a = p.ww.a == NONE ? NONE : p.ww.a + p.lidbase;
   r.ww_b = p.ww.b == NONE ? NONE : p.ww.b + p.lidbase;
   r.pad = 0;
-  reinterpret_cast<rc_record_dev*>(R.staging)[pos] = r;
+  RC_GLOBAL(rc_record_dev, R.staging)[pos] = r;
   const u64 scope = inter ? (u64)K.G * K.NI : (u64)p.gid * K.NI + p.interval;
-  R.rec_keys[pos] = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
-  R.rec_idx[pos] = (uint32_t)pos;
+  RC_GLOBAL(u64, R.rec_keys)[pos] = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
+  RC_GLOBAL(uint32_t, R.rec_idx)[pos] = (uint32_t)pos;
 }
 
 // wave-wide allocation of record slots: one atomic per wave
 __device__ __forceinline__ u64 wave_reserve(unsigned long long* counter, uint32_t n, uint32_t lane) {
   u64 base = 0;
-  if (lane == 0 && n) base = atomicAdd(counter, (u64)n);
+  if (lane == 0 && n)
+    base = __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, counter), (unsigned long long)n, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
   const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
   return ((u64)bhi << 32) | blo;
@@ -344,7 +358,13 @@ struct ItemView {
   uint32_t co_stride;
 };
 
-__device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE32, NONE32, NONE32, NONE32, 0u, NONE32}; }
+__device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE32, NONE32, NONE32, NONE32}; }
+
+// An LDS log entry on the per-cell table path, one word: bits 0-31 the value,
+// 32-41 the local id, 42 the store flag, 43-54 the cell's table index.
+__device__ __forceinline__ u64 tab_entry(uint32_t trel, bool store, uint32_t l, int32_t v) {
+  return ((u64)trel << 43) | ((u64)(store ? 1u : 0u) << 42) | ((u64)l << 32) | (uint32_t)v;
+}
 
 // The state of one item on its workgroup (uniform values in scalars, per-lane
 // values in vector registers) and the statement semantics of paper Section 4
@@ -358,6 +378,7 @@ struct Item {
   u64 log_base;
   u64* ovl;
   uint32_t tl, WP, wave, lane, tr;
+  uint32_t nthr;           // threads of the block (64 << width class)
   bool real;
   u64* locc;
   u64* lkey;
@@ -376,30 +397,44 @@ struct Item {
   // `slot` indexes the chunk's per-instance counters, `instance` the call's.
   __device__ __forceinline__ void init(const ItemView& view, Ctl* c, uint32_t slot_, uint32_t instance_,
                                        uint32_t gid_, uint64_t seed_, u64 log_base_, u64* ovl_,
-                                       uint32_t epoch_base_, uint32_t wg_index_) {
+                                       uint32_t epoch_base_, uint32_t wg_index_, uint32_t nthr_) {
     P = view;
     ctl = c;
     slot = slot_; instance = instance_; gid = gid_; seed = seed_; log_base = log_base_; ovl = ovl_;
     epoch_base = epoch_base_; wg_index = wg_index_;
     tl = threadIdx.x;
+    // (a launch parameter, not blockDim.x: reading the block size takes a
+    // vector memory load on this target)
+    nthr = nthr_;
     WP = P.nwaves * 64u;
     wave = tl >> 6;
     lane = tl & 63u;
     real = tl < P.W;
     tr = tl < WP ? tl : WP - 1u;   // waves past the group read a real lane's registers
     // dynamic LDS after the control block: local array cells (u64), the
-    // interval log (T keys, T payload words, T values), registers, table
+    // interval log (T packed words with the table; else T keys, T payload
+    // words, T values), registers, table
     locc = reinterpret_cast<u64*>(reinterpret_cast<unsigned char*>(ctl) + ((sizeof(Ctl) + 15) & ~(size_t)15));
     lkey = locc + P.lds_local_cells;
-    lmeta = reinterpret_cast<uint32_t*>(lkey + P.lds_log_cap);
-    lval = reinterpret_cast<int32_t*>(lmeta + P.lds_log_cap);
-    regs = lval + P.lds_log_cap;
+    if (P.tab_cells) {
+      lmeta = nullptr;
+      lval = nullptr;
+      regs = reinterpret_cast<int32_t*>(lkey + P.lds_log_cap);
+    } else {
+      lmeta = reinterpret_cast<uint32_t*>(lkey + P.lds_log_cap);
+      lval = reinterpret_cast<int32_t*>(lmeta + P.lds_log_cap);
+      regs = lval + P.lds_log_cap;
+    }
     // the per-cell check table (8-byte aligned after the registers)
-    tab = reinterpret_cast<TabCell*>((reinterpret_cast<uintptr_t>(regs + P.nregs * WP) + 7u) & ~(uintptr_t)7u);
+    // (offset arithmetic from the LDS base, so that the compiler still sees
+    // an LDS pointer and emits LDS atomics on the table)
+    unsigned char* const lds0 = reinterpret_cast<unsigned char*>(ctl);
+    const size_t toff = ((size_t)(reinterpret_cast<unsigned char*>(regs + P.nregs * WP) - lds0) + 7u) & ~(size_t)7u;
+    tab = reinterpret_cast<TabCell*>(lds0 + toff);
     const TabCell empty_cell = empty_tab_cell();
-    for (uint32_t i = tl; i < P.lds_local_cells; i += blockDim.x) locc[i] = 0ull;
-    for (uint32_t i = tl; i < P.nregs * WP; i += blockDim.x) regs[i] = 0;
-    for (uint32_t i = tl; i < P.tab_cells; i += blockDim.x) tab[i] = empty_cell;
+    for (uint32_t i = tl; i < P.lds_local_cells; i += nthr) locc[i] = 0ull;
+    for (uint32_t i = tl; i < P.nregs * WP; i += nthr) regs[i] = 0;
+    for (uint32_t i = tl; i < P.tab_cells; i += nthr) tab[i] = empty_cell;
     if (tl == 0) ctl->fault = ~0ull;
     if (tl < P.n_scalars) {
       const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
@@ -500,50 +535,47 @@ struct Item {
   const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
   const RecKey K = {P.bs, P.bc, P.G, P.NI};
   if (P.tab_cells) {
-    // Per-cell table: the same two passes as intra_check, merged with LDS
-    // atomics; the cell's first log entry (the owner) finishes the check
-    // and clears the cell for the next interval.
-    for (uint32_t i = tl; i < n; i += blockDim.x) {
-      TabCell& c = tab[(uint32_t)(lkey[i] >> 16) - P.tab_base];
-      const uint32_t meta = lmeta[i];
-      const uint32_t l = meta & 1023u;
-      if (meta & 1024u) atomicMin(&c.wmin, ((u64)l << 32) | ((uint32_t)lval[i] ^ 0x80000000u));
+    // Per-cell table: the two passes of intra_check merged with LDS atomics,
+    // then one pass over the table finishes every touched cell and clears it
+    // for the next interval.  q counts w1 too: w1 wrote a second value
+    // exactly when q == w1.
+    for (uint32_t i = tl; i < n; i += nthr) {
+      const u64 e = lkey[i];
+      TabCell& c = tab[(uint32_t)(e >> 43)];
+      const uint32_t l = (uint32_t)(e >> 32) & 1023u;
+      if ((e >> 42) & 1u) atomicMin(&c.wmin, ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u));
       else atomicMin(&c.r1, l);
-      atomicMin(&c.owner, i);
     }
     __syncthreads();
-    for (uint32_t i = tl; i < n; i += blockDim.x) {
-      TabCell& c = tab[(uint32_t)(lkey[i] >> 16) - P.tab_base];
-      const uint32_t meta = lmeta[i];
-      const uint32_t l = meta & 1023u;
-      const u64 wmin = c.wmin;
-      const uint32_t w1 = wmin == ~0ull ? NONE32 : (uint32_t)(wmin >> 32);
-      const int32_t x1 = (int32_t)((uint32_t)wmin ^ 0x80000000u);
-      if (meta & 1024u) {
-        const int32_t v = lval[i];
-        if (l == w1) { if (v != x1) atomicOr(&c.multi1, 1u); }
-        else {
-          atomicMin(&c.w2, l);
-          if (v != x1) atomicMin(&c.q, l);
-        }
+    for (uint32_t i = tl; i < n; i += nthr) {
+      const u64 e = lkey[i];
+      TabCell& c = tab[(uint32_t)(e >> 43)];
+      const uint32_t l = (uint32_t)(e >> 32) & 1023u;
+      if ((e >> 42) & 1u) {
+        const u64 wmin = c.wmin;
+        const uint32_t w1 = (uint32_t)(wmin >> 32);
+        if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u)) atomicMin(&c.q, l);
+        if (l != w1) atomicMin(&c.w2, l);
       } else if (l != c.r1) {
         atomicMin(&c.r2, l);
       }
     }
     __syncthreads();
-    for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
-      const uint32_t i = b0 + tl;
+    for (uint32_t b0 = 0; b0 < P.tab_cells; b0 += nthr) {
+      const uint32_t t = b0 + tl;
       bool has = false;
       PendingRec pr;
-      if (i < n) {
-        const uint32_t ck = (uint32_t)(lkey[i] >> 16);
-        TabCell& c = tab[ck - P.tab_base];
-        if (c.owner == i) {
+      if (t < P.tab_cells) {
+        const TabCell c = tab[t];
+        if (c.wmin != ~0ull || c.r1 != NONE32) {
+          tab[t] = empty_tab_cell();
+          const uint32_t w1 = c.wmin == ~0ull ? NONE32 : (uint32_t)(c.wmin >> 32);
+          const bool multi1 = c.q != NONE32 && c.q == w1;
           const Pass1 p1 = {c.r1, c.wmin};
-          const Intra2 p2 = {c.r2, c.w2, c.q, c.multi1};
-          c = empty_tab_cell();
+          const Intra2 p2 = {c.r2, c.w2, multi1 ? NONE32 : c.q, multi1 ? 1u : 0u};
           has = intra_finish(p1, p2, &pr.label, &pr.rw, &pr.ww);
           if (has) {
+            const uint32_t ck = P.tab_base + t;
             uint32_t aid = 0;
             for (uint32_t a = 0; a < P.n_arrays; ++a) {
               const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
@@ -566,11 +598,11 @@ struct Item {
   }
   uint32_t P2 = 2;
   while (P2 < n) P2 <<= 1;
-  for (uint32_t i = n + tl; i < P2; i += blockDim.x) lkey[i] = ~0ull;
+  for (uint32_t i = n + tl; i < P2; i += nthr) lkey[i] = ~0ull;
   __syncthreads();
   for (uint32_t k = 2; k <= P2; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = tl; i < P2; i += blockDim.x) {
+      for (uint32_t i = tl; i < P2; i += nthr) {
         const uint32_t ixj = i ^ j;
         if (ixj > i) {
           const u64 a = lkey[i], b = lkey[ixj];
@@ -580,7 +612,7 @@ struct Item {
       __syncthreads();
     }
   }
-  for (uint32_t b0 = 0; b0 < n; b0 += blockDim.x) {
+  for (uint32_t b0 = 0; b0 < n; b0 += nthr) {
     const uint32_t i = b0 + tl;
     bool has = false;
     PendingRec pr;
@@ -670,13 +702,24 @@ struct Item {
       if (to_lds && lds_used + total > P.lds_log_cap) {
         // the interval outgrows LDS: move its log to the global log, where
         // the global pass checks it
-        for (uint32_t i = tl; i < lds_used; i += blockDim.x) {
+        for (uint32_t i = tl; i < lds_used; i += nthr) {
           const u64 pos = log_used + i;
-          const u64 ck = lkey[i] >> 16;
+          const u64 e = lkey[i];
+          u64 ck;
+          uint32_t meta, v;
+          if (P.tab_cells) {
+            ck = P.tab_base + (e >> 43);
+            meta = (uint32_t)(e >> 32) & 2047u;   // store flag (bit 10) and local id
+            v = (uint32_t)e;
+          } else {
+            ck = e >> 16;
+            meta = lmeta[i];
+            v = (uint32_t)lval[i];
+          }
           if (pos < P.wg_log_cap) {
             P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
-            P.log_vals[log_base + pos] = ((u64)(uint32_t)lval[i] << 32) | lmeta[i];
-            if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (lmeta[i] & 1023u);
+            P.log_vals[log_base + pos] = ((u64)v << 32) | meta;
+            if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
           } else {
             atomicOr(P.status_word, 1u);
           }
@@ -691,9 +734,13 @@ struct Item {
       if (to_lds) {
         if (rec) {
           const uint32_t j = lds_used + below;
-          lkey[j] = ((u64)(A.cellbase + cell) << 16) | j;
-          lmeta[j] = meta;
-          lval[j] = val;
+          if (P.tab_cells) {
+            lkey[j] = tab_entry(A.cellbase + cell - P.tab_base, op == OP_STORE, tl, val);
+          } else {
+            lkey[j] = ((u64)(A.cellbase + cell) << 16) | j;
+            lmeta[j] = meta;
+            lval[j] = val;
+          }
         }
         lds_used += total;
       } else {
@@ -768,7 +815,10 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
   Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
   const uint32_t ci = const_load<uint32_t>(PP.chunk_index, 0);
   const ChunkDesc C = const_load<ChunkDesc>(PP.chunks, ci);
-  const uint32_t i0 = C.item0[PP.wclass], i1 = C.item0[PP.wclass + 1];
+  // (the class bounds are read from memory: a dynamic index into the loaded
+  // descriptor would go through scratch)
+  const uint32_t* item0 = PP.chunks[ci].item0;
+  const uint32_t i0 = const_load<uint32_t>(item0, PP.wclass), i1 = const_load<uint32_t>(item0, PP.wclass + 1);
   if (i0 == i1) return;
   for (;;) {
     if (threadIdx.x == 0) ctl->item = i0 + atomicAdd(&PP.queue[PP.wclass], 1u);
@@ -794,7 +844,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.cell_owner = PP.cell_owner; P.co_stride = PP.cell_owner_stride;
     Item it;
     it.init(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,
-            PP.overlay + S.ovl_base + (u64)gid * D.overlay_cells, C.epoch, S.wg_base + gid);
+            PP.overlay + S.ovl_base + (u64)gid * D.overlay_cells, C.epoch, S.wg_base + gid, 64u << PP.wclass);
     body(it);
     it.finish();
   }

@@ -1,0 +1,303 @@
+// ownership.cpp -- the owned-array proof of ownership.h: an abstract
+// interpretation of the bytecode over affine forms.
+#include "ownership.h"
+
+#include <algorithm>
+#include <map>
+#include <utility>
+
+#include "rc_internal.h"
+
+namespace rc {
+
+namespace {
+
+typedef __int128 i128;
+constexpr int64_t I32_MIN = -(int64_t(1) << 31), I32_MAX = (int64_t(1) << 31) - 1;
+constexpr int64_t COEF_MAX = int64_t(1) << 34;   // larger coefficients: unknown
+constexpr uint64_t VISIT_MAX = 20000000;         // instructions interpreted before giving up
+
+bool fits(i128 v) { return v <= COEF_MAX && v >= -COEF_MAX; }
+
+// c0 + cg * gid + cl * lid + sum(coef * loop counter), or unknown (top)
+struct Form {
+  bool top = true;
+  int64_t c0 = 0, cg = 0, cl = 0;
+  std::vector<std::pair<uint32_t, int64_t>> lc;   // (loop, coefficient), by loop, no zero coefficients
+
+  bool operator==(const Form& o) const {
+    if (top || o.top) return top == o.top;
+    return c0 == o.c0 && cg == o.cg && cl == o.cl && lc == o.lc;
+  }
+};
+
+Form unknown() { return Form(); }
+Form konst(int64_t v) {
+  Form f;
+  f.top = false;
+  f.c0 = v;
+  return f;
+}
+
+struct Range {
+  int64_t lo, hi;
+};
+
+class Prover {
+ public:
+  Prover(const Compiled& c, uint32_t G, uint32_t W) : c_(c), G_(G), W_(W) {}
+
+  std::vector<uint8_t> run() {
+    const uint32_t na = (uint32_t)c_.arrays.size();
+    std::vector<uint8_t> owned(na, 1);
+    if ((uint64_t)G_ * W_ <= 1) return owned;   // one work-item: no pair exists
+    std::vector<Form> env(MAX_REGS, konst(0));   // private variables start at 0
+    block(0, (uint32_t)(c_.code.size() / 4), env);
+    if (visits_ > VISIT_MAX) return std::vector<uint8_t>(na, 0);   // gave up: nothing is owned
+    // per array: one stride, offsets within a range shorter than it
+    std::vector<int64_t> stride(na, 0), olo(na, I32_MAX), ohi(na, I32_MIN);
+    for (const auto& acc : access_) {
+      const uint32_t a = acc.first.second;
+      const Form& f = acc.second;
+      if (!owned[a]) continue;
+      if (f.top) { owned[a] = 0; continue; }
+      int64_t S;
+      if (W_ == 1) {
+        S = f.cg;
+      } else {
+        S = f.cl;
+        if (G_ > 1 && f.cg != S * (int64_t)W_) { owned[a] = 0; continue; }
+      }
+      if (S == 0 || (stride[a] != 0 && stride[a] != S)) { owned[a] = 0; continue; }
+      stride[a] = S;
+      Form off = f;
+      off.cg = 0;
+      off.cl = 0;
+      const Range r = range(off);
+      olo[a] = std::min(olo[a], r.lo);
+      ohi[a] = std::max(ohi[a], r.hi);
+      const int64_t span = S < 0 ? -S : S;
+      if (ohi[a] - olo[a] >= span) owned[a] = 0;
+    }
+    return owned;
+  }
+
+ private:
+  const Compiled& c_;
+  const uint32_t G_, W_;
+  std::map<uint32_t, Range> loops_;                           // loop (its FOR index) -> counter range
+  std::map<std::pair<uint32_t, uint32_t>, Form> access_;      // (instruction, array) -> index form
+  uint64_t visits_ = 0;
+
+  uint32_t word(uint32_t i, int k) const { return c_.code[4 * i + k]; }
+
+  // the values a form takes over gid in [0, G), lid in [0, W) and the loop ranges
+  // (saturated to +-2^62; coefficients are at most 2^34 and symbols int32)
+  Range range(const Form& f) const {
+    i128 lo = f.c0, hi = f.c0;
+    auto add = [&](int64_t coef, int64_t a0, int64_t a1) {
+      const i128 a = (i128)coef * a0, b = (i128)coef * a1;
+      lo += std::min(a, b);
+      hi += std::max(a, b);
+    };
+    add(f.cg, 0, (int64_t)G_ - 1);
+    add(f.cl, 0, (int64_t)W_ - 1);
+    for (const auto& t : f.lc) {
+      const Range lr = loops_.at(t.first);
+      add(t.second, lr.lo, lr.hi);
+    }
+    const i128 cap = (i128)1 << 62;
+    return Range{(int64_t)std::max(lo, -cap), (int64_t)std::min(hi, cap)};
+  }
+
+  // drop symbols with a single value, bound the coefficients, and require
+  // the value to stay inside int32 for every value of the symbols
+  Form norm(Form f) const {
+    if (f.top) return f;
+    if (G_ == 1) f.cg = 0;
+    if (W_ == 1) f.cl = 0;
+    std::vector<std::pair<uint32_t, int64_t>> lc;
+    for (const auto& t : f.lc) {
+      const Range lr = loops_.at(t.first);
+      if (lr.lo == lr.hi) {
+        const i128 c0 = (i128)f.c0 + (i128)t.second * lr.lo;
+        if (!fits(c0)) return unknown();
+        f.c0 = (int64_t)c0;
+      } else if (t.second != 0) {
+        lc.push_back(t);
+      }
+    }
+    f.lc = lc;
+    const Range r = range(f);
+    if (r.lo < I32_MIN || r.hi > I32_MAX) return unknown();
+    return f;
+  }
+
+  // x + sy * y (sy = +-1) and k * x: exact in 128 bits, unknown when a
+  // coefficient leaves +-2^34 (operands are normalised forms)
+  static Form combine(const Form& x, const Form& y, int64_t sy) {
+    if (x.top || y.top) return unknown();
+    const i128 c0 = (i128)x.c0 + (i128)sy * y.c0, cg = (i128)x.cg + (i128)sy * y.cg,
+               cl = (i128)x.cl + (i128)sy * y.cl;
+    if (!fits(c0) || !fits(cg) || !fits(cl)) return unknown();
+    Form r;
+    r.top = false;
+    r.c0 = (int64_t)c0;
+    r.cg = (int64_t)cg;
+    r.cl = (int64_t)cl;
+    std::map<uint32_t, i128> m;
+    for (const auto& t : x.lc) m[t.first] += t.second;
+    for (const auto& t : y.lc) m[t.first] += (i128)sy * t.second;
+    for (const auto& t : m) {
+      if (!fits(t.second)) return unknown();
+      if (t.second != 0) r.lc.emplace_back(t.first, (int64_t)t.second);
+    }
+    return r;
+  }
+
+  static bool is_const(const Form& f) { return !f.top && f.cg == 0 && f.cl == 0 && f.lc.empty(); }
+
+  static Form scale(const Form& x, int64_t k) {
+    if (x.top || !fits(k)) return unknown();
+    const i128 c0 = (i128)x.c0 * k, cg = (i128)x.cg * k, cl = (i128)x.cl * k;
+    if (!fits(c0) || !fits(cg) || !fits(cl)) return unknown();
+    Form r;
+    r.top = false;
+    r.c0 = (int64_t)c0;
+    r.cg = (int64_t)cg;
+    r.cl = (int64_t)cl;
+    for (const auto& t : x.lc) {
+      const i128 v = (i128)t.second * k;
+      if (!fits(v)) return unknown();
+      if (v != 0) r.lc.emplace_back(t.first, (int64_t)v);
+    }
+    return r;
+  }
+
+  Form operand(bool imm, uint32_t w, const std::vector<Form>& env) const {
+    if (imm) return konst((int32_t)w);
+    if (w < MAX_REGS) return env[w];
+    Form f;
+    f.top = false;
+    switch (w) {
+      case SEL_LID: f.cl = 1; break;
+      case SEL_GID: f.cg = 1; break;
+      case SEL_TID: f.cg = W_; f.cl = 1; break;
+      case SEL_WGSIZE: f.c0 = W_; break;
+      case SEL_NGROUPS: f.c0 = G_; break;
+      case SEL_NTHREADS: f.c0 = (int64_t)G_ * W_; break;
+      default: return unknown();   // scalar parameters
+    }
+    return norm(f);
+  }
+
+  Form binary(uint32_t op, const Form& x, const Form& y) const {
+    switch (op) {
+      case B_ADD: return norm(combine(x, y, 1));
+      case B_SUB: return norm(combine(x, y, -1));
+      case B_MUL:
+        if (is_const(y)) return norm(scale(x, y.c0));
+        if (is_const(x)) return norm(scale(y, x.c0));
+        return unknown();
+      case B_SHL:
+        if (is_const(y)) {
+          const int64_t k = ((y.c0 % 32) + 32) % 32;   // the count is taken mod 32
+          return norm(scale(x, int64_t(1) << k));
+        }
+        return unknown();
+      default:
+        return unknown();
+    }
+  }
+
+  static void join(std::vector<Form>& a, const std::vector<Form>& b) {
+    for (size_t r = 0; r < a.size(); ++r)
+      if (!(a[r] == b[r])) a[r] = unknown();
+  }
+
+  // instructions [i, end) of one structured block
+  void block(uint32_t i, uint32_t end, std::vector<Form>& env) {
+    while (i < end) {
+      if (++visits_ > VISIT_MAX) return;
+      const uint32_t h = word(i, 0), op = h & 63u, sub = (h >> 8) & 63u, dst = (h >> 14) & 63u;
+      const bool fa = (h >> 6) & 1u, fb = (h >> 7) & 1u;
+      switch (op) {
+        case OP_BIN:
+          env[dst] = binary(sub, operand(fa, word(i, 1), env), operand(fb, word(i, 2), env));
+          ++i;
+          break;
+        case OP_UN: {
+          const Form x = operand(fa, word(i, 1), env);
+          env[dst] = sub == U_MOV ? x : sub == U_NEG ? norm(scale(x, -1)) : unknown();
+          ++i;
+          break;
+        }
+        case OP_LOAD:
+          access_[{i, word(i, 3)}] = operand(fa, word(i, 1), env);
+          env[dst] = unknown();
+          ++i;
+          break;
+        case OP_STORE:
+          access_[{i, word(i, 3)}] = operand(fa, word(i, 1), env);
+          ++i;
+          break;
+        case OP_IF: {
+          const uint32_t at_else = word(i, 2), at_endif = word(at_else, 3);
+          std::vector<Form> other = env;
+          block(i + 1, at_else, env);
+          block(at_else + 1, at_endif, other);
+          join(env, other);
+          i = at_endif + 1;
+          break;
+        }
+        case OP_FOR: {
+          const int64_t lo = (int32_t)word(i, 1), hi = (int32_t)word(i, 2);
+          const uint32_t after = word(i, 3);   // the instruction after ENDFOR
+          if (hi - lo <= 0) {                  // the body never runs
+            env[dst] = konst(lo);
+            i = after;
+            break;
+          }
+          loops_[i] = Range{lo, hi - 1};
+          Form counter;
+          counter.top = false;
+          counter.lc.emplace_back(i, 1);
+          counter = norm(counter);
+          // the state at the top of the body: the entry state joined with
+          // the state after each iteration, the counter reset by ENDFOR
+          std::vector<Form> head = env;
+          head[dst] = counter;
+          std::vector<Form> body;
+          for (;;) {
+            body = head;
+            block(i + 1, after - 1, body);   // also records the accesses of this pass
+            std::vector<Form> next = head;
+            join(next, body);
+            next[dst] = counter;
+            if (next == head) break;
+            head = next;
+          }
+          // after the last iteration ENDFOR leaves the counter at hi
+          env = body;
+          env[dst] = konst(hi);
+          i = after;
+          break;
+        }
+        case OP_END:
+          return;
+        default:   // barrier, assert, assume
+          ++i;
+          break;
+      }
+    }
+  }
+};
+
+}  // namespace
+
+std::vector<uint8_t> owned_arrays(const Compiled& c, uint32_t G, uint32_t W) {
+  Prover p(c, G, W);
+  return p.run();
+}
+
+}  // namespace rc

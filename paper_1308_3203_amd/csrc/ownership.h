@@ -1,0 +1,32 @@
+// ownership.h -- arrays whose cells each belong to a single work-item.
+//
+// Every record of the check (the race rule of the global semantics, paper
+// Section 4, as checked here per cell) pairs accesses of two different
+// work-items to one cell.  When the program's index expressions show that no
+// two work-items can ever touch a common cell of an array, that array can
+// carry no record, and its accesses need no log.  This pass proves it for
+// index expressions that are affine in the work-item id.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "frontend.h"
+
+namespace rc {
+
+// For an NDRange of G groups of W work-items: owned[a] = 1 when every load
+// and store of array a touches a cell S * tid + o, with one stride S != 0 for
+// all of the array's accesses and every offset o in one range [lo, hi] with
+// hi - lo < |S| (tid = gid * W + lid).  The proof follows the bytecode:
+// private variables start at 0, each register holds an affine form in gid,
+// lid and the loop counters (each with its known range) or is unknown, the
+// two branches of an if are joined, and a loop's entry state is iterated to
+// a fixed point.  Every intermediate value must stay inside int32 for all
+// values of its symbols, so the forms compute exactly what the wrapping
+// int32 arithmetic does.  Loads, scalar parameters and any operation other
+// than +, -, negation, multiplication by a constant and a left shift by a
+// constant give an unknown value.  With one work-item every array is owned.
+std::vector<uint8_t> owned_arrays(const Compiled& c, uint32_t G, uint32_t W);
+
+}  // namespace rc

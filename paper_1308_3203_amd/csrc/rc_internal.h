@@ -106,10 +106,11 @@ struct ProgDesc {                 // one program of the call
   uint32_t tab_base, tab_cells, pad2[2];
 };
 
-// one cell's running check state in the LDS table (32 bytes)
+// one cell's running check state in the LDS table (24 bytes)
 struct TabCell {
   unsigned long long wmin;   // (writer lid, value ^ sign) minimum
-  uint32_t r1, r2, w2, q, multi1, owner;
+  uint32_t r1, r2, w2;       // smallest reader; second reader; smallest writer other than w1
+  uint32_t q;                // smallest writer of a value other than x1 (w1 included)
 };
 constexpr uint32_t TAB_MAX_CELLS = 4096;
 

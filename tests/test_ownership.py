@@ -1,0 +1,165 @@
+"""The owned-array proof (host logic of the library, no device).
+
+An array is owned when no two work-items can touch a common cell of it; the
+library then skips logging its accesses.  Hand cases pin what the proof
+accepts and rejects, including int32 wrap-around, loop-carried variables and
+branch joins; a randomised check against the oracle (which logs every access)
+confirms that no owned array ever carries a record."""
+import random
+
+import pytest
+
+from oracle import oracle as O
+from paper_1308_3203_amd import binding as B
+from paper_1308_3203_amd import workloads as WL
+
+
+def owned(body, G, W, decl="global int x[4096], global int y[4096]", vars_="int v, w, k, j"):
+    src = f"kernel t({decl}) {{\n  {vars_};\n{body}\n}}\n"
+    return B.owned_arrays(src, G, W)
+
+
+CASES = [
+    # (body, G, W, expected ownership of x, y)
+    ("  x[tid] := 1;", 4, 64, [True, True]),
+    ("  x[tid] := 1;\n  v := x[tid + 1];", 4, 64, [False, True]),
+    ("  x[2 * tid] := 1;\n  x[2 * tid + 1] := 2;", 4, 64, [True, True]),
+    ("  x[2 * tid] := 1;\n  x[2 * tid + 2] := 2;", 4, 64, [False, True]),
+    ("  x[lid] := 1;", 2, 64, [False, True]),
+    ("  x[lid] := 1;", 1, 64, [True, True]),
+    ("  x[gid] := 1;", 8, 1, [True, True]),
+    ("  x[gid * wgsize + lid] := 1;", 8, 32, [True, True]),
+    ("  x[gid * 64 + lid] := 1;", 8, 32, [False, True]),
+    ("  x[1000 - tid] := 1;", 4, 64, [True, True]),
+    ("  x[tid << 2] := 1;\n  x[(tid << 2) + 3] := 1;", 4, 64, [True, True]),
+    ("  for k in 0..4 {\n    x[tid * 4 + k] := k;\n  }", 4, 64, [True, True]),
+    ("  for k in 0..5 {\n    x[tid * 4 + k] := k;\n  }", 4, 64, [False, True]),
+    ("  for k in 0..4 {\n    for j in 0..4 {\n      x[tid * 16 + k * 4 + j] := 1;\n    }\n  }", 2, 32,
+     [True, True]),
+    ("  for k in 0..4 {\n    for j in 0..4 {\n      x[tid * 16 + k * 4 + j * 2] := 1;\n    }\n  }", 2, 32,
+     [False, True]),
+    ("  v := tid * 4;\n  for k in 0..4 {\n    x[v + k] := 1;\n  }", 4, 64, [True, True]),
+    # a loop-carried index: tid, tid + 1, tid + 2 overlap between work-items
+    ("  v := tid;\n  for k in 0..3 {\n    x[v] := 1;\n    v := v + 1;\n  }", 4, 64, [False, True]),
+    # branches that assign different forms join to unknown
+    ("  if (tid < 5) {\n    v := tid;\n  } else {\n    v := tid - 1;\n  }\n  x[v] := 1;", 4, 64,
+     [False, True]),
+    ("  if (tid < 5) {\n    v := tid * 2;\n  } else {\n    v := tid * 2;\n  }\n  x[v] := 1;", 4, 64,
+     [True, True]),
+    # 4 * 2^30 wraps to 0 in int32: work-items 0 and 4 share cell 0
+    ("  x[tid * 1073741824] := 1;", 1, 8, [False, True]),
+    ("  x[tid mod 64] := 1;", 1, 64, [False, True]),
+    ("  v := y[tid];\n  x[v] := 1;", 4, 64, [False, True]),
+    ("  v := x[0];\n  x[tid] := v;", 4, 64, [False, True]),
+    ("  x[tid] := 1;\n  barrier;\n  v := x[tid];\n  y[tid] := v;", 4, 64, [True, True]),
+]
+
+
+@pytest.mark.parametrize("body,G,W,expect", CASES)
+def test_owned_cases(body, G, W, expect):
+    assert owned(body, G, W) == expect
+
+
+def test_scalar_in_index_is_unknown():
+    src = "kernel t(global int x[4096], int s) {\n  x[tid + s] := 1;\n}\n"
+    assert B.owned_arrays(src, 4, 64) == [False]
+    src = "kernel t(global int x[4096], int s) {\n  x[tid] := s;\n}\n"
+    assert B.owned_arrays(src, 4, 64) == [True]
+
+
+def test_one_work_item_owns_everything():
+    assert owned("  v := x[7];\n  x[v] := 1;\n  y[0] := 2;", 1, 1) == [True, True]
+
+
+def test_local_arrays():
+    src = ("kernel t(global int x[4096]) {\n  local int l[256];\n  int v;\n  l[lid] := 1;\n  barrier;\n"
+           "  v := l[lid];\n  x[tid] := v;\n}\n")
+    assert B.owned_arrays(src, 1, 64) == [True, True]
+    # with several groups the proof asks for distinct cells across the whole
+    # NDRange, which a per-group local array indexed by lid does not meet
+    assert B.owned_arrays(src, 4, 64) == [True, False]
+    src2 = src.replace("v := l[lid];", "v := l[lid + 1];")
+    assert B.owned_arrays(src2, 1, 64) == [True, False]
+
+
+def test_c2_templates():
+    got = {w.name: B.owned_arrays(w.src, w.G, w.W) for w in WL.c2_templates()}
+    # prefix sum: each work-item scans its own 16 cells of inp and out
+    assert got["prefix_sum"] == [True, True, False]
+    assert got["prefix_sum_race"] == [True, True, False]
+    assert got["tree_reduce"][1] is False          # out[gid] by lid 0: not provable
+    assert got["transpose"][1] is False            # div / mod in the index
+
+
+def test_errors():
+    with pytest.raises(B.RcError):
+        B.owned_arrays("kernel t(global int x[4]) { x[tid] := ; }", 1, 4)
+    with pytest.raises(B.RcError):
+        B.owned_arrays("kernel t(global int x[4]) { x[tid] := 1; }", 1, 2000)
+
+
+def _random_affine_program(r: random.Random):
+    """Affine indices over tid, lid, gid, loop counters and variables, with
+    branches and loop-carried updates; cells stay small so collisions are
+    common when the proof does not hold."""
+    def atom(loops):
+        k = r.random()
+        if k < 0.3:
+            return r.choice(["tid", "lid", "gid"])
+        if k < 0.5 and loops:
+            return r.choice(loops)
+        if k < 0.75:
+            return r.choice(["v", "w"])
+        return str(r.randint(0, 8))
+
+    def expr(loops, d=0):
+        if d >= 2 or r.random() < 0.4:
+            return atom(loops)
+        op = r.choice(["+", "-", "*", "<<"])
+        if op == "*":
+            return f"({expr(loops, d + 1)} * {r.randint(-3, 4)})"
+        if op == "<<":
+            return f"({expr(loops, d + 1)} << {r.randint(0, 3)})"
+        return f"({expr(loops, d + 1)} {op} {expr(loops, d + 1)})"
+
+    def stmts(n, loops, depth):
+        out = []
+        for _ in range(n):
+            k = r.random()
+            if k < 0.3:
+                out.append(f"{r.choice(['v', 'w'])} := {expr(loops)};")
+            elif k < 0.6:
+                out.append(f"x[{expr(loops)}] := {expr(loops)};")
+            elif k < 0.75:
+                out.append(f"{r.choice(['v', 'w'])} := x[{expr(loops)}];")
+            elif k < 0.85 and depth < 2:
+                body = " ".join(stmts(r.randint(1, 3), loops, depth + 1))
+                els = " ".join(stmts(r.randint(0, 2), loops, depth + 1))
+                out.append(f"if (tid < {r.randint(0, 40)}) {{ {body} }} else {{ {els} }}")
+            elif depth < 2:
+                lv = ["k", "j"][len(loops)] if len(loops) < 2 else None
+                if lv is None:
+                    continue
+                body = " ".join(stmts(r.randint(1, 3), loops + [lv], depth + 1))
+                out.append(f"for {lv} in 0..{r.randint(1, 4)} {{ {body} }}")
+        return out
+
+    # a few templates that the proof accepts, mixed with random statements
+    stride = r.choice([1, 2, 3, 4])
+    own = [f"x[tid * {stride} + {o}] := {expr([])};" for o in range(r.randint(1, stride))]
+    body = own + stmts(r.randint(1, 6), [], 0) if r.random() < 0.5 else own
+    return ("kernel t(global int x[256]) {\n  int v, w, k, j;\n  " + "\n  ".join(body) + "\n}\n")
+
+
+def test_owned_arrays_never_carry_records():
+    r = random.Random(20240611)
+    n_owned = 0
+    for case in range(300):
+        src = _random_affine_program(r)
+        G, W = r.choice([(1, 8), (2, 8), (4, 4), (3, 16)])
+        own = B.owned_arrays(src, G, W)
+        res = O.Program(src).run(G, W, arrays={"x": ("seeded", 0, 4)}, seed=case)
+        if own[0]:
+            n_owned += 1
+            assert not any(int(rec["array"]) == 0 for rec in res.records), (src, G, W)
+    assert n_owned >= 50

@@ -78,6 +78,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1308_3203_amd/build.py "
                            "(there is no CPU fallback)")
+    # torch ships its own HIP runtime; it has to be in the process before the
+    # library pulls in a runtime of its own, or the two do not share devices
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, u32, u64, i32, i64, sz = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
                                   ctypes.c_int64, ctypes.c_size_t)

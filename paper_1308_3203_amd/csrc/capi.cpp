@@ -909,9 +909,9 @@ rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint
   std::string err;
   bool is_limit = false;
   if (!compile_program(src, len, &c, &err, &is_limit)) return fail(is_limit ? RC_E_LIMIT : RC_E_PARSE, "%s", err.c_str());
-  const std::vector<uint8_t> o = owned_arrays(c, num_groups, group_size);
+  const std::vector<OwnedArray> o = owned_arrays(c, num_groups, group_size);
   *n_arrays = (uint32_t)o.size();
-  for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a];
+  for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a].owned;
   return RC_OK;
 }
 
@@ -973,7 +973,31 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->G = num_groups;
   p->W = W;
   p->shaped = true;
-  p->owned = owned_arrays(p->c, p->G, p->W);
+  const std::vector<OwnedArray> own = owned_arrays(p->c, p->G, p->W);
+  p->owned.assign(own.size(), 0);
+  for (size_t a = 0; a < own.size(); ++a) p->owned[a] = own[a].owned;
+  // overlay words per group: a global rw array owned with a stride keeps its
+  // work-items' cells lane by lane (so a wave's accesses to one offset are
+  // consecutive words), in own_span * W words instead of one word per cell
+  uint32_t ov = 0;
+  for (size_t a = 0; a < own.size(); ++a) {
+    ArrayDesc& d = p->arrays[a];
+    d.own_stride = 0;
+    d.own_lo = 0;
+    d.own_span = 0;
+    if (d.kind != AK_GLOBAL_RW) continue;
+    d.offset = ov;
+    const u64 span = own[a].stride != 0 ? (u64)(own[a].hi - own[a].lo + 1) : 0;
+    if (span != 0 && span * W <= d.size) {
+      d.own_stride = (int32_t)own[a].stride;
+      d.own_lo = (int32_t)own[a].lo;
+      d.own_span = (uint32_t)span;
+      ov += (uint32_t)(span * W);
+    } else {
+      ov += d.size;
+    }
+  }
+  p->overlay_cells = ov;
   p->logged_mem = p->c.dyn_logged_mem;
   p->logged_local = p->c.dyn_logged_local;
   for (size_t a = 0; a < p->owned.size(); ++a) {
@@ -1285,7 +1309,10 @@ rc_status rc_sync(rc_ctx* ctx) {
       msg = std::string("reading check status: ") + hipGetErrorString(e);
       break;
     }
-    if (status != 0u) {
+    if (status & 4u) {
+      result = RC_E_HIP;
+      msg = "internal error: an access left its owned-array placement";
+    } else if (status != 0u) {
       result = RC_E_HIP;
       msg = "internal capacity exceeded (access log or record staging)";
     } else if (n > pd.cap && result == RC_OK) {
@@ -1321,6 +1348,10 @@ rc_status rc_read_final(rc_prog* p, uint64_t seed, uint32_t array_id, int32_t* d
   M.G = p->G;
   M.overlay_cells = p->overlay_cells;
   M.offset = A.offset;
+  M.W = p->W;
+  M.own_stride = A.own_stride;
+  M.own_lo = A.own_lo;
+  M.own_span = A.own_span;
   M.array_id = array_id;
   M.bind = A.bind;
   M.rw = A.kind == AK_GLOBAL_RW ? 1u : 0u;

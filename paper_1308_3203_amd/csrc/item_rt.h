@@ -483,10 +483,11 @@ struct Item {
     }
     if (lane == 0) ctl->red[parity][wave] = mine;
     __syncthreads();
-    uint32_t acc = 0;
-    for (uint32_t w = 0; w < P.nwaves; ++w) acc |= ctl->red[parity][w];
+    // lane w reads wave w's word: one LDS round trip whatever the width
+    const uint32_t x = lane < P.nwaves ? ctl->red[parity][lane] : 0u;
     parity ^= 1u;
-    return uni(acc);
+    return (__ballot(x & 1u) != 0ull ? 1u : 0u) | (__ballot(x & 2u) != 0ull ? 2u : 0u) |
+           (__ballot(x & 4u) != 0ull ? 4u : 0u);
   }
 
   // The same snapshot reduction for a memory statement: bit 0 of each wave's
@@ -504,17 +505,22 @@ struct Item {
     }
     if (lane == 0) ctl->red[parity][wave] = (bf != 0ull ? 1u : 0u) | (cnt << 8);
     __syncthreads();
-    uint32_t f = 0, tot = 0, pre = 0;
-    for (uint32_t w = 0; w < P.nwaves; ++w) {
-      const uint32_t x = ctl->red[parity][w];
-      f |= x & 1u;
-      tot += x >> 8;
-      if (w < wave) pre += x >> 8;
-    }
+    // lane w reads wave w's word; the counts (at most 64: 7 bits) are summed
+    // bit-plane by bit-plane with ballots, over all waves and over the waves
+    // before this one
+    const uint32_t x = lane < P.nwaves ? ctl->red[parity][lane] : 0u;
     parity ^= 1u;
-    *prefix = uni(pre);
-    *total = uni(tot);
-    return uni(f) != 0u;
+    const u64 before = (1ull << wave) - 1ull;
+    uint32_t tot = 0, pre = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 7; ++b) {
+      const u64 m = __ballot((x >> (8u + b)) & 1u);
+      tot += (uint32_t)__popcll(m) << b;
+      pre += (uint32_t)__popcll(m & before) << b;
+    }
+    *prefix = pre;
+    *total = tot;
+    return __ballot(x & 1u) != 0ull;
   }
 
   __device__ __forceinline__ void raise(uint32_t spc, uint32_t code) {
@@ -668,6 +674,17 @@ struct Item {
     uint32_t prefix, total;
     if (mem_red(rec, &brec, &prefix, &total)) return true;
     const uint32_t cell = (uint32_t)idx;
+    // overlay word of the cell: by cell, or for an owned array by (offset
+    // from the work-item's stride, lid), which keeps a wave's words together
+    uint32_t word_at = A.offset + cell;
+    bool placed = true;
+    if (A.kind == AK_GLOBAL_RW && A.own_stride != 0 && active) {
+      // (mod 2^32, as the index arithmetic itself)
+      const uint32_t o = (uint32_t)idx - (uint32_t)A.own_stride * (gid * P.W + tl) - (uint32_t)A.own_lo;
+      placed = o < A.own_span;
+      word_at = A.offset + o * P.W + tl;
+      if (!placed) atomicOr(P.status_word, 4u);   // the ownership proof does not hold
+    }
     if (op == OP_LOAD) {
       if (active) {
         int32_t v;
@@ -676,8 +693,8 @@ struct Item {
         } else {
           bool have = false;
           v = 0;
-          if (A.kind == AK_GLOBAL_RW) {
-            u64 w = __hip_atomic_load(&ovl[A.offset + cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (A.kind == AK_GLOBAL_RW && placed) {
+            u64 w = __hip_atomic_load(&ovl[word_at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((uint32_t)(w >> 42) >= epoch_base) { v = (int32_t)(uint32_t)w; have = true; }
           }
           if (!have)
@@ -693,6 +710,9 @@ struct Item {
         const uint32_t ep = A.kind == AK_LOCAL ? store_seq : epoch_base + store_seq;
         const u64 word = ((u64)((ep << 10) | tl) << 32) | (uint32_t)val;
         if (A.kind == AK_LOCAL) atomicMax(&locc[A.offset + cell], word);
+        else if (A.own_stride != 0) {   // no other work-item has this word
+          if (placed) __hip_atomic_store(&ovl[word_at], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         else atomicMax(&ovl[A.offset + cell], word);
         ++n_acc;
       }

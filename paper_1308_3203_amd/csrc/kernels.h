@@ -81,6 +81,8 @@ struct SetupParams {
 
 struct FinalMemParams {
   uint32_t size, G, overlay_cells, offset, array_id, bind, rw, epoch;
+  uint32_t W, own_span;
+  int32_t own_stride, own_lo;   // placement of an owned array (ArrayDesc)
   int64_t lo, hi;
   uint64_t seed;
   const int32_t* dptr;

@@ -859,7 +859,19 @@ __global__ __launch_bounds__(256) void final_merge_kernel(FinalMemParams M) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= M.size) return;
   int32_t v = M.bind == BIND_SEEDED ? seeded_cell(M.seed, M.array_id, c, M.lo, M.hi) : M.dptr[c];
-  if (M.rw) {
+  if (M.rw && M.own_stride != 0) {
+    // an owned array: the one work-item whose cells include c, if any
+    const int64_t S = M.own_stride, lo = M.own_lo, cc = c;
+    int64_t t;
+    if (S > 0) t = (cc - lo) >= 0 ? (cc - lo) / S : -(((lo - cc) + S - 1) / S);
+    else t = (lo - cc) >= 0 ? ((lo - cc) + (-S) - 1) / (-S) : -((cc - lo) / (-S));
+    const int64_t o = cc - S * t - lo;
+    if (t >= 0 && t < (int64_t)M.G * M.W && o >= 0 && o < (int64_t)M.own_span) {
+      const uint64_t g = (uint64_t)t / M.W, l = (uint64_t)t % M.W;
+      const u64 w = M.overlay[g * M.overlay_cells + M.offset + (uint64_t)o * M.W + l];
+      if ((uint32_t)(w >> 42) >= M.epoch) v = (int32_t)(uint32_t)w;
+    }
+  } else if (M.rw) {
     for (uint32_t g = 0; g < M.G; ++g) {
       const u64 w = M.overlay[(size_t)g * M.overlay_cells + M.offset + c];
       if ((uint32_t)(w >> 42) >= M.epoch) v = (int32_t)(uint32_t)w;

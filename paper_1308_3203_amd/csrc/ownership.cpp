@@ -47,13 +47,15 @@ class Prover {
  public:
   Prover(const Compiled& c, uint32_t G, uint32_t W) : c_(c), G_(G), W_(W) {}
 
-  std::vector<uint8_t> run() {
+  std::vector<OwnedArray> run() {
     const uint32_t na = (uint32_t)c_.arrays.size();
     std::vector<uint8_t> owned(na, 1);
-    if ((uint64_t)G_ * W_ <= 1) return owned;   // one work-item: no pair exists
+    std::vector<OwnedArray> out(na);
+    for (OwnedArray& o : out) o.owned = 1;
+    if ((uint64_t)G_ * W_ <= 1) return out;     // one work-item: no pair exists
     std::vector<Form> env(MAX_REGS, konst(0));   // private variables start at 0
     block(0, (uint32_t)(c_.code.size() / 4), env);
-    if (visits_ > VISIT_MAX) return std::vector<uint8_t>(na, 0);   // gave up: nothing is owned
+    if (visits_ > VISIT_MAX) return std::vector<OwnedArray>(na);   // gave up: nothing is owned
     // per array: one stride, offsets within a range shorter than it
     std::vector<int64_t> stride(na, 0), olo(na, I32_MAX), ohi(na, I32_MIN);
     for (const auto& acc : access_) {
@@ -79,7 +81,15 @@ class Prover {
       const int64_t span = S < 0 ? -S : S;
       if (ohi[a] - olo[a] >= span) owned[a] = 0;
     }
-    return owned;
+    for (uint32_t a = 0; a < na; ++a) {
+      out[a].owned = owned[a];
+      if (owned[a] && stride[a] != 0) {
+        out[a].stride = stride[a];
+        out[a].lo = olo[a];
+        out[a].hi = ohi[a];
+      }
+    }
+    return out;
   }
 
  private:
@@ -295,7 +305,7 @@ class Prover {
 
 }  // namespace
 
-std::vector<uint8_t> owned_arrays(const Compiled& c, uint32_t G, uint32_t W) {
+std::vector<OwnedArray> owned_arrays(const Compiled& c, uint32_t G, uint32_t W) {
   Prover p(c, G, W);
   return p.run();
 }

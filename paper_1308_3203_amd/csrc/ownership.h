@@ -27,6 +27,15 @@ namespace rc {
 // int32 arithmetic does.  Loads, scalar parameters and any operation other
 // than +, -, negation, multiplication by a constant and a left shift by a
 // constant give an unknown value.  With one work-item every array is owned.
-std::vector<uint8_t> owned_arrays(const Compiled& c, uint32_t G, uint32_t W);
+//
+// For an owned array with stride != 0 every cell touched is stride * tid + o
+// with o in [lo, hi] (hi - lo < |stride|), so a work-item's cells can be
+// placed by (o - lo, lid) instead of by cell.  stride == 0: owned with no
+// such placement (the array is never accessed, or there is one work-item).
+struct OwnedArray {
+  uint8_t owned = 0;
+  int64_t stride = 0, lo = 0, hi = 0;
+};
+std::vector<OwnedArray> owned_arrays(const Compiled& c, uint32_t G, uint32_t W);
 
 }  // namespace rc

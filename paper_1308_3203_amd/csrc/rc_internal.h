@@ -68,7 +68,7 @@ enum : uint32_t { BIND_NONE = 0, BIND_SEEDED = 1, BIND_DEVICE = 2 };
 // (INTER scope): their accesses go to the global log.
 enum : uint32_t { LOG_NONE = 0, LOG_GLOBAL = 1, LOG_LDS = 2 };
 
-struct ArrayDesc {        // 48 bytes
+struct ArrayDesc {        // 64 bytes
   uint32_t kind;          // AK_*
   uint32_t size;          // cells
   uint32_t logged;        // LOG_NONE, LOG_GLOBAL or LOG_LDS (see below)
@@ -77,6 +77,11 @@ struct ArrayDesc {        // 48 bytes
   const int32_t* dptr;    // device binding
   uint32_t offset;        // LDS cell offset (local) or overlay cell offset (global rw)
   uint32_t cellbase;      // first cell key of this array in the log key space
+  // a global rw array whose cells each belong to one work-item (own_stride
+  // != 0): cell own_stride * tid + o sits at overlay word (o - own_lo) * W +
+  // lid of its group's region, which holds own_span * W words
+  int32_t own_stride, own_lo;
+  uint32_t own_span, pad;
 };
 
 struct ScalarDesc {

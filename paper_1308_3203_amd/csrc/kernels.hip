@@ -156,6 +156,49 @@ __global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* in, ui
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+// length of level `level` of a scan whose level-0 length is *m_ptr: each
+// level holds one sum per SCAN_BLOCK elements of the level below
+__device__ __forceinline__ uint64_t scan_level_len(const u64* m_ptr, uint32_t level) {
+  uint64_t m = *m_ptr;
+  for (uint32_t l = 0; l < level; ++l) m = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  return m;
+}
+
+// The same two steps when the length is known only on the device; a fixed
+// grid walks the level's blocks.
+__global__ __launch_bounds__(256) void scan_reduce_dev_kernel(const uint32_t* in, const u64* m_ptr,
+                                                              uint32_t level, uint32_t* sums) {
+  __shared__ uint32_t sh[4];
+  const uint64_t m = scan_level_len(m_ptr, level);
+  for (uint64_t j = blockIdx.x; j * SCAN_BLOCK < m; j += gridDim.x) {
+    const uint64_t base = j * SCAN_BLOCK + threadIdx.x * 4u;
+    uint32_t s = 0;
+    for (int k = 0; k < 4; ++k) if (base + k < m) s += in[base + k];
+    uint32_t total;
+    block_excl_scan_256(s, sh, &total);
+    if (threadIdx.x == 0) sums[j] = total;
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_block_dev_kernel(uint32_t* data, const u64* m_ptr, uint32_t level,
+                                                             const uint32_t* offs) {
+  __shared__ uint32_t sh[4];
+  const uint64_t m = scan_level_len(m_ptr, level);
+  for (uint64_t j = blockIdx.x; j * SCAN_BLOCK < m; j += gridDim.x) {
+    const uint64_t base = j * SCAN_BLOCK + threadIdx.x * 4u;
+    uint32_t v[4];
+    uint32_t s = 0;
+    for (int k = 0; k < 4; ++k) { v[k] = base + k < m ? data[base + k] : 0u; s += v[k]; }
+    uint32_t total;
+    uint32_t ex = block_excl_scan_256(s, sh, &total);
+    if (offs) ex += offs[j];
+    for (int k = 0; k < 4; ++k) {
+      if (base + k < m) data[base + k] = ex;
+      ex += v[k];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void scan_block_kernel(uint32_t* data, uint64_t m, const uint32_t* offs) {
   __shared__ uint32_t sh[4];
   const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * 4u;
@@ -226,6 +269,18 @@ __device__ __forceinline__ void rs_tile(const RsIn& in, uint32_t b, u64* start, 
   *count = t0 >= used ? 0u : (uint32_t)(used - t0 < RS_TILE ? used - t0 : RS_TILE);
 }
 
+// tiles of a pass: the dense entry count in tiles, or the regions' total
+__device__ __forceinline__ uint32_t rs_ntiles(const RsIn& in) {
+  if (in.seg_count == nullptr) return (uint32_t)((*in.n_ptr + RS_TILE - 1) / RS_TILE);
+  return in.tiles[in.n_regions];
+}
+
+// length of a pass's digit-major histogram, (2^dbits) x tiles, for the
+// device-sized scan
+__global__ void rs_hist_len_kernel(RsIn in, u64* m_out) {
+  *m_out = (u64)(1u << in.dbits) * rs_ntiles(in);
+}
+
 __global__ __launch_bounds__(256) void region_tiles_kernel(const uint32_t* counts, uint32_t* tiles, u64 n) {
   const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) tiles[r] = (counts[r] + RS_TILE - 1) / RS_TILE;
@@ -247,26 +302,32 @@ __device__ __forceinline__ void digit_peers(uint32_t d, bool valid, uint32_t dbi
 
 // Digit counts of one tile; one LDS atomic per distinct digit per wave
 // (sorted inputs make high digits nearly constant within a tile).
-__global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, uint32_t shift,
-                                                      uint32_t* hist, uint32_t nblocks) {
+// The histogram is digit-major over the pass's live tiles (the count read
+// on the device), so its scan and the grids scale with the entries, not
+// with the capacity; a fixed grid walks the tiles.
+__global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, uint32_t shift, uint32_t* hist) {
   __shared__ uint32_t h[256];
   const uint32_t t = threadIdx.x, lane = t & 63u;
   const uint32_t dmask = (1u << in.dbits) - 1u;
-  h[t] = 0;
-  __syncthreads();
-  u64 start;
-  uint32_t count;
-  rs_tile(in, blockIdx.x, &start, &count);
-  for (uint32_t i0 = 0; i0 < count; i0 += RS_THREADS) {
-    const uint32_t i = i0 + t;
-    const bool valid = i < count;
-    const uint32_t d = valid ? rs_digit(in, keys[start + i], shift, dmask) : 0u;
-    uint32_t rank, cnt;
-    digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
-    if (valid && rank == 0) atomicAdd(&h[d], cnt);
+  const uint32_t nt = rs_ntiles(in);
+  for (uint32_t b = blockIdx.x; b < nt; b += gridDim.x) {
+    h[t] = 0;
+    __syncthreads();
+    u64 start;
+    uint32_t count;
+    rs_tile(in, b, &start, &count);
+    for (uint32_t i0 = 0; i0 < count; i0 += RS_THREADS) {
+      const uint32_t i = i0 + t;
+      const bool valid = i < count;
+      const uint32_t d = valid ? rs_digit(in, keys[start + i], shift, dmask) : 0u;
+      uint32_t rank, cnt;
+      digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
+      if (valid && rank == 0) atomicAdd(&h[d], cnt);
+    }
+    __syncthreads();
+    if (t <= dmask) hist[(size_t)t * nt + b] = h[t];
+    __syncthreads();
   }
-  __syncthreads();
-  if (t <= dmask) hist[(size_t)t * nblocks + blockIdx.x] = h[t];
 }
 
 // Stable scatter of one tile: wave w owns the tile's w-th quarter (RS_ROUNDS
@@ -275,14 +336,14 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, 
 // wave then writes its entries in order.  Two block barriers per tile.
 template <typename V>
 __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
-                                                         RsIn in, uint32_t shift,
-                                                         const uint32_t* offs, uint32_t nblocks) {
+                                                         RsIn in, uint32_t shift, const uint32_t* offs) {
   __shared__ uint32_t woff[4][256];
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  const uint32_t nt = rs_ntiles(in);
+  for (uint32_t b = blockIdx.x; b < nt; b += gridDim.x) {
   u64 start;
   uint32_t count;
-  rs_tile(in, blockIdx.x, &start, &count);
-  if (count == 0) return;
+  rs_tile(in, b, &start, &count);
   const uint32_t dmask = (1u << in.dbits) - 1u;
   for (uint32_t ww = 0; ww < 4; ++ww) woff[ww][t] = 0u;
   __syncthreads();
@@ -302,7 +363,7 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
   }
   __syncthreads();
   if (t <= dmask) {
-    uint32_t o = offs[(size_t)t * nblocks + blockIdx.x];
+    uint32_t o = offs[(size_t)t * nt + b];
     for (uint32_t ww = 0; ww < 4; ++ww) {
       const uint32_t c = woff[ww][t];
       woff[ww][t] = o;
@@ -325,6 +386,8 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
       // of this round is complete before any lane advances the counter
       if (rank == 0) woff[w][d] = base + cnt;
     }
+  }
+  __syncthreads();   // woff is reset for the next tile
   }
 }
 
@@ -957,10 +1020,31 @@ static void scan_excl(uint32_t* data, u64 m, uint32_t* tmp, hipStream_t st) {
   hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, st, data, m, (const uint32_t*)sums);
 }
 
+// The same scan when the level-0 length is on the device (*m_ptr <= max_m).
+static void scan_excl_dev(uint32_t* data, const u64* m_ptr, uint32_t level, u64 max_m, uint32_t* tmp,
+                          hipStream_t st) {
+  if (max_m <= SCAN_BLOCK) {
+    hipLaunchKernelGGL(scan_block_dev_kernel, dim3(1), dim3(256), 0, st, data, m_ptr, level,
+                       (const uint32_t*)nullptr);
+    return;
+  }
+  const u64 nb = (max_m + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  const uint32_t grid = (uint32_t)std::min<u64>(nb, 2048);
+  uint32_t* sums = tmp;
+  hipLaunchKernelGGL(scan_reduce_dev_kernel, dim3(grid), dim3(256), 0, st, (const uint32_t*)data, m_ptr, level, sums);
+  scan_excl_dev(sums, m_ptr, level + 1, nb, tmp + nb, st);
+  hipLaunchKernelGGL(scan_block_dev_kernel, dim3(grid), dim3(256), 0, st, data, m_ptr, level, (const uint32_t*)sums);
+}
+
+// grid of the tile-walking sort kernels
+static uint32_t rs_grid(u64 max_tiles) { return (uint32_t)std::max<u64>(1, std::min<u64>(max_tiles, 4096)); }
+
+// hist region of a sort: the device-side histogram length (2 words), the
+// histogram (256 x tiles) and the scan's partial sums
 size_t sort_hist_words(u64 cap) {
   const u64 nb = (cap + RS_TILE - 1) / RS_TILE;
   const u64 m = 256ull * (nb ? nb : 1);
-  return m + scan_tmp_words(m);
+  return 2 + m + scan_tmp_words(m);
 }
 
 // upper bound of the tiles the first (segmented) pass walks
@@ -969,34 +1053,38 @@ static u64 seg_blocks(u64 n_regions, u64 cap) { return (cap + RS_TILE - 1) / RS_
 size_t sort_log_hist_words(u64 n_regions, u64 cap) {
   const u64 nb = std::max<u64>(seg_blocks(n_regions, cap), (cap + RS_TILE - 1) / RS_TILE);
   const u64 m = 256ull * (nb ? nb : 1);
-  return m + scan_tmp_words(std::max<u64>(m, n_regions + 1));
+  return 2 + m + scan_tmp_words(std::max<u64>(m, n_regions + 1));
 }
 
 // Second owner pass over the log regions: the interpreter stored, for every
 // logged access, its work-item id into the cell's owner word (one of the
 // stores survives).  An entry whose id differs from the stored one marks the
 // cell shared; a cell touched by a single work-item keeps its id.
-__global__ __launch_bounds__(256) void mark_shared_kernel(const u64* keys, const u64* vals, RsIn in,
-                                                          uint32_t* owner) {
-  u64 start;
-  uint32_t count;
-  rs_tile(in, blockIdx.x, &start, &count);
+__global__ __launch_bounds__(256) void mark_shared_kernel(const u64* keys, const u64* vals, RsIn in) {
   const u64 cmask = in.keep_bc >= 32 ? 0xFFFFFFFFull : ((1ull << in.keep_bc) - 1ull);
   const uint32_t gmask = in.keep_low > in.keep_bk ? ((1u << (in.keep_low - in.keep_bk)) - 1u) : 0u;
-  for (uint32_t i = threadIdx.x; i < count; i += RS_THREADS) {
-    const u64 k = keys[start + i];
-    const u64 cell = (k >> in.keep_low) & cmask;
-    const u64 slot = k >> (in.keep_low + in.keep_bc);
-    const uint32_t id = ((((uint32_t)(k >> in.keep_bk)) & gmask) << 10) | ((uint32_t)vals[start + i] & 1023u);
-    uint32_t* w = (uint32_t*)&in.keep[slot * in.keep_stride + cell];
-    if (*w != id) *w = OWNER_SHARED;
+  const uint32_t nt = rs_ntiles(in);
+  for (uint32_t b = blockIdx.x; b < nt; b += gridDim.x) {
+    u64 start;
+    uint32_t count;
+    rs_tile(in, b, &start, &count);
+    for (uint32_t i = threadIdx.x; i < count; i += RS_THREADS) {
+      const u64 k = keys[start + i];
+      const u64 cell = (k >> in.keep_low) & cmask;
+      const u64 slot = k >> (in.keep_low + in.keep_bc);
+      const uint32_t id = ((((uint32_t)(k >> in.keep_bk)) & gmask) << 10) | ((uint32_t)vals[start + i] & 1023u);
+      uint32_t* w = (uint32_t*)&in.keep[slot * in.keep_stride + cell];
+      if (*w != id) *w = OWNER_SHARED;
+    }
   }
-  (void)owner;
 }
 
 // after a filter pass: the exclusive digit-major scan holds the number of
 // kept (digit 0) entries at the first digit-1 slot
-__global__ void kept_count_kernel(const uint32_t* hist, uint32_t nblocks, u64* n_ptr) { *n_ptr = hist[nblocks]; }
+__global__ void kept_count_kernel(const uint32_t* hist, RsIn in, u64* n_ptr) {
+  const uint32_t nt = rs_ntiles(in);
+  *n_ptr = nt ? hist[nt] : 0ull;
+}
 
 template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
@@ -1007,6 +1095,10 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
   V *va = v0, *vb = v1;
   int passes = 0;
   if (dbits < 1 || dbits > 8) dbits = 8;
+  // the histogram's live length (written on the device each pass), then the
+  // histogram and the scan's partial sums
+  u64* mlen = reinterpret_cast<u64*>(hist);
+  uint32_t* hst = hist + 2;
   if (filter && seg_count) {
     // stable partition of the regions: entries of cells touched at least
     // twice first, in region order; the rest is dropped
@@ -1017,15 +1109,16 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
     in.seg_base = seg_base;
     in.tiles = tiles;
     in.n_regions = (uint32_t)n_regions;
-    const uint32_t nb = (uint32_t)std::max<u64>(1, seg_blocks(n_regions, cap));
-    uint32_t* tmp = hist + 2ull * nb;
-    hipLaunchKernelGGL(mark_shared_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const u64*)va, in,
-                       (uint32_t*)in.keep);
-    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, in, 0u, hist, nb);
-    scan_excl(hist, 2ull * nb, tmp, st);
-    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
-                       vb, in, 0u, (const uint32_t*)hist, nb);
-    hipLaunchKernelGGL(kept_count_kernel, dim3(1), dim3(1), 0, st, (const uint32_t*)hist, nb, (u64*)n_ptr);
+    const u64 nb = std::max<u64>(1, seg_blocks(n_regions, cap));
+    const uint32_t grid = rs_grid(nb);
+    uint32_t* tmp = hst + 2ull * nb;
+    hipLaunchKernelGGL(mark_shared_kernel, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, (const u64*)va, in);
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, in, 0u, hst);
+    hipLaunchKernelGGL(rs_hist_len_kernel, dim3(1), dim3(1), 0, st, in, mlen);
+    scan_excl_dev(hst, mlen, 0, 2ull * nb, tmp, st);
+    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
+                       vb, in, 0u, (const uint32_t*)hst);
+    hipLaunchKernelGGL(kept_count_kernel, dim3(1), dim3(1), 0, st, (const uint32_t*)hst, in, (u64*)n_ptr);
     u64* tk = ka; ka = kb; kb = tk;
     V* tv = va; va = vb; vb = tv;
     ++passes;
@@ -1049,13 +1142,15 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
     } else {
       nbl = blocks_for(cap ? cap : 1, RS_TILE);
     }
-    const uint32_t nb = (uint32_t)(nbl ? nbl : 1);
+    const u64 nb = nbl ? nbl : 1;
+    const uint32_t grid = rs_grid(nb);
     const u64 m = (1ull << dbits) * nb;
-    uint32_t* tmp = hist + m;
-    hipLaunchKernelGGL(rs_hist_kernel, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, in, shift, hist, nb);
-    scan_excl(hist, m, tmp, st);
-    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(nb), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
-                       vb, in, shift, (const uint32_t*)hist, nb);
+    uint32_t* tmp = hst + m;
+    hipLaunchKernelGGL(rs_hist_kernel, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, in, shift, hst);
+    hipLaunchKernelGGL(rs_hist_len_kernel, dim3(1), dim3(1), 0, st, in, mlen);
+    scan_excl_dev(hst, mlen, 0, m, tmp, st);
+    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
+                       vb, in, shift, (const uint32_t*)hst);
     u64* tk = ka; ka = kb; kb = tk;
     V* tv = va; va = vb; vb = tv;
     ++passes;

@@ -303,11 +303,217 @@ class Prover {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Second proof, by enumeration: when no index and no branch depends on a
+// loaded value or a scalar parameter, every work-item's accesses are the
+// same for every input.  Each work-item's register values are then computed
+// on the host (its own path through the program: its registers do not depend
+// on other work-items), and the cells each touches are compared.  A faulting
+// statement stops a group; the enumeration keeps going past it, which only
+// adds accesses, so an array it finds unshared is unshared.
+// ---------------------------------------------------------------------------
+constexpr uint64_t ENUM_STEPS_MAX = 60000000;   // instructions interpreted on the host
+
+struct Val {
+  bool known;
+  int32_t v;
+};
+
+// the language's int32 operators (wrapping; division by zero is a fault)
+bool host_alu(uint32_t op, int32_t x, int32_t y, int32_t* r) {
+  const uint32_t ux = (uint32_t)x, uy = (uint32_t)y;
+  switch (op) {
+    case B_ADD: *r = (int32_t)(ux + uy); return true;
+    case B_SUB: *r = (int32_t)(ux - uy); return true;
+    case B_MUL: *r = (int32_t)(ux * uy); return true;
+    case B_DIV:
+      if (y == 0) return false;
+      *r = y == -1 ? (int32_t)(0u - ux) : x / y;
+      return true;
+    case B_REM:
+      if (y == 0) return false;
+      *r = y == -1 ? 0 : x % y;
+      return true;
+    case B_MOD: {
+      if (y == 0) return false;
+      if (y == -1 || y == 1) { *r = 0; return true; }
+      int32_t m = x % y;
+      if (m < 0) m = (int32_t)((uint32_t)m + (y < 0 ? 0u - uy : uy));
+      *r = m;
+      return true;
+    }
+    case B_AND: *r = x & y; return true;
+    case B_OR: *r = x | y; return true;
+    case B_XOR: *r = x ^ y; return true;
+    case B_SHL: *r = (int32_t)(ux << (uy & 31u)); return true;
+    case B_SHR: *r = x >> (int32_t)(uy & 31u); return true;
+    case B_LT: *r = x < y; return true;
+    case B_LE: *r = x <= y; return true;
+    case B_GT: *r = x > y; return true;
+    case B_GE: *r = x >= y; return true;
+    case B_EQ: *r = x == y; return true;
+    case B_NE: *r = x != y; return true;
+    case B_LAND: *r = (x != 0) & (y != 0); return true;
+    case B_LOR: *r = (x != 0) | (y != 0); return true;
+    case B_MIN: *r = x < y ? x : y; return true;
+    default: *r = x > y ? x : y; return true;   // B_MAX
+  }
+}
+
+class Enumerator {
+ public:
+  Enumerator(const Compiled& c, uint32_t G, uint32_t W, std::vector<uint8_t> cand)
+      : c_(c), G_(G), W_(W), cand_(std::move(cand)) {}
+
+  // owned[a] for the candidate arrays (others 0); all 0 when the program's
+  // accesses depend on its inputs or the enumeration is too long
+  std::vector<uint8_t> run() {
+    const uint32_t na = (uint32_t)c_.arrays.size();
+    std::vector<uint8_t> none(na, 0);
+    if ((double)G_ * W_ * (double)c_.dyn_instr > (double)ENUM_STEPS_MAX) return none;
+    owner_.assign(na, std::vector<int64_t>());
+    for (uint32_t a = 0; a < na; ++a)
+      if (cand_[a]) owner_[a].assign(c_.arrays[a].size, -1);
+    for (uint32_t g = 0; g < G_; ++g) {
+      for (uint32_t a = 0; a < na; ++a)   // each group has its own local arrays
+        if (cand_[a] && !c_.arrays[a].global) std::fill(owner_[a].begin(), owner_[a].end(), -1);
+      for (uint32_t l = 0; l < W_; ++l) {
+        if (!item(g, l)) return none;
+        bool any = false;
+        for (uint32_t a = 0; a < na; ++a) any = any || cand_[a];
+        if (!any) return none;
+      }
+    }
+    return cand_;
+  }
+
+ private:
+  const Compiled& c_;
+  const uint32_t G_, W_;
+  std::vector<uint8_t> cand_;
+  std::vector<std::vector<int64_t>> owner_;   // per candidate array: touching work-item, or -1
+  uint64_t steps_ = 0;
+
+  uint32_t word(uint32_t i, int k) const { return c_.code[4 * i + k]; }
+
+  Val operand(bool imm, uint32_t w, const Val* regs, uint32_t g, uint32_t l) const {
+    if (imm) return Val{true, (int32_t)w};
+    if (w < MAX_REGS) return regs[w];
+    switch (w) {
+      case SEL_LID: return Val{true, (int32_t)l};
+      case SEL_GID: return Val{true, (int32_t)g};
+      case SEL_TID: return Val{true, (int32_t)(g * W_ + l)};
+      case SEL_WGSIZE: return Val{true, (int32_t)W_};
+      case SEL_NGROUPS: return Val{true, (int32_t)G_};
+      case SEL_NTHREADS: return Val{true, (int32_t)(G_ * W_)};
+      default: return Val{false, 0};   // scalar parameters differ between inputs
+    }
+  }
+
+  void touch(uint32_t a, Val idx, int64_t t) {
+    if (!cand_[a]) return;
+    if (!idx.known) { cand_[a] = 0; return; }
+    if (idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) return;   // faults: no access
+    int64_t& o = owner_[a][(uint32_t)idx.v];
+    if (o == -1) o = t;
+    else if (o != t) cand_[a] = 0;
+  }
+
+  // one work-item's path; false: the path depends on the inputs, or too long
+  bool item(uint32_t g, uint32_t l) {
+    Val regs[MAX_REGS];
+    for (Val& r : regs) r = Val{true, 0};
+    uint32_t lc[MAX_NEST + 1] = {};
+    const int64_t t = (int64_t)g * W_ + l;
+    const uint32_t n = (uint32_t)(c_.code.size() / 4);
+    uint32_t pc = 0;
+    while (pc < n) {
+      if (++steps_ > ENUM_STEPS_MAX) return false;
+      const uint32_t h = word(pc, 0), op = h & 63u, sub = (h >> 8) & 63u, dst = (h >> 14) & 63u;
+      const bool fa = (h >> 6) & 1u, fb = (h >> 7) & 1u;
+      switch (op) {
+        case OP_BIN: {
+          const Val x = operand(fa, word(pc, 1), regs, g, l), y = operand(fb, word(pc, 2), regs, g, l);
+          int32_t r = 0;
+          regs[dst] = x.known && y.known && host_alu(sub, x.v, y.v, &r) ? Val{true, r} : Val{false, 0};
+          ++pc;
+          break;
+        }
+        case OP_UN: {
+          const Val x = operand(fa, word(pc, 1), regs, g, l);
+          if (!x.known) regs[dst] = x;
+          else if (sub == U_MOV) regs[dst] = x;
+          else if (sub == U_NEG) regs[dst] = Val{true, (int32_t)(0u - (uint32_t)x.v)};
+          else if (sub == U_BNOT) regs[dst] = Val{true, ~x.v};
+          else regs[dst] = Val{true, x.v == 0 ? 1 : 0};
+          ++pc;
+          break;
+        }
+        case OP_LOAD:
+          touch(word(pc, 3), operand(fa, word(pc, 1), regs, g, l), t);
+          regs[dst] = Val{false, 0};
+          ++pc;
+          break;
+        case OP_STORE:
+          touch(word(pc, 3), operand(fa, word(pc, 1), regs, g, l), t);
+          ++pc;
+          break;
+        case OP_IF: {
+          const Val cnd = operand(fa, word(pc, 1), regs, g, l);
+          if (!cnd.known) return false;   // a data-dependent path
+          pc = cnd.v != 0 ? pc + 1 : word(pc, 2) + 1;
+          break;
+        }
+        case OP_ELSE:   // end of the taken then-branch
+          pc = word(pc, 3) + 1;
+          break;
+        case OP_FOR: {
+          const int32_t lo = (int32_t)word(pc, 1), hi = (int32_t)word(pc, 2);
+          regs[dst] = Val{true, lo};
+          if ((int64_t)hi - (int64_t)lo <= 0) {
+            pc = word(pc, 3);
+          } else {
+            lc[sub] = 0;
+            ++pc;
+          }
+          break;
+        }
+        case OP_ENDFOR: {
+          const int32_t lo = (int32_t)word(pc, 1), hi = (int32_t)word(pc, 2);
+          const uint32_t iters = (uint32_t)((int64_t)hi - (int64_t)lo);
+          lc[sub] += 1;
+          regs[dst] = Val{true, (int32_t)((uint32_t)lo + lc[sub])};
+          pc = lc[sub] < iters ? word(pc, 3) : pc + 1;
+          break;
+        }
+        case OP_END:
+          return true;
+        default:   // endif, barrier, assert, assume
+          ++pc;
+          break;
+      }
+    }
+    return true;
+  }
+};
+
 }  // namespace
 
 std::vector<OwnedArray> owned_arrays(const Compiled& c, uint32_t G, uint32_t W) {
   Prover p(c, G, W);
-  return p.run();
+  std::vector<OwnedArray> out = p.run();
+  // the enumeration settles written arrays the affine proof left open
+  std::vector<uint8_t> cand(out.size(), 0);
+  bool any = false;
+  for (size_t a = 0; a < out.size(); ++a) {
+    cand[a] = !out[a].owned && c.arrays[a].written;
+    any = any || cand[a];
+  }
+  if (!any) return out;
+  const std::vector<uint8_t> e = Enumerator(c, G, W, cand).run();
+  for (size_t a = 0; a < out.size(); ++a)
+    if (e[a]) out[a].owned = 1;   // owned, kept in the plain layout
+  return out;
 }
 
 }  // namespace rc

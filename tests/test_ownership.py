@@ -1,10 +1,13 @@
-"""The owned-array proof (host logic of the library, no device).
+"""The owned-array proofs (host logic of the library, no device).
 
 An array is owned when no two work-items can touch a common cell of it; the
-library then skips logging its accesses.  Hand cases pin what the proof
-accepts and rejects, including int32 wrap-around, loop-carried variables and
-branch joins; a randomised check against the oracle (which logs every access)
-confirms that no owned array ever carries a record."""
+library then skips logging its accesses.  Two proofs: affine index forms
+(which also give the lane-major overlay placement), and, when no index or
+branch depends on loaded values or scalars, enumeration of every work-item's
+cells.  Hand cases pin what they accept and reject, including int32
+wrap-around, loop-carried variables and branch joins; a randomised check
+against the oracle (which logs every access) confirms that no owned array
+ever carries a record."""
 import random
 
 import pytest
@@ -29,7 +32,8 @@ CASES = [
     ("  x[lid] := 1;", 1, 64, [True, True]),
     ("  x[gid] := 1;", 8, 1, [True, True]),
     ("  x[gid * wgsize + lid] := 1;", 8, 32, [True, True]),
-    ("  x[gid * 64 + lid] := 1;", 8, 32, [False, True]),
+    ("  x[gid * 64 + lid] := 1;", 8, 32, [True, True]),      # not affine in tid; enumerated
+    ("  x[gid * 16 + lid] := 1;", 8, 32, [False, True]),
     ("  x[1000 - tid] := 1;", 4, 64, [True, True]),
     ("  x[tid << 2] := 1;\n  x[(tid << 2) + 3] := 1;", 4, 64, [True, True]),
     ("  for k in 0..4 {\n    x[tid * 4 + k] := k;\n  }", 4, 64, [True, True]),
@@ -48,7 +52,11 @@ CASES = [
      [True, True]),
     # 4 * 2^30 wraps to 0 in int32: work-items 0 and 4 share cell 0
     ("  x[tid * 1073741824] := 1;", 1, 8, [False, True]),
-    ("  x[tid mod 64] := 1;", 1, 64, [False, True]),
+    ("  x[tid mod 64] := 1;", 1, 64, [True, True]),
+    ("  x[tid mod 32] := 1;", 1, 64, [False, True]),
+    ("  if (lid == 0) {\n    x[gid] := 1;\n  }", 8, 64, [True, True]),
+    ("  if (lid < 2) {\n    x[gid] := 1;\n  }", 8, 64, [False, True]),
+    ("  x[(lid / 8) * 64 + (lid % 8) + gid * 8] := 1;", 8, 64, [True, True]),
     ("  v := y[tid];\n  x[v] := 1;", 4, 64, [False, True]),
     ("  v := x[0];\n  x[tid] := v;", 4, 64, [False, True]),
     ("  x[tid] := 1;\n  barrier;\n  v := x[tid];\n  y[tid] := v;", 4, 64, [True, True]),
@@ -58,6 +66,15 @@ CASES = [
 @pytest.mark.parametrize("body,G,W,expect", CASES)
 def test_owned_cases(body, G, W, expect):
     assert owned(body, G, W) == expect
+
+
+def test_data_dependent_paths_are_not_enumerated():
+    # a branch on a loaded value: the accessed cells depend on the inputs
+    body = "  v := y[tid];\n  if (v < 3) {\n    x[tid] := 1;\n  } else {\n    x[tid + 1] := 1;\n  }"
+    assert owned(body, 2, 32) == [False, True]
+    # the affine proof is path-insensitive and still owns x when both paths agree
+    body = "  v := y[tid];\n  if (v < 3) {\n    x[tid] := 1;\n  } else {\n    x[tid] := 2;\n  }"
+    assert owned(body, 2, 32) == [True, True]
 
 
 def test_scalar_in_index_is_unknown():
@@ -75,9 +92,8 @@ def test_local_arrays():
     src = ("kernel t(global int x[4096]) {\n  local int l[256];\n  int v;\n  l[lid] := 1;\n  barrier;\n"
            "  v := l[lid];\n  x[tid] := v;\n}\n")
     assert B.owned_arrays(src, 1, 64) == [True, True]
-    # with several groups the proof asks for distinct cells across the whole
-    # NDRange, which a per-group local array indexed by lid does not meet
-    assert B.owned_arrays(src, 4, 64) == [True, False]
+    # each group has its own copy of a local array
+    assert B.owned_arrays(src, 4, 64) == [True, True]
     src2 = src.replace("v := l[lid];", "v := l[lid + 1];")
     assert B.owned_arrays(src2, 1, 64) == [True, False]
 
@@ -87,8 +103,11 @@ def test_c2_templates():
     # prefix sum: each work-item scans its own 16 cells of inp and out
     assert got["prefix_sum"] == [True, True, False]
     assert got["prefix_sum_race"] == [True, True, False]
-    assert got["tree_reduce"][1] is False          # out[gid] by lid 0: not provable
-    assert got["transpose"][1] is False            # div / mod in the index
+    # out[gid] written by lid 0 only, and the transpose's div / mod index:
+    # neither is affine in tid; both are enumerated
+    assert got["tree_reduce"][1:] == [True, False]
+    assert got["transpose"][1:] == [True, False]
+    assert got["transpose_race"][1:] == [True, False]
 
 
 def test_errors():

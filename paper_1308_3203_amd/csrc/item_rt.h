@@ -528,6 +528,51 @@ struct Item {
     if (k < my_fault) my_fault = k;
   }
 
+  // The record of a table cell, if its accesses form one (labels and pairs
+  // only; the caller adds the location).
+  __device__ __forceinline__ static bool tab_finish(const TabCell c, PendingRec* pr) {
+    if (c.wmin == ~0ull && c.r1 == NONE32) return false;
+    const uint32_t w1 = c.wmin == ~0ull ? NONE32 : (uint32_t)(c.wmin >> 32);
+    const bool multi1 = c.q != NONE32 && c.q == w1;
+    const Pass1 p1 = {c.r1, c.wmin};
+    const Intra2 p2 = {c.r2, c.w2, multi1 ? NONE32 : c.q, multi1 ? 1u : 0u};
+    return intra_finish(p1, p2, &pr->label, &pr->rw, &pr->ww);
+  }
+
+  // One atomic for the whole group: `n` slots for this thread, returned as
+  // the first of them (threads in order).  Every thread of the block calls it.
+  // (n <= 64: a thread finishes at most 4096 / 64 cells; the wave's scan
+  // is taken bit-plane by bit-plane with ballots)
+  __device__ __forceinline__ u64 group_reserve(unsigned long long* counter, uint32_t n) {
+    const u64 below = (1ull << lane) - 1ull;
+    uint32_t x = 0, wsum = 0;   // exclusive prefix in the wave, wave total
+#pragma unroll
+    for (uint32_t b = 0; b < 7; ++b) {
+      const u64 m = __ballot((n >> b) & 1u);
+      x += (uint32_t)__popcll(m & below) << b;
+      wsum += (uint32_t)__popcll(m) << b;
+    }
+    x += n;   // inclusive
+    if (lane == 0) ctl->rec_sum[wave] = wsum;
+    __syncthreads();
+    const uint32_t nw = nthr >> 6;
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < nw; ++w) {
+      const uint32_t v = ctl->rec_sum[w];
+      total += v;
+      if (w < wave) before += v;
+    }
+    if (tl == 0) {
+      ctl->rec_sum_total = total;
+      ctl->rec_base = total ? __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, counter),
+                                                     (unsigned long long)total, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                            : 0ull;
+    }
+    __syncthreads();
+    return ctl->rec_base + before + x - n;
+  }
+
   // Close the current interval on the LDS path: check its log in LDS (by a
   // per-cell table, or by a bitonic sort and runs) and stage the records of
   // the INTRA scope.  Callers have passed a barrier since the interval's last
@@ -567,37 +612,40 @@ struct Item {
       }
     }
     __syncthreads();
-    for (uint32_t b0 = 0; b0 < P.tab_cells; b0 += nthr) {
-      const uint32_t t = b0 + tl;
-      bool has = false;
+    // Each thread finishes cells tl, tl + nthr, ...: a first pass counts its
+    // records, the group reserves them with one atomic, a second pass stores
+    // them and clears the cells for the next interval.
+    // Cells without a record are cleared in the first pass; the second runs
+    // only when the group has records.
+    uint32_t mine = 0;
+    for (uint32_t t = tl; t < P.tab_cells; t += nthr) {
+      const TabCell c = tab[t];
+      if (c.wmin == ~0ull && c.r1 == NONE32) continue;
       PendingRec pr;
-      if (t < P.tab_cells) {
-        const TabCell c = tab[t];
-        if (c.wmin != ~0ull || c.r1 != NONE32) {
-          tab[t] = empty_tab_cell();
-          const uint32_t w1 = c.wmin == ~0ull ? NONE32 : (uint32_t)(c.wmin >> 32);
-          const bool multi1 = c.q != NONE32 && c.q == w1;
-          const Pass1 p1 = {c.r1, c.wmin};
-          const Intra2 p2 = {c.r2, c.w2, multi1 ? NONE32 : c.q, multi1 ? 1u : 0u};
-          has = intra_finish(p1, p2, &pr.label, &pr.rw, &pr.ww);
-          if (has) {
-            const uint32_t ck = P.tab_base + t;
-            uint32_t aid = 0;
-            for (uint32_t a = 0; a < P.n_arrays; ++a) {
-              const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
-              if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
-            }
-            const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
-            pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
-            pr.cellkey = ck; pr.lidbase = gid * P.W;
-          }
-        }
+      if (tab_finish(c, &pr)) ++mine;
+      else tab[t] = empty_tab_cell();
+    }
+    u64 at = group_reserve(R.rec_count, mine);
+    if (ctl->rec_sum_total == 0u) {
+      __syncthreads();
+      return;
+    }
+    for (uint32_t t = tl; t < P.tab_cells; t += nthr) {
+      const TabCell c = tab[t];
+      if (c.wmin == ~0ull && c.r1 == NONE32) continue;
+      tab[t] = empty_tab_cell();
+      PendingRec pr;
+      if (!tab_finish(c, &pr)) continue;
+      const uint32_t ck = P.tab_base + t;
+      uint32_t aid = 0;
+      for (uint32_t a = 0; a < P.n_arrays; ++a) {
+        const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
+        if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
       }
-      const u64 m = __ballot(has);
-      if (m != 0ull) {
-        const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
-        if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, instance, pr, false);
-      }
+      const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
+      pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
+      pr.cellkey = ck; pr.lidbase = gid * P.W;
+      store_record(R, K, at++, slot, instance, pr, false);
     }
     __syncthreads();
     return;

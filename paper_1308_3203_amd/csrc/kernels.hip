@@ -800,8 +800,10 @@ __global__ __launch_bounds__(256) void seg_long_kernel(SegParams S) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
   const u64 n = *Gp.n_ptr;
-  const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
+  // a fixed grid walks the staged records (their count is on the device)
+  for (u64 base = (u64)blockIdx.x * 256u; base < n; base += (u64)gridDim.x * 256u) {
+  const u64 p = base + threadIdx.x;
   bool valid = p < n;
   uint32_t slot = 0;
   bool race = false, benign = false;
@@ -827,6 +829,7 @@ __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
   } else if (valid) {
     if (race) atomicAdd(&Gp.inst_race[slot], 1u);
     if (benign) atomicAdd(&Gp.inst_benign[slot], 1u);
+  }
   }
 }
 
@@ -1195,7 +1198,8 @@ hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_gather(const GatherParams& G, u64 cap, hipStream_t st) {
-  hipLaunchKernelGGL(rec_gather_kernel, dim3(blocks_for(cap ? cap : 1, 256)), dim3(256), 0, st, G);
+  hipLaunchKernelGGL(rec_gather_kernel, dim3((uint32_t)std::min<u64>(blocks_for(cap ? cap : 1, 256), 8192)),
+                     dim3(256), 0, st, G);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const FinalParams& F, hipStream_t st) {

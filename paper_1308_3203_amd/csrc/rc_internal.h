@@ -182,7 +182,10 @@ struct rc_record_out {
 // LDS control block of the interpreter (after the local cells and registers)
 struct Ctl {
   unsigned long long fault;             // min fault key of the group (~0 = none)
+  unsigned long long rec_base;          // the group's record reservation
   uint32_t red[2][MAX_WAVES];           // per-wave reduction words, double-buffered
+  uint32_t rec_sum[MAX_WAVES];          // per-wave record counts of a reservation
+  uint32_t rec_sum_total, pad2;         // and their sum
   int32_t scal[MAX_SCALARS];
   uint32_t loopctr[MAX_WAVES][MAX_NEST];
   uint32_t item;                        // work item taken by the group

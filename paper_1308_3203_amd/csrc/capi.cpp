@@ -439,8 +439,14 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     L.nbits_log = L.bi + bc + bg + bk;
     L.nbits_rec = L.bi + bs + bc;
     L.cc_stride = std::max<uint32_t>(1, max_cells);
-    // a count word costs less than one entry's log and sort traffic
-    L.filter = L.max_log >= 4096 && (u64)L.max_slots * L.cc_stride <= 4 * L.max_log && bg <= 21;
+    // The owner filter drops the entries of cells one work-item touched,
+    // for the price of an owner word per access and one partition pass.  It
+    // pays when accesses are sparse over the cells: at more than one logged
+    // access per cell (static bound) most cells are shared and the pass
+    // would move nearly everything; the owner table must stay within four
+    // words per log entry.
+    const u64 owner_words = (u64)L.max_slots * L.cc_stride;
+    L.filter = L.max_log >= 4096 && owner_words >= L.max_log && owner_words <= 4 * L.max_log && bg <= 21;
     if (L.nbits_log > 64 || L.nbits_rec > 64) { *why = "sort key wider than 64 bits"; return false; }
     Layout lim = L;
     partition(C, lim);

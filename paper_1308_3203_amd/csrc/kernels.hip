@@ -391,6 +391,94 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
   }
 }
 
+// The same scatter staged through LDS: wave w owns the tile's w-th
+// quarter (RS_ROUNDS rounds of 64 consecutive entries, kept in registers).
+// Each wave counts its digits; one pass turns the counts into the tile's
+// digit order (a local, stable counting sort into LDS); the block then
+// writes the tile out in that order, so consecutive threads write
+// consecutive addresses of one digit's run.  Dynamic LDS: RS_TILE keys,
+// values and digits.
+template <typename V>
+__global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
+                                                             RsIn in, uint32_t shift, const uint32_t* offs) {
+  __shared__ uint32_t woff[4][256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t sh[4];
+  u64* lkey = reinterpret_cast<u64*>(rc_smem);
+  V* lval = reinterpret_cast<V*>(lkey + RS_TILE);
+  uint8_t* ldig = reinterpret_cast<uint8_t*>(lval + RS_TILE);
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  const uint32_t nt = rs_ntiles(in);
+  const uint32_t dmask = (1u << in.dbits) - 1u;
+  for (uint32_t b = blockIdx.x; b < nt; b += gridDim.x) {
+    u64 start;
+    uint32_t count;
+    rs_tile(in, b, &start, &count);
+    for (uint32_t ww = 0; ww < 4; ++ww) woff[ww][t] = 0u;
+    __syncthreads();
+    const uint32_t wbeg = w * (RS_TILE / 4);
+    u64 kr[RS_ROUNDS];
+    V vr[RS_ROUNDS];
+    uint32_t dr[RS_ROUNDS];
+#pragma unroll
+    for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+      const uint32_t i = wbeg + r * 64u + lane;
+      const bool valid = i < count;
+      kr[r] = valid ? kin[start + i] : 0ull;
+      vr[r] = valid ? vin[start + i] : (V)0;
+      dr[r] = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
+      uint32_t rank, cnt;
+      digit_peers(dr[r], valid, in.dbits, lane, &rank, &cnt);
+      if (valid && rank == 0) woff[w][dr[r]] += cnt;   // one lane per digit: no conflict in the wave
+    }
+    __syncthreads();
+    // tile-local start of each digit (scan over the digits), then each
+    // wave's start within it; gbase maps a local position to the output
+    {
+      const uint32_t c = t <= dmask ? woff[0][t] + woff[1][t] + woff[2][t] + woff[3][t] : 0u;
+      uint32_t total;
+      const uint32_t lstart = block_excl_scan_256(c, sh, &total);
+      if (t <= dmask) {
+        gbase[t] = offs[(size_t)t * nt + b] - lstart;
+        uint32_t o = lstart;
+        for (uint32_t ww = 0; ww < 4; ++ww) {
+          const uint32_t n = woff[ww][t];
+          woff[ww][t] = o;
+          o += n;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+      const uint32_t i = wbeg + r * 64u + lane;
+      const bool valid = i < count;
+      uint32_t rank, cnt;
+      digit_peers(dr[r], valid, in.dbits, lane, &rank, &cnt);
+      if (valid) {
+        const uint32_t base = woff[w][dr[r]];
+        lkey[base + rank] = kr[r];
+        lval[base + rank] = vr[r];
+        ldig[base + rank] = (uint8_t)dr[r];
+        // the new offset depends on the value just read, so the wave's read
+        // of this round is complete before any lane advances the counter
+        if (rank == 0) woff[w][dr[r]] = base + cnt;
+      }
+    }
+    __syncthreads();
+    for (uint32_t p = t; p < count; p += RS_THREADS) {
+      const uint32_t o = gbase[ldig[p]] + p;
+      kout[o] = lkey[p];
+      vout[o] = lval[p];
+    }
+    __syncthreads();   // the LDS tile and woff are reused for the next tile
+  }
+}
+
+// dynamic LDS of the scatter: keys, values and digits of one tile
+template <typename V>
+constexpr size_t rs_scatter_lds() { return (size_t)RS_TILE * (sizeof(u64) + sizeof(V) + 1); }
+
 __global__ __launch_bounds__(256) void sum_u32_kernel(const uint32_t* v, u64 n, u64* out) {
   u64 s = 0;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) s += v[i];
@@ -1093,7 +1181,8 @@ template <typename V>
 static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_ptr, u64 cap, uint32_t nbits,
                                   const uint32_t* seg_count, const u64* seg_base, const uint32_t* tiles,
                                   u64 n_regions, uint32_t* hist, uint32_t dbits, hipStream_t st,
-                                  int* result_in_second, uint32_t start_bit = 0, const RsIn* filter = nullptr) {
+                                  int* result_in_second, uint32_t start_bit = 0, const RsIn* filter = nullptr,
+                                  bool lds_scatter = false) {
   u64 *ka = k0, *kb = k1;
   V *va = v0, *vb = v1;
   int passes = 0;
@@ -1152,8 +1241,17 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
     hipLaunchKernelGGL(rs_hist_kernel, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, in, shift, hst);
     hipLaunchKernelGGL(rs_hist_len_kernel, dim3(1), dim3(1), 0, st, in, mlen);
     scan_excl_dev(hst, mlen, 0, m, tmp, st);
-    hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
-                       vb, in, shift, (const uint32_t*)hst);
+    // passes over full tiles of scattered digits go through LDS (one
+    // contiguous run per digit and tile); region passes whose regions
+    // average under half a tile, and nearly ordered record keys, scatter
+    // directly
+    const bool short_regions = in.seg_count && cap < (u64)n_regions * (RS_TILE / 2);
+    if (lds_scatter && !short_regions)
+      hipLaunchKernelGGL(rs_scatter_lds_kernel<V>, dim3(grid), dim3(RS_THREADS), rs_scatter_lds<V>(), st,
+                         (const u64*)ka, (const V*)va, kb, vb, in, shift, (const uint32_t*)hst);
+    else
+      hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,
+                         vb, in, shift, (const uint32_t*)hst);
     u64* tk = ka; ka = kb; kb = tk;
     V* tv = va; va = vb; vb = tv;
     ++passes;
@@ -1180,7 +1278,7 @@ hipError_t sort_log(u64* k0, u64* v0, u64* k1, u64* v1, const u64* n_ptr, u64 ca
   f.keep_bc = keep_bc;
   f.keep_bk = keep_bk;
   return sort_pairs_impl<u64>(k0, v0, k1, v1, n_ptr, cap, nbits, seg_count, seg_base, tiles, n_regions, hist, dbits,
-                              st, in_second, start_bit, keep ? &f : nullptr);
+                              st, in_second, start_bit, keep ? &f : nullptr, true);
 }
 hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u64* n_ptr, u64 cap,
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {

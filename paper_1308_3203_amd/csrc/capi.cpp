@@ -155,8 +155,10 @@ size_t lds_base_bytes(const rc_prog* p) {
 // (Only when the table and a minimal log fit in LDS beside the rest.)
 void lds_table(const rc_prog* p, uint32_t* base, uint32_t* cells) {
   uint32_t gcells = 0;
-  for (const CompiledArray& a : p->c.arrays)
-    if (a.global && a.written) gcells += a.size;
+  for (size_t i = 0; i < p->c.arrays.size(); ++i) {
+    const CompiledArray& a = p->c.arrays[i];
+    if (a.global && a.written && !p->owned[i]) gcells += a.size;
+  }
   *base = p->G == 1 ? 0u : gcells;
   const uint32_t n = p->n_logged_cells - *base;
   const bool fits = lds_base_bytes(p) + (size_t)n * sizeof(TabCell) + 64 * 16 <= LDS_LIMIT;
@@ -1004,6 +1006,15 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
     }
   }
   p->overlay_cells = ov;
+  // log cell keys: the written arrays that are not owned, global ones first
+  uint32_t cb = 0;
+  for (size_t a = 0; a < own.size(); ++a) {
+    const bool keyed = p->c.arrays[a].written && !own[a].owned;
+    p->arrays[a].cellbase = keyed ? cb : 0xFFFFFFFFu;
+    p->cellbase[a] = keyed ? cb : 0xFFFFFFFFu;
+    if (keyed) cb += p->c.arrays[a].size;
+  }
+  p->n_logged_cells = cb;
   p->logged_mem = p->c.dyn_logged_mem;
   p->logged_local = p->c.dyn_logged_local;
   for (size_t a = 0; a < p->owned.size(); ++a) {

@@ -170,15 +170,17 @@ class SweepResult:
 
 
 def sweep(ctx: B.Context, inst: Instances, order=None, chunk: int = 2000, ws_bytes: int = 16 << 30,
-          rec_cap: int = 1 << 22) -> SweepResult:
+          rec_cap: int = 1 << 22, ws=None) -> SweepResult:
     """Check every instance, in `order` (default: index order), `chunk`
     instances per rc_batch_check call, timing each call by the library's HIP
     event spans around its kernels.  Records are counted per instance; record
-    buffers that overflow only truncate the written list, not the counts."""
+    buffers that overflow only truncate the written list, not the counts.
+    `ws`: a workspace to use (else one of ws_bytes is allocated)."""
     torch = _torch()
     n = len(inst)
     order = np.arange(n, dtype=np.int64) if order is None else np.asarray(order, dtype=np.int64)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    if ws is None:
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     records = torch.empty(rec_cap * B.RECORD_BYTES, dtype=torch.uint8, device="cuda")
     n_rec = torch.zeros(1, dtype=torch.int64, device="cuda")
     summ = torch.empty(chunk * B.SUMMARY_BYTES, dtype=torch.uint8, device="cuda")
@@ -282,8 +284,11 @@ def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_
     train = Instances.grid(load_programs(ctx, train_workloads), train_seeds)
     held = Instances.grid(load_programs(ctx, eval_workloads), eval_seeds)
     say(f"loaded {len(train_workloads)} + {len(eval_workloads)} programs")
+    # one workspace for every sweep (a large one freed and asked for again
+    # may not fit beside what the caching allocator keeps)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     # labels from the exact checker
-    lab = sweep(ctx, train, chunk=label_chunk, ws_bytes=ws_bytes)
+    lab = sweep(ctx, train, chunk=label_chunk, ws=ws)
     say(f"labelled {len(train)} instances ({int(lab.racy.sum())} racy)")
     labels = torch.from_numpy(lab.racy.astype(np.float32)).cuda()
     net = TriageNet(ctx, seed=init_seed)
@@ -294,15 +299,15 @@ def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_
     losses, train_ms = timed(fit)
     say(f"trained: losses {losses}")
     # warm the held-out programs' tables, then the plain sweep
-    sweep(ctx, Instances(held.programs, held.prog[:64], held.seed[:64]), chunk=chunk, ws_bytes=ws_bytes)
-    plain = sweep(ctx, held, chunk=chunk, ws_bytes=ws_bytes)
+    sweep(ctx, Instances(held.programs, held.prog[:64], held.seed[:64]), chunk=chunk, ws=ws)
+    plain = sweep(ctx, held, chunk=chunk, ws=ws)
     say("plain sweep done")
 
     def infer():
         return rank(ctx, net.scores(features(ctx, held)))
     order_dev, infer_ms = timed(infer)
     order = order_dev.cpu().numpy().astype(np.int64)
-    learned = sweep(ctx, held, order=order, chunk=chunk, ws_bytes=ws_bytes)
+    learned = sweep(ctx, held, order=order, chunk=chunk, ws=ws)
     if not np.array_equal(learned.racy, plain.racy) or not np.array_equal(learned.race_cells, plain.race_cells):
         raise RuntimeError("the two sweeps disagree on an instance: the exact check must not depend on the order")
     rep = evaluate(plain, learned, infer_ms, budget_frac)

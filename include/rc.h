@@ -161,10 +161,16 @@ rc_status rc_prog_owned(const rc_prog* prog, uint32_t array_id, int* owned);
  * program's array count (global arrays first, then local arrays, in
  * declaration order) and owned[a] (0 or 1) is written for the first
  * min(capacity, *n_arrays) arrays; owned may be NULL when capacity is 0.
- * RC_E_PARSE / RC_E_LIMIT as rc_prog_load, RC_E_INVAL for a shape outside
+ * never_faults (may be NULL) receives 1 when no input can make the program
+ * fault: its accesses and branches do not depend on loaded values or scalar
+ * parameters, and enumerating every work-item finds every access in bounds,
+ * no division by zero, every assert and assume holding and no barrier passed
+ * by only part of a group.  Accesses to read-only and owned arrays of such a
+ * program skip the group step of a memory statement.  RC_E_PARSE /
+ * RC_E_LIMIT as rc_prog_load, RC_E_INVAL for a shape outside
  * rc_set_ndrange's range. */
 rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint32_t group_size,
-                          uint8_t* owned, uint32_t capacity, uint32_t* n_arrays);
+                          uint8_t* owned, uint32_t capacity, uint32_t* n_arrays, int* never_faults);
 
 /* Inputs (Section 3 K(Args): arguments passed by the host).  A global array is
  * bound either to seeded values U[lo, hi) (1 <= hi - lo <= 2^32; instance j's

@@ -99,7 +99,7 @@ def load_library(path: str = LIB_PATH):
         "rc_set_ndrange": ([vp, u32, u32], ctypes.c_int),
         "rc_prog_owned": ([vp, u32, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rc_owned_arrays": ([ctypes.c_char_p, sz, u32, u32, ctypes.POINTER(ctypes.c_uint8), u32,
-                             ctypes.POINTER(u32)], ctypes.c_int),
+                             ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rc_bind_seeded": ([vp, u32, i64, i64], ctypes.c_int),
         "rc_bind_device": ([vp, u32, vp], ctypes.c_int),
         "rc_bind_scalar_seeded": ([vp, u32, i64, i64], ctypes.c_int),
@@ -140,16 +140,19 @@ def _call(fn, *args):
     return st
 
 
-def owned_arrays(src: str, groups: int, group_size: int) -> list:
+def owned_arrays(src: str, groups: int, group_size: int, with_faults: bool = False):
     """Per array (global arrays first, then local ones): True when no two
-    work-items of the shape can touch a common cell of it (host only)."""
+    work-items of the shape can touch a common cell of it (host only).
+    with_faults: also return whether the program is proven never to fault."""
     lib = load_library()
     b = src.encode()
     n = ctypes.c_uint32(0)
-    _call(lib.rc_owned_arrays, b, len(b), groups, group_size, None, 0, ctypes.byref(n))
+    nf = ctypes.c_int(0)
+    _call(lib.rc_owned_arrays, b, len(b), groups, group_size, None, 0, ctypes.byref(n), None)
     out = (ctypes.c_uint8 * max(1, n.value))()
-    _call(lib.rc_owned_arrays, b, len(b), groups, group_size, out, n.value, ctypes.byref(n))
-    return [bool(out[i]) for i in range(n.value)]
+    _call(lib.rc_owned_arrays, b, len(b), groups, group_size, out, n.value, ctypes.byref(n), ctypes.byref(nf))
+    owned = [bool(out[i]) for i in range(n.value)]
+    return (owned, bool(nf.value)) if with_faults else owned
 
 
 class Context:

@@ -909,7 +909,7 @@ rc_status rc_prog_owned(const rc_prog* p, uint32_t id, int* owned) {
 }
 
 rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint32_t group_size, uint8_t* owned,
-                          uint32_t capacity, uint32_t* n_arrays) {
+                          uint32_t capacity, uint32_t* n_arrays, int* never_faults) {
   if (!src || !n_arrays || (capacity && !owned)) return fail(RC_E_INVAL, "NULL argument");
   if (group_size < 1 || group_size > MAX_WG || num_groups < 1 || (u64)num_groups * group_size >= (1ull << 26))
     return fail(RC_E_INVAL, "launch shape out of range");
@@ -917,7 +917,9 @@ rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint
   std::string err;
   bool is_limit = false;
   if (!compile_program(src, len, &c, &err, &is_limit)) return fail(is_limit ? RC_E_LIMIT : RC_E_PARSE, "%s", err.c_str());
-  const std::vector<OwnedArray> o = owned_arrays(c, num_groups, group_size);
+  const Ownership proof = prove_ownership(c, num_groups, group_size);
+  const std::vector<OwnedArray>& o = proof.arrays;
+  if (never_faults) *never_faults = proof.never_faults ? 1 : 0;
   *n_arrays = (uint32_t)o.size();
   for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a].owned;
   return RC_OK;
@@ -981,7 +983,8 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->G = num_groups;
   p->W = W;
   p->shaped = true;
-  const std::vector<OwnedArray> own = owned_arrays(p->c, p->G, p->W);
+  const Ownership proof = prove_ownership(p->c, p->G, p->W);
+  const std::vector<OwnedArray>& own = proof.arrays;
   p->owned.assign(own.size(), 0);
   for (size_t a = 0; a < own.size(); ++a) p->owned[a] = own[a].owned;
   // overlay words per group: a global rw array owned with a stride keeps its
@@ -1006,6 +1009,10 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
     }
   }
   p->overlay_cells = ov;
+  for (size_t a = 0; a < own.size(); ++a) {
+    ArrayDesc& d = p->arrays[a];
+    d.nosync = proof.never_faults && (d.kind == AK_GLOBAL_RO || own[a].owned) ? 1u : 0u;
+  }
   // log cell keys: the written arrays that are not owned, global ones first
   uint32_t cb = 0;
   for (size_t a = 0; a < own.size(); ++a) {

@@ -717,10 +717,11 @@ struct Item {
     const bool rec = active && P.do_log && A.logged != LOG_NONE;
     // the barrier completes every earlier statement's accesses, publishes
     // pending faults (a faulting statement has no effect) and each wave's
-    // number of log entries for this statement
-    u64 brec;
-    uint32_t prefix, total;
-    if (mem_red(rec, &brec, &prefix, &total)) return true;
+    // number of log entries for this statement; a nosync array needs none
+    // of that
+    u64 brec = 0;
+    uint32_t prefix = 0, total = 0;
+    if (!A.nosync && mem_red(rec, &brec, &prefix, &total)) return true;
     const uint32_t cell = (uint32_t)idx;
     // overlay word of the cell: by cell, or for an owned array by (offset
     // from the work-item's stride, lid), which keeps a wave's words together

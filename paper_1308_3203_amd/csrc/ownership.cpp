@@ -365,12 +365,18 @@ class Enumerator {
   Enumerator(const Compiled& c, uint32_t G, uint32_t W, std::vector<uint8_t> cand)
       : c_(c), G_(G), W_(W), cand_(std::move(cand)) {}
 
+  // Set by run(): no statement of any work-item can fault (every access in
+  // bounds, no division by a zero or unknown divisor, every assert and
+  // assume holds), whatever the inputs.
+  bool never_faults = false;
+
   // owned[a] for the candidate arrays (others 0); all 0 when the program's
   // accesses depend on its inputs or the enumeration is too long
   std::vector<uint8_t> run() {
     const uint32_t na = (uint32_t)c_.arrays.size();
     std::vector<uint8_t> none(na, 0);
     if ((double)G_ * W_ * (double)c_.dyn_instr > (double)ENUM_STEPS_MAX) return none;
+    faults_ = false;
     owner_.assign(na, std::vector<int64_t>());
     for (uint32_t a = 0; a < na; ++a)
       if (cand_[a]) owner_[a].assign(c_.arrays[a].size, -1);
@@ -378,12 +384,18 @@ class Enumerator {
       for (uint32_t a = 0; a < na; ++a)   // each group has its own local arrays
         if (cand_[a] && !c_.arrays[a].global) std::fill(owner_[a].begin(), owner_[a].end(), -1);
       for (uint32_t l = 0; l < W_; ++l) {
+        bar_.clear();
         if (!item(g, l)) return none;
-        bool any = false;
+        // a barrier some work-items of the group pass and others skip is a
+        // divergence fault: every work-item must pass the same barriers
+        if (l == 0) bar0_ = bar_;
+        else if (bar_ != bar0_) faults_ = true;
+        bool any = !faults_;   // the fault question needs every work-item
         for (uint32_t a = 0; a < na; ++a) any = any || cand_[a];
         if (!any) return none;
       }
     }
+    never_faults = !faults_;
     return cand_;
   }
 
@@ -393,6 +405,8 @@ class Enumerator {
   std::vector<uint8_t> cand_;
   std::vector<std::vector<int64_t>> owner_;   // per candidate array: touching work-item, or -1
   uint64_t steps_ = 0;
+  bool faults_ = false;                       // some statement may fault
+  std::vector<uint32_t> bar_, bar0_;          // barriers passed: this work-item, the group's first
 
   uint32_t word(uint32_t i, int k) const { return c_.code[4 * i + k]; }
 
@@ -411,6 +425,7 @@ class Enumerator {
   }
 
   void touch(uint32_t a, Val idx, int64_t t) {
+    if (!idx.known || idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) faults_ = true;
     if (!cand_[a]) return;
     if (!idx.known) { cand_[a] = 0; return; }
     if (idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) return;   // faults: no access
@@ -435,6 +450,8 @@ class Enumerator {
         case OP_BIN: {
           const Val x = operand(fa, word(pc, 1), regs, g, l), y = operand(fb, word(pc, 2), regs, g, l);
           int32_t r = 0;
+          const bool div = sub == B_DIV || sub == B_REM || sub == B_MOD;
+          if (div && (!y.known || y.v == 0)) faults_ = true;
           regs[dst] = x.known && y.known && host_alu(sub, x.v, y.v, &r) ? Val{true, r} : Val{false, 0};
           ++pc;
           break;
@@ -486,9 +503,20 @@ class Enumerator {
           pc = lc[sub] < iters ? word(pc, 3) : pc + 1;
           break;
         }
+        case OP_ASSERT:
+        case OP_ASSUME: {
+          const Val cnd = operand(fa, word(pc, 1), regs, g, l);
+          if (!cnd.known || cnd.v == 0) faults_ = true;
+          ++pc;
+          break;
+        }
+        case OP_BARRIER:
+          bar_.push_back(pc);
+          ++pc;
+          break;
         case OP_END:
           return true;
-        default:   // endif, barrier, assert, assume
+        default:   // endif
           ++pc;
           break;
       }
@@ -499,20 +527,19 @@ class Enumerator {
 
 }  // namespace
 
-std::vector<OwnedArray> owned_arrays(const Compiled& c, uint32_t G, uint32_t W) {
+Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W) {
   Prover p(c, G, W);
-  std::vector<OwnedArray> out = p.run();
-  // the enumeration settles written arrays the affine proof left open
-  std::vector<uint8_t> cand(out.size(), 0);
-  bool any = false;
-  for (size_t a = 0; a < out.size(); ++a) {
-    cand[a] = !out[a].owned && c.arrays[a].written;
-    any = any || cand[a];
-  }
-  if (!any) return out;
-  const std::vector<uint8_t> e = Enumerator(c, G, W, cand).run();
-  for (size_t a = 0; a < out.size(); ++a)
-    if (e[a]) out[a].owned = 1;   // owned, kept in the plain layout
+  Ownership out;
+  out.arrays = p.run();
+  // the enumeration settles written arrays the affine proof left open, and
+  // whether any statement can fault
+  std::vector<uint8_t> cand(out.arrays.size(), 0);
+  for (size_t a = 0; a < out.arrays.size(); ++a) cand[a] = !out.arrays[a].owned && c.arrays[a].written;
+  Enumerator e(c, G, W, cand);
+  const std::vector<uint8_t> owned = e.run();
+  for (size_t a = 0; a < out.arrays.size(); ++a)
+    if (owned[a]) out.arrays[a].owned = 1;   // owned, kept in the plain layout
+  out.never_faults = e.never_faults;
   return out;
 }
 

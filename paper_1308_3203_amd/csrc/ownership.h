@@ -36,6 +36,15 @@ struct OwnedArray {
   uint8_t owned = 0;
   int64_t stride = 0, lo = 0, hi = 0;
 };
-std::vector<OwnedArray> owned_arrays(const Compiled& c, uint32_t G, uint32_t W);
+
+// never_faults: when the accesses and branches do not depend on the inputs,
+// the enumeration also sees every statement of every work-item; no access
+// out of bounds, no division by zero and no failing assert or assume means
+// no input can make the program fault.
+struct Ownership {
+  std::vector<OwnedArray> arrays;
+  bool never_faults = false;
+};
+Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W);
 
 }  // namespace rc

@@ -81,7 +81,11 @@ struct ArrayDesc {        // 64 bytes
   // != 0): cell own_stride * tid + o sits at overlay word (o - own_lo) * W +
   // lid of its group's region, which holds own_span * W words
   int32_t own_stride, own_lo;
-  uint32_t own_span, pad;
+  uint32_t own_span;
+  // the program cannot fault, and the array is read-only or owned: its
+  // accesses need no group step (no fault to publish, no log, no other
+  // work-item's cell)
+  uint32_t nosync;
 };
 
 struct ScalarDesc {

@@ -182,3 +182,44 @@ def test_owned_arrays_never_carry_records():
             n_owned += 1
             assert not any(int(rec["array"]) == 0 for rec in res.records), (src, G, W)
     assert n_owned >= 50
+
+
+FAULT_CASES = [
+    # (body, G, W, never faults)
+    ("  x[tid] := 1;", 4, 64, True),
+    ("  x[tid + 4000] := 1;", 4, 64, False),                  # tid >= 96 is out of bounds
+    ("  v := tid / 3;\n  x[v] := 1;", 4, 64, True),
+    ("  v := 100 / lid;\n  x[tid] := v;", 4, 64, False),        # lid 0 divides by zero
+    ("  v := y[tid];\n  w := 7 mod v;\n  x[tid] := w;", 4, 64, False),   # divisor from the inputs
+    ("  assert(tid >= 0);\n  x[tid] := 1;", 4, 64, True),
+    ("  assert(lid < 10);\n  x[tid] := 1;", 4, 64, False),
+    ("  if (lid < 5) {\n    barrier;\n  }\n  x[tid] := 1;", 4, 64, False),   # part of a group at a barrier
+    ("  if (gid < 1) {\n    barrier;\n  }\n  x[tid] := 1;", 4, 64, True),    # whole groups agree
+    ("  v := y[tid];\n  if (v < 3) {\n    x[tid] := 1;\n  }", 4, 64, False),   # a data-dependent path
+    ("  for k in 0..4 {\n    barrier;\n    x[tid * 4 + k] := k;\n  }", 4, 64, True),
+]
+
+
+@pytest.mark.parametrize("body,G,W,expect", FAULT_CASES)
+def test_never_faults(body, G, W, expect):
+    src = f"kernel t(global int x[4096], global int y[4096]) {{\n  int v, w, k, j;\n{body}\n}}\n"
+    assert B.owned_arrays(src, G, W, with_faults=True)[1] == expect
+
+
+def test_never_faults_agrees_with_the_oracle():
+    """Where the proof says a program cannot fault, the oracle's runs on
+    several inputs end without a fault."""
+    r = random.Random(99)
+    proven = 0
+    for case in range(200):
+        src = _random_affine_program(r)
+        G, W = r.choice([(1, 8), (2, 8), (4, 4)])
+        _, nf = B.owned_arrays(src, G, W, with_faults=True)
+        if not nf:
+            continue
+        proven += 1
+        prog = O.Program(src)
+        for seed in range(3):
+            res = prog.run(G, W, arrays={"x": ("seeded", 0, 4)}, seed=seed)
+            assert res.status == "OK", (src, G, W, res.status)
+    assert proven >= 20

@@ -282,7 +282,9 @@ struct Layout {
 };
 
 // counters block: [0] log entries, [1] records, [2] status word, [3] long runs
-enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_WORDS = 8 };
+// per-chunk counters: log entries, record slots reserved, status bits,
+// queued long runs, record slots left unused, records (reserved - unused)
+enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_DEAD = 4, CNT_LIVE = 5, CNT_WORDS = 8 };
 
 void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n_items) {
   size_t o = 0;
@@ -436,10 +438,13 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     L.max_rec = std::min<u64>(T_rec, (T_rec + k - 1) / k + M_rec);
     L.max_ovl = std::min<u64>(T_ovl, (T_ovl + k - 1) / k + M_ovl);
     L.max_rec = std::max<u64>(L.max_rec, L.max_log);
+    // slots that work-groups reserve in chunks and leave unused: at most a
+    // chunk per launched block (a block per work item at most)
+    L.max_rec += std::min<u64>(L.max_wg, (u64)N_WCLASS * REC_MAX_BLOCKS) * REC_CHUNK;
     L.bi = bits_for(L.max_slots);
     L.bc = bc; L.bg = bg; L.bk = bk; L.bs = bs;
     L.nbits_log = L.bi + bc + bg + bk;
-    L.nbits_rec = L.bi + bs + bc;
+    L.nbits_rec = L.bi + bs + bc + 1;   // the top bit is set only in unused slots' keys
     L.cc_stride = std::max<uint32_t>(1, max_cells);
     // The owner filter drops the entries of cells one work-item touched,
     // for the price of an owner word per access and one partition pass.  It
@@ -522,13 +527,14 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
         if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, jp->jit_fn, (int)threads, lds) != hipSuccess ||
             occ < 1)
           occ = 1;
-        const uint32_t blocks = std::max<uint32_t>(1, std::min(L.max_items_class[c], (uint32_t)(cus * occ)));
+        const uint32_t blocks =
+            std::max<uint32_t>(1, std::min(std::min(L.max_items_class[c], (uint32_t)(cus * occ)), REC_MAX_BLOCKS));
         void* args[] = {&P};
         HIP_TRY(hipModuleLaunchKernel(jp->jit_fn, blocks, 1, 1, threads, 1, 1, (unsigned)lds, st, args, nullptr));
         continue;
       }
       const uint32_t resident = (uint32_t)cus * (uint32_t)interp_occupancy(threads, lds);
-      const uint32_t blocks = std::max<uint32_t>(1, std::min(L.max_items_class[c], resident));
+      const uint32_t blocks = std::max<uint32_t>(1, std::min(std::min(L.max_items_class[c], resident), REC_MAX_BLOCKS));
       HIP_TRY(launch_interp(P, blocks, threads, lds, st));
     }
   }
@@ -558,12 +564,14 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     memset(&S.out, 0, sizeof S.out);
     S.out.staging = ws + L.stage; S.out.rec_keys = (u64*)(ws + L.rk0); S.out.rec_idx = (uint32_t*)(ws + L.ri0);
     S.out.rec_count = cnt + CNT_REC; S.out.rec_cap = L.max_rec; S.out.status_word = (uint32_t*)(cnt + CNT_STATUS);
+    S.out.rec_dead = cnt + CNT_DEAD;
     S.longq = (u64*)(ws + L.longq);
     S.long_count = cnt + CNT_LONG;
     S.long_cap = L.long_cap;
     HIP_TRY(launch_seg_check(S, L.max_log, st));
   }
   HIP_TRY(launch_clamp(cnt + CNT_REC, L.max_rec, (uint32_t*)(cnt + CNT_STATUS), 2u, st));
+  HIP_TRY(launch_live_count(cnt + CNT_REC, cnt + CNT_DEAD, cnt + CNT_LIVE, st));
   int rsecond = 0;
   {
     PhaseTimer t(ctx, st, 3, timed);
@@ -576,7 +584,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     memset(&Gp, 0, sizeof Gp);
     Gp.staging = (const rc_record_dev*)(ws + L.stage);
     Gp.idx = (const uint32_t*)(ws + (rsecond ? L.ri1 : L.ri0));
-    Gp.n_ptr = cnt + CNT_REC;
+    Gp.n_ptr = cnt + CNT_LIVE;   // the unused slots sort after every record
     Gp.out_base = (u64*)d_n_records;
     Gp.out = (rc_record_dev*)d_records;
     Gp.cap = cap;
@@ -597,7 +605,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     F.out = (rc_summary_dev*)d_summaries;
     F.max_slots = L.max_slots;
     HIP_TRY(launch_finalize(F, st));
-    HIP_TRY(launch_advance((u64*)d_n_records, cnt + CNT_REC, (uint32_t*)(ws + L.chunk_index), st));
+    HIP_TRY(launch_advance((u64*)d_n_records, cnt + CNT_LIVE, (uint32_t*)(ws + L.chunk_index), st));
   }
   return RC_OK;
 }
@@ -672,6 +680,7 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
   R.rec_idx = (uint32_t*)(ws + L.ri0);
   R.rec_count = cnt + CNT_REC;
   R.rec_cap = L.max_rec;
+  R.rec_dead = cnt + CNT_DEAD;
   R.status_word = (uint32_t*)(cnt + CNT_STATUS);
   // one upload of all call tables (they sit contiguously after the overlay pool)
   const size_t tbytes = L.counters - L.tables;

@@ -379,6 +379,7 @@ struct Item {
   u64* ovl;
   uint32_t tl, WP, wave, lane, tr;
   uint32_t nthr;           // threads of the block (64 << width class)
+  u64 rec_at, rec_jump, rec_room;   // the last record reservation (see group_reserve)
   bool real;
   u64* locc;
   u64* lkey;
@@ -539,11 +540,14 @@ struct Item {
     return intra_finish(p1, p2, &pr->label, &pr->rw, &pr->ww);
   }
 
-  // One atomic for the whole group: `n` slots for this thread, returned as
-  // the first of them (threads in order).  Every thread of the block calls it.
-  // (n <= 64: a thread finishes at most 4096 / 64 cells; the wave's scan
-  // is taken bit-plane by bit-plane with ballots)
-  __device__ __forceinline__ u64 group_reserve(unsigned long long* counter, uint32_t n) {
+  // Record slots for the whole group: this thread's n records are the
+  // group's records [k, k + n) (threads in order), and the k-th record of
+  // the group goes to slot_of(k).  The block takes the slots from chunks of
+  // REC_CHUNK it reserves with one atomic (not one per interval): the rest
+  // of the current chunk first, then a new one.  Every thread of the block
+  // calls it.  (n <= 64: a thread finishes at most 4096 / 64 cells; the
+  // wave's scan is taken bit-plane by bit-plane with ballots.)
+  __device__ __forceinline__ uint32_t group_reserve(const rc_record_out& R, uint32_t n) {
     const u64 below = (1ull << lane) - 1ull;
     uint32_t x = 0, wsum = 0;   // exclusive prefix in the wave, wave total
 #pragma unroll
@@ -552,7 +556,6 @@ struct Item {
       x += (uint32_t)__popcll(m & below) << b;
       wsum += (uint32_t)__popcll(m) << b;
     }
-    x += n;   // inclusive
     if (lane == 0) ctl->rec_sum[wave] = wsum;
     __syncthreads();
     const uint32_t nw = nthr >> 6;
@@ -564,13 +567,31 @@ struct Item {
     }
     if (tl == 0) {
       ctl->rec_sum_total = total;
-      ctl->rec_base = total ? __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, counter),
-                                                     (unsigned long long)total, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)
-                            : 0ull;
+      const u64 room = ctl->rc_end - ctl->rc_cur;
+      ctl->rec_base = ctl->rc_cur;               // records [0, room) go here
+      ctl->rc_room = room;
+      if (total <= room) {
+        ctl->rc_cur += total;
+        ctl->rc_next = ctl->rc_end;
+      } else {
+        const u64 more = total - room;           // and the rest to a new chunk
+        const u64 take = more > REC_CHUNK ? more : REC_CHUNK;
+        const u64 base = __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, R.rec_count), (unsigned long long)take,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ctl->rc_next = base;
+        ctl->rc_cur = base + more;
+        ctl->rc_end = base + take;
+      }
     }
     __syncthreads();
-    return ctl->rec_base + before + x - n;
+    rec_room = ctl->rc_room;
+    rec_at = ctl->rec_base;
+    rec_jump = ctl->rc_next;
+    return before + x;
+  }
+  // the slot of the group's k-th record of the last reservation
+  __device__ __forceinline__ u64 slot_of(uint32_t k) const {
+    return k < rec_room ? rec_at + k : rec_jump + (k - rec_room);
   }
 
   // Close the current interval on the LDS path: check its log in LDS (by a
@@ -625,7 +646,7 @@ struct Item {
       if (tab_finish(c, &pr)) ++mine;
       else tab[t] = empty_tab_cell();
     }
-    u64 at = group_reserve(R.rec_count, mine);
+    uint32_t at = group_reserve(R, mine);
     if (ctl->rec_sum_total == 0u) {
       __syncthreads();
       return;
@@ -645,7 +666,7 @@ struct Item {
       const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
       pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
       pr.cellkey = ck; pr.lidbase = gid * P.W;
-      store_record(R, K, at++, slot, instance, pr, false);
+      store_record(R, K, slot_of(at++), slot, instance, pr, false);
     }
     __syncthreads();
     return;
@@ -889,12 +910,23 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
   const uint32_t* item0 = PP.chunks[ci].item0;
   const uint32_t i0 = const_load<uint32_t>(item0, PP.wclass), i1 = const_load<uint32_t>(item0, PP.wclass + 1);
   if (i0 == i1) return;
+  if (threadIdx.x == 0) ctl->rc_cur = ctl->rc_end = 0ull;   // no record slots yet
   for (;;) {
     if (threadIdx.x == 0) ctl->item = i0 + atomicAdd(&PP.queue[PP.wclass], 1u);
     __syncthreads();
     const uint32_t item = uni(ctl->item);
     __syncthreads();
-    if (item >= i1) break;
+    if (item >= i1) {
+      // the block's unused record slots
+      const rc_record_out R = const_load<rc_record_out>(PP.rec, 0);
+      const u64 a = ctl->rc_cur, b = ctl->rc_end;
+      const uint32_t nthr = 64u << PP.wclass;
+      for (u64 p = a + threadIdx.x; p < b && p < R.rec_cap; p += nthr) RC_GLOBAL(u64, R.rec_keys)[p] = ~0ull;
+      if (threadIdx.x == 0 && b > a)
+        __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, R.rec_dead), (unsigned long long)(b - a),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
     const uint32_t instance = const_load<uint32_t>(PP.items, 2u * item);
     const uint32_t gid = const_load<uint32_t>(PP.items, 2u * item + 1u);
     const SlotDesc S = const_load<SlotDesc>(PP.slots, instance);

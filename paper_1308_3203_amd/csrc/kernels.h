@@ -129,6 +129,8 @@ hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st);
 hipError_t launch_rank_keys(const float* scores, uint32_t n, uint32_t idx_bits, unsigned long long* keys,
                             uint32_t* vals, unsigned long long* n_ptr, hipStream_t st);
 hipError_t launch_features(const FeatItem* items, const FeatProg* progs, uint32_t n, float* out, hipStream_t st);
+hipError_t launch_live_count(const unsigned long long* reserved, const unsigned long long* unused,
+                             unsigned long long* live, hipStream_t st);
 hipError_t launch_clamp(unsigned long long* n_ptr, unsigned long long cap, uint32_t* status, uint32_t bit,
                         hipStream_t st);
 

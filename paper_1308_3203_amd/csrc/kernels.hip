@@ -924,6 +924,10 @@ __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
 
 // entries past a buffer's capacity were dropped (and flagged): later kernels
 // see at most `cap`
+__global__ void live_count_kernel(const u64* reserved, const u64* unused, u64* live) {
+  *live = *reserved > *unused ? *reserved - *unused : 0ull;
+}
+
 __global__ void clamp_count_kernel(u64* n_ptr, u64 cap, uint32_t* status, uint32_t bit) {
   if (*n_ptr > cap) {
     *n_ptr = cap;
@@ -1316,6 +1320,10 @@ hipError_t launch_fill_u32(uint32_t* p, u64 n, uint32_t v, hipStream_t st) {
   uint32_t nb = blocks_for(n, 256);
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(nb), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_live_count(const u64* reserved, const u64* unused, u64* live, hipStream_t st) {
+  hipLaunchKernelGGL(live_count_kernel, dim3(1), dim3(1), 0, st, reserved, unused, live);
   return hipGetLastError();
 }
 hipError_t launch_clamp(u64* n_ptr, u64 cap, uint32_t* status, uint32_t bit, hipStream_t st) {

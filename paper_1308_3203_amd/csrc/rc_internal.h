@@ -181,12 +181,22 @@ struct rc_record_out {
   unsigned long long* rec_count;
   unsigned long long rec_cap;
   uint32_t* status_word;               // bit 1: staging capacity exceeded
+  // slots reserved by work-groups in chunks and left unused: their keys
+  // are REC_DEAD_KEY (sorted after every record) and they are counted here
+  unsigned long long* rec_dead;
 };
+// interpreter work-groups reserve record slots REC_CHUNK at a time; a launch
+// runs at most REC_MAX_BLOCKS blocks per width class, so at most
+// N_WCLASS * REC_MAX_BLOCKS * REC_CHUNK reserved slots stay unused
+constexpr unsigned long long REC_CHUNK = 64;
+constexpr uint32_t REC_MAX_BLOCKS = 4096;
 
 // LDS control block of the interpreter (after the local cells and registers)
 struct Ctl {
   unsigned long long fault;             // min fault key of the group (~0 = none)
   unsigned long long rec_base;          // the group's record reservation
+  unsigned long long rc_cur, rc_end;    // the block's reserved record slots [cur, end)
+  unsigned long long rc_next, rc_room;  // a reservation: rc_room slots at rec_base, the rest at rc_next
   uint32_t red[2][MAX_WAVES];           // per-wave reduction words, double-buffered
   uint32_t rec_sum[MAX_WAVES];          // per-wave record counts of a reservation
   uint32_t rec_sum_total, pad2;         // and their sum

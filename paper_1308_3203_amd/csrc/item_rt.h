@@ -511,16 +511,15 @@ struct Item {
     // before this one
     const uint32_t x = lane < P.nwaves ? ctl->red[parity][lane] : 0u;
     parity ^= 1u;
-    const u64 before = (1ull << wave) - 1ull;
-    uint32_t tot = 0, pre = 0;
-#pragma unroll
-    for (uint32_t b = 0; b < 7; ++b) {
-      const u64 m = __ballot((x >> (8u + b)) & 1u);
-      tot += (uint32_t)__popcll(m) << b;
-      pre += (uint32_t)__popcll(m & before) << b;
-    }
-    *prefix = pre;
-    *total = tot;
+    // inclusive scan of the counts over lanes 0..15 (one DPP row): lane w
+    // then holds the entries of waves 0..w
+    uint32_t c = x >> 8;
+    c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x111, 0xf, 0xf, true);   // row_shr:1
+    c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x112, 0xf, 0xf, true);   // row_shr:2
+    c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x114, 0xf, 0xf, true);   // row_shr:4
+    c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x118, 0xf, 0xf, true);   // row_shr:8
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)c, 15);
+    *prefix = wave == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)c, (int)(wave < 16u ? wave - 1u : 15u));
     return __ballot(x & 1u) != 0ull;
   }
 
@@ -734,7 +733,7 @@ struct Item {
     ArrayDesc A = const_load<ArrayDesc>(P.arrays, wc);
     if (KIND >= 0) A.kind = (uint32_t)KIND;
     if (KIND == (int)AK_GLOBAL_RO) A.logged = LOG_NONE;   // never written, never logged
-    if (active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);
+    if (!A.nosync && active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);   // (nosync: in bounds)
     const bool rec = active && P.do_log && A.logged != LOG_NONE;
     // the barrier completes every earlier statement's accesses, publishes
     // pending faults (a faulting statement has no effect) and each wave's

@@ -202,6 +202,9 @@ def main():
                 "avg_launch_ms": round(per_launch_ms, 4),
                 "phases_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
                 "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}
+    if dom not in ALGO_BYTES:
+        roofline["note"] = ("the dominant phase is a sort, whose passes carry no algorithmic bytes "
+                            "(implementation cost); path_frac is the whole path against 28 B per access")
 
     cpu = None
     if args.cpu_seconds > 0:
@@ -292,6 +295,9 @@ def bench_c3(args, ctx, desc):
                 "phase": dom, "avg_launch_ms": round(per_launch_ms, 4),
                 "phases_ms": {k: round(v[0], 3) for k, v in prof.items()},
                 "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}
+    if dom not in ALGO_BYTES:
+        roofline["note"] = ("the dominant phase is a sort, whose passes carry no algorithmic bytes "
+                            "(implementation cost); path_frac is the whole path against 28 B per access")
     cpu = cpu_baseline([(w, seeds) for w in works[: max(1, min(len(works), 50))]], args.cpu_seconds) \
         if args.cpu_seconds > 0 else None
     line = {

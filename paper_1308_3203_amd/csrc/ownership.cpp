@@ -313,6 +313,7 @@ class Prover {
 // adds accesses, so an array it finds unshared is unshared.
 // ---------------------------------------------------------------------------
 constexpr uint64_t ENUM_STEPS_MAX = 5000000;   // instructions interpreted on the host (~0.3 s)
+constexpr uint64_t ENUM_CELLS_MAX = 1ull << 26;  // owner words kept on the host (4 B each)
 
 struct Val {
   bool known;
@@ -376,6 +377,10 @@ class Enumerator {
     const uint32_t na = (uint32_t)c_.arrays.size();
     std::vector<uint8_t> none(na, 0);
     if ((double)G_ * W_ * (double)c_.dyn_instr > (double)ENUM_STEPS_MAX) return none;
+    uint64_t cells = 0;
+    for (uint32_t a = 0; a < na; ++a)
+      if (cand_[a]) cells += c_.arrays[a].size;
+    if (cells > ENUM_CELLS_MAX) return none;
     faults_ = false;
     owner_.assign(na, std::vector<int64_t>());
     for (uint32_t a = 0; a < na; ++a)
@@ -403,7 +408,7 @@ class Enumerator {
   const Compiled& c_;
   const uint32_t G_, W_;
   std::vector<uint8_t> cand_;
-  std::vector<std::vector<int64_t>> owner_;   // per candidate array: touching work-item, or -1
+  std::vector<std::vector<int32_t>> owner_;   // per candidate array: touching work-item, or -1
   uint64_t steps_ = 0;
   bool faults_ = false;                       // some statement may fault
   std::vector<uint32_t> bar_, bar0_;          // barriers passed: this work-item, the group's first
@@ -429,9 +434,9 @@ class Enumerator {
     if (!cand_[a]) return;
     if (!idx.known) { cand_[a] = 0; return; }
     if (idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) return;   // faults: no access
-    int64_t& o = owner_[a][(uint32_t)idx.v];
-    if (o == -1) o = t;
-    else if (o != t) cand_[a] = 0;
+    int32_t& o = owner_[a][(uint32_t)idx.v];
+    if (o == -1) o = (int32_t)t;   // work-item ids are below 2^26
+    else if (o != (int32_t)t) cand_[a] = 0;
   }
 
   // one work-item's path; false: the path depends on the inputs, or too long

@@ -382,7 +382,7 @@ class Enumerator {
       if (cand_[a]) cells += c_.arrays[a].size;
     if (cells > ENUM_CELLS_MAX) return none;
     faults_ = false;
-    owner_.assign(na, std::vector<int64_t>());
+    owner_.assign(na, std::vector<int32_t>());
     for (uint32_t a = 0; a < na; ++a)
       if (cand_[a]) owner_[a].assign(c_.arrays[a].size, -1);
     for (uint32_t g = 0; g < G_; ++g) {

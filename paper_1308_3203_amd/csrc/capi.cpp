@@ -180,11 +180,11 @@ size_t lds_entry_bytes(const rc_prog* p) {
   return tc ? 8u : 16u;
 }
 
-// LDS of one work-group; a per-program kernel keeps the private variables in
-// registers, so they take no LDS there.
-size_t lds_bytes(const rc_prog* p, bool jit) {
+// LDS of one work-group; a per-program kernel and the VGPR-file interpreter
+// keep the private variables in registers, so they take no LDS there.
+size_t lds_bytes(const rc_prog* p, bool vgpr_regs) {
   const uint32_t WP = ((p->W + 63) / 64) * 64;
-  const size_t regs = jit ? (size_t)p->c.nregs * WP * 4 : 0;
+  const size_t regs = vgpr_regs ? (size_t)p->c.nregs * WP * 4 : 0;
   return lds_fixed_bytes(p) - regs + (size_t)p->lds_log_cap * lds_entry_bytes(p);
 }
 
@@ -338,6 +338,7 @@ struct Call {
   uint32_t epoch_stride = 1;
   uint32_t radix_bits = 8;              // digit width of the access-log sort
   bool jit = false;                     // one program, run by its own kernel
+  bool class_vreg[N_WCLASS] = {false, false, false, false, false};   // class interpreted with VGPR registers
 };
 
 // Split the instances into chunks whose resources stay under the limits.
@@ -414,6 +415,23 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
   }
   C.classes_used = 0;
   C.jit = C.progs.size() == 1 && C.progs[0]->jit_on && C.progs[0]->jit_fn;
+  // per width class: the VGPR-file interpreter when every program fits it
+  // and it keeps more work-groups resident (its registers leave LDS, but it
+  // needs more VGPRs)
+  bool vreg_ok[N_WCLASS] = {true, true, true, true, true};
+  size_t lds_l[N_WCLASS] = {0, 0, 0, 0, 0}, lds_v[N_WCLASS] = {0, 0, 0, 0, 0};
+  for (rc_prog* p : C.progs) {
+    const uint32_t c = width_class(p->W);
+    vreg_ok[c] = vreg_ok[c] && p->c.nregs <= VREG_FILE;
+    lds_l[c] = std::max(lds_l[c], lds_bytes(p, false));
+    lds_v[c] = std::max(lds_v[c], lds_bytes(p, true));
+  }
+  for (uint32_t c = 0; c < N_WCLASS; ++c) {
+    C.class_vreg[c] = false;
+    if (C.jit || !vreg_ok[c] || lds_v[c] == 0) continue;
+    const uint32_t threads = 64u << c;
+    C.class_vreg[c] = interp_occupancy(threads, lds_v[c], true) > interp_occupancy(threads, lds_l[c], false);
+  }
   for (rc_prog* p : C.progs) {
     bc = std::max(bc, bits_for(std::max<u64>(1, p->n_logged_cells)));
     max_cells = std::max(max_cells, p->n_logged_cells);
@@ -423,7 +441,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     max_stores = std::max<u64>(max_stores, p->c.dyn_stores);
     const uint32_t c = width_class(p->W);
     C.classes_used |= 1u << c;
-    C.class_lds[c] = std::max(C.class_lds[c], lds_bytes(p, C.jit));
+    C.class_lds[c] = std::max(C.class_lds[c], lds_bytes(p, C.jit || C.class_vreg[c]));
   }
   C.epoch_stride = (uint32_t)std::min<u64>(max_stores + 1, 1u << 22);
   C.radix_bits = C.progs.empty() ? 8u : C.progs[0]->radix_bits;
@@ -533,9 +551,9 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
         HIP_TRY(hipModuleLaunchKernel(jp->jit_fn, blocks, 1, 1, threads, 1, 1, (unsigned)lds, st, args, nullptr));
         continue;
       }
-      const uint32_t resident = (uint32_t)cus * (uint32_t)interp_occupancy(threads, lds);
+      const uint32_t resident = (uint32_t)cus * (uint32_t)interp_occupancy(threads, lds, C.class_vreg[c]);
       const uint32_t blocks = std::max<uint32_t>(1, std::min(std::min(L.max_items_class[c], resident), REC_MAX_BLOCKS));
-      HIP_TRY(launch_interp(P, blocks, threads, lds, st));
+      HIP_TRY(launch_interp(P, blocks, threads, lds, C.class_vreg[c], st));
     }
   }
   if (!do_log) return RC_OK;
@@ -660,7 +678,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     D.n_arrays = (uint32_t)p->c.arrays.size();
     D.n_global = p->c.n_global;
     D.n_scalars = (uint32_t)p->c.scalars.size();
-    D.nregs = C.jit ? 0u : p->c.nregs;   // no LDS registers in a per-program kernel
+    // no LDS registers for registers held in VGPRs
+    D.nregs = C.jit || C.class_vreg[width_class(p->W)] ? 0u : p->c.nregs;
     D.G = p->G;
     D.W = p->W;
     D.nwaves = (p->W + 63) / 64;

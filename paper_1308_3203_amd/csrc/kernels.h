@@ -90,8 +90,12 @@ struct FinalMemParams {
   int32_t* out;
 };
 
-hipError_t launch_interp(const PassParams& P, uint32_t blocks, uint32_t threads, size_t lds_bytes, hipStream_t st);
-int interp_occupancy(uint32_t threads, size_t lds_bytes);
+// vreg: the interpreter variant with the private variables in a 16-entry
+// VGPR file (every program of the call has at most 16 registers)
+constexpr uint32_t VREG_FILE = 16;
+hipError_t launch_interp(const PassParams& P, uint32_t blocks, uint32_t threads, size_t lds_bytes, bool vreg,
+                         hipStream_t st);
+int interp_occupancy(uint32_t threads, size_t lds_bytes, bool vreg);
 hipError_t launch_setup(const SetupParams& P, hipStream_t st);
 hipError_t launch_ws_validate(unsigned long long* header, unsigned long long magic, unsigned long long ctx_id,
                               unsigned long long gen, unsigned long long* pool, unsigned long long pool_cells,

@@ -28,6 +28,10 @@ namespace rc {
 // on the Item runtime.  Private variables live in LDS (register-major, so a
 // wave reads 64 consecutive dwords); control flow keeps a mask bit per
 // nesting depth.
+// NR == 0: private variables in LDS (regs[r * WP + lid]); NR > 0: in a
+// register file of NR VGPRs per lane, indexed by the instruction's (uniform)
+// register number, for programs with at most NR registers.
+template <int NR>
 __device__ __forceinline__ void interp_item(Item& it) {
   const ItemView& P = it.P;
   int32_t* regs = it.regs;
@@ -36,10 +40,23 @@ __device__ __forceinline__ void interp_item(Item& it) {
   uint32_t pc = 0, depth = 0, eany = 0;
   uint32_t mbits = it.real ? 1u : 0u, ebits = 0u;
   (void)lane;
+  (void)WP;
+  (void)tr;
+  int32_t vr[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int i = 0; i < (NR > 0 ? NR : 1); ++i) vr[i] = 0;
+  auto rd = [&](uint32_t w) -> int32_t {
+    if constexpr (NR > 0) return vr[w < (uint32_t)NR ? w : (uint32_t)(NR - 1)];
+    else return regs[w * WP + tr];
+  };
+  auto wr = [&](uint32_t w, int32_t v) {
+    if constexpr (NR > 0) vr[w < (uint32_t)NR ? w : (uint32_t)(NR - 1)] = v;
+    else regs[w * WP + tl] = v;
+  };
 
   auto fetch = [&](bool imm, uint32_t w) -> int32_t {
     if (imm) return (int32_t)w;
-    if (w < MAX_REGS) return regs[w * WP + tr];
+    if (w < MAX_REGS) return rd(w);
     return it.special(w);
   };
 
@@ -57,21 +74,21 @@ __device__ __forceinline__ void interp_item(Item& it) {
       bool dz = false;
       int32_t r = alu_bin(sub, x, y, dz);
       if (active) {
-        regs[dst * WP + tl] = r;
+        wr(dst, r);
         if (dz) it.raise(spc, F_DIV);
       }
       ++pc;
     } else if (op == OP_UN) {
       int32_t x = fetch(fa, wa);
       int32_t r = sub == U_MOV ? x : sub == U_NEG ? (int32_t)(0u - (uint32_t)x) : sub == U_BNOT ? ~x : (int32_t)(x == 0);
-      if (active) regs[dst * WP + tl] = r;
+      if (active) wr(dst, r);
       ++pc;
     } else if (op == OP_LOAD || op == OP_STORE) {
       const int32_t idx = fetch(fa, wa);
       const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;
       int32_t v = 0;
       if (it.mem(op, wc, idx, val, active, spc, v)) { it.faulted = true; break; }
-      if (op == OP_LOAD && active) regs[dst * WP + tl] = v;
+      if (op == OP_LOAD && active) wr(dst, v);
       ++pc;
     } else if (op == OP_IF) {
       const int32_t c = fetch(fa, wa);
@@ -92,7 +109,7 @@ __device__ __forceinline__ void interp_item(Item& it) {
       ++pc;
     } else if (op == OP_FOR) {
       const int32_t lo = (int32_t)wa, hi = (int32_t)wb;
-      if (active) regs[dst * WP + tl] = lo;
+      if (active) wr(dst, lo);
       if ((int64_t)hi - (int64_t)lo <= 0) {
         pc = wc;
       } else {
@@ -104,7 +121,7 @@ __device__ __forceinline__ void interp_item(Item& it) {
       const uint32_t iters = (uint32_t)((int64_t)hi - (int64_t)lo);
       const uint32_t ctr = uni(ctl->loopctr[wave][sub]) + 1u;
       if (it.lane == 0) ctl->loopctr[wave][sub] = ctr;
-      if (active) regs[dst * WP + tl] = (int32_t)((uint32_t)lo + ctr);
+      if (active) wr(dst, (int32_t)((uint32_t)lo + ctr));
       pc = ctr < iters ? wc : pc + 1u;
     } else if (op == OP_BARRIER) {
       if (it.barrier(active, spc)) { it.faulted = true; break; }
@@ -121,7 +138,12 @@ __device__ __forceinline__ void interp_item(Item& it) {
 }
 
 __global__ __launch_bounds__(1024) void rc_interp_kernel(PassParams PP) {
-  run_items(PP, [](Item& it) { interp_item(it); });
+  run_items(PP, [](Item& it) { interp_item<0>(it); });
+}
+
+// the same for calls whose programs all have at most 16 registers
+__global__ __launch_bounds__(1024) void rc_interp_vreg_kernel(PassParams PP) {
+  run_items(PP, [](Item& it) { interp_item<VREG_FILE>(it); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,21 +1070,29 @@ static void set_lds_attr() {
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rc_interp_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rc_interp_vreg_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
 }
 
-hipError_t launch_interp(const PassParams& P, uint32_t blocks, uint32_t threads, size_t lds_bytes, hipStream_t st) {
+hipError_t launch_interp(const PassParams& P, uint32_t blocks, uint32_t threads, size_t lds_bytes, bool vreg,
+                         hipStream_t st) {
   set_lds_attr();
-  hipLaunchKernelGGL(rc_interp_kernel, dim3(blocks), dim3(threads), lds_bytes, st, P);
+  if (vreg)
+    hipLaunchKernelGGL(rc_interp_vreg_kernel, dim3(blocks), dim3(threads), lds_bytes, st, P);
+  else
+    hipLaunchKernelGGL(rc_interp_kernel, dim3(blocks), dim3(threads), lds_bytes, st, P);
   return hipGetLastError();
 }
 
-int interp_occupancy(uint32_t threads, size_t lds_bytes) {
+int interp_occupancy(uint32_t threads, size_t lds_bytes, bool vreg) {
   set_lds_attr();
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rc_interp_kernel, (int)threads, lds_bytes) != hipSuccess)
-    return 1;
+  const hipError_t e =
+      vreg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rc_interp_vreg_kernel, (int)threads, lds_bytes)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rc_interp_kernel, (int)threads, lds_bytes);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 

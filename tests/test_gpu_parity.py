@@ -371,3 +371,16 @@ def test_autotune_invariance_and_cache(case, tmp_path):
     n = int(buf.n_records.item())
     g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 4))
     U.assert_same(g, U.oracle_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 4), f"{case} tuned {chosen}")
+
+
+def test_many_registers_interpreted_from_lds():
+    """A program with more private variables than the VGPR register file
+    holds runs on the interpreter that keeps them in LDS."""
+    names = [f"r{i}" for i in range(20)]
+    body = "\n".join(f"  {n} := tid * {i + 1} + {i};" for i, n in enumerate(names))
+    body += "\n  " + "\n  ".join(f"x[({n}) mod 512] := {n};" for n in names[::3])
+    body += "\n  barrier;\n  r0 := x[(tid + 1) mod 512];\n  y[tid mod 64] := r0 + r19;"
+    src = f"kernel many(global int x[512], global int y[64]) {{\n  int {', '.join(names)};\n{body}\n}}\n"
+    for G, W in [(1, 64), (2, 100), (3, 256)]:
+        g, o = both(src, G, W, {"x": ("seeded", 0, 16), "y": ("seeded", 0, 16)}, seed0=3, n=3)
+        U.assert_same(g, o, f"many registers G={G} W={W}")

@@ -214,8 +214,11 @@ rc_status rc_autotune(rc_prog* prog, uint64_t seed0, uint32_t n_seeds, void* d_w
  * kernel of its own (private variables in registers, no instruction
  * dispatch) and compile it for gfx950 with the runtime compiler (about a
  * second, synchronous); rc_check calls of this program then run it.  Results
- * are identical to the interpreter's.  Needs the NDRange; re-compiled when
- * the work-group size moves to another width class.  rc_batch_check calls
+ * are identical to the interpreter's.  Needs the NDRange.  The kernel is
+ * specialised for the launch shape (work-group size, number of groups, the
+ * LDS log size the tuning picks): rc_set_ndrange and rc_prog_set_tuning on a
+ * program with the kernel enabled compile one for the new shape, or take one
+ * compiled earlier for it (kept until rc_prog_free).  rc_batch_check calls
  * that mix programs always interpret.  enable == 0: back to the interpreter.
  * RC_E_HIP with the compiler's log if compilation fails.
  */

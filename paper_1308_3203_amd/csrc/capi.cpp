@@ -98,11 +98,19 @@ struct rc_prog {
   // and the per-item access bounds on the arrays that are logged
   std::vector<uint8_t> owned;
   uint64_t logged_mem = 0, logged_local = 0;
-  // per-program kernel (rc_prog_jit): module of the generated kernel, the
-  // width class it was compiled for, and whether single-program calls use it
-  hipModule_t jit_mod = nullptr;
+  // per-program kernels (rc_prog_jit): every module compiled so far, one per
+  // (width class, launch shape); the one for the current shape, and whether
+  // single-program calls use it
+  struct JitEntry {
+    uint32_t cls;
+    JitShape shape;
+    hipModule_t mod;
+    hipFunction_t fn;
+  };
+  std::vector<JitEntry> jit_mods;
   hipFunction_t jit_fn = nullptr;
   uint32_t jit_class = ~0u;
+  JitShape jit_shape;
   bool jit_on = false;
   // device: code, then tables
   void* d_mem = nullptr;
@@ -401,6 +409,23 @@ void partition(Call& C, const Layout& lim) {
 }
 
 // Choose chunk limits so that the layout fits `ws_bytes`, then partition.
+// The launch shape of the program's current NDRange and tuning, as the
+// device descriptor states it.
+JitShape jit_shape_of(const rc_prog* p) {
+  JitShape s;
+  s.W = p->W;
+  s.G = p->G;
+  s.n_arrays = (uint32_t)p->c.arrays.size();
+  lds_table(p, &s.tab_base, &s.tab_cells);
+  if (!p->lds_log_cap) s.tab_cells = 0;
+  s.lds_log_cap = p->lds_log_cap;
+  return s;
+}
+
+bool jit_current(const rc_prog* p) {
+  return p->jit_fn && p->jit_class == width_class(p->W) && p->jit_shape == jit_shape_of(p);
+}
+
 bool plan(Call& C, size_t ws_bytes, std::string* why) {
   const uint32_t N = (uint32_t)C.inst_prog.size();
   u64 T_log = 0, T_rec = 0, T_ovl = 0, T_wg = 0, M_log = 0, M_rec = 0, M_ovl = 0, M_wg = 0;
@@ -414,7 +439,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     items_total += nd.wg;
   }
   C.classes_used = 0;
-  C.jit = C.progs.size() == 1 && C.progs[0]->jit_on && C.progs[0]->jit_fn;
+  C.jit = C.progs.size() == 1 && C.progs[0]->jit_on && jit_current(C.progs[0]);
   // per width class: the VGPR-file interpreter when every program fits it
   // and it keeps more work-groups resident (its registers leave LDS, but it
   // needs more VGPRs)
@@ -895,7 +920,7 @@ rc_status rc_prog_load(rc_ctx* ctx, const char* src, size_t len, rc_prog** out) 
 
 rc_status rc_prog_free(rc_prog* p) {
   if (!p) return fail(RC_E_INVAL, "prog is NULL");
-  if (p->jit_mod) (void)hipModuleUnload(p->jit_mod);
+  for (const rc_prog::JitEntry& j : p->jit_mods) (void)hipModuleUnload(j.mod);
   if (p->d_mem) (void)hipFree(p->d_mem);
   delete p;
   return RC_OK;
@@ -954,12 +979,23 @@ rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint
 }
 
 // Generate, compile and load the program's kernel for its current width
-// class (synchronous; the runtime compiler takes about a second).
+// class and launch shape (synchronous; the runtime compiler takes about a
+// second), or take it from the kernels already compiled.
 static rc_status jit_build(rc_prog* p) {
   const uint32_t cls = width_class(p->W);
+  const JitShape shape = jit_shape_of(p);
+  for (const rc_prog::JitEntry& j : p->jit_mods) {
+    if (j.cls == cls && j.shape == shape) {
+      p->jit_fn = j.fn;
+      p->jit_class = cls;
+      p->jit_shape = shape;
+      p->jit_on = true;
+      return RC_OK;
+    }
+  }
   std::vector<uint32_t> kinds;
   for (const ArrayDesc& a : p->arrays) kinds.push_back(a.kind);
-  const std::string src = jit_source(p->c.code, p->c.nregs, 64u << cls, kinds);
+  const std::string src = jit_source(p->c.code, p->c.nregs, 64u << cls, kinds, shape);
   std::vector<char> obj;
   std::string log;
   if (!jit_compile(src, &obj, &log)) {
@@ -975,10 +1011,10 @@ static rc_status jit_build(rc_prog* p) {
     (void)hipModuleUnload(mod);
     return fail(RC_E_HIP, "hipModuleGetFunction: %s", hipGetErrorString(e));
   }
-  if (p->jit_mod) (void)hipModuleUnload(p->jit_mod);
-  p->jit_mod = mod;
+  p->jit_mods.push_back({cls, shape, mod, fn});
   p->jit_fn = fn;
   p->jit_class = cls;
+  p->jit_shape = shape;
   p->jit_on = true;
   return RC_OK;
 }
@@ -990,10 +1026,6 @@ rc_status rc_prog_jit(rc_prog* p, int enable) {
     return RC_OK;
   }
   if (!p->shaped) return fail(RC_E_STATE, "set the NDRange before compiling the program kernel");
-  if (p->jit_fn && p->jit_class == width_class(p->W)) {
-    p->jit_on = true;
-    return RC_OK;
-  }
   return jit_build(p);
 }
 
@@ -1058,8 +1090,8 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
     if (!p->c.arrays[a].global) p->logged_local -= std::min(p->logged_local, p->c.dyn_mem_array[a]);
   }
   p->lds_log_cap = lds_log_entries(p);
-  // a per-program kernel is compiled for one width class
-  if (p->jit_on && p->jit_class != width_class(W)) return jit_build(p);
+  // a per-program kernel is compiled for one launch shape
+  if (p->jit_on && !jit_current(p)) return jit_build(p);
   return RC_OK;
 }
 
@@ -1114,6 +1146,7 @@ rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   p->lds_log_pref = t->lds_log_entries;
   p->radix_bits = t->radix_bits ? t->radix_bits : 8;
   if (p->shaped) p->lds_log_cap = lds_log_entries(p);
+  if (p->jit_on && p->shaped && !jit_current(p)) return jit_build(p);
   return RC_OK;
 }
 
@@ -1364,6 +1397,9 @@ rc_status rc_sync(rc_ctx* ctx) {
     if (status & 4u) {
       result = RC_E_HIP;
       msg = "internal error: an access left its owned-array placement";
+    } else if (status & 8u) {
+      result = RC_E_HIP;
+      msg = "internal error: a per-program kernel ran on a program of another launch shape";
     } else if (status != 0u) {
       result = RC_E_HIP;
       msg = "internal capacity exceeded (access log or record staging)";

@@ -942,6 +942,23 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.inst_acc = PP.inst_acc; P.inst_intervals = PP.inst_intervals; P.inst_fault = PP.inst_fault;
     P.wg_count = PP.wg_count; P.wg_base = PP.wg_base;
     P.cell_owner = PP.cell_owner; P.co_stride = PP.cell_owner_stride;
+#ifdef RC_JIT_W
+    // A per-program kernel is compiled for one launch shape: its constants
+    // replace the descriptor's fields, so the compiler folds them.  A
+    // descriptor of another shape is a library error, reported through the
+    // status word; the item is skipped.
+    if (D.W != RC_JIT_W || D.G != RC_JIT_G || D.n_arrays != RC_JIT_NA || D.tab_cells != RC_JIT_TC ||
+        D.tab_base != RC_JIT_TB || D.lds_log_cap != RC_JIT_LC) {
+      if (threadIdx.x == 0) {
+        atomicOr(PP.status_word, 8u);
+        PP.wg_count[S.wg_base + gid] = 0u;   // nothing logged
+        PP.wg_base[S.wg_base + gid] = S.log_base + (u64)gid * D.wg_log_cap;
+      }
+      continue;
+    }
+    P.W = RC_JIT_W; P.G = RC_JIT_G; P.nwaves = (RC_JIT_W + 63u) / 64u; P.n_arrays = RC_JIT_NA;
+    P.tab_cells = RC_JIT_TC; P.tab_base = RC_JIT_TB; P.lds_log_cap = RC_JIT_LC;
+#endif
     Item it;
     it.init(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,
             PP.overlay + S.ovl_base + (u64)gid * D.overlay_cells, C.epoch, S.wg_base + gid, 64u << PP.wclass);

@@ -33,7 +33,7 @@ std::string operand(bool imm, uint32_t w) {
 }  // namespace
 
 std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32_t threads,
-                       const std::vector<uint32_t>& array_kind) {
+                       const std::vector<uint32_t>& array_kind, const JitShape& shape) {
   const uint32_t n = (uint32_t)(code.size() / 4);
   std::set<uint32_t> targets;
   std::set<uint32_t> slots;
@@ -45,6 +45,13 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
   }
   std::string s;
   char buf[512];
+  // the launch shape, folded by the runtime (item_rt.h checks every item's
+  // descriptor against it)
+  snprintf(buf, sizeof buf,
+           "#define RC_JIT_W %uu\n#define RC_JIT_G %uu\n#define RC_JIT_NA %uu\n#define RC_JIT_TB %uu\n"
+           "#define RC_JIT_TC %uu\n#define RC_JIT_LC %uu\n",
+           shape.W, shape.G, shape.n_arrays, shape.tab_base, shape.tab_cells, shape.lds_log_cap);
+  s += buf;
   s += "#include \"item_rt.h\"\n\nnamespace {\n\n__device__ __forceinline__ void jit_item(rc::Item& it) {\n";
   s += "  using namespace rc;\n";
   for (uint32_t r = 0; r < nregs; ++r) {

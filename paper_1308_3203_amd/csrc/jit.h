@@ -8,12 +8,26 @@
 
 namespace rc {
 
+// The launch shape a per-program kernel is compiled for: the NDRange, the
+// number of arrays and the LDS layout of the interval log (the per-cell
+// table's first cell key and size, the log's capacity in entries).  The
+// kernel folds them as constants; a program whose shape or tuning changes
+// needs another kernel.
+struct JitShape {
+  uint32_t W = 0, G = 0, n_arrays = 0, tab_base = 0, tab_cells = 0, lds_log_cap = 0;
+  bool operator==(const JitShape& o) const {
+    return W == o.W && G == o.G && n_arrays == o.n_arrays && tab_base == o.tab_base && tab_cells == o.tab_cells &&
+           lds_log_cap == o.lds_log_cap;
+  }
+};
+
 // HIP source of the kernel `rc_jit_kernel` for one program: `code` is the
 // bytecode (4 words per instruction), `threads` the workgroup size it is
-// launched with (64 << width class).
+// launched with (64 << width class), `shape` the launch shape it is
+// specialised for.
 // array_kind[a] is array a's AK_* kind (fixed by the program text).
 std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32_t threads,
-                       const std::vector<uint32_t>& array_kind);
+                       const std::vector<uint32_t>& array_kind, const JitShape& shape);
 
 // Compile for gfx950; false with the compiler's log on failure.
 bool jit_compile(const std::string& src, std::vector<char>* code_object, std::string* log);

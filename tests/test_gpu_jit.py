@@ -87,3 +87,24 @@ def test_jit_and_interpreter_agree_across_width_change():
             n = int(buf.n_records.item())
             outs.append((B.records_to_numpy(buf.records, n).tobytes(), B.summaries_to_numpy(buf.summaries, 16).tobytes()))
         assert outs[0] == outs[1], W
+
+
+def test_jit_follows_shape_and_tuning():
+    """The per-program kernel is specialised for the launch shape: a new
+    number of groups or LDS log size compiles another kernel (or takes the
+    one compiled for that shape before), and every result stays the
+    oracle's."""
+    w = [x for x in WL.c2_templates() if x.name == "tree_reduce_race"][0]
+    p = B.Program(U.ctx(), w.src)
+    p.bind(w.arrays, w.scalars)
+    p.set_ndrange(2, w.W)
+    p.jit(True)
+    for G, T in [(2, 0), (5, 0), (5, 64), (2, 0)]:
+        p.set_ndrange(G, w.W)
+        p.set_tuning(lds_log_entries=T)
+        buf = B.Buffers(p, 3, 1 << 16)
+        p.check_async(7, 3, buf.ws, buf.records, buf.n_records, buf.summaries)
+        U.ctx().sync()
+        n = int(buf.n_records.item())
+        g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 3))
+        U.assert_same(g, U.oracle_run(w.src, G, w.W, w.arrays, w.scalars, 7, 3), f"G={G} T={T}")

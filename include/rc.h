@@ -186,12 +186,17 @@ rc_status rc_bind_scalar(rc_prog* prog, uint32_t scalar_id, int32_t value);
  * the per-work-group interval log kept in LDS (rounded down to a power of
  * two and clamped to what LDS holds; 0 = the library's choice).  Intervals
  * larger than it are checked by the global pass instead.  radix_bits: digit
- * width of the global access-log sort, 1..8 (0 = 8); a batch uses the value
- * of its first instance's program. */
+ * width of the global access-log sort, 1..8 (0 = 8).  record_sort: 0 = the
+ * library's choice (a call with no global access log places each record by
+ * the record counts of the (instance, group, interval)s before it and its
+ * rank within its own, with no sort); 1 = always radix-sort the records by
+ * their full canonical key.  A batch uses radix_bits and record_sort of its
+ * first instance's program; rc_autotune keeps record_sort. */
 typedef struct {
   uint32_t lds_log_entries;
   uint32_t radix_bits;
-  uint32_t reserved[6];
+  uint32_t record_sort;
+  uint32_t reserved[5];
 } rc_tuning;
 rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
 

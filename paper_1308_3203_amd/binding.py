@@ -59,7 +59,7 @@ class _Profile(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_log_entries", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("record_sort", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -378,10 +378,11 @@ class Program:
         checks then run it instead of the interpreter."""
         _call(_lib.rc_prog_jit, self._h, 1 if enable else 0)
 
-    def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0):
+    def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0, record_sort: int = 0):
         t = _Tuning()
         t.lds_log_entries = lds_log_entries
         t.radix_bits = radix_bits
+        t.record_sort = record_sort
         _call(_lib.rc_prog_set_tuning, self._h, ctypes.byref(t))
 
     def autotune(self, seed0: int, n_seeds: int, ws, cache_path: str | None = None) -> dict:

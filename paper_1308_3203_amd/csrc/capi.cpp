@@ -93,6 +93,7 @@ struct rc_prog {
   uint32_t n_logged_cells = 0, overlay_cells = 0, lds_local_cells = 0;
   uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
+  uint32_t record_sort = 0;          // tuning: 1 = always sort records by their full key
   uint32_t lds_log_cap = 0;          // chosen for the current shape
   // arrays no two work-items share under the current shape (never logged),
   // and the per-item access bounds on the arrays that are logged
@@ -223,15 +224,19 @@ bool lds_logged(const rc_prog* p, uint32_t a) {
   return p->lds_log_cap && p->c.arrays[a].written && !p->owned[a] && (!p->c.arrays[a].global || p->G == 1);
 }
 
-// log entries one work-group may write to the global log
-u64 wg_log_entries(const rc_prog* p) {
+// log entries one work-group may write to the global log (0: none, the
+// program's logged accesses all stay in LDS)
+u64 wg_log_need(const rc_prog* p) {
   const Compiled& c = p->c;
   const u64 lds = p->lds_log_cap ? p->logged_local + (p->G == 1 ? p->logged_mem - p->logged_local : 0) : 0;
   const u64 glob = p->logged_mem - lds;
   const double ib = p->G == 1 ? c.interval_logged_all : c.interval_logged_local;
   const bool spill = p->lds_log_cap && (double)p->W * ib > (double)p->lds_log_cap;
-  return std::max<u64>(1, (u64)p->W * (glob + (spill ? lds : 0)));
+  return (u64)p->W * (glob + (spill ? lds : 0));
 }
+
+// the same, at least one entry (the global log's buffers are never empty)
+u64 wg_log_entries(const rc_prog* p) { return std::max<u64>(1, wg_log_need(p)); }
 
 uint32_t width_class(uint32_t W) {
   const uint32_t nw = (W + 63) / 64;
@@ -263,7 +268,12 @@ Need need_of(const rc_prog* p) {
   Need n;
   n.wg = p->G;
   n.log = (u64)p->G * wg_log_entries(p);
-  n.recs = std::max<u64>(1, (u64)p->G * p->W * p->logged_mem);
+  // A record stands for a cell of one scope with at least two logged
+  // accesses (an eligible pair needs two work-items), and the scopes of one
+  // kind split the accesses: at most half the logged accesses give INTRA
+  // records, and at most half the global ones give INTER records.
+  const u64 acc = (u64)p->G * p->W;
+  n.recs = std::max<u64>(1, (acc * p->logged_mem + acc * (p->logged_mem - p->logged_local) + 1) / 2);
   n.ovl = (u64)p->G * p->overlay_cells;
   return n;
 }
@@ -281,6 +291,12 @@ struct Layout {
   size_t lk0 = 0, lv0 = 0, lk1 = 0, lv1 = 0, hist = 0, stage = 0, rk0 = 0, ri0 = 0, rk1 = 0, ri1 = 0;
   size_t longq = 0;
   u64 long_cap = 0;
+  // records placed by rank (no global log, so every record comes from an
+  // interval closed in LDS): per-(slot, scope) record counts and the scan's
+  // partial sums
+  bool rank = false;
+  u64 scope_n = 0;
+  size_t scope_cnt = 0, scope_tmp = 0;
   // per-(slot, cell) owner words of the global log (cc_stride cells per
   // slot), when the table is small beside the log it filters
   size_t cc = 0;
@@ -324,12 +340,17 @@ void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n
   L->long_cap = 2 * L->max_log / (SEG_SHORT_RUN + 1) + 2;
   L->longq = take(L->long_cap * 16);
   L->cc = take(L->filter ? (size_t)L->max_slots * L->cc_stride * 4 : 0);
-  L->hist = take(std::max(sort_log_hist_words(L->max_wg, L->max_log), sort_hist_words(L->max_rec)) * 4);
+  // (placing records by rank needs no record sort: no second key buffer,
+  // no first index buffer, no sort histogram)
+  const u64 sorted_rec = L->rank ? 0 : L->max_rec;
+  L->hist = take(std::max(sort_log_hist_words(L->max_wg, L->max_log), sorted_rec ? sort_hist_words(sorted_rec) : 0) * 4);
   L->stage = take(L->max_rec * sizeof(rc_record));
   L->rk0 = take(L->max_rec * 8);
-  L->ri0 = take(L->max_rec * 4);
-  L->rk1 = take(L->max_rec * 8);
+  L->ri0 = take(sorted_rec * 4);
+  L->rk1 = take(sorted_rec * 8);
   L->ri1 = take(L->max_rec * 4);
+  L->scope_cnt = take(L->scope_n * 4);
+  L->scope_tmp = take(L->rank ? scan_tmp_words(L->scope_n) * 4 : 0);
   L->total = o;
 }
 
@@ -345,6 +366,7 @@ struct Call {
   size_t class_lds[N_WCLASS] = {0, 0, 0, 0, 0};
   uint32_t epoch_stride = 1;
   uint32_t radix_bits = 8;              // digit width of the access-log sort
+  uint32_t record_sort = 0;             // 1: never place records by rank
   bool jit = false;                     // one program, run by its own kernel
   bool class_vreg[N_WCLASS] = {false, false, false, false, false};   // class interpreted with VGPR registers
 };
@@ -470,6 +492,9 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
   }
   C.epoch_stride = (uint32_t)std::min<u64>(max_stores + 1, 1u << 22);
   C.radix_bits = C.progs.empty() ? 8u : C.progs[0]->radix_bits;
+  C.record_sort = C.progs.empty() ? 0u : C.progs[0]->record_sort;
+  bool lds_only = true;   // no program of the call writes the global log
+  for (const rc_prog* p : C.progs) lds_only = lds_only && wg_log_need(p) == 0;
   if (bc > 32 || bg > 26 || bk > 32) { *why = "sort key fields too wide"; return false; }
   // try 1, 2, 4, ... chunks
   for (u64 k = 1;; k *= 2) {
@@ -498,6 +523,12 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     const u64 owner_words = (u64)L.max_slots * L.cc_stride;
     L.filter = L.max_log >= 4096 && owner_words >= L.max_log && owner_words <= 4 * L.max_log && bg <= 21;
     if (L.nbits_log > 64 || L.nbits_rec > 64) { *why = "sort key wider than 64 bits"; return false; }
+    // Without a global log every record comes from an interval closed in
+    // LDS, which emits its records in cell-key order: a record's position
+    // is then fixed by the record counts of the (slot, scope)s before it
+    // and its rank, and the records need no sort.
+    L.rank = C.record_sort == 0 && lds_only && L.bi + bs <= 32 && ((u64)L.max_slots << bs) <= (1ull << 26);
+    L.scope_n = L.rank ? (u64)L.max_slots << bs : 0;
     Layout lim = L;
     partition(C, lim);
     lay_out(&L, C.progs.size(), N, C.chunks.size(), C.items.size() / 2);
@@ -539,6 +570,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     S.overlay = (u64*)(ws + L.overlay); S.overlay_cells = L.max_ovl; S.max_slots = L.max_slots;
     HIP_TRY(launch_setup(S, st));
     HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.wg_count), L.max_wg, 0u, st));
+    if (L.rank) HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.scope_cnt), L.scope_n, 0u, st));
   }
   {
     PhaseTimer t(ctx, st, 0, timed);
@@ -618,8 +650,16 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
   int rsecond = 0;
   {
     PhaseTimer t(ctx, st, 3, timed);
-    HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1), (uint32_t*)(ws + L.ri1),
-                           cnt + CNT_REC, L.max_rec, L.nbits_rec, (uint32_t*)(ws + L.hist), st, &rsecond));
+    if (L.rank) {
+      HIP_TRY(order_by_rank((uint32_t*)(ws + L.scope_cnt), L.scope_n, (uint32_t*)(ws + L.scope_tmp),
+                            (const u64*)(ws + L.rk0), cnt + CNT_REC, L.max_rec, (uint32_t*)(ws + L.ri1),
+                            (uint32_t*)(cnt + CNT_STATUS), st));
+      rsecond = 1;
+    } else {
+      HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1),
+                             (uint32_t*)(ws + L.ri1), cnt + CNT_REC, L.max_rec, L.nbits_rec,
+                             (uint32_t*)(ws + L.hist), st, &rsecond));
+    }
   }
   {
     PhaseTimer t(ctx, st, 4, timed);
@@ -628,6 +668,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     Gp.staging = (const rc_record_dev*)(ws + L.stage);
     Gp.idx = (const uint32_t*)(ws + (rsecond ? L.ri1 : L.ri0));
     Gp.n_ptr = cnt + CNT_LIVE;   // the unused slots sort after every record
+    Gp.stage_cap = L.max_rec;
     Gp.out_base = (u64*)d_n_records;
     Gp.out = (rc_record_dev*)d_records;
     Gp.cap = cap;
@@ -726,6 +767,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
   R.rec_cap = L.max_rec;
   R.rec_dead = cnt + CNT_DEAD;
   R.status_word = (uint32_t*)(cnt + CNT_STATUS);
+  R.rank_keys = L.rank ? 1u : 0u;
+  R.scope_cnt = L.rank ? (uint32_t*)(ws + L.scope_cnt) : nullptr;
   // one upload of all call tables (they sit contiguously after the overlay pool)
   const size_t tbytes = L.counters - L.tables;
   ctx->h_call.assign(tbytes, 0);
@@ -1143,6 +1186,8 @@ rc_status rc_bind_scalar(rc_prog* p, uint32_t id, int32_t value) {
 rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   if (!p || !t) return fail(RC_E_INVAL, "NULL argument");
   if (t->radix_bits > 8) return fail(RC_E_INVAL, "radix_bits must be in 1..8 (0: default)");
+  if (t->record_sort > 1) return fail(RC_E_INVAL, "record_sort must be 0 or 1");
+  p->record_sort = t->record_sort;
   p->lds_log_pref = t->lds_log_entries;
   p->radix_bits = t->radix_bits ? t->radix_bits : 8;
   if (p->shaped) p->lds_log_cap = lds_log_entries(p);
@@ -1215,6 +1260,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
   const std::string key = bucket_key(p, ctx->device);
   rc_tuning t;
   if (cache_path && cache_lookup(cache_path, key, &t)) {
+    t.record_sort = p->record_sort;
     s = rc_prog_set_tuning(p, &t);
     if (s) return s;
     *chosen = t;
@@ -1236,6 +1282,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
       memset(&c, 0, sizeof c);
       c.lds_log_entries = T;
       c.radix_bits = d;
+      c.record_sort = p->record_sort;
       cands.push_back(c);
     }
   }
@@ -1299,6 +1346,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
     memset(&back, 0, sizeof back);
     back.lds_log_entries = saved_pref;
     back.radix_bits = saved_bits;
+    back.record_sort = p->record_sort;
     rc_prog_set_tuning(p, &back);
     return result;
   }

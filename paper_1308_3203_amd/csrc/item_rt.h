@@ -299,8 +299,10 @@ __device__ __forceinline__ rc_record_dev make_record(const RecKey& K, uint32_t s
 #define RC_GLOBAL(T, ptr) ((T*)(ptr))   // the host pass only parses device code
 #endif
 
+// k: the record's rank among the records of its (group, interval) in
+// cell-key order (used by rank keys only)
 __device__ __forceinline__ void store_record(const rc_record_out& R, const RecKey& K, u64 pos, uint32_t slot,
-                                             uint32_t instance, const PendingRec& p, bool inter) {
+                                             uint32_t instance, const PendingRec& p, bool inter, uint32_t k = 0) {
   if (pos >= R.rec_cap) {
     __hip_atomic_fetch_or(RC_GLOBAL(uint32_t, R.status_word), 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -319,8 +321,12 @@ __device__ __forceinline__ void store_record(const rc_record_out& R, const RecKe
   r.pad = 0;
   RC_GLOBAL(rc_record_dev, R.staging)[pos] = r;
   const u64 scope = inter ? (u64)K.G * K.NI : (u64)p.gid * K.NI + p.interval;
-  RC_GLOBAL(u64, R.rec_keys)[pos] = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
-  RC_GLOBAL(uint32_t, R.rec_idx)[pos] = (uint32_t)pos;
+  if (R.rank_keys) {
+    RC_GLOBAL(u64, R.rec_keys)[pos] = ((((u64)slot << K.bs) | scope) << 32) | k;
+  } else {
+    RC_GLOBAL(u64, R.rec_keys)[pos] = ((u64)slot << (K.bs + K.bc)) | (scope << K.bc) | p.cellkey;
+    RC_GLOBAL(uint32_t, R.rec_idx)[pos] = (uint32_t)pos;
+  }
 }
 
 // wave-wide allocation of record slots: one atomic per wave
@@ -632,13 +638,16 @@ struct Item {
       }
     }
     __syncthreads();
-    // Each thread finishes cells tl, tl + nthr, ...: a first pass counts its
-    // records, the group reserves them with one atomic, a second pass stores
-    // them and clears the cells for the next interval.
+    // Each thread finishes a run of consecutive cells (so the records leave
+    // in cell-key order): a first pass counts its records, the group
+    // reserves them with one atomic, a second pass stores them and clears
+    // the cells for the next interval.
     // Cells without a record are cleared in the first pass; the second runs
     // only when the group has records.
+    const uint32_t per = (P.tab_cells + nthr - 1u) / nthr;
+    const uint32_t t0 = tl * per, t1 = min(t0 + per, P.tab_cells);
     uint32_t mine = 0;
-    for (uint32_t t = tl; t < P.tab_cells; t += nthr) {
+    for (uint32_t t = t0; t < t1; ++t) {
       const TabCell c = tab[t];
       if (c.wmin == ~0ull && c.r1 == NONE32) continue;
       PendingRec pr;
@@ -646,11 +655,14 @@ struct Item {
       else tab[t] = empty_tab_cell();
     }
     uint32_t at = group_reserve(R, mine);
-    if (ctl->rec_sum_total == 0u) {
+    const uint32_t total = ctl->rec_sum_total;
+    if (total == 0u) {
       __syncthreads();
       return;
     }
-    for (uint32_t t = tl; t < P.tab_cells; t += nthr) {
+    if (R.rank_keys && tl == 0)
+      RC_GLOBAL(uint32_t, R.scope_cnt)[((u64)slot << K.bs) | ((u64)gid * K.NI + interval)] = total;
+    for (uint32_t t = t0; t < t1; ++t) {
       const TabCell c = tab[t];
       if (c.wmin == ~0ull && c.r1 == NONE32) continue;
       tab[t] = empty_tab_cell();
@@ -665,7 +677,8 @@ struct Item {
       const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
       pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
       pr.cellkey = ck; pr.lidbase = gid * P.W;
-      store_record(R, K, slot_of(at++), slot, instance, pr, false);
+      store_record(R, K, slot_of(at), slot, instance, pr, false, at);
+      ++at;
     }
     __syncthreads();
     return;
@@ -686,6 +699,7 @@ struct Item {
       __syncthreads();
     }
   }
+  uint32_t kbase = 0;
   for (uint32_t b0 = 0; b0 < n; b0 += nthr) {
     const uint32_t i = b0 + tl;
     bool has = false;
@@ -713,12 +727,15 @@ struct Item {
         }
       }
     }
-    const u64 m = __ballot(has);
-    if (m != 0ull) {
-      const u64 base = wave_reserve(R.rec_count, (uint32_t)__popcll(m), lane);
-      if (has) store_record(R, K, base + (u64)__popcll(m & ((1ull << lane) - 1ull)), slot, instance, pr, false);
-    }
+    // the round's records in entry (cell-key) order, after the earlier
+    // rounds' (kbase)
+    const uint32_t at = group_reserve(R, has ? 1u : 0u);
+    const uint32_t got = ctl->rec_sum_total;
+    if (has) store_record(R, K, slot_of(at), slot, instance, pr, false, kbase + at);
+    kbase += got;
   }
+  if (R.rank_keys && tl == 0 && kbase)
+    RC_GLOBAL(uint32_t, R.scope_cnt)[((u64)slot << K.bs) | ((u64)gid * K.NI + interval)] = kbase;
   __syncthreads();
   }
 

@@ -38,6 +38,7 @@ struct GatherParams {
   const rc_record_dev* staging;
   const uint32_t* idx;              // sorted order of staged records
   const unsigned long long* n_ptr;  // staged records
+  unsigned long long stage_cap;     // staged record slots
   unsigned long long* out_base;     // records written by earlier chunks (caller's counter)
   rc_record_dev* out;
   unsigned long long cap;
@@ -128,6 +129,14 @@ hipError_t launch_gather(const GatherParams& G, unsigned long long cap, hipStrea
 hipError_t launch_finalize(const FinalParams& F, hipStream_t st);
 hipError_t launch_region_tiles(const uint32_t* counts, uint32_t* tiles, unsigned long long n_regions, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long n, unsigned long long v, hipStream_t st);
+// Record order from rank keys: exclusive scan of the per-(group, interval)
+// counts scope_cnt[table_n] (in place; tmp holds scan_tmp_words(table_n)
+// words), then idx[position] = staging slot for every live slot below
+// min(*n_ptr, cap); a key outside the table or a position past cap sets
+// status bit 1.
+hipError_t order_by_rank(uint32_t* scope_cnt, unsigned long long table_n, uint32_t* tmp, const unsigned long long* keys,
+                      const unsigned long long* n_ptr, unsigned long long cap, uint32_t* idx, uint32_t* status,
+                      hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStream_t st);
 hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st);
 hipError_t launch_rank_keys(const float* scores, uint32_t n, uint32_t idx_bits, unsigned long long* keys,

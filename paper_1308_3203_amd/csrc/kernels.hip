@@ -917,8 +917,13 @@ __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
   bool valid = p < n;
   uint32_t slot = 0;
   bool race = false, benign = false;
+  uint32_t ix = 0;
   if (valid) {
-    const rc_record_dev r = Gp.staging[Gp.idx[p]];
+    ix = Gp.idx[p];
+    valid = ix < Gp.stage_cap;   // (only an overflowed staging leaves a hole)
+  }
+  if (valid) {
+    const rc_record_dev r = Gp.staging[ix];
     const u64 out = *Gp.out_base + p;
     slot = r.instance - Gp.chunks[*Gp.chunk_index].slot0;
     const uint32_t label = r.array_label >> 16;
@@ -1318,6 +1323,32 @@ hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u6
                           uint32_t nbits, uint32_t* hist, hipStream_t st, int* in_second) {
   return sort_pairs_impl<uint32_t>(k0, v0, k1, v1, n_ptr, cap, nbits, nullptr, nullptr, nullptr, 0, hist, 8, st,
                                    in_second);
+}
+
+// Records with rank keys: the record in staging slot p goes to position
+// base[slot << bs | scope] + rank, where base is the exclusive scan of the
+// per-(group, interval) record counts in canonical order.
+__global__ __launch_bounds__(256) void rec_place_kernel(const u64* keys, const u64* n_ptr, u64 cap,
+                                                         const uint32_t* base, u64 table_n, uint32_t* idx,
+                                                         uint32_t* status) {
+  const u64 n = *n_ptr < cap ? *n_ptr : cap;
+  for (u64 p = (u64)blockIdx.x * 256u + threadIdx.x; p < n; p += (u64)gridDim.x * 256u) {
+    const u64 k = keys[p];
+    if (k == ~0ull) continue;   // a reserved slot left unused
+    const u64 t = k >> 32;
+    const u64 f = t < table_n ? (u64)base[t] + (uint32_t)k : cap;
+    if (f < cap) idx[f] = (uint32_t)p;
+    else atomicOr(status, 2u);
+  }
+}
+
+hipError_t order_by_rank(uint32_t* scope_cnt, u64 table_n, uint32_t* tmp, const u64* keys, const u64* n_ptr, u64 cap,
+                      uint32_t* idx, uint32_t* status, hipStream_t st) {
+  scan_excl(scope_cnt, table_n, tmp, st);
+  const uint32_t blocks = (uint32_t)std::min<u64>(blocks_for(cap ? cap : 1, 256), 8192);
+  hipLaunchKernelGGL(rec_place_kernel, dim3(blocks), dim3(256), 0, st, keys, n_ptr, cap, (const uint32_t*)scope_cnt,
+                     table_n, idx, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {

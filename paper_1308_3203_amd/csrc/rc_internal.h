@@ -184,6 +184,13 @@ struct rc_record_out {
   // slots reserved by work-groups in chunks and left unused: their keys
   // are REC_DEAD_KEY (sorted after every record) and they are counted here
   unsigned long long* rec_dead;
+  // rank_keys != 0: every record comes from an interval closed in LDS, and
+  // its key is (slot << bs | scope) << 32 | its rank among the records of
+  // that (group, interval), which are emitted in cell-key order; the
+  // closing work-group stores the count of those records in
+  // scope_cnt[slot << bs | scope].  0: the key is the full canonical key.
+  uint32_t* scope_cnt;
+  uint32_t rank_keys, pad_rk;
 };
 // interpreter work-groups reserve record slots REC_CHUNK at a time; a launch
 // runs at most REC_MAX_BLOCKS blocks per width class, so at most

@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--seeds", type=int, default=None, help="seeds per program (default: the config's)")
-    ap.add_argument("--ws-gb", type=float, default=160.0, help="workspace budget over all programs (HBM is 288 GB)")
+    ap.add_argument("--ws-gb", type=float, default=230.0, help="workspace budget over all programs (HBM is 288 GB)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0: skip)")
     ap.add_argument("--programs", type=int, default=10000, help="c3: number of random programs")
     ap.add_argument("--tune-cache", default=None, help="c3: autotuner cache file (default: a temp file)")

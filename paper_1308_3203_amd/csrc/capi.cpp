@@ -224,6 +224,11 @@ bool lds_logged(const rc_prog* p, uint32_t a) {
   return p->lds_log_cap && p->c.arrays[a].written && !p->owned[a] && (!p->c.arrays[a].global || p->G == 1);
 }
 
+// where an array's accesses are logged
+uint32_t array_logged(const rc_prog* p, uint32_t a) {
+  return !p->c.arrays[a].written || p->owned[a] ? LOG_NONE : (lds_logged(p, a) ? LOG_LDS : LOG_GLOBAL);
+}
+
 // log entries one work-group may write to the global log (0: none, the
 // program's logged accesses all stay in LDS)
 u64 wg_log_need(const rc_prog* p) {
@@ -441,6 +446,12 @@ JitShape jit_shape_of(const rc_prog* p) {
   lds_table(p, &s.tab_base, &s.tab_cells);
   if (!p->lds_log_cap) s.tab_cells = 0;
   s.lds_log_cap = p->lds_log_cap;
+  for (uint32_t i = 0; i < (uint32_t)p->arrays.size(); ++i) {
+    const ArrayDesc& a = p->arrays[i];
+    const uint32_t f[JIT_ARRAY_WORDS] = {a.kind, a.size, array_logged(p, i), a.offset, a.cellbase,
+                                         (uint32_t)a.own_stride, (uint32_t)a.own_lo, a.own_span, a.nosync};
+    s.arrays.insert(s.arrays.end(), f, f + JIT_ARRAY_WORDS);
+  }
   return s;
 }
 
@@ -723,11 +734,7 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
   std::vector<ProgDesc> pd(C.progs.size());
   for (size_t i = 0; i < C.progs.size(); ++i) {
     rc_prog* p = C.progs[i];
-    for (size_t a = 0; a < p->arrays.size(); ++a) {
-      ArrayDesc& d = p->arrays[a];
-      d.logged = !p->c.arrays[a].written || p->owned[a] ? LOG_NONE
-                 : (lds_logged(p, (uint32_t)a) ? LOG_LDS : LOG_GLOBAL);
-    }
+    for (size_t a = 0; a < p->arrays.size(); ++a) p->arrays[a].logged = array_logged(p, (uint32_t)a);
     unsigned char* h = p->h_tables.data();
     memcpy(h, p->arrays.data(), p->arrays.size() * sizeof(ArrayDesc));
     memcpy(h + (p->off_scalars - p->off_arrays), p->scalars.data(), p->scalars.size() * sizeof(ScalarDesc));

@@ -93,6 +93,18 @@ __device__ __forceinline__ T const_load(const void* base, uint32_t i) {
 #endif
 }
 
+// An array's descriptor.  A per-program kernel defines RC_JIT_ARRAYS and
+// jit_array(), which sets the fields fixed by the program and its launch
+// shape to constants the compiler folds (run_items checks them against the
+// descriptors it runs on).
+__device__ __forceinline__ ArrayDesc array_desc(const ArrayDesc* arrays, uint32_t a) {
+  ArrayDesc A = const_load<ArrayDesc>(arrays, a);
+#ifdef RC_JIT_ARRAYS
+  jit_array(a, A);
+#endif
+  return A;
+}
+
 // fault key: dynamic statement | lid | pc | priority | code  (smaller = earlier)
 // priority orders one item's faults inside a statement: DIV, OOB, the rest.
 __device__ __forceinline__ u64 fault_key(uint32_t step, uint32_t lid, uint32_t pc, uint32_t code) {
@@ -671,10 +683,10 @@ struct Item {
       const uint32_t ck = P.tab_base + t;
       uint32_t aid = 0;
       for (uint32_t a = 0; a < P.n_arrays; ++a) {
-        const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
+        const ArrayDesc D = array_desc(P.arrays, a);
         if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
       }
-      const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
+      const ArrayDesc D = array_desc(P.arrays, aid);
       pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = ck - D.cellbase;
       pr.cellkey = ck; pr.lidbase = gid * P.W;
       store_record(R, K, slot_of(at), slot, instance, pr, false, at);
@@ -717,10 +729,10 @@ struct Item {
           if (has) {
             uint32_t aid = 0;
             for (uint32_t a = 0; a < P.n_arrays; ++a) {
-              const ArrayDesc D = const_load<ArrayDesc>(P.arrays, a);
+              const ArrayDesc D = array_desc(P.arrays, a);
               if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
             }
-            const ArrayDesc D = const_load<ArrayDesc>(P.arrays, aid);
+            const ArrayDesc D = array_desc(P.arrays, aid);
             pr.gid = gid; pr.interval = interval; pr.aid = aid; pr.cell = (uint32_t)ck - D.cellbase;
             pr.cellkey = (uint32_t)ck; pr.lidbase = gid * P.W;
           }
@@ -747,7 +759,7 @@ struct Item {
   template <int KIND = -1>
   __device__ __forceinline__ bool mem(uint32_t op, uint32_t wc, int32_t idx, int32_t val, bool active,
                                       uint32_t spc, int32_t& out) {
-    ArrayDesc A = const_load<ArrayDesc>(P.arrays, wc);
+    ArrayDesc A = array_desc(P.arrays, wc);
     if (KIND >= 0) A.kind = (uint32_t)KIND;
     if (KIND == (int)AK_GLOBAL_RO) A.logged = LOG_NONE;   // never written, never logged
     if (!A.nosync && active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);   // (nosync: in bounds)
@@ -964,8 +976,16 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     // replace the descriptor's fields, so the compiler folds them.  A
     // descriptor of another shape is a library error, reported through the
     // status word; the item is skipped.
+    bool same_arrays = true;
+#pragma unroll
+    for (uint32_t a = 0; a < RC_JIT_NA; ++a) {
+      const ArrayDesc X = const_load<ArrayDesc>(D.arrays, a), Y = array_desc(D.arrays, a);
+      same_arrays = same_arrays && X.kind == Y.kind && X.size == Y.size && X.logged == Y.logged &&
+                    X.offset == Y.offset && X.cellbase == Y.cellbase && X.own_stride == Y.own_stride &&
+                    X.own_lo == Y.own_lo && X.own_span == Y.own_span && X.nosync == Y.nosync;
+    }
     if (D.W != RC_JIT_W || D.G != RC_JIT_G || D.n_arrays != RC_JIT_NA || D.tab_cells != RC_JIT_TC ||
-        D.tab_base != RC_JIT_TB || D.lds_log_cap != RC_JIT_LC) {
+        D.tab_base != RC_JIT_TB || D.lds_log_cap != RC_JIT_LC || !same_arrays) {
       if (threadIdx.x == 0) {
         atomicOr(PP.status_word, 8u);
         PP.wg_count[S.wg_base + gid] = 0u;   // nothing logged

@@ -52,6 +52,19 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
            "#define RC_JIT_TC %uu\n#define RC_JIT_LC %uu\n",
            shape.W, shape.G, shape.n_arrays, shape.tab_base, shape.tab_cells, shape.lds_log_cap);
   s += buf;
+  // the arrays' descriptor fields the shape fixes
+  s += "#define RC_JIT_ARRAYS 1\n#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n"
+       "#include \"rc_internal.h\"\n\nnamespace rc {\n\n"
+       "__device__ __forceinline__ void jit_array(uint32_t a, ArrayDesc& A) {\n  switch (a) {\n";
+  for (uint32_t a = 0; a < shape.n_arrays && (a + 1) * JIT_ARRAY_WORDS <= shape.arrays.size(); ++a) {
+    const uint32_t* f = &shape.arrays[a * JIT_ARRAY_WORDS];
+    snprintf(buf, sizeof buf,
+             "    case %uu: A.kind = %uu; A.size = %uu; A.logged = %uu; A.offset = %uu; A.cellbase = %uu;\n"
+             "      A.own_stride = %d; A.own_lo = %d; A.own_span = %uu; A.nosync = %uu; break;\n",
+             a, f[0], f[1], f[2], f[3], f[4], (int32_t)f[5], (int32_t)f[6], f[7], f[8]);
+    s += buf;
+  }
+  s += "    default: break;\n  }\n}\n\n}  // namespace rc\n\n";
   s += "#include \"item_rt.h\"\n\nnamespace {\n\n__device__ __forceinline__ void jit_item(rc::Item& it) {\n";
   s += "  using namespace rc;\n";
   for (uint32_t r = 0; r < nregs; ++r) {

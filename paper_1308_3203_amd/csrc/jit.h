@@ -13,11 +13,16 @@ namespace rc {
 // table's first cell key and size, the log's capacity in entries).  The
 // kernel folds them as constants; a program whose shape or tuning changes
 // needs another kernel.
+// arrays: per array the descriptor fields that the program and the shape
+// fix (kind, size, logged, offset, cellbase, own_stride, own_lo, own_span,
+// nosync; JIT_ARRAY_WORDS words each).
+constexpr uint32_t JIT_ARRAY_WORDS = 9;
 struct JitShape {
   uint32_t W = 0, G = 0, n_arrays = 0, tab_base = 0, tab_cells = 0, lds_log_cap = 0;
+  std::vector<uint32_t> arrays;
   bool operator==(const JitShape& o) const {
     return W == o.W && G == o.G && n_arrays == o.n_arrays && tab_base == o.tab_base && tab_cells == o.tab_cells &&
-           lds_log_cap == o.lds_log_cap;
+           lds_log_cap == o.lds_log_cap && arrays == o.arrays;
   }
 };
 

@@ -299,7 +299,7 @@ struct Layout {
   // records placed by rank (no global log, so every record comes from an
   // interval closed in LDS): per-(slot, scope) record counts and the scan's
   // partial sums
-  bool rank = false;
+  bool rank = false, lds_only = false;
   u64 scope_n = 0;
   size_t scope_cnt = 0, scope_tmp = 0;
   // per-(slot, cell) owner words of the global log (cc_stride cells per
@@ -346,14 +346,14 @@ void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n
   L->longq = take(L->long_cap * 16);
   L->cc = take(L->filter ? (size_t)L->max_slots * L->cc_stride * 4 : 0);
   // (placing records by rank needs no record sort: no second key buffer,
-  // no first index buffer, no sort histogram)
+  // no index buffers, no sort histogram)
   const u64 sorted_rec = L->rank ? 0 : L->max_rec;
   L->hist = take(std::max(sort_log_hist_words(L->max_wg, L->max_log), sorted_rec ? sort_hist_words(sorted_rec) : 0) * 4);
   L->stage = take(L->max_rec * sizeof(rc_record));
   L->rk0 = take(L->max_rec * 8);
   L->ri0 = take(sorted_rec * 4);
   L->rk1 = take(sorted_rec * 8);
-  L->ri1 = take(L->max_rec * 4);
+  L->ri1 = take(sorted_rec * 4);
   L->scope_cnt = take(L->scope_n * 4);
   L->scope_tmp = take(L->rank ? scan_tmp_words(L->scope_n) * 4 : 0);
   L->total = o;
@@ -540,6 +540,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     // and its rank, and the records need no sort.
     L.rank = C.record_sort == 0 && lds_only && L.bi + bs <= 32 && ((u64)L.max_slots << bs) <= (1ull << 26);
     L.scope_n = L.rank ? (u64)L.max_slots << bs : 0;
+    L.lds_only = lds_only;
     Layout lim = L;
     partition(C, lim);
     lay_out(&L, C.progs.size(), N, C.chunks.size(), C.items.size() / 2);
@@ -627,7 +628,9 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
   if (!do_log) return RC_OK;
   int second = 0;
   u64 *lk0 = (u64*)(ws + L.lk0), *lv0 = (u64*)(ws + L.lv0), *lk1 = (u64*)(ws + L.lk1), *lv1 = (u64*)(ws + L.lv1);
-  {
+  // (a call whose programs keep every logged access in LDS has an empty
+  // global log: no log sort, no global pass)
+  if (!L.lds_only) {
     PhaseTimer t(ctx, st, 1, timed);
     // Each work-group's log region holds one (instance, group) in execution
     // (so interval) order; a stable sort above the group and interval fields
@@ -638,7 +641,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
                      (const u64*)(ws + L.wg_base), (uint32_t*)(ws + L.tiles), L.max_wg, (uint32_t*)(ws + L.hist),
                      C.radix_bits, st, &second, L.filter ? (const uint32_t*)(ws + L.cc) : nullptr, L.cc_stride, L.bc, L.bk));
   }
-  {
+  if (!L.lds_only) {
     PhaseTimer t(ctx, st, 2, timed);
     SegParams S;
     memset(&S, 0, sizeof S);
@@ -662,10 +665,8 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
   {
     PhaseTimer t(ctx, st, 3, timed);
     if (L.rank) {
-      HIP_TRY(order_by_rank((uint32_t*)(ws + L.scope_cnt), L.scope_n, (uint32_t*)(ws + L.scope_tmp),
-                            (const u64*)(ws + L.rk0), cnt + CNT_REC, L.max_rec, (uint32_t*)(ws + L.ri1),
-                            (uint32_t*)(cnt + CNT_STATUS), st));
-      rsecond = 1;
+      // each (slot, scope)'s first output position
+      HIP_TRY(scan_counts((uint32_t*)(ws + L.scope_cnt), L.scope_n, (uint32_t*)(ws + L.scope_tmp), st));
     } else {
       HIP_TRY(sort_pairs_u32((u64*)(ws + L.rk0), (uint32_t*)(ws + L.ri0), (u64*)(ws + L.rk1),
                              (uint32_t*)(ws + L.ri1), cnt + CNT_REC, L.max_rec, L.nbits_rec,
@@ -687,7 +688,16 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     Gp.inst_flags = (uint32_t*)(ws + L.inst_flags);
     Gp.inst_race = (uint32_t*)(ws + L.inst_race);
     Gp.inst_benign = (uint32_t*)(ws + L.inst_benign);
-    HIP_TRY(launch_gather(Gp, L.max_rec, st));
+    if (L.rank) {
+      Gp.keys = (const u64*)(ws + L.rk0);
+      Gp.reserved = cnt + CNT_REC;
+      Gp.scope_base = (const uint32_t*)(ws + L.scope_cnt);
+      Gp.table_n = L.scope_n;
+      Gp.status_word = (uint32_t*)(cnt + CNT_STATUS);
+      HIP_TRY(launch_place_out(Gp, L.max_rec, st));
+    } else {
+      HIP_TRY(launch_gather(Gp, L.max_rec, st));
+    }
     FinalParams F;
     memset(&F, 0, sizeof F);
     F.progs = progs; F.slots = slots; F.chunks = chunks; F.chunk_index = chunk_index;

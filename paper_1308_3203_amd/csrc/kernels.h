@@ -47,6 +47,13 @@ struct GatherParams {
   uint32_t* inst_flags;
   uint32_t* inst_race;
   uint32_t* inst_benign;
+  // records placed by rank (launch_place_out): the staged slots' keys,
+  // their count (reserved slots) and the scanned per-(slot, scope) counts
+  const unsigned long long* keys;
+  const unsigned long long* reserved;
+  const uint32_t* scope_base;
+  unsigned long long table_n;
+  uint32_t* status_word;
 };
 
 struct FinalParams {
@@ -129,14 +136,14 @@ hipError_t launch_gather(const GatherParams& G, unsigned long long cap, hipStrea
 hipError_t launch_finalize(const FinalParams& F, hipStream_t st);
 hipError_t launch_region_tiles(const uint32_t* counts, uint32_t* tiles, unsigned long long n_regions, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long n, unsigned long long v, hipStream_t st);
-// Record order from rank keys: exclusive scan of the per-(group, interval)
-// counts scope_cnt[table_n] (in place; tmp holds scan_tmp_words(table_n)
-// words), then idx[position] = staging slot for every live slot below
-// min(*n_ptr, cap); a key outside the table or a position past cap sets
+// exclusive scan in place of counts[n]; tmp holds scan_tmp_words(n) words
+hipError_t scan_counts(uint32_t* counts, unsigned long long n, uint32_t* tmp, hipStream_t st);
+// Records with rank keys, in one pass over the staged slots: each live
+// record goes straight to its output position (the scanned count of its
+// (slot, scope) plus its rank), with the per-instance race and benign
+// counts; a key outside the table or a position past the staging sets
 // status bit 1.
-hipError_t order_by_rank(uint32_t* scope_cnt, unsigned long long table_n, uint32_t* tmp, const unsigned long long* keys,
-                      const unsigned long long* n_ptr, unsigned long long cap, uint32_t* idx, uint32_t* status,
-                      hipStream_t st);
+hipError_t launch_place_out(const GatherParams& G, unsigned long long stage_cap, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, unsigned long long n, uint32_t v, hipStream_t st);
 hipError_t launch_final_merge(const FinalMemParams& M, hipStream_t st);
 hipError_t launch_rank_keys(const float* scores, uint32_t n, uint32_t idx_bits, unsigned long long* keys,

@@ -949,6 +949,53 @@ __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
 }
 
 
+__global__ __launch_bounds__(256) void rec_place_out_kernel(GatherParams Gp) {
+  const u64 n = *Gp.reserved < Gp.stage_cap ? *Gp.reserved : Gp.stage_cap;
+  const u64 out0 = *Gp.out_base;
+  const uint32_t slot0 = Gp.chunks[*Gp.chunk_index].slot0;
+  const uint32_t lane = threadIdx.x & 63u;
+  for (u64 base = (u64)blockIdx.x * 256u; base < n; base += (u64)gridDim.x * 256u) {
+    const u64 p = base + threadIdx.x;
+    bool valid = false;
+    uint32_t slot = 0;
+    bool race = false, benign = false;
+    if (p < n) {
+      const u64 k = Gp.keys[p];
+      if (k != ~0ull) {   // (not a reserved slot left unused)
+        const u64 t = k >> 32;
+        const u64 f = t < Gp.table_n ? (u64)Gp.scope_base[t] + (uint32_t)k : Gp.stage_cap;
+        if (f < Gp.stage_cap) {
+          valid = true;
+          const rc_record_dev r = Gp.staging[p];
+          slot = r.instance - slot0;
+          const uint32_t label = r.array_label >> 16;
+          race = (label & 3u) != 0u;
+          benign = label == 4u;
+          const u64 out = out0 + f;
+          if (out < Gp.cap) Gp.out[out] = r;
+          else atomicOr(&Gp.inst_flags[slot], 1u);
+        } else {
+          atomicOr(Gp.status_word, 2u);
+        }
+      }
+    }
+    // per-instance counts: one atomic per instance the wave holds (staged
+    // slots come in chunks, so a wave spans few instances)
+    u64 rem = __ballot(valid);
+    const u64 rm = __ballot(race), bm = __ballot(benign);
+    while (rem != 0ull) {
+      const uint32_t s0 = (uint32_t)__shfl((int)slot, (int)__builtin_ctzll(rem));
+      const u64 m = __ballot(valid && slot == s0);
+      const uint32_t nr = (uint32_t)__popcll(rm & m), nb = (uint32_t)__popcll(bm & m);
+      if (lane == 0) {
+        if (nr) atomicAdd(&Gp.inst_race[s0], nr);
+        if (nb) atomicAdd(&Gp.inst_benign[s0], nb);
+      }
+      rem &= ~m;
+    }
+  }
+}
+
 // entries past a buffer's capacity were dropped (and flagged): later kernels
 // see at most `cap`
 __global__ void live_count_kernel(const u64* reserved, const u64* unused, u64* live) {
@@ -1325,29 +1372,8 @@ hipError_t sort_pairs_u32(u64* k0, uint32_t* v0, u64* k1, uint32_t* v1, const u6
                                    in_second);
 }
 
-// Records with rank keys: the record in staging slot p goes to position
-// base[slot << bs | scope] + rank, where base is the exclusive scan of the
-// per-(group, interval) record counts in canonical order.
-__global__ __launch_bounds__(256) void rec_place_kernel(const u64* keys, const u64* n_ptr, u64 cap,
-                                                         const uint32_t* base, u64 table_n, uint32_t* idx,
-                                                         uint32_t* status) {
-  const u64 n = *n_ptr < cap ? *n_ptr : cap;
-  for (u64 p = (u64)blockIdx.x * 256u + threadIdx.x; p < n; p += (u64)gridDim.x * 256u) {
-    const u64 k = keys[p];
-    if (k == ~0ull) continue;   // a reserved slot left unused
-    const u64 t = k >> 32;
-    const u64 f = t < table_n ? (u64)base[t] + (uint32_t)k : cap;
-    if (f < cap) idx[f] = (uint32_t)p;
-    else atomicOr(status, 2u);
-  }
-}
-
-hipError_t order_by_rank(uint32_t* scope_cnt, u64 table_n, uint32_t* tmp, const u64* keys, const u64* n_ptr, u64 cap,
-                      uint32_t* idx, uint32_t* status, hipStream_t st) {
-  scan_excl(scope_cnt, table_n, tmp, st);
-  const uint32_t blocks = (uint32_t)std::min<u64>(blocks_for(cap ? cap : 1, 256), 8192);
-  hipLaunchKernelGGL(rec_place_kernel, dim3(blocks), dim3(256), 0, st, keys, n_ptr, cap, (const uint32_t*)scope_cnt,
-                     table_n, idx, status);
+hipError_t scan_counts(uint32_t* counts, u64 n, uint32_t* tmp, hipStream_t st) {
+  scan_excl(counts, n, tmp, st);
   return hipGetLastError();
 }
 
@@ -1365,6 +1391,12 @@ hipError_t launch_gather(const GatherParams& G, u64 cap, hipStream_t st) {
                      dim3(256), 0, st, G);
   return hipGetLastError();
 }
+hipError_t launch_place_out(const GatherParams& G, u64 stage_cap, hipStream_t st) {
+  hipLaunchKernelGGL(rec_place_out_kernel, dim3((uint32_t)std::min<u64>(blocks_for(stage_cap ? stage_cap : 1, 256), 8192)),
+                     dim3(256), 0, st, G);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const FinalParams& F, hipStream_t st) {
   hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(std::max<u64>(F.max_slots, 1), 256)), dim3(256), 0, st, F);
   return hipGetLastError();

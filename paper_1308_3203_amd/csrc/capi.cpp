@@ -229,15 +229,18 @@ uint32_t array_logged(const rc_prog* p, uint32_t a) {
   return !p->c.arrays[a].written || p->owned[a] ? LOG_NONE : (lds_logged(p, a) ? LOG_LDS : LOG_GLOBAL);
 }
 
+// an interval's LDS-logged accesses may outgrow the LDS log (static bound)
+bool lds_may_spill(const rc_prog* p) {
+  const double ib = p->G == 1 ? p->c.interval_logged_all : p->c.interval_logged_local;
+  return p->lds_log_cap && (double)p->W * ib > (double)p->lds_log_cap;
+}
+
 // log entries one work-group may write to the global log (0: none, the
 // program's logged accesses all stay in LDS)
 u64 wg_log_need(const rc_prog* p) {
-  const Compiled& c = p->c;
   const u64 lds = p->lds_log_cap ? p->logged_local + (p->G == 1 ? p->logged_mem - p->logged_local : 0) : 0;
   const u64 glob = p->logged_mem - lds;
-  const double ib = p->G == 1 ? c.interval_logged_all : c.interval_logged_local;
-  const bool spill = p->lds_log_cap && (double)p->W * ib > (double)p->lds_log_cap;
-  return (u64)p->W * (glob + (spill ? lds : 0));
+  return (u64)p->W * (glob + (lds_may_spill(p) ? lds : 0));
 }
 
 // the same, at least one entry (the global log's buffers are never empty)
@@ -446,6 +449,7 @@ JitShape jit_shape_of(const rc_prog* p) {
   lds_table(p, &s.tab_base, &s.tab_cells);
   if (!p->lds_log_cap) s.tab_cells = 0;
   s.lds_log_cap = p->lds_log_cap;
+  s.nospill = p->lds_log_cap && !lds_may_spill(p) ? 1u : 0u;
   for (uint32_t i = 0; i < (uint32_t)p->arrays.size(); ++i) {
     const ArrayDesc& a = p->arrays[i];
     const uint32_t f[JIT_ARRAY_WORDS] = {a.kind, a.size, array_logged(p, i), a.offset, a.cellbase,

@@ -816,8 +816,15 @@ struct Item {
       }
     }
     if (total != 0u) {
+#ifdef RC_JIT_NOSPILL
+      // (a per-program kernel of a program whose intervals always fit the
+      // LDS log: the log never moves to the global log)
+      bool to_lds = A.logged == LOG_LDS;
+      if (false) {
+#else
       bool to_lds = A.logged == LOG_LDS && !lds_spilled;
       if (to_lds && lds_used + total > P.lds_log_cap) {
+#endif
         // the interval outgrows LDS: move its log to the global log, where
         // the global pass checks it
         for (uint32_t i = tl; i < lds_used; i += nthr) {

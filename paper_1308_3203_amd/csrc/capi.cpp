@@ -94,6 +94,7 @@ struct rc_prog {
   uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t record_sort = 0;          // tuning: 1 = always sort records by their full key
+  bool never_faults = false;         // proven for the current shape
   uint32_t lds_log_cap = 0;          // chosen for the current shape
   // arrays no two work-items share under the current shape (never logged),
   // and the per-item access bounds on the arrays that are logged
@@ -450,6 +451,7 @@ JitShape jit_shape_of(const rc_prog* p) {
   if (!p->lds_log_cap) s.tab_cells = 0;
   s.lds_log_cap = p->lds_log_cap;
   s.nospill = p->lds_log_cap && !lds_may_spill(p) ? 1u : 0u;
+  s.nofault = p->never_faults ? 1u : 0u;
   for (uint32_t i = 0; i < (uint32_t)p->arrays.size(); ++i) {
     const ArrayDesc& a = p->arrays[i];
     const uint32_t f[JIT_ARRAY_WORDS] = {a.kind, a.size, array_logged(p, i), a.offset, a.cellbase,
@@ -1133,6 +1135,7 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
     }
   }
   p->overlay_cells = ov;
+  p->never_faults = proof.never_faults;
   for (size_t a = 0; a < own.size(); ++a) {
     ArrayDesc& d = p->arrays[a];
     d.nosync = proof.never_faults && (d.kind == AK_GLOBAL_RO || own[a].owned) ? 1u : 0u;
@@ -1469,6 +1472,9 @@ rc_status rc_sync(rc_ctx* ctx) {
     } else if (status & 8u) {
       result = RC_E_HIP;
       msg = "internal error: a per-program kernel ran on a program of another launch shape";
+    } else if (status & 16u) {
+      result = RC_E_HIP;
+      msg = "internal error: a program proven never to fault faulted";
     } else if (status != 0u) {
       result = RC_E_HIP;
       msg = "internal capacity exceeded (access log or record staging)";

@@ -494,7 +494,7 @@ struct Item {
   // a buffer after the next reduction's barrier, which every reader passes
   // after reading.
   __device__ __forceinline__ uint32_t group_red(bool p0, bool p1, bool sync_always) {
-    const u64 b0 = __ballot(p0), b1 = __ballot(p1), bf = __ballot(my_fault != ~0ull);
+    const u64 b0 = __ballot(p0), b1 = __ballot(p1), bf = __ballot(fault_pending());
     const uint32_t mine = (b0 != 0ull ? 1u : 0u) | (b1 != 0ull ? 2u : 0u) | (bf != 0ull ? 4u : 0u);
     if (P.nwaves == 1) {
       if (sync_always) __syncthreads();
@@ -505,15 +505,19 @@ struct Item {
     // lane w reads wave w's word: one LDS round trip whatever the width
     const uint32_t x = lane < P.nwaves ? ctl->red[parity][lane] : 0u;
     parity ^= 1u;
+#ifdef RC_JIT_NOFAULT
+    return (__ballot(x & 1u) != 0ull ? 1u : 0u) | (__ballot(x & 2u) != 0ull ? 2u : 0u);
+#else
     return (__ballot(x & 1u) != 0ull ? 1u : 0u) | (__ballot(x & 2u) != 0ull ? 2u : 0u) |
            (__ballot(x & 4u) != 0ull ? 4u : 0u);
+#endif
   }
 
   // The same snapshot reduction for a memory statement: bit 0 of each wave's
   // word is its pending-fault flag, bits 8.. its count of log entries; every
   // wave gets the group total and the count of the waves before it.
   __device__ __forceinline__ bool mem_red(bool rec, u64* brec, uint32_t* prefix, uint32_t* total) {
-    const u64 br = __ballot(rec), bf = __ballot(my_fault != ~0ull);
+    const u64 br = __ballot(rec), bf = __ballot(fault_pending());
     *brec = br;
     const uint32_t cnt = (uint32_t)__popcll(br);
     if (P.nwaves == 1) {
@@ -541,9 +545,25 @@ struct Item {
     return __ballot(x & 1u) != 0ull;
   }
 
+  // A per-program kernel of a program proven never to fault (RC_JIT_NOFAULT)
+  // has no fault to agree on: a fault there means the proof is wrong, and
+  // it is reported as a library error (status bit 4) instead.
+  __device__ __forceinline__ bool fault_pending() const {
+#ifdef RC_JIT_NOFAULT
+    return false;
+#else
+    return my_fault != ~0ull;
+#endif
+  }
   __device__ __forceinline__ void raise(uint32_t spc, uint32_t code) {
+#ifdef RC_JIT_NOFAULT
+    (void)spc;
+    (void)code;
+    atomicOr(P.status_word, 16u);
+#else
     const u64 k = fault_key(step, tl, spc, code);
     if (k < my_fault) my_fault = k;
+#endif
   }
 
   // The record of a table cell, if its accesses form one (labels and pairs
@@ -762,7 +782,14 @@ struct Item {
     ArrayDesc A = array_desc(P.arrays, wc);
     if (KIND >= 0) A.kind = (uint32_t)KIND;
     if (KIND == (int)AK_GLOBAL_RO) A.logged = LOG_NONE;   // never written, never logged
+#ifdef RC_JIT_NOFAULT
+    if (active && (idx < 0 || (uint32_t)idx >= A.size)) {   // (reported; the access is dropped)
+      raise(spc, F_OOB);
+      active = false;
+    }
+#else
     if (!A.nosync && active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);   // (nosync: in bounds)
+#endif
     const bool rec = active && P.do_log && A.logged != LOG_NONE;
     // the barrier completes every earlier statement's accesses, publishes
     // pending faults (a faulting statement has no effect) and each wave's

@@ -53,6 +53,7 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
            shape.W, shape.G, shape.n_arrays, shape.tab_base, shape.tab_cells, shape.lds_log_cap);
   s += buf;
   if (shape.nospill) s += "#define RC_JIT_NOSPILL 1\n";
+  if (shape.nofault) s += "#define RC_JIT_NOFAULT 1\n";
   // the arrays' descriptor fields the shape fixes
   s += "#define RC_JIT_ARRAYS 1\n#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n"
        "#include \"rc_internal.h\"\n\nnamespace rc {\n\n"

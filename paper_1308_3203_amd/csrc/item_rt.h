@@ -454,7 +454,10 @@ struct Item {
     for (uint32_t i = tl; i < P.lds_local_cells; i += nthr) locc[i] = 0ull;
     for (uint32_t i = tl; i < P.nregs * WP; i += nthr) regs[i] = 0;
     for (uint32_t i = tl; i < P.tab_cells; i += nthr) tab[i] = empty_cell;
-    if (tl == 0) ctl->fault = ~0ull;
+    if (tl == 0) {
+      ctl->fault = ~0ull;
+      ctl->lds_cnt[0] = ctl->lds_cnt[1] = 0u;
+    }
     if (tl < P.n_scalars) {
       const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
       ctl->scal[tl] = S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
@@ -636,7 +639,16 @@ struct Item {
   // the INTRA scope.  Callers have passed a barrier since the interval's last
   // access.
   __device__ __forceinline__ void close_interval() {
+#ifdef RC_JIT_ELIDE
+    // the interval's entries, from its LDS counter; the next interval's
+    // counter was last read at the previous close, before the barrier
+    // every thread passed to get here
+    const uint32_t n = uni(ctl->lds_cnt[interval & 1u]);
+    if (tl == 0) ctl->lds_cnt[(interval + 1u) & 1u] = 0u;
+    __syncthreads();
+#else
     const uint32_t n = lds_used;
+#endif
   const bool spilled = lds_spilled;
   lds_used = 0;
   lds_spilled = false;
@@ -776,7 +788,12 @@ struct Item {
   // when the group stops on a fault (the statement then has no effect).
   // KIND >= 0: the array's kind (AK_*) known when the caller is compiled,
   // so only its path is generated; -1: read from the descriptor.
-  template <int KIND = -1>
+  // SYNC == false (per-program kernels with RC_JIT_ELIDE only): the
+  // statement needs no group step, because no access since the group's last
+  // synchronisation conflicts with it (a load after a store of the array, or
+  // a store after a load); faults cannot occur and LDS log entries are
+  // numbered by an LDS counter.
+  template <int KIND = -1, bool SYNC = true>
   __device__ __forceinline__ bool mem(uint32_t op, uint32_t wc, int32_t idx, int32_t val, bool active,
                                       uint32_t spc, int32_t& out) {
     ArrayDesc A = array_desc(P.arrays, wc);
@@ -797,7 +814,7 @@ struct Item {
     // of that
     u64 brec = 0;
     uint32_t prefix = 0, total = 0;
-    if (!A.nosync && mem_red(rec, &brec, &prefix, &total)) return true;
+    if (!A.nosync && SYNC && mem_red(rec, &brec, &prefix, &total)) return true;
     const uint32_t cell = (uint32_t)idx;
     // overlay word of the cell: by cell, or for an owned array by (offset
     // from the work-item's stride, lid), which keeps a wave's words together
@@ -842,6 +859,29 @@ struct Item {
         ++n_acc;
       }
     }
+#ifdef RC_JIT_ELIDE
+    if (A.logged == LOG_LDS) {
+      const u64 br = __ballot(rec);
+      if (br != 0ull) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&ctl->lds_cnt[interval & 1u], (uint32_t)__popcll(br));
+        base = (uint32_t)__shfl((int)base, 0);
+        if (rec) {
+          const uint32_t j = base + (uint32_t)__popcll(br & ((1ull << lane) - 1ull));
+          if (j >= P.lds_log_cap) {
+            atomicOr(P.status_word, 16u);   // (the static interval bound does not hold)
+          } else if (P.tab_cells) {
+            lkey[j] = tab_entry(A.cellbase + cell - P.tab_base, op == OP_STORE, tl, val);
+          } else {
+            lkey[j] = ((u64)(A.cellbase + cell) << 16) | j;
+            lmeta[j] = ((op == OP_STORE) ? 1024u : 0u) | tl;
+            lval[j] = val;
+          }
+        }
+      }
+      return false;
+    }
+#endif
     if (total != 0u) {
 #ifdef RC_JIT_NOSPILL
       // (a per-program kernel of a program whose intervals always fit the

@@ -9,7 +9,9 @@
 
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cstdio>
+#include <map>
 #include <set>
 #include <string>
 #include <vector>
@@ -28,6 +30,60 @@ std::string operand(bool imm, uint32_t w) {
   else if (w < MAX_REGS) snprintf(buf, sizeof buf, "R%u", w);
   else snprintf(buf, sizeof buf, "it.special(%uu)", w);
   return buf;
+}
+
+// The memory statements that keep their group step when the kernel elides
+// the others (RC_JIT_ELIDE: the program cannot fault and its intervals fit
+// the LDS log).  A step is kept where an access since the group's last
+// synchronisation conflicts with the statement's: a load of an array stored
+// to, or a store to an array loaded (stores of one cell are ordered by their
+// version words).  Barriers and branch votes synchronise the group, and so
+// does a kept step; the statements of a loop body also follow the body's
+// own end.  Arrays whose accesses never take the step (read-only or owned)
+// cannot conflict; statements on an array logged to the global log keep the
+// step, which numbers its entries.
+std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitShape& shape) {
+  const uint32_t n = (uint32_t)(code.size() / 4), na = shape.n_arrays;
+  std::vector<uint8_t> keep(n, 0);
+  auto field = [&](uint32_t a, uint32_t f) { return shape.arrays[a * JIT_ARRAY_WORDS + f]; };
+  std::map<uint32_t, std::vector<uint8_t>> back;   // first body instruction -> accesses at the body's end
+  for (bool changed = true; changed;) {
+    changed = false;
+    std::vector<uint8_t> S(na, 0);   // per array: bit 0 loaded, bit 1 stored since the last synchronisation
+    for (uint32_t i = 0; i < n; ++i) {
+      const auto b = back.find(i);
+      if (b != back.end())
+        for (uint32_t a = 0; a < na; ++a) S[a] |= b->second[a];
+      const uint32_t h = code[4 * i], op = h & 63u, wc = code[4 * i + 3];
+      if (op == OP_LOAD || op == OP_STORE) {
+        if (wc >= na || (wc + 1) * JIT_ARRAY_WORDS > shape.arrays.size()) {
+          keep[i] = 1;
+          std::fill(S.begin(), S.end(), 0);
+          continue;
+        }
+        if (field(wc, 8)) continue;   // nosync
+        const uint8_t bit = op == OP_LOAD ? 1 : 2, other = op == OP_LOAD ? 2 : 1;
+        if ((field(wc, 2) == LOG_GLOBAL || (S[wc] & other)) && !keep[i]) {
+          keep[i] = 1;
+          changed = true;
+        }
+        if (keep[i]) std::fill(S.begin(), S.end(), 0);
+        S[wc] |= bit;
+      } else if (op == OP_IF || op == OP_BARRIER) {
+        std::fill(S.begin(), S.end(), 0);
+      } else if (op == OP_ENDFOR) {
+        std::vector<uint8_t>& e = back[wc];
+        if (e.empty()) e.assign(na, 0);
+        for (uint32_t a = 0; a < na; ++a) {
+          if ((e[a] | S[a]) != e[a]) {
+            e[a] |= S[a];
+            changed = true;
+          }
+        }
+      }
+    }
+  }
+  return keep;
 }
 
 }  // namespace
@@ -54,6 +110,9 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
   s += buf;
   if (shape.nospill) s += "#define RC_JIT_NOSPILL 1\n";
   if (shape.nofault) s += "#define RC_JIT_NOFAULT 1\n";
+  const bool elide = shape.nofault && shape.nospill;
+  if (elide) s += "#define RC_JIT_ELIDE 1\n";
+  const std::vector<uint8_t> keep = elide ? group_steps(code, shape) : std::vector<uint8_t>(n, 1);
   // the arrays' descriptor fields the shape fixes
   s += "#define RC_JIT_ARRAYS 1\n#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n"
        "#include \"rc_internal.h\"\n\nnamespace rc {\n\n"
@@ -113,8 +172,8 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
         const std::string val = op == OP_STORE ? operand(fb, wb) : std::string("0");
         const int kind = wc < array_kind.size() ? (int)array_kind[wc] : -1;
         snprintf(buf, sizeof buf,
-                 "  { int32_t v = 0; if (it.mem<%d>(%uu, %uu, %s, %s, %s, %uu, v)) { it.faulted = true; goto Ldone; }",
-                 kind, op, wc, operand(fa, wa).c_str(), val.c_str(), act, spc);
+                 "  { int32_t v = 0; if (it.mem<%d, %s>(%uu, %uu, %s, %s, %s, %uu, v)) { it.faulted = true; goto Ldone; }",
+                 kind, keep[i] ? "true" : "false", op, wc, operand(fa, wa).c_str(), val.c_str(), act, spc);
         s += buf;
         if (op == OP_LOAD) {
           snprintf(buf, sizeof buf, " if (%s) R%u = v;", act, dst);

@@ -211,6 +211,8 @@ struct Ctl {
   uint32_t loopctr[MAX_WAVES][MAX_NEST];
   uint32_t item;                        // work item taken by the group
   uint32_t pad;
+  uint32_t lds_cnt[2];                  // LDS log entries of the even / odd intervals
+                                        // (per-program kernels with elided group steps)
 };
 
 constexpr uint32_t LDS_LIMIT = 160u * 1024u;

@@ -108,3 +108,29 @@ def test_jit_follows_shape_and_tuning():
         n = int(buf.n_records.item())
         g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 3))
         U.assert_same(g, U.oracle_run(w.src, G, w.W, w.arrays, w.scalars, 7, 3), f"G={G} T={T}")
+
+
+ELIDE = [
+    # a load at the loop's start after a store at its end (the back edge)
+    "  L[lid] := lid;\n  barrier;\n  for k in 0..4 {\n    v := L[(lid + 64) % 256];\n    L[lid] := v + k;\n  }\n",
+    # a store after a load of the same array, in straight-line code
+    "  L[lid] := lid;\n  barrier;\n  v := L[(lid + 64) % 256];\n  L[lid] := v;\n  v := L[(lid + 128) % 256];\n"
+    "  L[lid] := v + 1;\n",
+    # the same across a branch (its vote synchronises the group)
+    "  L[lid] := lid;\n  barrier;\n  for k in 0..3 {\n    if (lid < 128) {\n      v := L[lid + 128];\n    }\n"
+    "    L[lid] := v + 1;\n  }\n",
+    # stores only between synchronisations, then loads only
+    "  for k in 0..4 {\n    L[(lid * 3 + k) % 256] := lid + k;\n  }\n  barrier;\n  for k in 0..4 {\n"
+    "    v := L[(lid + k * 64) % 256];\n    A[lid] := v;\n  }\n",
+]
+
+
+@pytest.mark.parametrize("body", ELIDE)
+def test_elided_group_steps(body):
+    """Never-faulting programs whose intervals fit LDS run with most group
+    steps elided; the steps kept for conflicting accesses (including across
+    a loop's back edge) keep the results the oracle's, over four waves."""
+    src = f"kernel t(global int A[256]) {{\n  local int L[256];\n  int v, k;\n{body}}}\n"
+    assert B.owned_arrays(src, 1, 256, with_faults=True)[1]
+    U.assert_same(*both(src, 1, 256, {"A": ("seeded", 0, 8)}, n=20), src)
+    U.assert_same(*both(src, 2, 256, {"A": ("seeded", 0, 8)}, seed0=40, n=8), src)

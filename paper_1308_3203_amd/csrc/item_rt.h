@@ -886,12 +886,12 @@ struct Item {
 #ifdef RC_JIT_NOSPILL
       // (a per-program kernel of a program whose intervals always fit the
       // LDS log: the log never moves to the global log)
-      bool to_lds = A.logged == LOG_LDS;
-      if (false) {
+      constexpr bool may_spill = false;
 #else
-      bool to_lds = A.logged == LOG_LDS && !lds_spilled;
-      if (to_lds && lds_used + total > P.lds_log_cap) {
+      constexpr bool may_spill = true;
 #endif
+      bool to_lds = A.logged == LOG_LDS && !(may_spill && lds_spilled);
+      if (may_spill && to_lds && lds_used + total > P.lds_log_cap) {
         // the interval outgrows LDS: move its log to the global log, where
         // the global pass checks it
         for (uint32_t i = tl; i < lds_used; i += nthr) {

@@ -146,21 +146,28 @@ rc_status rc_prog_scalar(const rc_prog* prog, uint32_t scalar_id, char* name, si
  * program's static bounds exceed the library's limits for this shape. */
 rc_status rc_set_ndrange(rc_prog* prog, uint32_t num_groups, uint32_t group_size);
 
-/* *owned = 1 when, under the current launch shape, no two work-items can
- * touch a common cell of array `array_id`, so that the array can carry no
- * record (every record pairs two work-items, Section 4) and its accesses are
- * not logged; 0 when that is not proven.  The proof: every index of the
- * array is S * tid + o for one stride S != 0 and offsets o in a range
- * shorter than |S|, with indices followed through + - * << by constants over
- * gid, lid, tid, the shape constants and loop counters, in int32 without
- * wrapping.  Results never depend on it.  RC_E_STATE before rc_set_ndrange. */
+/* *owned = 1 when, under the current launch shape, array `array_id` can
+ * carry no record (every record pairs two work-items, Section 4), so its
+ * accesses are not logged; 0 when that is not proven.  Either no two
+ * work-items can touch a common cell of the array (every index is
+ * S * tid + o for one stride S != 0 and offsets o in a range shorter than
+ * |S|, with indices followed through + - * << by constants over gid, lid,
+ * tid, the shape constants and loop counters, in int32 without wrapping; or,
+ * when no index or branch depends on the inputs, every work-item's cells are
+ * enumerated), or, for a local array of a program that cannot fault, no cell
+ * is written by one work-item and touched by another within a barrier
+ * interval of a group.  Results never depend on it.  RC_E_STATE before
+ * rc_set_ndrange. */
 rc_status rc_prog_owned(const rc_prog* prog, uint32_t array_id, int* owned);
 
 /* The same proof on program text, host only (no context, no device), under
  * num_groups groups of group_size work-items: *n_arrays receives the
  * program's array count (global arrays first, then local arrays, in
- * declaration order) and owned[a] (0 or 1) is written for the first
- * min(capacity, *n_arrays) arrays; owned may be NULL when capacity is 0.
+ * declaration order) and owned[a] is written for the first
+ * min(capacity, *n_arrays) arrays: 1 when no two work-items can touch a
+ * common cell, 2 for a local array that is not that but is race-free within
+ * every interval (see rc_prog_owned), else 0; owned may be NULL when
+ * capacity is 0.
  * never_faults (may be NULL) receives 1 when no input can make the program
  * fault: its accesses and branches do not depend on loaded values or scalar
  * parameters, and enumerating every work-item finds every access in bounds,

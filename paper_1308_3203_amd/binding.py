@@ -140,9 +140,11 @@ def _call(fn, *args):
     return st
 
 
-def owned_arrays(src: str, groups: int, group_size: int, with_faults: bool = False):
+def owned_arrays(src: str, groups: int, group_size: int, with_faults: bool = False, race_free: bool = False):
     """Per array (global arrays first, then local ones): True when no two
     work-items of the shape can touch a common cell of it (host only).
+    race_free: instead, True for the local arrays that are not owned but
+    race-free within every barrier interval (never logged either).
     with_faults: also return whether the program is proven never to fault."""
     lib = load_library()
     b = src.encode()
@@ -151,7 +153,7 @@ def owned_arrays(src: str, groups: int, group_size: int, with_faults: bool = Fal
     _call(lib.rc_owned_arrays, b, len(b), groups, group_size, None, 0, ctypes.byref(n), None)
     out = (ctypes.c_uint8 * max(1, n.value))()
     _call(lib.rc_owned_arrays, b, len(b), groups, group_size, out, n.value, ctypes.byref(n), ctypes.byref(nf))
-    owned = [bool(out[i]) for i in range(n.value)]
+    owned = [out[i] == (2 if race_free else 1) for i in range(n.value)]
     return (owned, bool(nf.value)) if with_faults else owned
 
 
@@ -349,8 +351,11 @@ class Program:
         self.G, self.W = groups, group_size
 
     def owned(self, name: str) -> bool:
-        """True when no two work-items can touch a common cell of the array
-        under the current shape (its accesses are then not logged)."""
+        """True when the array can carry no record under the current shape,
+        so its accesses are not logged: no two work-items can touch a common
+        cell of it, or (a local array of a program that cannot fault) no cell
+        is written by one work-item and touched by another within an
+        interval."""
         v = ctypes.c_int(0)
         _call(_lib.rc_prog_owned, self._h, self.array_id(name), ctypes.byref(v))
         return bool(v.value)

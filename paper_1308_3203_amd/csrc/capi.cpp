@@ -1040,7 +1040,7 @@ rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint
   const std::vector<OwnedArray>& o = proof.arrays;
   if (never_faults) *never_faults = proof.never_faults ? 1 : 0;
   *n_arrays = (uint32_t)o.size();
-  for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a].owned;
+  for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a].owned ? 1 : (o[a].race_free ? 2 : 0);
   return RC_OK;
 }
 
@@ -1111,8 +1111,9 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->shaped = true;
   const Ownership proof = prove_ownership(p->c, p->G, p->W);
   const std::vector<OwnedArray>& own = proof.arrays;
+  // not logged: owned arrays, and local arrays race-free within every interval
   p->owned.assign(own.size(), 0);
-  for (size_t a = 0; a < own.size(); ++a) p->owned[a] = own[a].owned;
+  for (size_t a = 0; a < own.size(); ++a) p->owned[a] = own[a].owned || own[a].race_free;
   // overlay words per group: a global rw array owned with a stride keeps its
   // work-items' cells lane by lane (so a wave's accesses to one offset are
   // consecutive words), in own_span * W words instead of one word per cell
@@ -1138,12 +1139,12 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->never_faults = proof.never_faults;
   for (size_t a = 0; a < own.size(); ++a) {
     ArrayDesc& d = p->arrays[a];
-    d.nosync = proof.never_faults && (d.kind == AK_GLOBAL_RO || own[a].owned) ? 1u : 0u;
+    d.nosync = proof.never_faults && (d.kind == AK_GLOBAL_RO || p->owned[a]) ? 1u : 0u;
   }
   // log cell keys: the written arrays that are not owned, global ones first
   uint32_t cb = 0;
   for (size_t a = 0; a < own.size(); ++a) {
-    const bool keyed = p->c.arrays[a].written && !own[a].owned;
+    const bool keyed = p->c.arrays[a].written && !p->owned[a];
     p->arrays[a].cellbase = keyed ? cb : 0xFFFFFFFFu;
     p->cellbase[a] = keyed ? cb : 0xFFFFFFFFu;
     if (keyed) cb += p->c.arrays[a].size;

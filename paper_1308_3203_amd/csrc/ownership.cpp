@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <map>
+#include <unordered_map>
 #include <utility>
 
 #include "rc_internal.h"
@@ -370,6 +371,9 @@ class Enumerator {
   // bounds, no division by a zero or unknown divisor, every assert and
   // assume holds), whatever the inputs.
   bool never_faults = false;
+  // Set by run(): the candidate local arrays that are race-free within every
+  // interval (see OwnedArray), in a program that cannot fault.
+  std::vector<uint8_t> race_free;
 
   // owned[a] for the candidate arrays (others 0); all 0 when the program's
   // accesses depend on its inputs or the enumeration is too long
@@ -385,9 +389,14 @@ class Enumerator {
     owner_.assign(na, std::vector<int32_t>());
     for (uint32_t a = 0; a < na; ++a)
       if (cand_[a]) owner_[a].assign(c_.arrays[a].size, -1);
+    rf_.assign(na, 0);
+    for (uint32_t a = 0; a < na; ++a) rf_[a] = cand_[a] && !c_.arrays[a].global;
+    cells_.assign(na, std::unordered_map<uint64_t, CellUse>());
     for (uint32_t g = 0; g < G_; ++g) {
-      for (uint32_t a = 0; a < na; ++a)   // each group has its own local arrays
+      for (uint32_t a = 0; a < na; ++a) {   // each group has its own local arrays
         if (cand_[a] && !c_.arrays[a].global) std::fill(owner_[a].begin(), owner_[a].end(), -1);
+        cells_[a].clear();
+      }
       for (uint32_t l = 0; l < W_; ++l) {
         bar_.clear();
         if (!item(g, l)) return none;
@@ -401,6 +410,8 @@ class Enumerator {
       }
     }
     never_faults = !faults_;
+    race_free.assign(na, 0);
+    for (uint32_t a = 0; a < na; ++a) race_free[a] = never_faults && rf_[a] && !cand_[a];
     return cand_;
   }
 
@@ -412,6 +423,13 @@ class Enumerator {
   uint64_t steps_ = 0;
   bool faults_ = false;                       // some statement may fault
   std::vector<uint32_t> bar_, bar0_;          // barriers passed: this work-item, the group's first
+  // race-freeness per interval (local candidates): per (interval, cell) of
+  // the current group, its writer and reader (-1 none, -2 several)
+  struct CellUse {
+    int32_t writer = -1, reader = -1;
+  };
+  std::vector<uint8_t> rf_;
+  std::vector<std::unordered_map<uint64_t, CellUse>> cells_;
 
   uint32_t word(uint32_t i, int k) const { return c_.code[4 * i + k]; }
 
@@ -429,11 +447,28 @@ class Enumerator {
     }
   }
 
-  void touch(uint32_t a, Val idx, int64_t t) {
+  void touch(uint32_t a, Val idx, int64_t t, bool write) {
     if (!idx.known || idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) faults_ = true;
-    if (!cand_[a]) return;
-    if (!idx.known) { cand_[a] = 0; return; }
+    if (!cand_[a] && !rf_[a]) return;
+    if (!idx.known) {
+      cand_[a] = 0;
+      rf_[a] = 0;
+      return;
+    }
     if (idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) return;   // faults: no access
+    if (rf_[a]) {
+      CellUse& u = cells_[a][((uint64_t)bar_.size() << 32) | (uint32_t)idx.v];
+      const int32_t me = (int32_t)t;
+      if (write) {
+        if (u.writer != -1 && u.writer != me) rf_[a] = 0;      // two writers
+        if (u.reader != -1 && u.reader != me) rf_[a] = 0;      // another work-item read it
+        u.writer = me;
+      } else {
+        if (u.writer != -1 && u.writer != me) rf_[a] = 0;      // another work-item wrote it
+        u.reader = u.reader == -1 || u.reader == me ? me : -2;
+      }
+    }
+    if (!cand_[a]) return;
     int32_t& o = owner_[a][(uint32_t)idx.v];
     if (o == -1) o = (int32_t)t;   // work-item ids are below 2^26
     else if (o != (int32_t)t) cand_[a] = 0;
@@ -472,12 +507,12 @@ class Enumerator {
           break;
         }
         case OP_LOAD:
-          touch(word(pc, 3), operand(fa, word(pc, 1), regs, g, l), t);
+          touch(word(pc, 3), operand(fa, word(pc, 1), regs, g, l), t, false);
           regs[dst] = Val{false, 0};
           ++pc;
           break;
         case OP_STORE:
-          touch(word(pc, 3), operand(fa, word(pc, 1), regs, g, l), t);
+          touch(word(pc, 3), operand(fa, word(pc, 1), regs, g, l), t, true);
           ++pc;
           break;
         case OP_IF: {
@@ -542,8 +577,10 @@ Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W) {
   for (size_t a = 0; a < out.arrays.size(); ++a) cand[a] = !out.arrays[a].owned && c.arrays[a].written;
   Enumerator e(c, G, W, cand);
   const std::vector<uint8_t> owned = e.run();
-  for (size_t a = 0; a < out.arrays.size(); ++a)
+  for (size_t a = 0; a < out.arrays.size(); ++a) {
     if (owned[a]) out.arrays[a].owned = 1;   // owned, kept in the plain layout
+    if (a < e.race_free.size() && e.race_free[a]) out.arrays[a].race_free = 1;
+  }
   out.never_faults = e.never_faults;
   return out;
 }

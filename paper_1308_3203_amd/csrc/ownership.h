@@ -32,8 +32,17 @@ namespace rc {
 // with o in [lo, hi] (hi - lo < |stride|), so a work-item's cells can be
 // placed by (o - lo, lid) instead of by cell.  stride == 0: owned with no
 // such placement (the array is never accessed, or there is one work-item).
+//
+// race_free (local arrays, by the enumeration below): within every barrier
+// interval of every group, no cell is written by one work-item and read or
+// written by another.  Every record of an INTRA scope pairs two such
+// accesses, and a local array has no INTER scope, so such an array can
+// carry no record either: its accesses need no log, and (in a program that
+// cannot fault) no group step, since no work-item reads within an interval
+// what another writes.
 struct OwnedArray {
   uint8_t owned = 0;
+  uint8_t race_free = 0;
   int64_t stride = 0, lo = 0, hi = 0;
 };
 

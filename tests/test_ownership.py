@@ -223,3 +223,92 @@ def test_never_faults_agrees_with_the_oracle():
             res = prog.run(G, W, arrays={"x": ("seeded", 0, 4)}, seed=seed)
             assert res.status == "OK", (src, G, W, res.status)
     assert proven >= 20
+
+
+def race_free(body, G, W, decl="global int x[4096]", locs="local int l[512]"):
+    src = f"kernel t({decl}) {{\n  {locs};\n  int v, w, k, j;\n{body}\n}}\n"
+    return B.owned_arrays(src, G, W, race_free=True)
+
+
+RACE_FREE_CASES = [
+    # (body, G, W, local array race-free within every interval)
+    ("  l[lid] := 1;\n  barrier;\n  v := l[lid + 1];\n  x[tid] := v;", 2, 64, True),
+    ("  l[lid] := 1;\n  v := l[lid + 1];\n  x[tid] := v;", 2, 64, False),     # same interval
+    ("  l[lid % 32] := lid;", 1, 64, False),                                     # two writers
+    ("  l[lid] := 1;\n  barrier;\n  v := l[0];\n  x[tid] := v;", 1, 64, True),   # readers only
+    ("  l[lid] := 1;\n  v := l[lid];\n  l[lid] := v + 1;", 1, 64, False),        # owned, not race-free
+    ("  for k in 0..4 {\n    l[lid + 64 * (k % 2)] := k;\n    barrier;\n    v := l[(lid + 1) % 64 + 64 * (k % 2)];\n"
+     "    barrier;\n  }", 1, 64, True),
+    ("  for k in 0..4 {\n    l[lid + 64 * (k % 2)] := k;\n    v := l[(lid + 1) % 64 + 64 * ((k + 1) % 2)];\n"
+     "    barrier;\n  }", 1, 64, True),                                          # double buffering
+    ("  for k in 0..4 {\n    l[lid] := k;\n    v := l[(lid + 1) % 64];\n    barrier;\n  }", 1, 64, False),
+    ("  assert(lid < 10);\n  l[lid] := 1;\n  barrier;\n  v := l[lid + 1];", 1, 64, False),   # may fault
+    ("  v := x[tid];\n  l[v % 64] := 1;", 1, 64, False),                         # data-dependent index
+]
+
+
+@pytest.mark.parametrize("body,G,W,expect", RACE_FREE_CASES)
+def test_race_free_locals(body, G, W, expect):
+    assert race_free(body, G, W)[1] == expect
+
+
+def test_c2_templates_race_free():
+    got = {w.name: B.owned_arrays(w.src, w.G, w.W, race_free=True)[-1] for w in WL.c2_templates()}
+    assert got == {"tree_reduce": True, "tree_reduce_race": False, "prefix_sum": True, "prefix_sum_race": False,
+                   "transpose": True, "transpose_race": False}
+
+
+def _random_local_program(r: random.Random):
+    """Loads and stores of one local array with indices over lid, loop
+    counters and constants, barriers, loops and branches on lid; small
+    arrays, so conflicts are common when the proof does not hold."""
+    def idx(loops):
+        t = r.choice(["lid", f"(lid + {r.randint(1, 5)})", f"(lid * {r.randint(1, 3)})", f"{r.randint(0, 7)}",
+                      f"(lid / {r.randint(2, 4)})"])
+        if loops and r.random() < 0.4:
+            t = f"({t} + {r.choice(loops)} * {r.randint(0, 16)})"
+        return f"({t}) % 64"
+
+    def stmts(n, loops, depth):
+        out = []
+        for _ in range(n):
+            k = r.random()
+            if k < 0.3:   # stores mostly to the work-item's own cell, so the proof often holds
+                out.append(f"l[{idx(loops) if r.random() < 0.3 else 'lid % 64'}] := lid;")
+            elif k < 0.6:
+                out.append(f"v := l[{idx(loops)}];")
+            elif k < 0.8:
+                out.append("barrier;")
+            elif k < 0.87 and depth < 2:
+                out.append(f"if (lid < {r.randint(0, 40)}) {{ " + " ".join(
+                    s for s in stmts(r.randint(1, 2), loops, depth + 1) if s != "barrier;") + " }")
+            elif depth < 2 and len(loops) < 2:
+                lv = ["k", "j"][len(loops)]
+                out.append(f"for {lv} in 0..{r.randint(1, 3)} {{ " + " ".join(
+                    stmts(r.randint(1, 3), loops + [lv], depth + 1)) + " }")
+        return out
+
+    body = stmts(r.randint(2, 7), [], 0)
+    return ("kernel t(global int x[64]) {\n  local int l[64];\n  int v, w, k, j;\n  " + "\n  ".join(body) +
+            "\n  x[lid] := v;\n}\n")
+
+
+def test_race_free_locals_never_carry_records():
+    """Where the proof says a local array is race-free in every interval,
+    the oracle (which logs every access) reports no record on it."""
+    r = random.Random(31337)
+    n_rf = 0
+    for case in range(1500):
+        src = _random_local_program(r)
+        G, W = r.choice([(1, 8), (2, 16), (1, 32), (3, 8)])
+        try:
+            rf = B.owned_arrays(src, G, W, race_free=True)
+        except B.RcError:
+            continue
+        if not rf[1]:
+            continue
+        n_rf += 1
+        res = O.Program(src).run(G, W, arrays={"x": ("seeded", 0, 4)}, seed=case)
+        assert res.status == "OK", (src, G, W)
+        assert not any(int(rec["array"]) == 1 for rec in res.records), (src, G, W)
+    assert n_rf >= 60

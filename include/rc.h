@@ -179,6 +179,17 @@ rc_status rc_prog_owned(const rc_prog* prog, uint32_t array_id, int* owned);
 rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint32_t group_size,
                           uint8_t* owned, uint32_t capacity, uint32_t* n_arrays, int* never_faults);
 
+/* The barrier intervals in which local-array accesses are logged, from the
+ * same enumeration, host only: bit k of *mask for interval k < 64 (the
+ * accesses after k barriers), *later = 1 when every later interval is.
+ * An interval is left out only when the program cannot fault and, in every
+ * group, no cell of a local array is written by one work-item and touched
+ * by another in it (INTRA records of local arrays, Section 4, need such a
+ * pair); all bits are set when that is not proven.  Errors as
+ * rc_owned_arrays. */
+rc_status rc_log_intervals(const char* src, size_t len, uint32_t num_groups, uint32_t group_size, uint64_t* mask,
+                           int* later);
+
 /* Inputs (Section 3 K(Args): arguments passed by the host).  A global array is
  * bound either to seeded values U[lo, hi) (1 <= hi - lo <= 2^32; instance j's
  * seed is seed0 + j) or to caller-owned device memory of size(array) int32

@@ -41,6 +41,7 @@ EXPORTS = [
     "rc_features_workspace_size", "rc_features", "rc_mlp_workspace_size", "rc_mlp_forward", "rc_mlp_grad",
     "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank", "rc_prog_jit", "rc_prog_owned",
     "rc_owned_arrays",
+    "rc_log_intervals",
 ]
 N_FEATURES = 128
 MLP_PARAMS = 99073
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH):
         "rc_prog_owned": ([vp, u32, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rc_owned_arrays": ([ctypes.c_char_p, sz, u32, u32, ctypes.POINTER(ctypes.c_uint8), u32,
                              ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "rc_log_intervals": ([ctypes.c_char_p, sz, u32, u32, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_int)],
+                             ctypes.c_int),
         "rc_bind_seeded": ([vp, u32, i64, i64], ctypes.c_int),
         "rc_bind_device": ([vp, u32, vp], ctypes.c_int),
         "rc_bind_scalar_seeded": ([vp, u32, i64, i64], ctypes.c_int),
@@ -155,6 +158,18 @@ def owned_arrays(src: str, groups: int, group_size: int, with_faults: bool = Fal
     _call(lib.rc_owned_arrays, b, len(b), groups, group_size, out, n.value, ctypes.byref(n), ctypes.byref(nf))
     owned = [out[i] == (2 if race_free else 1) for i in range(n.value)]
     return (owned, bool(nf.value)) if with_faults else owned
+
+
+def log_intervals(src: str, groups: int, group_size: int):
+    """(mask, later): the barrier intervals whose local-array accesses are
+    logged under the shape (bit k: interval k < 64; later: every interval
+    from 64 on), host only."""
+    lib = load_library()
+    b = src.encode()
+    m = ctypes.c_uint64(0)
+    later = ctypes.c_int(0)
+    _call(lib.rc_log_intervals, b, len(b), groups, group_size, ctypes.byref(m), ctypes.byref(later))
+    return int(m.value), bool(later.value)
 
 
 class Context:

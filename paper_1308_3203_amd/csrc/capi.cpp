@@ -95,6 +95,8 @@ struct rc_prog {
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t record_sort = 0;          // tuning: 1 = always sort records by their full key
   bool never_faults = false;         // proven for the current shape
+  uint64_t log_mask = ~0ull;         // intervals whose local-array accesses are logged (ProgDesc)
+  uint32_t log_high = 1;
   uint32_t lds_log_cap = 0;          // chosen for the current shape
   // arrays no two work-items share under the current shape (never logged),
   // and the per-item access bounds on the arrays that are logged
@@ -452,6 +454,8 @@ JitShape jit_shape_of(const rc_prog* p) {
   s.lds_log_cap = p->lds_log_cap;
   s.nospill = p->lds_log_cap && !lds_may_spill(p) ? 1u : 0u;
   s.nofault = p->never_faults ? 1u : 0u;
+  s.log_mask = p->log_mask;
+  s.log_high = p->log_high;
   for (uint32_t i = 0; i < (uint32_t)p->arrays.size(); ++i) {
     const ArrayDesc& a = p->arrays[i];
     const uint32_t f[JIT_ARRAY_WORDS] = {a.kind, a.size, array_logged(p, i), a.offset, a.cellbase,
@@ -779,6 +783,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     D.overlay_cells = p->overlay_cells;
     D.NI = (uint32_t)p->c.max_intervals;
     D.wg_log_cap = wg_log_entries(p);
+    D.log_mask = p->log_mask;
+    D.log_high = p->log_high;
   }
   rc_record_out R;
   memset(&R, 0, sizeof R);
@@ -1044,6 +1050,21 @@ rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint
   return RC_OK;
 }
 
+rc_status rc_log_intervals(const char* src, size_t len, uint32_t num_groups, uint32_t group_size, uint64_t* mask,
+                           int* later) {
+  if (!src || !mask || !later) return fail(RC_E_INVAL, "NULL argument");
+  if (group_size < 1 || group_size > MAX_WG || num_groups < 1 || (u64)num_groups * group_size >= (1ull << 26))
+    return fail(RC_E_INVAL, "launch shape out of range");
+  Compiled c;
+  std::string err;
+  bool is_limit = false;
+  if (!compile_program(src, len, &c, &err, &is_limit)) return fail(is_limit ? RC_E_LIMIT : RC_E_PARSE, "%s", err.c_str());
+  const Ownership proof = prove_ownership(c, num_groups, group_size);
+  *mask = proof.local_log_mask;
+  *later = proof.local_log_high ? 1 : 0;
+  return RC_OK;
+}
+
 // Generate, compile and load the program's kernel for its current width
 // class and launch shape (synchronous; the runtime compiler takes about a
 // second), or take it from the kernels already compiled.
@@ -1137,6 +1158,8 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   }
   p->overlay_cells = ov;
   p->never_faults = proof.never_faults;
+  p->log_mask = proof.local_log_mask;
+  p->log_high = proof.local_log_high ? 1u : 0u;
   for (size_t a = 0; a < own.size(); ++a) {
     ArrayDesc& d = p->arrays[a];
     d.nosync = proof.never_faults && (d.kind == AK_GLOBAL_RO || p->owned[a]) ? 1u : 0u;

@@ -362,6 +362,8 @@ struct ItemView {
   uint32_t n_arrays, n_global, n_scalars, nregs, G, W, nwaves, lds_local_cells;
   uint32_t lds_log_cap, overlay_cells, NI, bc, bg, bk, bs, do_log;
   uint32_t tab_base, tab_cells;
+  u64 log_mask;            // intervals whose local-array accesses are logged (ProgDesc)
+  uint32_t log_high;
   u64 wg_log_cap;
   u64* log_keys;
   u64* log_vals;
@@ -807,14 +809,20 @@ struct Item {
 #else
     if (!A.nosync && active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);   // (nosync: in bounds)
 #endif
-    const bool rec = active && P.do_log && A.logged != LOG_NONE;
+    // a local array's accesses in an interval the proof shows race-free
+    // (no cell written by one work-item and touched by another) can give no
+    // record: they are not logged, and (the program cannot fault) need no
+    // group step
+    const bool quiet = A.kind == AK_LOCAL && A.logged != LOG_NONE &&
+                       !(interval < 64u ? ((P.log_mask >> interval) & 1ull) != 0ull : P.log_high != 0u);
+    const bool rec = active && P.do_log && A.logged != LOG_NONE && !quiet;
     // the barrier completes every earlier statement's accesses, publishes
     // pending faults (a faulting statement has no effect) and each wave's
     // number of log entries for this statement; a nosync array needs none
     // of that
     u64 brec = 0;
     uint32_t prefix = 0, total = 0;
-    if (!A.nosync && SYNC && mem_red(rec, &brec, &prefix, &total)) return true;
+    if (!A.nosync && SYNC && !quiet && mem_red(rec, &brec, &prefix, &total)) return true;
     const uint32_t cell = (uint32_t)idx;
     // overlay word of the cell: by cell, or for an owned array by (offset
     // from the work-item's stride, lid), which keeps a wave's words together
@@ -1039,6 +1047,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.G = D.G; P.W = D.W; P.nwaves = D.nwaves; P.lds_local_cells = D.lds_local_cells;
     P.lds_log_cap = D.lds_log_cap; P.overlay_cells = D.overlay_cells; P.NI = D.NI;
     P.tab_base = D.tab_base; P.tab_cells = D.tab_cells;
+    P.log_mask = D.log_mask; P.log_high = D.log_high;
     P.bc = PP.bc; P.bg = PP.bg; P.bk = PP.bk; P.bs = PP.bs; P.do_log = PP.do_log;
     P.wg_log_cap = D.wg_log_cap;
     P.log_keys = PP.log_keys; P.log_vals = PP.log_vals; P.status_word = PP.status_word; P.rec = PP.rec;
@@ -1059,7 +1068,8 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
                     X.own_lo == Y.own_lo && X.own_span == Y.own_span && X.nosync == Y.nosync;
     }
     if (D.W != RC_JIT_W || D.G != RC_JIT_G || D.n_arrays != RC_JIT_NA || D.tab_cells != RC_JIT_TC ||
-        D.tab_base != RC_JIT_TB || D.lds_log_cap != RC_JIT_LC || !same_arrays) {
+        D.tab_base != RC_JIT_TB || D.lds_log_cap != RC_JIT_LC || D.log_mask != RC_JIT_LOGMASK ||
+        D.log_high != RC_JIT_LOGHIGH || !same_arrays) {
       if (threadIdx.x == 0) {
         atomicOr(PP.status_word, 8u);
         PP.wg_count[S.wg_base + gid] = 0u;   // nothing logged
@@ -1069,6 +1079,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     }
     P.W = RC_JIT_W; P.G = RC_JIT_G; P.nwaves = (RC_JIT_W + 63u) / 64u; P.n_arrays = RC_JIT_NA;
     P.tab_cells = RC_JIT_TC; P.tab_base = RC_JIT_TB; P.lds_log_cap = RC_JIT_LC;
+    P.log_mask = RC_JIT_LOGMASK; P.log_high = RC_JIT_LOGHIGH;
 #endif
     Item it;
     it.init(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,

@@ -110,6 +110,9 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
   s += buf;
   if (shape.nospill) s += "#define RC_JIT_NOSPILL 1\n";
   if (shape.nofault) s += "#define RC_JIT_NOFAULT 1\n";
+  snprintf(buf, sizeof buf, "#define RC_JIT_LOGMASK 0x%016llxull\n#define RC_JIT_LOGHIGH %uu\n",
+           (unsigned long long)shape.log_mask, shape.log_high);
+  s += buf;
   const bool elide = shape.nofault && shape.nospill;
   if (elide) s += "#define RC_JIT_ELIDE 1\n";
   const std::vector<uint8_t> keep = elide ? group_steps(code, shape) : std::vector<uint8_t>(n, 1);

@@ -21,10 +21,13 @@ struct JitShape {
   uint32_t W = 0, G = 0, n_arrays = 0, tab_base = 0, tab_cells = 0, lds_log_cap = 0;
   uint32_t nospill = 0;   // every interval's LDS-logged accesses fit the LDS log
   uint32_t nofault = 0;   // the program is proven never to fault under this shape
+  uint64_t log_mask = ~0ull;   // intervals whose local-array accesses are logged
+  uint32_t log_high = 1;
   std::vector<uint32_t> arrays;
   bool operator==(const JitShape& o) const {
     return W == o.W && G == o.G && n_arrays == o.n_arrays && tab_base == o.tab_base && tab_cells == o.tab_cells &&
-           lds_log_cap == o.lds_log_cap && nospill == o.nospill && nofault == o.nofault && arrays == o.arrays;
+           lds_log_cap == o.lds_log_cap && nospill == o.nospill && nofault == o.nofault && log_mask == o.log_mask &&
+           log_high == o.log_high && arrays == o.arrays;
   }
 };
 

@@ -365,15 +365,18 @@ bool host_alu(uint32_t op, int32_t x, int32_t y, int32_t* r) {
 class Enumerator {
  public:
   Enumerator(const Compiled& c, uint32_t G, uint32_t W, std::vector<uint8_t> cand)
-      : c_(c), G_(G), W_(W), cand_(std::move(cand)) {}
+      : c_(c), G_(G), W_(W), cand_(std::move(cand)), cand0_(cand_) {}
 
   // Set by run(): no statement of any work-item can fault (every access in
   // bounds, no division by a zero or unknown divisor, every assert and
   // assume holds), whatever the inputs.
   bool never_faults = false;
   // Set by run(): the candidate local arrays that are race-free within every
-  // interval (see OwnedArray), in a program that cannot fault.
+  // interval (see OwnedArray), in a program that cannot fault, and the
+  // intervals with a conflict on some local array (see Ownership).
   std::vector<uint8_t> race_free;
+  uint64_t racy_mask = ~0ull;
+  bool racy_high = true;
 
   // owned[a] for the candidate arrays (others 0); all 0 when the program's
   // accesses depend on its inputs or the enumeration is too long
@@ -390,7 +393,10 @@ class Enumerator {
     for (uint32_t a = 0; a < na; ++a)
       if (cand_[a]) owner_[a].assign(c_.arrays[a].size, -1);
     rf_.assign(na, 0);
-    for (uint32_t a = 0; a < na; ++a) rf_[a] = cand_[a] && !c_.arrays[a].global;
+    track_.assign(na, 0);
+    for (uint32_t a = 0; a < na; ++a) track_[a] = rf_[a] = cand_[a] && !c_.arrays[a].global;
+    mask_ = 0;
+    high_ = false;
     cells_.assign(na, std::unordered_map<uint64_t, CellUse>());
     for (uint32_t g = 0; g < G_; ++g) {
       for (uint32_t a = 0; a < na; ++a) {   // each group has its own local arrays
@@ -412,13 +418,20 @@ class Enumerator {
     never_faults = !faults_;
     race_free.assign(na, 0);
     for (uint32_t a = 0; a < na; ++a) race_free[a] = never_faults && rf_[a] && !cand_[a];
+    bool tracked = true;   // every local written array that is not owned was followed to the end
+    for (uint32_t a = 0; a < na; ++a)
+      if (!c_.arrays[a].global && cand0_[a] && !track_[a]) tracked = false;
+    if (never_faults && tracked) {
+      racy_mask = mask_;
+      racy_high = high_;
+    }
     return cand_;
   }
 
  private:
   const Compiled& c_;
   const uint32_t G_, W_;
-  std::vector<uint8_t> cand_;
+  std::vector<uint8_t> cand_, cand0_;   // candidates left; the initial ones
   std::vector<std::vector<int32_t>> owner_;   // per candidate array: touching work-item, or -1
   uint64_t steps_ = 0;
   bool faults_ = false;                       // some statement may fault
@@ -428,8 +441,14 @@ class Enumerator {
   struct CellUse {
     int32_t writer = -1, reader = -1;
   };
-  std::vector<uint8_t> rf_;
+  std::vector<uint8_t> rf_, track_;   // race-free so far; still followed
   std::vector<std::unordered_map<uint64_t, CellUse>> cells_;
+  uint64_t mask_ = 0;                 // intervals with a conflict (< 64), and any later one
+  bool high_ = false;
+  void racy(size_t k) {
+    if (k < 64) mask_ |= 1ull << k;
+    else high_ = true;
+  }
 
   uint32_t word(uint32_t i, int k) const { return c_.code[4 * i + k]; }
 
@@ -449,23 +468,28 @@ class Enumerator {
 
   void touch(uint32_t a, Val idx, int64_t t, bool write) {
     if (!idx.known || idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) faults_ = true;
-    if (!cand_[a] && !rf_[a]) return;
+    if (!cand_[a] && !track_[a]) return;
     if (!idx.known) {
       cand_[a] = 0;
       rf_[a] = 0;
+      track_[a] = 0;
       return;
     }
     if (idx.v < 0 || (uint32_t)idx.v >= c_.arrays[a].size) return;   // faults: no access
-    if (rf_[a]) {
+    if (track_[a]) {
       CellUse& u = cells_[a][((uint64_t)bar_.size() << 32) | (uint32_t)idx.v];
       const int32_t me = (int32_t)t;
-      if (write) {
-        if (u.writer != -1 && u.writer != me) rf_[a] = 0;      // two writers
-        if (u.reader != -1 && u.reader != me) rf_[a] = 0;      // another work-item read it
+      bool conflict;
+      if (write) {   // two writers, or another work-item read it
+        conflict = (u.writer != -1 && u.writer != me) || (u.reader != -1 && u.reader != me);
         u.writer = me;
-      } else {
-        if (u.writer != -1 && u.writer != me) rf_[a] = 0;      // another work-item wrote it
+      } else {       // another work-item wrote it
+        conflict = u.writer != -1 && u.writer != me;
         u.reader = u.reader == -1 || u.reader == me ? me : -2;
+      }
+      if (conflict) {
+        rf_[a] = 0;
+        racy(bar_.size());
       }
     }
     if (!cand_[a]) return;
@@ -581,6 +605,8 @@ Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W) {
     if (owned[a]) out.arrays[a].owned = 1;   // owned, kept in the plain layout
     if (a < e.race_free.size() && e.race_free[a]) out.arrays[a].race_free = 1;
   }
+  out.local_log_mask = e.racy_mask;
+  out.local_log_high = e.racy_high;
   out.never_faults = e.never_faults;
   return out;
 }

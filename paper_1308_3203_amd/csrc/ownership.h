@@ -50,9 +50,17 @@ struct OwnedArray {
 // the enumeration also sees every statement of every work-item; no access
 // out of bounds, no division by zero and no failing assert or assume means
 // no input can make the program fault.
+//
+// local_log_mask / local_log_high: the barrier intervals (k < 64 by bit k,
+// all later ones by local_log_high) in which some group has a local-array
+// cell written by one work-item and touched by another, in a program that
+// cannot fault.  Only those intervals can give records on local arrays;
+// all bits stay set when that is not proven.
 struct Ownership {
   std::vector<OwnedArray> arrays;
   bool never_faults = false;
+  uint64_t local_log_mask = ~0ull;
+  bool local_log_high = true;
 };
 Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W);
 

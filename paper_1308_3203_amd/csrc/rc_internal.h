@@ -112,7 +112,12 @@ struct ProgDesc {                 // one program of the call
   uint64_t wg_log_cap;            // log entries reserved per work-group
   // LDS interval check by a per-cell table instead of a sort: table entry of
   // log cell key ck is ck - tab_base; tab_cells = 0 selects the sort
-  uint32_t tab_base, tab_cells, pad2[2];
+  uint32_t tab_base, tab_cells;
+  // intervals whose local-array accesses are logged: interval k < 64 when
+  // bit k of log_mask is set, every later one when log_high != 0 (all set
+  // unless a proof shows the other intervals race-free)
+  uint32_t log_high, pad2;
+  uint64_t log_mask;
 };
 
 // one cell's running check state in the LDS table (24 bytes)

@@ -312,3 +312,44 @@ def test_race_free_locals_never_carry_records():
         assert res.status == "OK", (src, G, W)
         assert not any(int(rec["array"]) == 1 for rec in res.records), (src, G, W)
     assert n_rf >= 60
+
+
+def test_logged_intervals_of_the_racy_templates():
+    """Only the intervals with a conflicting local-array cell keep their log
+    (worked out by hand from the template texts): the transpose with the
+    injected race lacks the barrier between reading tile 2 and writing tile
+    3, so interval 5 holds both; the racy prefix sum writes one cell past its
+    half into the cell work-item 0 reads, at every level (intervals 1-8); the
+    racy tree reduction reads loc[s - 1] written by work-item s - 1 at the
+    levels with s >= 2 (intervals 1-7)."""
+    T = {w.name: w for w in WL.c2_templates()}
+    got = {n: B.log_intervals(T[n].src, T[n].G, T[n].W) for n in ("transpose_race", "prefix_sum_race",
+                                                                   "tree_reduce_race")}
+    assert got == {"transpose_race": (1 << 5, False), "prefix_sum_race": (0x1FE, False),
+                   "tree_reduce_race": (0xFE, False)}
+    # not proven (a data-dependent index, a possible fault): every interval
+    src = "kernel t(global int x[64]) {\n  local int l[64];\n  int v;\n  v := x[lid];\n  l[v % 64] := 1;\n}\n"
+    assert B.log_intervals(src, 1, 64) == ((1 << 64) - 1, True)
+
+
+def test_records_only_in_logged_intervals():
+    """The oracle's records on the local array fall in intervals the proof
+    keeps logged."""
+    r = random.Random(4242)
+    n_partial = 0
+    for case in range(800):
+        src = _random_local_program(r)
+        G, W = r.choice([(1, 8), (2, 16), (1, 32), (3, 8)])
+        try:
+            mask, later = B.log_intervals(src, G, W)
+        except B.RcError:
+            continue
+        if mask == (1 << 64) - 1 and later:
+            continue
+        n_partial += mask != 0
+        res = O.Program(src).run(G, W, arrays={"x": ("seeded", 0, 4)}, seed=case)
+        for rec in res.records:
+            if int(rec["array"]) == 1:
+                k = int(rec["interval"])
+                assert (k < 64 and (mask >> k) & 1) or (k >= 64 and later), (src, G, W, k, hex(mask))
+    assert n_partial >= 50

@@ -41,11 +41,18 @@ std::string operand(bool imm, uint32_t w) {
 // does a kept step; the statements of a loop body also follow the body's
 // own end.  Arrays whose accesses never take the step (read-only or owned)
 // cannot conflict; statements on an array logged to the global log keep the
-// step, which numbers its entries.
+// step, which numbers its entries.  A kept step on a logged local array
+// synchronises only in the intervals whose local accesses are logged (in
+// the others the runtime skips it, the array being race-free there), so
+// unless every interval is logged it does not count as a synchronisation.
 std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitShape& shape) {
   const uint32_t n = (uint32_t)(code.size() / 4), na = shape.n_arrays;
   std::vector<uint8_t> keep(n, 0);
   auto field = [&](uint32_t a, uint32_t f) { return shape.arrays[a * JIT_ARRAY_WORDS + f]; };
+  const bool every_interval_logged = shape.log_mask == ~0ull && shape.log_high != 0u;
+  auto may_be_quiet = [&](uint32_t a) {
+    return !every_interval_logged && field(a, 0) == AK_LOCAL && field(a, 2) != LOG_NONE;
+  };
   std::map<uint32_t, std::vector<uint8_t>> back;   // first body instruction -> accesses at the body's end
   for (bool changed = true; changed;) {
     changed = false;
@@ -67,7 +74,7 @@ std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitSha
           keep[i] = 1;
           changed = true;
         }
-        if (keep[i]) std::fill(S.begin(), S.end(), 0);
+        if (keep[i] && !may_be_quiet(wc)) std::fill(S.begin(), S.end(), 0);
         S[wc] |= bit;
       } else if (op == OP_IF || op == OP_BARRIER) {
         std::fill(S.begin(), S.end(), 0);

@@ -134,3 +134,62 @@ def test_elided_group_steps(body):
     assert B.owned_arrays(src, 1, 256, with_faults=True)[1]
     U.assert_same(*both(src, 1, 256, {"A": ("seeded", 0, 8)}, n=20), src)
     U.assert_same(*both(src, 2, 256, {"A": ("seeded", 0, 8)}, seed0=40, n=8), src)
+
+
+def quiet_step_src(W):
+    """A global array shared between work-items (not owned) next to a local
+    array that is race-free in interval 0 and racy in interval 1: the load of
+    L in interval 0 keeps its group step only in logged intervals, so it must
+    not stand in for the synchronisation the following load of A needs."""
+    return (f"kernel q(global int A[{W}], global int Bo[{W}]) {{\n  local int L[{W}];\n  int x, y;\n"
+            f"  A[(lid + 1) % {W}] := lid;\n  L[lid] := lid;\n  x := L[lid];\n  y := A[lid];\n"
+            f"  Bo[lid] := y + x;\n  barrier;\n  L[(lid + 1) % {W}] := x;\n  x := L[lid];\n}}\n")
+
+
+@pytest.mark.parametrize("W", [128, 256])
+def test_elided_step_after_quiet_local_access(W):
+    """Regression: a shared global array logged in LDS, read after a group
+    step on a local array that the runtime skips in a quiet interval.  The
+    per-program kernel must read the other wave's store (final memory and
+    records equal the oracle's)."""
+    import torch
+    from oracle import oracle as O
+    src = quiet_step_src(W)
+    owned, nofault = B.owned_arrays(src, 1, W, with_faults=True)
+    assert nofault and owned == [False, True, False]
+    assert B.log_intervals(src, 1, W) == (0b10, False)
+    arrays = {"A": ("seeded", 0, 1000), "Bo": ("seeded", 0, 8)}
+    U.assert_same(*both(src, 1, W, arrays, seed0=1, n=6), src)
+    p = B.Program(U.ctx(), src)
+    p.set_ndrange(1, W)
+    p.bind(arrays, None)
+    p.jit(True)
+    ws = torch.empty(p.workspace_size(1), dtype=torch.uint8, device="cuda")
+    for seed in (0, 3):
+        for name in ("A", "Bo"):
+            fin = p.read_final(seed, name, ws).cpu().numpy()
+            U.ctx().sync()
+            orc = O.check(src, 1, W, arrays=arrays, seed=seed, final=name)
+            assert np.array_equal(fin, orc.final), (W, seed, name)
+
+
+@pytest.mark.parametrize("w", WL.c2_templates(), ids=lambda w: w.name)
+def test_proofs_off_same_reports(w):
+    """With the static proofs turned off every written array is logged and
+    every memory statement takes its group step; the reports stay the
+    oracle's, for the per-program kernel and the interpreter."""
+    o = U.oracle_run(w.src, w.G, w.W, w.arrays, w.scalars, 21, 3)
+    for jit in (True, False):
+        p = B.Program(U.ctx(), w.src)
+        p.set_ndrange(w.G, w.W)
+        p.bind(w.arrays, w.scalars)
+        p.set_tuning(proofs_off=True)
+        assert not any(p.owned(a[0]) for a in p.arrays)
+        if jit:
+            p.jit(True)
+        buf = B.Buffers(p, 3, 1 << 18)
+        p.check_async(21, 3, buf.ws, buf.records, buf.n_records, buf.summaries)
+        U.ctx().sync()
+        n = int(buf.n_records.item())
+        U.assert_same((B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 3)), o,
+                      f"{w.name} jit={jit}")

@@ -353,3 +353,21 @@ def test_records_only_in_logged_intervals():
                 k = int(rec["interval"])
                 assert (k < 64 and (mask >> k) & 1) or (k >= 64 and later), (src, G, W, k, hex(mask))
     assert n_partial >= 50
+
+
+def test_quiet_interval_proof_of_shared_global_next_to_local():
+    """The proof the per-program kernels' step elision relies on, for a
+    shared global array beside a local array race-free in interval 0 only:
+    A is not owned (work-item l writes A[l+1], l+1 reads it), Bo is owned,
+    L is logged in interval 1 only, and the program cannot fault."""
+    for W in (128, 256):
+        src = (f"kernel q(global int A[{W}], global int Bo[{W}]) {{\n  local int L[{W}];\n  int x, y;\n"
+               f"  A[(lid + 1) % {W}] := lid;\n  L[lid] := lid;\n  x := L[lid];\n  y := A[lid];\n"
+               f"  Bo[lid] := y + x;\n  barrier;\n  L[(lid + 1) % {W}] := x;\n  x := L[lid];\n}}\n")
+        owned, nofault = B.owned_arrays(src, 1, W, with_faults=True)
+        assert nofault and owned == [False, True, False]
+        assert B.log_intervals(src, 1, W) == (0b10, False)
+        # the oracle: records on A in interval 0, on L in interval 1 only
+        r = O.check(src, 1, W, arrays={"A": ("seeded", 0, 1000), "Bo": ("seeded", 0, 8)}, seed=1)
+        got = {(int(x["interval"]), int(x["array"])) for x in r.records}
+        assert got == {(0, 0), (1, 2)}

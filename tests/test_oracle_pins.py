@@ -48,6 +48,32 @@ def test_splitmix64_published_sequence():
     assert got == expect
 
 
+def test_seeded_range_scaling_worked_by_hand():
+    # value = lo + ((u * (hi - lo)) >> 32) with u the top 32 bits of the
+    # output.  Worked from the three published outputs above:
+    #   u = 0xE220A839 = 3793791033, 0x6E789E6A = 1853398634, 0x06C45D18 = 113532184
+    #   U[0,16):   u >> 28                       -> 14, 6, 0
+    #   U[0,100):  floor(u * 100 / 2^32)         -> 88 (88.33), 43 (43.15), 2 (2.64)
+    #   U[-5,3):   -5 + (u >> 29)                -> -5 + 7, -5 + 3, -5 + 0 = 2, -2, -5
+    # (a modulo reduction, u % 16, would give 9, 10, 8 instead)
+    assert [O.seeded_value(0, 0, i, 0, 16) for i in range(3)] == [14, 6, 0]
+    assert [O.seeded_value(0, 0, i, 0, 100) for i in range(3)] == [88, 43, 2]
+    assert [O.seeded_value(0, 0, i, -5, 3) for i in range(3)] == [2, -2, -5]
+    # full int32 range: -2^31 + u = -2147483648 + 3793791033
+    assert O.seeded_value(0, 0, 0, -(2 ** 31), 2 ** 31) == 1646307385
+
+
+def test_seeded_counter_form():
+    # The seed is added to golden * counter: starting from seed = golden * k
+    # the sequence is the published one shifted by k outputs.  Stream s,
+    # index i is counter s * 2^32 + i + 1.
+    golden = 0x9E3779B97F4A7C15
+    assert O.seeded_value(golden % 2 ** 64, 0, 0, 0, 2 ** 32) & 0xFFFFFFFF == 0x6E789E6A
+    assert O.seeded_value(2 * golden % 2 ** 64, 0, 0, 0, 2 ** 32) & 0xFFFFFFFF == 0x06C45D18
+    for i in range(4):
+        assert O.seeded_value(0, 1, i, 0, 2 ** 32) == O.seeded_value((golden << 32) % 2 ** 64, 0, i, 0, 2 ** 32)
+
+
 def test_seeded_range_bounds():
     for lo, hi in [(0, 16), (-5, 3), (-(2 ** 31), 2 ** 31), (7, 8)]:
         vals = [O.seeded_value(123, 2, i, lo, hi) for i in range(2000)]

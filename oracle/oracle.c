@@ -758,13 +758,14 @@ static void emit_record(Group* g, const PairState* s, uint32_t array, uint32_t c
   rec_push(g->recs, r);
 }
 
-static const Access* g_sort_base;
-static int cmp_cell_idx(const void* x, const void* y) {
-  const Access* a = &g_sort_base[*(const size_t*)x];
-  const Access* b = &g_sort_base[*(const size_t*)y];
+/* bucketing key of one access: (array, cell), then its position in the log */
+typedef struct { uint32_t array, cell; size_t pos; } CellKey;
+static int cmp_cell_key(const void* x, const void* y) {
+  const CellKey* a = (const CellKey*)x;
+  const CellKey* b = (const CellKey*)y;
   if (a->array != b->array) return a->array < b->array ? -1 : 1;
   if (a->cell != b->cell) return a->cell < b->cell ? -1 : 1;
-  return (*(const size_t*)x < *(const size_t*)y) ? -1 : 1;
+  return a->pos < b->pos ? -1 : (a->pos > b->pos ? 1 : 0);
 }
 
 static void check_scope(Group* g, const Access* acc, size_t n, int inter,
@@ -791,10 +792,12 @@ static void check_scope(Group* g, const Access* acc, size_t n, int inter,
     free(cells);
     return;
   }
+  CellKey* keys = (CellKey*)malloc(n * sizeof(CellKey));
   size_t* idx = (size_t*)malloc(n * sizeof(size_t));
-  for (size_t i = 0; i < n; i++) idx[i] = i;
-  g_sort_base = acc;
-  qsort(idx, n, sizeof(size_t), cmp_cell_idx);
+  for (size_t i = 0; i < n; i++) { keys[i].array = acc[i].array; keys[i].cell = acc[i].cell; keys[i].pos = i; }
+  qsort(keys, n, sizeof(CellKey), cmp_cell_key);
+  for (size_t i = 0; i < n; i++) idx[i] = keys[i].pos;
+  free(keys);
   size_t i = 0;
   while (i < n) {
     size_t j = i;

@@ -208,13 +208,19 @@ rc_status rc_bind_scalar(rc_prog* prog, uint32_t scalar_id, int32_t value);
  * library's choice (a call with no global access log places each record by
  * the record counts of the (instance, group, interval)s before it and its
  * rank within its own, with no sort); 1 = always radix-sort the records by
- * their full canonical key.  A batch uses radix_bits and record_sort of its
- * first instance's program; rc_autotune keeps record_sort. */
+ * their full canonical key.  proofs_off: 0 = the library proves, per launch
+ * shape, which arrays can carry no record and whether the program can fault
+ * (see rc_prog_owned and rc_log_intervals) and skips the logs and group
+ * steps those proofs make unnecessary; 1 = no proof: every access to a
+ * written array is logged and checked (the reports are the same).  A batch
+ * uses radix_bits and record_sort of its first instance's program;
+ * rc_autotune keeps record_sort and proofs_off. */
 typedef struct {
   uint32_t lds_log_entries;
   uint32_t radix_bits;
   uint32_t record_sort;
-  uint32_t reserved[5];
+  uint32_t proofs_off;
+  uint32_t reserved[4];
 } rc_tuning;
 rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
 
@@ -290,6 +296,20 @@ rc_status rc_batch_check(rc_ctx* ctx, rc_prog* const* programs, const uint64_t* 
 /* Wait for the ctx stream; returns RC_E_OVERFLOW or RC_E_HIP for deferred
  * failures of earlier rc_check calls on this ctx, then clears them. */
 rc_status rc_sync(rc_ctx* ctx);
+
+/* Log statistics of the last rc_check / rc_batch_check call on the context
+ * (waits for the stream; the workspace of that call must not have been
+ * reused since).  logged: accesses appended to an interval log (accesses
+ * to arrays never written, and those the static proofs exempt, are not
+ * logged); logged_global: entries written to the global access log (arrays
+ * logged there, and intervals that outgrew the LDS log); intervals_spilled:
+ * intervals whose LDS log moved to the global log; intervals: intervals
+ * closed, summed over work-groups and instances.  RC_E_STATE before the
+ * first check call. */
+typedef struct {
+  uint64_t logged, logged_global, intervals_spilled, intervals;
+} rc_stats;
+rc_status rc_call_stats(rc_ctx* ctx, rc_stats* out);
 
 /* Final contents of global array `array_id` for one seed (asynchronous):
  * per cell, the value left by the highest work-group that wrote it, else the

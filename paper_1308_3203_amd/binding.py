@@ -41,7 +41,7 @@ EXPORTS = [
     "rc_features_workspace_size", "rc_features", "rc_mlp_workspace_size", "rc_mlp_forward", "rc_mlp_grad",
     "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank", "rc_prog_jit", "rc_prog_owned",
     "rc_owned_arrays",
-    "rc_log_intervals",
+    "rc_log_intervals", "rc_call_stats",
 ]
 N_FEATURES = 128
 MLP_PARAMS = 99073
@@ -58,9 +58,15 @@ class _Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint32 * 8)]
 
 
+class _Stats(ctypes.Structure):
+    _fields_ = [("logged", ctypes.c_uint64), ("logged_global", ctypes.c_uint64),
+                ("intervals_spilled", ctypes.c_uint64), ("intervals", ctypes.c_uint64)]
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_log_entries", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
-                ("record_sort", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+                ("record_sort", ctypes.c_uint32), ("proofs_off", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -113,6 +119,7 @@ def load_library(path: str = LIB_PATH):
         "rc_read_final": ([vp, u64, u32, vp, vp, sz], ctypes.c_int),
         "rc_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "rc_ctx_profile_read": ([vp, ctypes.POINTER(_Profile)], ctypes.c_int),
+        "rc_call_stats": ([vp, ctypes.POINTER(_Stats)], ctypes.c_int),
         "rc_prog_set_tuning": ([vp, ctypes.POINTER(_Tuning)], ctypes.c_int),
         "rc_autotune": ([vp, u64, u32, vp, sz, ctypes.c_char_p, ctypes.POINTER(_Tuning)], ctypes.c_int),
         "rc_batch_check": ([vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_uint64), u32, vp, sz,
@@ -289,6 +296,12 @@ class Context:
         _call(_lib.rc_ctx_profile_read, self._h, ctypes.byref(out))
         return {PHASES[i]: (float(out.ms[i]), int(out.launches[i])) for i in range(len(PHASES))}
 
+    def call_stats(self) -> dict:
+        """Log statistics of the last check call (waits for the stream)."""
+        out = _Stats()
+        _call(_lib.rc_call_stats, self._h, ctypes.byref(out))
+        return {k: int(getattr(out, k)) for k, _ in _Stats._fields_}
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.rc_ctx_destroy(self._h)
@@ -398,11 +411,13 @@ class Program:
         checks then run it instead of the interpreter."""
         _call(_lib.rc_prog_jit, self._h, 1 if enable else 0)
 
-    def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0, record_sort: int = 0):
+    def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0, record_sort: int = 0,
+                   proofs_off: bool = False):
         t = _Tuning()
         t.lds_log_entries = lds_log_entries
         t.radix_bits = radix_bits
         t.record_sort = record_sort
+        t.proofs_off = 1 if proofs_off else 0
         _call(_lib.rc_prog_set_tuning, self._h, ctypes.byref(t))
 
     def autotune(self, seed0: int, n_seeds: int, ws, cache_path: str | None = None) -> dict:

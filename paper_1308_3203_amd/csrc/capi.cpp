@@ -80,6 +80,7 @@ struct rc_ctx {
   hipStream_t capture_stream = nullptr;    // private stream used only to capture graphs
   std::vector<hipGraphExec_t> graphs_to_free;   // executable graphs of calls in flight
   bool use_graphs = true;
+  u64* last_stats = nullptr;               // log statistics of the last check call (device)
 };
 
 struct rc_prog {
@@ -94,6 +95,7 @@ struct rc_prog {
   uint32_t lds_log_pref = 0;         // tuning: LDS log entries (0: the library's choice)
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t record_sort = 0;          // tuning: 1 = always sort records by their full key
+  uint32_t proofs_off = 0;           // tuning: 1 = no static proof (every written array logged)
   bool never_faults = false;         // proven for the current shape
   uint64_t log_mask = ~0ull;         // intervals whose local-array accesses are logged (ProgDesc)
   uint32_t log_high = 1;
@@ -319,7 +321,8 @@ struct Layout {
 // counters block: [0] log entries, [1] records, [2] status word, [3] long runs
 // per-chunk counters: log entries, record slots reserved, status bits,
 // queued long runs, record slots left unused, records (reserved - unused)
-enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_DEAD = 4, CNT_LIVE = 5, CNT_WORDS = 8 };
+enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_DEAD = 4, CNT_LIVE = 5, CNT_STATS = 8,
+       N_STATS = 4, CNT_WORDS = 16 };
 
 void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n_items) {
   size_t o = 0;
@@ -609,6 +612,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     // owner words need no clearing: each is written before it is read
     P.cell_owner = (L.filter && do_log) ? (uint32_t*)(ws + L.cc) : nullptr;
     P.cell_owner_stride = L.cc_stride;
+    P.stats = do_log ? cnt + CNT_STATS : nullptr;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     // a call of one program with a compiled kernel runs that kernel; any
@@ -812,6 +816,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
   HIP_TRY(hipEventRecord(ctx->upload_done, st));
   HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.chunk_index), 1, 0u, st));
   HIP_TRY(launch_fill_u32((uint32_t*)(cnt + CNT_STATUS), 1, 0u, st));
+  HIP_TRY(launch_fill_u64(cnt + CNT_STATS, N_STATS, 0ull, st));
+  if (do_log) ctx->last_stats = cnt + CNT_STATS;
   if (d_n_records) HIP_TRY(launch_fill_u64((u64*)d_n_records, 1, 0ull, st));
   const size_t n_chunks = C.chunks.size();
   // With several chunks and no profiling, capture one chunk's kernels as a
@@ -1116,6 +1122,8 @@ rc_status rc_prog_jit(rc_prog* p, int enable) {
   return jit_build(p);
 }
 
+static rc_status apply_shape(rc_prog* p);
+
 rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   if (!p) return fail(RC_E_INVAL, "prog is NULL");
   if (group_size < 1 || group_size > MAX_WG) return fail(RC_E_LIMIT, "group size must be in [1, 1024]");
@@ -1130,7 +1138,17 @@ rc_status rc_set_ndrange(rc_prog* p, uint32_t num_groups, uint32_t group_size) {
   p->G = num_groups;
   p->W = W;
   p->shaped = true;
-  const Ownership proof = prove_ownership(p->c, p->G, p->W);
+  return apply_shape(p);
+}
+
+// The program's descriptors for its launch shape and tuning: the static
+// proofs (none when the tuning turns them off), overlay placement, log cell
+// keys and the LDS log size; a per-program kernel for the shape.
+static rc_status apply_shape(rc_prog* p) {
+  const uint32_t W = p->W;
+  Ownership proof;
+  if (p->proofs_off) proof.arrays.assign(p->c.arrays.size(), OwnedArray());
+  else proof = prove_ownership(p->c, p->G, p->W);
   const std::vector<OwnedArray>& own = proof.arrays;
   // not logged: owned arrays, and local arrays race-free within every interval
   p->owned.assign(own.size(), 0);
@@ -1235,9 +1253,13 @@ rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   if (!p || !t) return fail(RC_E_INVAL, "NULL argument");
   if (t->radix_bits > 8) return fail(RC_E_INVAL, "radix_bits must be in 1..8 (0: default)");
   if (t->record_sort > 1) return fail(RC_E_INVAL, "record_sort must be 0 or 1");
+  if (t->proofs_off > 1) return fail(RC_E_INVAL, "proofs_off must be 0 or 1");
   p->record_sort = t->record_sort;
   p->lds_log_pref = t->lds_log_entries;
   p->radix_bits = t->radix_bits ? t->radix_bits : 8;
+  const bool reprove = p->proofs_off != t->proofs_off;
+  p->proofs_off = t->proofs_off;
+  if (p->shaped && reprove) return apply_shape(p);
   if (p->shaped) p->lds_log_cap = lds_log_entries(p);
   if (p->jit_on && p->shaped && !jit_current(p)) return jit_build(p);
   return RC_OK;
@@ -1309,6 +1331,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
   rc_tuning t;
   if (cache_path && cache_lookup(cache_path, key, &t)) {
     t.record_sort = p->record_sort;
+    t.proofs_off = p->proofs_off;
     s = rc_prog_set_tuning(p, &t);
     if (s) return s;
     *chosen = t;
@@ -1331,6 +1354,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
       c.lds_log_entries = T;
       c.radix_bits = d;
       c.record_sort = p->record_sort;
+      c.proofs_off = p->proofs_off;
       cands.push_back(c);
     }
   }
@@ -1395,6 +1419,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
     back.lds_log_entries = saved_pref;
     back.radix_bits = saved_bits;
     back.record_sort = p->record_sort;
+    back.proofs_off = p->proofs_off;
     rc_prog_set_tuning(p, &back);
     return result;
   }
@@ -1511,6 +1536,20 @@ rc_status rc_sync(rc_ctx* ctx) {
   }
   ctx->pending.clear();
   if (result != RC_OK) return fail(result, "%s", msg.c_str());
+  return RC_OK;
+}
+
+rc_status rc_call_stats(rc_ctx* ctx, rc_stats* out) {
+  if (!ctx || !out) return fail(RC_E_INVAL, "NULL argument");
+  if (!ctx->last_stats) return fail(RC_E_STATE, "no check call on this context yet");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  u64 v[N_STATS];
+  HIP_TRY(hipMemcpy(v, ctx->last_stats, sizeof v, hipMemcpyDeviceToHost));
+  out->logged = v[0];
+  out->logged_global = v[1];
+  out->intervals_spilled = v[2];
+  out->intervals = v[3];
   return RC_OK;
 }
 

@@ -376,6 +376,7 @@ struct ItemView {
   u64* wg_base;
   uint32_t* cell_owner;    // see PassParams
   uint32_t co_stride;
+  u64* stats;              // see PassParams (may be null)
 };
 
 __device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE32, NONE32, NONE32, NONE32}; }
@@ -412,6 +413,8 @@ struct Item {
   uint32_t lds_used;       // entries of the current interval in the LDS log
   bool lds_spilled;        // the current interval moved to the global log
   uint32_t step, last_spc, store_seq, interval, parity, n_acc;
+  uint32_t n_logged;       // this work-item's logged accesses
+  uint32_t n_spilled;      // intervals of the group whose log moved to the global log
   u64 my_fault;            // earliest fault of this work-item (fault_key order)
   bool faulted;
 
@@ -470,6 +473,7 @@ struct Item {
     lds_used = 0;
     lds_spilled = false;
     step = 0; last_spc = ~0u; store_seq = 0; interval = 0; parity = 0; n_acc = 0;
+    n_logged = 0; n_spilled = 0;
     my_fault = ~0ull;
     faulted = false;
   }
@@ -816,6 +820,7 @@ struct Item {
     const bool quiet = A.kind == AK_LOCAL && A.logged != LOG_NONE &&
                        !(interval < 64u ? ((P.log_mask >> interval) & 1ull) != 0ull : P.log_high != 0u);
     const bool rec = active && P.do_log && A.logged != LOG_NONE && !quiet;
+    n_logged += rec ? 1u : 0u;
     // the barrier completes every earlier statement's accesses, publishes
     // pending faults (a faulting statement has no effect) and each wave's
     // number of log entries for this statement; a nosync array needs none
@@ -927,6 +932,7 @@ struct Item {
         log_used += lds_used;
         lds_used = 0;
         lds_spilled = true;
+        ++n_spilled;
         to_lds = false;
       }
       const uint32_t below = prefix + (uint32_t)__popcll(brec & ((1ull << lane) - 1ull));
@@ -1001,6 +1007,18 @@ struct Item {
     u64 acc = n_acc;
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
     if (lane == 0 && acc) atomicAdd(&P.inst_acc[slot], acc);
+    // the call's log statistics: logged accesses, those in the global log,
+    // intervals moved to the global log, intervals closed
+    if (P.stats) {
+      u64 lg = n_logged;
+      for (int off = 32; off > 0; off >>= 1) lg += __shfl_down(lg, off);
+      if (lane == 0 && lg) atomicAdd(&P.stats[0], lg);
+      if (tl == 0) {
+        if (log_used) atomicAdd(&P.stats[1], (u64)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap));
+        if (n_spilled) atomicAdd(&P.stats[2], (u64)n_spilled);
+        atomicAdd(&P.stats[3], (u64)(interval + 1u));
+      }
+    }
     __syncthreads();
   }
 };
@@ -1054,6 +1072,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.inst_acc = PP.inst_acc; P.inst_intervals = PP.inst_intervals; P.inst_fault = PP.inst_fault;
     P.wg_count = PP.wg_count; P.wg_base = PP.wg_base;
     P.cell_owner = PP.cell_owner; P.co_stride = PP.cell_owner_stride;
+    P.stats = PP.stats;
 #ifdef RC_JIT_W
     // A per-program kernel is compiled for one launch shape: its constants
     // replace the descriptor's fields, so the compiler folds them.  A

@@ -171,6 +171,10 @@ struct PassParams {
   // cell can hold an eligible pair in any scope)
   uint32_t* cell_owner;
   uint32_t cell_owner_stride, pad_co;
+  // the call's log statistics (summed over chunks), or null: [0] logged
+  // accesses, [1] entries written to the global log, [2] intervals whose LDS
+  // log moved to the global log, [3] intervals closed
+  unsigned long long* stats;
 };
 constexpr uint32_t OWNER_SHARED = 0xFFFFFFFFu;
 

@@ -589,6 +589,219 @@ class Enumerator {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Third proof, by value ranges, of "no statement can fault" only: every
+// register holds an interval of int32 values (private variables start at
+// 0; loaded values and scalar parameters are any int32), the two branches
+// of an if are joined by their hull, and a loop's entry state is iterated
+// to a fixed point (registers still changing after a few passes become any
+// int32).  No statement can fault when every index's interval lies inside
+// its array, no divisor's interval holds 0, every assert and assume
+// condition's interval excludes 0, and no barrier is inside an if (loop
+// bounds are constants, so every work-item of a group then passes the same
+// barriers).  Unlike the enumeration it needs no input-independent
+// accesses: an index (e) mod size(A) is in bounds whatever e is.
+// ---------------------------------------------------------------------------
+struct Iv {
+  int64_t lo, hi;
+  bool operator==(const Iv& o) const { return lo == o.lo && hi == o.hi; }
+};
+
+class RangeProver {
+ public:
+  RangeProver(const Compiled& c, uint32_t G, uint32_t W) : c_(c), G_(G), W_(W) {}
+
+  bool run() {
+    std::vector<Iv> env(MAX_REGS, Iv{0, 0});
+    ok_ = true;
+    block(0, (uint32_t)(c_.code.size() / 4), env, 0);
+    return ok_ && visits_ <= VISIT_MAX;
+  }
+
+ private:
+  const Compiled& c_;
+  const uint32_t G_, W_;
+  bool ok_ = true;
+  uint64_t visits_ = 0;
+  static constexpr int WIDEN_AFTER = 8;
+
+  uint32_t word(uint32_t i, int k) const { return c_.code[4 * i + k]; }
+  static Iv full() { return Iv{I32_MIN, I32_MAX}; }
+  static Iv konst(int64_t v) { return Iv{v, v}; }
+  // a result outside int32 wraps: any int32
+  static Iv clamp(i128 lo, i128 hi) {
+    if (lo < I32_MIN || hi > I32_MAX) return full();
+    return Iv{(int64_t)lo, (int64_t)hi};
+  }
+  static int64_t mag(const Iv& y) { return std::max(y.lo < 0 ? -y.lo : y.lo, y.hi < 0 ? -y.hi : y.hi); }
+  static bool has_zero(const Iv& y) { return y.lo <= 0 && y.hi >= 0; }
+  static int64_t ones_above(int64_t v) {   // 2^k - 1 >= v
+    int64_t m = 0;
+    while (m < v) m = m * 2 + 1;
+    return m;
+  }
+
+  Iv operand(bool imm, uint32_t w, const std::vector<Iv>& env) const {
+    if (imm) return konst((int32_t)w);
+    if (w < MAX_REGS) return env[w];
+    switch (w) {
+      case SEL_LID: return Iv{0, (int64_t)W_ - 1};
+      case SEL_GID: return Iv{0, (int64_t)G_ - 1};
+      case SEL_TID: return Iv{0, (int64_t)G_ * W_ - 1};
+      case SEL_WGSIZE: return konst(W_);
+      case SEL_NGROUPS: return konst(G_);
+      case SEL_NTHREADS: return konst((int64_t)G_ * W_);
+      default: return full();   // scalar parameters
+    }
+  }
+
+  Iv binary(uint32_t op, const Iv& x, const Iv& y) {
+    switch (op) {
+      case B_ADD: return clamp((i128)x.lo + y.lo, (i128)x.hi + y.hi);
+      case B_SUB: return clamp((i128)x.lo - y.hi, (i128)x.hi - y.lo);
+      case B_MUL: {
+        const i128 p[4] = {(i128)x.lo * y.lo, (i128)x.lo * y.hi, (i128)x.hi * y.lo, (i128)x.hi * y.hi};
+        return clamp(*std::min_element(p, p + 4), *std::max_element(p, p + 4));
+      }
+      case B_DIV: {   // |x / y| <= |x| for |y| >= 1 (INT_MIN / -1 = INT_MIN stays inside)
+        if (has_zero(y)) { ok_ = false; return full(); }
+        const int64_t m = mag(x);
+        return Iv{std::max(-m, I32_MIN), std::min(m, I32_MAX)};
+      }
+      case B_REM: {   // sign of x, |r| < |y|, |r| <= |x|
+        if (has_zero(y)) { ok_ = false; return full(); }
+        const int64_t m = mag(y) - 1;
+        return Iv{x.lo >= 0 ? 0 : std::max(x.lo, -m), x.hi <= 0 ? 0 : std::min(x.hi, m)};
+      }
+      case B_MOD: {   // in [0, |y|)
+        if (has_zero(y)) { ok_ = false; return full(); }
+        const int64_t m = mag(y) - 1;
+        return Iv{0, x.lo >= 0 ? std::min(x.hi, m) : m};
+      }
+      case B_AND:
+        if (x.lo >= 0 && y.lo >= 0) return Iv{0, std::min(x.hi, y.hi)};
+        if (x.lo >= 0) return Iv{0, x.hi};
+        if (y.lo >= 0) return Iv{0, y.hi};
+        return full();
+      case B_OR:
+      case B_XOR:
+        if (x.lo >= 0 && y.lo >= 0) return Iv{0, ones_above(std::max(x.hi, y.hi))};
+        return full();
+      case B_SHL:
+        if (y.lo == y.hi) {
+          const int k = (int)(((y.lo % 32) + 32) % 32);
+          return clamp((i128)x.lo << k, (i128)x.hi << k);
+        }
+        return full();
+      case B_SHR:
+        if (y.lo == y.hi) {
+          const int k = (int)(((y.lo % 32) + 32) % 32);
+          return Iv{x.lo >> k, x.hi >> k};
+        }
+        if (x.lo >= 0) return Iv{0, x.hi};
+        if (x.hi < 0) return Iv{x.lo, -1};
+        return x;
+      case B_MIN: return Iv{std::min(x.lo, y.lo), std::min(x.hi, y.hi)};
+      case B_MAX: return Iv{std::max(x.lo, y.lo), std::max(x.hi, y.hi)};
+      default: return Iv{0, 1};   // comparisons and logical operators
+    }
+  }
+
+  void check_index(uint32_t a, const Iv& idx) {
+    if (a >= c_.arrays.size() || idx.lo < 0 || idx.hi >= (int64_t)c_.arrays[a].size) ok_ = false;
+  }
+
+  static void hull(std::vector<Iv>& a, const std::vector<Iv>& b) {
+    for (size_t r = 0; r < a.size(); ++r) a[r] = Iv{std::min(a[r].lo, b[r].lo), std::max(a[r].hi, b[r].hi)};
+  }
+
+  // instructions [i, end) of one structured block, `ifs` ifs deep
+  void block(uint32_t i, uint32_t end, std::vector<Iv>& env, uint32_t ifs) {
+    while (i < end && ok_) {
+      if (++visits_ > VISIT_MAX) { ok_ = false; return; }
+      const uint32_t h = word(i, 0), op = h & 63u, sub = (h >> 8) & 63u, dst = (h >> 14) & 63u;
+      const bool fa = (h >> 6) & 1u, fb = (h >> 7) & 1u;
+      switch (op) {
+        case OP_BIN:
+          env[dst] = binary(sub, operand(fa, word(i, 1), env), operand(fb, word(i, 2), env));
+          ++i;
+          break;
+        case OP_UN: {
+          const Iv x = operand(fa, word(i, 1), env);
+          if (sub == U_MOV) env[dst] = x;
+          else if (sub == U_NEG) env[dst] = clamp(-(i128)x.hi, -(i128)x.lo);
+          else if (sub == U_BNOT) env[dst] = Iv{-x.hi - 1, -x.lo - 1};
+          else env[dst] = Iv{0, 1};
+          ++i;
+          break;
+        }
+        case OP_LOAD:
+          check_index(word(i, 3), operand(fa, word(i, 1), env));
+          env[dst] = full();
+          ++i;
+          break;
+        case OP_STORE:
+          check_index(word(i, 3), operand(fa, word(i, 1), env));
+          ++i;
+          break;
+        case OP_IF: {
+          const uint32_t at_else = word(i, 2), at_endif = word(at_else, 3);
+          std::vector<Iv> other = env;
+          block(i + 1, at_else, env, ifs + 1);
+          block(at_else + 1, at_endif, other, ifs + 1);
+          hull(env, other);
+          i = at_endif + 1;
+          break;
+        }
+        case OP_FOR: {
+          const int64_t lo = (int32_t)word(i, 1), hi = (int32_t)word(i, 2);
+          const uint32_t after = word(i, 3);
+          if (hi - lo <= 0) {
+            env[dst] = konst(lo);
+            i = after;
+            break;
+          }
+          std::vector<Iv> head = env, body;
+          head[dst] = Iv{lo, hi - 1};
+          for (int pass = 0;; ++pass) {
+            body = head;
+            block(i + 1, after - 1, body, ifs);
+            if (!ok_) return;
+            std::vector<Iv> next = head;
+            hull(next, body);
+            next[dst] = Iv{lo, hi - 1};
+            if (next == head) break;
+            if (pass >= WIDEN_AFTER)
+              for (size_t r = 0; r < next.size(); ++r)
+                if (!(next[r] == head[r])) next[r] = full();
+            head = next;
+          }
+          env = body;
+          env[dst] = konst(hi);
+          i = after;
+          break;
+        }
+        case OP_BARRIER:
+          if (ifs > 0) ok_ = false;   // reached by part of a group: a divergence fault
+          ++i;
+          break;
+        case OP_ASSERT:
+        case OP_ASSUME: {
+          const Iv cnd = operand(fa, word(i, 1), env);
+          if (has_zero(cnd)) ok_ = false;
+          ++i;
+          break;
+        }
+        case OP_END:
+          return;
+        default:   // else, endif
+          ++i;
+          break;
+      }
+    }
+  }
+};
+
 }  // namespace
 
 Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W) {
@@ -607,7 +820,9 @@ Ownership prove_ownership(const Compiled& c, uint32_t G, uint32_t W) {
   }
   out.local_log_mask = e.racy_mask;
   out.local_log_high = e.racy_high;
-  out.never_faults = e.never_faults;
+  // the value ranges can prove "no fault" where the enumeration gives up
+  // (indices that depend on the inputs)
+  out.never_faults = e.never_faults || RangeProver(c, G, W).run();
   return out;
 }
 

@@ -195,7 +195,19 @@ FAULT_CASES = [
     ("  assert(lid < 10);\n  x[tid] := 1;", 4, 64, False),
     ("  if (lid < 5) {\n    barrier;\n  }\n  x[tid] := 1;", 4, 64, False),   # part of a group at a barrier
     ("  if (gid < 1) {\n    barrier;\n  }\n  x[tid] := 1;", 4, 64, True),    # whole groups agree
-    ("  v := y[tid];\n  if (v < 3) {\n    x[tid] := 1;\n  }", 4, 64, False),   # a data-dependent path
+    # a data-dependent path whose accesses are all in bounds (value ranges)
+    ("  v := y[tid];\n  if (v < 3) {\n    x[tid] := 1;\n  }", 4, 64, True),
+    ("  v := y[tid];\n  x[v mod 4096] := 1;", 4, 64, True),           # Euclidean mod: in [0, 4096)
+    ("  v := y[tid];\n  x[v & 4095] := 1;", 4, 64, True),
+    ("  v := y[tid];\n  x[v % 4096] := 1;", 4, 64, False),           # C99 remainder can be negative
+    ("  v := y[tid];\n  x[v] := 1;", 4, 64, False),                  # a loaded index
+    ("  v := y[tid];\n  x[(v mod 64) + tid] := 1;", 4, 64, True),     # at most 63 + 255
+    ("  v := y[tid];\n  x[(v mod 64) * 64 + 4032] := 1;", 4, 64, False),   # up to 8064
+    ("  v := y[tid];\n  if (v < 3) {\n    barrier;\n  }", 4, 64, False),   # a data-dependent barrier
+    ("  v := y[tid];\n  w := 100 / (v mod 7 + 1);\n  x[tid] := w;", 4, 64, True),   # divisor in [1, 7]
+    ("  v := y[tid];\n  w := 100 / (v mod 7);\n  x[tid] := w;", 4, 64, False),      # divisor may be 0
+    ("  v := y[tid];\n  assert(v mod 5 < 5);\n  x[tid] := 1;", 4, 64, False),  # a condition is 0 or 1
+    ("  for k in 0..16 {\n    v := y[(v + k) mod 4096];\n    x[v mod 4096] := k;\n  }", 1, 256, True),
     ("  for k in 0..4 {\n    barrier;\n    x[tid * 4 + k] := k;\n  }", 4, 64, True),
 ]
 
@@ -371,3 +383,84 @@ def test_quiet_interval_proof_of_shared_global_next_to_local():
         r = O.check(src, 1, W, arrays={"A": ("seeded", 0, 1000), "Bo": ("seeded", 0, 8)}, seed=1)
         got = {(int(x["interval"]), int(x["array"])) for x in r.records}
         assert got == {(0, 0), (1, 2)}
+
+
+def test_never_faults_on_random_kernels_agrees_with_the_oracle():
+    """The batched random kernels (indices of loaded values reduced mod the
+    array size) are proven fault-free by their value ranges; the oracle's
+    runs confirm it on every sampled input."""
+    for pseed in range(0, 400, 20):
+        w = WL.c3_kernel(pseed)
+        assert B.owned_arrays(w.src, w.G, w.W, with_faults=True)[1], w.name
+        prog = O.Program(w.src)
+        for seed in (0, 7):
+            r = prog.run(w.G, w.W, arrays=w.arrays, scalars=w.scalars, seed=seed)
+            assert r.status == "OK", (w.name, seed)
+
+
+def _random_fault_program(r: random.Random) -> str:
+    """Random statements over every operator, loaded values, scalars,
+    asserts, loops and barriers (some under branches)."""
+    ops = ["+", "-", "*", "/", "%", "mod", "&", "|", "^", "<<", ">>", "<", "==", "&&"]
+
+    def e(d=0):
+        k = r.random()
+        if d >= 2 or k < 0.3:
+            return r.choice(["v", "w", "tid", "lid", "gid", "s", str(r.randint(-9, 300)), "k", "j"])
+        if k < 0.4:
+            return f"min({e(d + 1)}, {e(d + 1)})"
+        if k < 0.5:
+            return f"max({e(d + 1)}, {e(d + 1)})"
+        return f"({e(d + 1)} {r.choice(ops)} {e(d + 1)})"
+
+    def idx():
+        k = r.random()
+        if k < 0.4:
+            return f"({e()}) mod {r.choice([64, 256, 300])}"
+        if k < 0.6:
+            return f"({e()}) & {r.choice([63, 255, 511])}"
+        if k < 0.8:
+            return f"tid + {r.randint(-2, 40)}"
+        return e()
+
+    def stmts(n, depth):
+        out = []
+        for _ in range(n):
+            k = r.random()
+            if k < 0.3:
+                out.append(f"{r.choice(['v', 'w'])} := {e()};")
+            elif k < 0.5:
+                out.append(f"{r.choice(['v', 'w'])} := {r.choice(['x', 'y'])}[{idx()}];")
+            elif k < 0.65:
+                out.append(f"x[{idx()}] := {e()};")
+            elif k < 0.7:
+                out.append(f"assert({e()});")
+            elif k < 0.78:
+                out.append("barrier;")
+            elif k < 0.9 and depth < 2:
+                out.append(f"if ({e()} < {r.randint(0, 50)}) {{ " + " ".join(stmts(r.randint(1, 3), depth + 1)) + " }")
+            elif depth < 2:
+                lv = "kj"[depth]
+                out.append(f"for {lv} in 0..{r.randint(1, 5)} {{ " + " ".join(stmts(r.randint(1, 3), depth + 1)) + " }")
+        return out
+    return ("kernel f(global int x[300], global int y[300], int s) {\n  int v, w, k, j;\n  "
+            + "\n  ".join(stmts(r.randint(3, 8), 0)) + "\n}\n")
+
+
+def test_range_proof_never_contradicts_the_oracle():
+    """Fuzz: wherever the proofs say a program cannot fault, the oracle runs
+    it without a fault on several inputs and launch shapes."""
+    r = random.Random(4242)
+    proven = 0
+    for case in range(600):
+        src = _random_fault_program(r)
+        G, W = r.choice([(1, 64), (2, 32), (3, 7), (1, 100)])
+        if not B.owned_arrays(src, G, W, with_faults=True)[1]:
+            continue
+        proven += 1
+        prog = O.Program(src)
+        for seed in range(3):
+            res = prog.run(G, W, arrays={"x": ("seeded", -50, 400), "y": ("seeded", -(2 ** 31), 2 ** 31)},
+                           scalars={"s": ("seeded", -(2 ** 31), 2 ** 31)}, seed=seed)
+            assert res.status == "OK", (src, G, W, seed, res.status)
+    assert proven >= 60

@@ -96,6 +96,7 @@ struct rc_prog {
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t record_sort = 0;          // tuning: 1 = always sort records by their full key
   uint32_t proofs_off = 0;           // tuning: 1 = no static proof (every written array logged)
+  uint32_t step_limit = DEFAULT_STEP_LIMIT;   // tuning: loop iterations a work-group may start
   bool never_faults = false;         // proven for the current shape
   uint64_t log_mask = ~0ull;         // intervals whose local-array accesses are logged (ProgDesc)
   uint32_t log_high = 1;
@@ -789,6 +790,10 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     D.wg_log_cap = wg_log_entries(p);
     D.log_mask = p->log_mask;
     D.log_high = p->log_high;
+    // interpreted programs that cannot fault elide group steps (the code's
+    // per-instruction flags, set for the current shape)
+    D.nf = !C.jit && p->never_faults ? 1u : 0u;
+    D.step_limit = p->step_limit;
   }
   rc_record_out R;
   memset(&R, 0, sizeof R);
@@ -1050,7 +1055,7 @@ rc_status rc_owned_arrays(const char* src, size_t len, uint32_t num_groups, uint
   if (!compile_program(src, len, &c, &err, &is_limit)) return fail(is_limit ? RC_E_LIMIT : RC_E_PARSE, "%s", err.c_str());
   const Ownership proof = prove_ownership(c, num_groups, group_size);
   const std::vector<OwnedArray>& o = proof.arrays;
-  if (never_faults) *never_faults = proof.never_faults ? 1 : 0;
+  if (never_faults) *never_faults = proof.never_faults && c.dyn_iters <= DEFAULT_STEP_LIMIT ? 1 : 0;
   *n_arrays = (uint32_t)o.size();
   for (uint32_t a = 0; a < capacity && a < o.size(); ++a) owned[a] = o[a].owned ? 1 : (o[a].race_free ? 2 : 0);
   return RC_OK;
@@ -1175,7 +1180,8 @@ static rc_status apply_shape(rc_prog* p) {
     }
   }
   p->overlay_cells = ov;
-  p->never_faults = proof.never_faults;
+  // (a program that can reach the loop-iteration limit can stop there)
+  p->never_faults = proof.never_faults && p->c.dyn_iters <= p->step_limit;
   p->log_mask = proof.local_log_mask;
   p->log_high = proof.local_log_high ? 1u : 0u;
   for (size_t a = 0; a < own.size(); ++a) {
@@ -1199,6 +1205,21 @@ static rc_status apply_shape(rc_prog* p) {
     if (!p->c.arrays[a].global) p->logged_local -= std::min(p->logged_local, p->c.dyn_mem_array[a]);
   }
   p->lds_log_cap = lds_log_entries(p);
+  // the interpreter's code: load and store instructions of a program that
+  // cannot fault carry INSN_NO_STEP where no conflicting access needs their
+  // group step
+  {
+    std::vector<uint32_t> code = p->c.code;
+    if (p->never_faults) {
+      const std::vector<uint8_t> keep = group_steps(p->c.code, jit_shape_of(p), false);
+      for (size_t i = 0; i < keep.size(); ++i) {
+        const uint32_t op = code[4 * i] & 63u;
+        if ((op == OP_LOAD || op == OP_STORE) && !keep[i]) code[4 * i + 3] |= INSN_NO_STEP;
+      }
+    }
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(hipMemcpy(p->d_mem, code.data(), code.size() * 4, hipMemcpyHostToDevice));
+  }
   // a per-program kernel is compiled for one launch shape
   if (p->jit_on && !jit_current(p)) return jit_build(p);
   return RC_OK;
@@ -1257,8 +1278,10 @@ rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   p->record_sort = t->record_sort;
   p->lds_log_pref = t->lds_log_entries;
   p->radix_bits = t->radix_bits ? t->radix_bits : 8;
-  const bool reprove = p->proofs_off != t->proofs_off;
+  const uint32_t limit = t->step_limit ? t->step_limit : DEFAULT_STEP_LIMIT;
+  const bool reprove = p->proofs_off != t->proofs_off || p->step_limit != limit;
   p->proofs_off = t->proofs_off;
+  p->step_limit = limit;
   if (p->shaped && reprove) return apply_shape(p);
   if (p->shaped) p->lds_log_cap = lds_log_entries(p);
   if (p->jit_on && p->shaped && !jit_current(p)) return jit_build(p);
@@ -1332,6 +1355,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
   if (cache_path && cache_lookup(cache_path, key, &t)) {
     t.record_sort = p->record_sort;
     t.proofs_off = p->proofs_off;
+    t.step_limit = p->step_limit;
     s = rc_prog_set_tuning(p, &t);
     if (s) return s;
     *chosen = t;
@@ -1355,6 +1379,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
       c.radix_bits = d;
       c.record_sort = p->record_sort;
       c.proofs_off = p->proofs_off;
+      c.step_limit = p->step_limit;
       cands.push_back(c);
     }
   }
@@ -1420,6 +1445,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
     back.radix_bits = saved_bits;
     back.record_sort = p->record_sort;
     back.proofs_off = p->proofs_off;
+    back.step_limit = p->step_limit;
     rc_prog_set_tuning(p, &back);
     return result;
   }

@@ -377,6 +377,8 @@ struct ItemView {
   uint32_t* cell_owner;    // see PassParams
   uint32_t co_stride;
   u64* stats;              // see PassParams (may be null)
+  uint32_t nf;             // elided group steps (ProgDesc::nf)
+  uint32_t step_limit;     // loop iterations the group may start
 };
 
 __device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE32, NONE32, NONE32, NONE32}; }
@@ -413,6 +415,7 @@ struct Item {
   uint32_t lds_used;       // entries of the current interval in the LDS log
   bool lds_spilled;        // the current interval moved to the global log
   uint32_t step, last_spc, store_seq, interval, parity, n_acc;
+  uint32_t iters;          // loop iterations the group started (uniform)
   uint32_t n_logged;       // this work-item's logged accesses
   uint32_t n_spilled;      // intervals of the group whose log moved to the global log
   u64 my_fault;            // earliest fault of this work-item (fault_key order)
@@ -462,6 +465,7 @@ struct Item {
     if (tl == 0) {
       ctl->fault = ~0ull;
       ctl->lds_cnt[0] = ctl->lds_cnt[1] = 0u;
+      ctl->gl_cnt = 0ull;
     }
     if (tl < P.n_scalars) {
       const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
@@ -473,7 +477,7 @@ struct Item {
     lds_used = 0;
     lds_spilled = false;
     step = 0; last_spc = ~0u; store_seq = 0; interval = 0; parity = 0; n_acc = 0;
-    n_logged = 0; n_spilled = 0;
+    n_logged = 0; n_spilled = 0; iters = 0;
     my_fault = ~0ull;
     faulted = false;
   }
@@ -481,6 +485,15 @@ struct Item {
   // statements are numbered by execution: a new statement pc starts a new step
   __device__ __forceinline__ void stmt(uint32_t spc) {
     if (spc != last_spc) { ++step; last_spc = spc; }
+  }
+
+  // A loop iteration starts (every thread, at the same point): true when
+  // the group has started more than its limit, a fault of the whole group
+  // (reported for its first work-item; every wave stops here).
+  __device__ __forceinline__ bool iter_start(uint32_t spc) {
+    if (++iters <= P.step_limit) return false;
+    raise(spc, F_STEP_LIMIT);
+    return true;
   }
 
   // lid, tid, gid, wgsize, ngroups, nthreads, scalar parameters
@@ -570,6 +583,10 @@ struct Item {
     (void)code;
     atomicOr(P.status_word, 16u);
 #else
+    if (P.nf) {   // proven not to fault: a fault means the proof is wrong
+      atomicOr(P.status_word, 16u);
+      return;
+    }
     const u64 k = fault_key(step, tl, spc, code);
     if (k < my_fault) my_fault = k;
 #endif
@@ -640,6 +657,38 @@ struct Item {
     return k < rec_room ? rec_at + k : rec_jump + (k - rec_room);
   }
 
+  // Move LDS log entries [0, count) of the current interval to the group's
+  // global log (elided group steps; every thread has passed a barrier since
+  // the interval's last access).
+  __device__ __forceinline__ void spill_nf(uint32_t count) {
+    const u64 base = ((u64)uni((uint32_t)(ctl->gl_cnt >> 32)) << 32) | uni((uint32_t)ctl->gl_cnt);
+    __syncthreads();
+    if (tl == 0) ctl->gl_cnt = base + count;
+    for (uint32_t i = tl; i < count; i += nthr) {
+      const u64 pos = base + i;
+      const u64 e = lkey[i];
+      u64 ck;
+      uint32_t meta, v;
+      if (P.tab_cells) {
+        ck = P.tab_base + (e >> 43);
+        meta = (uint32_t)(e >> 32) & 2047u;   // store flag (bit 10) and local id
+        v = (uint32_t)e;
+      } else {
+        ck = e >> 16;
+        meta = lmeta[i];
+        v = (uint32_t)lval[i];
+      }
+      if (pos < P.wg_log_cap) {
+        P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
+        P.log_vals[log_base + pos] = ((u64)v << 32) | meta;
+        if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
+      } else {
+        atomicOr(P.status_word, 1u);
+      }
+    }
+    __syncthreads();
+  }
+
   // Close the current interval on the LDS path: check its log in LDS (by a
   // per-cell table, or by a bitonic sort and runs) and stage the records of
   // the INTRA scope.  Callers have passed a barrier since the interval's last
@@ -653,7 +702,22 @@ struct Item {
     if (tl == 0) ctl->lds_cnt[(interval + 1u) & 1u] = 0u;
     __syncthreads();
 #else
-    const uint32_t n = lds_used;
+    uint32_t n = lds_used;
+    if (P.nf) {
+      // elided group steps: the entries from the interval's LDS counter (the
+      // next interval's counter was last read at the previous close, before
+      // the barrier every thread passed to get here); an interval that
+      // outgrew the LDS log moves what it holds to the global log, beside
+      // its other entries
+      n = uni(ctl->lds_cnt[interval & 1u]);
+      if (tl == 0) ctl->lds_cnt[(interval + 1u) & 1u] = 0u;
+      __syncthreads();
+      if (n > P.lds_log_cap) {
+        spill_nf(P.lds_log_cap);
+        ++n_spilled;
+        return;
+      }
+    }
 #endif
   const bool spilled = lds_spilled;
   lds_used = 0;
@@ -789,45 +853,12 @@ struct Item {
   __syncthreads();
   }
 
-  // One load or store statement (op OP_LOAD / OP_STORE on array wc) for the
-  // whole group; a load's value goes to `out` on active lanes.  Returns true
-  // when the group stops on a fault (the statement then has no effect).
-  // KIND >= 0: the array's kind (AK_*) known when the caller is compiled,
-  // so only its path is generated; -1: read from the descriptor.
-  // SYNC == false (per-program kernels with RC_JIT_ELIDE only): the
-  // statement needs no group step, because no access since the group's last
-  // synchronisation conflicts with it (a load after a store of the array, or
-  // a store after a load); faults cannot occur and LDS log entries are
-  // numbered by an LDS counter.
-  template <int KIND = -1, bool SYNC = true>
-  __device__ __forceinline__ bool mem(uint32_t op, uint32_t wc, int32_t idx, int32_t val, bool active,
-                                      uint32_t spc, int32_t& out) {
-    ArrayDesc A = array_desc(P.arrays, wc);
-    if (KIND >= 0) A.kind = (uint32_t)KIND;
-    if (KIND == (int)AK_GLOBAL_RO) A.logged = LOG_NONE;   // never written, never logged
-#ifdef RC_JIT_NOFAULT
-    if (active && (idx < 0 || (uint32_t)idx >= A.size)) {   // (reported; the access is dropped)
-      raise(spc, F_OOB);
-      active = false;
-    }
-#else
-    if (!A.nosync && active && (idx < 0 || (uint32_t)idx >= A.size)) raise(spc, F_OOB);   // (nosync: in bounds)
-#endif
-    // a local array's accesses in an interval the proof shows race-free
-    // (no cell written by one work-item and touched by another) can give no
-    // record: they are not logged, and (the program cannot fault) need no
-    // group step
-    const bool quiet = A.kind == AK_LOCAL && A.logged != LOG_NONE &&
-                       !(interval < 64u ? ((P.log_mask >> interval) & 1ull) != 0ull : P.log_high != 0u);
-    const bool rec = active && P.do_log && A.logged != LOG_NONE && !quiet;
-    n_logged += rec ? 1u : 0u;
-    // the barrier completes every earlier statement's accesses, publishes
-    // pending faults (a faulting statement has no effect) and each wave's
-    // number of log entries for this statement; a nosync array needs none
-    // of that
-    u64 brec = 0;
-    uint32_t prefix = 0, total = 0;
-    if (!A.nosync && SYNC && !quiet && mem_red(rec, &brec, &prefix, &total)) return true;
+  // The access itself: a load reads the group's view of the cell (LDS for a
+  // local array; for a global array its overlay word when this chunk wrote
+  // it, else the input); a store applies with the highest work-item's value
+  // staying within one statement (version words compared by atomicMax).
+  __device__ __forceinline__ void access(uint32_t op, uint32_t wc, const ArrayDesc& A, int32_t idx, int32_t val,
+                                         bool active, int32_t& out) {
     const uint32_t cell = (uint32_t)idx;
     // overlay word of the cell: by cell, or for an owned array by (offset
     // from the work-item's stride, lid), which keeps a wave's words together
@@ -872,6 +903,119 @@ struct Item {
         ++n_acc;
       }
     }
+  }
+
+  // Append this lane's entry (when rec) to the global log at a position
+  // reserved with one LDS atomic per wave; lanes in `mask` take part.
+  __device__ __forceinline__ void glog_append(u64 mask, bool mine, u64 ck, uint32_t meta, int32_t v) {
+    if (mask == 0ull) return;
+    u64 base = 0;
+    if (lane == 0) base = atomicAdd(&ctl->gl_cnt, (u64)__popcll(mask));
+    base = ((u64)(uint32_t)__shfl((int)(base >> 32), 0) << 32) | (uint32_t)__shfl((int)(uint32_t)base, 0);
+    if (!mine) return;
+    const u64 pos = base + (u64)__popcll(mask & ((1ull << lane) - 1ull));
+    if (pos < P.wg_log_cap) {
+      P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
+      P.log_vals[log_base + pos] = ((u64)(uint32_t)v << 32) | meta;
+      if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
+    } else {
+      atomicOr(P.status_word, 1u);
+    }
+  }
+
+  // Log an access with elided group steps: an LDS log position from the
+  // interval's LDS counter; entries past the LDS log's end, and accesses to
+  // arrays logged globally, go to the global log (positions from the
+  // group's global counter).  Entry order inside an interval does not
+  // matter to the check.  Called by every lane of the wave.
+  __device__ __forceinline__ void log_nf(uint32_t op, const ArrayDesc& A, uint32_t cell, int32_t val, bool rec) {
+    const u64 br = __ballot(rec);
+    if (br == 0ull) return;
+    const bool store = op == OP_STORE;
+    const uint32_t meta = (store ? 1024u : 0u) | tl;
+    const u64 ck = (u64)A.cellbase + cell;
+    if (A.logged == LOG_LDS) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&ctl->lds_cnt[interval & 1u], (uint32_t)__popcll(br));
+      base = (uint32_t)__shfl((int)base, 0);
+      const uint32_t j = base + (uint32_t)__popcll(br & ((1ull << lane) - 1ull));
+      const bool over = rec && j >= P.lds_log_cap;
+      if (rec && !over) {
+        if (P.tab_cells) {
+          lkey[j] = tab_entry((uint32_t)ck - P.tab_base, store, tl, val);
+        } else {
+          lkey[j] = (ck << 16) | j;
+          lmeta[j] = meta;
+          lval[j] = val;
+        }
+      }
+      glog_append(__ballot(over), over, ck, meta, val);
+    } else {
+      glog_append(br, rec, ck, meta, val);
+    }
+  }
+
+  // One load or store statement (op OP_LOAD / OP_STORE on array wc) for the
+  // whole group; a load's value goes to `out` on active lanes.  Returns true
+  // when the group stops on a fault (the statement then has no effect).
+  // KIND >= 0: the array's kind (AK_*) known when the caller is compiled,
+  // so only its path is generated; -1: read from the descriptor.
+  // SYNC == false (per-program kernels with RC_JIT_ELIDE only): the
+  // statement needs no group step, because no access since the group's last
+  // synchronisation conflicts with it (a load after a store of the array, or
+  // a store after a load); faults cannot occur and LDS log entries are
+  // numbered by an LDS counter.
+  // keep (interpreter, elided group steps only): whether this statement's
+  // group step is kept (INSN_NO_STEP clear).
+  template <int KIND = -1, bool SYNC = true>
+  __device__ __forceinline__ bool mem(uint32_t op, uint32_t wc, int32_t idx, int32_t val, bool active,
+                                      uint32_t spc, int32_t& out, bool keep = true) {
+    ArrayDesc A = array_desc(P.arrays, wc);
+    if (KIND >= 0) A.kind = (uint32_t)KIND;
+    if (KIND == (int)AK_GLOBAL_RO) A.logged = LOG_NONE;   // never written, never logged
+    const bool oob = active && (idx < 0 || (uint32_t)idx >= A.size);
+#ifdef RC_JIT_NOFAULT
+    if (oob) {   // (reported; the access is dropped)
+      raise(spc, F_OOB);
+      active = false;
+    }
+#else
+    if (oob) {
+      if (A.nosync || P.nf) {   // proven in bounds: the proof is wrong (reported; the access is dropped)
+        atomicOr(P.status_word, 16u);
+        active = false;
+      } else {
+        raise(spc, F_OOB);
+      }
+    }
+#endif
+    // a local array's accesses in an interval the proof shows race-free
+    // (no cell written by one work-item and touched by another) can give no
+    // record: they are not logged, and (the program cannot fault) need no
+    // group step
+    const bool quiet = A.kind == AK_LOCAL && A.logged != LOG_NONE &&
+                       !(interval < 64u ? ((P.log_mask >> interval) & 1ull) != 0ull : P.log_high != 0u);
+    const bool rec = active && P.do_log && A.logged != LOG_NONE && !quiet;
+    n_logged += rec ? 1u : 0u;
+#ifndef RC_JIT_W
+    if (P.nf) {
+      // no fault to publish and no entry numbering: synchronise only where
+      // an earlier access since the last synchronisation conflicts
+      if (keep && !quiet && !A.nosync) __syncthreads();
+      access(op, wc, A, idx, val, active, out);
+      if (P.do_log && A.logged != LOG_NONE && !quiet) log_nf(op, A, (uint32_t)idx, val, rec);
+      return false;
+    }
+#endif
+    // the barrier completes every earlier statement's accesses, publishes
+    // pending faults (a faulting statement has no effect) and each wave's
+    // number of log entries for this statement; a nosync array needs none
+    // of that
+    u64 brec = 0;
+    uint32_t prefix = 0, total = 0;
+    if (!A.nosync && SYNC && !quiet && mem_red(rec, &brec, &prefix, &total)) return true;
+    access(op, wc, A, idx, val, active, out);
+    const uint32_t cell = (uint32_t)idx;
 #ifdef RC_JIT_ELIDE
     if (A.logged == LOG_LDS) {
       const u64 br = __ballot(rec);
@@ -992,6 +1136,9 @@ struct Item {
       __syncthreads();
     }
     if (P.do_log) close_interval();
+#ifndef RC_JIT_W
+    if (P.nf) log_used = ctl->gl_cnt;   // (thread 0 reads what the last barrier published)
+#endif
     if (tl == 0) {
       P.wg_count[wg_index] = (uint32_t)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
       P.wg_base[wg_index] = log_base;
@@ -1073,6 +1220,8 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.wg_count = PP.wg_count; P.wg_base = PP.wg_base;
     P.cell_owner = PP.cell_owner; P.co_stride = PP.cell_owner_stride;
     P.stats = PP.stats;
+    P.nf = D.nf;
+    P.step_limit = D.step_limit;
 #ifdef RC_JIT_W
     // A per-program kernel is compiled for one launch shape: its constants
     // replace the descriptor's fields, so the compiler folds them.  A
@@ -1099,6 +1248,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.W = RC_JIT_W; P.G = RC_JIT_G; P.nwaves = (RC_JIT_W + 63u) / 64u; P.n_arrays = RC_JIT_NA;
     P.tab_cells = RC_JIT_TC; P.tab_base = RC_JIT_TB; P.lds_log_cap = RC_JIT_LC;
     P.log_mask = RC_JIT_LOGMASK; P.log_high = RC_JIT_LOGHIGH;
+    P.nf = 0u;
 #endif
     Item it;
     it.init(P, ctl, instance - C.slot0, instance, gid, S.seed, S.log_base + (u64)gid * D.wg_log_cap,

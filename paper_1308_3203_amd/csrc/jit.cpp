@@ -40,12 +40,14 @@ std::string operand(bool imm, uint32_t w) {
 // version words).  Barriers and branch votes synchronise the group, and so
 // does a kept step; the statements of a loop body also follow the body's
 // own end.  Arrays whose accesses never take the step (read-only or owned)
-// cannot conflict; statements on an array logged to the global log keep the
-// step, which numbers its entries.  A kept step on a logged local array
+// cannot conflict; with number_global, statements on an array logged to the
+// global log keep the step, which numbers its entries.  A kept step on a logged local array
 // synchronises only in the intervals whose local accesses are logged (in
 // the others the runtime skips it, the array being race-free there), so
 // unless every interval is logged it does not count as a synchronisation.
-std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitShape& shape) {
+}  // namespace
+
+std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitShape& shape, bool number_global) {
   const uint32_t n = (uint32_t)(code.size() / 4), na = shape.n_arrays;
   std::vector<uint8_t> keep(n, 0);
   auto field = [&](uint32_t a, uint32_t f) { return shape.arrays[a * JIT_ARRAY_WORDS + f]; };
@@ -70,7 +72,7 @@ std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitSha
         }
         if (field(wc, 8)) continue;   // nosync
         const uint8_t bit = op == OP_LOAD ? 1 : 2, other = op == OP_LOAD ? 2 : 1;
-        if ((field(wc, 2) == LOG_GLOBAL || (S[wc] & other)) && !keep[i]) {
+        if (((number_global && field(wc, 2) == LOG_GLOBAL) || (S[wc] & other)) && !keep[i]) {
           keep[i] = 1;
           changed = true;
         }
@@ -92,8 +94,6 @@ std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitSha
   }
   return keep;
 }
-
-}  // namespace
 
 std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32_t threads,
                        const std::vector<uint32_t>& array_kind, const JitShape& shape) {
@@ -122,7 +122,7 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
   s += buf;
   const bool elide = shape.nofault && shape.nospill;
   if (elide) s += "#define RC_JIT_ELIDE 1\n";
-  const std::vector<uint8_t> keep = elide ? group_steps(code, shape) : std::vector<uint8_t>(n, 1);
+  const std::vector<uint8_t> keep = elide ? group_steps(code, shape, true) : std::vector<uint8_t>(n, 1);
   // the arrays' descriptor fields the shape fixes
   s += "#define RC_JIT_ARRAYS 1\n#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n"
        "#include \"rc_internal.h\"\n\nnamespace rc {\n\n"
@@ -222,16 +222,24 @@ std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32
         snprintf(buf, sizeof buf, "  if (%s) R%u = (int32_t)0x%08xu;\n", act, dst, (uint32_t)lo);
         s += buf;
         if ((int64_t)hi - (int64_t)lo <= 0) snprintf(buf, sizeof buf, "  goto L%u;\n", wc);
-        else snprintf(buf, sizeof buf, "  LC%u = 0u;\n", sub);
+        else if (shape.nofault) snprintf(buf, sizeof buf, "  LC%u = 0u;\n", sub);
+        else snprintf(buf, sizeof buf, "  if (it.iter_start(%uu)) { it.faulted = true; goto Ldone; }\n  LC%u = 0u;\n", spc, sub);
         s += buf;
         break;
       }
       case OP_ENDFOR: {
         const int32_t lo = (int32_t)wa, hi = (int32_t)wb;
         const uint32_t iters = (uint32_t)((int64_t)hi - (int64_t)lo);
-        snprintf(buf, sizeof buf,
-                 "  LC%u += 1u; if (%s) R%u = (int32_t)(0x%08xu + LC%u); if (LC%u < %uu) goto L%u;\n", sub, act,
-                 dst, (uint32_t)lo, sub, sub, iters, wc);
+        // (a program proven not to fault never reaches the iteration limit)
+        if (shape.nofault)
+          snprintf(buf, sizeof buf,
+                   "  LC%u += 1u; if (%s) R%u = (int32_t)(0x%08xu + LC%u); if (LC%u < %uu) goto L%u;\n", sub, act,
+                   dst, (uint32_t)lo, sub, sub, iters, wc);
+        else
+          snprintf(buf, sizeof buf,
+                   "  LC%u += 1u; if (%s) R%u = (int32_t)(0x%08xu + LC%u);\n"
+                   "  if (LC%u < %uu) { if (it.iter_start(%uu)) { it.faulted = true; goto Ldone; } goto L%u; }\n",
+                   sub, act, dst, (uint32_t)lo, sub, sub, iters, spc, wc);
         s += buf;
         break;
       }

@@ -39,6 +39,13 @@ struct JitShape {
 std::string jit_source(const std::vector<uint32_t>& code, uint32_t nregs, uint32_t threads,
                        const std::vector<uint32_t>& array_kind, const JitShape& shape);
 
+// Per instruction, whether a load or store keeps its group step when a
+// program that cannot fault runs with elided steps: kept where an access
+// since the group's last synchronisation conflicts with it (see jit.cpp).
+// number_global: statements on arrays logged to the global log keep their
+// step too (their entries are numbered by it).
+std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitShape& shape, bool number_global);
+
 // Compile for gfx950; false with the compiler's log on failure.
 bool jit_compile(const std::string& src, std::vector<char>* code_object, std::string* log);
 

@@ -87,7 +87,10 @@ __device__ __forceinline__ void interp_item(Item& it) {
       const int32_t idx = fetch(fa, wa);
       const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;
       int32_t v = 0;
-      if (it.mem(op, wc, idx, val, active, spc, v)) { it.faulted = true; break; }
+      if (it.mem(op, wc & ~INSN_NO_STEP, idx, val, active, spc, v, (wc & INSN_NO_STEP) == 0u)) {
+        it.faulted = true;
+        break;
+      }
       if (op == OP_LOAD && active) wr(dst, v);
       ++pc;
     } else if (op == OP_IF) {
@@ -113,6 +116,7 @@ __device__ __forceinline__ void interp_item(Item& it) {
       if ((int64_t)hi - (int64_t)lo <= 0) {
         pc = wc;
       } else {
+        if (it.iter_start(spc)) { it.faulted = true; break; }
         if (it.lane == 0) ctl->loopctr[wave][sub] = 0u;
         ++pc;
       }
@@ -122,6 +126,7 @@ __device__ __forceinline__ void interp_item(Item& it) {
       const uint32_t ctr = uni(ctl->loopctr[wave][sub]) + 1u;
       if (it.lane == 0) ctl->loopctr[wave][sub] = ctr;
       if (active) wr(dst, (int32_t)((uint32_t)lo + ctr));
+      if (ctr < iters && it.iter_start(spc)) { it.faulted = true; break; }
       pc = ctr < iters ? wc : pc + 1u;
     } else if (op == OP_BARRIER) {
       if (it.barrier(active, spc)) { it.faulted = true; break; }

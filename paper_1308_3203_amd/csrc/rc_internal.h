@@ -46,7 +46,8 @@ inline uint32_t make_hdr(uint32_t op, bool fa, bool fb, uint32_t sub, uint32_t d
 }
 
 // fault codes (rc_summary.status)
-enum : uint32_t { F_OK = 0, F_OOB = 1, F_DIV = 2, F_ASSERT = 3, F_ASSUME = 4, F_BARDIV = 5 };
+enum : uint32_t { F_OK = 0, F_OOB = 1, F_DIV = 2, F_ASSERT = 3, F_ASSUME = 4, F_BARDIV = 5, F_STEP_LIMIT = 6 };
+constexpr uint32_t DEFAULT_STEP_LIMIT = 1u << 24;
 
 // limits
 enum : uint32_t {
@@ -108,7 +109,12 @@ struct ProgDesc {                 // one program of the call
   const uint32_t* size;           // per array: cells
   uint32_t n_arrays, n_global, n_scalars, nregs;
   uint32_t G, W, nwaves, lds_local_cells;
-  uint32_t lds_log_cap, overlay_cells, NI, pad;
+  uint32_t lds_log_cap, overlay_cells, NI;
+  // interpreted with elided group steps: the program cannot fault, and a
+  // memory statement synchronises the group only when its instruction
+  // says so (bit 31 of its array word clear); log entries take their
+  // positions from LDS counters (see Item::mem_nf)
+  uint32_t nf;
   uint64_t wg_log_cap;            // log entries reserved per work-group
   // LDS interval check by a per-cell table instead of a sort: table entry of
   // log cell key ck is ck - tab_base; tab_cells = 0 selects the sort
@@ -116,7 +122,8 @@ struct ProgDesc {                 // one program of the call
   // intervals whose local-array accesses are logged: interval k < 64 when
   // bit k of log_mask is set, every later one when log_high != 0 (all set
   // unless a proof shows the other intervals race-free)
-  uint32_t log_high, pad2;
+  uint32_t log_high;
+  uint32_t step_limit;            // loop iterations a work-group may start (then F_STEP_LIMIT)
   uint64_t log_mask;
 };
 
@@ -221,8 +228,12 @@ struct Ctl {
   uint32_t item;                        // work item taken by the group
   uint32_t pad;
   uint32_t lds_cnt[2];                  // LDS log entries of the even / odd intervals
-                                        // (per-program kernels with elided group steps)
+                                        // (elided group steps)
+  unsigned long long gl_cnt;            // global log entries of the group (elided group steps)
 };
+// bit of a load / store instruction's array word: the interpreter skips the
+// statement's group step (programs interpreted with elided steps only)
+constexpr uint32_t INSN_NO_STEP = 0x80000000u;
 
 constexpr uint32_t LDS_LIMIT = 160u * 1024u;
 

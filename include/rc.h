@@ -56,7 +56,14 @@ enum {
   RC_STATUS_DIV_ZERO = 2,           /* '/', '%' or 'mod' by zero            */
   RC_STATUS_ASSERT = 3,             /* assert(b) with b false               */
   RC_STATUS_ASSUME = 4,             /* assume(b) with b false               */
-  RC_STATUS_BARRIER_DIVERGENCE = 5  /* barrier reached by part of a group   */
+  RC_STATUS_BARRIER_DIVERGENCE = 5, /* barrier reached by part of a group   */
+  RC_STATUS_STEP_LIMIT = 6          /* the work-group would start more loop
+                                       iterations (summed over its loops)
+                                       than its limit (rc_tuning.step_limit,
+                                       2^24 by default): it stops at that for
+                                       statement, reported for its first
+                                       work-item (a safety net; Section 4
+                                       has no such rule)                    */
 };
 
 /* Record labels (bit set).  A record is a race when bit 1 or 2 is set. */
@@ -172,7 +179,9 @@ rc_status rc_prog_owned(const rc_prog* prog, uint32_t array_id, int* owned);
  * fault: its accesses and branches do not depend on loaded values or scalar
  * parameters, and enumerating every work-item finds every access in bounds,
  * no division by zero, every assert and assume holding and no barrier passed
- * by only part of a group.  Accesses to read-only and owned arrays of such a
+ * by only part of a group (or value ranges show the same for every input),
+ * and no work-group can start more loop iterations than the default step
+ * limit.  Accesses to read-only and owned arrays of such a
  * program skip the group step of a memory statement.  RC_E_PARSE /
  * RC_E_LIMIT as rc_prog_load, RC_E_INVAL for a shape outside
  * rc_set_ndrange's range. */
@@ -212,7 +221,10 @@ rc_status rc_bind_scalar(rc_prog* prog, uint32_t scalar_id, int32_t value);
  * shape, which arrays can carry no record and whether the program can fault
  * (see rc_prog_owned and rc_log_intervals) and skips the logs and group
  * steps those proofs make unnecessary; 1 = no proof: every access to a
- * written array is logged and checked (the reports are the same).  A batch
+ * written array is logged and checked (the reports are the same).
+ * step_limit: loop iterations one work-group may start before it stops
+ * with RC_STATUS_STEP_LIMIT (0 = 2^24); unlike the other fields it is part
+ * of the semantics, not a tuning, and rc_autotune keeps it.  A batch
  * uses radix_bits and record_sort of its first instance's program;
  * rc_autotune keeps record_sort and proofs_off. */
 typedef struct {
@@ -220,7 +232,8 @@ typedef struct {
   uint32_t radix_bits;
   uint32_t record_sort;
   uint32_t proofs_off;
-  uint32_t reserved[4];
+  uint32_t step_limit;
+  uint32_t reserved[3];
 } rc_tuning;
 rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
 

@@ -664,13 +664,14 @@ typedef struct {
   AccessLog* inter_log;     /* global-array accesses of all groups */
   uint32_t interval;
   uint64_t n_accesses;
+  uint64_t iterations, step_limit;   /* loop iterations started by the group; its limit */
   /* fault of this group */
   int fault_code; uint32_t fault_pc, fault_lid;
   RecList* recs;
   uint32_t n_race_cells, n_benign_cells;
 } Group;
 
-enum { ST_OK = 0, ST_OOB = 1, ST_DIV = 2, ST_ASSERT = 3, ST_ASSUME = 4, ST_BARDIV = 5 };
+enum { ST_OK = 0, ST_OOB = 1, ST_DIV = 2, ST_ASSERT = 3, ST_ASSUME = 4, ST_BARDIV = 5, ST_STEP_LIMIT = 6 };
 
 static int32_t eval(Group* g, const Expr* e, uint32_t lid, int* dz) {
   switch (e->kind) {
@@ -938,6 +939,10 @@ static int exec_stmt(Group* g, const Stmt* s, const unsigned char* mask) {
     case S_FOR: {
       int64_t iters = s->hi - s->lo; if (iters < 0) iters = 0;
       for (int64_t j = 0; j < iters; j++) {
+        /* the safety net of reading R13: a group that would start more loop */
+        /* iterations than its limit stops here, reported for its first      */
+        /* work-item (every work-item of the group reaches the limit)        */
+        if (++g->iterations > g->step_limit) return set_fault(g, s, ST_STEP_LIMIT, 0);
         for (uint32_t l = 0; l < W; l++) if (mask[l]) g->vars[(size_t)s->var * W + l] = wrap(s->lo + j);
         int r = exec_block(g, s->body, s->nbody, mask);
         if (r != RUN_OK) return r;
@@ -980,6 +985,15 @@ int orc_run(const orc_prog* P, uint32_t G, uint32_t W,
             const orc_bind* scalars, int n_scalars,
             uint64_t seed, uint32_t instance, int flags, int final_array,
             orc_result* out, char* err, int errlen) {
+  return orc_run_limit(P, G, W, arrays, n_arrays, scalars, n_scalars, seed, instance, flags, final_array,
+                       ORC_STEP_LIMIT, out, err, errlen);
+}
+
+int orc_run_limit(const orc_prog* P, uint32_t G, uint32_t W,
+                  const orc_bind* arrays, int n_arrays,
+                  const orc_bind* scalars, int n_scalars,
+                  uint64_t seed, uint32_t instance, int flags, int final_array, uint64_t step_limit,
+                  orc_result* out, char* err, int errlen) {
   memset(out, 0, sizeof *out);
   if (W < 1 || W > 1024 || G < 1 || (uint64_t)G * W >= (1ull << 26)) {
     set_err(err, errlen, "bad launch shape: need 1 <= W <= 1024, G >= 1, G*W < 2^26");
@@ -992,7 +1006,7 @@ int orc_run(const orc_prog* P, uint32_t G, uint32_t W,
   }
   if (final_array >= P->n_global) { set_err(err, errlen, "final_array out of range"); return -1; }
   Group g; memset(&g, 0, sizeof g);
-  g.P = P; g.G = G; g.W = W; g.seed = seed; g.instance = instance; g.flags = flags;
+  g.P = P; g.G = G; g.W = W; g.seed = seed; g.instance = instance; g.flags = flags; g.step_limit = step_limit;
   for (int j = 0; j < P->n_scalars; j++) {
     const orc_bind* b = &scalars[j];
     if (b->kind == 1) g.scalar_val[j] = *b->data;
@@ -1027,7 +1041,7 @@ int orc_run(const orc_prog* P, uint32_t G, uint32_t W,
   /* Each work-group runs on its own view of global memory (initial contents */
   /* plus its own writes); barriers synchronise one work-group.              */
   for (uint32_t gid = 0; gid < G; gid++) {
-    g.gid = gid; g.interval = 0; g.n_accesses = 0; g.fault_code = 0;
+    g.gid = gid; g.interval = 0; g.n_accesses = 0; g.fault_code = 0; g.iterations = 0;
     memset(g.vars, 0, (size_t)(P->n_vars ? P->n_vars : 1) * W * sizeof(int32_t));
     for (int a = 0; a < P->n_global; a++) {
       g.view[a] = (int32_t*)calloc((size_t)P->arr_size[a], sizeof(int32_t));

@@ -73,6 +73,16 @@ int orc_run(const orc_prog* p, uint32_t G, uint32_t W,
             const orc_bind* scalars, int n_scalars,
             uint64_t seed, uint32_t instance, int flags, int final_array,
             orc_result* out, char* err, int errlen);
+/* The same with the group's loop-iteration limit (reading R13's safety
+ * net: a work-group that would start more loop iterations, summed over all
+ * its loops, stops with status 6 at that for statement, reported for its
+ * first work-item).  orc_run uses ORC_STEP_LIMIT. */
+#define ORC_STEP_LIMIT (1ull << 24)
+int orc_run_limit(const orc_prog* p, uint32_t G, uint32_t W,
+                  const orc_bind* arrays, int n_arrays,
+                  const orc_bind* scalars, int n_scalars,
+                  uint64_t seed, uint32_t instance, int flags, int final_array, uint64_t step_limit,
+                  orc_result* out, char* err, int errlen);
 void orc_result_free(orc_result*);
 
 /*

@@ -35,7 +35,8 @@ SUMMARY_DTYPE = np.dtype([
 assert SUMMARY_DTYPE.itemsize == 40
 
 LABEL_RW, LABEL_WW_DIFF, LABEL_BENIGN = 1, 2, 4
-STATUS = {0: "OK", 1: "OOB", 2: "DIV_ZERO", 3: "ASSERT", 4: "ASSUME", 5: "BARRIER_DIVERGENCE"}
+STATUS = {0: "OK", 1: "OOB", 2: "DIV_ZERO", 3: "ASSERT", 4: "ASSUME", 5: "BARRIER_DIVERGENCE", 6: "STEP_LIMIT"}
+STEP_LIMIT = 1 << 24   # loop iterations a work-group may start (reading R13's safety net)
 NONE = 0xFFFFFFFF
 
 
@@ -94,6 +95,12 @@ def _load():
                                 ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(_Result), ctypes.c_char_p, ctypes.c_int]
         lib.orc_run.restype = ctypes.c_int
+        lib.orc_run_limit.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.POINTER(_Bind), ctypes.c_int,
+                                      ctypes.POINTER(_Bind), ctypes.c_int,
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                      ctypes.POINTER(_Result), ctypes.c_char_p, ctypes.c_int]
+        lib.orc_run_limit.restype = ctypes.c_int
         lib.orc_result_free.argtypes = [ctypes.POINTER(_Result)]
         lib.orc_seeded_value.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_int64, ctypes.c_int64]
@@ -177,7 +184,7 @@ class Program:
 
     def run(self, G: int, W: int, arrays: dict | None = None, scalars: dict | None = None,
             seed: int = 0, instance: int = 0, literal: bool = False,
-            final: str | None = None) -> OracleResult:
+            final: str | None = None, step_limit: int = STEP_LIMIT) -> OracleResult:
         lib = _load()
         arrays = arrays or {}
         scalars = scalars or {}
@@ -198,9 +205,9 @@ class Program:
             final_idx = [n for n, _ in self.arrays].index(final)
         res = _Result()
         err = ctypes.create_string_buffer(512)
-        rc = lib.orc_run(self._p, G, W, abind, len(self.arrays), sbind, len(self.scalars),
-                         ctypes.c_uint64(seed & (2**64 - 1)), instance,
-                         1 if literal else 0, final_idx, ctypes.byref(res), err, 512)
+        rc = lib.orc_run_limit(self._p, G, W, abind, len(self.arrays), sbind, len(self.scalars),
+                               ctypes.c_uint64(seed & (2**64 - 1)), instance,
+                               1 if literal else 0, final_idx, ctypes.c_uint64(step_limit), ctypes.byref(res), err, 512)
         if rc != 0:
             raise OracleError(err.value.decode())
         try:

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librc.so")
 
 RC_OK, RC_E_INVAL, RC_E_PARSE, RC_E_LIMIT, RC_E_STATE, RC_E_OVERFLOW, RC_E_HIP = 0, -1, -2, -3, -4, -5, -6
-STATUS_NAMES = {0: "OK", 1: "OOB", 2: "DIV_ZERO", 3: "ASSERT", 4: "ASSUME", 5: "BARRIER_DIVERGENCE"}
+STATUS_NAMES = {0: "OK", 1: "OOB", 2: "DIV_ZERO", 3: "ASSERT", 4: "ASSUME", 5: "BARRIER_DIVERGENCE",
+                6: "STEP_LIMIT"}
 NONE = 0xFFFFFFFF
 
 RECORD_DTYPE = np.dtype([
@@ -66,7 +67,7 @@ class _Stats(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_log_entries", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
                 ("record_sort", ctypes.c_uint32), ("proofs_off", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 4)]
+                ("step_limit", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -412,12 +413,13 @@ class Program:
         _call(_lib.rc_prog_jit, self._h, 1 if enable else 0)
 
     def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0, record_sort: int = 0,
-                   proofs_off: bool = False):
+                   proofs_off: bool = False, step_limit: int = 0):
         t = _Tuning()
         t.lds_log_entries = lds_log_entries
         t.radix_bits = radix_bits
         t.record_sort = record_sort
         t.proofs_off = 1 if proofs_off else 0
+        t.step_limit = step_limit
         _call(_lib.rc_prog_set_tuning, self._h, ctypes.byref(t))
 
     def autotune(self, seed0: int, n_seeds: int, ws, cache_path: str | None = None) -> dict:

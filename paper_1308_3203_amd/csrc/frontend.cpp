@@ -582,7 +582,7 @@ class Lowering {
 // static bounds per work-item (every branch taken)
 // ---------------------------------------------------------------------------
 struct Bounds {
-  double instr = 0, mem = 0, logged = 0, logged_local = 0, stores = 0, barriers = 0;
+  double instr = 0, mem = 0, logged = 0, logged_local = 0, stores = 0, barriers = 0, iters = 0;
   std::vector<double> arr;   // loads/stores per array
 };
 
@@ -621,6 +621,7 @@ void bound_block(const std::vector<Statement>& body, const Compiled& c, double m
       case Statement::FOR: {
         double iters = (double)(s.hi > s.lo ? s.hi - s.lo : 0);
         b->instr += mult * (1 + iters);
+        b->iters += mult * iters;
         bound_block(s.then_body, c, mult * iters, b);
         break;
       }
@@ -927,6 +928,7 @@ bool compile_program(const char* src, size_t len, Compiled* out, std::string* er
     for (size_t a = 0; a < b.arr.size() && a < out->arrays.size(); ++a)
       out->dyn_mem_array[a] = (uint64_t)(b.arr[a] < cap ? b.arr[a] : cap);
     out->max_intervals = (uint64_t)(b.barriers + 1);
+    out->dyn_iters = (uint64_t)(b.iters < cap ? b.iters : cap);
     {
       const Compiled& cc = *out;
       IntervalBound lo = interval_block(body, {0, 0}, [&](int a) { return cc.arrays[a].written && !cc.arrays[a].global; });

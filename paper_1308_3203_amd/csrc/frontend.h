@@ -29,6 +29,7 @@ struct Compiled {
   uint64_t dyn_stores = 0;             // store statements
   std::vector<uint64_t> dyn_mem_array; // loads/stores per array
   uint64_t max_intervals = 1;          // 1 + barriers executed
+  uint64_t dyn_iters = 0;              // loop iterations started
   // largest interval (accesses per work-item between two barriers) on
   // written local arrays / on all written arrays
   double interval_logged_local = 0, interval_logged_all = 0;

@@ -384,3 +384,29 @@ def test_many_registers_interpreted_from_lds():
     for G, W in [(1, 64), (2, 100), (3, 256)]:
         g, o = both(src, G, W, {"x": ("seeded", 0, 16), "y": ("seeded", 0, 16)}, seed0=3, n=3)
         U.assert_same(g, o, f"many registers G={G} W={W}")
+
+
+@pytest.mark.parametrize("jit", [False, True])
+@pytest.mark.parametrize("limit,G,W", [(5000, 1, 64), (5000, 3, 130), (10099, 2, 64), (10100, 2, 64)])
+def test_step_limit(limit, G, W, jit):
+    """A work-group that would start more loop iterations than the limit
+    stops there with STEP_LIMIT (reading R13); interpreter and per-program
+    kernel against the oracle, with the limit set through the tuning."""
+    from tests.test_oracle_pins import STEP_SRC
+    src = STEP_SRC.replace("x[64]", "x[512]")
+    arrays = {"x": ("seeded", 0, 4)}
+    p = B.Program(U.ctx(), src)
+    p.set_ndrange(G, W)
+    p.bind(arrays, None)
+    p.set_tuning(step_limit=limit)
+    if jit:
+        p.jit(True)
+    buf = B.Buffers(p, 3, 1 << 16)
+    p.check_async(4, 3, buf.ws, buf.records, buf.n_records, buf.summaries)
+    U.ctx().sync()
+    n = int(buf.n_records.item())
+    g = (B.records_to_numpy(buf.records, n), B.summaries_to_numpy(buf.summaries, 3))
+    o = [O.Program(src).run(G, W, arrays=arrays, seed=4 + j, instance=j, step_limit=limit) for j in range(3)]
+    orc = (np.concatenate([x.records for x in o]), np.array([x.summary for x in o], dtype=O.SUMMARY_DTYPE))
+    U.assert_same(g, orc, f"limit={limit} G={G} W={W} jit={jit}")
+    assert (g[1]["status"] == (6 if limit < 10100 else 0)).all()

@@ -509,3 +509,55 @@ def test_soundness_detects_schedule_dependence():
 def test_parse_errors(src):
     with pytest.raises(O.OracleError):
         O.Program(src)
+
+
+# ---------------------------------------------------------------------------
+# The loop-iteration limit (reading R13's safety net): a work-group that would
+# start more loop iterations than its limit stops at that for statement.
+# ---------------------------------------------------------------------------
+STEP_SRC = """kernel s(global int x[64]) {
+  int v, i, j;
+  x[5] := tid;
+  for i in 0..100 {
+    for j in 0..100 {
+      v := v + 1;
+    }
+  }
+  x[7] := tid;
+}
+"""
+
+
+@pytest.mark.parametrize("limit,G", [(5000, 1), (5000, 3), (10099, 1), (10100, 2)])
+def test_step_limit_closed_form(limit, G):
+    # Iteration starts run 1 (outer), 2..101 (inner), 102 (outer), ...: the
+    # outer loop's k-th start is number 1 + 101 (k - 1), every other number
+    # is an inner start, 10100 in all.  Past the limit the group stops at
+    # the statement that would start one more: the inner for (pc 2) for
+    # limits 5000 and 10099 (5001 and 10100 are inner starts).  Interval 0
+    # then holds only the store to x[5], whose writes all differ.
+    r = O.check(STEP_SRC, G, 64, arrays={"x": ("seeded", 0, 4)}, step_limit=limit)
+    recs = recs_as_tuples(r.records)
+    if limit >= 10100:
+        assert r.status == "OK"
+        expect = [(g, 0, 0, c, 2, NONE, NONE, g * 64, g * 64 + 1) for g in range(G) for c in (5, 7)]
+        inter = [(NONE, 0, 0, c, 2, NONE, NONE, 0, 64) for c in (5, 7)] if G > 1 else []
+        assert recs == expect + inter
+    else:
+        assert r.status == "STEP_LIMIT"
+        assert (int(r.summary["fault_gid"]), int(r.summary["fault_pc"]), int(r.summary["fault_tid"])) == (0, 2, 0)
+        expect = [(g, 0, 0, 5, 2, NONE, NONE, g * 64, g * 64 + 1) for g in range(G)]
+        inter = [(NONE, 0, 0, 5, 2, NONE, NONE, 0, 64)] if G > 1 else []
+        assert recs == expect + inter
+        assert int(r.summary["n_accesses"]) == 64 * G
+
+
+def test_step_limit_default():
+    # 4200 outer x 4000 inner iterations: 4200 + 4200 * 4000 = 16 804 200
+    # starts, above 2^24.  Start 2^24 + 1 = 16 777 217 falls after the
+    # 4194-th outer start (number 1 + 4001 * 4193 = 16 776 194): an inner start.
+    src = STEP_SRC.replace("0..100 {\n    for j in 0..100", "0..4200 {\n    for j in 0..4000")
+    r = O.check(src, 1, 1, arrays={"x": ("seeded", 0, 4)})
+    assert r.status == "STEP_LIMIT" and int(r.summary["fault_pc"]) == 2
+    r = O.check(src, 1, 1, arrays={"x": ("seeded", 0, 4)}, step_limit=16804200)
+    assert r.status == "OK"

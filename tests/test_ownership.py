@@ -464,3 +464,13 @@ def test_range_proof_never_contradicts_the_oracle():
                            scalars={"s": ("seeded", -(2 ** 31), 2 ** 31)}, seed=seed)
             assert res.status == "OK", (src, G, W, seed, res.status)
     assert proven >= 60
+
+
+def test_never_faults_needs_the_iteration_limit():
+    """A program that can start more loop iterations than the default limit
+    (2^24) can stop with STEP_LIMIT, so it is not proven fault-free."""
+    body = "  for k in 0..{} {{\n    for j in 0..4000 {{\n      v := v + 1;\n    }}\n  }}\n  x[tid] := v;"
+    assert B.owned_arrays(f"kernel t(global int x[64]) {{\n  int v, k, j;\n{body.format(4000)}\n}}\n", 1, 64,
+                          with_faults=True)[1]
+    assert not B.owned_arrays(f"kernel t(global int x[64]) {{\n  int v, k, j;\n{body.format(4200)}\n}}\n", 1, 64,
+                              with_faults=True)[1]

@@ -1066,7 +1066,7 @@ int orc_run_limit(const orc_prog* P, uint32_t G, uint32_t W,
   }
   /* INTER scope: global-array accesses of different work-groups, whole run */
   if (G > 1) check_scope(&g, inter_log.a, inter_log.n, 1, 0, 0);
-  qsort(recs.r, recs.n, sizeof(orc_record), cmp_record);
+  if (recs.n > 1) qsort(recs.r, recs.n, sizeof(orc_record), cmp_record);
   out->records = recs.r; out->n_records = recs.n;
   out->summary.n_accesses = total_acc;
   out->summary.n_race_cells = g.n_race_cells;

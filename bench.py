@@ -4,18 +4,30 @@ A step is one pass of the whole path (interpretation, access logging, interval
 checks, ordered race report) over one batch of synthetic instances, with inputs
 seeded on the device.  Prints one JSON line.
 
-    python bench.py [--config c2] [--steps K] [--warmup W] [--seeds N]
+    python bench.py [--config c3] [--steps K] [--warmup W]
 
-Configs: c1 (one random 20-statement kernel, 1 x 64, 1000 seeds),
-c2 (six template kernels, 16 x 256, 10^4 seeds each; the default),
-c3 (random kernels of widths 32..1024 in one batched call; --programs x --seeds),
-c4 (large intervals, 64 x 1024 x 64 iterations, 16 seeds),
-c5 (learned triage over the c3 generator: train, then sweep held-out
-instances in learned and in plain order).
+The headline is the batched random-kernel sweep (c3: 10^4 random kernels of
+widths 32..1024 x 100 seeds, 10^6 instances, one rc_batch_check call per
+step), the largest configuration.  The same line carries, as secondary
+figures, the template kernels (c2: six programs, 16 x 256, 10^4 seeds each)
+with the static proofs on and off, and the large-interval kernel (c4: 64 x
+1024 x 64 iterations, 16 seeds).  Other configurations: c1 (one random
+20-statement kernel, 1 x 64, 1000 seeds) and c5 (learned triage over the c3
+generator: train, then sweep held-out instances in learned and plain order).
+
+Roofline: a race-checked access costs 28 algorithmic bytes (4 for the
+simulated cell, 12 to write its access record once, 12 to read it once).
+Each kernel is credited the bytes of the work it does: the interpreting
+kernel the cell and the record write of every access, and the record read
+as well for every access whose check completes inside it (checked in LDS,
+or exempt by a static proof); the global interval check the record read of
+every access that went to the global log.  Sort passes are implementation
+cost and are credited nothing.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,24 +37,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BYTES_PER_ACCESS = 28.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-# algorithmic bytes per race-checked access: the simulated cell (4 B), the
-# 12-byte access record written once (interpretation) and read once (check)
-ALGO_BYTES = {"interpret": 16.0, "interval_check": 12.0}
-KERNEL_OF_PHASE = {"interpret": "rc_interp_kernel", "log_sort": "rs_scatter_kernel/rs_hist_kernel",
-                   "interval_check": "seg_check_kernel+seg_long_kernel",
-                   "record_sort": "rs_scatter_kernel/rs_hist_kernel",
-                   "output": "rec_gather_kernel", "setup": "fill kernels"}
+PHASE_KERNELS = {"log_sort": "rs_hist_kernel/rs_scatter_lds_kernel", "interval_check": "seg_check_kernel",
+                 "record_sort": "rs_hist_kernel/rs_scatter_kernel", "output": "rec_place_out_kernel",
+                 "setup": "fill kernels"}
+
+
+def say(msg: str):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources: counter-derived traffic is valid only for
+    """Hash of the library sources: counter-derived traffic is valid only for
     the kernels it was measured on."""
-    import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1308_3203_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
+        if f.endswith((".hip", ".h", ".cpp")) and not f.startswith("_"):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -63,6 +75,530 @@ def measured_traffic(kernel: str, workload_name: str):
     return e.get("bytes_per_launch")
 
 
+def credited_bytes(phase: str, accesses: int, logged_global: int) -> float:
+    """Algorithmic bytes a phase is credited for one step (module docstring)."""
+    if phase == "interpret":
+        return 28.0 * (accesses - logged_global) + 16.0 * logged_global
+    if phase == "interval_check":
+        return 12.0 * logged_global
+    return 0.0
+
+
+# ---------------------------------------------------------------------------
+# runners: one step = every instance of the workload checked once
+# ---------------------------------------------------------------------------
+class SingleRunner:
+    """One rc_check call per program and step (c1, c2, c4)."""
+
+    def __init__(self, ctx, works_seeds, ws_gb: float, jit: bool, proofs_off: bool = False):
+        from paper_1308_3203_amd import binding as B
+        self.B = B
+        self.ctx = ctx
+        self.jit = jit
+        self.runs = []
+        per_ws = int(ws_gb * (1 << 30) / len(works_seeds))
+        for w, n in works_seeds:
+            p = B.Program(ctx, w.src)
+            p.set_ndrange(w.G, w.W)
+            p.bind(w.arrays, w.scalars)
+            if proofs_off:
+                p.set_tuning(proofs_off=True)
+            if jit:
+                p.jit(True)            # compiled here, outside the timed region
+            # record capacity from a probe over the first seeds (every record
+            # of the timed steps is written out)
+            n_probe = min(n, 16)
+            probe = B.Buffers(p, n_probe, cap=1 << 22, ws_limit=per_ws)
+            p.check_async(0, n_probe, probe.ws, probe.records, probe.n_records, probe.summaries)
+            try:
+                ctx.sync()
+            except B.RcError as err:        # the count is complete even when the list is cut
+                if err.status != B.RC_E_OVERFLOW:
+                    raise
+            per_inst = int(probe.n_records.item()) / n_probe
+            del probe
+            cap = int(per_inst * n * 1.25) + (1 << 16)
+            self.runs.append((w, n, p, B.Buffers(p, n, cap=cap, ws_limit=per_ws)))
+        self.n = sum(n for _, n, _, _ in self.runs)
+
+    def step(self):
+        for w, n, p, buf in self.runs:
+            p.check_async(0, n, buf.ws, buf.records, buf.n_records, buf.summaries)
+
+    def step_with_stats(self) -> dict:
+        tot = {}
+        for w, n, p, buf in self.runs:
+            p.check_async(0, n, buf.ws, buf.records, buf.n_records, buf.summaries)
+            self.ctx.sync()
+            for k, v in self.ctx.call_stats().items():
+                tot[k] = tot.get(k, 0) + v
+        return tot
+
+    def results(self):
+        """Per program: (workload, numpy records, numpy summaries) of the last step."""
+        B = self.B
+        out = []
+        for w, n, p, buf in self.runs:
+            nr = int(buf.n_records.item())
+            out.append((w, B.records_to_numpy(buf.records, min(nr, buf.cap)), B.summaries_to_numpy(buf.summaries, n)))
+        return out
+
+    def instance(self, i: int):
+        """(workload, seed, index in its own call) of instance i of the step."""
+        for w, n, _, _ in self.runs:
+            if i < n:
+                return w, i, i
+            i -= n
+        raise IndexError(i)
+
+    def free(self):
+        for _, _, p, _ in self.runs:
+            p.close()
+        self.runs = []
+
+
+class BatchRunner:
+    """The whole workload in one rc_batch_check call per step (c3)."""
+
+    def __init__(self, ctx, n_programs: int, seeds: int, ws_gb: float, tune_cache: str | None):
+        from paper_1308_3203_amd import batches
+        self.ctx = ctx
+        self.batch = batches.RandomKernelBatch(ctx, n_programs, seeds, ws_gb=ws_gb, tune_cache=tune_cache,
+                                               progress=say)
+        self.n = self.batch.n
+
+    def step(self):
+        self.batch.enqueue()
+
+    def step_with_stats(self) -> dict:
+        self.batch.step()
+        return self.ctx.call_stats()
+
+    def results(self):
+        recs, summ = self.batch.results()
+        return [(None, recs, summ)]
+
+    def instance(self, i: int):
+        w, seed = self.batch.instance(i)
+        return w, seed, i
+
+    def free(self):
+        self.batch.free()
+
+
+def measure(runner, ctx, steps: int, warmup: int, jit: bool) -> dict:
+    """Warm up (the last warmup step also reads the log statistics), then
+    time `steps` steps with the library's HIP events on its own stream."""
+    import torch
+    for _ in range(max(1, warmup) - 1):
+        runner.step()
+        ctx.sync()
+    stats = runner.step_with_stats()
+    accesses = 0
+    records = 0
+    racy = 0
+    for _, recs, summ in runner.results():
+        accesses += int(summ["n_accesses"].sum())
+        records += len(recs)
+        racy += int((summ["n_race_cells"] > 0).sum())
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        runner.step()
+        ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    value = accesses * steps / elapsed
+    lg = int(stats.get("logged_global", 0))
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, launches = prof[dom]
+    per_launch_ms = ms / max(1, launches)
+    algo_step = credited_bytes(dom, accesses, lg)
+    algo_launch = algo_step * steps / max(1, launches)
+    achieved = algo_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    if dom == "interpret":
+        kernel = "rc_jit_kernel" if jit else "rc_interp_kernel"
+    else:
+        kernel = PHASE_KERNELS[dom]
+    return {
+        "value": value, "ms_per_step": elapsed / steps * 1e3, "steps": steps, "accesses": accesses,
+        "accesses_logged": int(stats.get("logged", 0)), "accesses_logged_global": lg,
+        "intervals": int(stats.get("intervals", 0)), "intervals_spilled": int(stats.get("intervals_spilled", 0)),
+        "instructions": int(stats.get("instructions", 0)), "wave_instructions": int(stats.get("wave_instructions", 0)),
+        "records": records, "racy_instances": racy,
+        "dominant": {"phase": dom, "kernel": kernel, "launches_per_step": launches / steps,
+                     "avg_launch_ms": per_launch_ms, "algo_bytes_per_launch": algo_launch,
+                     "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS},
+        "phases_ms": {k: round(v[0] / steps, 3) for k, v in prof.items()},
+        "path_frac": BYTES_PER_ACCESS * value / (HBM_PEAK_GBS * 1e9),
+    }
+
+
+def summary_of(m: dict) -> dict:
+    """The JSON fields of one measured configuration."""
+    d = m["dominant"]
+    out = {"value": round(m["value"], 1), "unit": "accesses/s", "ms_per_step": round(m["ms_per_step"], 3),
+           "accesses_per_step": m["accesses"], "accesses_logged": m["accesses_logged"],
+           "accesses_logged_global": m["accesses_logged_global"], "intervals": m["intervals"],
+           "intervals_spilled": m["intervals_spilled"], "race_records_per_step": m["records"],
+           "racy_instances_per_step": m["racy_instances"], "instructions": m["instructions"],
+           "wave_instructions": m["wave_instructions"],
+           "dominant_kernel": d["kernel"], "dominant_phase": d["phase"],
+           "avg_launch_ms": round(d["avg_launch_ms"], 4), "frac": round(d["frac"], 5),
+           "path_frac": round(m["path_frac"], 5), "phases_ms": m["phases_ms"]}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the oracle beside the GPU: a bounded sample on the host's cores
+# ---------------------------------------------------------------------------
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(runner, order, budget_s: float, threads: int):
+    """The oracle as it stands (plain C, one instance per call) on `threads`
+    host threads over instances taken in `order` until `budget_s` seconds of
+    wall time have passed.  The ctypes calls release the interpreter lock, so
+    the threads run the oracle in parallel.  Also returns SHA-256 hashes of
+    the oracle's and the GPU's records and summaries over the same
+    instances."""
+    import concurrent.futures as cf
+    import threading
+    import numpy as np
+    from oracle import oracle as O
+    res = runner.results()
+    # GPU output per instance: records are in instance order within each call
+    gpu = []
+    for w, recs, summ in res:
+        counts = summ["n_race_cells"].astype(np.int64) + summ["n_benign_cells"].astype(np.int64)
+        offs = np.concatenate([[0], np.cumsum(counts)])
+        gpu.append((recs, summ, offs))
+    call_of = []
+    if len(res) == 1:
+        call_of = None
+    else:
+        for k, (_, _, summ) in enumerate(res):
+            call_of += [(k, j) for j in range(len(summ))]
+
+    def gpu_bytes(i):
+        k, j = (0, i) if call_of is None else call_of[i]
+        recs, summ, offs = gpu[k]
+        return recs[offs[j]:offs[j + 1]].tobytes() + summ[j:j + 1].tobytes()
+
+    lock = threading.Lock()
+    nxt = [0]
+    done = {}
+    deadline = time.perf_counter() + budget_s
+
+    def worker():
+        acc = 0
+        while time.perf_counter() < deadline:
+            with lock:
+                if nxt[0] >= len(order):
+                    break
+                i = order[nxt[0]]
+                nxt[0] += 1
+            w, seed, local = runner.instance(i)
+            r = O.Program(w.src).run(w.G, w.W, arrays=w.arrays, scalars=w.scalars, seed=seed, instance=local)
+            out = r.records.tobytes() + np.array([r.summary], dtype=O.SUMMARY_DTYPE).tobytes()
+            with lock:
+                done[i] = out
+            acc += int(r.summary["n_accesses"])
+        return acc
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        accs = list(ex.map(lambda _: worker(), range(threads)))
+    wall = time.perf_counter() - t0
+    ids = sorted(done)
+    h_o, h_g = hashlib.sha256(), hashlib.sha256()
+    for i in ids:
+        h_o.update(done[i])
+        h_g.update(gpu_bytes(i))
+    acc = sum(accs)
+    return {"value": round(acc / wall, 1), "unit": "accesses/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(ids)} instances of the same step ({acc} accesses) in {wall:.1f} s of wall time "
+                      f"on {threads} threads, one instance per oracle call",
+            "parity_sha256_oracle": h_o.hexdigest(), "parity_sha256_gpu": h_g.hexdigest(),
+            "parity_match": h_o.hexdigest() == h_g.hexdigest(), "parity_instances": len(ids)}
+
+
+# ---------------------------------------------------------------------------
+# configurations
+# ---------------------------------------------------------------------------
+C2_DESC = "c2: tree reduction, Hillis-Steele prefix sum, 32x32 tiled transpose (clean + injected), G=16 x W=256"
+C3_DESC = ("c3: random kernels, W in {32..1024}, 10-200 statements, 1-8 barriers, loops to 16 iterations, "
+           "arrays of 4096-262144 cells, one batched call")
+C4_DESC = "c4: large intervals, G=64 x W=1024 x 64 iterations, 2^20 cells"
+
+
+def single_works(name: str, seeds):
+    from paper_1308_3203_amd import workloads as WL
+    if name == "c1":
+        return [(WL.c1_kernel(1), seeds or 1000)], "c1: one random 20-statement kernel, G=1 x W=64"
+    if name == "c2":
+        return [(w, seeds or 10000) for w in WL.c2_templates()], C2_DESC
+    if name == "c4":
+        return [(WL.c4_kernel(), seeds or 16)], C4_DESC
+    raise SystemExit(f"unknown config {name}")
+
+
+def run_secondary(ctx, name: str, args, proofs_off: bool = False) -> dict:
+    import torch
+    works, desc = single_works(name, None)
+    say(f"secondary {name}{' (proofs off)' if proofs_off else ''}: set-up")
+    r = SingleRunner(ctx, works, args.ws_gb, jit=True, proofs_off=proofs_off)
+    try:
+        m = measure(r, ctx, args.secondary_steps, 2, jit=True)
+    finally:
+        r.free()
+        del r
+        torch.cuda.empty_cache()
+    out = summary_of(m)
+    out["workload"] = desc + (", static proofs off (every access to a written array logged and checked)"
+                              if proofs_off else "")
+    out["execution"] = "per-program kernels"
+    out["instances_per_step"] = sum(n for _, n in works)
+    out["steps"] = m["steps"]
+    say(f"secondary {name}: {out['value']:.3e} accesses/s, {out['ms_per_step']:.2f} ms per step")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", help="c3 (default), c1, c2, c4 or c5")
+    ap.add_argument("--seeds", type=int, default=None, help="seeds per program (default: the config's)")
+    ap.add_argument("--ws-gb", type=float, default=230.0, help="workspace budget over all programs (HBM is 288 GB)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget in wall seconds (0: skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (default: the host's cores)")
+    ap.add_argument("--programs", type=int, default=10000, help="c3: number of random programs")
+    ap.add_argument("--tune-cache", default=None, help="c3: autotuner cache file (default: a temp file)")
+    ap.add_argument("--no-secondary", action="store_true", help="only the headline configuration")
+    ap.add_argument("--secondary-steps", type=int, default=10)
+    ap.add_argument("--proofs-off", action="store_true", help="c1/c2/c4: no static proofs")
+    ap.add_argument("--eval-programs", type=int, default=1000, help="c5: held-out programs")
+    ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
+    ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
+    ap.add_argument("--copy-probe", type=float, default=0.0, help="only run a plain copy of this many GiB")
+    ap.add_argument("--no-jit", action="store_true", help="c1/c2/c4: interpret instead of per-program kernels")
+    ap.add_argument("--profile-summary", action="store_true",
+                    help="summarize rocprofv3 output (no GPU): --kernel, --last, and the directories below")
+    ap.add_argument("--kernel", default="rc_interp_kernel")
+    ap.add_argument("--last", type=int, default=0, help="dispatches of the timed steps (the run's last ones)")
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--trace-dir", default=None)
+    ap.add_argument("--counter-dir", default=None)
+    ap.add_argument("--fetch-dir", default=None)
+    ap.add_argument("--write-dir", default=None)
+    ap.add_argument("--copy-fetch-dir", default=None)
+    ap.add_argument("--copy-write-dir", default=None)
+    ap.add_argument("--copy-gib", type=float, default=1.0)
+    args = ap.parse_args()
+    if args.profile_summary:
+        return profile_main(args)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1308_3203_amd import binding as B
+
+    if args.copy_probe > 0:
+        return copy_probe(args.copy_probe)
+    ctx = B.Context(0)
+    if args.config == "c5":
+        return bench_c5(args, ctx)
+    jit = not args.no_jit and args.config != "c3"
+    t_setup = time.perf_counter()
+    if args.config == "c3":
+        seeds = args.seeds or 100
+        runner = BatchRunner(ctx, args.programs, seeds, args.ws_gb, args.tune_cache)
+        desc = C3_DESC
+        cfg_extra = {"programs": args.programs, "seeds_per_program": seeds, "execution": "interpreter",
+                     "tunings": runner.batch.tunings}
+        order = [p * seeds + s for s in range(seeds) for p in range(args.programs)]
+    else:
+        works, desc = single_works(args.config, args.seeds)
+        runner = SingleRunner(ctx, works, args.ws_gb, jit=jit, proofs_off=args.proofs_off)
+        cfg_extra = {"programs": len(works), "seeds_per_program": works[0][1],
+                     "execution": "per-program kernels" if jit else "interpreter",
+                     "static_proofs": not args.proofs_off}
+        n_each = works[0][1]
+        order = [k * n_each + s for s in range(n_each) for k in range(len(works))]
+    setup_s = time.perf_counter() - t_setup
+    say(f"{args.config}: set-up {setup_s:.1f} s, {runner.n} instances; warmup")
+    m = measure(runner, ctx, args.steps, args.warmup, jit=jit)
+    say(f"{args.config}: {m['value']:.3e} accesses/s, {m['ms_per_step']:.1f} ms per step")
+    d = m["dominant"]
+    roofline = {"bound": "hbm", "achieved": round(d["achieved_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["frac"], 5), "traffic": measured_traffic(d["kernel"], args.config),
+                "kernel": d["kernel"], "phase": d["phase"],
+                "launches_per_step": d["launches_per_step"],
+                "algo_bytes_per_launch": round(d["algo_bytes_per_launch"]),
+                "avg_launch_ms": round(d["avg_launch_ms"], 4),
+                "phases_ms": m["phases_ms"], "path_frac": round(m["path_frac"], 5),
+                "bytes_per_access": BYTES_PER_ACCESS}
+    cpu = None
+    if args.cpu_seconds > 0:
+        threads = args.cpu_threads or host_cores()
+        say(f"oracle sample on {threads} threads for {args.cpu_seconds:.0f} s")
+        cpu = cpu_baseline(runner, order, args.cpu_seconds, threads)
+        say(f"oracle: {cpu['value']:.3e} accesses/s, parity over {cpu['parity_instances']} instances: "
+            f"{'match' if cpu['parity_match'] else 'MISMATCH'}")
+    n_inst = runner.n
+    runner.free()
+    del runner
+    torch.cuda.empty_cache()
+    secondary = {}
+    if not args.no_secondary and args.config == "c3":
+        secondary["c2"] = run_secondary(ctx, "c2", args)
+        secondary["c2_proofs_off"] = run_secondary(ctx, "c2", args, proofs_off=True)
+        secondary["c4"] = run_secondary(ctx, "c4", args)
+    config = {"workload": desc, **cfg_extra, "instances_per_step": n_inst, "setup_s": round(setup_s, 2),
+              "accesses_per_step": m["accesses"], "accesses_logged": m["accesses_logged"],
+              "accesses_logged_global": m["accesses_logged_global"], "intervals": m["intervals"],
+              "intervals_spilled": m["intervals_spilled"], "race_records_per_step": m["records"],
+              "racy_instances_per_step": m["racy_instances"], "instructions": m["instructions"],
+              "wave_instructions": m["wave_instructions"]}
+    line = {
+        "metric": "race-checked accesses/s", "value": round(m["value"], 1), "unit": "accesses/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(m["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": config, "roofline": roofline, "cpu_baseline": cpu, "secondary": secondary or None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 output -> the summaries kept under profiles/
+# ---------------------------------------------------------------------------
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    rows = []
+    for dp, _, files in os.walk(directory):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(dp, f), newline="") as fh:
+                    rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _dispatch_key(r):
+    return int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0)
+
+
+def summarize_trace(directory: str, kernel: str, last: int) -> dict:
+    """Kernel trace of one rocprofv3 run: the `last` dispatches of every
+    kernel whose name contains `kernel` (the timed steps come last), and the
+    whole run's per-kernel statistics."""
+    rows = _csv_rows(directory, "kernel_trace.csv")
+    mine = sorted((r for r in rows if kernel in r["Kernel_Name"]), key=_dispatch_key)
+    sel = mine[-last:] if last else mine
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in sel]
+    stats = _csv_rows(directory, "kernel_stats.csv")
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    return {"dispatches": len(mine), "selected": len(sel),
+            "avg_ms": (sum(durs) / len(durs) / 1e6) if durs else None,
+            "min_ms": min(durs) / 1e6 if durs else None, "max_ms": max(durs) / 1e6 if durs else None,
+            "stats": [(r["Name"][:90], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                       float(r["AverageNs"]) / 1e6, float(r["Percentage"])) for r in stats[:12]]}
+
+
+def summarize_counters(directory: str, kernel: str, last: int) -> dict:
+    """Per counter: its average per dispatch over the `last` dispatches of
+    the kernel (all dispatches when last is 0)."""
+    rows = _csv_rows(directory, "counter_collection.csv")
+    per = {}
+    for r in rows:
+        if kernel in r["Kernel_Name"]:
+            d = per.setdefault(_dispatch_key(r), {})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    keys = sorted(per)
+    sel = keys[-last:] if last else keys
+    out = {"dispatches": len(keys), "selected": len(sel)}
+    names = sorted({c for k in sel for c in per[k]})
+    for c in names:
+        out[c] = sum(per[k].get(c, 0.0) for k in sel) / max(1, len(sel))
+    return out
+
+
+def profile_main(args):
+    """--profile-summary: print a markdown summary of rocprofv3 output and,
+    given the four FETCH_SIZE / WRITE_SIZE runs, record the kernel's HBM
+    traffic per launch in profiles/traffic.json."""
+    kernel, last = args.kernel, args.last
+    lines = []
+    if args.trace_dir:
+        t = summarize_trace(args.trace_dir, kernel, last)
+        lines.append(f"## Kernel trace: `{kernel}`\n")
+        lines.append(f"{t['selected']} of {t['dispatches']} dispatches (the last ones: the timed steps): "
+                     f"average {t['avg_ms']:.4f} ms, min {t['min_ms']:.4f}, max {t['max_ms']:.4f}\n")
+        lines.append("| kernel (whole run) | calls | total ms | avg ms | % |\n|---|---|---|---|---|")
+        for name, calls, tot, avg, pct in t["stats"]:
+            lines.append(f"| `{name}` | {calls} | {tot:.2f} | {avg:.4f} | {pct:.1f} |")
+        lines.append("")
+    if args.counter_dir:
+        c = summarize_counters(args.counter_dir, kernel, last)
+        lines.append(f"## Counters: `{kernel}`, average per dispatch over {c['selected']} of "
+                     f"{c['dispatches']} dispatches\n")
+        lines.append("| counter | per dispatch |\n|---|---|")
+        for k, v in c.items():
+            if k not in ("dispatches", "selected"):
+                lines.append(f"| {k} | {v:.6g} |")
+        if "SQ_LDS_BANK_CONFLICT" in c and "SQ_LDS_IDX_ACTIVE" in c:
+            lines.append(f"| LdsBankConflict (conflict cycles per LDS access cycle) | "
+                         f"{c['SQ_LDS_BANK_CONFLICT'] / max(1.0, c['SQ_LDS_IDX_ACTIVE'] - c['SQ_LDS_BANK_CONFLICT']):.4f} |")
+        if "SQ_THREAD_CYCLES_VALU" in c and "SQ_ACTIVE_INST_VALU" in c:
+            lines.append(f"| VALUUtilization (% active lanes per VALU instruction) | "
+                         f"{100 * c['SQ_THREAD_CYCLES_VALU'] / max(1.0, 64 * c['SQ_ACTIVE_INST_VALU']):.2f} |")
+        if "SQ_ACTIVE_INST_VALU" in c and "GRBM_GUI_ACTIVE" in c:
+            lines.append(f"| VALUBusy (% of GPU time, 256 CUs) | "
+                         f"{100 * c['SQ_ACTIVE_INST_VALU'] / 256 / max(1.0, c['GRBM_GUI_ACTIVE']):.2f} |")
+        lines.append("")
+    if args.fetch_dir and args.write_dir and args.copy_fetch_dir and args.copy_write_dir:
+        cf = summarize_counters(args.copy_fetch_dir, "copyBuffer", 0)
+        cw = summarize_counters(args.copy_write_dir, "copyBuffer", 0)
+        f = summarize_counters(args.fetch_dir, kernel, last)
+        w = summarize_counters(args.write_dir, kernel, last)
+        copy_bytes = args.copy_gib * (1 << 30)
+        ff = copy_bytes / (cf["FETCH_SIZE"] * 1024.0)
+        wf = copy_bytes / (cw["WRITE_SIZE"] * 1024.0)
+        per_launch = f["FETCH_SIZE"] * 1024.0 * ff + w["WRITE_SIZE"] * 1024.0 * wf
+        lines.append(f"## HBM traffic: `{kernel}` on {args.workload}\n")
+        lines.append("| counter | KiB per dispatch | copy calibration factor | bytes per launch |\n|---|---|---|---|")
+        lines.append(f"| FETCH_SIZE | {f['FETCH_SIZE']:.1f} | {ff:.4f} | {f['FETCH_SIZE'] * 1024 * ff:.4e} |")
+        lines.append(f"| WRITE_SIZE | {w['WRITE_SIZE']:.1f} | {wf:.4f} | {w['WRITE_SIZE'] * 1024 * wf:.4e} |")
+        lines.append(f"| total | | | {per_launch:.4e} |\n")
+        try:
+            with open(TRAFFIC_FILE) as fh:
+                table = json.load(fh)
+        except (OSError, ValueError):
+            table = {}
+        table[f"{kernel}|{args.workload}"] = {
+            "bytes_per_launch": int(per_launch), "fetch_kib_avg": round(f["FETCH_SIZE"], 1),
+            "write_kib_avg": round(w["WRITE_SIZE"], 1), "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+            "dispatches": f["selected"], "source_sha256_16": kernel_source_hash()}
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(table, fh, indent=1)
+    print("\n".join(lines))
+
+
 def copy_probe(gib: float, reps: int = 3):
     """A plain device-to-device copy of known size, to calibrate the HBM
     byte counters (run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)."""
@@ -78,239 +614,6 @@ def copy_probe(gib: float, reps: int = 3):
     dt = (time.perf_counter() - t0) / reps
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps,
                       "gbs": round(2 * n * 4 / dt / 1e9, 1)}), flush=True)
-
-
-def workload(name: str, seeds: int | None):
-    from paper_1308_3203_amd import workloads as WL
-    if name == "c1":
-        return [(WL.c1_kernel(1), seeds or 1000)], "c1: one random 20-statement kernel, G=1 x W=64"
-    if name == "c2":
-        return ([(w, seeds or 10000) for w in WL.c2_templates()],
-                "c2: tree reduction, Hillis-Steele prefix sum, 32x32 tiled transpose (clean + injected), G=16 x W=256")
-    if name == "c3":
-        return None, "c3: random kernels, W in {32..1024}, 10-200 statements, 1-8 barriers, one batched call"
-    if name == "c4":
-        return [(WL.c4_kernel(), seeds or 16)], "c4: large intervals, G=64 x W=1024 x 64 iterations, 2^20 cells"
-    if name == "c5":
-        return None, "c5"
-    raise SystemExit(f"unknown config {name}")
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
-    ap.add_argument("--seeds", type=int, default=None, help="seeds per program (default: the config's)")
-    ap.add_argument("--ws-gb", type=float, default=230.0, help="workspace budget over all programs (HBM is 288 GB)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0: skip)")
-    ap.add_argument("--programs", type=int, default=10000, help="c3: number of random programs")
-    ap.add_argument("--tune-cache", default=None, help="c3: autotuner cache file (default: a temp file)")
-    ap.add_argument("--eval-programs", type=int, default=1000, help="c5: held-out programs")
-    ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
-    ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
-    ap.add_argument("--copy-probe", type=float, default=0.0, help="only run a plain copy of this many GiB")
-    ap.add_argument("--no-jit", action="store_true", help="c1/c2/c4: interpret instead of per-program kernels")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_1308_3203_amd import binding as B
-
-    if args.copy_probe > 0:
-        return copy_probe(args.copy_probe)
-    progs, desc = workload(args.config, args.seeds)
-    ctx = B.Context(0)
-    if args.config == "c3":
-        return bench_c3(args, ctx, desc)
-    if args.config == "c5":
-        return bench_c5(args, ctx)
-    runs = []
-    per_ws = int(args.ws_gb * (1 << 30) / len(progs))
-    for w, n in progs:
-        p = B.Program(ctx, w.src)
-        p.set_ndrange(w.G, w.W)
-        p.bind(w.arrays, w.scalars)
-        if not args.no_jit:
-            p.jit(True)            # compiled here, outside the timed region
-        # record capacity from a probe over the first seeds (every record of
-        # the timed steps is written out)
-        n_probe = min(n, 16)
-        probe = B.Buffers(p, n_probe, cap=1 << 22, ws_limit=per_ws)
-        p.check_async(0, n_probe, probe.ws, probe.records, probe.n_records, probe.summaries)
-        try:
-            ctx.sync()
-        except B.RcError as err:        # the count is complete even when the list is cut
-            if err.status != B.RC_E_OVERFLOW:
-                raise
-        per_inst = int(probe.n_records.item()) / n_probe
-        del probe
-        cap = int(per_inst * n * 1.25) + (1 << 16)
-        buf = B.Buffers(p, n, cap=cap, ws_limit=per_ws)
-        runs.append((w, n, p, buf))
-
-    def step(seed0):
-        for w, n, p, buf in runs:
-            p.check_async(seed0, n, buf.ws, buf.records, buf.n_records, buf.summaries)
-
-    # warmup (also the first-use clearing of each workspace); instances checked
-    # per step are deterministic, so the access count is taken here
-    for i in range(max(1, args.warmup)):
-        step(0)
-        ctx.sync()
-    accesses = 0
-    records = 0
-    race_instances = 0
-    for w, n, p, buf in runs:
-        s = B.summaries_to_numpy(buf.summaries, n)
-        accesses += int(s["n_accesses"].sum())
-        records += int(buf.n_records.item())
-        race_instances += int((s["n_race_cells"] > 0).sum())
-
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(0)
-        ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    elapsed = t1 - t0
-    value = accesses * args.steps / elapsed
-
-    # roofline of the dominant phase
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, launches = prof[dom]
-    per_launch_ms = ms / max(1, launches)
-    units_per_launch = accesses * args.steps / max(1, launches)
-    algo = ALGO_BYTES.get(dom, 0.0) * units_per_launch
-    achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
-    kernel = KERNEL_OF_PHASE[dom]
-    if dom == "interpret" and not args.no_jit:
-        kernel = "rc_jit_kernel"       # the program's own kernel runs the interpret phase
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(kernel, args.config),
-                "kernel": kernel, "phase": dom,
-                "algo_bytes_per_launch": round(algo),
-                "avg_launch_ms": round(per_launch_ms, 4),
-                "phases_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
-                "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}
-    if dom not in ALGO_BYTES:
-        roofline["note"] = ("the dominant phase is a sort, whose passes carry no algorithmic bytes "
-                            "(implementation cost); path_frac is the whole path against 28 B per access")
-
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline([(w, n) for w, n, _, _ in runs], args.cpu_seconds)
-
-    line = {
-        "metric": "race-checked accesses/s", "value": round(value, 1), "unit": "accesses/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": desc, "execution": "interpreter" if args.no_jit else "per-program kernels",
-                   "programs": len(runs), "seeds_per_program": runs[0][1],
-                   "instances_per_step": sum(n for _, n, _, _ in runs),
-                   "accesses_per_step": accesses, "race_records_per_step": records,
-                   "racy_instances_per_step": race_instances},
-        "roofline": roofline, "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
-
-
-def bench_c3(args, ctx, desc):
-    """The batched sweep: every (program, seed) instance of the random-kernel
-    generator in one rc_batch_check call per step."""
-    import tempfile
-    import numpy as np
-    import torch
-    from paper_1308_3203_amd import binding as B
-    from paper_1308_3203_amd import workloads as WL
-    seeds = args.seeds or 100
-    t0 = time.perf_counter()
-    works = [WL.c3_kernel(s) for s in range(args.programs)]
-    progs = []
-    for w in works:
-        p = B.Program(ctx, w.src)
-        p.set_ndrange(w.G, w.W)
-        p.bind(w.arrays, w.scalars)
-        progs.append(p)
-    cache = args.tune_cache or os.path.join(tempfile.gettempdir(), f"rc_tune_{os.getpid()}.json")
-    small = torch.empty(max(p.workspace_size(2) for p in progs[:64]) * 2, dtype=torch.uint8, device="cuda")
-    tuned = {}
-    for p in progs:
-        need = p.workspace_size(2)
-        if need > small.numel():
-            small = torch.empty(need, dtype=torch.uint8, device="cuda")
-        key = json.dumps(p.autotune(1 << 40, 2, small, cache), sort_keys=True)
-        tuned[key] = tuned.get(key, 0) + 1
-    del small
-    setup_s = time.perf_counter() - t0
-    handles = np.repeat(B.handles_of(progs), seeds)
-    seed_arr = np.tile(np.arange(seeds, dtype=np.uint64), len(progs))
-    n = int(handles.size)
-    ws = torch.empty(int(args.ws_gb * (1 << 30)), dtype=torch.uint8, device="cuda")
-    cap = 1 << 24
-    rec = torch.empty(cap * B.RECORD_BYTES, dtype=torch.uint8, device="cuda")
-    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    summ = torch.empty(n * B.SUMMARY_BYTES, dtype=torch.uint8, device="cuda")
-
-    def step():
-        ctx.batch_check_async(handles, seed_arr, ws, rec, cnt, summ)
-        ctx.sync()
-
-    for _ in range(max(1, args.warmup)):
-        step()
-    s = B.summaries_to_numpy(summ, n)
-    accesses = int(s["n_accesses"].sum())
-    records = int(cnt.item())
-    racy = int((s["n_race_cells"] > 0).sum())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # phase split from one more (profiled, eager) step
-    ctx.profile(True)
-    step()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    value = accesses * args.steps / elapsed
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, launches = prof[dom]
-    per_launch_ms = ms / max(1, launches)
-    algo = ALGO_BYTES.get(dom, 0.0) * accesses / max(1, launches)
-    achieved = algo / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic(KERNEL_OF_PHASE[dom], "c3"), "kernel": KERNEL_OF_PHASE[dom],
-                "phase": dom, "avg_launch_ms": round(per_launch_ms, 4),
-                "phases_ms": {k: round(v[0], 3) for k, v in prof.items()},
-                "path_frac": round(28.0 * value / (HBM_PEAK_GBS * 1e9), 5)}
-    if dom not in ALGO_BYTES:
-        roofline["note"] = ("the dominant phase is a sort, whose passes carry no algorithmic bytes "
-                            "(implementation cost); path_frac is the whole path against 28 B per access")
-    cpu = cpu_baseline([(w, seeds) for w in works[: max(1, min(len(works), 50))]], args.cpu_seconds) \
-        if args.cpu_seconds > 0 else None
-    line = {
-        "metric": "race-checked accesses/s", "value": round(value, 1), "unit": "accesses/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": desc, "programs": len(progs), "seeds_per_program": seeds, "instances_per_step": n,
-                   "accesses_per_step": accesses, "race_records_per_step": records,
-                   "racy_instances_per_step": racy, "setup_s": round(setup_s, 2), "tunings": tuned},
-        "roofline": roofline, "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
 
 
 def bench_c5(args, ctx):
@@ -354,31 +657,6 @@ def bench_c5(args, ctx):
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
-
-
-def cpu_baseline(programs, budget_s: float):
-    """The oracle as it stands, single-threaded, on a bounded sample of the
-    same instances (round-robin over the programs, seeds from 0)."""
-    from oracle import oracle as O
-    compiled = [(w, O.Program(w.src)) for w, _ in programs]
-    t_total = 0.0
-    acc = 0
-    n_inst = 0
-    seed = 0
-    t_start = time.perf_counter()
-    while time.perf_counter() - t_start < budget_s:
-        for w, p in compiled:
-            t = time.perf_counter()
-            r = p.run(w.G, w.W, arrays=w.arrays, scalars=w.scalars, seed=seed, instance=seed)
-            t_total += time.perf_counter() - t
-            acc += int(r.summary["n_accesses"])
-            n_inst += 1
-            if time.perf_counter() - t_start >= budget_s:
-                break
-        seed += 1
-    return {"value": round(acc / t_total, 1), "unit": "accesses/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_inst} instances (seeds from 0, round-robin over {len(compiled)} programs), "
-                      f"{acc} accesses in {t_total:.1f} s"}
 
 
 if __name__ == "__main__":

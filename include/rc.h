@@ -317,10 +317,16 @@ rc_status rc_sync(rc_ctx* ctx);
  * logged); logged_global: entries written to the global access log (arrays
  * logged there, and intervals that outgrew the LDS log); intervals_spilled:
  * intervals whose LDS log moved to the global log; intervals: intervals
- * closed, summed over work-groups and instances.  RC_E_STATE before the
- * first check call. */
+ * closed, summed over work-groups and instances; instructions: bytecode
+ * instructions executed, counted once per work-group (the lockstep group
+ * runs each one for all its work-items); wave_instructions: the same
+ * times the wavefronts that ran each work-group (a work-group runs on a
+ * block of 64, 128, 256, 512 or 1024 lanes, and every wave of the block
+ * takes every instruction).  RC_E_STATE
+ * before the first check call. */
 typedef struct {
   uint64_t logged, logged_global, intervals_spilled, intervals;
+  uint64_t instructions, wave_instructions;
 } rc_stats;
 rc_status rc_call_stats(rc_ctx* ctx, rc_stats* out);
 

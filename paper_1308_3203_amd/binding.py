@@ -61,7 +61,8 @@ class _Profile(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("logged", ctypes.c_uint64), ("logged_global", ctypes.c_uint64),
-                ("intervals_spilled", ctypes.c_uint64), ("intervals", ctypes.c_uint64)]
+                ("intervals_spilled", ctypes.c_uint64), ("intervals", ctypes.c_uint64),
+                ("instructions", ctypes.c_uint64), ("wave_instructions", ctypes.c_uint64)]
 
 
 class _Tuning(ctypes.Structure):

@@ -323,7 +323,7 @@ struct Layout {
 // per-chunk counters: log entries, record slots reserved, status bits,
 // queued long runs, record slots left unused, records (reserved - unused)
 enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_DEAD = 4, CNT_LIVE = 5, CNT_STATS = 8,
-       N_STATS = 4, CNT_WORDS = 16 };
+       N_STATS = 6, CNT_WORDS = 16 };
 
 void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n_items) {
   size_t o = 0;
@@ -599,7 +599,6 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     if (L.rank) HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.scope_cnt), L.scope_n, 0u, st));
   }
   {
-    PhaseTimer t(ctx, st, 0, timed);
     PassParams P;
     memset(&P, 0, sizeof P);
     P.progs = progs; P.slots = slots; P.chunks = chunks; P.chunk_index = chunk_index;
@@ -619,8 +618,10 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     // a call of one program with a compiled kernel runs that kernel; any
     // other call runs the interpreter
     rc_prog* jp = C.jit ? C.progs[0] : nullptr;
+    // one timed span per kernel launch (a launch per width class used)
     for (uint32_t c = 0; c < N_WCLASS; ++c) {
       if (!(C.classes_used & (1u << c))) continue;
+      PhaseTimer t(ctx, st, 0, timed);
       P.wclass = c;
       const uint32_t threads = 64u << c;
       const size_t lds = C.class_lds[c];
@@ -1576,6 +1577,8 @@ rc_status rc_call_stats(rc_ctx* ctx, rc_stats* out) {
   out->logged_global = v[1];
   out->intervals_spilled = v[2];
   out->intervals = v[3];
+  out->instructions = v[4];
+  out->wave_instructions = v[5];
   return RC_OK;
 }
 

@@ -418,6 +418,7 @@ struct Item {
   uint32_t iters;          // loop iterations the group started (uniform)
   uint32_t n_logged;       // this work-item's logged accesses
   uint32_t n_spilled;      // intervals of the group whose log moved to the global log
+  uint32_t n_insn;         // instructions the group executed (uniform)
   u64 my_fault;            // earliest fault of this work-item (fault_key order)
   bool faulted;
 
@@ -477,13 +478,14 @@ struct Item {
     lds_used = 0;
     lds_spilled = false;
     step = 0; last_spc = ~0u; store_seq = 0; interval = 0; parity = 0; n_acc = 0;
-    n_logged = 0; n_spilled = 0; iters = 0;
+    n_logged = 0; n_spilled = 0; iters = 0; n_insn = 0;
     my_fault = ~0ull;
     faulted = false;
   }
 
   // statements are numbered by execution: a new statement pc starts a new step
   __device__ __forceinline__ void stmt(uint32_t spc) {
+    ++n_insn;
     if (spc != last_spc) { ++step; last_spc = spc; }
   }
 
@@ -1164,6 +1166,8 @@ struct Item {
         if (log_used) atomicAdd(&P.stats[1], (u64)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap));
         if (n_spilled) atomicAdd(&P.stats[2], (u64)n_spilled);
         atomicAdd(&P.stats[3], (u64)(interval + 1u));
+        atomicAdd(&P.stats[4], (u64)n_insn);
+        atomicAdd(&P.stats[5], (u64)n_insn * (nthr >> 6));
       }
     }
     __syncthreads();

@@ -87,10 +87,12 @@ def test_c3_bench_batch_sampled():
     import torch
     from paper_1308_3203_amd import batches
     torch.cuda.empty_cache()
-    batch = batches.RandomKernelBatch(U.ctx(), 10000, 100, ws_gb=230.0)
+    batch = batches.RandomKernelBatch(U.ctx(), 10000, 100, ws_gb=230.0,
+                                      progress=lambda m: print(f"batched random kernels: {m}", flush=True))
     try:
         batch.step()
         recs, summ = batch.results()
+        print(f"batched random kernels: checked {batch.n} instances, {len(recs)} records", flush=True)
         # every instance's record counts against the record list
         counts = summ["n_race_cells"].astype(np.int64) + summ["n_benign_cells"].astype(np.int64)
         per_inst = np.bincount(recs["instance"].astype(np.int64), minlength=batch.n)
@@ -107,7 +109,9 @@ def test_c3_bench_batch_sampled():
             return i, o
 
         with cf.ThreadPoolExecutor(max_workers=8) as ex:
-            for i, o in ex.map(one, ids):
+            for k, (i, o) in enumerate(ex.map(one, ids)):
+                if k % 50 == 0:
+                    print(f"batched random kernels: oracle comparison {k} of {len(ids)}", flush=True)
                 got = recs[offs[i]:offs[i + 1]]
                 U.assert_same((got, summ[i:i + 1]), (o.records, np.array([o.summary], dtype=O.SUMMARY_DTYPE)),
                               f"batched random kernels, instance {i} ({batch.instance(i)[0].name}, "

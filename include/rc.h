@@ -294,6 +294,28 @@ rc_status rc_check(rc_prog* prog, uint64_t seed0, uint32_t n_seeds,
                    rc_summary* d_summaries);
 
 /*
+ * rc_check for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same check, with the library's static workspace in place of d_ws.
+ * That workspace is a fixed array of RC_STATIC_WS_BYTES in device memory,
+ * one copy per GPU, held from the first rc_ctx_create on that GPU until the
+ * process ends.  The call allocates nothing: it launches its chunks one by
+ * one on the ctx stream (no graph, no timing events; rc_ctx_profile does
+ * not see it) and keeps its state in the static workspace between calls,
+ * like a d_ws passed unmodified.  Every call on one GPU, from any context,
+ * uses the same array: calls whose work overlaps on one GPU (other streams,
+ * other contexts, other host threads) race and must be serialised by the
+ * caller.  RC_E_INVAL, with the sizes in the message, when one instance
+ * needs more workspace than RC_STATIC_WS_BYTES (rc_workspace_size(prog,
+ * 1)); more seeds than fit at once run in several passes.  Other arguments,
+ * results and errors as rc_check.
+ */
+#define RC_STATIC_WS_BYTES (256u << 20)
+rc_status rc_check_static(rc_prog* prog, uint64_t seed0, uint32_t n_seeds,
+                          rc_record* d_records, uint64_t cap, uint64_t* d_n_records,
+                          rc_summary* d_summaries);
+
+/*
  * Check a list of instances of possibly different programs (all loaded on
  * `ctx`, shaped and bound): instance i runs programs[i] with seed seeds[i].
  * Records and summaries follow the list order (record.instance = i); other

@@ -42,7 +42,7 @@ EXPORTS = [
     "rc_features_workspace_size", "rc_features", "rc_mlp_workspace_size", "rc_mlp_forward", "rc_mlp_grad",
     "rc_mlp_train_step", "rc_rank_workspace_size", "rc_rank", "rc_prog_jit", "rc_prog_owned",
     "rc_owned_arrays",
-    "rc_log_intervals", "rc_call_stats",
+    "rc_log_intervals", "rc_call_stats", "rc_check_static",
 ]
 N_FEATURES = 128
 MLP_PARAMS = 99073
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "rc_bind_scalar": ([vp, u32, i32], ctypes.c_int),
         "rc_workspace_size": ([vp, u32, ctypes.POINTER(sz)], ctypes.c_int),
         "rc_check": ([vp, u64, u32, vp, sz, vp, u64, vp, vp], ctypes.c_int),
+        "rc_check_static": ([vp, u64, u32, vp, u64, vp, vp], ctypes.c_int),
         "rc_sync": ([vp], ctypes.c_int),
         "rc_read_final": ([vp, u64, u32, vp, vp, sz], ctypes.c_int),
         "rc_ctx_profile": ([vp, ctypes.c_int], ctypes.c_int),
@@ -441,6 +442,14 @@ class Program:
         cap = records.numel() // RECORD_BYTES
         _call(_lib.rc_check, self._h, ctypes.c_uint64(seed0 & (2 ** 64 - 1)), n_seeds,
               ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+              ctypes.c_void_p(records.data_ptr() if cap else 0), cap,
+              ctypes.c_void_p(n_records.data_ptr()), ctypes.c_void_p(summaries.data_ptr()))
+
+    def check_static_async(self, seed0: int, n_seeds: int, records, n_records, summaries):
+        """check_async with the library's static workspace (rc_check_static):
+        no workspace argument, no device allocation."""
+        cap = records.numel() // RECORD_BYTES
+        _call(_lib.rc_check_static, self._h, ctypes.c_uint64(seed0 & (2 ** 64 - 1)), n_seeds,
               ctypes.c_void_p(records.data_ptr() if cap else 0), cap,
               ctypes.c_void_p(n_records.data_ptr()), ctypes.c_void_p(summaries.data_ptr()))
 

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -29,6 +30,10 @@ static_assert(sizeof(rc_summary) == 40, "rc_summary is 40 bytes");
 namespace {
 
 thread_local std::string g_err;
+
+// per device: the address of the static workspace (rc_check_static)
+std::mutex g_static_ws_mu;
+std::vector<void*> g_static_ws;
 
 rc_status fail(rc_status st, const char* fmt, ...) {
   char buf[512];
@@ -81,6 +86,7 @@ struct rc_ctx {
   std::vector<hipGraphExec_t> graphs_to_free;   // executable graphs of calls in flight
   bool use_graphs = true;
   u64* last_stats = nullptr;               // log statistics of the last check call (device)
+  void* static_ws = nullptr;               // this device's static workspace (rc_check_static)
 };
 
 struct rc_prog {
@@ -732,8 +738,11 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
 }
 
 // Build the call's tables, upload them, and enqueue every chunk.
+// no_alloc: the caller cannot allocate (rc_check_static): chunks are
+// launched one by one, with no graph and no timing events.
 rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d_records, u64 cap,
-                   u64* d_n_records, rc_summary* d_summaries, int do_log, uint32_t* epoch_out) {
+                   u64* d_n_records, rc_summary* d_summaries, int do_log, uint32_t* epoch_out,
+                   bool no_alloc = false) {
   hipStream_t st = ctx->stream;
   std::string why;
   if (!plan(C, ws_bytes, &why)) return fail(RC_E_INVAL, "%s", why.c_str());
@@ -828,7 +837,7 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
   const size_t n_chunks = C.chunks.size();
   // With several chunks and no profiling, capture one chunk's kernels as a
   // graph and replay it; every chunk reads its parameters from device tables.
-  if (n_chunks > 1 && ctx->use_graphs && !ctx->profiling) {
+  if (n_chunks > 1 && ctx->use_graphs && !ctx->profiling && !no_alloc) {
     if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
@@ -849,7 +858,7 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     return RC_OK;
   }
   for (size_t c = 0; c < n_chunks; ++c) {
-    rc_status s = enqueue_chunk(ctx, C, ws, st, d_n_records, d_records, cap, d_summaries, do_log, true);
+    rc_status s = enqueue_chunk(ctx, C, ws, st, d_n_records, d_records, cap, d_summaries, do_log, !no_alloc);
     if (s) return s;
   }
   return RC_OK;
@@ -880,8 +889,23 @@ rc_status rc_ctx_create(int device, void* hip_stream, rc_ctx** out) {
   if (e != hipSuccess || n == 0) return fail(RC_E_HIP, "no HIP device available");
   if (device < 0 || device >= n) return fail(RC_E_INVAL, "device %d out of range (%d devices)", device, n);
   HIP_TRY(hipSetDevice(device));
+  // the static workspace's address on this device, once per device (each
+  // GPU holds its own copy of the array at its own address)
+  void* sws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_static_ws_mu);
+    if (device >= (int)g_static_ws.size()) g_static_ws.resize(device + 1, nullptr);
+    if (!g_static_ws[device]) {
+      void* addr = nullptr;
+      HIP_TRY(static_ws_address(&addr));
+      if (!addr) return fail(RC_E_HIP, "the static workspace has no address on device %d", device);
+      g_static_ws[device] = addr;
+    }
+    sws = g_static_ws[device];
+  }
   rc_ctx* c = new rc_ctx;
   c->device = device;
+  c->static_ws = sws;
   c->stream = (hipStream_t)hip_stream;
   *out = c;
   return RC_OK;
@@ -1490,6 +1514,38 @@ rc_status rc_check(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, siz
   s = run_call(ctx, C, (char*)d_ws, ws_bytes, d_records, cap, (u64*)d_n_records, d_summaries, 1, nullptr);
   if (s) return s;
   ctx->pending.push_back(Pending{(u64*)d_n_records, cap, (uint32_t*)((char*)d_ws + C.L.counters + CNT_STATUS * 8)});
+  return RC_OK;
+}
+
+rc_status rc_check_static(rc_prog* p, uint64_t seed0, uint32_t n_seeds, rc_record* d_records, uint64_t cap,
+                          uint64_t* d_n_records, rc_summary* d_summaries) {
+  static_assert(STATIC_WS_BYTES == (size_t)RC_STATIC_WS_BYTES, "static workspace size");
+  if (!p || !d_n_records || !d_summaries) return fail(RC_E_INVAL, "NULL argument");
+  if (cap > 0 && !d_records) return fail(RC_E_INVAL, "d_records is NULL with cap > 0");
+  rc_status s = check_ready(p);
+  if (s) return s;
+  rc_ctx* ctx = p->ctx;
+  if (!ctx->static_ws) return fail(RC_E_STATE, "the context has no static workspace");
+  size_t one = 0;
+  s = rc_workspace_size(p, 1, &one);
+  if (s) return s;
+  if (one > STATIC_WS_BYTES)
+    return fail(RC_E_INVAL, "one instance needs %zu bytes of workspace, more than the %zu bytes of the static workspace",
+                one, STATIC_WS_BYTES);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (n_seeds == 0) {
+    HIP_TRY(launch_fill_u64((u64*)d_n_records, 1, 0ull, ctx->stream));
+    return RC_OK;
+  }
+  Call C;
+  C.progs.push_back(p);
+  C.inst_prog.assign(n_seeds, 0);
+  C.inst_seed.resize(n_seeds);
+  for (uint32_t j = 0; j < n_seeds; ++j) C.inst_seed[j] = seed0 + j;
+  char* ws = (char*)ctx->static_ws;
+  s = run_call(ctx, C, ws, STATIC_WS_BYTES, d_records, cap, (u64*)d_n_records, d_summaries, 1, nullptr, true);
+  if (s) return s;
+  ctx->pending.push_back(Pending{(u64*)d_n_records, cap, (uint32_t*)(ws + C.L.counters + CNT_STATUS * 8)});
   return RC_OK;
 }
 

@@ -154,4 +154,9 @@ hipError_t launch_live_count(const unsigned long long* reserved, const unsigned 
 hipError_t launch_clamp(unsigned long long* n_ptr, unsigned long long cap, uint32_t* status, uint32_t bit,
                         hipStream_t st);
 
+// Bytes of the static workspace (rc_check_static) and its address on the
+// current device.
+constexpr size_t STATIC_WS_BYTES = (size_t)256 << 20;
+hipError_t static_ws_address(void** out);
+
 }  // namespace rc

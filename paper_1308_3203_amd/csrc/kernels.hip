@@ -1505,4 +1505,15 @@ hipError_t launch_rank_keys(const float* scores, uint32_t n, uint32_t idx_bits, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The workspace of rc_check_static, for callers that cannot allocate: a
+// fixed array of device memory, one copy per GPU, held until the process
+// ends.  On the host the array's name is only a handle, never an address:
+// host code reaches the memory through the address hipGetSymbolAddress
+// returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+hipError_t static_ws_address(void** out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
+
 }  // namespace rc

@@ -20,8 +20,9 @@ simulated cell, 12 to write its access record once, 12 to read it once).
 Each kernel is credited the bytes of the work it does: the interpreting
 kernel the cell and the record write of every access, and the record read
 as well for every access whose check completes inside it (checked in LDS,
-or exempt by a static proof); the global interval check the record read of
-every access that went to the global log.  Sort passes are implementation
+or exempt by a static proof); the checks after it (the global pass, or the
+per-instance check of one-group programs' spilled intervals) the record
+read of every access they check.  Sort passes are implementation
 cost and are credited nothing.
 """
 from __future__ import annotations
@@ -39,7 +40,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_ACCESS = 28.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-PHASE_KERNELS = {"log_sort": "rs_hist_kernel/rs_scatter_lds_kernel", "interval_check": "seg_check_kernel",
+PHASE_KERNELS = {"log_sort": "rs_hist_kernel/rs_scatter_lds_kernel", "interval_check": "sc_group_kernel/seg_check_kernel",
                  "record_sort": "rs_hist_kernel/rs_scatter_kernel", "output": "rec_place_out_kernel",
                  "setup": "fill kernels"}
 
@@ -75,12 +76,13 @@ def measured_traffic(kernel: str, workload_name: str):
     return e.get("bytes_per_launch")
 
 
-def credited_bytes(phase: str, accesses: int, logged_global: int) -> float:
-    """Algorithmic bytes a phase is credited for one step (module docstring)."""
+def credited_bytes(phase: str, accesses: int, global_pass: int) -> float:
+    """Algorithmic bytes a phase is credited for one step (module docstring):
+    global_pass is the number of log entries the global pass checked."""
     if phase == "interpret":
-        return 28.0 * (accesses - logged_global) + 16.0 * logged_global
+        return 28.0 * (accesses - global_pass) + 16.0 * global_pass
     if phase == "interval_check":
-        return 12.0 * logged_global
+        return 12.0 * global_pass
     return 0.0
 
 
@@ -186,10 +188,15 @@ class BatchRunner:
         self.batch.free()
 
 
-def measure(runner, ctx, steps: int, warmup: int, jit: bool) -> dict:
+def measure(runner, ctx, steps: int, warmup: int, jit: bool, eager: bool = False) -> dict:
     """Warm up (the last warmup step also reads the log statistics), then
-    time `steps` steps with the library's HIP events on its own stream."""
+    time `steps` steps with the library's HIP events on its own stream.
+    The timed steps launch every chunk eagerly (timing is on); eager: the
+    warmup steps too, with no graph replay anywhere (rocprofv3 counter
+    collection does not take graph-launched kernels)."""
     import torch
+    if eager:
+        ctx.profile(True)
     for _ in range(max(1, warmup) - 1):
         runner.step()
         ctx.sync()
@@ -213,10 +220,11 @@ def measure(runner, ctx, steps: int, warmup: int, jit: bool) -> dict:
     ctx.profile(False)
     value = accesses * steps / elapsed
     lg = int(stats.get("logged_global", 0))
+    gp = int(stats.get("global_pass", 0))
     dom = max(prof, key=lambda k: prof[k][0])
     ms, launches = prof[dom]
     per_launch_ms = ms / max(1, launches)
-    algo_step = credited_bytes(dom, accesses, lg)
+    algo_step = credited_bytes(dom, accesses, gp)
     algo_launch = algo_step * steps / max(1, launches)
     achieved = algo_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     if dom == "interpret":
@@ -226,6 +234,7 @@ def measure(runner, ctx, steps: int, warmup: int, jit: bool) -> dict:
     return {
         "value": value, "ms_per_step": elapsed / steps * 1e3, "steps": steps, "accesses": accesses,
         "accesses_logged": int(stats.get("logged", 0)), "accesses_logged_global": lg,
+        "accesses_global_pass": gp,
         "intervals": int(stats.get("intervals", 0)), "intervals_spilled": int(stats.get("intervals_spilled", 0)),
         "instructions": int(stats.get("instructions", 0)), "wave_instructions": int(stats.get("wave_instructions", 0)),
         "records": records, "racy_instances": racy,
@@ -242,7 +251,8 @@ def summary_of(m: dict) -> dict:
     d = m["dominant"]
     out = {"value": round(m["value"], 1), "unit": "accesses/s", "ms_per_step": round(m["ms_per_step"], 3),
            "accesses_per_step": m["accesses"], "accesses_logged": m["accesses_logged"],
-           "accesses_logged_global": m["accesses_logged_global"], "intervals": m["intervals"],
+           "accesses_logged_global": m["accesses_logged_global"],
+           "accesses_global_pass": m["accesses_global_pass"], "intervals": m["intervals"],
            "intervals_spilled": m["intervals_spilled"], "race_records_per_step": m["records"],
            "racy_instances_per_step": m["racy_instances"], "instructions": m["instructions"],
            "wave_instructions": m["wave_instructions"],
@@ -395,6 +405,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
     ap.add_argument("--copy-probe", type=float, default=0.0, help="only run a plain copy of this many GiB")
     ap.add_argument("--no-jit", action="store_true", help="c1/c2/c4: interpret instead of per-program kernels")
+    ap.add_argument("--eager", action="store_true",
+                    help="no graph replay, warmup included (for rocprofv3 --pmc runs)")
     ap.add_argument("--profile-summary", action="store_true",
                     help="summarize rocprofv3 output (no GPU): --kernel, --last, and the directories below")
     ap.add_argument("--kernel", default="rc_interp_kernel")
@@ -442,7 +454,7 @@ def main():
         order = [k * n_each + s for s in range(n_each) for k in range(len(works))]
     setup_s = time.perf_counter() - t_setup
     say(f"{args.config}: set-up {setup_s:.1f} s, {runner.n} instances; warmup")
-    m = measure(runner, ctx, args.steps, args.warmup, jit=jit)
+    m = measure(runner, ctx, args.steps, args.warmup, jit=jit, eager=args.eager)
     say(f"{args.config}: {m['value']:.3e} accesses/s, {m['ms_per_step']:.1f} ms per step")
     d = m["dominant"]
     roofline = {"bound": "hbm", "achieved": round(d["achieved_gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -471,7 +483,8 @@ def main():
         secondary["c4"] = run_secondary(ctx, "c4", args)
     config = {"workload": desc, **cfg_extra, "instances_per_step": n_inst, "setup_s": round(setup_s, 2),
               "accesses_per_step": m["accesses"], "accesses_logged": m["accesses_logged"],
-              "accesses_logged_global": m["accesses_logged_global"], "intervals": m["intervals"],
+              "accesses_logged_global": m["accesses_logged_global"],
+              "accesses_global_pass": m["accesses_global_pass"], "intervals": m["intervals"],
               "intervals_spilled": m["intervals_spilled"], "race_records_per_step": m["records"],
               "racy_instances_per_step": m["racy_instances"], "instructions": m["instructions"],
               "wave_instructions": m["wave_instructions"]}

@@ -224,16 +224,22 @@ rc_status rc_bind_scalar(rc_prog* prog, uint32_t scalar_id, int32_t value);
  * written array is logged and checked (the reports are the same).
  * step_limit: loop iterations one work-group may start before it stops
  * with RC_STATUS_STEP_LIMIT (0 = 2^24); unlike the other fields it is part
- * of the semantics, not a tuning, and rc_autotune keeps it.  A batch
- * uses radix_bits and record_sort of its first instance's program;
- * rc_autotune keeps record_sort and proofs_off. */
+ * of the semantics, not a tuning, and rc_autotune keeps it.
+ * global_spills: 0 = the library's choice (a program of one work-group
+ * whose interval outgrows the LDS log has that interval checked after the
+ * interpreter by a block per instance, from the group's log region, with
+ * no log sort); 1 = such intervals always go to the global pass (log sort
+ * and segmented check).  A batch uses radix_bits and
+ * record_sort of its first instance's program; rc_autotune keeps
+ * record_sort, proofs_off and global_spills. */
 typedef struct {
   uint32_t lds_log_entries;
   uint32_t radix_bits;
   uint32_t record_sort;
   uint32_t proofs_off;
   uint32_t step_limit;
-  uint32_t reserved[3];
+  uint32_t global_spills;
+  uint32_t reserved[2];
 } rc_tuning;
 rc_status rc_prog_set_tuning(rc_prog* prog, const rc_tuning* tuning);
 
@@ -344,11 +350,14 @@ rc_status rc_sync(rc_ctx* ctx);
  * runs each one for all its work-items); wave_instructions: the same
  * times the wavefronts that ran each work-group (a work-group runs on a
  * block of 64, 128, 256, 512 or 1024 lanes, and every wave of the block
- * takes every instruction).  RC_E_STATE
+ * takes every instruction); global_pass: the entries of logged_global
+ * checked after the interpreter (by the global pass, or for one-group
+ * programs by the per-instance check of spilled intervals); it equals
+ * logged_global.  RC_E_STATE
  * before the first check call. */
 typedef struct {
   uint64_t logged, logged_global, intervals_spilled, intervals;
-  uint64_t instructions, wave_instructions;
+  uint64_t instructions, wave_instructions, global_pass;
 } rc_stats;
 rc_status rc_call_stats(rc_ctx* ctx, rc_stats* out);
 

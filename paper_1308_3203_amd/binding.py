@@ -62,13 +62,15 @@ class _Profile(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("logged", ctypes.c_uint64), ("logged_global", ctypes.c_uint64),
                 ("intervals_spilled", ctypes.c_uint64), ("intervals", ctypes.c_uint64),
-                ("instructions", ctypes.c_uint64), ("wave_instructions", ctypes.c_uint64)]
+                ("instructions", ctypes.c_uint64), ("wave_instructions", ctypes.c_uint64),
+                ("global_pass", ctypes.c_uint64)]
 
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lds_log_entries", ctypes.c_uint32), ("radix_bits", ctypes.c_uint32),
                 ("record_sort", ctypes.c_uint32), ("proofs_off", ctypes.c_uint32),
-                ("step_limit", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("step_limit", ctypes.c_uint32), ("global_spills", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class _ProgInfo(ctypes.Structure):
@@ -415,13 +417,14 @@ class Program:
         _call(_lib.rc_prog_jit, self._h, 1 if enable else 0)
 
     def set_tuning(self, lds_log_entries: int = 0, radix_bits: int = 0, record_sort: int = 0,
-                   proofs_off: bool = False, step_limit: int = 0):
+                   proofs_off: bool = False, step_limit: int = 0, global_spills: bool = False):
         t = _Tuning()
         t.lds_log_entries = lds_log_entries
         t.radix_bits = radix_bits
         t.record_sort = record_sort
         t.proofs_off = 1 if proofs_off else 0
         t.step_limit = step_limit
+        t.global_spills = 1 if global_spills else 0
         _call(_lib.rc_prog_set_tuning, self._h, ctypes.byref(t))
 
     def autotune(self, seed0: int, n_seeds: int, ws, cache_path: str | None = None) -> dict:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -102,6 +103,8 @@ struct rc_prog {
   uint32_t radix_bits = 8;           // tuning: digit width of the access-log sort
   uint32_t record_sort = 0;          // tuning: 1 = always sort records by their full key
   uint32_t proofs_off = 0;           // tuning: 1 = no static proof (every written array logged)
+  uint32_t global_spills = 0;        // tuning: 1 = spilled intervals always go to the global pass
+  bool sc = false;                   // spilled intervals checked by the work-group (current shape)
   uint32_t step_limit = DEFAULT_STEP_LIMIT;   // tuning: loop iterations a work-group may start
   bool never_faults = false;         // proven for the current shape
   uint64_t log_mask = ~0ull;         // intervals whose local-array accesses are logged (ProgDesc)
@@ -252,11 +255,33 @@ bool lds_may_spill(const rc_prog* p) {
 u64 wg_log_need(const rc_prog* p) {
   const u64 lds = p->lds_log_cap ? p->logged_local + (p->G == 1 ? p->logged_mem - p->logged_local : 0) : 0;
   const u64 glob = p->logged_mem - lds;
-  return (u64)p->W * (glob + (lds_may_spill(p) ? lds : 0));
+  // (a one-group program whose spills go to the group check: a trailer per interval)
+  return (u64)p->W * (glob + (lds_may_spill(p) ? lds : 0)) + (p->sc ? p->c.max_intervals : 0);
 }
 
-// the same, at least one entry (the global log's buffers are never empty)
+// the entries a work-group's region holds: at least one (the global log's
+// buffers are never empty)
 u64 wg_log_entries(const rc_prog* p) { return std::max<u64>(1, wg_log_need(p)); }
+
+// the words of a work-group's region
+u64 wg_region_words(const rc_prog* p) { return wg_log_entries(p); }
+
+// Spilled intervals go to the group check kernel (sc_check) instead of the
+// global pass when the program has one group (no INTER scope, every logged
+// array in LDS), its intervals may outgrow the LDS log and its cell keys
+// fit the packed entries (and so SC_NB_MAX windows of the check).
+bool sc_feasible(const rc_prog* p) {
+  static_assert((u64)SC_WIN * SC_NB_MAX >= SC_MAX_CELLS, "the group check's windows cover every cell key");
+  if (p->global_spills || p->G != 1 || !p->lds_log_cap || !lds_may_spill(p)) return false;
+  return p->n_logged_cells >= 1 && p->n_logged_cells <= SC_MAX_CELLS;
+}
+
+// the interval log's size for the current shape and tuning, and whether the
+// group checks its own spills
+void set_log_cap(rc_prog* p) {
+  p->lds_log_cap = lds_log_entries(p);
+  p->sc = sc_feasible(p);
+}
 
 uint32_t width_class(uint32_t W) {
   const uint32_t nw = (W + 63) / 64;
@@ -287,7 +312,7 @@ struct Need {          // resources of one instance
 Need need_of(const rc_prog* p) {
   Need n;
   n.wg = p->G;
-  n.log = (u64)p->G * wg_log_entries(p);
+  n.log = (u64)p->G * wg_region_words(p);
   // A record stands for a cell of one scope with at least two logged
   // accesses (an eligible pair needs two work-items), and the scopes of one
   // kind split the accesses: at most half the logged accesses give INTRA
@@ -315,6 +340,10 @@ struct Layout {
   // interval closed in LDS): per-(slot, scope) record counts and the scan's
   // partial sums
   bool rank = false, lds_only = false;
+  // one-group programs' spilled intervals checked after the interpreter
+  // (sc_group_kernel): blocks of the check and their bucket-bound words
+  uint32_t sc_blocks = 0;
+  size_t sc_ends = 0;
   u64 scope_n = 0;
   size_t scope_cnt = 0, scope_tmp = 0;
   // per-(slot, cell) owner words of the global log (cc_stride cells per
@@ -329,7 +358,7 @@ struct Layout {
 // per-chunk counters: log entries, record slots reserved, status bits,
 // queued long runs, record slots left unused, records (reserved - unused)
 enum { CNT_LOG = 0, CNT_REC = 1, CNT_STATUS = 2, CNT_LONG = 3, CNT_DEAD = 4, CNT_LIVE = 5, CNT_STATS = 8,
-       N_STATS = 6, CNT_WORDS = 16 };
+       N_STATS = 7, CNT_WORDS = 16 };
 
 void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n_items) {
   size_t o = 0;
@@ -343,7 +372,8 @@ void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n
   L->items = take(n_items * 8);
   L->recout = take(sizeof(rc_record_out));
   L->counters = take(CNT_WORDS * 8);
-  L->queue = take(N_WCLASS * 4);
+  L->queue = take((N_WCLASS + 1) * 4);   // the classes' queues, then the group check's
+  L->sc_ends = take((size_t)L->sc_blocks * SC_NB_MAX * 4);
   L->chunk_index = take(4);
   L->wg_count = take((size_t)L->max_wg * 4);
   L->wg_base = take((size_t)L->max_wg * 8);
@@ -525,7 +555,11 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
   C.radix_bits = C.progs.empty() ? 8u : C.progs[0]->radix_bits;
   C.record_sort = C.progs.empty() ? 0u : C.progs[0]->record_sort;
   bool lds_only = true;   // no program of the call writes the global log
-  for (const rc_prog* p : C.progs) lds_only = lds_only && wg_log_need(p) == 0;
+  bool any_sc = false;    // some program's spills go to the group check
+  for (const rc_prog* p : C.progs) {
+    lds_only = lds_only && (wg_log_need(p) == 0 || p->sc);
+    any_sc = any_sc || p->sc;
+  }
   if (bc > 32 || bg > 26 || bk > 32) { *why = "sort key fields too wide"; return false; }
   // try 1, 2, 4, ... chunks
   for (u64 k = 1;; k *= 2) {
@@ -561,6 +595,7 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     L.rank = C.record_sort == 0 && lds_only && L.bi + bs <= 32 && ((u64)L.max_slots << bs) <= (1ull << 26);
     L.scope_n = L.rank ? (u64)L.max_slots << bs : 0;
     L.lds_only = lds_only;
+    L.sc_blocks = any_sc ? std::min<uint32_t>(L.max_slots, SC_MAX_BLOCKS) : 0u;
     Layout lim = L;
     partition(C, lim);
     lay_out(&L, C.progs.size(), N, C.chunks.size(), C.items.size() / 2);
@@ -645,6 +680,21 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
       const uint32_t resident = (uint32_t)cus * (uint32_t)interp_occupancy(threads, lds, C.class_vreg[c]);
       const uint32_t blocks = std::max<uint32_t>(1, std::min(std::min(L.max_items_class[c], resident), REC_MAX_BLOCKS));
       HIP_TRY(launch_interp(P, blocks, threads, lds, C.class_vreg[c], st));
+    }
+    // one-group programs' spilled intervals, checked by the group check
+    if (do_log && L.sc_blocks) {
+      PhaseTimer t(ctx, st, 2, timed);
+      ScParams S;
+      memset(&S, 0, sizeof S);
+      S.progs = progs; S.slots = slots; S.chunks = chunks; S.chunk_index = chunk_index;
+      S.log_keys = P.log_keys; S.log_vals = P.log_vals; S.wg_count = P.wg_count;
+      S.queue = P.queue + N_WCLASS;
+      S.ends = (uint32_t*)(ws + L.sc_ends);
+      S.rec = P.rec;
+      S.bs = L.bs; S.bc = L.bc;
+      const uint32_t blocks =
+          std::max<uint32_t>(1, std::min<uint32_t>(L.sc_blocks, (uint32_t)cus * (uint32_t)sc_group_occupancy()));
+      HIP_TRY(launch_sc_group(S, blocks, st));
     }
   }
   if (!do_log) return RC_OK;
@@ -798,6 +848,8 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
     D.overlay_cells = p->overlay_cells;
     D.NI = (uint32_t)p->c.max_intervals;
     D.wg_log_cap = wg_log_entries(p);
+    D.sc = p->sc ? 1u : 0u;
+    D.n_cells = p->n_logged_cells;
     D.log_mask = p->log_mask;
     D.log_high = p->log_high;
     // interpreted programs that cannot fault elide group steps (the code's
@@ -1229,7 +1281,7 @@ static rc_status apply_shape(rc_prog* p) {
     p->logged_mem -= std::min(p->logged_mem, p->c.dyn_mem_array[a]);
     if (!p->c.arrays[a].global) p->logged_local -= std::min(p->logged_local, p->c.dyn_mem_array[a]);
   }
-  p->lds_log_cap = lds_log_entries(p);
+  set_log_cap(p);
   // the interpreter's code: load and store instructions of a program that
   // cannot fault carry INSN_NO_STEP where no conflicting access needs their
   // group step
@@ -1300,7 +1352,9 @@ rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   if (t->radix_bits > 8) return fail(RC_E_INVAL, "radix_bits must be in 1..8 (0: default)");
   if (t->record_sort > 1) return fail(RC_E_INVAL, "record_sort must be 0 or 1");
   if (t->proofs_off > 1) return fail(RC_E_INVAL, "proofs_off must be 0 or 1");
+  if (t->global_spills > 1) return fail(RC_E_INVAL, "global_spills must be 0 or 1");
   p->record_sort = t->record_sort;
+  p->global_spills = t->global_spills;
   p->lds_log_pref = t->lds_log_entries;
   p->radix_bits = t->radix_bits ? t->radix_bits : 8;
   const uint32_t limit = t->step_limit ? t->step_limit : DEFAULT_STEP_LIMIT;
@@ -1308,7 +1362,7 @@ rc_status rc_prog_set_tuning(rc_prog* p, const rc_tuning* t) {
   p->proofs_off = t->proofs_off;
   p->step_limit = limit;
   if (p->shaped && reprove) return apply_shape(p);
-  if (p->shaped) p->lds_log_cap = lds_log_entries(p);
+  if (p->shaped) set_log_cap(p);
   if (p->jit_on && p->shaped && !jit_current(p)) return jit_build(p);
   return RC_OK;
 }
@@ -1321,7 +1375,7 @@ static std::string bucket_key(const rc_prog* p, int device) {
   if (colon != std::string::npos) arch = arch.substr(0, colon);
   const double ib = (double)p->W * (p->G == 1 ? p->c.interval_logged_all : p->c.interval_logged_local);
   char b[160];
-  snprintf(b, sizeof b, "%s|wclass%u|groups%u|interval%u|cells%u|v1", arch.c_str(), width_class(p->W),
+  snprintf(b, sizeof b, "%s|wclass%u|groups%u|interval%u|cells%u|v2", arch.c_str(), width_class(p->W),
            bits_for(p->G), bits_for((u64)(ib + 1)), bits_for(std::max<uint32_t>(1, p->n_logged_cells)));
   return b;
 }
@@ -1381,6 +1435,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
     t.record_sort = p->record_sort;
     t.proofs_off = p->proofs_off;
     t.step_limit = p->step_limit;
+    t.global_spills = p->global_spills;
     s = rc_prog_set_tuning(p, &t);
     if (s) return s;
     *chosen = t;
@@ -1405,6 +1460,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
       c.record_sort = p->record_sort;
       c.proofs_off = p->proofs_off;
       c.step_limit = p->step_limit;
+      c.global_spills = p->global_spills;
       cands.push_back(c);
     }
   }
@@ -1471,6 +1527,7 @@ rc_status rc_autotune(rc_prog* p, uint64_t seed0, uint32_t n_seeds, void* d_ws, 
     back.record_sort = p->record_sort;
     back.proofs_off = p->proofs_off;
     back.step_limit = p->step_limit;
+    back.global_spills = p->global_spills;
     rc_prog_set_tuning(p, &back);
     return result;
   }
@@ -1635,6 +1692,7 @@ rc_status rc_call_stats(rc_ctx* ctx, rc_stats* out) {
   out->intervals = v[3];
   out->instructions = v[4];
   out->wave_instructions = v[5];
+  out->global_pass = v[6];
   return RC_OK;
 }
 

@@ -379,6 +379,7 @@ struct ItemView {
   u64* stats;              // see PassParams (may be null)
   uint32_t nf;             // elided group steps (ProgDesc::nf)
   uint32_t step_limit;     // loop iterations the group may start
+  uint32_t sc;             // spilled intervals go to the group check (ProgDesc)
 };
 
 __device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE32, NONE32, NONE32, NONE32}; }
@@ -387,6 +388,220 @@ __device__ __forceinline__ TabCell empty_tab_cell() { return TabCell{~0ull, NONE
 // 32-41 the local id, 42 the store flag, 43-54 the cell's table index.
 __device__ __forceinline__ u64 tab_entry(uint32_t trel, bool store, uint32_t l, int32_t v) {
   return ((u64)trel << 43) | ((u64)(store ? 1u : 0u) << 42) | ((u64)l << 32) | (uint32_t)v;
+}
+
+// The record of a table cell, if its accesses form one (labels and pairs
+// only; the caller adds the location).  q counts w1 too: w1 wrote a second
+// value exactly when q == w1.
+__device__ __forceinline__ bool tab_cell_finish(const TabCell c, PendingRec* pr) {
+  if (c.wmin == ~0ull && c.r1 == NONE32) return false;
+  const uint32_t w1 = c.wmin == ~0ull ? NONE32 : (uint32_t)(c.wmin >> 32);
+  const bool multi1 = c.q != NONE32 && c.q == w1;
+  const Pass1 p1 = {c.r1, c.wmin};
+  const Intra2 p2 = {c.r2, c.w2, multi1 ? NONE32 : c.q, multi1 ? 1u : 0u};
+  return intra_finish(p1, p2, &pr->label, &pr->rw, &pr->ww);
+}
+
+// Record slots for the whole group: this thread's n records are the
+// group's records [k, k + n) (threads in order), and the k-th record of the
+// group goes to slot k < room ? at + k : jump + (k - room).  The block takes
+// the slots from chunks of REC_CHUNK it reserves with one atomic (not one
+// per interval): the rest of the current chunk first, then a new one.  Every
+// thread of the block calls it.  (n <= 64; the wave's scan is taken
+// bit-plane by bit-plane with ballots.)  Returns k.
+__device__ __forceinline__ uint32_t reserve_records(Ctl* ctl, const rc_record_out& R, uint32_t n, uint32_t tl,
+                                                    uint32_t nthr, u64* room_out, u64* at_out, u64* jump_out) {
+  const uint32_t lane = tl & 63u, wave = tl >> 6;
+  const u64 below = (1ull << lane) - 1ull;
+  uint32_t x = 0, wsum = 0;   // exclusive prefix in the wave, wave total
+#pragma unroll
+  for (uint32_t b = 0; b < 7; ++b) {
+    const u64 m = __ballot((n >> b) & 1u);
+    x += (uint32_t)__popcll(m & below) << b;
+    wsum += (uint32_t)__popcll(m) << b;
+  }
+  if (lane == 0) ctl->rec_sum[wave] = wsum;
+  __syncthreads();
+  const uint32_t nw = nthr >> 6;
+  uint32_t before = 0, total = 0;
+  for (uint32_t w = 0; w < nw; ++w) {
+    const uint32_t v = ctl->rec_sum[w];
+    total += v;
+    if (w < wave) before += v;
+  }
+  if (tl == 0) {
+    ctl->rec_sum_total = total;
+    const u64 room = ctl->rc_end - ctl->rc_cur;
+    ctl->rec_base = ctl->rc_cur;               // records [0, room) go here
+    ctl->rc_room = room;
+    if (total <= room) {
+      ctl->rc_cur += total;
+      ctl->rc_next = ctl->rc_end;
+    } else {
+      const u64 more = total - room;           // and the rest to a new chunk
+      const u64 take = more > REC_CHUNK ? more : REC_CHUNK;
+      const u64 base = __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, R.rec_count), (unsigned long long)take,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ctl->rc_next = base;
+      ctl->rc_cur = base + more;
+      ctl->rc_end = base + take;
+    }
+  }
+  __syncthreads();
+  *room_out = ctl->rc_room;
+  *at_out = ctl->rec_base;
+  *jump_out = ctl->rc_next;
+  return before + x;
+}
+
+// ---------------------------------------------------------------------------
+// A spilled interval of a one-group program, checked by one block of the
+// group check kernel.  With one group there is no INTER scope, so the
+// interval's accesses, in the group's log region as packed words (cell key,
+// store flag, lid, value), need only be grouped by cell.  They are bucketed
+// by windows of SC_WIN cells into a second buffer (a count, a scan and a
+// scatter, LDS counters), and each bucket is checked through a per-cell
+// table over its window in LDS: the two passes of min-reductions as LDS
+// atomics, a bitmap of the touched cells, then a pass over the touched
+// cells in cell order that emits the records and clears the cells again.
+// The table therefore stays clean between buckets and intervals (the block
+// clears it once).  Buckets are taken in cell order, so the records leave
+// in cell-key order with their ranks, as from the LDS path.  Arguments are
+// uniform; every thread of the block calls it.
+// ---------------------------------------------------------------------------
+struct ScEnv {
+  u64* src;              // the interval's m packed entries in the region
+  u64* dst;              // the same words of the second log buffer
+  uint32_t* ends;        // the block's bucket ends (SC_NB_MAX words)
+  uint32_t cells, nthr;
+  uint32_t slot, instance, interval, n_arrays;
+  const ArrayDesc* arrays;
+  const rc_record_out* recp;
+  RecKey K;
+  TabCell* tab;          // LDS: SC_WIN cells, clean
+  uint32_t* bits;        // LDS: SC_WORDS words, zero
+  uint32_t* cnt;         // LDS: SC_NB_MAX bucket counters
+};
+
+__device__ __forceinline__ uint32_t sc_aid(const ScEnv& E, uint32_t ck) {
+  uint32_t aid = 0;
+  for (uint32_t a = 0; a < E.n_arrays; ++a) {
+    const ArrayDesc D = const_load<ArrayDesc>(E.arrays, a);
+    if (D.logged == LOG_LDS && ck >= D.cellbase && ck - D.cellbase < D.size) aid = a;
+  }
+  return aid;
+}
+
+// Bucket in[0, n) by window (cell key >> SC_WIN_BITS) into out, nb
+// buckets; E.ends[b] = end of bucket b in out.
+__device__ void sc_bucket(const ScEnv& E, const u64* in, u64* out, u64 n, uint32_t nb) {
+  const uint32_t tl = threadIdx.x, lane = tl & 63u;
+  uint32_t* cnt = E.cnt;
+  for (uint32_t i = tl; i < nb; i += E.nthr) cnt[i] = 0u;
+  __syncthreads();
+  for (u64 i = tl; i < n; i += E.nthr) atomicAdd(&cnt[(uint32_t)(in[i] >> 43) >> SC_WIN_BITS], 1u);
+  __syncthreads();
+  if (tl < 64u) {   // exclusive scan: lane l takes a contiguous run of counters
+    const uint32_t per = (nb + 63u) / 64u, lo = lane * per, hi = lo + per < nb ? lo + per : nb;
+    uint32_t sum = 0;
+    for (uint32_t j = lo; j < hi; ++j) sum += cnt[j];
+    uint32_t run = sum;
+    for (uint32_t off = 1; off < 64u; off <<= 1) {
+      const uint32_t o = __shfl_up(run, off);
+      if (lane >= off) run += o;
+    }
+    run -= sum;
+    for (uint32_t j = lo; j < hi; ++j) {
+      const uint32_t c = cnt[j];
+      cnt[j] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (u64 i = tl; i < n; i += E.nthr) {
+    const u64 e = in[i];
+    const uint32_t pos = atomicAdd(&cnt[(uint32_t)(e >> 43) >> SC_WIN_BITS], 1u);
+    out[pos] = e;
+  }
+  __syncthreads();
+  for (uint32_t i = tl; i < nb; i += E.nthr) E.ends[i] = cnt[i];
+  // the bucket contents and bounds are read back by other threads of the block
+  __threadfence();
+  __syncthreads();
+}
+
+// Check bucket in[0, n) (cell keys base .. base + SC_WIN - 1) through the
+// table; kb = records of the interval so far; returns the new count.
+__device__ uint32_t sc_window(const ScEnv& E, const u64* in, uint32_t n, uint32_t base, uint32_t kb) {
+  const uint32_t tl = threadIdx.x;
+  TabCell* tab = E.tab;
+  Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
+  for (uint32_t i = tl; i < n; i += E.nthr) {
+    const u64 e = in[i];
+    const uint32_t c = (uint32_t)(e >> 43) - base;
+    TabCell& t = tab[c];
+    const uint32_t l = (uint32_t)(e >> 32) & 1023u;
+    if ((e >> 42) & 1u) atomicMin(&t.wmin, ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u));
+    else atomicMin(&t.r1, l);
+    atomicOr(&E.bits[c >> 5], 1u << (c & 31u));
+  }
+  __syncthreads();
+  for (uint32_t i = tl; i < n; i += E.nthr) {
+    const u64 e = in[i];
+    TabCell& t = tab[(uint32_t)(e >> 43) - base];
+    const uint32_t l = (uint32_t)(e >> 32) & 1023u;
+    if ((e >> 42) & 1u) {
+      const u64 wmin = t.wmin;
+      if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u)) atomicMin(&t.q, l);
+      if (l != (uint32_t)(wmin >> 32)) atomicMin(&t.w2, l);
+    } else if (l != t.r1) {
+      atomicMin(&t.r2, l);
+    }
+  }
+  __syncthreads();
+  // thread w < SC_WORDS finishes the touched cells of bitmap word w, in
+  // cell order: a count, the group's reservation, then the records; every
+  // touched cell is cleared again
+  const uint32_t word = tl < SC_WORDS ? E.bits[tl] : 0u;
+  uint32_t mine = 0;
+  for (uint32_t m = word; m; m &= m - 1u) {
+    PendingRec pr;
+    if (tab_cell_finish(tab[tl * 32u + (uint32_t)__ffs(m) - 1u], &pr)) ++mine;
+  }
+  const rc_record_out R = const_load<rc_record_out>(E.recp, 0);
+  u64 room, at0, jump;
+  uint32_t k = reserve_records(ctl, R, mine, tl, E.nthr, &room, &at0, &jump);
+  const uint32_t total = ctl->rec_sum_total;
+  const TabCell empty_cell = empty_tab_cell();
+  for (uint32_t m = word; m; m &= m - 1u) {
+    const uint32_t c = tl * 32u + (uint32_t)__ffs(m) - 1u;
+    const TabCell t = tab[c];
+    tab[c] = empty_cell;
+    PendingRec pr;
+    if (!tab_cell_finish(t, &pr)) continue;
+    const uint32_t ck = base + c;
+    const uint32_t aid = sc_aid(E, ck);
+    pr.gid = 0; pr.interval = E.interval; pr.aid = aid;
+    pr.cell = ck - const_load<ArrayDesc>(E.arrays, aid).cellbase;
+    pr.cellkey = ck; pr.lidbase = 0;
+    store_record(R, E.K, k < room ? at0 + k : jump + (k - room), E.slot, E.instance, pr, false, kb + k);
+    ++k;
+  }
+  if (tl < SC_WORDS) E.bits[tl] = 0u;
+  __syncthreads();   // the table is clean again
+  return kb + total;
+}
+
+__device__ __forceinline__ uint32_t sc_check(const ScEnv& E, u64 m) {
+  const uint32_t nb = (E.cells + SC_WIN - 1u) >> SC_WIN_BITS;
+  sc_bucket(E, E.src, E.dst, m, nb);
+  uint32_t kb = 0, s = 0;
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uint32_t e = uni(E.ends[b]);
+    if (e - s >= 2u) kb = sc_window(E, E.dst + s, e - s, b << SC_WIN_BITS, kb);
+    s = e;
+  }
+  return kb;
 }
 
 // The state of one item on its workgroup (uniform values in scalars, per-lane
@@ -419,6 +634,8 @@ struct Item {
   uint32_t n_logged;       // this work-item's logged accesses
   uint32_t n_spilled;      // intervals of the group whose log moved to the global log
   uint32_t n_insn;         // instructions the group executed (uniform)
+  u64 n_glog;              // entries of spilled intervals (one-group programs: trailers not counted)
+  u64 ival_base;           // (one-group programs) region word where the current spilled interval starts
   u64 my_fault;            // earliest fault of this work-item (fault_key order)
   bool faulted;
 
@@ -478,7 +695,7 @@ struct Item {
     lds_used = 0;
     lds_spilled = false;
     step = 0; last_spc = ~0u; store_seq = 0; interval = 0; parity = 0; n_acc = 0;
-    n_logged = 0; n_spilled = 0; iters = 0; n_insn = 0;
+    n_logged = 0; n_spilled = 0; iters = 0; n_insn = 0; n_glog = 0; ival_base = 0;
     my_fault = ~0ull;
     faulted = false;
   }
@@ -597,66 +814,35 @@ struct Item {
   // The record of a table cell, if its accesses form one (labels and pairs
   // only; the caller adds the location).
   __device__ __forceinline__ static bool tab_finish(const TabCell c, PendingRec* pr) {
-    if (c.wmin == ~0ull && c.r1 == NONE32) return false;
-    const uint32_t w1 = c.wmin == ~0ull ? NONE32 : (uint32_t)(c.wmin >> 32);
-    const bool multi1 = c.q != NONE32 && c.q == w1;
-    const Pass1 p1 = {c.r1, c.wmin};
-    const Intra2 p2 = {c.r2, c.w2, multi1 ? NONE32 : c.q, multi1 ? 1u : 0u};
-    return intra_finish(p1, p2, &pr->label, &pr->rw, &pr->ww);
+    return tab_cell_finish(c, pr);
   }
 
-  // Record slots for the whole group: this thread's n records are the
-  // group's records [k, k + n) (threads in order), and the k-th record of
-  // the group goes to slot_of(k).  The block takes the slots from chunks of
-  // REC_CHUNK it reserves with one atomic (not one per interval): the rest
-  // of the current chunk first, then a new one.  Every thread of the block
-  // calls it.  (n <= 64: a thread finishes at most 4096 / 64 cells; the
-  // wave's scan is taken bit-plane by bit-plane with ballots.)
+  // Record slots for the whole group (reserve_records): this thread's n
+  // records (n <= 64: a thread finishes at most 4096 / 64 cells) are the
+  // group's records [k, k + n), the k-th going to slot_of(k).
   __device__ __forceinline__ uint32_t group_reserve(const rc_record_out& R, uint32_t n) {
-    const u64 below = (1ull << lane) - 1ull;
-    uint32_t x = 0, wsum = 0;   // exclusive prefix in the wave, wave total
-#pragma unroll
-    for (uint32_t b = 0; b < 7; ++b) {
-      const u64 m = __ballot((n >> b) & 1u);
-      x += (uint32_t)__popcll(m & below) << b;
-      wsum += (uint32_t)__popcll(m) << b;
-    }
-    if (lane == 0) ctl->rec_sum[wave] = wsum;
-    __syncthreads();
-    const uint32_t nw = nthr >> 6;
-    uint32_t before = 0, total = 0;
-    for (uint32_t w = 0; w < nw; ++w) {
-      const uint32_t v = ctl->rec_sum[w];
-      total += v;
-      if (w < wave) before += v;
-    }
-    if (tl == 0) {
-      ctl->rec_sum_total = total;
-      const u64 room = ctl->rc_end - ctl->rc_cur;
-      ctl->rec_base = ctl->rc_cur;               // records [0, room) go here
-      ctl->rc_room = room;
-      if (total <= room) {
-        ctl->rc_cur += total;
-        ctl->rc_next = ctl->rc_end;
-      } else {
-        const u64 more = total - room;           // and the rest to a new chunk
-        const u64 take = more > REC_CHUNK ? more : REC_CHUNK;
-        const u64 base = __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, R.rec_count), (unsigned long long)take,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ctl->rc_next = base;
-        ctl->rc_cur = base + more;
-        ctl->rc_end = base + take;
-      }
-    }
-    __syncthreads();
-    rec_room = ctl->rc_room;
-    rec_at = ctl->rec_base;
-    rec_jump = ctl->rc_next;
-    return before + x;
+    return reserve_records(ctl, R, n, tl, nthr, &rec_room, &rec_at, &rec_jump);
   }
   // the slot of the group's k-th record of the last reservation
   __device__ __forceinline__ u64 slot_of(uint32_t k) const {
     return k < rec_room ? rec_at + k : rec_jump + (k - rec_room);
+  }
+
+  // One entry at position pos of the group's global log region: key and
+  // payload words (with the owner word when filtering), or for a group that
+  // checks its spilled intervals itself (P.sc) one packed word.
+  __device__ __forceinline__ void glog_put(u64 pos, u64 ck, uint32_t meta, uint32_t v) {
+    if (pos >= P.wg_log_cap) {
+      atomicOr(P.status_word, 1u);
+      return;
+    }
+    if (P.sc) {
+      P.log_keys[log_base + pos] = tab_entry((uint32_t)ck, (meta & 1024u) != 0u, meta & 1023u, (int32_t)v);
+      return;
+    }
+    P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
+    P.log_vals[log_base + pos] = ((u64)v << 32) | meta;
+    if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
   }
 
   // Move LDS log entries [0, count) of the current interval to the group's
@@ -680,15 +866,24 @@ struct Item {
         meta = lmeta[i];
         v = (uint32_t)lval[i];
       }
-      if (pos < P.wg_log_cap) {
-        P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
-        P.log_vals[log_base + pos] = ((u64)v << 32) | meta;
-        if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
-      } else {
-        atomicOr(P.status_word, 1u);
-      }
+      glog_put(pos, ck, meta, v);
     }
     __syncthreads();
+  }
+
+  // A spilled interval of a one-group program closes: a trailer word after
+  // its entries in the group's region, (interval << 32) | entry count,
+  // lets the group check kernel find it (sc_group_kernel walks the
+  // trailers back from the region's end).  end: the region's words so far.
+  __device__ __forceinline__ u64 spill_trailer(u64 end) {
+    const u64 count = end - ival_base;
+    if (tl == 0) {
+      if (end < P.wg_log_cap) P.log_keys[log_base + end] = ((u64)interval << 32) | count;
+      else atomicOr(P.status_word, 1u);
+    }
+    n_glog += count;
+    ival_base = end + 1u;
+    return end + 1u;
   }
 
   // Close the current interval on the LDS path: check its log in LDS (by a
@@ -717,6 +912,12 @@ struct Item {
       if (n > P.lds_log_cap) {
         spill_nf(P.lds_log_cap);
         ++n_spilled;
+        if (P.sc) {
+          const u64 end = ((u64)uni((uint32_t)(ctl->gl_cnt >> 32)) << 32) | uni((uint32_t)ctl->gl_cnt);
+          const u64 next = spill_trailer(end);
+          if (tl == 0) ctl->gl_cnt = next;
+          __syncthreads();
+        }
         return;
       }
     }
@@ -724,6 +925,12 @@ struct Item {
   const bool spilled = lds_spilled;
   lds_used = 0;
   lds_spilled = false;
+#ifndef RC_JIT_NOSPILL
+  if (spilled && P.sc) {
+    log_used = spill_trailer(log_used);
+    return;
+  }
+#endif
   if (spilled || n < 2u) return;
   const rc_record_out R = const_load<rc_record_out>(P.rec, 0);
   const RecKey K = {P.bs, P.bc, P.G, P.NI};
@@ -916,13 +1123,7 @@ struct Item {
     base = ((u64)(uint32_t)__shfl((int)(base >> 32), 0) << 32) | (uint32_t)__shfl((int)(uint32_t)base, 0);
     if (!mine) return;
     const u64 pos = base + (u64)__popcll(mask & ((1ull << lane) - 1ull));
-    if (pos < P.wg_log_cap) {
-      P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
-      P.log_vals[log_base + pos] = ((u64)(uint32_t)v << 32) | meta;
-      if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
-    } else {
-      atomicOr(P.status_word, 1u);
-    }
+    glog_put(pos, ck, meta, (uint32_t)v);
   }
 
   // Log an access with elided group steps: an LDS log position from the
@@ -1067,13 +1268,7 @@ struct Item {
             meta = lmeta[i];
             v = (uint32_t)lval[i];
           }
-          if (pos < P.wg_log_cap) {
-            P.log_keys[log_base + pos] = key_slot | (((ck << P.bg) | gid) << P.bk) | interval;
-            P.log_vals[log_base + pos] = ((u64)v << 32) | meta;
-            if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + ck] = (gid << 10) | (meta & 1023u);
-          } else {
-            atomicOr(P.status_word, 1u);
-          }
+          glog_put(pos, ck, meta, v);
         }
         log_used += lds_used;
         lds_used = 0;
@@ -1096,16 +1291,7 @@ struct Item {
         }
         lds_used += total;
       } else {
-        if (rec) {
-          const u64 pos = log_used + below;
-          if (pos < P.wg_log_cap) {
-            P.log_keys[log_base + pos] = key_slot | ((((u64)(A.cellbase + cell) << P.bg) | gid) << P.bk) | interval;
-            P.log_vals[log_base + pos] = ((u64)(uint32_t)val << 32) | meta;
-            if (P.cell_owner) P.cell_owner[(u64)slot * P.co_stride + A.cellbase + cell] = (gid << 10) | tl;
-          } else {
-            atomicOr(P.status_word, 1u);
-          }
-        }
+        if (rec) glog_put(log_used + below, (u64)A.cellbase + cell, meta, (uint32_t)val);
         log_used += total;
       }
     }
@@ -1163,7 +1349,13 @@ struct Item {
       for (int off = 32; off > 0; off >>= 1) lg += __shfl_down(lg, off);
       if (lane == 0 && lg) atomicAdd(&P.stats[0], lg);
       if (tl == 0) {
-        if (log_used) atomicAdd(&P.stats[1], (u64)(log_used < P.wg_log_cap ? log_used : P.wg_log_cap));
+        // entries for the global pass or (one-group programs) the group
+        // check, trailers not counted
+        const u64 left = P.sc ? n_glog : (log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
+        if (left) {
+          atomicAdd(&P.stats[1], left);
+          atomicAdd(&P.stats[6], left);
+        }
         if (n_spilled) atomicAdd(&P.stats[2], (u64)n_spilled);
         atomicAdd(&P.stats[3], (u64)(interval + 1u));
         atomicAdd(&P.stats[4], (u64)n_insn);
@@ -1226,6 +1418,7 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
     P.stats = PP.stats;
     P.nf = D.nf;
     P.step_limit = D.step_limit;
+    P.sc = D.sc;
 #ifdef RC_JIT_W
     // A per-program kernel is compiled for one launch shape: its constants
     // replace the descriptor's fields, so the compiler folds them.  A

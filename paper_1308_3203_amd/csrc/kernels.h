@@ -98,6 +98,28 @@ struct FinalMemParams {
   int32_t* out;
 };
 
+// Spilled intervals of one-group programs, checked after the interpreter
+// (sc_group_kernel): the chunk's instances from queue (zeroed by the chunk
+// setup), per block SC_NB_MAX u32 of bucket bounds at ends.
+struct ScParams {
+  const ProgDesc* progs;
+  const SlotDesc* slots;
+  const ChunkDesc* chunks;
+  const uint32_t* chunk_index;
+  unsigned long long* log_keys;   // the regions: packed entries and trailers
+  unsigned long long* log_vals;   // the same regions, second buffer
+  uint32_t* wg_count;             // [work-group] region words written (zeroed once checked)
+  uint32_t* queue;
+  uint32_t* ends;
+  const rc_record_out* rec;
+  uint32_t bs, bc;
+};
+constexpr uint32_t SC_THREADS = 256;
+constexpr uint32_t SC_CTL_BYTES = (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15);
+constexpr uint32_t SC_MAX_BLOCKS = 1024;
+hipError_t launch_sc_group(const ScParams& S, uint32_t blocks, hipStream_t st);
+int sc_group_occupancy();
+
 // vreg: the interpreter variant with the private variables in a 16-entry
 // VGPR file (every program of the call has at most 16 registers)
 constexpr uint32_t VREG_FILE = 16;

@@ -152,6 +152,101 @@ __global__ __launch_bounds__(1024) void rc_interp_vreg_kernel(PassParams PP) {
 }
 
 // ---------------------------------------------------------------------------
+// Spilled intervals of one-group programs (ProgDesc::sc), after the
+// interpreter: persistent blocks take the chunk's instances from a queue;
+// for each one whose program has sc set, the block walks its region's
+// trailers back from the end, checks every spilled interval in LDS
+// (sc_check), and sets the region's count to zero.  Its records carry the interval's ranks and counts like those
+// of an interval closed in LDS.  LDS: the control block, then the work area.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SC_THREADS) void sc_group_kernel(ScParams S) {
+  Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
+  const uint32_t tl = threadIdx.x;
+  const ChunkDesc C = const_load<ChunkDesc>(S.chunks, const_load<uint32_t>(S.chunk_index, 0));
+  const rc_record_out R = const_load<rc_record_out>(S.rec, 0);
+  if (tl == 0) ctl->rc_cur = ctl->rc_end = 0ull;   // no record slots yet
+  // the work area: the window table (cleared once, kept clean), the
+  // touched-cell bitmap, the bucket counters
+  TabCell* tab = reinterpret_cast<TabCell*>(rc_smem + SC_CTL_BYTES);
+  uint32_t* bits = reinterpret_cast<uint32_t*>(rc_smem + SC_CTL_BYTES + SC_WIN * sizeof(TabCell));
+  uint32_t* cnt = bits + SC_WORDS;
+  {
+    const TabCell empty_cell = empty_tab_cell();
+    for (uint32_t i = tl; i < SC_WIN; i += SC_THREADS) tab[i] = empty_cell;
+    for (uint32_t i = tl; i < SC_WORDS; i += SC_THREADS) bits[i] = 0u;
+  }
+  __syncthreads();
+  for (;;) {
+    if (tl == 0) ctl->item = atomicAdd(S.queue, 1u);
+    __syncthreads();
+    const uint32_t rel = uni(ctl->item);
+    __syncthreads();
+    if (rel >= C.n_slots) {
+      // the block's unused record slots
+      const u64 a = ctl->rc_cur, b = ctl->rc_end;
+      for (u64 q = a + tl; q < b && q < R.rec_cap; q += SC_THREADS) RC_GLOBAL(u64, R.rec_keys)[q] = ~0ull;
+      if (tl == 0 && b > a)
+        __hip_atomic_fetch_add(RC_GLOBAL(unsigned long long, R.rec_dead), (unsigned long long)(b - a),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    const uint32_t instance = C.slot0 + rel;
+    const SlotDesc Sd = const_load<SlotDesc>(S.slots, instance);
+    const ProgDesc D = const_load<ProgDesc>(S.progs, Sd.prog);
+    if (!D.sc) continue;
+    u64 pos = uni(S.wg_count[Sd.wg_base]);
+    if (pos == 0u) continue;
+    u64* region = S.log_keys + Sd.log_base;
+    ScEnv E;
+    E.ends = S.ends + (u64)blockIdx.x * SC_NB_MAX;
+    E.cells = D.n_cells;
+    E.nthr = SC_THREADS;
+    E.tab = tab;
+    E.bits = bits;
+    E.cnt = cnt;
+    E.slot = rel;
+    E.instance = instance;
+    E.n_arrays = D.n_arrays;
+    E.arrays = D.arrays;
+    E.recp = S.rec;
+    E.K = RecKey{S.bs, S.bc, D.G, D.NI};
+    while (pos > 0u) {
+      const u64 t = region[pos - 1u];
+      const uint32_t cnt = uni((uint32_t)t), interval = uni((uint32_t)(t >> 32));
+      if ((u64)cnt >= pos) break;   // (a region that overflowed: already reported)
+      const u64 start = pos - 1u - cnt;
+      E.src = region + start;
+      E.dst = S.log_vals + Sd.log_base + start;
+      E.interval = interval;
+      const uint32_t kb = cnt >= 2u ? sc_check(E, cnt) : 0u;
+      if (R.rank_keys && tl == 0 && kb)
+        RC_GLOBAL(uint32_t, R.scope_cnt)[((u64)rel << S.bs) | interval] = kb;
+      pos = start;
+    }
+    // the region is consumed: in a call that also has a global pass (other
+    // programs log globally), that pass must not take its packed words for
+    // (key, payload) entries
+    __syncthreads();   // (every thread has read the count)
+    if (tl == 0) S.wg_count[Sd.wg_base] = 0u;
+  }
+}
+
+// LDS of a group check block: control block, window table, bitmap, counters
+constexpr size_t SC_LDS_BYTES = SC_CTL_BYTES + SC_WIN * sizeof(TabCell) + SC_WORDS * 4 + SC_NB_MAX * 4;
+
+hipError_t launch_sc_group(const ScParams& S, uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(sc_group_kernel, dim3(blocks), dim3(SC_THREADS), SC_LDS_BYTES, st, S);
+  return hipGetLastError();
+}
+
+int sc_group_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sc_group_kernel, (int)SC_THREADS, SC_LDS_BYTES) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+// ---------------------------------------------------------------------------
 // exclusive scan of u32 arrays (three-level, 1024 elements per block)
 // ---------------------------------------------------------------------------
 constexpr uint32_t SCAN_BLOCK = 1024;
@@ -1046,7 +1141,7 @@ __global__ __launch_bounds__(256) void chunk_setup_kernel(SetupParams P) {
   const ChunkDesc C = P.chunks[*P.chunk_index];
   const uint32_t t = threadIdx.x;
   if (blockIdx.x == 0 && t < 8) P.counters[t] = 0ull;       // log, records, queue words
-  if (blockIdx.x == 0 && t < N_WCLASS) P.queue[t] = 0u;
+  if (blockIdx.x == 0 && t <= N_WCLASS) P.queue[t] = 0u;   // the classes' queues and the group check's
   for (uint32_t s = blockIdx.x * blockDim.x + t; s < P.max_slots; s += gridDim.x * blockDim.x) {
     P.inst_acc[s] = 0ull;
     P.inst_fault[s] = ~0ull;

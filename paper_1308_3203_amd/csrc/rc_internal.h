@@ -125,7 +125,19 @@ struct ProgDesc {                 // one program of the call
   uint32_t log_high;
   uint32_t step_limit;            // loop iterations a work-group may start (then F_STEP_LIMIT)
   uint64_t log_mask;
+  // spilled intervals of a one-group program checked by the group check
+  // kernel (sc_group_kernel) instead of the global pass: sc != 0; n_cells
+  // log cell keys.  The group's region then holds, per spilled interval,
+  // its entries as packed words and a trailer (interval << 32 | count).
+  uint32_t sc, n_cells;
 };
+// (one-group programs) spilled intervals: log entries are packed words (cell
+// key:21 | store:1 | lid:10 | value:32, as tab_entry), at most SC_MAX_CELLS
+// cell keys, so at most SC_NB_MAX windows of SC_WIN cells in the check
+constexpr uint32_t SC_MAX_CELLS = 1u << 21;
+constexpr uint32_t SC_NB_MAX = 1024;
+constexpr uint32_t SC_WIN_BITS = 11, SC_WIN = 1u << SC_WIN_BITS;   // cells per table window of the check
+constexpr uint32_t SC_WORDS = SC_WIN / 32u;                        // bitmap words of a window
 
 // one cell's running check state in the LDS table (24 bytes)
 struct TabCell {
@@ -180,7 +192,9 @@ struct PassParams {
   uint32_t cell_owner_stride, pad_co;
   // the call's log statistics (summed over chunks), or null: [0] logged
   // accesses, [1] entries written to the global log, [2] intervals whose LDS
-  // log moved to the global log, [3] intervals closed
+  // log moved to the global log, [3] intervals closed, [4] instructions
+  // executed (per work-group), [5] the same times the block's waves, [6]
+  // global log entries left to the global pass
   unsigned long long* stats;
 };
 constexpr uint32_t OWNER_SHARED = 0xFFFFFFFFu;

@@ -403,6 +403,8 @@ def main():
     ap.add_argument("--eval-programs", type=int, default=1000, help="c5: held-out programs")
     ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
     ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
+    ap.add_argument("--weight-records", action="store_true",
+                    help="c5: training rows repeated by their RACE record count (log2)")
     ap.add_argument("--copy-probe", type=float, default=0.0, help="only run a plain copy of this many GiB")
     ap.add_argument("--no-jit", action="store_true", help="c1/c2/c4: interpret instead of per-program kernels")
     ap.add_argument("--eager", action="store_true",
@@ -643,7 +645,7 @@ def bench_c5(args, ctx):
     r = T.run(ctx, [WL.c3_kernel(s) for s in range(n_train)], seeds,
               [WL.c3_kernel(10000 + s) for s in range(n_eval)], seeds,
               epochs=args.epochs, batch=4096, lr=1e-3, chunk=args.chunk, label_chunk=20000,
-              ws_bytes=int(args.ws_gb * (1 << 30)),
+              ws_bytes=int(args.ws_gb * (1 << 30)), weight_records=args.weight_records,
               progress=lambda m: print(f"[c5 {time.perf_counter() - t0:.1f}s] {m}", file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -658,6 +660,7 @@ def bench_c5(args, ctx):
                                                                           seeds),
                    "train_instances": r.n_train, "eval_instances": r.n_eval,
                    "train_racy_frac": round(r.train_racy_frac, 4), "epochs": args.epochs,
+                   "weight_records": args.weight_records,
                    "losses": [round(x, 5) for x in r.losses]},
         "triage": {"recall_racy_instances": round(rep.recall_instances, 4),
                    "recall_race_records": round(rep.recall_records, 4),
@@ -666,7 +669,12 @@ def bench_c5(args, ctx):
                    "plain_sweep_gpu_ms": round(rep.plain_ms, 2), "budget_frac": rep.budget_frac,
                    "inference_gpu_ms": round(rep.inference_ms, 3), "label_sweep_gpu_ms": round(r.label_ms, 1),
                    "train_gpu_ms": round(r.train_ms, 1), "racy_instances": rep.n_racy,
-                   "race_records": rep.n_race_records},
+                   "race_records": rep.n_race_records,
+                   "orders": {k: {"recall_racy_instances": round(o.recall_instances, 4),
+                                  "recall_race_records": round(o.recall_records, 4),
+                                  "races_per_gpu_s": round(o.races_per_gpu_s, 1),
+                                  "curve_frac_time_instances_records": o.curve}
+                              for k, o in rep.orders.items()}},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)

@@ -573,7 +573,8 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     L.max_rec = std::max<u64>(L.max_rec, L.max_log);
     // slots that work-groups reserve in chunks and leave unused: at most a
     // chunk per launched block (a block per work item at most)
-    L.max_rec += std::min<u64>(L.max_wg, (u64)N_WCLASS * REC_MAX_BLOCKS) * REC_CHUNK;
+    // (and a chunk per block of the group check)
+    L.max_rec += (std::min<u64>(L.max_wg, (u64)N_WCLASS * REC_MAX_BLOCKS) + (any_sc ? SC_MAX_BLOCKS : 0)) * REC_CHUNK;
     L.bi = bits_for(L.max_slots);
     L.bc = bc; L.bg = bg; L.bk = bk; L.bs = bs;
     L.nbits_log = L.bi + bc + bg + bk;

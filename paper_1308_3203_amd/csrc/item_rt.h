@@ -478,8 +478,11 @@ struct ScEnv {
   const ArrayDesc* arrays;
   const rc_record_out* recp;
   RecKey K;
-  TabCell* tab;          // LDS: SC_WIN cells, clean
-  uint32_t* bits;        // LDS: SC_WORDS words, zero
+  // LDS: the window table, one array per field of a cell (consecutive
+  // cells in consecutive banks), clean; the bitmap, zero
+  u64* wmin;
+  uint32_t *r1, *r2, *w2, *q;
+  uint32_t* bits;        // SC_WORDS words
   uint32_t* cnt;         // LDS: SC_NB_MAX bucket counters
 };
 
@@ -492,6 +495,25 @@ __device__ __forceinline__ uint32_t sc_aid(const ScEnv& E, uint32_t ck) {
   return aid;
 }
 
+// f(e) for every entry e of in[0, n), in rounds of four loads per thread
+// (issued together: the passes are bound by memory latency)
+template <typename F>
+__device__ __forceinline__ void sc_each(const u64* in, u64 n, uint32_t nthr, F f) {
+  for (u64 i0 = threadIdx.x; i0 < n; i0 += 4u * (u64)nthr) {
+    u64 e[4];
+    bool ok[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const u64 i = i0 + (u64)k * nthr;
+      ok[k] = i < n;
+      e[k] = ok[k] ? in[i] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (ok[k]) f(e[k]);
+  }
+}
+
 // Bucket in[0, n) by window (cell key >> SC_WIN_BITS) into out, nb
 // buckets; E.ends[b] = end of bucket b in out.
 __device__ void sc_bucket(const ScEnv& E, const u64* in, u64* out, u64 n, uint32_t nb) {
@@ -499,7 +521,7 @@ __device__ void sc_bucket(const ScEnv& E, const u64* in, u64* out, u64 n, uint32
   uint32_t* cnt = E.cnt;
   for (uint32_t i = tl; i < nb; i += E.nthr) cnt[i] = 0u;
   __syncthreads();
-  for (u64 i = tl; i < n; i += E.nthr) atomicAdd(&cnt[(uint32_t)(in[i] >> 43) >> SC_WIN_BITS], 1u);
+  sc_each(in, n, E.nthr, [&](u64 e) { atomicAdd(&cnt[(uint32_t)(e >> 43) >> SC_WIN_BITS], 1u); });
   __syncthreads();
   if (tl < 64u) {   // exclusive scan: lane l takes a contiguous run of counters
     const uint32_t per = (nb + 63u) / 64u, lo = lane * per, hi = lo + per < nb ? lo + per : nb;
@@ -518,11 +540,7 @@ __device__ void sc_bucket(const ScEnv& E, const u64* in, u64* out, u64 n, uint32
     }
   }
   __syncthreads();
-  for (u64 i = tl; i < n; i += E.nthr) {
-    const u64 e = in[i];
-    const uint32_t pos = atomicAdd(&cnt[(uint32_t)(e >> 43) >> SC_WIN_BITS], 1u);
-    out[pos] = e;
-  }
+  sc_each(in, n, E.nthr, [&](u64 e) { out[atomicAdd(&cnt[(uint32_t)(e >> 43) >> SC_WIN_BITS], 1u)] = e; });
   __syncthreads();
   for (uint32_t i = tl; i < nb; i += E.nthr) E.ends[i] = cnt[i];
   // the bucket contents and bounds are read back by other threads of the block
@@ -531,54 +549,74 @@ __device__ void sc_bucket(const ScEnv& E, const u64* in, u64* out, u64 n, uint32
 }
 
 // Check bucket in[0, n) (cell keys base .. base + SC_WIN - 1) through the
-// table; kb = records of the interval so far; returns the new count.
+// table; kb = records of the interval so far; returns the new count.  A
+// bucket of at least SC_SCAN_MIN entries finishes every cell of the window
+// (each thread SC_WIN / nthr consecutive ones); a smaller one finishes the
+// cells its bitmap marks (set by the first reader and the first writer of
+// each cell).
+constexpr uint32_t SC_SCAN_MIN = 256;
+__device__ __forceinline__ bool sc_touched(const ScEnv& E, uint32_t c) {
+  return E.wmin[c] != ~0ull || E.r1[c] != NONE32;
+}
+__device__ __forceinline__ TabCell sc_cell(const ScEnv& E, uint32_t c) {
+  return TabCell{E.wmin[c], E.r1[c], E.r2[c], E.w2[c], E.q[c]};
+}
+__device__ __forceinline__ void sc_clear(const ScEnv& E, uint32_t c) {
+  E.wmin[c] = ~0ull;
+  E.r1[c] = E.r2[c] = E.w2[c] = E.q[c] = NONE32;
+}
+
 __device__ uint32_t sc_window(const ScEnv& E, const u64* in, uint32_t n, uint32_t base, uint32_t kb) {
   const uint32_t tl = threadIdx.x;
-  TabCell* tab = E.tab;
   Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
-  for (uint32_t i = tl; i < n; i += E.nthr) {
-    const u64 e = in[i];
+  const bool scan = n >= SC_SCAN_MIN;
+  sc_each(in, n, E.nthr, [&](u64 e) {
     const uint32_t c = (uint32_t)(e >> 43) - base;
-    TabCell& t = tab[c];
     const uint32_t l = (uint32_t)(e >> 32) & 1023u;
-    if ((e >> 42) & 1u) atomicMin(&t.wmin, ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u));
-    else atomicMin(&t.r1, l);
-    atomicOr(&E.bits[c >> 5], 1u << (c & 31u));
-  }
+    bool first;
+    if ((e >> 42) & 1u) first = atomicMin(&E.wmin[c], ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u)) == ~0ull;
+    else first = atomicMin(&E.r1[c], l) == NONE32;
+    if (!scan && first) atomicOr(&E.bits[c >> 5], 1u << (c & 31u));
+  });
   __syncthreads();
-  for (uint32_t i = tl; i < n; i += E.nthr) {
-    const u64 e = in[i];
-    TabCell& t = tab[(uint32_t)(e >> 43) - base];
+  sc_each(in, n, E.nthr, [&](u64 e) {
+    const uint32_t c = (uint32_t)(e >> 43) - base;
     const uint32_t l = (uint32_t)(e >> 32) & 1023u;
     if ((e >> 42) & 1u) {
-      const u64 wmin = t.wmin;
-      if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u)) atomicMin(&t.q, l);
-      if (l != (uint32_t)(wmin >> 32)) atomicMin(&t.w2, l);
-    } else if (l != t.r1) {
-      atomicMin(&t.r2, l);
+      const u64 wmin = E.wmin[c];
+      if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u)) atomicMin(&E.q[c], l);
+      if (l != (uint32_t)(wmin >> 32)) atomicMin(&E.w2[c], l);
+    } else if (l != E.r1[c]) {
+      atomicMin(&E.r2[c], l);
     }
-  }
+  });
   __syncthreads();
-  // thread w < SC_WORDS finishes the touched cells of bitmap word w, in
-  // cell order: a count, the group's reservation, then the records; every
-  // touched cell is cleared again
-  const uint32_t word = tl < SC_WORDS ? E.bits[tl] : 0u;
+  // the cells this thread finishes, in cell order: a count, the group's
+  // reservation, then the records; every touched cell is cleared again
+  const uint32_t per = SC_WIN / E.nthr;
+  const uint32_t c0 = tl * per;
+  const uint32_t word = !scan && tl < SC_WORDS ? E.bits[tl] : 0u;
   uint32_t mine = 0;
-  for (uint32_t m = word; m; m &= m - 1u) {
-    PendingRec pr;
-    if (tab_cell_finish(tab[tl * 32u + (uint32_t)__ffs(m) - 1u], &pr)) ++mine;
+  if (scan) {
+    for (uint32_t c = c0; c < c0 + per; ++c) {
+      if (!sc_touched(E, c)) continue;
+      PendingRec pr;
+      if (tab_cell_finish(sc_cell(E, c), &pr)) ++mine;
+    }
+  } else {
+    for (uint32_t m = word; m; m &= m - 1u) {
+      PendingRec pr;
+      if (tab_cell_finish(sc_cell(E, tl * 32u + (uint32_t)__ffs(m) - 1u), &pr)) ++mine;
+    }
   }
   const rc_record_out R = const_load<rc_record_out>(E.recp, 0);
   u64 room, at0, jump;
   uint32_t k = reserve_records(ctl, R, mine, tl, E.nthr, &room, &at0, &jump);
-  const uint32_t total = ctl->rec_sum_total;
-  const TabCell empty_cell = empty_tab_cell();
-  for (uint32_t m = word; m; m &= m - 1u) {
-    const uint32_t c = tl * 32u + (uint32_t)__ffs(m) - 1u;
-    const TabCell t = tab[c];
-    tab[c] = empty_cell;
+  auto emit = [&](uint32_t c) {
+    const TabCell t = sc_cell(E, c);
+    sc_clear(E, c);
     PendingRec pr;
-    if (!tab_cell_finish(t, &pr)) continue;
+    if (!tab_cell_finish(t, &pr)) return;
     const uint32_t ck = base + c;
     const uint32_t aid = sc_aid(E, ck);
     pr.gid = 0; pr.interval = E.interval; pr.aid = aid;
@@ -586,8 +624,15 @@ __device__ uint32_t sc_window(const ScEnv& E, const u64* in, uint32_t n, uint32_
     pr.cellkey = ck; pr.lidbase = 0;
     store_record(R, E.K, k < room ? at0 + k : jump + (k - room), E.slot, E.instance, pr, false, kb + k);
     ++k;
+  };
+  const uint32_t total = ctl->rec_sum_total;
+  if (scan) {
+    for (uint32_t c = c0; c < c0 + per; ++c)
+      if (sc_touched(E, c)) emit(c);
+  } else {
+    for (uint32_t m = word; m; m &= m - 1u) emit(tl * 32u + (uint32_t)__ffs(m) - 1u);
+    if (tl < SC_WORDS) E.bits[tl] = 0u;
   }
-  if (tl < SC_WORDS) E.bits[tl] = 0u;
   __syncthreads();   // the table is clean again
   return kb + total;
 }

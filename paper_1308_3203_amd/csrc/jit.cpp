@@ -41,10 +41,15 @@ std::string operand(bool imm, uint32_t w) {
 // does a kept step; the statements of a loop body also follow the body's
 // own end.  Arrays whose accesses never take the step (read-only or owned)
 // cannot conflict; with number_global, statements on an array logged to the
-// global log keep the step, which numbers its entries.  A kept step on a logged local array
-// synchronises only in the intervals whose local accesses are logged (in
-// the others the runtime skips it, the array being race-free there), so
-// unless every interval is logged it does not count as a synchronisation.
+// global log keep the step, which numbers its entries.  A kept step on a
+// logged local array synchronises only in the intervals whose local
+// accesses are logged (in the others the runtime skips it, every local
+// array being race-free there).  Unless every interval is logged, such a
+// step therefore settles only what a skipped step cannot break: the local
+// arrays (race-free whenever it is skipped) and, with number_global, the
+// arrays logged globally (each of their statements keeps its own step).
+// A global array logged in LDS (one group), or logged globally on the
+// interpreter's elided path, stays pending across it.
 }  // namespace
 
 std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitShape& shape, bool number_global) {
@@ -76,7 +81,14 @@ std::vector<uint8_t> group_steps(const std::vector<uint32_t>& code, const JitSha
           keep[i] = 1;
           changed = true;
         }
-        if (keep[i] && !may_be_quiet(wc)) std::fill(S.begin(), S.end(), 0);
+        if (keep[i]) {
+          if (!may_be_quiet(wc)) {
+            std::fill(S.begin(), S.end(), 0);
+          } else {
+            for (uint32_t a = 0; a < na; ++a)
+              if (field(a, 0) == AK_LOCAL || (number_global && field(a, 2) == LOG_GLOBAL)) S[a] = 0;
+          }
+        }
         S[wc] |= bit;
       } else if (op == OP_IF || op == OP_BARRIER) {
         std::fill(S.begin(), S.end(), 0);

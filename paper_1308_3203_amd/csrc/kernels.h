@@ -114,7 +114,7 @@ struct ScParams {
   const rc_record_out* rec;
   uint32_t bs, bc;
 };
-constexpr uint32_t SC_THREADS = 256;
+constexpr uint32_t SC_THREADS = 512;
 constexpr uint32_t SC_CTL_BYTES = (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15);
 constexpr uint32_t SC_MAX_BLOCKS = 1024;
 hipError_t launch_sc_group(const ScParams& S, uint32_t blocks, hipStream_t st);

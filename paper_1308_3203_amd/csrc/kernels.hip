@@ -165,16 +165,20 @@ __global__ __launch_bounds__(SC_THREADS) void sc_group_kernel(ScParams S) {
   const ChunkDesc C = const_load<ChunkDesc>(S.chunks, const_load<uint32_t>(S.chunk_index, 0));
   const rc_record_out R = const_load<rc_record_out>(S.rec, 0);
   if (tl == 0) ctl->rc_cur = ctl->rc_end = 0ull;   // no record slots yet
-  // the work area: the window table (cleared once, kept clean), the
-  // touched-cell bitmap, the bucket counters
-  TabCell* tab = reinterpret_cast<TabCell*>(rc_smem + SC_CTL_BYTES);
-  uint32_t* bits = reinterpret_cast<uint32_t*>(rc_smem + SC_CTL_BYTES + SC_WIN * sizeof(TabCell));
+  // the work area: the window table, field by field (cleared once, kept
+  // clean), the touched-cell bitmap, the bucket counters
+  u64* wmin = reinterpret_cast<u64*>(rc_smem + SC_CTL_BYTES);
+  uint32_t* r1 = reinterpret_cast<uint32_t*>(wmin + SC_WIN);
+  uint32_t* r2 = r1 + SC_WIN;
+  uint32_t* w2 = r2 + SC_WIN;
+  uint32_t* q = w2 + SC_WIN;
+  uint32_t* bits = q + SC_WIN;
   uint32_t* cnt = bits + SC_WORDS;
-  {
-    const TabCell empty_cell = empty_tab_cell();
-    for (uint32_t i = tl; i < SC_WIN; i += SC_THREADS) tab[i] = empty_cell;
-    for (uint32_t i = tl; i < SC_WORDS; i += SC_THREADS) bits[i] = 0u;
+  for (uint32_t i = tl; i < SC_WIN; i += SC_THREADS) {
+    wmin[i] = ~0ull;
+    r1[i] = r2[i] = w2[i] = q[i] = NONE32;
   }
+  for (uint32_t i = tl; i < SC_WORDS; i += SC_THREADS) bits[i] = 0u;
   __syncthreads();
   for (;;) {
     if (tl == 0) ctl->item = atomicAdd(S.queue, 1u);
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(SC_THREADS) void sc_group_kernel(ScParams S) {
     E.ends = S.ends + (u64)blockIdx.x * SC_NB_MAX;
     E.cells = D.n_cells;
     E.nthr = SC_THREADS;
-    E.tab = tab;
+    E.wmin = wmin; E.r1 = r1; E.r2 = r2; E.w2 = w2; E.q = q;
     E.bits = bits;
     E.cnt = cnt;
     E.slot = rel;
@@ -231,8 +235,9 @@ __global__ __launch_bounds__(SC_THREADS) void sc_group_kernel(ScParams S) {
   }
 }
 
-// LDS of a group check block: control block, window table, bitmap, counters
-constexpr size_t SC_LDS_BYTES = SC_CTL_BYTES + SC_WIN * sizeof(TabCell) + SC_WORDS * 4 + SC_NB_MAX * 4;
+// LDS of a group check block: control block, window table (8 + 4 x 4 bytes
+// a cell), bitmap, counters
+constexpr size_t SC_LDS_BYTES = SC_CTL_BYTES + SC_WIN * 24u + SC_WORDS * 4 + SC_NB_MAX * 4;
 
 hipError_t launch_sc_group(const ScParams& S, uint32_t blocks, hipStream_t st) {
   hipLaunchKernelGGL(sc_group_kernel, dim3(blocks), dim3(SC_THREADS), SC_LDS_BYTES, st, S);

@@ -105,12 +105,18 @@ class TriageNet:
             self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
         return self._ws
 
-    def train(self, feat, labels, epochs: int = 5, batch: int = 4096, lr: float = 1e-3, shuffle_seed: int = 7):
+    def train(self, feat, labels, epochs: int = 5, batch: int = 4096, lr: float = 1e-3, shuffle_seed: int = 7,
+              copies=None):
         """Adam on minibatches of a seeded permutation each epoch; returns the
-        loss of each epoch's last minibatch (read back once per epoch)."""
+        loss of each epoch's last minibatch (read back once per epoch).
+        copies (int array, one per row, or None): how many times each row
+        appears in an epoch; a row seen k times weighs k times in the loss."""
         torch = _torch()
         n = feat.shape[0]
-        batch = min(batch, n)
+        rows_all = np.arange(n, dtype=np.int32) if copies is None else np.repeat(
+            np.arange(n, dtype=np.int32), np.asarray(copies, dtype=np.int64))
+        total = rows_all.size
+        batch = min(batch, total)
         rng = np.random.default_rng(shuffle_seed)
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
         ws = self._workspace(batch)
@@ -118,8 +124,8 @@ class TriageNet:
         history = []
         for _ in range(epochs):
             # the kernels read each minibatch's rows through the index list
-            perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
-            for a in range(0, n - batch + 1, batch):      # full batches only
+            perm = torch.from_numpy(rows_all[rng.permutation(total)]).cuda()
+            for a in range(0, total - batch + 1, batch):      # full batches only
                 self.step += 1
                 self.ctx.mlp_train_step_async(self.params, self.m, self.v, self.step, flat, labels, lr, loss, ws,
                                               rows=perm[a:a + batch])
@@ -212,42 +218,75 @@ def sweep(ctx: B.Context, inst: Instances, order=None, chunk: int = 2000, ws_byt
 
 
 @dataclass
+class OrderResult:
+    """What one visiting order finds within the budget."""
+    recall_instances: float      # racy instances found within budget / all racy instances
+    recall_records: float        # RACE records found within budget / all RACE records
+    races_per_gpu_s: float       # RACE records found per GPU-second of the budget
+    curve: list                  # (fraction of the plain sweep's GPU time, instance recall, record recall)
+
+
+@dataclass
 class TriageReport:
     plain_ms: float
     budget_frac: float
     inference_ms: float
-    recall_instances: float      # racy instances found within budget / all racy instances
-    recall_records: float        # RACE records found within budget / all RACE records
+    recall_instances: float      # learned order (inference counted)
+    recall_records: float
     plain_recall_instances: float
     races_per_gpu_s_learned: float
     races_per_gpu_s_plain: float
     n_racy: int
     n_race_records: int
+    orders: dict = field(default_factory=dict)   # name -> OrderResult: learned, plain and the baselines
 
 
-def evaluate(plain: SweepResult, learned: SweepResult, inference_ms: float, budget_frac: float = 0.25
-             ) -> TriageReport:
-    """Recall of the learned order within budget_frac of the plain sweep's GPU
-    time (inference counted), against everything the plain sweep found."""
-    T = float(plain.chunk_ms.sum())
-    budget = budget_frac * T
-    n_racy = int(plain.racy.sum())
-    n_cells = int(plain.race_cells.sum())
-    t, c_racy, c_cells = learned.cumulative(inference_ms)
+def order_result(res: SweepResult, start_ms: float, plain_ms: float, budget_frac: float, n_racy: int,
+                 n_cells: int, points: int = 24) -> OrderResult:
+    t, c_racy, c_cells = res.cumulative(start_ms)
+    budget = budget_frac * plain_ms
     k = np.searchsorted(t, budget, side="right")
     got_i = int(c_racy[k - 1]) if k > 0 else 0
     got_c = int(c_cells[k - 1]) if k > 0 else 0
-    tp, p_racy, p_cells = plain.cumulative(0.0)
-    kp = np.searchsorted(tp, budget, side="right")
-    pgot_i = int(p_racy[kp - 1]) if kp > 0 else 0
-    pgot_c = int(p_cells[kp - 1]) if kp > 0 else 0
+    curve = []
+    for f in np.linspace(0.0, 1.0, points + 1)[1:]:
+        j = np.searchsorted(t, f * plain_ms, side="right")
+        curve.append((round(float(f), 4), round((int(c_racy[j - 1]) if j > 0 else 0) / max(1, n_racy), 4),
+                      round((int(c_cells[j - 1]) if j > 0 else 0) / max(1, n_cells), 4)))
+    return OrderResult(got_i / max(1, n_racy), got_c / max(1, n_cells),
+                       got_c / (budget * 1e-3) if budget > 0 else 0.0, curve)
+
+
+def evaluate(plain: SweepResult, learned: SweepResult, inference_ms: float, budget_frac: float = 0.25,
+             baselines: dict | None = None) -> TriageReport:
+    """Recall of the learned order within budget_frac of the plain sweep's GPU
+    time (inference counted), against everything the plain sweep found; the
+    same for the plain order and for baseline orders (name -> (sweep, GPU
+    time spent before it starts))."""
+    T = float(plain.chunk_ms.sum())
+    n_racy = int(plain.racy.sum())
+    n_cells = int(plain.race_cells.sum())
+    orders = {"learned": order_result(learned, inference_ms, T, budget_frac, n_racy, n_cells),
+              "plain": order_result(plain, 0.0, T, budget_frac, n_racy, n_cells)}
+    for name, (res, start) in (baselines or {}).items():
+        orders[name] = order_result(res, start, T, budget_frac, n_racy, n_cells)
+    L, P = orders["learned"], orders["plain"]
     return TriageReport(
         plain_ms=T, budget_frac=budget_frac, inference_ms=inference_ms,
-        recall_instances=got_i / max(1, n_racy), recall_records=got_c / max(1, n_cells),
-        plain_recall_instances=pgot_i / max(1, n_racy),
-        races_per_gpu_s_learned=got_c / (budget * 1e-3) if budget > 0 else 0.0,
-        races_per_gpu_s_plain=pgot_c / (budget * 1e-3) if budget > 0 else 0.0,
-        n_racy=n_racy, n_race_records=n_cells)
+        recall_instances=L.recall_instances, recall_records=L.recall_records,
+        plain_recall_instances=P.recall_instances,
+        races_per_gpu_s_learned=L.races_per_gpu_s, races_per_gpu_s_plain=P.races_per_gpu_s,
+        n_racy=n_racy, n_race_records=n_cells, orders=orders)
+
+
+def static_heuristic(feat_host: np.ndarray) -> np.ndarray:
+    """The baseline without a network: the number of candidate conflicting
+    access pairs the affine index analysis finds (features 16..23: stores
+    every work-item aims at one cell, non-affine stores, overlapping affine
+    pairs, pairs across loops holding a barrier), higher first, ties by
+    index."""
+    score = feat_host[:, 16:24].astype(np.float64).sum(axis=1)
+    return np.lexsort((np.arange(score.size), -score))
 
 
 def timed(fn):
@@ -276,9 +315,17 @@ class TriageRun:
     train_racy_frac: float
 
 
+def record_copies(race_cells: np.ndarray) -> np.ndarray:
+    """Rows per training instance: 1, plus floor(log2(1 + RACE records)) for a
+    racy instance, so that instances with many records weigh more and the
+    order finds records, not only racy instances, early."""
+    return 1 + np.floor(np.log2(1.0 + race_cells.astype(np.float64))).astype(np.int64)
+
+
 def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_seeds: int, epochs: int = 5,
         batch: int = 4096, lr: float = 1e-3, chunk: int = 2000, label_chunk: int = 20000, init_seed: int = 7,
-        ws_bytes: int = 16 << 30, budget_frac: float = 0.25, progress=None) -> TriageRun:
+        ws_bytes: int = 16 << 30, budget_frac: float = 0.25, progress=None, weight_records: bool = False,
+        baselines: bool = True) -> TriageRun:
     torch = _torch()
     say = progress or (lambda msg: None)
     train = Instances.grid(load_programs(ctx, train_workloads), train_seeds)
@@ -293,9 +340,11 @@ def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_
     labels = torch.from_numpy(lab.racy.astype(np.float32)).cuda()
     net = TriageNet(ctx, seed=init_seed)
 
+    copies = record_copies(lab.race_cells) if weight_records else None
+
     def fit():
         f = features(ctx, train)
-        return net.train(f, labels, epochs=epochs, batch=batch, lr=lr)
+        return net.train(f, labels, epochs=epochs, batch=batch, lr=lr, copies=copies)
     losses, train_ms = timed(fit)
     say(f"trained: losses {losses}")
     # warm the held-out programs' tables, then the plain sweep
@@ -310,6 +359,17 @@ def run(ctx: B.Context, train_workloads, train_seeds: int, eval_workloads, eval_
     learned = sweep(ctx, held, order=order, chunk=chunk, ws=ws)
     if not np.array_equal(learned.racy, plain.racy) or not np.array_equal(learned.race_cells, plain.race_cells):
         raise RuntimeError("the two sweeps disagree on an instance: the exact check must not depend on the order")
-    rep = evaluate(plain, learned, infer_ms, budget_frac)
+    base = {}
+    if baselines:
+        # a seeded random order, and the static heuristic (its features are
+        # computed on the GPU like the network's; the ordering is counted as
+        # the same feature time)
+        rnd = np.random.default_rng(12345).permutation(len(held)).astype(np.int64)
+        base["random"] = (sweep(ctx, held, order=rnd, chunk=chunk, ws=ws), 0.0)
+        fh, feat_ms = timed(lambda: features(ctx, held))
+        heur = static_heuristic(fh.cpu().numpy())
+        base["static_heuristic"] = (sweep(ctx, held, order=heur, chunk=chunk, ws=ws), feat_ms)
+        say("baseline sweeps done")
+    rep = evaluate(plain, learned, infer_ms, budget_frac, base)
     return TriageRun(rep, losses, float(lab.chunk_ms.sum()), train_ms, len(train), len(held),
                      float(lab.racy.mean()) if len(train) else 0.0)

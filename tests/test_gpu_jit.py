@@ -173,6 +173,22 @@ def test_elided_step_after_quiet_local_access(W):
             assert np.array_equal(fin, orc.final), (W, seed, name)
 
 
+@pytest.mark.parametrize("G,W", [(2, 128), (4, 256)])
+@pytest.mark.parametrize("jit", [True, False])
+def test_elided_step_after_quiet_local_access_groups(G, W, jit):
+    """The same program with several groups: the shared global array is
+    logged globally.  The per-program kernel keeps every step on it; the
+    interpreter's elided steps do not, so the skipped local step must not
+    settle it there either.  Records and summaries equal the oracle's."""
+    src = quiet_step_src(W)
+    owned, nofault = B.owned_arrays(src, G, W, with_faults=True)
+    assert nofault and owned == [False, False, False]
+    assert B.log_intervals(src, G, W) == (0b10, False)
+    arrays = {"A": ("seeded", 0, 1000), "Bo": ("seeded", 0, 8)}
+    g = U.gpu_run(src, G, W, arrays, None, 1, 6, jit=jit)
+    U.assert_same(g, U.oracle_run(src, G, W, arrays, None, 1, 6), f"{src} G={G} jit={jit}")
+
+
 @pytest.mark.parametrize("w", WL.c2_templates(), ids=lambda w: w.name)
 def test_proofs_off_same_reports(w):
     """With the static proofs turned off every written array is logged and

@@ -369,3 +369,12 @@ def test_learned_order_finds_races_sooner_than_plain_order():
     assert rep.recall_records >= 0.95
     assert rep.recall_instances >= rep.plain_recall_instances + 0.3
     assert rep.races_per_gpu_s_learned >= 10 * rep.races_per_gpu_s_plain
+    # and more than the orders without the network: a random permutation
+    # and the static count of candidate conflicting pairs
+    assert set(rep.orders) == {"learned", "plain", "random", "static_heuristic"}
+    for base in ("random", "static_heuristic"):
+        assert rep.recall_records >= rep.orders[base].recall_records, base
+    # every curve ends with the plain sweep's GPU time spent and is monotone
+    for o in rep.orders.values():
+        inst = [c[1] for c in o.curve]
+        assert inst == sorted(inst)

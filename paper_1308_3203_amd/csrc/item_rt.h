@@ -1389,22 +1389,22 @@ struct Item {
     if (lane == 0 && acc) atomicAdd(&P.inst_acc[slot], acc);
     // the call's log statistics: logged accesses, those in the global log,
     // intervals moved to the global log, intervals closed
+    // (into the block's LDS totals: one global atomic per block and
+    // statistic when the block leaves, not one per item)
     if (P.stats) {
       u64 lg = n_logged;
       for (int off = 32; off > 0; off >>= 1) lg += __shfl_down(lg, off);
-      if (lane == 0 && lg) atomicAdd(&P.stats[0], lg);
+      if (lane == 0 && lg) atomicAdd(&ctl->stat[0], lg);
       if (tl == 0) {
         // entries for the global pass or (one-group programs) the group
         // check, trailers not counted
         const u64 left = P.sc ? n_glog : (log_used < P.wg_log_cap ? log_used : P.wg_log_cap);
-        if (left) {
-          atomicAdd(&P.stats[1], left);
-          atomicAdd(&P.stats[6], left);
-        }
-        if (n_spilled) atomicAdd(&P.stats[2], (u64)n_spilled);
-        atomicAdd(&P.stats[3], (u64)(interval + 1u));
-        atomicAdd(&P.stats[4], (u64)n_insn);
-        atomicAdd(&P.stats[5], (u64)n_insn * (nthr >> 6));
+        ctl->stat[1] += left;
+        ctl->stat[6] += left;
+        ctl->stat[2] += n_spilled;
+        ctl->stat[3] += interval + 1u;
+        ctl->stat[4] += n_insn;
+        ctl->stat[5] += (u64)n_insn * (nthr >> 6);
       }
     }
     __syncthreads();
@@ -1426,13 +1426,19 @@ __device__ __forceinline__ void run_items(const PassParams& PP, Body body) {
   const uint32_t* item0 = PP.chunks[ci].item0;
   const uint32_t i0 = const_load<uint32_t>(item0, PP.wclass), i1 = const_load<uint32_t>(item0, PP.wclass + 1);
   if (i0 == i1) return;
-  if (threadIdx.x == 0) ctl->rc_cur = ctl->rc_end = 0ull;   // no record slots yet
+  if (threadIdx.x == 0) {
+    ctl->rc_cur = ctl->rc_end = 0ull;   // no record slots yet
+    for (int k = 0; k < 7; ++k) ctl->stat[k] = 0ull;
+  }
   for (;;) {
     if (threadIdx.x == 0) ctl->item = i0 + atomicAdd(&PP.queue[PP.wclass], 1u);
     __syncthreads();
     const uint32_t item = uni(ctl->item);
     __syncthreads();
     if (item >= i1) {
+      // the block's log statistics
+      if (PP.stats && threadIdx.x < 7u && ctl->stat[threadIdx.x])
+        atomicAdd(&PP.stats[threadIdx.x], ctl->stat[threadIdx.x]);
       // the block's unused record slots
       const rc_record_out R = const_load<rc_record_out>(PP.rec, 0);
       const u64 a = ctl->rc_cur, b = ctl->rc_end;

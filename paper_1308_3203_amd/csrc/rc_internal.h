@@ -244,6 +244,9 @@ struct Ctl {
   uint32_t lds_cnt[2];                  // LDS log entries of the even / odd intervals
                                         // (elided group steps)
   unsigned long long gl_cnt;            // global log entries of the group (elided group steps)
+  // the call's log statistics (PassParams::stats) summed over the block's
+  // items, added to the call's totals once, when the block leaves
+  unsigned long long stat[7];
 };
 // bit of a load / store instruction's array word: the interpreter skips the
 // statement's group step (programs interpreted with elided steps only)

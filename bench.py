@@ -561,6 +561,8 @@ def profile_main(args):
     lines = []
     if args.trace_dir:
         t = summarize_trace(args.trace_dir, kernel, last)
+        if not t["selected"]:
+            raise SystemExit(f"no dispatch of a kernel named like {kernel!r} under {args.trace_dir}")
         lines.append(f"## Kernel trace: `{kernel}`\n")
         lines.append(f"{t['selected']} of {t['dispatches']} dispatches (the last ones: the timed steps): "
                      f"average {t['avg_ms']:.4f} ms, min {t['min_ms']:.4f}, max {t['max_ms']:.4f}\n")
@@ -583,8 +585,17 @@ def profile_main(args):
             lines.append(f"| VALUUtilization (% active lanes per VALU instruction) | "
                          f"{100 * c['SQ_THREAD_CYCLES_VALU'] / max(1.0, 64 * c['SQ_ACTIVE_INST_VALU']):.2f} |")
         if "SQ_ACTIVE_INST_VALU" in c and "GRBM_GUI_ACTIVE" in c:
-            lines.append(f"| VALUBusy (% of GPU time, 256 CUs) | "
-                         f"{100 * c['SQ_ACTIVE_INST_VALU'] / 256 / max(1.0, c['GRBM_GUI_ACTIVE']):.2f} |")
+            # GRBM_GUI_ACTIVE comes summed over the 8 XCDs: the kernel's
+            # cycles are an eighth of it; VALU busy = VALU issue cycles per
+            # SIMD (4 per CU, 256 CUs) over those cycles
+            cycles = c["GRBM_GUI_ACTIVE"] / 8.0
+            lines.append(f"| GPU cycles per dispatch (GRBM_GUI_ACTIVE / 8 XCDs) | {cycles:.6g} |")
+            lines.append(f"| VALUBusy (% of SIMD cycles issuing VALU) | "
+                         f"{100 * c['SQ_ACTIVE_INST_VALU'] * 4 / 1024 / max(1.0, cycles):.2f} |")
+        if "SQ_INSTS_SALU" in c and "SQ_WAVES" in c:
+            lines.append(f"| SALU instructions per wave | {c['SQ_INSTS_SALU'] / max(1.0, c['SQ_WAVES']):.6g} |")
+        if "SQ_INSTS_VALU" in c and "SQ_WAVES" in c:
+            lines.append(f"| VALU instructions per wave | {c['SQ_INSTS_VALU'] / max(1.0, c['SQ_WAVES']):.6g} |")
         lines.append("")
     if args.fetch_dir and args.write_dir and args.copy_fetch_dir and args.copy_write_dir:
         cf = summarize_counters(args.copy_fetch_dir, "copyBuffer", 0)

@@ -25,8 +25,6 @@ SAMPLES = [0, 1, 2499, 2500, 3333, 3334, 5000, 6667, 6668, 9998, 9999]
 @pytest.mark.parametrize("jit", [True, False])
 @pytest.mark.parametrize("name", [w.name for w in WL.c2_templates()])
 def test_c2_full_size_sampled(name, jit):
-    if not jit and name not in ("transpose_race", "prefix_sum"):
-        pytest.skip("the interpreter is sampled on two templates")
     w = [x for x in WL.c2_templates() if x.name == name][0]
     p = B.Program(U.ctx(), w.src)
     p.set_ndrange(w.G, w.W)

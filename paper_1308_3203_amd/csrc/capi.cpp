@@ -561,8 +561,11 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     any_sc = any_sc || p->sc;
   }
   if (bc > 32 || bg > 26 || bk > 32) { *why = "sort key fields too wide"; return false; }
-  // try 1, 2, 4, ... chunks
-  for (u64 k = 1;; k *= 2) {
+  // The fewest chunks that fit: the limits for k chunks are first laid out
+  // with a one-chunk table (a lower bound of the total, no partition) and
+  // partitioned only when that fits; k grows by an eighth, so the chunks
+  // come out within about an eighth of the fewest the budget allows
+  for (u64 k = 1;; k = std::max<u64>(k + 1, k + k / 8)) {
     Layout L;
     const u64 per = (N + k - 1) / k;
     L.max_slots = (uint32_t)std::min<u64>(N, per + 1);
@@ -597,24 +600,28 @@ bool plan(Call& C, size_t ws_bytes, std::string* why) {
     L.scope_n = L.rank ? (u64)L.max_slots << bs : 0;
     L.lds_only = lds_only;
     L.sc_blocks = any_sc ? std::min<uint32_t>(L.max_slots, SC_MAX_BLOCKS) : 0u;
-    Layout lim = L;
-    partition(C, lim);
-    lay_out(&L, C.progs.size(), N, C.chunks.size(), C.items.size() / 2);
-    if (L.total <= ws_bytes) {
-      // class grid sizes: the most items one class has in any chunk
-      for (const ChunkDesc& ch : C.chunks)
-        for (uint32_t c = 0; c < N_WCLASS; ++c)
-          L.max_items_class[c] = std::max(L.max_items_class[c], ch.item0[c + 1] - ch.item0[c]);
-      C.L = L;
-      return true;
+    Layout bound = L;
+    lay_out(&bound, C.progs.size(), N, 1, items_total);
+    if (bound.total <= ws_bytes) {
+      Layout lim = L;
+      partition(C, lim);
+      lay_out(&L, C.progs.size(), N, C.chunks.size(), C.items.size() / 2);
+      if (L.total <= ws_bytes) {
+        // class grid sizes: the most items one class has in any chunk
+        for (const ChunkDesc& ch : C.chunks)
+          for (uint32_t c = 0; c < N_WCLASS; ++c)
+            L.max_items_class[c] = std::max(L.max_items_class[c], ch.item0[c + 1] - ch.item0[c]);
+        C.L = L;
+        return true;
+      }
+      C.items.clear();
     }
     if (k >= 2 * (u64)N + 2) {
       char b[200];
-      snprintf(b, sizeof b, "workspace of %zu bytes is too small: one instance needs %zu", ws_bytes, L.total);
+      snprintf(b, sizeof b, "workspace of %zu bytes is too small: one instance needs %zu", ws_bytes, bound.total);
       *why = b;
       return false;
     }
-    C.items.clear();
   }
 }
 

@@ -732,7 +732,16 @@ struct Item {
     }
     if (tl < P.n_scalars) {
       const ScalarDesc S = const_load<ScalarDesc>(P.scalars, tl);
-      ctl->scal[tl] = S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
+      ctl->uval[SEL_SCALAR0 - SEL_LID + tl] =
+          S.bind == BIND_SEEDED ? seeded_cell(seed, 0x10000u + tl, 0, S.lo, S.hi) : S.value;
+    }
+    if (tl == 0) {
+      ctl->uval[SEL_LID - SEL_LID] = 0;
+      ctl->uval[SEL_TID - SEL_LID] = (int32_t)(gid * P.W);
+      ctl->uval[SEL_GID - SEL_LID] = (int32_t)gid;
+      ctl->uval[SEL_WGSIZE - SEL_LID] = (int32_t)P.W;
+      ctl->uval[SEL_NGROUPS - SEL_LID] = (int32_t)P.G;
+      ctl->uval[SEL_NTHREADS - SEL_LID] = (int32_t)(P.G * P.W);
     }
     __syncthreads();
     key_slot = (u64)slot << (P.bc + P.bg + P.bk);
@@ -769,8 +778,14 @@ struct Item {
       case SEL_WGSIZE: return (int32_t)P.W;
       case SEL_NGROUPS: return (int32_t)P.G;
       case SEL_NTHREADS: return (int32_t)(P.G * P.W);
-      default: return ctl->scal[w - SEL_SCALAR0];
+      default: return ctl->uval[w - SEL_LID];
     }
+  }
+  // the same for a selector known only at run time (the interpreter): one
+  // LDS read and no branch
+  __device__ __forceinline__ int32_t special_dyn(uint32_t w) const {
+    const uint32_t k = w - SEL_LID;
+    return (int32_t)((uint32_t)ctl->uval[k] + (k < 2u ? tl : 0u));
   }
 
   // Group-wide OR of two per-lane predicates (bits 0, 1) and of "some

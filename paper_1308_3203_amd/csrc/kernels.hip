@@ -57,7 +57,7 @@ __device__ __forceinline__ void interp_item(Item& it) {
   auto fetch = [&](bool imm, uint32_t w) -> int32_t {
     if (imm) return (int32_t)w;
     if (w < MAX_REGS) return rd(w);
-    return it.special(w);
+    return it.special_dyn(w);
   };
 
   for (;;) {
@@ -69,20 +69,34 @@ __device__ __forceinline__ void interp_item(Item& it) {
     it.stmt(spc);
     const bool active = (mbits >> depth) & 1u;
 
-    if (op == OP_BIN) {
-      int32_t x = fetch(fa, wa), y = fetch(fb, wb);
-      bool dz = false;
-      int32_t r = alu_bin(sub, x, y, dz);
-      if (active) {
-        wr(dst, r);
-        if (dz) it.raise(spc, F_DIV);
+    if (op == OP_BIN || op == OP_UN) {
+      // a run of arithmetic instructions (an expression's nodes) in a loop
+      // of its own: the mask does not change inside it, and the state the
+      // rest of the interpreter carries stays out of it
+      uint32_t hh = h, xa = wa, xb = wb, hop = op, hsub = sub, hdst = dst, hspc = spc;
+      bool ffa = fa, ffb = fb;
+      for (;;) {
+        const int32_t x = fetch(ffa, xa);
+        int32_t r;
+        if (hop == OP_BIN) {
+          const int32_t y = fetch(ffb, xb);
+          bool dz = false;
+          r = alu_bin(hsub, x, y, dz);
+          if (active && dz) it.raise(hspc, F_DIV);
+        } else {
+          r = hsub == U_MOV ? x : hsub == U_NEG ? (int32_t)(0u - (uint32_t)x) : hsub == U_BNOT ? ~x : (int32_t)(x == 0);
+        }
+        if (active) wr(hdst, r);
+        ++pc;
+        const Insn nx = const_load<Insn>(P.code, pc);
+        hh = nx.h;
+        hop = hh & 63u;
+        if (hop != OP_BIN && hop != OP_UN) break;
+        xa = nx.a; xb = nx.b;
+        hsub = (hh >> 8) & 63u; hdst = (hh >> 14) & 63u; hspc = hh >> 20;
+        ffa = (hh >> 6) & 1u; ffb = (hh >> 7) & 1u;
+        it.stmt(hspc);
       }
-      ++pc;
-    } else if (op == OP_UN) {
-      int32_t x = fetch(fa, wa);
-      int32_t r = sub == U_MOV ? x : sub == U_NEG ? (int32_t)(0u - (uint32_t)x) : sub == U_BNOT ? ~x : (int32_t)(x == 0);
-      if (active) wr(dst, r);
-      ++pc;
     } else if (op == OP_LOAD || op == OP_STORE) {
       const int32_t idx = fetch(fa, wa);
       const int32_t val = op == OP_STORE ? fetch(fb, wb) : 0;

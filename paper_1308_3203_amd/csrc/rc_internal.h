@@ -237,7 +237,10 @@ struct Ctl {
   uint32_t red[2][MAX_WAVES];           // per-wave reduction words, double-buffered
   uint32_t rec_sum[MAX_WAVES];          // per-wave record counts of a reservation
   uint32_t rec_sum_total, pad2;         // and their sum
-  int32_t scal[MAX_SCALARS];
+  // the interpreter's special operands by selector (SEL_LID ...): lid and
+  // tid add the work-item's lid to words 0 and 1; the scalar parameters
+  // follow at SEL_SCALAR0
+  int32_t uval[SEL_SCALAR0 - SEL_LID + MAX_SCALARS];
   uint32_t loopctr[MAX_WAVES][MAX_NEST];
   uint32_t item;                        // work item taken by the group
   uint32_t pad;

@@ -138,7 +138,10 @@ rc_status rc_ctx_profile_read(rc_ctx* ctx, rc_profile* out);
  * syntax is given in the repository's design notes).  `len` bytes of `src`
  * are read; the text need not be NUL-terminated.  RC_E_PARSE carries
  * "line:col: message"; RC_E_LIMIT reports an exceeded limit.  The program
- * starts with no launch shape and no bindings. */
+ * starts with no launch shape and no bindings.  The one device allocation
+ * outside the caller's workspace: the program's bytecode and descriptor
+ * tables (a few KB, hipMalloc here, freed by rc_prog_free), so that the
+ * checks themselves allocate nothing; RC_E_HIP if it fails. */
 rc_status rc_prog_load(rc_ctx* ctx, const char* src, size_t len, rc_prog** out);
 rc_status rc_prog_free(rc_prog* prog);
 rc_status rc_prog_get_info(const rc_prog* prog, rc_prog_info* out);
@@ -325,9 +328,11 @@ rc_status rc_check_static(rc_prog* prog, uint64_t seed0, uint32_t n_seeds,
  * Check a list of instances of possibly different programs (all loaded on
  * `ctx`, shaped and bound): instance i runs programs[i] with seed seeds[i].
  * Records and summaries follow the list order (record.instance = i); other
- * arguments and rules as rc_check.  The instances run in chunks that fit the
- * workspace; inside a chunk, persistent workgroups take (instance, group)
- * work items from a queue ordered longest first.
+ * arguments and rules as rc_check.  The instances run in chunks of
+ * consecutive list entries that fit the workspace, in list order: a caller
+ * that wants an order (the triage ranking, say) permutes the list.  Inside a
+ * chunk, persistent workgroups take (instance, group) work items from a
+ * queue ordered longest first.
  */
 rc_status rc_batch_check(rc_ctx* ctx, rc_prog* const* programs, const uint64_t* seeds, uint32_t n,
                          void* d_ws, size_t ws_bytes,

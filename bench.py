@@ -381,6 +381,11 @@ def run_secondary(ctx, name: str, args, proofs_off: bool = False) -> dict:
     out["execution"] = "per-program kernels"
     out["instances_per_step"] = sum(n for _, n in works)
     out["steps"] = m["steps"]
+    # measured HBM bytes per launch (counters taken with the proofs on)
+    t = None if proofs_off else measured_traffic(out["dominant_kernel"], name)
+    out["traffic"] = t
+    out["traffic_frac"] = (round(t / (out["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+                           if t and out.get("avg_launch_ms") else None)
     say(f"secondary {name}: {out['value']:.3e} accesses/s, {out['ms_per_step']:.2f} ms per step")
     return out
 
@@ -467,6 +472,11 @@ def main():
                 "avg_launch_ms": round(d["avg_launch_ms"], 4),
                 "phases_ms": m["phases_ms"], "path_frac": round(m["path_frac"], 5),
                 "bytes_per_access": BYTES_PER_ACCESS}
+    # the kernel's measured HBM bytes per launch (counters, when they were
+    # taken on these sources) over its launch time, against the same peak
+    t = roofline["traffic"]
+    roofline["traffic_frac"] = (round(t / (d["avg_launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+                                if t and d["avg_launch_ms"] > 0 else None)
     cpu = None
     if args.cpu_seconds > 0:
         threads = args.cpu_threads or host_cores()

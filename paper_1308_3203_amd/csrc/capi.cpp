@@ -344,6 +344,7 @@ struct Layout {
   // (sc_group_kernel): blocks of the check and their bucket-bound words
   uint32_t sc_blocks = 0;
   size_t sc_ends = 0;
+  size_t sc_order = 0;   // per instance of the call: the group check's queue order (chunk-relative slots)
   u64 scope_n = 0;
   size_t scope_cnt = 0, scope_tmp = 0;
   // per-(slot, cell) owner words of the global log (cc_stride cells per
@@ -370,6 +371,7 @@ void lay_out(Layout* L, size_t n_progs, size_t n_inst, size_t n_chunks, size_t n
   L->slots = take(n_inst * sizeof(SlotDesc));
   L->chunks = take(n_chunks * sizeof(ChunkDesc));
   L->items = take(n_items * 8);
+  L->sc_order = take(L->sc_blocks ? n_inst * 4 : 0);
   L->recout = take(sizeof(rc_record_out));
   L->counters = take(CNT_WORDS * 8);
   L->queue = take((N_WCLASS + 1) * 4);   // the classes' queues, then the group check's
@@ -412,6 +414,9 @@ struct Call {
   std::vector<SlotDesc> slots;
   std::vector<ChunkDesc> chunks;
   std::vector<uint32_t> items;          // pairs (instance, gid)
+  // the group check's queue, per chunk: its slots (relative to the chunk)
+  // in descending static log bound, so the largest spills start first
+  std::vector<uint32_t> sc_order;
   Layout L;
   uint32_t classes_used = 0;            // bit c: width class c occurs
   size_t class_lds[N_WCLASS] = {0, 0, 0, 0, 0};
@@ -425,7 +430,10 @@ struct Call {
 // Split the instances into chunks whose resources stay under the limits.
 void partition(Call& C, const Layout& lim) {
   C.chunks.clear();
+  C.sc_order.clear();
   C.slots.assign(C.inst_prog.size(), SlotDesc());
+  bool any_sc = false;
+  for (const rc_prog* p : C.progs) any_sc = any_sc || p->sc;
   std::vector<std::vector<uint32_t>> class_items(N_WCLASS);
   u64 log = 0, ovl = 0;
   uint32_t wg = 0, n = 0;
@@ -453,6 +461,18 @@ void partition(Call& C, const Layout& lim) {
     }
     cur.item0[N_WCLASS] = at;
     cur.n_items = at - cur.item0[0];
+    if (any_sc) {
+      // the group check's order: instances with the largest static log
+      // bound first (the others are skipped at once)
+      const size_t o = C.sc_order.size();
+      for (uint32_t k = 0; k < n; ++k) C.sc_order.push_back(k);
+      auto cost = [&](uint32_t k) -> u64 {
+        const rc_prog* p = C.progs[C.inst_prog[cur.slot0 + k]];
+        return p->sc ? wg_log_need(p) : 0u;
+      };
+      std::stable_sort(C.sc_order.begin() + o, C.sc_order.end(),
+                       [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+    }
     C.chunks.push_back(cur);
     memset(&cur, 0, sizeof cur);
     cur.slot0 = next_slot0;
@@ -698,6 +718,7 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
       S.log_keys = P.log_keys; S.log_vals = P.log_vals; S.wg_count = P.wg_count;
       S.queue = P.queue + N_WCLASS;
       S.ends = (uint32_t*)(ws + L.sc_ends);
+      S.order = (const uint32_t*)(ws + L.sc_order);
       S.rec = P.rec;
       S.bs = L.bs; S.bc = L.bc;
       const uint32_t blocks =
@@ -885,6 +906,7 @@ rc_status run_call(rc_ctx* ctx, Call& C, char* ws, size_t ws_bytes, rc_record* d
   memcpy(h + (L.slots - L.tables), C.slots.data(), C.slots.size() * sizeof(SlotDesc));
   memcpy(h + (L.chunks - L.tables), C.chunks.data(), C.chunks.size() * sizeof(ChunkDesc));
   memcpy(h + (L.items - L.tables), C.items.data(), C.items.size() * 4);
+  if (L.sc_blocks) memcpy(h + (L.sc_order - L.tables), C.sc_order.data(), C.sc_order.size() * 4);
   memcpy(h + (L.recout - L.tables), &R, sizeof R);
   HIP_TRY(hipMemcpyAsync(ws + L.tables, h, tbytes, hipMemcpyHostToDevice, st));
   if (!ctx->upload_done) HIP_TRY(hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));

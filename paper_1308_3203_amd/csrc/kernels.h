@@ -111,6 +111,7 @@ struct ScParams {
   uint32_t* wg_count;             // [work-group] region words written (zeroed once checked)
   uint32_t* queue;
   uint32_t* ends;
+  const uint32_t* order;          // [call instance] chunk-relative slots in queue order, per chunk
   const rc_record_out* rec;
   uint32_t bs, bc;
 };

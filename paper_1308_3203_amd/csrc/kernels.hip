@@ -167,7 +167,8 @@ __global__ __launch_bounds__(1024) void rc_interp_vreg_kernel(PassParams PP) {
 
 // ---------------------------------------------------------------------------
 // Spilled intervals of one-group programs (ProgDesc::sc), after the
-// interpreter: persistent blocks take the chunk's instances from a queue;
+// interpreter: persistent blocks take the chunk's instances from a queue,
+// in the planner's order (largest static log bound first);
 // for each one whose program has sc set, the block walks its region's
 // trailers back from the end, checks every spilled interval in LDS
 // (sc_check), and sets the region's count to zero.  Its records carry the interval's ranks and counts like those
@@ -197,9 +198,9 @@ __global__ __launch_bounds__(SC_THREADS) void sc_group_kernel(ScParams S) {
   for (;;) {
     if (tl == 0) ctl->item = atomicAdd(S.queue, 1u);
     __syncthreads();
-    const uint32_t rel = uni(ctl->item);
+    const uint32_t taken = uni(ctl->item);
     __syncthreads();
-    if (rel >= C.n_slots) {
+    if (taken >= C.n_slots) {
       // the block's unused record slots
       const u64 a = ctl->rc_cur, b = ctl->rc_end;
       for (u64 q = a + tl; q < b && q < R.rec_cap; q += SC_THREADS) RC_GLOBAL(u64, R.rec_keys)[q] = ~0ull;
@@ -208,6 +209,8 @@ __global__ __launch_bounds__(SC_THREADS) void sc_group_kernel(ScParams S) {
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
+    // the chunk's slots largest static log bound first
+    const uint32_t rel = const_load<uint32_t>(S.order, C.slot0 + taken);
     const uint32_t instance = C.slot0 + rel;
     const SlotDesc Sd = const_load<SlotDesc>(S.slots, instance);
     const ProgDesc D = const_load<ProgDesc>(S.progs, Sd.prog);

@@ -116,7 +116,12 @@ struct ScParams {
   uint32_t bs, bc;
 };
 constexpr uint32_t SC_THREADS = 512;
-constexpr uint32_t SC_CTL_BYTES = (uint32_t)((sizeof(Ctl) + 15) & ~(size_t)15);
+// the group check's part of the control block: the queue item and the record
+// reservation words, which come first in Ctl; its work area starts after them
+constexpr uint32_t SC_CTL_BYTES = (uint32_t)((offsetof(Ctl, uval) + 15) & ~(size_t)15);
+static_assert(offsetof(Ctl, item) < offsetof(Ctl, uval) && offsetof(Ctl, rc_room) < offsetof(Ctl, uval) &&
+                  offsetof(Ctl, rec_sum_total) < offsetof(Ctl, uval),
+              "the group check's control fields must precede its work area");
 constexpr uint32_t SC_MAX_BLOCKS = 1024;
 hipError_t launch_sc_group(const ScParams& S, uint32_t blocks, hipStream_t st);
 int sc_group_occupancy();

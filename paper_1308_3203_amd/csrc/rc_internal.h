@@ -237,13 +237,15 @@ struct Ctl {
   uint32_t red[2][MAX_WAVES];           // per-wave reduction words, double-buffered
   uint32_t rec_sum[MAX_WAVES];          // per-wave record counts of a reservation
   uint32_t rec_sum_total, pad2;         // and their sum
+  uint32_t item;                        // work item taken by the group
+  uint32_t pad;
+  // (the group check kernel uses the fields above and puts its work area
+  // where the next one starts)
   // the interpreter's special operands by selector (SEL_LID ...): lid and
   // tid add the work-item's lid to words 0 and 1; the scalar parameters
   // follow at SEL_SCALAR0
   int32_t uval[SEL_SCALAR0 - SEL_LID + MAX_SCALARS];
   uint32_t loopctr[MAX_WAVES][MAX_NEST];
-  uint32_t item;                        // work item taken by the group
-  uint32_t pad;
   uint32_t lds_cnt[2];                  // LDS log entries of the even / odd intervals
                                         // (elided group steps)
   unsigned long long gl_cnt;            // global log entries of the group (elided group steps)

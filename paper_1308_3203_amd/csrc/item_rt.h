@@ -53,6 +53,9 @@ __device__ __forceinline__ int32_t alu_bin(uint32_t op, int32_t x, int32_t y, bo
       if (y == -1) return 0;
       return x % y;
     case B_MOD: {
+      // a positive power of two: the result in [0, y) is the low bits of x
+      // in two's complement (no division)
+      if (y > 0 && (uy & (uy - 1u)) == 0u) return (int32_t)(ux & (uy - 1u));
       if (y == 0) { dz = true; return 0; }
       if (y == -1 || y == 1) return 0;
       int32_t r = x % y;

@@ -140,6 +140,31 @@ def test_int32_corners_final_memory():
     assert np.array_equal(fin.cpu().numpy(), orc.final)
 
 
+@pytest.mark.parametrize("jit", [False, True])
+def test_mod_by_powers_of_two_final_memory(jit):
+    """mod by a positive power of two takes the low bits; other divisors,
+    negative ones and zero's neighbours take the division path.  Lanes mix
+    both (divisor tid + 1), with negative dividends, and the corners of
+    int32 (m = -2^31)."""
+    src = """kernel md(global int out[72], int m, int s) {
+      out[tid] := (s * tid - 77) mod (tid + 1);
+      out[64] := m mod 65536; out[65] := m mod 1; out[66] := (0 - 1) mod 4096; out[67] := m mod 1073741824;
+      out[68] := (m + 5) mod (0 - 4); out[69] := (0 - 4097) mod 4096; out[70] := 2147483647 mod 2;
+      out[71] := (0 - 1) mod (m + 2147483647 + 1 + 8); }"""
+    import torch
+    prog = B.Program(U.ctx(), src)
+    prog.set_ndrange(1, 64)
+    prog.bind({"out": torch.zeros(72, dtype=torch.int32, device="cuda")}, {"m": -(2 ** 31), "s": -12345})
+    if jit:
+        prog.jit(True)
+    ws = torch.empty(prog.workspace_size(1), dtype=torch.uint8, device="cuda")
+    fin = prog.read_final(0, "out", ws)
+    U.ctx().sync()
+    orc = O.check(src, 1, 64, arrays={"out": np.zeros(72, np.int32)}, scalars={"m": -(2 ** 31), "s": -12345},
+                  final="out")
+    assert np.array_equal(fin.cpu().numpy(), orc.final)
+
+
 # ---------------------------------------------------------------------------
 # c2 templates
 # ---------------------------------------------------------------------------

@@ -10,10 +10,13 @@ The headline is the batched random-kernel sweep (c3: 10^4 random kernels of
 widths 32..1024 x 100 seeds, 10^6 instances, one rc_batch_check call per
 step), the largest configuration.  The same line carries, as secondary
 figures, the template kernels (c2: six programs, 16 x 256, 10^4 seeds each)
-with the static proofs on and off, and the large-interval kernel (c4: 64 x
-1024 x 64 iterations, 16 seeds).  Other configurations: c1 (one random
-20-statement kernel, 1 x 64, 1000 seeds) and c5 (learned triage over the c3
-generator: train, then sweep held-out instances in learned and plain order).
+with the static proofs on and off, the large-interval kernel (c4: 64 x
+1024 x 64 iterations, 16 seeds), and the learned triage (c5 over the c3
+generator: 10^5 training programs x 10 seeds labelled by the checker, the
+network trained, then 10^4 held-out programs x 10 seeds swept in learned,
+plain, random and static-heuristic order; --no-c5 leaves it out).  Other
+configurations: c1 (one random 20-statement kernel, 1 x 64, 1000 seeds),
+and each of the secondaries alone (--config c2, c4, c5).
 
 Roofline: a race-checked access costs 28 algorithmic bytes (4 for the
 simulated cell, 12 to write its access record once, 12 to read it once).
@@ -405,7 +408,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="only the headline configuration")
     ap.add_argument("--secondary-steps", type=int, default=10)
     ap.add_argument("--proofs-off", action="store_true", help="c1/c2/c4: no static proofs")
-    ap.add_argument("--eval-programs", type=int, default=1000, help="c5: held-out programs")
+    ap.add_argument("--no-c5", action="store_true", help="c3: no learned-triage field in the line")
+    ap.add_argument("--train-programs", type=int, default=100000, help="c5: training programs")
+    ap.add_argument("--eval-programs", type=int, default=10000, help="c5: held-out programs")
     ap.add_argument("--epochs", type=int, default=5, help="c5: training epochs")
     ap.add_argument("--chunk", type=int, default=1000, help="c5: instances per sweep call")
     ap.add_argument("--weight-records", action="store_true",
@@ -493,6 +498,8 @@ def main():
         secondary["c2"] = run_secondary(ctx, "c2", args)
         secondary["c2_proofs_off"] = run_secondary(ctx, "c2", args, proofs_off=True)
         secondary["c4"] = run_secondary(ctx, "c4", args)
+        if not args.no_c5:
+            secondary["c5"] = c5_secondary(args, ctx)
     config = {"workload": desc, **cfg_extra, "instances_per_step": n_inst, "setup_s": round(setup_s, 2),
               "accesses_per_step": m["accesses"], "accesses_logged": m["accesses_logged"],
               "accesses_logged_global": m["accesses_logged_global"],
@@ -652,7 +659,10 @@ def copy_probe(gib: float, reps: int = 3):
                       "gbs": round(2 * n * 4 / dt / 1e9, 1)}), flush=True)
 
 
-def bench_c5(args, ctx):
+C5_HELD0 = 1000000   # first generator seed of the held-out programs
+
+
+def c5_line(args, ctx) -> dict:
     """Learned triage: label the training instances with the exact checker,
     train the network on the GPU, then sweep the held-out instances in plain
     and in learned order and compare what each finds within a quarter of the
@@ -660,11 +670,14 @@ def bench_c5(args, ctx):
     import torch
     from paper_1308_3203_amd import triage as T
     from paper_1308_3203_amd import workloads as WL
-    n_train, n_eval = args.programs, args.eval_programs
-    seeds = args.seeds or 100
+    # many programs, few seeds each: the network has to generalise across
+    # programs (the seeds of one program differ only in their histograms);
+    # held-out programs come from a disjoint range of generator seeds
+    n_train, n_eval = args.train_programs, args.eval_programs
+    seeds = args.seeds or 10
     t0 = time.perf_counter()
     r = T.run(ctx, [WL.c3_kernel(s) for s in range(n_train)], seeds,
-              [WL.c3_kernel(10000 + s) for s in range(n_eval)], seeds,
+              [WL.c3_kernel(C5_HELD0 + s) for s in range(n_eval)], seeds,
               epochs=args.epochs, batch=4096, lr=1e-3, chunk=args.chunk, label_chunk=20000,
               ws_bytes=int(args.ws_gb * (1 << 30)), weight_records=args.weight_records,
               progress=lambda m: print(f"[c5 {time.perf_counter() - t0:.1f}s] {m}", file=sys.stderr, flush=True))
@@ -677,8 +690,8 @@ def bench_c5(args, ctx):
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(wall * 1e3, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 network, int32 checker", "data": "synthetic",
         "config": {"workload": "c5: learned triage over the c3 generator; train programs 0..%d x %d seeds, "
-                               "held-out programs 10000..%d x %d seeds" % (n_train - 1, seeds, 10000 + n_eval - 1,
-                                                                          seeds),
+                               "held-out programs %d..%d x %d seeds" % (n_train - 1, seeds, C5_HELD0,
+                                                                       C5_HELD0 + n_eval - 1, seeds),
                    "train_instances": r.n_train, "eval_instances": r.n_eval,
                    "train_racy_frac": round(r.train_racy_frac, 4), "epochs": args.epochs,
                    "weight_records": args.weight_records,
@@ -698,7 +711,28 @@ def bench_c5(args, ctx):
                               for k, o in rep.orders.items()}},
         "roofline": None, "cpu_baseline": None,
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def bench_c5(args, ctx):
+    print(json.dumps(c5_line(args, ctx)), flush=True)
+
+
+def c5_secondary(args, ctx) -> dict:
+    """The learned-triage experiment as a field of the default line: its
+    recalls, the baselines' and its own value."""
+    line = c5_line(args, ctx)
+    t = line["triage"]
+    out = {"metric": line["metric"], "value": line["value"], "unit": line["unit"],
+           "ms_per_step": line["ms_per_step"], "workload": line["config"]["workload"],
+           "recall_racy_instances": t["recall_racy_instances"], "recall_race_records": t["recall_race_records"],
+           "budget_frac": t["budget_frac"], "inference_gpu_ms": t["inference_gpu_ms"],
+           "racy_instances": t["racy_instances"], "race_records": t["race_records"],
+           "orders": {k: {"recall_racy_instances": o["recall_racy_instances"],
+                          "recall_race_records": o["recall_race_records"]} for k, o in t["orders"].items()}}
+    say(f"secondary c5: recall {out['recall_racy_instances']} of racy instances, "
+        f"{out['recall_race_records']} of RACE records within {out['budget_frac']} of the plain sweep's GPU time")
+    return out
 
 
 if __name__ == "__main__":

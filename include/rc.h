@@ -416,7 +416,10 @@ rc_status rc_read_final(rc_prog* prog, uint64_t seed, uint32_t array_id, int32_t
  *   [24..32)  stores whose value is affine with a != 0 (/16); stores whose
  *             value is not affine (/16); deepest if nesting (/16); deepest
  *             loop nesting (/4); memory statements under an if (/16), under a
- *             loop (/16); distinct static intervals holding a store (/8); 0
+ *             loop (/16); distinct static intervals holding a store (/8);
+ *             of the pairs with equal a and different b, those whose cells
+ *             meet within 1024 work-items: a*d = b_q - b_p (mod size(A)) for
+ *             some 1 <= |d| <= 1024 (/8)
  *   [32..96)  memory statements k = 0..15, 4 each (zeros when absent):
  *             store ? 1 : -1;  affine ? a / (1+|a|) : -2;  affine ? b / size
  *             : -2;  (interval+1) / 8 (all three exact ratios)

@@ -1260,7 +1260,7 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
   /* candidate conflicting pairs: same array, a store among them, same static
      interval (statements under a loop that holds a barrier counted apart) */
   int64_t self_const = 0, self_const_if = 0, self_other = 0, shifted = 0, aligned = 0;
-  int64_t strides = 0, opaque = 0, looped = 0;
+  int64_t strides = 0, opaque = 0, looped = 0, shifted_meet = 0;
   for (int64_t i = 0; i < F.n_mem; i++) {
     for (int64_t j = i; j < F.n_mem; j++) {
       const FMem* x = &F.mem[i];
@@ -1277,8 +1277,20 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
       if (!x->idx.ok || !y->idx.ok) { opaque++; continue; }
       if (x->idx.a != y->idx.a) { strides++; continue; }
       int64_t S = P->arr_size[x->arr];
-      if (pos_mod(x->idx.b, S) == pos_mod(y->idx.b, S)) aligned++;
-      else shifted++;
+      if (pos_mod(x->idx.b, S) == pos_mod(y->idx.b, S)) {
+        aligned++;
+      } else {
+        shifted++;
+        /* work-items d apart (1 <= |d| <= 1024) reach one cell when
+           a*d and the offset difference agree mod the array size */
+        int64_t diff = pos_mod(y->idx.b - x->idx.b, S), d;
+        for (d = 1; d <= 1024; d++) {
+          if (pos_mod(x->idx.a * d - diff, S) == 0 || pos_mod(-x->idx.a * d - diff, S) == 0) {
+            shifted_meet++;
+            break;
+          }
+        }
+      }
     }
   }
   f[16] = fsq(self_const, 8);
@@ -1306,6 +1318,7 @@ int orc_features(const orc_prog* P, uint32_t G, uint32_t W, const orc_bind* arra
     }
     f[30] = fsq(distinct, 8);
   }
+  f[31] = fsq(shifted_meet, 8);
   /* the first 16 memory statements */
   for (int64_t k = 0; k < 16 && k < F.n_mem; k++) {
     const FMem* m = &F.mem[k];

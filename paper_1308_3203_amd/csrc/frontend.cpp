@@ -838,6 +838,13 @@ void static_features(const std::vector<Statement>& body, const Compiled& c, floa
   f[15] = ratio((int64_t)c.scalars.size(), 16);
   // pairs of memory statements that may touch one cell from two work-items
   int64_t pc[8] = {};
+  int64_t meet = 0;   // of the equal-a, different-b pairs: those whose cells meet
+  // within 1024 work-items: a*d = (b_q - b_p) mod S for some 1 <= |d| <= 1024
+  auto meets = [](int64_t a, int64_t db, int64_t S) {
+    for (int64_t d = 1; d <= 1024; ++d)
+      if (emod(a * d - db, S) == 0 || emod(-a * d - db, S) == 0) return true;
+    return false;
+  };
   const size_t M = w.mem.size();
   for (size_t p = 0; p < M; ++p) {
     for (size_t q = p; q < M; ++q) {
@@ -855,7 +862,12 @@ void static_features(const std::vector<Statement>& body, const Compiled& c, floa
       if (!x.idx.ok || !y.idx.ok) { ++pc[6]; continue; }
       if (x.idx.a != y.idx.a) { ++pc[5]; continue; }
       const int64_t S = c.arrays[x.arr].size;
-      if (emod(x.idx.b, S) != emod(y.idx.b, S)) ++pc[3]; else ++pc[4];
+      if (emod(x.idx.b, S) != emod(y.idx.b, S)) {
+        ++pc[3];
+        if (meets(x.idx.a, emod(y.idx.b - x.idx.b, S), S)) ++meet;
+      } else {
+        ++pc[4];
+      }
     }
   }
   for (int k = 0; k < 8; ++k) f[16 + k] = squash(pc[k], 8);
@@ -873,7 +885,7 @@ void static_features(const std::vector<Statement>& body, const Compiled& c, floa
     }
     f[30] = squash((int64_t)ivls.size(), 8);
   }
-  f[31] = 0.f;
+  f[31] = squash(meet, 8);
   for (size_t k = 0; k < 16; ++k) {
     float* s = f + 32 + 4 * k;
     if (k >= M) { s[0] = s[1] = s[2] = s[3] = 0.f; continue; }

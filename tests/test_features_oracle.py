@@ -52,6 +52,9 @@ def test_features_two_intervals_with_shifted_and_constant_cells():
          # shifted pairs: A[tid] / A[tid+1 mod 64], B[0] / B[2]
          16: sq(2, 8), 17: sq(1, 8), 19: sq(2, 8),
          24: sq(1, 16), 25: sq(1, 16), 26: sq(1, 16), 28: sq(1, 16), 30: sq(2, 8),
+         # of the shifted pairs, A's meet one work-item apart; B[0] / B[2]
+         # (a = 0) never do
+         31: sq(1, 8),
          # memory statements: (kind, a/(1+|a|), b/size, (interval+1)/8)
          32: -1, 33: 0.5, 34: 0, 35: (1, 8),
          36: 1, 37: 0.5, 38: (1, 64), 39: (1, 8),
@@ -159,3 +162,28 @@ def test_features_full_width_seeded_range():
             u = (O.seeded_value(9, 0, c, lo, lo + 2**32) - lo) % 2**32
             want[u * 8 // 2**32] += 1
         assert np.array_equal(f[112:120], (want / 256).astype(np.float32))
+
+
+SRC_MEET = """
+kernel k(global int A[64], global int B[4096]) {
+  int v;
+  A[(tid * 4) mod 64] := tid;
+  v := A[(tid * 4 + 2) mod 64];
+  v := A[(tid * 4 + 8) mod 64];
+  v := A[(tid * 4 - 8) mod 64];
+  B[(tid * 3 + 5) mod 4096] := v;
+  v := B[(tid * 3 + 3080) mod 4096];
+  v := B[(tid * 3 + 2) mod 4096];
+}
+"""
+
+
+def test_features_shifted_pairs_that_meet():
+    """Pairs with equal a and different b (feature 19) and those of them
+    whose cells meet within 1024 work-items (feature 31), worked by hand:
+    A: store at 4t, loads at 4t+2 (4d = 2 mod 64 has no solution), 4t+8
+    (d = 2) and 4t-8 (d = -2); B: store at 3t+5, loads at 3t+3080 (3d =
+    3075 mod 4096 only for d = 1025 mod 4096) and 3t+2 (d = -1)."""
+    f = O.Program(SRC_MEET).features(1, 64, {"A": ("seeded", 0, 16), "B": ("seeded", 0, 16)}, seed=3)
+    assert f[19] == np.float32(5) / np.float32(13)
+    assert f[31] == np.float32(3) / np.float32(11)

@@ -355,9 +355,12 @@ def test_rank_orders_by_score_then_index(n):
 # ---------------------------------------------------------------------------
 def test_learned_order_finds_races_sooner_than_plain_order():
     from paper_1308_3203_amd import triage as T
-    train = [WL.c3_kernel(s) for s in range(3000)]
-    held = [WL.c3_kernel(10000 + s) for s in range(300)]
-    r = T.run(ctx(), train, 4, held, 5, epochs=10, batch=1024, lr=2e-3, chunk=50, label_chunk=4000,
+    # many programs with few seeds each, as the benchmark runs it (the
+    # network has to generalise across programs); held-out programs from a
+    # disjoint range of generator seeds
+    train = [WL.c3_kernel(s) for s in range(12000)]
+    held = [WL.c3_kernel(1000000 + s) for s in range(1500)]
+    r = T.run(ctx(), train, 2, held, 2, epochs=10, batch=1024, lr=2e-3, chunk=100, label_chunk=4000,
               ws_bytes=8 << 30)
     rep = r.report
     print("triage:", rep, "losses", r.losses[0], r.losses[-1], "train racy", r.train_racy_frac, flush=True)
@@ -365,10 +368,13 @@ def test_learned_order_finds_races_sooner_than_plain_order():
     # within a quarter of the plain sweep's GPU time the learned order reaches
     # most racy instances and nearly every RACE record, far more than the
     # plain order does
-    assert rep.recall_instances >= 0.75
+    assert rep.recall_instances >= 0.9
     assert rep.recall_records >= 0.95
     assert rep.recall_instances >= rep.plain_recall_instances + 0.3
-    assert rep.races_per_gpu_s_learned >= 10 * rep.races_per_gpu_s_plain
+    # (records per GPU-second over the same budget: with the records spread
+    # over many programs the plain order finds about the budget's fraction
+    # of them, so the ratio cannot pass about 1 / budget_frac = 4)
+    assert rep.races_per_gpu_s_learned >= 3 * rep.races_per_gpu_s_plain
     # and more than the orders without the network: a random permutation
     # and the static count of candidate conflicting pairs
     assert set(rep.orders) == {"learned", "plain", "random", "static_heuristic"}

@@ -603,7 +603,9 @@ __global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, con
         const uint32_t base = woff[w][dr[r]];
         lkey[base + rank] = kr[r];
         lval[base + rank] = vr[r];
-        ldig[base + rank] = (uint8_t)dr[r];
+        // (the filter pass's digit comes from the owner table; any other
+        // pass's digit is read off the key again below)
+        if (in.keep) ldig[base + rank] = (uint8_t)dr[r];
         // the new offset depends on the value just read, so the wave's read
         // of this round is complete before any lane advances the counter
         if (rank == 0) woff[w][dr[r]] = base + cnt;
@@ -611,9 +613,10 @@ __global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, con
     }
     __syncthreads();
     for (uint32_t p = t; p < count; p += RS_THREADS) {
-      const uint32_t o = gbase[ldig[p]] + p;
-      kout[o] = lkey[p];
-      vout[o] = lval[p];
+      const u64 k = lkey[p];
+      const uint32_t d = in.keep ? (uint32_t)ldig[p] : (uint32_t)(k >> shift) & dmask;
+      kout[gbase[d] + p] = k;
+      vout[gbase[d] + p] = lval[p];
     }
     __syncthreads();   // the LDS tile and woff are reused for the next tile
   }

@@ -274,7 +274,8 @@ int sc_group_occupancy() {
 constexpr uint32_t SCAN_BLOCK = 1024;
 
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh, uint32_t* total) {
-  // 256 threads: inclusive scan via waves + LDS
+  // the values of the first 256 threads (any threads beyond hold 0): scan
+  // via waves + LDS; sh holds a word per wave of the block
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
   uint32_t x = v;
   for (int off = 1; off < 64; off <<= 1) {
@@ -362,6 +363,9 @@ __global__ __launch_bounds__(256) void scan_block_kernel(uint32_t* data, uint64_
 // stable LSD radix sort, 8-bit digits; n lives on the device
 // ---------------------------------------------------------------------------
 constexpr uint32_t RS_THREADS = 256, RS_ROUNDS = 16, RS_TILE = RS_THREADS * RS_ROUNDS;
+// the LDS-staged scatter ranks a tile with 512 threads (8 waves, 8 rounds):
+// its 70 KB of LDS allow two blocks, 16 waves, per CU
+constexpr uint32_t RSL_THREADS = 512, RSL_WAVES = RSL_THREADS / 64, RSL_ROUNDS = RS_TILE / RSL_THREADS;
 
 // Input of one radix pass: dense (n on the device), or segmented: region r
 // starts at entry seg_base[r] and holds seg_count[r] entries; tiles[r] is the
@@ -543,11 +547,11 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
 // consecutive addresses of one digit's run.  Dynamic LDS: RS_TILE keys,
 // values and digits.
 template <typename V>
-__global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
+__global__ __launch_bounds__(RSL_THREADS) void rs_scatter_lds_kernel(const u64* kin, const V* vin, u64* kout, V* vout,
                                                              RsIn in, uint32_t shift, const uint32_t* offs) {
-  __shared__ uint32_t woff[4][256];
+  __shared__ uint32_t woff[RSL_WAVES][256];
   __shared__ uint32_t gbase[256];
-  __shared__ uint32_t sh[4];
+  __shared__ uint32_t sh[RSL_WAVES];
   u64* lkey = reinterpret_cast<u64*>(rc_smem);
   V* lval = reinterpret_cast<V*>(lkey + RS_TILE);
   uint8_t* ldig = reinterpret_cast<uint8_t*>(lval + RS_TILE);
@@ -558,14 +562,14 @@ __global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, con
     u64 start;
     uint32_t count;
     rs_tile(in, b, &start, &count);
-    for (uint32_t ww = 0; ww < 4; ++ww) woff[ww][t] = 0u;
+    for (uint32_t i = t; i < RSL_WAVES * 256u; i += RSL_THREADS) (&woff[0][0])[i] = 0u;
     __syncthreads();
-    const uint32_t wbeg = w * (RS_TILE / 4);
-    u64 kr[RS_ROUNDS];
-    V vr[RS_ROUNDS];
-    uint32_t dr[RS_ROUNDS];
+    const uint32_t wbeg = w * (RS_TILE / RSL_WAVES);
+    u64 kr[RSL_ROUNDS];
+    V vr[RSL_ROUNDS];
+    uint32_t dr[RSL_ROUNDS];
 #pragma unroll
-    for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+    for (uint32_t r = 0; r < RSL_ROUNDS; ++r) {
       const uint32_t i = wbeg + r * 64u + lane;
       const bool valid = i < count;
       kr[r] = valid ? kin[start + i] : 0ull;
@@ -579,13 +583,17 @@ __global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, con
     // tile-local start of each digit (scan over the digits), then each
     // wave's start within it; gbase maps a local position to the output
     {
-      const uint32_t c = t <= dmask ? woff[0][t] + woff[1][t] + woff[2][t] + woff[3][t] : 0u;
+      uint32_t c = 0;
+      if (t <= dmask)
+        for (uint32_t ww = 0; ww < RSL_WAVES; ++ww) c += woff[ww][t];
+      // (threads from 256 on hold no digit and add nothing: the scan of
+      // the first 256 is exact)
       uint32_t total;
       const uint32_t lstart = block_excl_scan_256(c, sh, &total);
       if (t <= dmask) {
         gbase[t] = offs[(size_t)t * nt + b] - lstart;
         uint32_t o = lstart;
-        for (uint32_t ww = 0; ww < 4; ++ww) {
+        for (uint32_t ww = 0; ww < RSL_WAVES; ++ww) {
           const uint32_t n = woff[ww][t];
           woff[ww][t] = o;
           o += n;
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, con
     }
     __syncthreads();
 #pragma unroll
-    for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+    for (uint32_t r = 0; r < RSL_ROUNDS; ++r) {
       const uint32_t i = wbeg + r * 64u + lane;
       const bool valid = i < count;
       uint32_t rank, cnt;
@@ -612,7 +620,7 @@ __global__ __launch_bounds__(256) void rs_scatter_lds_kernel(const u64* kin, con
       }
     }
     __syncthreads();
-    for (uint32_t p = t; p < count; p += RS_THREADS) {
+    for (uint32_t p = t; p < count; p += RSL_THREADS) {
       const u64 k = lkey[p];
       const uint32_t d = in.keep ? (uint32_t)ldig[p] : (uint32_t)(k >> shift) & dmask;
       kout[gbase[d] + p] = k;
@@ -1458,7 +1466,7 @@ static hipError_t sort_pairs_impl(u64* k0, V* v0, u64* k1, V* v1, const u64* n_p
     // directly
     const bool short_regions = in.seg_count && cap < (u64)n_regions * (RS_TILE / 2);
     if (lds_scatter && !short_regions)
-      hipLaunchKernelGGL(rs_scatter_lds_kernel<V>, dim3(grid), dim3(RS_THREADS), rs_scatter_lds<V>(), st,
+      hipLaunchKernelGGL(rs_scatter_lds_kernel<V>, dim3(grid), dim3(RSL_THREADS), rs_scatter_lds<V>(), st,
                          (const u64*)ka, (const V*)va, kb, vb, in, shift, (const uint32_t*)hst);
     else
       hipLaunchKernelGGL(rs_scatter_kernel<V>, dim3(grid), dim3(RS_THREADS), 0, st, (const u64*)ka, (const V*)va, kb,

@@ -712,21 +712,47 @@ __device__ __forceinline__ void push_long(const SegParams& S, u64 s, u64 e, bool
 
 // Segmented inclusive minimum over the lanes of a wave: `heads` has a bit
 // per lane that starts a run; each lane ends with the minimum of its run up
-// to itself, so a run's last lane holds the run's minimum.
+// to itself, so a run's last lane holds the run's minimum.  A scan of
+// (value, started) pairs with DPP moves: shifts by 1, 2, 4 and 8 lanes inside
+// each row of 16, then row 0's and row 2's last lanes into rows 1 and 3, and
+// lane 31 into rows 2 and 3.  A lane takes the value it receives unless a
+// run starts between the two (its flag), and lanes that receive nothing get
+// the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_min_step(uint32_t& v, uint32_t& f) {
+  const uint32_t vo = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)v, CTRL, ROWS, 0xF, false);
+  const uint32_t fo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, CTRL, ROWS, 0xF, false);
+  if (!f) v = vo < v ? vo : v;
+  f |= fo;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_min_step64(u64& v, uint32_t& f) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+  const uint32_t fo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, CTRL, ROWS, 0xF, false);
+  const u64 vo = ((u64)hi << 32) | lo;
+  if (!f) v = vo < v ? vo : v;
+  f |= fo;
+}
+// DPP controls: row_shr:n is 0x110 + n, row_bcast:15 0x142, row_bcast:31 0x143
 __device__ __forceinline__ uint32_t seg_min_u32(uint32_t v, u64 heads, uint32_t lane) {
-  for (uint32_t off = 1; off < 64; off <<= 1) {
-    const uint32_t o = __shfl_up(v, off);
-    // lanes (lane - off, lane] hold no run head: the source is in this run
-    if (lane >= off && ((heads >> (lane + 1u - off)) & ((1ull << off) - 1ull)) == 0ull) v = o < v ? o : v;
-  }
+  uint32_t f = (uint32_t)(heads >> lane) & 1u;
+  seg_min_step<0x111, 0xF>(v, f);
+  seg_min_step<0x112, 0xF>(v, f);
+  seg_min_step<0x114, 0xF>(v, f);
+  seg_min_step<0x118, 0xF>(v, f);
+  seg_min_step<0x142, 0xA>(v, f);
+  seg_min_step<0x143, 0xC>(v, f);
   return v;
 }
 __device__ __forceinline__ u64 seg_min_u64(u64 v, u64 heads, uint32_t lane) {
-  for (uint32_t off = 1; off < 64; off <<= 1) {
-    const uint32_t lo = __shfl_up((uint32_t)v, off), hi = __shfl_up((uint32_t)(v >> 32), off);
-    const u64 o = ((u64)hi << 32) | lo;
-    if (lane >= off && ((heads >> (lane + 1u - off)) & ((1ull << off) - 1ull)) == 0ull) v = o < v ? o : v;
-  }
+  uint32_t f = (uint32_t)(heads >> lane) & 1u;
+  seg_min_step64<0x111, 0xF>(v, f);
+  seg_min_step64<0x112, 0xF>(v, f);
+  seg_min_step64<0x114, 0xF>(v, f);
+  seg_min_step64<0x118, 0xF>(v, f);
+  seg_min_step64<0x142, 0xA>(v, f);
+  seg_min_step64<0x143, 0xC>(v, f);
   return v;
 }
 __device__ __forceinline__ u64 shfl_u64(u64 v, uint32_t src) {

@@ -573,12 +573,21 @@ __device__ uint32_t sc_window(const ScEnv& E, const u64* in, uint32_t n, uint32_
   const uint32_t tl = threadIdx.x;
   Ctl* ctl = reinterpret_cast<Ctl*>(rc_smem);
   const bool scan = n >= SC_SCAN_MIN;
+  // Every field only decreases, so an entry whose value is not below the
+  // field's current one (a read that may be stale, never below the true
+  // value) needs no atomic: a cell that every work-item touches sees few
+  // atomics instead of one per lane.  (A cell already touched is not the
+  // first touch, so skipping leaves the bitmap right.)
   sc_each(in, n, E.nthr, [&](u64 e) {
     const uint32_t c = (uint32_t)(e >> 43) - base;
     const uint32_t l = (uint32_t)(e >> 32) & 1023u;
-    bool first;
-    if ((e >> 42) & 1u) first = atomicMin(&E.wmin[c], ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u)) == ~0ull;
-    else first = atomicMin(&E.r1[c], l) == NONE32;
+    bool first = false;
+    if ((e >> 42) & 1u) {
+      const u64 v = ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u);
+      if (E.wmin[c] > v) first = atomicMin(&E.wmin[c], v) == ~0ull;
+    } else if (E.r1[c] > l) {
+      first = atomicMin(&E.r1[c], l) == NONE32;
+    }
     if (!scan && first) atomicOr(&E.bits[c >> 5], 1u << (c & 31u));
   });
   __syncthreads();
@@ -587,9 +596,9 @@ __device__ uint32_t sc_window(const ScEnv& E, const u64* in, uint32_t n, uint32_
     const uint32_t l = (uint32_t)(e >> 32) & 1023u;
     if ((e >> 42) & 1u) {
       const u64 wmin = E.wmin[c];
-      if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u)) atomicMin(&E.q[c], l);
-      if (l != (uint32_t)(wmin >> 32)) atomicMin(&E.w2[c], l);
-    } else if (l != E.r1[c]) {
+      if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u) && E.q[c] > l) atomicMin(&E.q[c], l);
+      if (l != (uint32_t)(wmin >> 32) && E.w2[c] > l) atomicMin(&E.w2[c], l);
+    } else if (l != E.r1[c] && E.r2[c] > l) {
       atomicMin(&E.r2[c], l);
     }
   });
@@ -1006,8 +1015,14 @@ struct Item {
       const u64 e = lkey[i];
       TabCell& c = tab[(uint32_t)(e >> 43)];
       const uint32_t l = (uint32_t)(e >> 32) & 1023u;
-      if ((e >> 42) & 1u) atomicMin(&c.wmin, ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u));
-      else atomicMin(&c.r1, l);
+      // (fields only decrease: an entry not below the current value needs
+      // no atomic)
+      if ((e >> 42) & 1u) {
+        const u64 v = ((u64)l << 32) | ((uint32_t)e ^ 0x80000000u);
+        if (c.wmin > v) atomicMin(&c.wmin, v);
+      } else if (c.r1 > l) {
+        atomicMin(&c.r1, l);
+      }
     }
     __syncthreads();
     for (uint32_t i = tl; i < n; i += nthr) {
@@ -1017,9 +1032,9 @@ struct Item {
       if ((e >> 42) & 1u) {
         const u64 wmin = c.wmin;
         const uint32_t w1 = (uint32_t)(wmin >> 32);
-        if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u)) atomicMin(&c.q, l);
-        if (l != w1) atomicMin(&c.w2, l);
-      } else if (l != c.r1) {
+        if ((uint32_t)e != ((uint32_t)wmin ^ 0x80000000u) && c.q > l) atomicMin(&c.q, l);
+        if (l != w1 && c.w2 > l) atomicMin(&c.w2, l);
+      } else if (l != c.r1 && c.r2 > l) {
         atomicMin(&c.r2, l);
       }
     }

@@ -667,6 +667,8 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.wg_count), L.max_wg, 0u, st));
     if (L.rank) HIP_TRY(launch_fill_u32((uint32_t*)(ws + L.scope_cnt), L.scope_n, 0u, st));
   }
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   {
     PassParams P;
     memset(&P, 0, sizeof P);
@@ -682,8 +684,6 @@ rc_status enqueue_chunk(rc_ctx* ctx, const Call& C, char* ws, hipStream_t st, u6
     P.cell_owner = (L.filter && do_log) ? (uint32_t*)(ws + L.cc) : nullptr;
     P.cell_owner_stride = L.cc_stride;
     P.stats = do_log ? cnt + CNT_STATS : nullptr;
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     // a call of one program with a compiled kernel runs that kernel; any
     // other call runs the interpreter
     rc_prog* jp = C.jit ? C.progs[0] : nullptr;

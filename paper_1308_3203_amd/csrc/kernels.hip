@@ -906,14 +906,19 @@ __global__ __launch_bounds__(256) void seg_check_kernel(SegParams S) {
     const int32_t v = pay_val(p);
     const uint32_t lid = pay_lid(p);
     const uint32_t g = (uint32_t)(k >> S.bk) & gmask;
-    const RunSums ri = window_runs(valid, lid, w, v, hsub, last_sub, lane, false);
-    const RunSums rx = window_runs(valid, (g << 10) | lid, w, v, hcell, last_cell, lane, true);
-    bool has_intra = false, has_inter = false;
-    SegHead H;
-    PendingRec pa, pb;
     const uint32_t len_sub = last_sub + 1u - lane, len_cell = last_cell + 1u - lane;
     const bool want_intra = sub_head && (open_sub || len_sub >= 2u);
     const bool want_inter = head && (open_cell || len_cell >= 2u);
+    // the lane reductions of a scope only where some run of it ends in the
+    // window with two entries or more (the conditions are wave-uniform)
+    RunSums ri, rx;
+    if (__ballot(want_intra && !open_sub) != 0ull)
+      ri = window_runs(valid, lid, w, v, hsub, last_sub, lane, false);
+    if (__ballot(want_inter && !open_cell) != 0ull)
+      rx = window_runs(valid, (g << 10) | lid, w, v, hcell, last_cell, lane, true);
+    bool has_intra = false, has_inter = false;
+    SegHead H;
+    PendingRec pa, pb;
     if (want_intra || want_inter) {
       H = seg_head(S, k);
       if (want_intra) {
@@ -1070,41 +1075,66 @@ __global__ __launch_bounds__(256) void seg_long_kernel(SegParams S) {
 __global__ __launch_bounds__(256) void rec_gather_kernel(GatherParams Gp) {
   const u64 n = *Gp.n_ptr;
   const uint32_t lane = threadIdx.x & 63u;
-  // a fixed grid walks the staged records (their count is on the device)
-  for (u64 base = (u64)blockIdx.x * 256u; base < n; base += (u64)gridDim.x * 256u) {
-  const u64 p = base + threadIdx.x;
-  bool valid = p < n;
-  uint32_t slot = 0;
-  bool race = false, benign = false;
-  uint32_t ix = 0;
-  if (valid) {
-    ix = Gp.idx[p];
-    valid = ix < Gp.stage_cap;   // (only an overflowed staging leaves a hole)
-  }
-  if (valid) {
-    const rc_record_dev r = Gp.staging[ix];
-    const u64 out = *Gp.out_base + p;
-    slot = r.instance - Gp.chunks[*Gp.chunk_index].slot0;
-    const uint32_t label = r.array_label >> 16;
-    race = (label & 3u) != 0u;
-    benign = label == 4u;
-    if (out < Gp.cap) Gp.out[out] = r;
-    else atomicOr(&Gp.inst_flags[slot], 1u);
-  }
-  // aggregate per-instance counts over the wave when it holds one instance
-  const uint32_t s0 = __builtin_amdgcn_readfirstlane(slot);
-  const u64 same = __ballot(!valid || slot == s0);
-  if (same == ~0ull) {
-    const uint32_t nr = (uint32_t)__popcll(__ballot(race)), nb = (uint32_t)__popcll(__ballot(benign));
-    if (lane == 0) {
-      if (nr) atomicAdd(&Gp.inst_race[s0], nr);
-      if (nb) atomicAdd(&Gp.inst_benign[s0], nb);
+  const u64 out0 = *Gp.out_base;
+  const uint32_t slot0 = Gp.chunks[*Gp.chunk_index].slot0;
+  // each wave walks one contiguous range of the sorted records in rounds of
+  // 64 (the count is on the device); the records of an instance are
+  // consecutive, so a wave adds up the instance counts of its rounds while
+  // they stay on one instance and touches the shared counters only when the
+  // instance changes: a call of few instances sees few atomics on them
+  const u64 waves = (u64)gridDim.x * (blockDim.x >> 6);
+  const u64 n_rounds = (n + 63u) / 64u, per = (n_rounds + waves - 1u) / waves;
+  const u64 wid = (u64)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const u64 r_end = (wid + 1u) * per < n_rounds ? (wid + 1u) * per : n_rounds;
+  uint32_t acc_slot = NONE32, acc_race = 0, acc_benign = 0;   // wave-uniform
+  auto flush = [&]() {
+    if (acc_slot != NONE32 && lane == 0) {
+      if (acc_race) atomicAdd(&Gp.inst_race[acc_slot], acc_race);
+      if (acc_benign) atomicAdd(&Gp.inst_benign[acc_slot], acc_benign);
     }
-  } else if (valid) {
-    if (race) atomicAdd(&Gp.inst_race[slot], 1u);
-    if (benign) atomicAdd(&Gp.inst_benign[slot], 1u);
+    acc_slot = NONE32;
+    acc_race = acc_benign = 0;
+  };
+  for (u64 rd = wid * per; rd < r_end; ++rd) {
+    const u64 p = rd * 64u + lane;
+    bool valid = p < n;
+    uint32_t slot = 0;
+    bool race = false, benign = false;
+    uint32_t ix = 0;
+    if (valid) {
+      ix = Gp.idx[p];
+      valid = ix < Gp.stage_cap;   // (only an overflowed staging leaves a hole)
+    }
+    if (valid) {
+      const rc_record_dev r = Gp.staging[ix];
+      const u64 out = out0 + p;
+      slot = r.instance - slot0;
+      const uint32_t label = r.array_label >> 16;
+      race = (label & 3u) != 0u;
+      benign = label == 4u;
+      if (out < Gp.cap) Gp.out[out] = r;
+      else atomicOr(&Gp.inst_flags[slot], 1u);
+    }
+    const u64 vm = __ballot(valid);
+    if (vm == 0ull) continue;
+    const uint32_t s0 = __builtin_amdgcn_readlane(slot, (uint32_t)__ffsll((long long)vm) - 1u);
+    const u64 same = __ballot(!valid || slot == s0);
+    if (same == ~0ull) {
+      if (s0 != acc_slot) {
+        flush();
+        acc_slot = s0;
+      }
+      acc_race += (uint32_t)__popcll(__ballot(race));
+      acc_benign += (uint32_t)__popcll(__ballot(benign));
+    } else {
+      flush();
+      if (valid) {
+        if (race) atomicAdd(&Gp.inst_race[slot], 1u);
+        if (benign) atomicAdd(&Gp.inst_benign[slot], 1u);
+      }
+    }
   }
-  }
+  flush();
 }
 
 
@@ -1546,7 +1576,7 @@ hipError_t launch_seg_check(const SegParams& S, u64 cap, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_gather(const GatherParams& G, u64 cap, hipStream_t st) {
-  hipLaunchKernelGGL(rec_gather_kernel, dim3((uint32_t)std::min<u64>(blocks_for(cap ? cap : 1, 256), 8192)),
+  hipLaunchKernelGGL(rec_gather_kernel, dim3((uint32_t)std::min<u64>(blocks_for(cap ? cap : 1, 256), 2048)),
                      dim3(256), 0, st, G);
   return hipGetLastError();
 }

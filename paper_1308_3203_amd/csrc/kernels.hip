@@ -464,10 +464,18 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, 
     u64 start;
     uint32_t count;
     rs_tile(in, b, &start, &count);
-    for (uint32_t i0 = 0; i0 < count; i0 += RS_THREADS) {
-      const uint32_t i = i0 + t;
-      const bool valid = i < count;
-      const uint32_t d = valid ? rs_digit(in, keys[start + i], shift, dmask) : 0u;
+    // the tile's keys are loaded before any is counted, so each thread has
+    // all its loads in flight at once (the pass is bound by memory latency)
+    u64 kr[RS_ROUNDS];
+#pragma unroll
+    for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+      const uint32_t i = r * RS_THREADS + t;
+      kr[r] = i < count ? keys[start + i] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+      const bool valid = r * RS_THREADS + t < count;
+      const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
       uint32_t rank, cnt;
       digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
       if (valid && rank == 0) atomicAdd(&h[d], cnt);
@@ -498,12 +506,18 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
   const uint32_t wbeg = w * (RS_TILE / 4);
   u64 kr[RS_ROUNDS];
   V vr[RS_ROUNDS];
+  // all loads of the wave's rounds first, then the counting
 #pragma unroll
   for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
     const uint32_t i = wbeg + r * 64u + lane;
     const bool valid = i < count;
     kr[r] = valid ? kin[start + i] : 0ull;
     vr[r] = valid ? vin[start + i] : (V)0;
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
+    const uint32_t i = wbeg + r * 64u + lane;
+    const bool valid = i < count;
     const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
     uint32_t rank, cnt;
     digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
@@ -568,12 +582,18 @@ __global__ __launch_bounds__(RSL_THREADS) void rs_scatter_lds_kernel(const u64* 
     u64 kr[RSL_ROUNDS];
     V vr[RSL_ROUNDS];
     uint32_t dr[RSL_ROUNDS];
+    // all loads of the wave's rounds first, then the counting
 #pragma unroll
     for (uint32_t r = 0; r < RSL_ROUNDS; ++r) {
       const uint32_t i = wbeg + r * 64u + lane;
       const bool valid = i < count;
       kr[r] = valid ? kin[start + i] : 0ull;
       vr[r] = valid ? vin[start + i] : (V)0;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < RSL_ROUNDS; ++r) {
+      const uint32_t i = wbeg + r * 64u + lane;
+      const bool valid = i < count;
       dr[r] = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
       uint32_t rank, cnt;
       digit_peers(dr[r], valid, in.dbits, lane, &rank, &cnt);

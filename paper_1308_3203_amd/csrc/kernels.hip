@@ -732,47 +732,62 @@ __device__ __forceinline__ void push_long(const SegParams& S, u64 s, u64 e, bool
 
 // Segmented inclusive minimum over the lanes of a wave: `heads` has a bit
 // per lane that starts a run; each lane ends with the minimum of its run up
-// to itself, so a run's last lane holds the run's minimum.  A scan of
-// (value, started) pairs with DPP moves: shifts by 1, 2, 4 and 8 lanes inside
-// each row of 16, then row 0's and row 2's last lanes into rows 1 and 3, and
-// lane 31 into rows 2 and 3.  A lane takes the value it receives unless a
-// run starts between the two (its flag), and lanes that receive nothing get
-// the identity.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_min_step(uint32_t& v, uint32_t& f) {
-  const uint32_t vo = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)v, CTRL, ROWS, 0xF, false);
-  const uint32_t fo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, CTRL, ROWS, 0xF, false);
-  if (!f) v = vo < v ? vo : v;
-  f |= fo;
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_min_step64(u64& v, uint32_t& f) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
-  const uint32_t fo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, CTRL, ROWS, 0xF, false);
-  const u64 vo = ((u64)hi << 32) | lo;
-  if (!f) v = vo < v ? vo : v;
-  f |= fo;
-}
+// to itself, so a run's last lane holds the run's minimum.  A scan with DPP
+// moves: shifts by 1, 2, 4 and 8 lanes inside each row of 16, then row 0's
+// and row 2's last lanes into rows 1 and 3, and lane 31 into rows 2 and 3.
+// A lane takes the value it receives unless a run starts between the two,
+// and lanes that receive nothing get the identity.  Whether a run starts
+// between them depends on `heads` only: SegMasks holds it per step as an
+// all-ones word (take nothing) or zero, built once by the same moves and
+// shared by every scan over the same runs, so a step is a move, an OR and
+// a minimum.
 // DPP controls: row_shr:n is 0x110 + n, row_bcast:15 0x142, row_bcast:31 0x143
-__device__ __forceinline__ uint32_t seg_min_u32(uint32_t v, u64 heads, uint32_t lane) {
-  uint32_t f = (uint32_t)(heads >> lane) & 1u;
-  seg_min_step<0x111, 0xF>(v, f);
-  seg_min_step<0x112, 0xF>(v, f);
-  seg_min_step<0x114, 0xF>(v, f);
-  seg_min_step<0x118, 0xF>(v, f);
-  seg_min_step<0x142, 0xA>(v, f);
-  seg_min_step<0x143, 0xC>(v, f);
+struct SegMasks {
+  uint32_t m[6];
+};
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t seg_mask_step(uint32_t m) {
+  return m | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ SegMasks seg_masks(u64 heads, uint32_t lane) {
+  SegMasks M;
+  M.m[0] = ((heads >> lane) & 1ull) ? ~0u : 0u;
+  M.m[1] = seg_mask_step<0x111, 0xF>(M.m[0]);
+  M.m[2] = seg_mask_step<0x112, 0xF>(M.m[1]);
+  M.m[3] = seg_mask_step<0x114, 0xF>(M.m[2]);
+  M.m[4] = seg_mask_step<0x118, 0xF>(M.m[3]);
+  M.m[5] = seg_mask_step<0x142, 0xA>(M.m[4]);
+  return M;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_min_step(uint32_t& v, uint32_t m) {
+  const uint32_t vo = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)v, CTRL, ROWS, 0xF, false) | m;
+  v = vo < v ? vo : v;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_min_step64(u64& v, uint32_t m) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)(uint32_t)v, CTRL, ROWS, 0xF, false) | m;
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)NONE32, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false) | m;
+  const u64 vo = ((u64)hi << 32) | lo;
+  v = vo < v ? vo : v;
+}
+__device__ __forceinline__ uint32_t seg_min_u32(uint32_t v, const SegMasks& M) {
+  seg_min_step<0x111, 0xF>(v, M.m[0]);
+  seg_min_step<0x112, 0xF>(v, M.m[1]);
+  seg_min_step<0x114, 0xF>(v, M.m[2]);
+  seg_min_step<0x118, 0xF>(v, M.m[3]);
+  seg_min_step<0x142, 0xA>(v, M.m[4]);
+  seg_min_step<0x143, 0xC>(v, M.m[5]);
   return v;
 }
-__device__ __forceinline__ u64 seg_min_u64(u64 v, u64 heads, uint32_t lane) {
-  uint32_t f = (uint32_t)(heads >> lane) & 1u;
-  seg_min_step64<0x111, 0xF>(v, f);
-  seg_min_step64<0x112, 0xF>(v, f);
-  seg_min_step64<0x114, 0xF>(v, f);
-  seg_min_step64<0x118, 0xF>(v, f);
-  seg_min_step64<0x142, 0xA>(v, f);
-  seg_min_step64<0x143, 0xC>(v, f);
+__device__ __forceinline__ u64 seg_min_u64(u64 v, const SegMasks& M) {
+  seg_min_step64<0x111, 0xF>(v, M.m[0]);
+  seg_min_step64<0x112, 0xF>(v, M.m[1]);
+  seg_min_step64<0x114, 0xF>(v, M.m[2]);
+  seg_min_step64<0x118, 0xF>(v, M.m[3]);
+  seg_min_step64<0x142, 0xA>(v, M.m[4]);
+  seg_min_step64<0x143, 0xC>(v, M.m[5]);
   return v;
 }
 __device__ __forceinline__ u64 shfl_u64(u64 v, uint32_t src) {
@@ -796,8 +811,9 @@ __device__ __forceinline__ RunSums window_runs(bool valid, uint32_t id, bool w, 
   // pass 1
   uint32_t r1 = valid && !w ? id : NONE32;
   u64 wm = valid && w ? (((u64)id << 32) | ((uint32_t)v ^ 0x80000000u)) : ~0ull;
-  r1 = __shfl(seg_min_u32(r1, heads, lane), last);
-  wm = shfl_u64(seg_min_u64(wm, heads, lane), last);
+  const SegMasks M = seg_masks(heads, lane);
+  r1 = __shfl(seg_min_u32(r1, M), last);
+  wm = shfl_u64(seg_min_u64(wm, M), last);
   r.p1.r1 = r1;
   r.p1.wmin = wm;
   const uint32_t w1 = wm == ~0ull ? NONE32 : (uint32_t)(wm >> 32);
@@ -831,10 +847,10 @@ __device__ __forceinline__ RunSums window_runs(bool valid, uint32_t id, bool w, 
       }
     }
   }
-  r.a = __shfl(seg_min_u32(a, heads, lane), last);
-  r.b = __shfl(seg_min_u32(b, heads, lane), last);
-  r.q = __shfl(seg_min_u32(q, heads, lane), last);
-  r.A = inter ? __shfl(seg_min_u32(A, heads, lane), last) : NONE32;
+  r.a = __shfl(seg_min_u32(a, M), last);
+  r.b = __shfl(seg_min_u32(b, M), last);
+  r.q = __shfl(seg_min_u32(q, M), last);
+  r.A = inter ? __shfl(seg_min_u32(A, M), last) : NONE32;
   // OR over the run: the run's lanes are [first, last]
   const u64 mm = __ballot(m1);
   // the run's first lane: the last head at or below this lane (lane 0 when

@@ -236,6 +236,42 @@ def test_record_overflow():
     assert ei.value.status == B.RC_E_OVERFLOW
 
 
+def test_record_overflow_global_path():
+    """More records than the capacity on the path of the log sort, the
+    segmented check and the record gather (a program of several groups):
+    the first cap records are the canonical ones, exactly the instances that
+    lost records have flags bit 0 (the rest of every summary unchanged), the
+    counter holds the full count, and the call reports the overflow."""
+    # (seeds 0..2 have 198, 147 and 137 records by the oracle: a capacity of
+    # half the total keeps instance 0 whole, cuts instance 1 and drops 2)
+    w = WL.c4_kernel(8, 64, 8, log2_cells=12)
+    full_recs, full_sums = U.gpu_run(w.src, w.G, w.W, w.arrays, w.scalars, 0, 3)
+    n = len(full_recs)
+    assert n >= 4 and len(set(full_recs["instance"].tolist())) == 3
+    cap = n // 2
+    ctx = U.ctx()
+    p = B.Program(ctx, w.src)
+    p.set_ndrange(w.G, w.W)
+    p.bind(w.arrays, w.scalars)
+    buf = B.Buffers(p, 3, cap=cap, ws_limit=4 << 30)
+    p.check_async(0, 3, buf.ws, buf.records, buf.n_records, buf.summaries)
+    with pytest.raises(B.RcError) as ei:
+        ctx.sync()
+    assert ei.value.status == B.RC_E_OVERFLOW
+    assert int(buf.n_records.item()) == n
+    recs = B.records_to_numpy(buf.records, cap)
+    sums = B.summaries_to_numpy(buf.summaries, 3)
+    p.close()
+    assert recs.tobytes() == full_recs[:cap].tobytes()
+    lost = set(full_recs["instance"][cap:].tolist())
+    assert lost == {1, 2}
+    for j in range(3):
+        assert (int(sums[j]["flags"]) & 1) == (1 if j in lost else 0), j
+        a, b = sums[j].copy(), full_sums[j].copy()
+        a["flags"] = b["flags"] = 0
+        assert a.tobytes() == b.tobytes(), j
+
+
 def test_api_errors():
     ctx = U.ctx()
     with pytest.raises(B.RcError) as ei:

@@ -448,8 +448,8 @@ __device__ __forceinline__ void digit_peers(uint32_t d, bool valid, uint32_t dbi
   *count = (uint32_t)__popcll(eq);
 }
 
-// Digit counts of one tile; one LDS atomic per distinct digit per wave
-// (sorted inputs make high digits nearly constant within a tile).
+// Digit counts of one tile: an LDS atomic per entry, or one per wave round
+// whose lanes all hold the same digit.
 // The histogram is digit-major over the pass's live tiles (the count read
 // on the device), so its scan and the grids scale with the entries, not
 // with the capacity; a fixed grid walks the tiles.
@@ -472,13 +472,21 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, 
       const uint32_t i = r * RS_THREADS + t;
       kr[r] = i < count ? keys[start + i] : 0ull;
     }
+    // a round whose lanes share one digit (sorted inputs make high digits
+    // nearly constant within a tile) takes one atomic; any other round one
+    // atomic per lane, since the counts need no ranks
 #pragma unroll
     for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
       const bool valid = r * RS_THREADS + t < count;
       const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
-      uint32_t rank, cnt;
-      digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
-      if (valid && rank == 0) atomicAdd(&h[d], cnt);
+      const u64 vm = __ballot(valid);
+      if (vm == 0ull) continue;
+      const uint32_t d0 = __builtin_amdgcn_readlane(d, (uint32_t)__ffsll((long long)vm) - 1u);
+      if (__ballot(valid && d != d0) == 0ull) {
+        if (lane == (uint32_t)__ffsll((long long)vm) - 1u) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+      } else if (valid) {
+        atomicAdd(&h[d], 1u);
+      }
     }
     __syncthreads();
     if (t <= dmask) hist[(size_t)t * nt + b] = h[t];

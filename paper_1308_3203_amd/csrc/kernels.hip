@@ -448,6 +448,21 @@ __device__ __forceinline__ void digit_peers(uint32_t d, bool valid, uint32_t dbi
   *count = (uint32_t)__popcll(eq);
 }
 
+// Count one wave round's digits into LDS counters: an atomic per lane, or
+// one for the round when its lanes all hold the same digit (sorted inputs
+// make high digits nearly constant within a tile).  Counts need no ranks.
+__device__ __forceinline__ void wave_count_digits(uint32_t* cnt, uint32_t d, bool valid, uint32_t lane) {
+  const u64 vm = __ballot(valid);
+  if (vm == 0ull) return;
+  const uint32_t first = (uint32_t)__ffsll((long long)vm) - 1u;
+  const uint32_t d0 = __builtin_amdgcn_readlane(d, first);
+  if (__ballot(valid && d != d0) == 0ull) {
+    if (lane == first) atomicAdd(&cnt[d0], (uint32_t)__popcll(vm));
+  } else if (valid) {
+    atomicAdd(&cnt[d], 1u);
+  }
+}
+
 // Digit counts of one tile: an LDS atomic per entry, or one per wave round
 // whose lanes all hold the same digit.
 // The histogram is digit-major over the pass's live tiles (the count read
@@ -472,21 +487,10 @@ __global__ __launch_bounds__(256) void rs_hist_kernel(const u64* keys, RsIn in, 
       const uint32_t i = r * RS_THREADS + t;
       kr[r] = i < count ? keys[start + i] : 0ull;
     }
-    // a round whose lanes share one digit (sorted inputs make high digits
-    // nearly constant within a tile) takes one atomic; any other round one
-    // atomic per lane, since the counts need no ranks
 #pragma unroll
     for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
       const bool valid = r * RS_THREADS + t < count;
-      const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
-      const u64 vm = __ballot(valid);
-      if (vm == 0ull) continue;
-      const uint32_t d0 = __builtin_amdgcn_readlane(d, (uint32_t)__ffsll((long long)vm) - 1u);
-      if (__ballot(valid && d != d0) == 0ull) {
-        if (lane == (uint32_t)__ffsll((long long)vm) - 1u) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
-      } else if (valid) {
-        atomicAdd(&h[d], 1u);
-      }
+      wave_count_digits(h, valid ? rs_digit(in, kr[r], shift, dmask) : 0u, valid, lane);
     }
     __syncthreads();
     if (t <= dmask) hist[(size_t)t * nt + b] = h[t];
@@ -526,10 +530,7 @@ __global__ __launch_bounds__(256) void rs_scatter_kernel(const u64* kin, const V
   for (uint32_t r = 0; r < RS_ROUNDS; ++r) {
     const uint32_t i = wbeg + r * 64u + lane;
     const bool valid = i < count;
-    const uint32_t d = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
-    uint32_t rank, cnt;
-    digit_peers(d, valid, in.dbits, lane, &rank, &cnt);
-    if (valid && rank == 0) woff[w][d] += cnt;      // one lane per digit: no conflict in the wave
+    wave_count_digits(woff[w], valid ? rs_digit(in, kr[r], shift, dmask) : 0u, valid, lane);
   }
   __syncthreads();
   if (t <= dmask) {
@@ -603,9 +604,7 @@ __global__ __launch_bounds__(RSL_THREADS) void rs_scatter_lds_kernel(const u64* 
       const uint32_t i = wbeg + r * 64u + lane;
       const bool valid = i < count;
       dr[r] = valid ? rs_digit(in, kr[r], shift, dmask) : 0u;
-      uint32_t rank, cnt;
-      digit_peers(dr[r], valid, in.dbits, lane, &rank, &cnt);
-      if (valid && rank == 0) woff[w][dr[r]] += cnt;   // one lane per digit: no conflict in the wave
+      wave_count_digits(woff[w], dr[r], valid, lane);
     }
     __syncthreads();
     // tile-local start of each digit (scan over the digits), then each
